@@ -1,0 +1,209 @@
+#!/usr/bin/env python3
+"""Throughput of the improved Yau-Yau filter step on one MI355X.
+
+A step is one pass of the whole hot path over the synthetic cubic-sensor
+workload r=1000, n=65536 (f = cos, h = x^3, noise std 0.3, dt = 0.005, kernel
+scales {1, 2, 4}, restart every 2 steps with R = 0.3): yy_propagate,
+yy_loglik_update, yy_normalise_moments and, every second step, yy_restart with
+its normalisation.  Inputs (nodes, weights, observation increments) are
+resident in HBM before the timed region starts.
+
+Prints one JSON line: steps/s, propagation TFLOP/s (algorithmic 2 n^2 r P per
+step, P = 2 products x.x and x.f for several scales), the roofline of the
+pairwise kernel (timed with HIP events on its own stream), the plain FP32 form
+timed beside it, and the FP64 oracle on a bounded sample of the same step on
+the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "filter steps/sec + propagation TFLOP/s at r=1000,n=65536 vs plain FP32, same error"
+PEAK_TFLOPS = {"bf16x3": 2500.0, "bf16x1": 2500.0, "fp32_mfma": 157.3}
+VALU_FP32_PEAK = 78.6   # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz, packed FP32 disabled
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def alg_flops(w) -> float:
+    P = 1 if len(w.scales) == 1 else 2
+    return 2.0 * w.n * w.n * w.r * P
+
+
+def run_gpu(w, dys, prec, warmup, steps, timing=True):
+    import torch
+    from paper_2509_16896_amd import yy
+    from paper_2509_16896_amd.filter import GpuFilter
+
+    f = GpuFilter(w, prec=prec)
+    f.set_observations(dys)
+    f.init()
+    k = 0
+    for _ in range(warmup):
+        k += 1
+        f.step(k, restart=(w.restart_every and k % w.restart_every == 0))
+    torch.cuda.synchronize()
+    if timing:
+        yy.yy_timing_enable(f.ctx, True)
+        yy.yy_timing_read(f.ctx)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        k += 1
+        f.step(k, restart=(w.restart_every and k % w.restart_every == 0))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms, launches = yy.yy_timing_read(f.ctx) if timing else (0.0, 0)
+    yy.yy_timing_enable(f.ctx, False)
+    return f, k, t1 - t0, ms, launches
+
+
+def cpu_baseline(w, f, k_last, target_s=15.0):
+    """The oracle on a bounded sample of one step of the same workload: the propagation of a
+    few target rows (extrapolated to all n rows) plus the full correction and normalisation."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from oracle import filter as ofilter
+
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    threads = int(os.environ.get("OMP_NUM_THREADS", cores))
+    torch.cuda.synchronize()
+    x = f.x.cpu().numpy().reshape(w.n, w.r)
+    lw = f.lw[f.cur].cpu().numpy()
+    lo, hi = f.lo.cpu().numpy(), f.hi.cpu().numpy()
+    model = ofilter.model_of(w)
+    s = np.asarray(w.scales, float)
+    c = oracle.kernel_coefficients(s)
+    rng = np.random.default_rng(0)
+    probe = rng.choice(w.n, 4, replace=False)
+    t0 = time.perf_counter()
+    oracle.propagate_rows(model, s, c, x, lo, hi, w.dt, lw, probe)
+    per_row = (time.perf_counter() - t0) / len(probe)
+    nrows = int(max(8, min(512, target_s / max(per_row, 1e-6))))
+    rows = np.sort(rng.choice(w.n, nrows, replace=False))
+    t0 = time.perf_counter()
+    ref_rows, _ = oracle.propagate_rows(model, s, c, x, lo, hi, w.dt, lw, rows)
+    t_rows = time.perf_counter() - t0
+    dy = f.dys[k_last - 1].cpu().numpy()
+    t0 = time.perf_counter()
+    lw2 = oracle.loglik_update(model, x, dy, w.dt, lw)
+    oracle.normalise_moments(x, lw2, 0.0, want_cov=False)
+    t_rest = time.perf_counter() - t0
+    t_step = t_rows * (w.n / nrows) + t_rest
+    return dict(value=1.0 / t_step, unit="steps/s", cores=threads, kind="oracle",
+                sample=f"FP64 oracle: propagation of {nrows} of {w.n} target rows of one step "
+                       f"({t_rows:.1f} s, extrapolated to all rows) + full correction/normalisation "
+                       f"({t_rest:.2f} s)"), (rows, ref_rows, x, lw, lo, hi)
+
+
+def sampled_parity(w, f, prec, sample):
+    """GPU propagation of the same state compared with the oracle's rows."""
+    import numpy as np
+    import torch
+    from scipy.special import logsumexp
+
+    from paper_2509_16896_amd import yy
+
+    rows, ref_rows, x, lw, lo, hi = sample
+    out = torch.empty(w.n, dtype=torch.float64, device=f.dev)
+    yy.yy_propagate(f.ctx, f.model, f.scales, prec, w.n, f.x, f.version, f.lo, f.hi, w.dt, f.lw[f.cur], out)
+    got = out.cpu().numpy()
+    fin = np.isfinite(ref_rows)
+    # both sides are row samples of the same vector: compare relative to the full GPU normaliser
+    z = logsumexp(got[np.isfinite(got)])
+    rel = np.abs(got[rows][fin] - ref_rows[fin]) / np.maximum(1.0, np.abs(ref_rows[fin] - z))
+    return float(np.max(rel)) if rel.size else float("nan")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--prec", default="bf16x3", choices=["fp32", "fp32_mfma", "bf16x3", "bf16x1"])
+    ap.add_argument("--baseline-prec", default="fp32_mfma", help="plain FP32 form timed beside ('none' to skip)")
+    ap.add_argument("--baseline-steps", type=int, default=4)
+    ap.add_argument("--workload", default="cubic_r1000", choices=["cubic_r1000", "cubic_r100"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build benchmarks one GPU only; run with --gpus 1"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2509_16896_amd import workloads as W
+
+    w = {"cubic_r1000": W.cubic_r1000, "cubic_r100": W.cubic_r100}[args.workload]()
+    total = args.warmup + args.steps
+    w.K = max(w.K, total + 1)
+    xs, dys = W.simulate(w)
+    log(f"[bench] workload {w.name}: r={w.r} n={w.n} scales={w.scales} prec={args.prec} "
+        f"warmup={args.warmup} steps={args.steps}")
+    f, k_last, elapsed, ms, launches = run_gpu(w, dys, args.prec, args.warmup, args.steps)
+    steps_s = args.steps / elapsed
+    avg_kernel_s = (ms / 1e3) / max(launches, 1)
+    achieved = alg_flops(w) / avg_kernel_s / 1e12
+    prop_tflops = alg_flops(w) * args.steps / elapsed / 1e12
+    log(f"[bench] {steps_s:.3f} steps/s, pairwise kernel {1e3 * avg_kernel_s:.2f} ms/launch "
+        f"({launches} launches), {achieved:.1f} TFLOP/s algorithmic")
+    mfma = args.prec != "fp32"
+    roofline = {"bound": "mfma" if mfma else "alu", "achieved": round(achieved, 3),
+                "peak": PEAK_TFLOPS[args.prec] if mfma else VALU_FP32_PEAK, "unit": "TFLOP/s"}
+    roofline["frac"] = round(roofline["achieved"] / roofline["peak"], 4)
+    roofline["traffic"] = None
+    roofline["kernel"] = "k_pair_mfma" if mfma else "k_pair_valu"
+    roofline["kernel_ms"] = round(1e3 * avg_kernel_s, 3)
+
+    base = None
+    if args.baseline_prec != "none" and args.baseline_prec != args.prec:
+        g, _, el2, ms2, l2 = run_gpu(w, dys, args.baseline_prec, 1, args.baseline_steps)
+        base = {"prec": args.baseline_prec, "steps_per_s": round(args.baseline_steps / el2, 4),
+                "kernel_ms": round(ms2 / max(l2, 1), 3)}
+        g.close()
+        log(f"[bench] plain {args.baseline_prec}: {base['steps_per_s']} steps/s")
+
+    cpu = None
+    parity = None
+    if not args.no_cpu_baseline:
+        log("[bench] timing the FP64 oracle on a sample of the step ...")
+        cpu, sample = cpu_baseline(w, f, k_last, args.cpu_seconds)
+        parity = sampled_parity(w, f, args.prec, sample)
+        log(f"[bench] oracle {cpu['value']:.3g} steps/s on {cpu['cores']} threads; sampled rows max rel err {parity:.3g}")
+    f.close()
+
+    dtype = {"fp32": "f32", "fp32_mfma": "f32", "bf16x3": "bf16", "bf16x1": "bf16"}[args.prec]
+    line = {
+        "metric": METRIC, "value": round(steps_s, 4), "unit": "steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed / args.steps, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+        "data": "synthetic",
+        "config": {"workload": w.name, "r": w.r, "n": w.n, "dt": w.dt, "scales": list(w.scales),
+                   "restart_every": w.restart_every, "R": w.R, "precision": args.prec},
+        "propagation_tflops": round(prop_tflops, 3),
+        "roofline": roofline,
+        "plain_fp32": base,
+        "vs_plain_fp32": None if base is None else round(steps_s / base["steps_per_s"], 3),
+        "sampled_row_max_rel_err": parity,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

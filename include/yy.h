@@ -1,0 +1,209 @@
+/*
+ * yy.h -- C ABI of libyy, the MI355X (gfx950) implementation of one time step
+ * of the improved Yau-Yau filter (arXiv 2509.16896, "An Improved Yau-Yau
+ * Algorithm for High Dimensional Nonlinear Filtering Problems").
+ *
+ * Problem (Sec. 2.1, eq. NonlinearFilter, with the constant isotropic noise
+ * coefficients a = q I, b = rho2 I of Table tab:generalformulas):
+ *     dx = f(x) dt + sqrt(q) dV,     dy = h(x) dt + sqrt(rho2) dW.
+ * The filter keeps log-densities logw[i] at n quasi-random nodes x_i in a box
+ * and advances them per step k (Sec. 2.2.2 procedure, Sec. 9 log domain):
+ *     propagate  (yy_propagate)          multi-scale Gaussian kernel sum
+ *     correct    (yy_loglik_update)      h(x).dy - dt/2 |h(x)|^2, scaled by 1/rho2
+ *     normalise  (yy_normalise_moments)  logZ, weights, posterior mean/covariance, ESS
+ *     restart    (yy_restart)            every few steps, Sec. 6 local restart
+ * with nodes from yy_nodes_sobol (Appendix A, Sobol sequence).
+ *
+ * Conventions for every call:
+ *  - Arrays are DEVICE memory owned by the caller unless a comment says host.
+ *    Node arrays are row-major [n x r]: coordinate k of node i is x[i*r + k].
+ *  - Calls are asynchronous and ordered on the context's stream; outputs are
+ *    valid after that stream is synchronised.  Nothing is read back to the
+ *    host inside a call, so a sequence of calls can be captured in a graph
+ *    once every buffer has been allocated (first call at a given size).
+ *  - Every call returns a yy_status and never throws or exits.  Argument
+ *    errors are detected on the host before anything is launched; the text
+ *    of the last error of the calling thread is returned by yy_last_error().
+ *  - Numerical events found on the device (all weights vanished, a negative
+ *    multi-scale sum clamped to zero, all resampling weights zero) set bits of
+ *    the context's status word, read with yy_get_status().
+ *  - Output arrays may not alias input arrays unless the call says in place.
+ */
+#ifndef YY_H
+#define YY_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  YY_OK = 0,
+  YY_ERR_ARG = 1,          /* invalid argument (size, pointer, enum value) */
+  YY_ERR_ALLOC = 2,        /* device allocation failed */
+  YY_ERR_HIP = 3,          /* a HIP runtime call failed; text in yy_last_error() */
+  YY_ERR_NUMERIC = 4,      /* reserved for numerical failures reported synchronously */
+  YY_ERR_UNSUPPORTED = 5   /* valid but unsupported combination (e.g. r too large) */
+} yy_status;
+
+/* Status-word bits (yy_get_status). */
+#define YY_FLAG_ALL_ZERO     1u   /* normalisation found every weight zero (-inf) */
+#define YY_FLAG_CLAMPED      2u   /* a signed multi-scale sum was <= 0 and was set to -inf */
+#define YY_FLAG_RESAMPLE_ZERO 4u  /* resampling weights summed to zero */
+#define YY_FLAG_LOW_ESS      8u   /* ESS below the restart's ess_min */
+
+#define YY_MAX_SCALES 6
+#define YY_MAX_R 3600             /* largest state dimension with generated direction numbers */
+
+/* Thread-local text describing the last non-OK status returned on this thread. */
+const char* yy_last_error(void);
+
+typedef struct yy_ctx_s* yy_ctx;
+
+/* Creates a context on HIP device `device` that issues all work on `stream`
+ * (a hipStream_t; NULL = the device's default stream).  The context owns its
+ * scratch buffers and caches; it is not thread safe. */
+yy_status yy_create(yy_ctx* out, int device, void* stream);
+yy_status yy_destroy(yy_ctx ctx);
+/* Changes the stream used by later calls. */
+yy_status yy_set_stream(yy_ctx ctx, void* stream);
+/* Synchronises the stream, returns the status word and the number of clamped
+ * rows accumulated since the last call, and clears both.  Any pointer may be NULL. */
+yy_status yy_get_status(yy_ctx ctx, uint32_t* flags, int64_t* nclamped);
+
+/* ------------------------------------------------------------------------ */
+/* Model (Sec. 2.1).  Drift f and observation h are chosen from a closed set. */
+typedef enum {
+  YY_F_ZERO = 0,    /* f(x) = 0 */
+  YY_F_COS = 1,     /* f_k(x) = cos(x_k) */
+  YY_F_LINEAR = 2   /* f(x) = A x, A device row-major [r x r] */
+} yy_drift;
+
+typedef enum {
+  YY_H_IDENTITY = 0, /* h(x) = x (m = r) */
+  YY_H_CUBE = 1,     /* h_k(x) = (x_k - h_shift)^3 (m = r) */
+  YY_H_LINEAR = 2    /* h(x) = H x, H device row-major [m x r] */
+} yy_obs;
+
+typedef struct {
+  int32_t r;          /* state dimension, 1 <= r <= YY_MAX_R */
+  int32_t m;          /* observation dimension */
+  int32_t drift;      /* yy_drift */
+  const double* A;    /* device, used when drift == YY_F_LINEAR */
+  int32_t obs;        /* yy_obs */
+  const double* H;    /* device, used when obs == YY_H_LINEAR */
+  double h_shift;
+  double q;           /* process-noise variance (> 0) */
+  double rho2;        /* observation-noise variance (> 0) */
+} yy_model;
+
+/* Multi-time-scale kernel (Sec. 4.3.3, eq. general_kernel):
+ *   K = sum_{j<S} c_j K_{dt/s_j} + c_S delta.
+ * s: host array of S distinct positive scale divisors (paper: 1, 2, 4, ...).
+ * c: host array of S+1 coefficients, or NULL to solve V c = d with the error
+ *    exponents mu_k = (k+2)/2 (the paper's mu_1 = 3/2, mu_2 = 2). */
+typedef struct {
+  int32_t S;          /* 1 <= S <= YY_MAX_SCALES */
+  const double* s;    /* host [S] */
+  const double* c;    /* host [S+1] or NULL */
+} yy_scales;
+
+/* Solves V c = d of Sec. 4.3.3 on the host (Cramer's rule, as the paper
+ * states it).  s: host [S]; c_out: host [S+1]. */
+yy_status yy_kernel_coefficients(int32_t S, const double* s, double* c_out);
+
+/* Arithmetic of the pairwise kernel sum in yy_propagate. */
+typedef enum {
+  YY_PREC_AUTO = 0,      /* VALU for r < 32, BF16X3 otherwise */
+  YY_PREC_FP32 = 1,      /* plain FP32: direct differences on the vector ALUs */
+  YY_PREC_FP32_MFMA = 2, /* FP32 matrix cores for the distance expansion + exact near pairs */
+  YY_PREC_BF16X3 = 3,    /* BF16 hi/lo split (3 products) on matrix cores + exact near pairs */
+  YY_PREC_BF16X1 = 4     /* one BF16 product on matrix cores as a screen + exact near pairs */
+} yy_prec;
+
+/* ------------------------------------------------------------------------ */
+/* Sobol nodes (Appendix A; Sec. 2.2.1 state sampling; Sec. 6 reference set).
+ * Points first_index .. first_index+n-1 of the r-dimensional Sobol sequence in
+ * Gray-code order, 32-bit codes, optionally scrambled by a random linear
+ * (Matousek) scramble plus digital shift keyed by `seed`, mapped to the box:
+ *   x[i*r+k] = c_k + hw_k * (code * 2^-31 - 1),  c = (lo+hi)/2, hw = (hi-lo)/2,
+ * in double precision without fused multiply-add.
+ *   box_lo, box_hi: device [r]; codes: device [n*r] uint32 or NULL;
+ *   x: device [n*r] double or NULL.  first_index + n <= 2^32. */
+yy_status yy_nodes_sobol(yy_ctx ctx, int32_t r, int64_t n, int64_t first_index, int32_t scramble,
+                         uint64_t seed, const double* box_lo, const double* box_hi, uint32_t* codes,
+                         double* x);
+
+/* Prediction (Sec. 4 kernel operator, push form; Sec. 9 log-domain prediction).
+ *   logw_out[i] = log( sum_s c_s dV sum_j N(x_i; x_j + tau_s f(x_j), q tau_s I) exp(logw_in[j])
+ *                      + c_S exp(logw_in[i]) ),   tau_s = dt / s_s,  dV = vol(box) / n.
+ * Nodes within 1e-12 of a face of the box (Sec. 4.2, boundary conditions) are
+ * excluded as sources and get -inf as targets; a sum <= 0 (possible because
+ * some c_s < 0) gives -inf and sets YY_FLAG_CLAMPED.
+ *   x: device [n*r] double, the node set; node_version: any value that
+ *   changes whenever x or the box change (the context caches the prepared
+ *   node set under (x, n, r, drift, node_version)); box_lo/hi: device [r];
+ *   logw_in, logw_out: device [n] double, must not alias. */
+yy_status yy_propagate(yy_ctx ctx, const yy_model* model, const yy_scales* scales, int32_t prec,
+                       int64_t n, const double* x, uint64_t node_version, const double* box_lo,
+                       const double* box_hi, double dt, const double* logw_in, double* logw_out);
+
+/* Correction with the Ito term (Sec. 2.2 online stage; Sec. 9 observation
+ * update; 1/rho2 from Table tab:generalformulas), in place:
+ *   logw[i] += ( h(x_i) . dy - dt/2 |h(x_i)|^2 ) / rho2      (-inf stays -inf)
+ *   x: device [n*r]; dy: device [m]; logw: device [n]. */
+yy_status yy_loglik_update(yy_ctx ctx, const yy_model* model, int64_t n, const double* x,
+                           const double* dy, double dt, double* logw);
+
+/* Normalisation and estimation (Sec. 2.2.2 step 4; Sec. 9 normalisation), in
+ * double precision with fixed-order reductions:
+ *   logZ = LSE_i logw[i];  logw[i] -= logZ (in place);  w[i] = exp(logw[i]);
+ *   mean = sum_i w_i x_i;  cov = sum_i w_i (x_i - mean)(x_i - mean)^T;
+ *   ess = 1 / sum_i w_i^2;  *logZ_acc += logZ.
+ *   w: device [n] or NULL; logZ_step, logZ_acc (read-modify-write), ess:
+ *   device scalars; mean: device [r]; cov: device [r*r] or NULL.
+ * If every weight is -inf, YY_FLAG_ALL_ZERO is set and the outputs are left
+ * unchanged except logZ_step = -inf. */
+yy_status yy_normalise_moments(yy_ctx ctx, int64_t n, int32_t r, const double* x, double* logw,
+                               double* w, double* logZ_step, double* logZ_acc, double* mean,
+                               double* cov, double* ess);
+
+/* Local resample-restart (Sec. 6). */
+typedef struct {
+  double R;           /* half-width of the new box [mean - R, mean + R]^r */
+  double ess_min;     /* YY_FLAG_LOW_ESS is set when ess < ess_min (ess: device scalar or NULL) */
+  uint64_t seed;      /* key of the resampling random numbers */
+} yy_restart_params;
+
+/* (1) Integer systematic resampling of the normalised weights w into ancestor
+ *     indices idx (W_i = floor(w_i 2^53), C = prefix sums, U = 32 bits of
+ *     SplitMix64 keyed by (seed, step), P_t = floor((t 2^32 + U) W / (n 2^32)),
+ *     idx[t] = min{i : C_i > P_t}).  idx may be NULL to skip it.
+ * (2) New box [mean - R, mean + R]^r written to box_lo/box_hi, and the new
+ *     nodes x_new = the reference codes mapped to that box (the pre-generated
+ *     reference set translated to the estimate, Sec. 6).
+ * (3) Prior logw_new[i] = -|x_new_i - mean|^2 / 2 (the initial density
+ *     N(mean, I) up to a constant), -inf for boundary nodes; not normalised.
+ *   codes: device [n*r]; w: device [n]; mean: device [r]; ess: device scalar
+ *   or NULL; idx: device [n] int64 or NULL; box_lo/hi: device [r];
+ *   x_new: device [n*r]; logw_new: device [n]. */
+yy_status yy_restart(yy_ctx ctx, int64_t n, int32_t r, const uint32_t* codes, const double* w,
+                     const double* mean, const double* ess, int64_t step,
+                     const yy_restart_params* params, int64_t* idx, double* box_lo, double* box_hi,
+                     double* x_new, double* logw_new);
+
+/* ------------------------------------------------------------------------ */
+/* Timing of the pairwise kernel (the dominant kernel of yy_propagate).  While
+ * enabled, each yy_propagate records a pair of HIP events on the context's
+ * stream around its pairwise kernel.  yy_timing_read synchronises the stream,
+ * returns the summed kernel time in milliseconds and the number of timed
+ * launches since the last read, and resets both.  Do not enable it while a
+ * graph is being captured. */
+yy_status yy_timing_enable(yy_ctx ctx, int32_t on);
+yy_status yy_timing_read(yy_ctx ctx, double* ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* YY_H */

@@ -1,0 +1,124 @@
+// yy_internal.h -- shared declarations of libyy's host and device code (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/yy.h"
+
+namespace yy {
+
+constexpr int kBlock = 256;          // threads per block of the support kernels
+constexpr int kWave = 64;            // CDNA wavefront width
+constexpr double kBoundaryTol = 1e-12;  // distance to a face that marks a boundary node
+constexpr double kLog2e = 1.4426950408889634073599246810019;
+constexpr double kLn2 = 0.69314718055994530941723212145818;
+
+// Sets the thread-local error text and returns `st`.
+yy_status fail(yy_status st, const std::string& msg);
+yy_status hip_fail(hipError_t e, const char* what);
+
+#define YY_HIP(call)                                    \
+  do {                                                  \
+    hipError_t e_ = (call);                             \
+    if (e_ != hipSuccess) return ::yy::hip_fail(e_, #call); \
+  } while (0)
+
+#define YY_LAUNCH_CHECK(name)                                   \
+  do {                                                          \
+    hipError_t e_ = hipGetLastError();                          \
+    if (e_ != hipSuccess) return ::yy::hip_fail(e_, name);      \
+  } while (0)
+
+// Grow-only device buffer owned by the context.
+struct DevBuf {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+  yy_status ensure(size_t want);
+  void release();
+  template <class T>
+  T* as() const { return static_cast<T*>(ptr); }
+};
+
+// The node set as the pairwise kernels consume it; rebuilt when the nodes change.
+struct Prepared {
+  bool valid = false;
+  const double* x = nullptr;
+  int64_t n = 0;
+  int32_t r = 0;
+  int32_t rp = 0;           // r rounded up to the matrix-core K step (zero padded)
+  int32_t drift = -1;
+  const double* A = nullptr;
+  uint64_t version = 0;
+  const double* lo = nullptr;
+  const double* hi = nullptr;
+  bool have_bf16 = false;
+  DevBuf xc32;              // float [n*rp]  x - box centre
+  DevBuf f32;               // float [n*rp]  f(x)
+  DevBuf bf;                // bf16  [4][n*rp]  hi(xc), lo(xc), hi(f), lo(f)
+  DevBuf node;              // double [3][n]  |xc|^2, |f|^2, xc.f
+  DevBuf bnd;               // int [n]  1 = boundary node
+  DevBuf scal;              // double [4]  log vol(box), max |xc|, max |f|, spare
+};
+
+}  // namespace yy
+
+struct yy_ctx_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  uint32_t* d_flags = nullptr;        // status word
+  unsigned long long* d_nclamped = nullptr;
+  // Sobol direction numbers (host, unscrambled) for dimensions < dir_r.
+  std::vector<uint32_t> dirs;
+  int32_t dir_r = 0;
+  yy::DevBuf d_dirs;                  // uint32 [r][33]: 32 scrambled direction numbers + shift
+  int32_t d_dirs_r = -1;
+  int32_t d_dirs_scramble = -1;
+  uint64_t d_dirs_seed = 0;
+  yy::Prepared prep;
+  yy::DevBuf lw2;                     // float [n]: source log2-weights relative to their max
+  yy::DevBuf part;                    // pairwise partial (max, sum) results
+  yy::DevBuf red;                     // reduction scratch
+  yy::DevBuf red2;
+  yy::DevBuf scan;                    // resampling prefix sums
+  // pairwise-kernel timing
+  bool timing = false;
+  std::vector<hipEvent_t> ev_start, ev_stop;
+  size_t ev_used = 0;
+};
+
+namespace yy {
+
+// Host-side pieces shared by the call implementations.
+yy_status sobol_prepare_dirs(yy_ctx ctx, int32_t r, int32_t scramble, uint64_t seed);
+yy_status prepare_nodes(yy_ctx ctx, const yy_model* model, int64_t n, const double* x,
+                        uint64_t version, const double* lo, const double* hi, bool want_bf16);
+yy_status coefficients_cramer(int32_t S, const double* s, double* c);
+yy_status validate_model(const yy_model* m);
+yy_status timing_begin(yy_ctx ctx);
+yy_status timing_end(yy_ctx ctx);
+
+// Pairwise kernel launchers (per-(target, scale) partial max/sum in base 2).
+struct PairArgs {
+  int64_t n;
+  int32_t r, rp, S;
+  float kap2[YY_MAX_SCALES];   // log2(e) * s / (2 q dt): multiplies |x_i - m_j|^2
+  float tau[YY_MAX_SCALES];    // dt / s
+  const float* xc;
+  const float* f;
+  const float* lw2;            // [n]
+  const double* node;          // [3][n]
+  const int* bnd;
+  const uint16_t* bf;          // [4][n*rp] or null
+  const double* scal;
+  float2* part;                // [nsplit][S][n]
+  int32_t nsplit;
+};
+yy_status launch_pair_valu(hipStream_t st, const PairArgs& a);
+yy_status launch_pair_mfma(hipStream_t st, const PairArgs& a, int prec);
+int pair_mfma_rp(int32_t r);
+
+}  // namespace yy

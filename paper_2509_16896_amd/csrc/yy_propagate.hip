@@ -1,0 +1,557 @@
+// yy_propagate.hip -- the prediction step (Sec. 4 kernel operator in push form,
+// Sec. 4.3.3 multi-scale combination, Sec. 9 log-domain prediction).
+//
+//   logw_out[i] = log( sum_s c_s dV sum_j N(x_i; x_j + tau_s f(x_j), q tau_s I) e^{logw_in[j]}
+//                      + c_S e^{logw_in[i]} )
+//
+// Stages: (1) prepare the node set once per node version: centred FP32
+// coordinates, f(x), BF16 hi/lo splits, per-node norms, boundary flags, the box
+// volume and the norm maxima used by the near-pair error bound; (2) source
+// weights relative to their maximum in base 2; (3) pairwise kernel: for every
+// target i and scale s a running (max, sum) over sources in base 2; (4) FP64
+// combination of the scales with the Gaussian constants, the quadrature
+// weight and the identity term.
+#include <algorithm>
+#include <cmath>
+
+#include "yy_common.h"
+#include "yy_internal.h"
+
+namespace yy {
+
+// ---------------------------------------------------------------------------
+// (1) node preparation: one wavefront per node.
+__global__ void __launch_bounds__(kBlock) k_prepare(int64_t n, int32_t r, int32_t rp, int32_t drift,
+                                                    const double* __restrict__ A,
+                                                    const double* __restrict__ x,
+                                                    const double* __restrict__ lo,
+                                                    const double* __restrict__ hi,
+                                                    float* __restrict__ xc32, float* __restrict__ f32,
+                                                    uint16_t* __restrict__ bf, double* __restrict__ node,
+                                                    int* __restrict__ bnd) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  const size_t plane = (size_t)n * rp;
+  for (int64_t i = wave; i < n; i += nwaves) {
+    const double* xi = x + (size_t)i * r;
+    double sxx = 0.0, sff = 0.0, sxf = 0.0;
+    int b = 0;
+    for (int32_t k = lane; k < rp; k += 64) {
+      float xcv = 0.f, fv = 0.f;
+      double xcd = 0.0, fd = 0.0;
+      if (k < r) {
+        const double xv = xi[k];
+        const double c = 0.5 * (lo[k] + hi[k]);
+        xcd = xv - c;
+        b |= (fabs(xv - lo[k]) <= kBoundaryTol) || (fabs(hi[k] - xv) <= kBoundaryTol);
+        if (drift == YY_F_COS) {
+          fd = cos(xv);
+        } else if (drift == YY_F_LINEAR) {
+          const double* Ak = A + (size_t)k * r;
+          double acc = 0.0;
+          for (int32_t l = 0; l < r; ++l) acc = fma(Ak[l], xi[l], acc);
+          fd = acc;
+        }
+        sxx = fma(xcd, xcd, sxx);
+        sff = fma(fd, fd, sff);
+        sxf = fma(xcd, fd, sxf);
+        xcv = (float)xcd;
+        fv = (float)fd;
+      }
+      const size_t o = (size_t)i * rp + k;
+      xc32[o] = xcv;
+      f32[o] = fv;
+      if (bf) {
+        const uint16_t xh = f32_to_bf16(xcv);
+        const uint16_t xl = f32_to_bf16((float)(xcd - (double)bf16_to_f32(xh)));
+        const uint16_t fh = f32_to_bf16(fv);
+        const uint16_t fl = f32_to_bf16((float)(fd - (double)bf16_to_f32(fh)));
+        bf[o] = xh;
+        bf[plane + o] = xl;
+        bf[2 * plane + o] = fh;
+        bf[3 * plane + o] = fl;
+      }
+    }
+    sxx = wave_sum(sxx);
+    sff = wave_sum(sff);
+    sxf = wave_sum(sxf);
+    b = wave_or(b);
+    if (lane == 0) {
+      node[i] = sxx;
+      node[n + i] = sff;
+      node[2 * n + i] = sxf;
+      bnd[i] = b;
+    }
+  }
+}
+
+// Box volume (log) and the maxima of |xc| and |f| over the nodes: one block.
+__global__ void __launch_bounds__(kBlock) k_prepare_scalars(int64_t n, int32_t r,
+                                                            const double* __restrict__ lo,
+                                                            const double* __restrict__ hi,
+                                                            const double* __restrict__ node,
+                                                            double* __restrict__ scal) {
+  __shared__ double sh[kBlock / 64];
+  double lv = 0.0;
+  for (int32_t k = threadIdx.x; k < r; k += kBlock) lv += log(hi[k] - lo[k]);
+  lv = block_sum<kBlock>(lv, sh);
+  double mx = 0.0, mf = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += kBlock) {
+    mx = fmax(mx, node[i]);
+    mf = fmax(mf, node[n + i]);
+  }
+  mx = block_max<kBlock>(mx, sh);
+  mf = block_max<kBlock>(mf, sh);
+  if (threadIdx.x == 0) {
+    scal[0] = lv;
+    scal[1] = sqrt(mx);
+    scal[2] = sqrt(mf);
+    scal[3] = 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// (2) source weights: lw2[j] = (logw[j] - max_valid logw) * log2(e), -inf for
+// boundary nodes and zero weights.  Two kernels: block maxima, then every
+// block re-reduces the (short) list of block maxima in the same order.
+__global__ void __launch_bounds__(kBlock) k_lw_max(int64_t n, const double* __restrict__ lw,
+                                                   const int* __restrict__ bnd,
+                                                   double* __restrict__ part) {
+  __shared__ double sh[kBlock / 64];
+  double m = -INFINITY;
+  for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlock)
+    if (!bnd[j]) m = fmax(m, lw[j]);
+  m = block_max<kBlock>(m, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = m;
+}
+
+__global__ void __launch_bounds__(kBlock) k_lw_convert(int64_t n, int nparts,
+                                                       const double* __restrict__ part,
+                                                       const double* __restrict__ lw,
+                                                       const int* __restrict__ bnd,
+                                                       float* __restrict__ lw2,
+                                                       double* __restrict__ ref_out) {
+  __shared__ double sh[kBlock / 64];
+  double m = -INFINITY;
+  for (int p = threadIdx.x; p < nparts; p += kBlock) m = fmax(m, part[p]);
+  m = block_max<kBlock>(m, sh);
+  if (blockIdx.x == 0 && threadIdx.x == 0) *ref_out = m;
+  for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlock) {
+    const double v = lw[j];
+    lw2[j] = (bnd[j] || v == -INFINITY || m == -INFINITY) ? -INFINITY : (float)((v - m) * kLog2e);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// (3a) pairwise kernel on the vector ALUs (plain FP32 direct differences).
+// Block: 64 targets x 64 sources, 256 threads, each thread 4 targets x 4
+// sources x S scales.  The source range of one block is [j_begin, j_end).
+// Each thread keeps its own running (max, sum) per (target, scale) across all
+// its source tiles; the 16 threads that share targets merge at the end.
+constexpr int kVI = 64, kVJ = 64;
+
+template <int S, int KC>
+__global__ void __launch_bounds__(256) k_pair_valu(PairArgs a, int64_t j_per_split,
+                                                   double tau0, double tau1, double tau2, double tau3,
+                                                   double tau4, double tau5, double kd0, double kd1,
+                                                   double kd2, double kd3, double kd4, double kd5) {
+  __shared__ float sxi[KC][kVI + 4];
+  __shared__ float sxj[KC][kVJ + 4];
+  __shared__ float sfj[KC][kVJ + 4];
+  __shared__ float slw[kVJ];
+  const int tid = threadIdx.x;
+  const int ti = tid >> 4, tj = tid & 15;
+  const int64_t n = a.n;
+  const int64_t i0 = (int64_t)blockIdx.x * kVI;
+  const int64_t jb = (int64_t)blockIdx.y * j_per_split;
+  const int64_t je = jb + j_per_split < n ? jb + j_per_split : n;
+  const double taud[6] = {tau0, tau1, tau2, tau3, tau4, tau5};
+  const double kapd[6] = {kd0, kd1, kd2, kd3, kd4, kd5};
+
+  float M[4][S], Ssum[4][S];
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      M[p][s] = -INFINITY;
+      Ssum[p][s] = 0.f;
+    }
+  float tau[S], kap[S];
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    tau[s] = a.tau[s];
+    kap[s] = a.kap2[s];
+  }
+
+  for (int64_t j0 = jb; j0 < je; j0 += kVJ) {
+    float acc[4][4][S];
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int s = 0; s < S; ++s) acc[p][q][s] = 0.f;
+    __syncthreads();
+    if (tid < kVJ) slw[tid] = (j0 + tid < je) ? a.lw2[j0 + tid] : -INFINITY;
+    for (int k0 = 0; k0 < a.r; k0 += KC) {
+      __syncthreads();
+      // load KC dims of 64 targets and 64 sources (zero outside the ranges)
+      for (int e = tid; e < 64 * KC; e += 256) {
+        const int row = e / KC, kk = e % KC;
+        const int k = k0 + kk;
+        const int64_t gi = i0 + row, gj = j0 + row;
+        sxi[kk][row] = (gi < n && k < a.r) ? a.xc[(size_t)gi * a.rp + k] : 0.f;
+        const bool vj = (gj < je && k < a.r);
+        sxj[kk][row] = vj ? a.xc[(size_t)gj * a.rp + k] : 0.f;
+        sfj[kk][row] = vj ? a.f[(size_t)gj * a.rp + k] : 0.f;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int kk = 0; kk < KC; ++kk) {
+        const float4 xi = *reinterpret_cast<const float4*>(&sxi[kk][ti * 4]);
+        const float4 xj = *reinterpret_cast<const float4*>(&sxj[kk][tj * 4]);
+        const float4 fj = *reinterpret_cast<const float4*>(&sfj[kk][tj * 4]);
+        const float xia[4] = {xi.x, xi.y, xi.z, xi.w};
+        const float xja[4] = {xj.x, xj.y, xj.z, xj.w};
+        const float fja[4] = {fj.x, fj.y, fj.z, fj.w};
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const float d = xia[p] - xja[q];
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+              const float e = fmaf(-tau[s], fja[q], d);
+              acc[p][q][s] = fmaf(e, e, acc[p][q][s]);
+            }
+          }
+      }
+    }
+    // exponents and the running (max, sum)
+    const bool diag = (j0 < i0 + kVI) && (i0 < j0 + kVJ);
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      const int64_t gi = i0 + ti * 4 + p;
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        float ev[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int64_t gj = j0 + tj * 4 + q;
+          float e = slw[tj * 4 + q] - kap[s] * acc[p][q][s];
+          if (diag && gj == gi && gi < n) {
+            // self pair: |tau_s f(x_i)|^2 from the FP64 norm
+            e = slw[tj * 4 + q] - (float)(kapd[s] * taud[s] * taud[s] * a.node[n + gi]);
+          }
+          ev[q] = e;
+        }
+        const float m = fmaxf(fmaxf(ev[0], ev[1]), fmaxf(ev[2], ev[3]));
+        if (m == -INFINITY) continue;
+        if (m > M[p][s]) {
+          Ssum[p][s] *= exp2f(M[p][s] - m);
+          M[p][s] = m;
+        }
+        float t = 0.f;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) t += exp2f(ev[q] - M[p][s]);
+        Ssum[p][s] += t;
+      }
+    }
+  }
+  // merge the 16 threads (consecutive lanes) that share the same targets
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      float m = M[p][s], sm = Ssum[p][s];
+#pragma unroll
+      for (int off = 1; off < 16; off <<= 1) {
+        const float mo = __shfl_xor(m, off, 64);
+        const float so = __shfl_xor(sm, off, 64);
+        lse2_merge(m, sm, mo, so);
+      }
+      M[p][s] = m;
+      Ssum[p][s] = sm;
+    }
+  if (tj == 0) {
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      const int64_t gi = i0 + ti * 4 + p;
+      if (gi >= n) continue;
+#pragma unroll
+      for (int s = 0; s < S; ++s)
+        a.part[((size_t)blockIdx.y * S + s) * n + gi] = make_float2(M[p][s], Ssum[p][s]);
+    }
+  }
+}
+
+template <int S>
+static yy_status launch_valu_s(hipStream_t st, const PairArgs& a, const double* taud,
+                               const double* kapd) {
+  const int64_t tiles = (a.n + kVI - 1) / kVI;
+  const int64_t jtiles = (a.n + kVJ - 1) / kVJ;
+  const int64_t per = ((jtiles + a.nsplit - 1) / a.nsplit) * kVJ;
+  dim3 grid((unsigned)tiles, (unsigned)a.nsplit);
+#define YY_VALU_LAUNCH(KC)                                                                      \
+  k_pair_valu<S, KC><<<grid, 256, 0, st>>>(a, per, taud[0], taud[1], taud[2], taud[3], taud[4], \
+                                           taud[5], kapd[0], kapd[1], kapd[2], kapd[3], kapd[4], \
+                                           kapd[5])
+  if (a.r <= 2) YY_VALU_LAUNCH(2);
+  else if (a.r <= 4) YY_VALU_LAUNCH(4);
+  else if (a.r <= 8) YY_VALU_LAUNCH(8);
+  else YY_VALU_LAUNCH(16);
+#undef YY_VALU_LAUNCH
+  YY_LAUNCH_CHECK("k_pair_valu");
+  return YY_OK;
+}
+
+static yy_status launch_pair_valu_d(hipStream_t st, const PairArgs& a, const double* taud,
+                                    const double* kapd) {
+  switch (a.S) {
+    case 1: return launch_valu_s<1>(st, a, taud, kapd);
+    case 2: return launch_valu_s<2>(st, a, taud, kapd);
+    case 3: return launch_valu_s<3>(st, a, taud, kapd);
+    case 4: return launch_valu_s<4>(st, a, taud, kapd);
+    case 5: return launch_valu_s<5>(st, a, taud, kapd);
+    case 6: return launch_valu_s<6>(st, a, taud, kapd);
+  }
+  return fail(YY_ERR_ARG, "bad scale count");
+}
+
+// ---------------------------------------------------------------------------
+// (4) combination in FP64: merge the source splits, add the constants, signed
+// log-sum-exp over the scales and the identity term.
+struct CombineArgs {
+  int64_t n;
+  int32_t S, nsplit;
+  double kap[YY_MAX_SCALES];       // log|c_s| - log n - (r/2) log(2 pi q tau_s)
+  double sign[YY_MAX_SCALES + 1];  // sign(c_s), 0 for c_s = 0
+  double logc_id;                  // log|c_S|
+  const float2* part;
+  const double* scal;              // [0] = log vol(box)
+  const double* lref;              // max source log-weight
+  const double* logw_in;
+  const int* bnd;
+  double* logw_out;
+  uint32_t* flags;
+  unsigned long long* nclamped;
+};
+
+__global__ void __launch_bounds__(kBlock) k_combine(CombineArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= a.n) return;
+  if (a.bnd[i]) {
+    a.logw_out[i] = -INFINITY;
+    return;
+  }
+  const double logvol = a.scal[0];
+  const double lref = *a.lref;
+  double T[YY_MAX_SCALES + 1], sg[YY_MAX_SCALES + 1];
+  int nt = 0;
+  for (int s = 0; s < a.S; ++s) {
+    if (a.sign[s] == 0.0 || lref == -INFINITY) continue;
+    float M = -INFINITY;
+    for (int p = 0; p < a.nsplit; ++p) M = fmaxf(M, a.part[((size_t)p * a.S + s) * a.n + i].x);
+    if (M == -INFINITY) continue;
+    double sum = 0.0;
+    for (int p = 0; p < a.nsplit; ++p) {
+      const float2 v = a.part[((size_t)p * a.S + s) * a.n + i];
+      if (v.x != -INFINITY) sum += (double)v.y * exp2((double)v.x - (double)M);
+    }
+    const double L = ((double)M + log2(sum)) * kLn2 + lref;
+    T[nt] = a.kap[s] + logvol + L;
+    sg[nt] = a.sign[s];
+    ++nt;
+  }
+  const double li = a.logw_in[i];
+  if (a.sign[a.S] != 0.0 && li != -INFINITY) {
+    T[nt] = a.logc_id + li;
+    sg[nt] = a.sign[a.S];
+    ++nt;
+  }
+  if (nt == 0) {
+    a.logw_out[i] = -INFINITY;
+    return;
+  }
+  double Mx = T[0];
+  for (int t = 1; t < nt; ++t) Mx = fmax(Mx, T[t]);
+  double acc = 0.0;
+  for (int t = 0; t < nt; ++t) acc += sg[t] * exp(T[t] - Mx);
+  if (!(acc > 0.0)) {
+    a.logw_out[i] = -INFINITY;
+    atomicOr(a.flags, YY_FLAG_CLAMPED);
+    atomicAdd(a.nclamped, 1ULL);
+    return;
+  }
+  a.logw_out[i] = Mx + log(acc);
+}
+
+// ---------------------------------------------------------------------------
+int pair_mfma_rp(int32_t r) { return ((r + 63) / 64) * 64; }
+
+yy_status prepare_nodes(yy_ctx ctx, const yy_model* m, int64_t n, const double* x,
+                        uint64_t version, const double* lo, const double* hi, bool want_bf16) {
+  Prepared& P = ctx->prep;
+  const bool same = P.valid && P.x == x && P.n == n && P.r == m->r && P.drift == m->drift &&
+                    P.A == m->A && P.version == version && P.lo == lo && P.hi == hi &&
+                    (P.have_bf16 || !want_bf16);
+  if (same) return YY_OK;
+  const int32_t rp = pair_mfma_rp(m->r);
+  yy_status st;
+  if ((st = P.xc32.ensure((size_t)n * rp * sizeof(float))) != YY_OK) return st;
+  if ((st = P.f32.ensure((size_t)n * rp * sizeof(float))) != YY_OK) return st;
+  if (want_bf16 && (st = P.bf.ensure((size_t)4 * n * rp * sizeof(uint16_t))) != YY_OK) return st;
+  if ((st = P.node.ensure((size_t)3 * n * sizeof(double))) != YY_OK) return st;
+  if ((st = P.bnd.ensure((size_t)n * sizeof(int))) != YY_OK) return st;
+  if ((st = P.scal.ensure(8 * sizeof(double))) != YY_OK) return st;
+  int64_t blocks = (n + 3) / 4;
+  if (blocks > 16384) blocks = 16384;
+  k_prepare<<<(unsigned)blocks, kBlock, 0, ctx->stream>>>(
+      n, m->r, rp, m->drift, m->A, x, lo, hi, P.xc32.as<float>(), P.f32.as<float>(),
+      want_bf16 ? P.bf.as<uint16_t>() : nullptr, P.node.as<double>(), P.bnd.as<int>());
+  YY_LAUNCH_CHECK("k_prepare");
+  k_prepare_scalars<<<1, kBlock, 0, ctx->stream>>>(n, m->r, lo, hi, P.node.as<double>(),
+                                                   P.scal.as<double>());
+  YY_LAUNCH_CHECK("k_prepare_scalars");
+  P.valid = true;
+  P.x = x;
+  P.n = n;
+  P.r = m->r;
+  P.rp = rp;
+  P.drift = m->drift;
+  P.A = m->A;
+  P.version = version;
+  P.lo = lo;
+  P.hi = hi;
+  P.have_bf16 = want_bf16;
+  return YY_OK;
+}
+
+static yy_status check_model(const yy_model* m) {
+  if (!m) return fail(YY_ERR_ARG, "model is NULL");
+  if (m->r < 1 || m->r > YY_MAX_R) return fail(YY_ERR_ARG, "model r out of range");
+  if (m->drift < YY_F_ZERO || m->drift > YY_F_LINEAR) return fail(YY_ERR_ARG, "unknown drift");
+  if (m->drift == YY_F_LINEAR && !m->A) return fail(YY_ERR_ARG, "linear drift needs A");
+  if (m->obs < YY_H_IDENTITY || m->obs > YY_H_LINEAR) return fail(YY_ERR_ARG, "unknown observation");
+  if (m->obs == YY_H_LINEAR && !m->H) return fail(YY_ERR_ARG, "linear observation needs H");
+  if (m->obs != YY_H_LINEAR && m->m != m->r) return fail(YY_ERR_ARG, "m must equal r for this h");
+  if (m->m < 1) return fail(YY_ERR_ARG, "m must be positive");
+  if (!(m->q > 0.0) || !(m->rho2 > 0.0)) return fail(YY_ERR_ARG, "noise variances must be positive");
+  return YY_OK;
+}
+
+yy_status validate_model(const yy_model* m) { return check_model(m); }
+
+}  // namespace yy
+
+using namespace yy;
+
+extern "C" yy_status yy_propagate(yy_ctx ctx, const yy_model* model, const yy_scales* scales,
+                                  int32_t prec, int64_t n, const double* x, uint64_t node_version,
+                                  const double* box_lo, const double* box_hi, double dt,
+                                  const double* logw_in, double* logw_out) {
+  if (!ctx) return fail(YY_ERR_ARG, "yy_propagate: ctx is NULL");
+  yy_status st = check_model(model);
+  if (st != YY_OK) return st;
+  if (!scales || scales->S < 1 || scales->S > YY_MAX_SCALES || !scales->s)
+    return fail(YY_ERR_ARG, "yy_propagate: bad scales");
+  if (n < 0) return fail(YY_ERR_ARG, "yy_propagate: n < 0");
+  if (n > ((int64_t)1 << 31)) return fail(YY_ERR_UNSUPPORTED, "yy_propagate: n above 2^31");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(YY_ERR_ARG, "yy_propagate: dt must be positive");
+  if (n == 0) return YY_OK;
+  if (!x || !box_lo || !box_hi || !logw_in || !logw_out)
+    return fail(YY_ERR_ARG, "yy_propagate: NULL array");
+  if (logw_in == logw_out) return fail(YY_ERR_ARG, "yy_propagate: logw_in and logw_out alias");
+  if (prec < YY_PREC_AUTO || prec > YY_PREC_BF16X1) return fail(YY_ERR_ARG, "yy_propagate: bad prec");
+  const int32_t S = scales->S;
+  double c[YY_MAX_SCALES + 1];
+  for (int s = 0; s < S; ++s)
+    if (!(scales->s[s] > 0.0)) return fail(YY_ERR_ARG, "yy_propagate: scale divisors must be > 0");
+  if (scales->c) {
+    for (int s = 0; s <= S; ++s) c[s] = scales->c[s];
+  } else if ((st = coefficients_cramer(S, scales->s, c)) != YY_OK) {
+    return st;
+  }
+  const int32_t r = model->r;
+  if (prec == YY_PREC_AUTO) prec = r < 32 ? YY_PREC_FP32 : YY_PREC_BF16X3;
+  const bool mfma = prec != YY_PREC_FP32;
+  YY_HIP(hipSetDevice(ctx->device));
+  st = prepare_nodes(ctx, model, n, x, node_version, box_lo, box_hi,
+                     prec == YY_PREC_BF16X3 || prec == YY_PREC_BF16X1);
+  if (st != YY_OK) return st;
+  const Prepared& P = ctx->prep;
+
+  // (2) source weights relative to their maximum
+  const int nparts = (int)std::min<int64_t>((n + kBlock - 1) / kBlock, 1024);
+  if ((st = ctx->red.ensure((size_t)(nparts + 8) * sizeof(double))) != YY_OK) return st;
+  if ((st = ctx->lw2.ensure((size_t)n * sizeof(float))) != YY_OK) return st;
+  double* d_part = ctx->red.as<double>();
+  double* d_lref = d_part + nparts;
+  k_lw_max<<<nparts, kBlock, 0, ctx->stream>>>(n, logw_in, P.bnd.as<int>(), d_part);
+  YY_LAUNCH_CHECK("k_lw_max");
+  k_lw_convert<<<nparts, kBlock, 0, ctx->stream>>>(n, nparts, d_part, logw_in, P.bnd.as<int>(),
+                                                   ctx->lw2.as<float>(), d_lref);
+  YY_LAUNCH_CHECK("k_lw_convert");
+
+  // (3) pairwise partials
+  PairArgs a{};
+  a.n = n;
+  a.r = r;
+  a.rp = P.rp;
+  a.S = S;
+  double taud[6] = {0, 0, 0, 0, 0, 0}, kapd[6] = {0, 0, 0, 0, 0, 0};
+  for (int s = 0; s < S; ++s) {
+    taud[s] = dt / scales->s[s];
+    kapd[s] = kLog2e / (2.0 * model->q * taud[s]);
+    a.tau[s] = (float)taud[s];
+    a.kap2[s] = (float)kapd[s];
+  }
+  a.xc = P.xc32.as<float>();
+  a.f = P.f32.as<float>();
+  a.lw2 = ctx->lw2.as<float>();
+  a.node = P.node.as<double>();
+  a.bnd = P.bnd.as<int>();
+  a.bf = P.have_bf16 ? P.bf.as<uint16_t>() : nullptr;
+  a.scal = P.scal.as<double>();
+  // enough blocks to cover the chip: split the source range when targets are few
+  const int64_t ttiles = (n + kVI - 1) / kVI;
+  int nsplit = 1;
+  while (ttiles * nsplit < 512 && nsplit < 64 && (int64_t)nsplit * kVJ * 2 <= n) nsplit *= 2;
+  if (mfma) nsplit = 1;
+  a.nsplit = nsplit;
+  if ((st = ctx->part.ensure((size_t)nsplit * S * n * sizeof(float2))) != YY_OK) return st;
+  a.part = ctx->part.as<float2>();
+  if ((st = timing_begin(ctx)) != YY_OK) return st;
+  if (mfma) {
+    st = launch_pair_mfma(ctx->stream, a, prec);
+  } else {
+    st = launch_pair_valu_d(ctx->stream, a, taud, kapd);
+  }
+  if (st != YY_OK) return st;
+  if ((st = timing_end(ctx)) != YY_OK) return st;
+
+  // (4) combination
+  CombineArgs cb{};
+  cb.n = n;
+  cb.S = S;
+  cb.nsplit = a.nsplit;
+  for (int s = 0; s < S; ++s) {
+    cb.kap[s] = (c[s] != 0.0 ? std::log(std::fabs(c[s])) : 0.0) - std::log((double)n) -
+                0.5 * r * std::log(2.0 * M_PI * model->q * taud[s]);
+    cb.sign[s] = c[s] > 0 ? 1.0 : (c[s] < 0 ? -1.0 : 0.0);
+  }
+  cb.sign[S] = c[S] > 0 ? 1.0 : (c[S] < 0 ? -1.0 : 0.0);
+  cb.logc_id = c[S] != 0.0 ? std::log(std::fabs(c[S])) : 0.0;
+  cb.part = a.part;
+  cb.scal = P.scal.as<double>();
+  cb.lref = d_lref;
+  cb.logw_in = logw_in;
+  cb.bnd = P.bnd.as<int>();
+  cb.logw_out = logw_out;
+  cb.flags = ctx->d_flags;
+  cb.nclamped = ctx->d_nclamped;
+  k_combine<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, ctx->stream>>>(cb);
+  YY_LAUNCH_CHECK("k_combine");
+  return YY_OK;
+}

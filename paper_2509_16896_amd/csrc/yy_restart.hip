@@ -1,0 +1,193 @@
+// yy_restart.hip -- the local resample-restart (Sec. 6): integer systematic
+// resampling of the normalised weights, a new box [mean - R, mean + R]^r,
+// the pre-generated reference codes mapped to that box, and the restart prior
+// (the initial density re-centred at the estimate).
+#include <algorithm>
+#include <cmath>
+
+#include "yy_common.h"
+#include "yy_internal.h"
+
+namespace yy {
+
+static const uint64_t kDomainResample = 2ULL;
+
+static uint64_t h_sm64(uint64_t seed, uint64_t counter) {
+  uint64_t z = seed + (counter + 1ULL) * 0x9E3779B97F4A7C15ULL;
+  z ^= z >> 30;
+  z *= 0xBF58476D1CE4E5B9ULL;
+  z ^= z >> 27;
+  z *= 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+// Integer weights W_i = floor(w_i 2^53) and their inclusive prefix sums within
+// each block of kBlock elements; block totals go to `tot`.
+__global__ void __launch_bounds__(kBlock) k_rs_local(int64_t n, const double* __restrict__ w,
+                                                     unsigned long long* __restrict__ C,
+                                                     unsigned long long* __restrict__ tot) {
+  __shared__ unsigned long long s[kBlock];
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  unsigned long long v = 0;
+  if (i < n) {
+    const double wi = w[i] > 0.0 ? w[i] : 0.0;
+    v = (unsigned long long)floor(wi * 0x1p53);
+  }
+  s[threadIdx.x] = v;
+  __syncthreads();
+  for (int off = 1; off < kBlock; off <<= 1) {  // Hillis-Steele inclusive scan
+    unsigned long long t = threadIdx.x >= off ? s[threadIdx.x - off] : 0ULL;
+    __syncthreads();
+    s[threadIdx.x] += t;
+    __syncthreads();
+  }
+  if (i < n) C[i] = s[threadIdx.x];
+  if (threadIdx.x == kBlock - 1) tot[blockIdx.x] = s[kBlock - 1];
+}
+
+// Exclusive offsets of the block totals (one thread, integer sums).
+__global__ void k_rs_offsets(int nb, unsigned long long* __restrict__ tot) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  unsigned long long run = 0;
+  for (int b = 0; b < nb; ++b) {
+    const unsigned long long t = tot[b];
+    tot[b] = run;
+    run += t;
+  }
+  tot[nb] = run;  // W
+}
+
+__global__ void __launch_bounds__(kBlock) k_rs_add(int64_t n, const unsigned long long* __restrict__ tot,
+                                                   unsigned long long* __restrict__ C) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) C[i] += tot[blockIdx.x];
+}
+
+// P_t = floor((t 2^32 + U) W / (n 2^32)); idx[t] = min{i : C_i > P_t}.
+// The 119-bit product is formed from 64-bit halves; the quotient is taken as
+// floor(floor(A W / 2^32) / n) with a 96-by-32-bit long division.
+__global__ void __launch_bounds__(kBlock) k_rs_search(int64_t n, int nb,
+                                                      const unsigned long long* __restrict__ tot,
+                                                      const unsigned long long* __restrict__ C,
+                                                      uint64_t U, int64_t* __restrict__ idx,
+                                                      uint32_t* __restrict__ flags) {
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const unsigned long long W = tot[nb];
+  if (W == 0ULL) {
+    if (t == 0) atomicOr(flags, YY_FLAG_RESAMPLE_ZERO);
+    return;
+  }
+  if (t >= n) return;
+  const uint64_t A = ((uint64_t)t << 32) + U;
+  const uint64_t lo = A * W;
+  const uint64_t hi = __umul64hi(A, W);
+  // X = (hi:lo) >> 32, at most 86 bits: three 32-bit digits x2 x1 x0.
+  const uint64_t x0 = (lo >> 32) & 0xFFFFFFFFULL;
+  const uint64_t x1 = hi & 0xFFFFFFFFULL;
+  const uint64_t x2 = hi >> 32;
+  const uint64_t d = (uint64_t)n;
+  // P < W <= 2^54, so the top quotient digit x2 / n is zero and the
+  // remainders below stay under n < 2^32.
+  uint64_t rem = x2 % d;
+  uint64_t cur = (rem << 32) | x1;
+  const uint64_t q1 = cur / d;
+  rem = cur % d;
+  cur = (rem << 32) | x0;
+  const uint64_t q0 = cur / d;
+  const uint64_t P = (q1 << 32) + q0;
+  int64_t lo_i = 0, hi_i = n - 1;  // C[n-1] = W > P, so the answer exists
+  while (lo_i < hi_i) {
+    const int64_t mid = (lo_i + hi_i) >> 1;
+    if (C[mid] > P) hi_i = mid;
+    else lo_i = mid + 1;
+  }
+  idx[t] = lo_i;
+}
+
+// New box, nodes and prior.  One wavefront per node; the box is recomputed
+// per coordinate exactly as the node map defines it (no fused multiply-add).
+__global__ void __launch_bounds__(kBlock) k_restart_nodes(int64_t n, int32_t r, double R,
+                                                          const uint32_t* __restrict__ codes,
+                                                          const double* __restrict__ mean,
+                                                          double* __restrict__ box_lo,
+                                                          double* __restrict__ box_hi,
+                                                          double* __restrict__ x_new,
+                                                          double* __restrict__ logw_new) {
+#pragma clang fp contract(off)
+  const int lane = threadIdx.x & 63;
+  const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t wave = gt >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  if (gt < r) {
+    box_lo[gt] = __dsub_rn(mean[gt], R);
+    box_hi[gt] = __dadd_rn(mean[gt], R);
+  }
+  for (int64_t i = wave; i < n; i += nwaves) {
+    double acc = 0.0;
+    int b = 0;
+    for (int32_t k = lane; k < r; k += 64) {
+      const double lo = __dsub_rn(mean[k], R), hi = __dadd_rn(mean[k], R);
+      const double c = __dmul_rn(0.5, __dadd_rn(lo, hi));
+      const double hw = __dmul_rn(0.5, __dsub_rn(hi, lo));
+      const double u = __dsub_rn((double)codes[(size_t)i * r + k] * 0x1p-31, 1.0);
+      const double xv = __dadd_rn(c, __dmul_rn(hw, u));
+      x_new[(size_t)i * r + k] = xv;
+      b |= (fabs(xv - lo) <= kBoundaryTol) || (fabs(hi - xv) <= kBoundaryTol);
+      const double dv = __dsub_rn(xv, mean[k]);
+      acc = __dadd_rn(acc, __dmul_rn(dv, dv));
+    }
+    acc = wave_sum(acc);
+    b = wave_or(b);
+    if (lane == 0) logw_new[i] = b ? -INFINITY : -0.5 * acc;
+  }
+}
+
+__global__ void k_ess_check(const double* __restrict__ ess, double ess_min, uint32_t* __restrict__ flags) {
+  if (threadIdx.x == 0 && blockIdx.x == 0 && *ess < ess_min) atomicOr(flags, YY_FLAG_LOW_ESS);
+}
+
+}  // namespace yy
+
+using namespace yy;
+
+extern "C" yy_status yy_restart(yy_ctx ctx, int64_t n, int32_t r, const uint32_t* codes,
+                                const double* w, const double* mean, const double* ess, int64_t step,
+                                const yy_restart_params* params, int64_t* idx, double* box_lo,
+                                double* box_hi, double* x_new, double* logw_new) {
+  if (!ctx) return fail(YY_ERR_ARG, "yy_restart: ctx is NULL");
+  if (!params) return fail(YY_ERR_ARG, "yy_restart: params is NULL");
+  if (n < 1 || n > ((int64_t)1 << 32)) return fail(YY_ERR_ARG, "yy_restart: n out of range");
+  if (r < 1 || r > YY_MAX_R) return fail(YY_ERR_ARG, "yy_restart: r out of range");
+  if (!(params->R > 0.0) || !std::isfinite(params->R)) return fail(YY_ERR_ARG, "yy_restart: R must be positive");
+  if (!codes || !mean || !box_lo || !box_hi || !x_new || !logw_new)
+    return fail(YY_ERR_ARG, "yy_restart: NULL array");
+  if (idx && !w) return fail(YY_ERR_ARG, "yy_restart: resampling needs w");
+  YY_HIP(hipSetDevice(ctx->device));
+  if (ess) {
+    k_ess_check<<<1, 64, 0, ctx->stream>>>(ess, params->ess_min, ctx->d_flags);
+    YY_LAUNCH_CHECK("k_ess_check");
+  }
+  if (idx) {
+    const int nb = (int)((n + kBlock - 1) / kBlock);
+    yy_status st = ctx->scan.ensure(((size_t)n + nb + 1) * sizeof(unsigned long long));
+    if (st != YY_OK) return st;
+    unsigned long long* C = ctx->scan.as<unsigned long long>();
+    unsigned long long* tot = C + n;
+    k_rs_local<<<nb, kBlock, 0, ctx->stream>>>(n, w, C, tot);
+    YY_LAUNCH_CHECK("k_rs_local");
+    k_rs_offsets<<<1, 64, 0, ctx->stream>>>(nb, tot);
+    YY_LAUNCH_CHECK("k_rs_offsets");
+    k_rs_add<<<nb, kBlock, 0, ctx->stream>>>(n, tot, C);
+    YY_LAUNCH_CHECK("k_rs_add");
+    const uint64_t U = h_sm64(h_sm64(params->seed, kDomainResample), (uint64_t)step) >> 32;
+    k_rs_search<<<nb, kBlock, 0, ctx->stream>>>(n, nb, tot, C, U, idx, ctx->d_flags);
+    YY_LAUNCH_CHECK("k_rs_search");
+  }
+  int64_t blocks = (n + 3) / 4;
+  if (blocks > 16384) blocks = 16384;
+  if (blocks * kBlock < r) blocks = (r + kBlock - 1) / kBlock;
+  k_restart_nodes<<<(unsigned)blocks, kBlock, 0, ctx->stream>>>(n, r, params->R, codes, mean, box_lo,
+                                                                box_hi, x_new, logw_new);
+  YY_LAUNCH_CHECK("k_restart_nodes");
+  return YY_OK;
+}

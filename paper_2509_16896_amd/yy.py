@@ -1,0 +1,216 @@
+"""Python binding of libyy (the C ABI in include/yy.h) -- argument marshalling only.
+
+Each ``yy_*`` function here calls the C function of the same name: tensors are
+passed as device pointers (torch supplies device memory and streams, nothing
+else), scalars and small host arrays are converted to C types, and a non-OK
+status raises ``YYError`` with the library's error text.  Every step of the
+filter runs in the library's HIP kernels.  There is no fallback: if libyy.so
+is missing or fails to load, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libyy.so")
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"libyy.so not found at {LIB_PATH}; build it with paper_2509_16896_amd/build.py")
+_lib = ctypes.CDLL(LIB_PATH)
+
+YY_OK, YY_ERR_ARG, YY_ERR_ALLOC, YY_ERR_HIP, YY_ERR_NUMERIC, YY_ERR_UNSUPPORTED = range(6)
+YY_FLAG_ALL_ZERO, YY_FLAG_CLAMPED, YY_FLAG_RESAMPLE_ZERO, YY_FLAG_LOW_ESS = 1, 2, 4, 8
+YY_F_ZERO, YY_F_COS, YY_F_LINEAR = 0, 1, 2
+YY_H_IDENTITY, YY_H_CUBE, YY_H_LINEAR = 0, 1, 2
+YY_PREC_AUTO, YY_PREC_FP32, YY_PREC_FP32_MFMA, YY_PREC_BF16X3, YY_PREC_BF16X1 = 0, 1, 2, 3, 4
+PREC_BY_NAME = {"auto": YY_PREC_AUTO, "fp32": YY_PREC_FP32, "fp32_mfma": YY_PREC_FP32_MFMA,
+                "bf16x3": YY_PREC_BF16X3, "bf16x1": YY_PREC_BF16X1}
+EXPORTED = ["yy_last_error", "yy_create", "yy_destroy", "yy_set_stream", "yy_get_status",
+            "yy_kernel_coefficients", "yy_nodes_sobol", "yy_propagate", "yy_loglik_update",
+            "yy_normalise_moments", "yy_restart", "yy_timing_enable", "yy_timing_read"]
+
+
+class YYError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        text = _lib.yy_last_error().decode(errors="replace")
+        super().__init__(f"{where} failed with status {status}: {text}")
+
+
+class yy_model(ctypes.Structure):
+    _fields_ = [("r", ctypes.c_int32), ("m", ctypes.c_int32), ("drift", ctypes.c_int32),
+                ("A", ctypes.c_void_p), ("obs", ctypes.c_int32), ("H", ctypes.c_void_p),
+                ("h_shift", ctypes.c_double), ("q", ctypes.c_double), ("rho2", ctypes.c_double)]
+
+
+class yy_scales(ctypes.Structure):
+    _fields_ = [("S", ctypes.c_int32), ("s", ctypes.POINTER(ctypes.c_double)),
+                ("c", ctypes.POINTER(ctypes.c_double))]
+
+
+class yy_restart_params(ctypes.Structure):
+    _fields_ = [("R", ctypes.c_double), ("ess_min", ctypes.c_double), ("seed", ctypes.c_uint64)]
+
+
+_P, _i32, _i64, _u64, _f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double
+_lib.yy_last_error.restype = ctypes.c_char_p
+_lib.yy_last_error.argtypes = []
+for _name, _args in {
+    "yy_create": [ctypes.POINTER(_P), ctypes.c_int, _P],
+    "yy_destroy": [_P],
+    "yy_set_stream": [_P, _P],
+    "yy_get_status": [_P, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(_i64)],
+    "yy_kernel_coefficients": [_i32, ctypes.POINTER(_f64), ctypes.POINTER(_f64)],
+    "yy_nodes_sobol": [_P, _i32, _i64, _i64, _i32, _u64, _P, _P, _P, _P],
+    "yy_propagate": [_P, ctypes.POINTER(yy_model), ctypes.POINTER(yy_scales), _i32, _i64, _P, _u64,
+                     _P, _P, _f64, _P, _P],
+    "yy_loglik_update": [_P, ctypes.POINTER(yy_model), _i64, _P, _P, _f64, _P],
+    "yy_normalise_moments": [_P, _i64, _i32, _P, _P, _P, _P, _P, _P, _P, _P],
+    "yy_restart": [_P, _i64, _i32, _P, _P, _P, _P, _i64, ctypes.POINTER(yy_restart_params), _P, _P,
+                   _P, _P, _P],
+    "yy_timing_enable": [_P, _i32],
+    "yy_timing_read": [_P, ctypes.POINTER(_f64), ctypes.POINTER(_i64)],
+}.items():
+    _fn = getattr(_lib, _name)
+    _fn.argtypes = _args
+    _fn.restype = ctypes.c_int
+
+
+def _check(status: int, where: str):
+    if status != YY_OK:
+        raise YYError(status, where)
+
+
+def _dptr(t, dtype=None, numel=None, name="array"):
+    """Device pointer of a contiguous CUDA/HIP tensor (None -> NULL)."""
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype and not (dtype == torch.uint32 and t.dtype == torch.int32):
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if numel is not None and t.numel() < numel:
+        raise ValueError(f"{name} has {t.numel()} elements, needs {numel}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_handle(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Model:
+    """Host description of yy_model; keeps A/H device tensors alive."""
+
+    def __init__(self, r, m=None, drift=YY_F_COS, A=None, obs=YY_H_CUBE, H=None, h_shift=0.0, q=1.0,
+                 rho2=1.0, device="cuda"):
+        self.A = None if A is None else torch.as_tensor(A, dtype=torch.float64, device=device).contiguous()
+        self.H = None if H is None else torch.as_tensor(H, dtype=torch.float64, device=device).contiguous()
+        m = int(m if m is not None else (self.H.shape[0] if self.H is not None else r))
+        self.c = yy_model(int(r), m, int(drift), None if self.A is None else self.A.data_ptr(), int(obs),
+                          None if self.H is None else self.H.data_ptr(), float(h_shift), float(q), float(rho2))
+
+    @property
+    def r(self):
+        return self.c.r
+
+    @property
+    def m(self):
+        return self.c.m
+
+
+class Scales:
+    def __init__(self, s, c=None):
+        self._s = (ctypes.c_double * len(s))(*[float(v) for v in s])
+        self._c = None if c is None else (ctypes.c_double * (len(s) + 1))(*[float(v) for v in c])
+        self.c = yy_scales(len(s), self._s, self._c)
+
+
+def yy_kernel_coefficients(s) -> list:
+    S = len(s)
+    sa = (ctypes.c_double * S)(*[float(v) for v in s])
+    ca = (ctypes.c_double * (S + 1))()
+    _check(_lib.yy_kernel_coefficients(S, sa, ca), "yy_kernel_coefficients")
+    return list(ca)
+
+
+def yy_create(device: int = 0, stream=None):
+    ctx = ctypes.c_void_p()
+    _check(_lib.yy_create(ctypes.byref(ctx), int(device), _stream_handle(stream)), "yy_create")
+    return ctx
+
+
+def yy_destroy(ctx):
+    _check(_lib.yy_destroy(ctx), "yy_destroy")
+
+
+def yy_set_stream(ctx, stream=None):
+    _check(_lib.yy_set_stream(ctx, _stream_handle(stream)), "yy_set_stream")
+
+
+def yy_get_status(ctx):
+    flags = ctypes.c_uint32(0)
+    ncl = ctypes.c_int64(0)
+    _check(_lib.yy_get_status(ctx, ctypes.byref(flags), ctypes.byref(ncl)), "yy_get_status")
+    return int(flags.value), int(ncl.value)
+
+
+def yy_nodes_sobol(ctx, r, n, first_index, scramble, seed, box_lo, box_hi, codes=None, x=None):
+    _check(_lib.yy_nodes_sobol(ctx, int(r), int(n), int(first_index), int(bool(scramble)),
+                               int(seed) & 0xFFFFFFFFFFFFFFFF,
+                               _dptr(box_lo, torch.float64, r, "box_lo"), _dptr(box_hi, torch.float64, r, "box_hi"),
+                               _dptr(codes, torch.uint32, n * r, "codes"), _dptr(x, torch.float64, n * r, "x")),
+           "yy_nodes_sobol")
+
+
+def yy_propagate(ctx, model: Model, scales: Scales, prec, n, x, node_version, box_lo, box_hi, dt,
+                 logw_in, logw_out):
+    prec = PREC_BY_NAME[prec] if isinstance(prec, str) else int(prec)
+    r = model.r
+    _check(_lib.yy_propagate(ctx, ctypes.byref(model.c), ctypes.byref(scales.c), prec, int(n),
+                             _dptr(x, torch.float64, n * r, "x"), int(node_version) & 0xFFFFFFFFFFFFFFFF,
+                             _dptr(box_lo, torch.float64, r, "box_lo"), _dptr(box_hi, torch.float64, r, "box_hi"),
+                             float(dt), _dptr(logw_in, torch.float64, n, "logw_in"),
+                             _dptr(logw_out, torch.float64, n, "logw_out")), "yy_propagate")
+
+
+def yy_loglik_update(ctx, model: Model, n, x, dy, dt, logw):
+    _check(_lib.yy_loglik_update(ctx, ctypes.byref(model.c), int(n), _dptr(x, torch.float64, n * model.r, "x"),
+                                 _dptr(dy, torch.float64, model.m, "dy"), float(dt),
+                                 _dptr(logw, torch.float64, n, "logw")), "yy_loglik_update")
+
+
+def yy_normalise_moments(ctx, n, r, x, logw, w, logZ_step, logZ_acc, mean, cov, ess):
+    _check(_lib.yy_normalise_moments(ctx, int(n), int(r), _dptr(x, torch.float64, n * r, "x"),
+                                     _dptr(logw, torch.float64, n, "logw"), _dptr(w, torch.float64, n, "w"),
+                                     _dptr(logZ_step, torch.float64, 1, "logZ_step"),
+                                     _dptr(logZ_acc, torch.float64, 1, "logZ_acc"),
+                                     _dptr(mean, torch.float64, r, "mean"), _dptr(cov, torch.float64, r * r, "cov"),
+                                     _dptr(ess, torch.float64, 1, "ess")), "yy_normalise_moments")
+
+
+def yy_restart(ctx, n, r, codes, w, mean, ess, step, R, ess_min, seed, idx, box_lo, box_hi, x_new, logw_new):
+    params = yy_restart_params(float(R), float(ess_min), int(seed) & 0xFFFFFFFFFFFFFFFF)
+    _check(_lib.yy_restart(ctx, int(n), int(r), _dptr(codes, torch.uint32, n * r, "codes"),
+                           _dptr(w, torch.float64, n, "w"), _dptr(mean, torch.float64, r, "mean"),
+                           _dptr(ess, torch.float64, 1, "ess"), int(step), ctypes.byref(params),
+                           _dptr(idx, torch.int64, n, "idx"), _dptr(box_lo, torch.float64, r, "box_lo"),
+                           _dptr(box_hi, torch.float64, r, "box_hi"), _dptr(x_new, torch.float64, n * r, "x_new"),
+                           _dptr(logw_new, torch.float64, n, "logw_new")), "yy_restart")
+
+
+def yy_timing_enable(ctx, on: bool = True):
+    _check(_lib.yy_timing_enable(ctx, int(bool(on))), "yy_timing_enable")
+
+
+def yy_timing_read(ctx):
+    """Returns (total pairwise-kernel milliseconds, number of timed launches) and resets them."""
+    ms = ctypes.c_double(0.0)
+    cnt = ctypes.c_int64(0)
+    _check(_lib.yy_timing_read(ctx, ctypes.byref(ms), ctypes.byref(cnt)), "yy_timing_read")
+    return float(ms.value), int(cnt.value)
