@@ -272,6 +272,8 @@ yy_status yy_destroy(yy_ctx ctx) {
   ctx->prep.xc32.release();
   ctx->prep.f32.release();
   ctx->prep.bf.release();
+  ctx->prep.f32t.release();
+  ctx->bsrc.release();
   ctx->prep.node.release();
   ctx->prep.bnd.release();
   ctx->prep.scal.release();

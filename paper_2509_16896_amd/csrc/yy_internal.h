@@ -56,9 +56,12 @@ struct Prepared {
   const double* lo = nullptr;
   const double* hi = nullptr;
   bool have_bf16 = false;
+  bool have_f32t = false;
+  int64_t n_pad = 0;        // n rounded up to the matrix-core target block
   DevBuf xc32;              // float [n*rp]  x - box centre
   DevBuf f32;               // float [n*rp]  f(x)
-  DevBuf bf;                // bf16  [4][n*rp]  hi(xc), lo(xc), hi(f), lo(f)
+  DevBuf bf;                // bf16 tiled [4][rp/32][n_pad][32]: hi(xc), hi(f), lo(xc), lo(f)
+  DevBuf f32t;              // float tiled [2][rp/32][n_pad][32]: xc, f
   DevBuf node;              // double [3][n]  |xc|^2, |f|^2, xc.f
   DevBuf bnd;               // int [n]  1 = boundary node
   DevBuf scal;              // double [4]  log vol(box), max |xc|, max |f|, spare
@@ -84,6 +87,7 @@ struct yy_ctx_s {
   yy::DevBuf red;                     // reduction scratch
   yy::DevBuf red2;
   yy::DevBuf scan;                    // resampling prefix sums
+  yy::DevBuf bsrc;                    // matrix-core source biases
   // pairwise-kernel timing
   bool timing = false;
   std::vector<hipEvent_t> ev_start, ev_stop;
@@ -95,7 +99,8 @@ namespace yy {
 // Host-side pieces shared by the call implementations.
 yy_status sobol_prepare_dirs(yy_ctx ctx, int32_t r, int32_t scramble, uint64_t seed);
 yy_status prepare_nodes(yy_ctx ctx, const yy_model* model, int64_t n, const double* x,
-                        uint64_t version, const double* lo, const double* hi, bool want_bf16);
+                        uint64_t version, const double* lo, const double* hi, bool want_bf16,
+                        bool want_f32t);
 yy_status coefficients_cramer(int32_t S, const double* s, double* c);
 yy_status validate_model(const yy_model* m);
 yy_status timing_begin(yy_ctx ctx);
@@ -117,8 +122,18 @@ struct PairArgs {
   float2* part;                // [nsplit][S][n]
   int32_t nsplit;
 };
-yy_status launch_pair_valu(hipStream_t st, const PairArgs& a);
-yy_status launch_pair_mfma(hipStream_t st, const PairArgs& a, int prec);
+// Extra inputs of the matrix-core kernel.
+struct MfmaExtra {
+  int64_t n_pad;               // rows of the tiled planes (n rounded up to the target block)
+  const float* f32t;           // fp32 tiled planes (FP32 variant) or null
+  float* bsrc;                 // [S][n_pad] source biases (written by launch_src_bias)
+  int64_t j_per_split;
+  double kapd[YY_MAX_SCALES];
+  double taud[YY_MAX_SCALES];
+};
+yy_status launch_src_bias(hipStream_t st, const PairArgs& a, const MfmaExtra& ex);
+yy_status launch_pair_mfma(hipStream_t st, const PairArgs& a, int prec, const MfmaExtra& ex);
+int64_t pair_mfma_npad(int64_t n);
 int pair_mfma_rp(int32_t r);
 
 }  // namespace yy

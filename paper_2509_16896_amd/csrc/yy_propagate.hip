@@ -21,19 +21,29 @@ namespace yy {
 
 // ---------------------------------------------------------------------------
 // (1) node preparation: one wavefront per node.
-__global__ void __launch_bounds__(kBlock) k_prepare(int64_t n, int32_t r, int32_t rp, int32_t drift,
-                                                    const double* __restrict__ A,
+// Matrix-core planes are tiled [plane][rp/32][n_pad][32] so that 32 K values
+// of consecutive nodes are contiguous; rows n..n_pad-1 are zero.
+__global__ void __launch_bounds__(kBlock) k_prepare(int64_t n, int64_t n_pad, int32_t r, int32_t rp,
+                                                    int32_t drift, const double* __restrict__ A,
                                                     const double* __restrict__ x,
                                                     const double* __restrict__ lo,
                                                     const double* __restrict__ hi,
                                                     float* __restrict__ xc32, float* __restrict__ f32,
-                                                    uint16_t* __restrict__ bf, double* __restrict__ node,
-                                                    int* __restrict__ bnd) {
+                                                    uint16_t* __restrict__ bf, float* __restrict__ f32t,
+                                                    double* __restrict__ node, int* __restrict__ bnd) {
   const int lane = threadIdx.x & 63;
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-  const size_t plane = (size_t)n * rp;
-  for (int64_t i = wave; i < n; i += nwaves) {
+  const size_t plane = (size_t)n_pad * rp;
+  for (int64_t i = wave; i < n_pad; i += nwaves) {
+    if (i >= n) {
+      for (int32_t k = lane; k < rp; k += 64) {
+        const size_t t = ((size_t)(k >> 5) * n_pad + i) * 32 + (k & 31);
+        if (bf) bf[t] = bf[plane + t] = bf[2 * plane + t] = bf[3 * plane + t] = 0;
+        if (f32t) f32t[t] = f32t[plane + t] = 0.f;
+      }
+      continue;
+    }
     const double* xi = x + (size_t)i * r;
     double sxx = 0.0, sff = 0.0, sxf = 0.0;
     int b = 0;
@@ -62,15 +72,20 @@ __global__ void __launch_bounds__(kBlock) k_prepare(int64_t n, int32_t r, int32_
       const size_t o = (size_t)i * rp + k;
       xc32[o] = xcv;
       f32[o] = fv;
+      const size_t t = ((size_t)(k >> 5) * n_pad + i) * 32 + (k & 31);
       if (bf) {
         const uint16_t xh = f32_to_bf16(xcv);
         const uint16_t xl = f32_to_bf16((float)(xcd - (double)bf16_to_f32(xh)));
         const uint16_t fh = f32_to_bf16(fv);
         const uint16_t fl = f32_to_bf16((float)(fd - (double)bf16_to_f32(fh)));
-        bf[o] = xh;
-        bf[plane + o] = xl;
-        bf[2 * plane + o] = fh;
-        bf[3 * plane + o] = fl;
+        bf[t] = xh;
+        bf[plane + t] = fh;
+        bf[2 * plane + t] = xl;
+        bf[3 * plane + t] = fl;
+      }
+      if (f32t) {
+        f32t[t] = xcv;
+        f32t[plane + t] = fv;
       }
     }
     sxx = wave_sum(sxx);
@@ -391,25 +406,29 @@ __global__ void __launch_bounds__(kBlock) k_combine(CombineArgs a) {
 int pair_mfma_rp(int32_t r) { return ((r + 63) / 64) * 64; }
 
 yy_status prepare_nodes(yy_ctx ctx, const yy_model* m, int64_t n, const double* x,
-                        uint64_t version, const double* lo, const double* hi, bool want_bf16) {
+                        uint64_t version, const double* lo, const double* hi, bool want_bf16,
+                        bool want_f32t) {
   Prepared& P = ctx->prep;
   const bool same = P.valid && P.x == x && P.n == n && P.r == m->r && P.drift == m->drift &&
                     P.A == m->A && P.version == version && P.lo == lo && P.hi == hi &&
-                    (P.have_bf16 || !want_bf16);
+                    (P.have_bf16 || !want_bf16) && (P.have_f32t || !want_f32t);
   if (same) return YY_OK;
   const int32_t rp = pair_mfma_rp(m->r);
+  const int64_t n_pad = pair_mfma_npad(n);
   yy_status st;
   if ((st = P.xc32.ensure((size_t)n * rp * sizeof(float))) != YY_OK) return st;
   if ((st = P.f32.ensure((size_t)n * rp * sizeof(float))) != YY_OK) return st;
-  if (want_bf16 && (st = P.bf.ensure((size_t)4 * n * rp * sizeof(uint16_t))) != YY_OK) return st;
+  if (want_bf16 && (st = P.bf.ensure((size_t)4 * n_pad * rp * sizeof(uint16_t))) != YY_OK) return st;
+  if (want_f32t && (st = P.f32t.ensure((size_t)2 * n_pad * rp * sizeof(float))) != YY_OK) return st;
   if ((st = P.node.ensure((size_t)3 * n * sizeof(double))) != YY_OK) return st;
   if ((st = P.bnd.ensure((size_t)n * sizeof(int))) != YY_OK) return st;
   if ((st = P.scal.ensure(8 * sizeof(double))) != YY_OK) return st;
-  int64_t blocks = (n + 3) / 4;
+  int64_t blocks = (n_pad + 3) / 4;
   if (blocks > 16384) blocks = 16384;
   k_prepare<<<(unsigned)blocks, kBlock, 0, ctx->stream>>>(
-      n, m->r, rp, m->drift, m->A, x, lo, hi, P.xc32.as<float>(), P.f32.as<float>(),
-      want_bf16 ? P.bf.as<uint16_t>() : nullptr, P.node.as<double>(), P.bnd.as<int>());
+      n, n_pad, m->r, rp, m->drift, m->A, x, lo, hi, P.xc32.as<float>(), P.f32.as<float>(),
+      want_bf16 ? P.bf.as<uint16_t>() : nullptr, want_f32t ? P.f32t.as<float>() : nullptr,
+      P.node.as<double>(), P.bnd.as<int>());
   YY_LAUNCH_CHECK("k_prepare");
   k_prepare_scalars<<<1, kBlock, 0, ctx->stream>>>(n, m->r, lo, hi, P.node.as<double>(),
                                                    P.scal.as<double>());
@@ -417,6 +436,7 @@ yy_status prepare_nodes(yy_ctx ctx, const yy_model* m, int64_t n, const double* 
   P.valid = true;
   P.x = x;
   P.n = n;
+  P.n_pad = n_pad;
   P.r = m->r;
   P.rp = rp;
   P.drift = m->drift;
@@ -425,6 +445,7 @@ yy_status prepare_nodes(yy_ctx ctx, const yy_model* m, int64_t n, const double* 
   P.lo = lo;
   P.hi = hi;
   P.have_bf16 = want_bf16;
+  P.have_f32t = want_f32t;
   return YY_OK;
 }
 
@@ -478,7 +499,7 @@ extern "C" yy_status yy_propagate(yy_ctx ctx, const yy_model* model, const yy_sc
   const bool mfma = prec != YY_PREC_FP32;
   YY_HIP(hipSetDevice(ctx->device));
   st = prepare_nodes(ctx, model, n, x, node_version, box_lo, box_hi,
-                     prec == YY_PREC_BF16X3 || prec == YY_PREC_BF16X1);
+                     prec == YY_PREC_BF16X3 || prec == YY_PREC_BF16X1, prec == YY_PREC_FP32_MFMA);
   if (st != YY_OK) return st;
   const Prepared& P = ctx->prep;
 
@@ -517,14 +538,35 @@ extern "C" yy_status yy_propagate(yy_ctx ctx, const yy_model* model, const yy_sc
   // enough blocks to cover the chip: split the source range when targets are few
   const int64_t ttiles = (n + kVI - 1) / kVI;
   int nsplit = 1;
-  while (ttiles * nsplit < 512 && nsplit < 64 && (int64_t)nsplit * kVJ * 2 <= n) nsplit *= 2;
-  if (mfma) nsplit = 1;
+  MfmaExtra ex{};
+  if (mfma) {
+    // the matrix-core kernel: 256-target blocks, 128-source tiles.  16 source
+    // splits let one XCD (32 CUs, one block each) work on 2 target blocks at a
+    // time; small problems split further until 256 blocks cover the chip.
+    const int64_t n_pad = P.n_pad, tbs = n_pad / 256, jtl = (n + 127) / 128;
+    nsplit = 16;
+    while (tbs * nsplit < 256 && nsplit < 256) nsplit *= 2;
+    if (nsplit > jtl) nsplit = (int)jtl;
+    ex.n_pad = n_pad;
+    ex.f32t = P.have_f32t ? P.f32t.as<float>() : nullptr;
+    ex.j_per_split = ((jtl + nsplit - 1) / nsplit) * 128;
+    nsplit = (int)((jtl * 128 + ex.j_per_split - 1) / ex.j_per_split);
+    for (int s = 0; s < S; ++s) {
+      ex.kapd[s] = kapd[s];
+      ex.taud[s] = taud[s];
+    }
+    if ((st = ctx->bsrc.ensure((size_t)S * n_pad * sizeof(float))) != YY_OK) return st;
+    ex.bsrc = ctx->bsrc.as<float>();
+  } else {
+    while (ttiles * nsplit < 512 && nsplit < 64 && (int64_t)nsplit * kVJ * 2 <= n) nsplit *= 2;
+  }
   a.nsplit = nsplit;
   if ((st = ctx->part.ensure((size_t)nsplit * S * n * sizeof(float2))) != YY_OK) return st;
   a.part = ctx->part.as<float2>();
+  if (mfma && (st = launch_src_bias(ctx->stream, a, ex)) != YY_OK) return st;
   if ((st = timing_begin(ctx)) != YY_OK) return st;
   if (mfma) {
-    st = launch_pair_mfma(ctx->stream, a, prec);
+    st = launch_pair_mfma(ctx->stream, a, prec, ex);
   } else {
     st = launch_pair_valu_d(ctx->stream, a, taud, kapd);
   }

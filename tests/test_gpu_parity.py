@@ -213,3 +213,47 @@ def test_restart_nodes_bit_exact(ctx, r, n):
     assert np.array_equal(np.isinf(glw), np.isinf(lw))
     f = np.isfinite(lw)
     assert np.allclose(glw[f], lw[f], rtol=1e-13, atol=1e-13)
+
+
+# ---------------------------------------------------------------- matrix-core propagation
+MFMA_CASES = {
+    # r >= 32: the distance expansion runs on the matrix cores, near pairs exactly
+    "cos_r64_n512_s124": dict(r=64, n=512, drift=oracle.F_COS, scales=(1.0, 2.0, 4.0), q=0.09, dt=0.005, half=0.3,
+                              seed=11),
+    "cos_r100_n1000_ragged_s124": dict(r=100, n=1000, drift=oracle.F_COS, scales=(1.0, 2.0, 4.0), q=0.09, dt=0.005,
+                                       half=0.3, seed=12),
+    "cos_r33_n300_s1": dict(r=33, n=300, drift=oracle.F_COS, scales=(1.0,), q=0.5, dt=0.02, half=0.5, seed=13),
+    "linear_r128_n2048_s12": dict(r=128, n=2048, drift=oracle.F_LINEAR, scales=(1.0, 2.0), q=0.1, dt=0.01, half=0.4,
+                                  seed=14),
+    # many near pairs (wide kernel, small box): exercises the exact near-pair path heavily
+    "cos_r40_n1024_dense_near": dict(r=40, n=1024, drift=oracle.F_COS, scales=(1.0,), q=2.0, dt=0.05, half=0.25,
+                                     seed=15),
+    "cos_r36_n2048_near_s12": dict(r=36, n=2048, drift=oracle.F_COS, scales=(1.0, 2.0), q=1.0, dt=0.06, half=0.4,
+                                   seed=18),
+    "zero_r48_n257_sparse": dict(r=48, n=257, drift=oracle.F_ZERO, scales=(1.0, 2.0), q=1.0, dt=0.05, half=0.5,
+                                 seed=16, lw_kind="sparse"),
+    "cos_r64_n512_unscrambled_boundary": dict(r=64, n=512, drift=oracle.F_COS, scales=(1.0, 2.0, 4.0), q=0.09,
+                                              dt=0.005, half=0.3, seed=17, scramble=False),
+}
+
+
+@pytest.mark.parametrize("prec", ["fp32_mfma", "bf16x3", "bf16x1"])
+@pytest.mark.parametrize("name", sorted(MFMA_CASES))
+def test_propagate_mfma_parity(ctx, name, prec):
+    kw = dict(MFMA_CASES[name])
+    A = None
+    if kw["drift"] == oracle.F_LINEAR:
+        from paper_2509_16896_amd.workloads import linear_drift_matrix
+        A = linear_drift_matrix(kw["r"], 0)
+    case = _prop_case(A=A, **kw)
+    got = _gpu_prop(ctx, case, prec)
+    worst, cnt = compare_logw(got, case["ref"], 1e-5)
+    print(f"{name} [{prec}]: worst err/allowed = {worst:.3g} over {cnt} nodes")
+    assert worst <= 1.0
+    bnd = oracle.is_boundary(case["x"], case["lo"], case["hi"])
+    assert np.all(np.isneginf(got[bnd]))
+    # the matrix-core forms reproduce the plain FP32 form up to summation order
+    plain = _gpu_prop(ctx, case, "fp32")
+    f = np.isfinite(plain)
+    assert np.array_equal(np.isfinite(got), f)
+    assert np.max(np.abs(got[f] - plain[f]) / np.maximum(1.0, np.abs(plain[f]))) < 2e-6
