@@ -28,7 +28,7 @@ typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16_t;
 
 constexpr int kMI = 256;   // targets per block
 constexpr int kMJ = 128;   // sources per tile
-constexpr int kKC = 32;    // K per LDS stage
+constexpr int kKC = 16;    // K per LDS stage
 constexpr int kNT = 256;   // 4 waves: 2 along targets x 2 along sources
 constexpr int kIB = 4;     // 32-wide target blocks per wave (128 targets)
 constexpr int kJB = 2;     // 32-wide source blocks per wave (64 sources)
@@ -43,8 +43,8 @@ struct MArgs {
   float tau[YY_MAX_SCALES];
   double kapd[YY_MAX_SCALES];
   double taud[YY_MAX_SCALES];
-  const uint16_t* bf;          // bf16 planes [4][rp/32][n_pad][32]: hi(x), hi(f), lo(x), lo(f)
-  const float* f32t;           // fp32 planes [2][rp/32][n_pad][32]: x, f
+  const uint16_t* bf;          // bf16 planes [4][rp/16][n_pad][16]: hi(x), hi(f), lo(x), lo(f)
+  const float* f32t;           // fp32 planes [2][rp/16][n_pad][16]: x, f
   const float* xc;             // row-major FP32 [n][rp] (exact near pairs)
   const float* f;
   const float* lw2;            // [n]
@@ -60,7 +60,7 @@ struct MArgs {
 // Physical 16-byte chunk of logical chunk c in LDS row `row` (bank-conflict swizzle).
 template <int CPR>
 __device__ inline int swz(int row, int c) {
-  return CPR == 4 ? (c ^ ((row >> 1) & 3)) : (c ^ (row & 7));
+  return CPR == 2 ? (c ^ ((row >> 2) & 1)) : (c ^ ((row >> 1) & 3));
 }
 
 // Block -> (target block, source split).  Blocks are dealt round-robin to the 8
@@ -82,85 +82,137 @@ __device__ inline void block_map(const MArgs& a, int& tb, int& split) {
   }
 }
 
-__device__ inline float exact_pair(const MArgs& a, int64_t i, int64_t j, int s) {
-  if (i == j) return a.lw2[j] - (float)(a.kapd[s] * a.taud[s] * a.taud[s] * a.node[a.n + i]);
-  const float* xi = a.xc + (size_t)i * a.rp;
-  const float* xj = a.xc + (size_t)j * a.rp;
-  const float* fj = a.f + (size_t)j * a.rp;
+// Parameters of the rare exact path, copied to LDS once per block so that the
+// hot loop does not hold them in scalar registers.
+struct Rare {
+  const float* xc;
+  const float* f;
+  const float* lw2;
+  const double* node;
+  int64_t n;
+  int32_t rp, pad;
+  float kap[YY_MAX_SCALES], tau[YY_MAX_SCALES];
+  double kapd[YY_MAX_SCALES], taud[YY_MAX_SCALES];
+};
+
+__device__ inline void fill_rare(const MArgs& a, Rare& rr) {
+  rr.xc = a.xc;
+  rr.f = a.f;
+  rr.lw2 = a.lw2;
+  rr.node = a.node;
+  rr.n = a.n;
+  rr.rp = a.rp;
+  for (int s = 0; s < YY_MAX_SCALES; ++s) {
+    rr.kap[s] = a.kap[s];
+    rr.tau[s] = a.tau[s];
+    rr.kapd[s] = a.kapd[s];
+    rr.taud[s] = a.taud[s];
+  }
+}
+
+// Exact base-2 exponent of a pair j != i by FP32 direct differences, summed in
+// k order (zero-padded K adds exact zeros), the vector-ALU kernel's arithmetic.
+__device__ inline float exact_pair(const Rare& a, int64_t i, int64_t j, int s) {
+  const float4* xi = reinterpret_cast<const float4*>(a.xc + (size_t)i * a.rp);
+  const float4* xj = reinterpret_cast<const float4*>(a.xc + (size_t)j * a.rp);
+  const float4* fj = reinterpret_cast<const float4*>(a.f + (size_t)j * a.rp);
   const float t = a.tau[s];
   float acc = 0.f;
-  for (int k = 0; k < a.r; ++k) {
-    const float d = xi[k] - xj[k];
-    const float e = fmaf(-t, fj[k], d);
+  const int nq = a.rp >> 2;
+#pragma unroll 4
+  for (int q = 0; q < nq; ++q) {
+    const float4 p = xi[q], u = xj[q], w = fj[q];
+    float e = fmaf(-t, w.x, p.x - u.x);
+    acc = fmaf(e, e, acc);
+    e = fmaf(-t, w.y, p.y - u.y);
+    acc = fmaf(e, e, acc);
+    e = fmaf(-t, w.z, p.z - u.z);
+    acc = fmaf(e, e, acc);
+    e = fmaf(-t, w.w, p.w - u.w);
     acc = fmaf(e, e, acc);
   }
   return a.lw2[j] - a.kap[s] * acc;
 }
 
 // Folds the accumulators of one target (kJB blocks x 16 sources of this lane)
-// into the lane's running (max, sum) of that target for every scale.  Flagged
-// near pairs are taken out of the approximate set and folded in one at a time
-// from their exact values.
+// into the lane's running (max, sum) of that target for every scale.
+__device__ inline float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+
 __device__ inline void lse2_push(float& M, float& S, float v) {
   if (v == -INFINITY) return;
   if (v > M) {
-    S = S * exp2f(M - v) + 1.f;
+    S = S * fast_exp2(M - v) + 1.f;
     M = v;
   } else {
-    S += exp2f(v - M);
+    S += fast_exp2(v - M);
   }
 }
 
+// The rare path of a slab that reaches within 2^-64 of the running maximum:
+// exponents within `margin` of the maximum are recomputed exactly, the others
+// are summed from their approximate values.  Out of line so that the hot
+// loop's register allocation does not carry it.  e: the 32 approximate
+// exponents (self pair already -inf); returns the new (max, sum).
+__device__ __noinline__ float2 refine_slab(const Rare* rr, int64_t i, int64_t jbase, int g, int s,
+                                           float margin, const float* e, float M, float S) {
+  float m = -INFINITY;
+  for (int b = 0; b < 32; ++b) m = fmaxf(m, e[b]);
+  const float thr = fmaxf(M, m) - margin;
+  float m2 = -INFINITY;
+  for (int b = 0; b < 32; ++b) {
+    if (e[b] >= thr) {
+      const int jb = b >> 4, v = b & 15;
+      const int64_t j = jbase + jb * 32 + 8 * (v >> 2) + 4 * g + (v & 3);
+      lse2_push(M, S, exact_pair(*rr, i, j, s));
+    } else {
+      m2 = fmaxf(m2, e[b]);
+    }
+  }
+  const float Mn = fmaxf(M, m2);
+  if (Mn == -INFINITY) return make_float2(M, S);
+  float sum = S * fast_exp2(M - Mn);
+  for (int b = 0; b < 32; ++b)
+    if (e[b] < thr) sum += fast_exp2(e[b] - Mn);
+  return make_float2(Mn, sum);
+}
+
 template <int S>
-__device__ inline void epilogue_target(const MArgs& a, const f32x16_t (&G)[kJB], const f32x16_t (&H)[kJB],
-                                       const float* sb, int64_t i, int64_t j0, int jl0, int g,
-                                       const float (&at)[S], const float (&margin)[S], float (&M)[S],
-                                       float (&Ssum)[S]) {
+__device__ inline void epilogue_target(const MArgs& a, const Rare* rare, const f32x16_t (&G)[kJB],
+                                       const f32x16_t (&H)[kJB], const float* sb, int64_t i, int64_t j0,
+                                       int jl0, int g, bool diag, const float (&at)[S],
+                                       const float (&margin)[S], float (&M)[S], float (&Ssum)[S]) {
+  // The self pair (source j = i) is accounted for at initialisation; this
+  // lane holds it iff d = i - j0 - jl0 is in [0, 64) with bit 2 equal to g.
+  const int64_t d = i - j0 - jl0;
+  const bool self = diag && d >= 0 && d < 32 * kJB && (int)((d >> 2) & 1) == g;
+  const int dself = (int)d;
 #pragma unroll
   for (int s = 0; s < S; ++s) {
-    float e[kJB][16];
+    const float c1 = a.c1[s], c2 = a.c2[s];
     float m = -INFINITY;
 #pragma unroll
     for (int jb = 0; jb < kJB; ++jb)
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
-        const int jl = jl0 + jb * 32 + 8 * (v >> 2) + 4 * g + (v & 3);
-        const float base = at[s] + sb[s * kMJ + jl];
-        e[jb][v] = fmaf(a.c2[s], H[jb][v], fmaf(a.c1[s], G[jb][v], base));
-        m = fmaxf(m, e[jb][v]);
+        const int jl = jb * 32 + 8 * (v >> 2) + 4 * g + (v & 3);
+        float e = fmaf(c2, H[jb][v], fmaf(c1, G[jb][v], at[s] + sb[s * kMJ + jl0 + jl]));
+        if (self && jl == dself) e = -INFINITY;
+        m = fmaxf(m, e);
       }
-    if (!(m > M[s] - kSkip)) continue;
-    const float thr = fmaxf(M[s], m) - margin[s];
-    uint32_t flagged = 0u;
+    if (!(m > M[s] - kSkip)) continue;   // every term is below 2^-64 of the running maximum
+    float e[32];
 #pragma unroll
     for (int jb = 0; jb < kJB; ++jb)
 #pragma unroll
-      for (int v = 0; v < 16; ++v)
-        if (e[jb][v] >= thr) {
-          flagged |= 1u << (jb * 16 + v);
-          e[jb][v] = -INFINITY;
-        }
-    while (flagged) {
-      const int bit = __builtin_ctz(flagged);
-      flagged &= flagged - 1u;
-      const int jb = bit >> 4, v = bit & 15;
-      const int jl = jl0 + jb * 32 + 8 * (v >> 2) + 4 * g + (v & 3);
-      lse2_push(M[s], Ssum[s], exact_pair(a, i, j0 + jl, s));
-    }
-    float m2 = -INFINITY;
-#pragma unroll
-    for (int jb = 0; jb < kJB; ++jb)
-#pragma unroll
-      for (int v = 0; v < 16; ++v) m2 = fmaxf(m2, e[jb][v]);
-    const float Mn = fmaxf(M[s], m2);
-    if (Mn == -INFINITY) continue;
-    float sum = Ssum[s] * exp2f(M[s] - Mn);
-#pragma unroll
-    for (int jb = 0; jb < kJB; ++jb)
-#pragma unroll
-      for (int v = 0; v < 16; ++v) sum += exp2f(e[jb][v] - Mn);
-    Ssum[s] = sum;
-    M[s] = Mn;
+      for (int v = 0; v < 16; ++v) {
+        const int jl = jb * 32 + 8 * (v >> 2) + 4 * g + (v & 3);
+        float x = fmaf(c2, H[jb][v], fmaf(c1, G[jb][v], at[s] + sb[s * kMJ + jl0 + jl]));
+        if (self && jl == dself) x = -INFINITY;
+        e[jb * 16 + v] = x;
+      }
+    const float2 r = refine_slab(rare, i, j0 + jl0, g, s, margin[s], e, M[s], Ssum[s]);
+    M[s] = r.x;
+    Ssum[s] = r.y;
   }
 }
 
@@ -206,10 +258,10 @@ __device__ inline void merge_and_store(const MArgs& a, float (&M)[kIB][S], float
 // worst-case FP32 accumulation over rp products, FP32 evaluation of e; the
 // margin adds the skip depth and 16 bits of safety.
 template <int S>
-__device__ inline void init_targets(const MArgs& a, int64_t i0, float (&at)[kIB][S], float (&M)[kIB][S],
-                                    float (&Ssum)[kIB][S], float (&margin)[S]) {
+__device__ inline void init_targets(const MArgs& a, int64_t i0, int split, float (&at)[kIB][S],
+                                    float (&M)[kIB][S], float (&Ssum)[kIB][S], float (&margin)[S]) {
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int wi = wave >> 1, col = lane & 31;
+  const int wi = wave >> 1, wj = wave & 1, col = lane & 31, g = lane >> 5;
   const double X = a.scal[1], F = a.scal[2];
   const double gam = a.rp * 0x1p-24;
 #pragma unroll
@@ -221,51 +273,104 @@ __device__ inline void init_targets(const MArgs& a, int64_t i0, float (&at)[kIB]
 #pragma unroll
   for (int ib = 0; ib < kIB; ++ib) {
     const int64_t i = i0 + wi * (32 * kIB) + ib * 32 + col;
-    const double nx = i < a.n ? a.node[i] : 0.0;
+    const bool valid = i < a.n;
+    const double nx = valid ? a.node[i] : 0.0;
+    const double nf = valid ? a.node[a.n + i] : 0.0;
+    const float li = valid ? a.lw2[i] : -INFINITY;
+    // The self pair is one of the terms, so its exact exponent bounds the row
+    // maximum from below: every partial state starts at it (tiles far below
+    // are then skipped untouched) and exactly one state -- the one whose
+    // source range holds j = i -- starts with it counted.
+    const bool owner = valid && (int64_t)split == i / a.j_per_split && wj == (int)((i % kMJ) / (32 * kJB)) &&
+                       g == (int)((i >> 2) & 1);
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-      at[ib][s] = i < a.n ? (float)(-a.kapd[s] * nx) : -INFINITY;
-      M[ib][s] = -INFINITY;
-      Ssum[ib][s] = 0.f;
+      at[ib][s] = valid ? (float)(-a.kapd[s] * nx) : -INFINITY;
+      M[ib][s] = (valid && li != -INFINITY) ? li - (float)(a.kapd[s] * a.taud[s] * a.taud[s] * nf) : -INFINITY;
+      Ssum[ib][s] = (owner && M[ib][s] != -INFINITY) ? 1.f : 0.f;
     }
   }
 }
 
-// Direct global -> LDS copy of one K stage (global_load_lds_dwordx4): each
-// instruction moves 1 KB, lane L landing at byte 16 L of the region, so the
-// bank-conflict swizzle is applied by choosing which global chunk a lane loads.
-// ROWB = bytes per row per stage (64: bf16 planes, 128: fp32 planes).
-template <int ROWB, int NTP, int NSP>
-__device__ inline void issue_stage(const MArgs& a, const void* const* tplane, const void* const* splane,
-                                   unsigned char* stage, int c, int64_t i0, int64_t j0) {
+// ---------------------------------------------------------------------------
+// Global -> LDS pipeline.  Every 1 KB region of a stage is filled by one
+// global_load_lds_dwordx4 of one wave (lane L's 16 bytes land at byte 16 L of
+// the region), so the bank-conflict swizzle is applied by choosing which
+// global chunk a lane fetches.  The copies are issued through inline asm: the
+// compiler then neither inserts conservative vmcnt waits before unrelated LDS
+// reads nor keeps LDS values in registers across them ("memory" clobber); the
+// kernel waits for each stage explicitly with s_waitcnt vmcnt before the
+// barrier that publishes it.  M0 is saved and restored around the copy.
+__device__ inline uint32_t lds_addr(const void* p) {
+  return (uint32_t)reinterpret_cast<uintptr_t>((const __attribute__((address_space(3))) void*)p);
+}
+
+__device__ inline void dma_1k(const void* gsrc, uint32_t lds) {
+  uint32_t saved;
+  asm volatile(
+      "s_mov_b32 %0, m0\n\t"
+      "s_mov_b32 m0, %1\n\t"
+      "s_nop 0\n\t"
+      "global_load_lds_dwordx4 %2, off\n\t"
+      "s_mov_b32 m0, %0"
+      : "=&s"(saved)
+      : "s"(lds), "v"(gsrc)
+      : "memory");
+}
+
+// s_waitcnt immediate that waits until at most V vector-memory operations of
+// this wave are outstanding (expcnt and lgkmcnt left unconstrained).
+template <int V>
+__device__ inline void wait_vmcnt() {
+  static_assert(V >= 0 && V < 64, "vmcnt out of range");
+  __builtin_amdgcn_s_waitcnt((V & 15) | ((V >> 4) << 14) | 0x70 | 0xF00);
+}
+
+// Issues the copies of one K stage: target planes (rows i0..i0+255) then source
+// planes (rows j0..j0+127) of K chunk c.  ESZ = element bytes (2: bf16, 4: fp32).
+// Global planes are [chunk][n_pad][16 elements]; target planes are global
+// planes 0 and 2, source planes 0..3.
+template <int ESZ, int NTP, int NSP>
+__device__ inline void issue_stage(const unsigned char* gb, uint64_t plane_bytes, int64_t n_pad,
+                                   uint32_t stage_lds, int c, int64_t i0, int64_t j0, int wave, int lane) {
+  constexpr int ROWB = kKC * ESZ;              // bytes per row per stage
   constexpr int CPR = ROWB / 16;               // 16-byte chunks per row
   constexpr int RPR = 64 / CPR;                // rows per 1 KB region
   constexpr int TREG = kMI / RPR, SREG = kMJ / RPR;
   constexpr int R = NTP * TREG + NSP * SREG;
-  constexpr int ESZ = ROWB / kKC;              // element size in bytes
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  static_assert(R % 4 == 0, "regions per stage must split over 4 waves");
+  const unsigned char* tb = gb + ((uint64_t)c * (uint64_t)n_pad + (uint64_t)i0) * ROWB;
+  const unsigned char* sbp = gb + ((uint64_t)c * (uint64_t)n_pad + (uint64_t)j0) * ROWB;
   const int rl = lane / CPR, pc = lane % CPR;
 #pragma unroll
   for (int u = 0; u < R / 4; ++u) {
-    const int q = wave + 4 * u;
+    const int q = wave + 4 * u;   // wave-uniform
     const unsigned char* src;
     int off;
     if (q < NTP * TREG) {
       const int p = q / TREG, rb = (q % TREG) * RPR, row = rb + rl;
-      const int lc = swz<CPR>(row, pc);
-      src = static_cast<const unsigned char*>(tplane[p]) +
-            (((size_t)c * a.n_pad + (size_t)(i0 + row)) * kKC) * ESZ + lc * 16;
+      src = tb + (uint64_t)(2 * p) * plane_bytes + row * ROWB + swz<CPR>(row, pc) * 16;
       off = p * (kMI * ROWB) + rb * ROWB;
     } else {
       const int q2 = q - NTP * TREG;
       const int p = q2 / SREG, rb = (q2 % SREG) * RPR, row = rb + rl;
-      const int lc = swz<CPR>(row, pc);
-      src = static_cast<const unsigned char*>(splane[p]) +
-            (((size_t)c * a.n_pad + (size_t)(j0 + row)) * kKC) * ESZ + lc * 16;
+      src = sbp + (uint64_t)p * plane_bytes + row * ROWB + swz<CPR>(row, pc) * 16;
       off = NTP * kMI * ROWB + p * (kMJ * ROWB) + rb * ROWB;
     }
-    __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(src),
-                                     (__attribute__((address_space(3))) void*)(stage + off), 16, 0, 0);
+    dma_1k(src, stage_lds + off);
+  }
+}
+
+// Source biases of tile j0 -> sb (wave 0 only): [S][128] floats, lane-ordered.
+__device__ inline void issue_bias(const MArgs& a, uint32_t sb_lds, int64_t j0, int wave, int lane) {
+  if (wave != 0) return;
+  const int regions = (a.S * kMJ * 4 + 1023) / 1024;
+  for (int u = 0; u < regions; ++u) {
+    const int idx = 256 * u + 4 * lane;
+    int s = idx / kMJ;
+    if (s >= a.S) s = a.S - 1;   // lanes past the last scale fetch a valid address; never read
+    const float* src = a.bsrc + (size_t)s * a.n_pad + j0 + (idx % kMJ);
+    dma_1k(src, sb_lds + u * 1024);
   }
 }
 
@@ -282,171 +387,162 @@ __device__ inline void zero_acc(f32x16_t (&G)[kIB][kJB], f32x16_t (&H)[kIB][kJB]
       }
 }
 
-// ---------------------------------------------------------------------------
-// BF16 variants.  LDS stage: target planes [NTP][256 rows][64 B] (hi, lo of x),
-// source planes [NSP][128 rows][64 B] (hi x, hi f, lo x, lo f); NTP = 2, NSP = 4
-// for the hi/lo split, 1 and 2 for hi only.  Each wave: 128 targets x 64 sources.
-template <int S, int PASSES>
-__global__ void __launch_bounds__(kNT, 1) k_pair_mfma_bf16(MArgs a) {
+// One K stage of the products on the matrix cores.
+template <int PASSES>
+__device__ inline void mfma_stage_bf16(const unsigned char* base, f32x16_t (&G)[kIB][kJB],
+                                       f32x16_t (&H)[kIB][kJB]) {
+  constexpr int ROWB = 32;
   constexpr int NTP = PASSES == 3 ? 2 : 1;
-  constexpr int NSP = PASSES == 3 ? 4 : 2;
-  constexpr int ROWB = 64;
   constexpr int TB = NTP * kMI * ROWB;
-  constexpr int STAGE = TB + NSP * kMJ * ROWB;
-  __shared__ __attribute__((aligned(1024))) unsigned char smem[2 * STAGE];
-  __shared__ float sb[YY_MAX_SCALES * kMJ];
-
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wi = wave >> 1, wj = wave & 1, col = lane & 31, g = lane >> 5;
-  int tb, split;
-  block_map(a, tb, split);
-  const int64_t i0 = (int64_t)tb * kMI;
-  const int64_t jb0 = (int64_t)split * a.j_per_split;
-  const int64_t jb1 = jb0 + a.j_per_split < a.n ? jb0 + a.j_per_split : a.n;
-  const int nchunks = a.rp / kKC;
-  const size_t plane = (size_t)nchunks * a.n_pad * kKC;   // elements per global plane
-  const void* sp[4] = {a.bf, a.bf + plane, a.bf + 2 * plane, a.bf + 3 * plane};
-  const void* tp[2] = {a.bf, a.bf + 2 * plane};
-
-  float at[kIB][S], M[kIB][S], Ssum[kIB][S], margin[S];
-  init_targets<S>(a, i0, at, M, Ssum, margin);
-
-  for (int64_t j0 = jb0; j0 < jb1; j0 += kMJ) {
-    f32x16_t G[kIB][kJB], H[kIB][kJB];
-    zero_acc<S>(G, H);
-    __syncthreads();   // the previous tile's readers are done with stage 0 and sb
-    issue_stage<ROWB, NTP, NSP>(a, tp, sp, smem, 0, i0, j0);
-    for (int t = tid; t < S * kMJ; t += kNT) sb[t] = a.bsrc[(size_t)(t / kMJ) * a.n_pad + j0 + (t % kMJ)];
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-
-    for (int c = 0; c < nchunks; ++c) {
-      const int stage = c & 1;
-      if (c + 1 < nchunks) issue_stage<ROWB, NTP, NSP>(a, tp, sp, smem + (stage ^ 1) * STAGE, c + 1, i0, j0);
-      const unsigned char* base = smem + stage * STAGE;
+  bf16x8_t bh[kIB], bl[kIB], xh[kJB], xl[kJB], fh[kJB], fl[kJB];
 #pragma unroll
-      for (int ks = 0; ks < 2; ++ks) {
-        const int lc = 2 * ks + g;   // logical 16-byte chunk of this lane group
-        bf16x8_t bh[kIB], bl[kIB], xh[kJB], xl[kJB], fh[kJB], fl[kJB];
+  for (int ib = 0; ib < kIB; ++ib) {
+    const int row = wi * (32 * kIB) + ib * 32 + col;
+    const int off = row * ROWB + swz<2>(row, g) * 16;
+    bh[ib] = *reinterpret_cast<const bf16x8_t*>(base + off);
+    if (PASSES == 3) bl[ib] = *reinterpret_cast<const bf16x8_t*>(base + kMI * ROWB + off);
+  }
 #pragma unroll
-        for (int ib = 0; ib < kIB; ++ib) {
-          const int row = wi * (32 * kIB) + ib * 32 + col;
-          const int off = row * ROWB + swz<4>(row, lc) * 16;
-          bh[ib] = *reinterpret_cast<const bf16x8_t*>(base + off);
-          if (PASSES == 3) bl[ib] = *reinterpret_cast<const bf16x8_t*>(base + kMI * ROWB + off);
-        }
-#pragma unroll
-        for (int jb = 0; jb < kJB; ++jb) {
-          const int row = wj * (32 * kJB) + jb * 32 + col;
-          const int off = TB + row * ROWB + swz<4>(row, lc) * 16;
-          xh[jb] = *reinterpret_cast<const bf16x8_t*>(base + off);
-          fh[jb] = *reinterpret_cast<const bf16x8_t*>(base + kMJ * ROWB + off);
-          if (PASSES == 3) {
-            xl[jb] = *reinterpret_cast<const bf16x8_t*>(base + 2 * kMJ * ROWB + off);
-            fl[jb] = *reinterpret_cast<const bf16x8_t*>(base + 3 * kMJ * ROWB + off);
-          }
-        }
-#pragma unroll
-        for (int ib = 0; ib < kIB; ++ib)
-#pragma unroll
-          for (int jb = 0; jb < kJB; ++jb) {
-            G[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[jb], bh[ib], G[ib][jb], 0, 0, 0);
-            H[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fh[jb], bh[ib], H[ib][jb], 0, 0, 0);
-            if (PASSES == 3) {
-              G[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xl[jb], bh[ib], G[ib][jb], 0, 0, 0);
-              H[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fl[jb], bh[ib], H[ib][jb], 0, 0, 0);
-              G[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[jb], bl[ib], G[ib][jb], 0, 0, 0);
-              H[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fh[jb], bl[ib], H[ib][jb], 0, 0, 0);
-            }
-          }
-      }
-      __builtin_amdgcn_s_waitcnt(0);
-      __syncthreads();
-    }
-#pragma unroll
-    for (int ib = 0; ib < kIB; ++ib) {
-      const int64_t i = i0 + wi * (32 * kIB) + ib * 32 + col;
-      epilogue_target<S>(a, G[ib], H[ib], sb, i, j0, wj * (32 * kJB), g, at[ib], margin, M[ib], Ssum[ib]);
+  for (int jb = 0; jb < kJB; ++jb) {
+    const int row = wj * (32 * kJB) + jb * 32 + col;
+    const int off = TB + row * ROWB + swz<2>(row, g) * 16;
+    xh[jb] = *reinterpret_cast<const bf16x8_t*>(base + off);
+    fh[jb] = *reinterpret_cast<const bf16x8_t*>(base + kMJ * ROWB + off);
+    if (PASSES == 3) {
+      xl[jb] = *reinterpret_cast<const bf16x8_t*>(base + 2 * kMJ * ROWB + off);
+      fl[jb] = *reinterpret_cast<const bf16x8_t*>(base + 3 * kMJ * ROWB + off);
     }
   }
-  merge_and_store<S>(a, M, Ssum, i0, split, reinterpret_cast<float2*>(smem));
+#pragma unroll
+  for (int ib = 0; ib < kIB; ++ib)
+#pragma unroll
+    for (int jb = 0; jb < kJB; ++jb) {
+      G[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[jb], bh[ib], G[ib][jb], 0, 0, 0);
+      H[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fh[jb], bh[ib], H[ib][jb], 0, 0, 0);
+      if (PASSES == 3) {
+        G[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xl[jb], bh[ib], G[ib][jb], 0, 0, 0);
+        H[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fl[jb], bh[ib], H[ib][jb], 0, 0, 0);
+        G[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[jb], bl[ib], G[ib][jb], 0, 0, 0);
+        H[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fh[jb], bl[ib], H[ib][jb], 0, 0, 0);
+      }
+    }
 }
 
-// ---------------------------------------------------------------------------
-// FP32 variant (v_mfma_f32_32x32x2_f32).  LDS stage: target plane [256 rows][128 B],
-// source planes x, f [128 rows][128 B].  Within a 32-wide K stage, lane group g
-// owns k = 16 g + t in K step t (any fixed assignment of k to steps is valid as
-// long as both operands use it), so each lane reads 16 consecutive floats.
-template <int S>
-__global__ void __launch_bounds__(kNT, 1) k_pair_mfma_f32(MArgs a) {
-  constexpr int ROWB = 128;
+// FP32: within a 16-wide K stage, lane group g owns k = 8 g + t in K step t
+// (any fixed assignment of k to steps is valid when both operands use it), so
+// a lane reads two consecutive 16-byte chunks of its row.
+__device__ inline void mfma_stage_f32(const unsigned char* base, f32x16_t (&G)[kIB][kJB],
+                                      f32x16_t (&H)[kIB][kJB]) {
+  constexpr int ROWB = 64;
   constexpr int TB = kMI * ROWB;
-  constexpr int STAGE = TB + 2 * kMJ * ROWB;
-  __shared__ __attribute__((aligned(1024))) unsigned char smem[2 * STAGE];
-  __shared__ float sb[YY_MAX_SCALES * kMJ];
-
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wi = wave >> 1, wj = wave & 1, col = lane & 31, g = lane >> 5;
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int lc = 2 * g + u;
+    float4 bt[kIB], xs[kJB], fs[kJB];
+#pragma unroll
+    for (int ib = 0; ib < kIB; ++ib) {
+      const int row = wi * (32 * kIB) + ib * 32 + col;
+      bt[ib] = *reinterpret_cast<const float4*>(base + row * ROWB + swz<4>(row, lc) * 16);
+    }
+#pragma unroll
+    for (int jb = 0; jb < kJB; ++jb) {
+      const int row = wj * (32 * kJB) + jb * 32 + col;
+      const int off = TB + row * ROWB + swz<4>(row, lc) * 16;
+      xs[jb] = *reinterpret_cast<const float4*>(base + off);
+      fs[jb] = *reinterpret_cast<const float4*>(base + kMJ * ROWB + off);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+      for (int ib = 0; ib < kIB; ++ib)
+#pragma unroll
+        for (int jb = 0; jb < kJB; ++jb) {
+          G[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x2f32(xs[jb][e], bt[ib][e], G[ib][jb], 0, 0, 0);
+          H[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x2f32(fs[jb][e], bt[ib][e], H[ib][jb], 0, 0, 0);
+        }
+  }
+}
+
+// The pairwise kernel.  VAR: 3 = BF16 hi/lo split, 1 = BF16 hi only, 0 = FP32.
+// The (source tile, K chunk) steps of a block form one flat sequence; stage
+// q % NS of an NS-deep LDS ring holds step q, whose copies were issued NS - 1
+// steps earlier, so the pipeline keeps running across tile boundaries while a
+// tile's epilogue folds its products into the running (max, sum).
+template <int S, int VAR, int NS>
+__global__ void __launch_bounds__(kNT, 1) k_pair_mfma(MArgs a) {
+  constexpr int ESZ = VAR == 0 ? 4 : 2;
+  constexpr int NTP = VAR == 3 ? 2 : 1;
+  constexpr int NSP = VAR == 3 ? 4 : 2;
+  constexpr int ROWB = kKC * ESZ;
+  constexpr int STAGE = (NTP * kMI + NSP * kMJ) * ROWB;
+  constexpr int L = STAGE / 1024 / 4;          // copies per wave per stage
+  __shared__ __attribute__((aligned(1024))) unsigned char smem[NS * STAGE];
+  __shared__ __attribute__((aligned(1024))) float sbuf[2][4 * kMJ];
+
+  __shared__ Rare rare;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wi = wave >> 1, wj = wave & 1, col = lane & 31, g = lane >> 5;
+  if (tid == 0) fill_rare(a, rare);
   int tb, split;
   block_map(a, tb, split);
   const int64_t i0 = (int64_t)tb * kMI;
   const int64_t jb0 = (int64_t)split * a.j_per_split;
   const int64_t jb1 = jb0 + a.j_per_split < a.n ? jb0 + a.j_per_split : a.n;
+  const int ntiles = (int)((jb1 - jb0 + kMJ - 1) / kMJ);
   const int nchunks = a.rp / kKC;
-  const size_t plane = (size_t)nchunks * a.n_pad * kKC;
-  const void* sp[2] = {a.f32t, a.f32t + plane};
-  const void* tp[1] = {a.f32t};
+  const int Q = ntiles * nchunks;
+  const uint64_t plane = (uint64_t)nchunks * a.n_pad * kKC * ESZ;   // bytes per global plane
+  const unsigned char* gb = VAR == 0 ? reinterpret_cast<const unsigned char*>(a.f32t)
+                                     : reinterpret_cast<const unsigned char*>(a.bf);
+  const int64_t n_pad = a.n_pad;
+  const uint32_t smem_lds = __builtin_amdgcn_readfirstlane(lds_addr(smem));
+  const uint32_t sb_lds = __builtin_amdgcn_readfirstlane(lds_addr(&sbuf[0][0]));
 
   float at[kIB][S], M[kIB][S], Ssum[kIB][S], margin[S];
-  init_targets<S>(a, i0, at, M, Ssum, margin);
+  init_targets<S>(a, i0, split, at, M, Ssum, margin);
 
-  for (int64_t j0 = jb0; j0 < jb1; j0 += kMJ) {
+  issue_bias(a, sb_lds, jb0, wave, lane);
+#pragma unroll
+  for (int p = 0; p < NS - 1; ++p)
+    if (p < Q) issue_stage<ESZ, NTP, NSP>(gb, plane, n_pad, smem_lds + p * STAGE, p % nchunks, i0,
+                                          jb0 + (int64_t)(p / nchunks) * kMJ, wave, lane);
+
+  for (int t = 0; t < ntiles; ++t) {
+    const int64_t j0 = jb0 + (int64_t)t * kMJ;
     f32x16_t G[kIB][kJB], H[kIB][kJB];
     zero_acc<S>(G, H);
-    __syncthreads();
-    issue_stage<ROWB, 1, 2>(a, tp, sp, smem, 0, i0, j0);
-    for (int t = tid; t < S * kMJ; t += kNT) sb[t] = a.bsrc[(size_t)(t / kMJ) * a.n_pad + j0 + (t % kMJ)];
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-
     for (int c = 0; c < nchunks; ++c) {
-      const int stage = c & 1;
-      if (c + 1 < nchunks) issue_stage<ROWB, 1, 2>(a, tp, sp, smem + (stage ^ 1) * STAGE, c + 1, i0, j0);
-      const unsigned char* base = smem + stage * STAGE;
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int lc = 4 * g + u;
-        float4 bt[kIB], xs[kJB], fs[kJB];
-#pragma unroll
-        for (int ib = 0; ib < kIB; ++ib) {
-          const int row = wi * (32 * kIB) + ib * 32 + col;
-          bt[ib] = *reinterpret_cast<const float4*>(base + row * ROWB + swz<8>(row, lc) * 16);
-        }
-#pragma unroll
-        for (int jb = 0; jb < kJB; ++jb) {
-          const int row = wj * (32 * kJB) + jb * 32 + col;
-          const int off = TB + row * ROWB + swz<8>(row, lc) * 16;
-          xs[jb] = *reinterpret_cast<const float4*>(base + off);
-          fs[jb] = *reinterpret_cast<const float4*>(base + kMJ * ROWB + off);
-        }
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-#pragma unroll
-          for (int ib = 0; ib < kIB; ++ib)
-#pragma unroll
-            for (int jb = 0; jb < kJB; ++jb) {
-              G[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x2f32(xs[jb][e], bt[ib][e], G[ib][jb], 0, 0, 0);
-              H[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x2f32(fs[jb][e], bt[ib][e], H[ib][jb], 0, 0, 0);
-            }
+      const int q = t * nchunks + c;
+      if (q + NS - 2 < Q) wait_vmcnt<(NS - 2) * L>();
+      else wait_vmcnt<0>();
+      __syncthreads();   // stage q is in LDS for every wave; stage q-1 is free again
+      if (c == 0 && t + 1 < ntiles) issue_bias(a, sb_lds + ((t + 1) & 1) * (4 * kMJ * 4), j0 + kMJ, wave, lane);
+      const int qn = q + NS - 1;
+      if (qn < Q) {
+        const int tn = qn / nchunks;
+        issue_stage<ESZ, NTP, NSP>(gb, plane, n_pad, smem_lds + (qn % NS) * STAGE, qn - tn * nchunks, i0,
+                                   jb0 + (int64_t)tn * kMJ, wave, lane);
       }
-      __builtin_amdgcn_s_waitcnt(0);
-      __syncthreads();
+      const unsigned char* base = smem + (q % NS) * STAGE;
+      if (VAR == 0) mfma_stage_f32(base, G, H);
+      else mfma_stage_bf16<VAR>(base, G, H);
     }
+    const bool diag = j0 < i0 + kMI && i0 < j0 + kMJ;
+    const float* sb = &sbuf[t & 1][0];
 #pragma unroll
     for (int ib = 0; ib < kIB; ++ib) {
       const int64_t i = i0 + wi * (32 * kIB) + ib * 32 + col;
-      epilogue_target<S>(a, G[ib], H[ib], sb, i, j0, wj * (32 * kJB), g, at[ib], margin, M[ib], Ssum[ib]);
+      // keep one target's accumulators in flight at a time (register pressure)
+      __builtin_amdgcn_sched_barrier(0);
+      epilogue_target<S>(a, &rare, G[ib], H[ib], sb, i, j0, wj * (32 * kJB), g, diag, at[ib], margin, M[ib],
+                         Ssum[ib]);
     }
+    __builtin_amdgcn_sched_barrier(0);
   }
   merge_and_store<S>(a, M, Ssum, i0, split, reinterpret_cast<float2*>(smem));
 }
@@ -515,9 +611,9 @@ yy_status launch_src_bias(hipStream_t st, const PairArgs& pa, const MfmaExtra& e
 
 template <int S>
 static yy_status launch_s(hipStream_t st, const MArgs& m, int prec, int nblocks) {
-  if (prec == YY_PREC_BF16X3) k_pair_mfma_bf16<S, 3><<<nblocks, kNT, 0, st>>>(m);
-  else if (prec == YY_PREC_BF16X1) k_pair_mfma_bf16<S, 1><<<nblocks, kNT, 0, st>>>(m);
-  else k_pair_mfma_f32<S><<<nblocks, kNT, 0, st>>>(m);
+  if (prec == YY_PREC_BF16X3) k_pair_mfma<S, 3, 4><<<nblocks, kNT, 0, st>>>(m);
+  else if (prec == YY_PREC_BF16X1) k_pair_mfma<S, 1, 8><<<nblocks, kNT, 0, st>>>(m);
+  else k_pair_mfma<S, 0, 4><<<nblocks, kNT, 0, st>>>(m);
   YY_LAUNCH_CHECK("k_pair_mfma");
   return YY_OK;
 }

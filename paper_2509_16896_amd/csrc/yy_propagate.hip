@@ -21,7 +21,7 @@ namespace yy {
 
 // ---------------------------------------------------------------------------
 // (1) node preparation: one wavefront per node.
-// Matrix-core planes are tiled [plane][rp/32][n_pad][32] so that 32 K values
+// Matrix-core planes are tiled [plane][rp/16][n_pad][16] so that 16 K values
 // of consecutive nodes are contiguous; rows n..n_pad-1 are zero.
 __global__ void __launch_bounds__(kBlock) k_prepare(int64_t n, int64_t n_pad, int32_t r, int32_t rp,
                                                     int32_t drift, const double* __restrict__ A,
@@ -38,7 +38,7 @@ __global__ void __launch_bounds__(kBlock) k_prepare(int64_t n, int64_t n_pad, in
   for (int64_t i = wave; i < n_pad; i += nwaves) {
     if (i >= n) {
       for (int32_t k = lane; k < rp; k += 64) {
-        const size_t t = ((size_t)(k >> 5) * n_pad + i) * 32 + (k & 31);
+        const size_t t = ((size_t)(k >> 4) * n_pad + i) * 16 + (k & 15);
         if (bf) bf[t] = bf[plane + t] = bf[2 * plane + t] = bf[3 * plane + t] = 0;
         if (f32t) f32t[t] = f32t[plane + t] = 0.f;
       }
@@ -72,7 +72,7 @@ __global__ void __launch_bounds__(kBlock) k_prepare(int64_t n, int64_t n_pad, in
       const size_t o = (size_t)i * rp + k;
       xc32[o] = xcv;
       f32[o] = fv;
-      const size_t t = ((size_t)(k >> 5) * n_pad + i) * 32 + (k & 31);
+      const size_t t = ((size_t)(k >> 4) * n_pad + i) * 16 + (k & 15);
       if (bf) {
         const uint16_t xh = f32_to_bf16(xcv);
         const uint16_t xl = f32_to_bf16((float)(xcd - (double)bf16_to_f32(xh)));
