@@ -29,8 +29,9 @@ typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16_t;
 constexpr int kMI = 256;   // targets per block
 constexpr int kMJ = 128;   // sources per tile
 constexpr int kKC = 16;    // K per LDS stage
-constexpr int kNT = 256;   // 4 waves: 2 along targets x 2 along sources
-constexpr int kIB = 4;     // 32-wide target blocks per wave (128 targets)
+constexpr int kNT = 512;   // 8 waves (2 per SIMD): 4 along targets x 2 along sources
+constexpr int kWaves = kNT / 64;
+constexpr int kIB = 2;     // 32-wide target blocks per wave (64 targets)
 constexpr int kJB = 2;     // 32-wide source blocks per wave (64 sources)
 constexpr float kSkip = 64.f;     // tiles whose exponents are all 2^-64 below the max are skipped
 
@@ -338,13 +339,13 @@ __device__ inline void issue_stage(const unsigned char* gb, uint64_t plane_bytes
   constexpr int RPR = 64 / CPR;                // rows per 1 KB region
   constexpr int TREG = kMI / RPR, SREG = kMJ / RPR;
   constexpr int R = NTP * TREG + NSP * SREG;
-  static_assert(R % 4 == 0, "regions per stage must split over 4 waves");
+  static_assert(R % kWaves == 0, "regions per stage must split over the waves");
   const unsigned char* tb = gb + ((uint64_t)c * (uint64_t)n_pad + (uint64_t)i0) * ROWB;
   const unsigned char* sbp = gb + ((uint64_t)c * (uint64_t)n_pad + (uint64_t)j0) * ROWB;
   const int rl = lane / CPR, pc = lane % CPR;
 #pragma unroll
-  for (int u = 0; u < R / 4; ++u) {
-    const int q = wave + 4 * u;   // wave-uniform
+  for (int u = 0; u < R / kWaves; ++u) {
+    const int q = wave + kWaves * u;   // wave-uniform
     const unsigned char* src;
     int off;
     if (q < NTP * TREG) {
@@ -479,7 +480,7 @@ __global__ void __launch_bounds__(kNT, 1) k_pair_mfma(MArgs a) {
   constexpr int NSP = VAR == 3 ? 4 : 2;
   constexpr int ROWB = kKC * ESZ;
   constexpr int STAGE = (NTP * kMI + NSP * kMJ) * ROWB;
-  constexpr int L = STAGE / 1024 / 4;          // copies per wave per stage
+  constexpr int L = STAGE / 1024 / kWaves;     // copies per wave per stage
   __shared__ __attribute__((aligned(1024))) unsigned char smem[NS * STAGE];
   __shared__ __attribute__((aligned(1024))) float sbuf[2][4 * kMJ];
 
