@@ -59,9 +59,12 @@ struct MArgs {
 };
 
 // Physical 16-byte chunk of logical chunk c in LDS row `row` (bank-conflict swizzle).
+// A 32-lane group reads 16 bytes from each of 32 consecutive rows; the XOR
+// makes any 8 (16) consecutive rows hit distinct 16-byte slots of a 128-byte
+// (256-byte) bank window.
 template <int CPR>
 __device__ inline int swz(int row, int c) {
-  return CPR == 2 ? (c ^ ((row >> 2) & 1)) : (c ^ ((row >> 1) & 3));
+  return CPR == 2 ? (c ^ ((row >> 2) & 1) ^ ((row >> 3) & 1)) : (c ^ ((row >> 1) & 3) ^ ((row >> 3) & 1));
 }
 
 // Block -> (target block, source split).  Blocks are dealt round-robin to the 8
@@ -469,12 +472,16 @@ __device__ inline void mfma_stage_f32(const unsigned char* base, f32x16_t (&G)[k
 }
 
 // The pairwise kernel.  VAR: 3 = BF16 hi/lo split, 1 = BF16 hi only, 0 = FP32.
-// The (source tile, K chunk) steps of a block form one flat sequence; stage
-// q % NS of an NS-deep LDS ring holds step q, whose copies were issued NS - 1
-// steps earlier, so the pipeline keeps running across tile boundaries while a
-// tile's epilogue folds its products into the running (max, sum).
-template <int S, int VAR, int NS>
+// The (source tile, K chunk) steps of a block form one flat sequence, taken
+// in groups of SPB steps, one barrier per group.  The LDS ring holds NS
+// stages = NS / SPB groups: while one group is consumed the copies of the
+// next LA = NS / SPB - 1 groups are in flight, so the pipeline keeps running
+// across tile boundaries while a tile's epilogue folds its products into the
+// running (max, sum).
+template <int S, int VAR, int NS, int SPB>
 __global__ void __launch_bounds__(kNT, 1) k_pair_mfma(MArgs a) {
+  static_assert(NS % SPB == 0 && NS / SPB >= 2, "the ring holds at least two groups of stages");
+  constexpr int LA = NS / SPB - 1;
   constexpr int ESZ = VAR == 0 ? 4 : 2;
   constexpr int NTP = VAR == 3 ? 2 : 1;
   constexpr int NSP = VAR == 3 ? 4 : 2;
@@ -509,7 +516,7 @@ __global__ void __launch_bounds__(kNT, 1) k_pair_mfma(MArgs a) {
 
   issue_bias(a, sb_lds, jb0, wave, lane);
 #pragma unroll
-  for (int p = 0; p < NS - 1; ++p)
+  for (int p = 0; p < LA * SPB; ++p)
     if (p < Q) issue_stage<ESZ, NTP, NSP>(gb, plane, n_pad, smem_lds + p * STAGE, p % nchunks, i0,
                                           jb0 + (int64_t)(p / nchunks) * kMJ, wave, lane);
 
@@ -517,21 +524,28 @@ __global__ void __launch_bounds__(kNT, 1) k_pair_mfma(MArgs a) {
     const int64_t j0 = jb0 + (int64_t)t * kMJ;
     f32x16_t G[kIB][kJB], H[kIB][kJB];
     zero_acc<S>(G, H);
-    for (int c = 0; c < nchunks; ++c) {
+    for (int c = 0; c < nchunks; c += SPB) {
       const int q = t * nchunks + c;
-      if (q + NS - 2 < Q) wait_vmcnt<(NS - 2) * L>();
+      // this wave's copies of steps q .. q+SPB-1 have landed (the later groups may still fly) ...
+      if (q + LA * SPB - 1 < Q) wait_vmcnt<(LA - 1) * SPB * L>();
       else wait_vmcnt<0>();
-      __syncthreads();   // stage q is in LDS for every wave; stage q-1 is free again
+      __syncthreads();   // ... for every wave; the previous group's stages are free again
       if (c == 0 && t + 1 < ntiles) issue_bias(a, sb_lds + ((t + 1) & 1) * (4 * kMJ * 4), j0 + kMJ, wave, lane);
-      const int qn = q + NS - 1;
-      if (qn < Q) {
-        const int tn = qn / nchunks;
-        issue_stage<ESZ, NTP, NSP>(gb, plane, n_pad, smem_lds + (qn % NS) * STAGE, qn - tn * nchunks, i0,
-                                   jb0 + (int64_t)tn * kMJ, wave, lane);
+#pragma unroll
+      for (int u = 0; u < SPB; ++u) {
+        const int qn = q + LA * SPB + u;
+        if (qn < Q) {
+          const int tn = qn / nchunks;
+          issue_stage<ESZ, NTP, NSP>(gb, plane, n_pad, smem_lds + (qn % NS) * STAGE, qn - tn * nchunks, i0,
+                                     jb0 + (int64_t)tn * kMJ, wave, lane);
+        }
       }
-      const unsigned char* base = smem + (q % NS) * STAGE;
-      if (VAR == 0) mfma_stage_f32(base, G, H);
-      else mfma_stage_bf16<VAR>(base, G, H);
+#pragma unroll
+      for (int u = 0; u < SPB; ++u) {
+        const unsigned char* base = smem + ((q + u) % NS) * STAGE;
+        if (VAR == 0) mfma_stage_f32(base, G, H);
+        else mfma_stage_bf16<VAR>(base, G, H);
+      }
     }
     const bool diag = j0 < i0 + kMI && i0 < j0 + kMJ;
     const float* sb = &sbuf[t & 1][0];
@@ -612,9 +626,9 @@ yy_status launch_src_bias(hipStream_t st, const PairArgs& pa, const MfmaExtra& e
 
 template <int S>
 static yy_status launch_s(hipStream_t st, const MArgs& m, int prec, int nblocks) {
-  if (prec == YY_PREC_BF16X3) k_pair_mfma<S, 3, 4><<<nblocks, kNT, 0, st>>>(m);
-  else if (prec == YY_PREC_BF16X1) k_pair_mfma<S, 1, 8><<<nblocks, kNT, 0, st>>>(m);
-  else k_pair_mfma<S, 0, 4><<<nblocks, kNT, 0, st>>>(m);
+  if (prec == YY_PREC_BF16X3) k_pair_mfma<S, 3, 4, 2><<<nblocks, kNT, 0, st>>>(m);
+  else if (prec == YY_PREC_BF16X1) k_pair_mfma<S, 1, 8, 4><<<nblocks, kNT, 0, st>>>(m);
+  else k_pair_mfma<S, 0, 4, 2><<<nblocks, kNT, 0, st>>>(m);
   YY_LAUNCH_CHECK("k_pair_mfma");
   return YY_OK;
 }
