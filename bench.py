@@ -28,7 +28,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "filter steps/sec + propagation TFLOP/s at r=1000,n=65536 vs plain FP32, same error"
-PEAK_TFLOPS = {"bf16x3": 2500.0, "bf16x1": 2500.0, "fp32_mfma": 157.3}
+PEAK_TFLOPS = {"bf16x3": 2500.0, "bf16x3g": 2500.0, "bf16x1": 2500.0, "fp32_mfma": 157.3}
 VALU_FP32_PEAK = 78.6   # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz, packed FP32 disabled
 
 
@@ -132,7 +132,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--prec", default="bf16x3", choices=["fp32", "fp32_mfma", "bf16x3", "bf16x1"])
+    ap.add_argument("--prec", default="bf16x3", choices=["fp32", "fp32_mfma", "bf16x3", "bf16x3g", "bf16x1"])
     ap.add_argument("--baseline-prec", default="fp32_mfma", help="plain FP32 form timed beside ('none' to skip)")
     ap.add_argument("--baseline-steps", type=int, default=4)
     ap.add_argument("--workload", default="cubic_r1000", choices=["cubic_r1000", "cubic_r100"])
@@ -187,7 +187,7 @@ def main():
         log(f"[bench] oracle {cpu['value']:.3g} steps/s on {cpu['cores']} threads; sampled rows max rel err {parity:.3g}")
     f.close()
 
-    dtype = {"fp32": "f32", "fp32_mfma": "f32", "bf16x3": "bf16", "bf16x1": "bf16"}[args.prec]
+    dtype = {"fp32": "f32", "fp32_mfma": "f32", "bf16x3": "bf16", "bf16x3g": "bf16", "bf16x1": "bf16"}[args.prec]
     line = {
         "metric": METRIC, "value": round(steps_s, 4), "unit": "steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed / args.steps, 3),

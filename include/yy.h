@@ -119,7 +119,8 @@ typedef enum {
   YY_PREC_FP32 = 1,      /* plain FP32: direct differences on the vector ALUs */
   YY_PREC_FP32_MFMA = 2, /* FP32 matrix cores for the distance expansion + exact near pairs */
   YY_PREC_BF16X3 = 3,    /* BF16 hi/lo split (3 products) on matrix cores + exact near pairs */
-  YY_PREC_BF16X1 = 4     /* one BF16 product on matrix cores as a screen + exact near pairs */
+  YY_PREC_BF16X1 = 4,    /* one BF16 product on matrix cores as a screen + exact near pairs */
+  YY_PREC_BF16X3G = 5    /* BF16X3 for x_i.x_j, one BF16 product for the tau-scaled x_i.f_j */
 } yy_prec;
 
 /* ------------------------------------------------------------------------ */

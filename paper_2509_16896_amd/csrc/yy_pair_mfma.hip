@@ -16,8 +16,9 @@
 // the FP64 norm |f_i|^2), with the same arithmetic as the vector-ALU kernel,
 // so the approximate products only ever contribute terms that are at least
 // 2^-80 below the maximum.  Variants:
-//   BF16X3: hi/lo split of both operands, hi*hi + lo*hi + hi*lo (3 MFMAs),
-//   BF16X1: hi*hi only (a screen),  FP32: v_mfma_f32_32x32x2_f32 on FP32 data.
+//   BF16X3:  hi/lo split of both operands, hi*hi + lo*hi + hi*lo, for G and H,
+//   BF16X3G: the split for G only; H, which enters scaled by tau_s, is hi*hi,
+//   BF16X1:  hi*hi only (a screen),  FP32: v_mfma_f32_32x32x2_f32 on FP32 data.
 #include "yy_common.h"
 #include "yy_internal.h"
 
@@ -33,7 +34,7 @@ constexpr int kNT = 512;   // 8 waves (2 per SIMD): 4 along targets x 2 along so
 constexpr int kWaves = kNT / 64;
 constexpr int kIB = 2;     // 32-wide target blocks per wave (64 targets)
 constexpr int kJB = 2;     // 32-wide source blocks per wave (64 sources)
-constexpr float kSkip = 64.f;     // tiles whose exponents are all 2^-64 below the max are skipped
+constexpr float kSkip = 64.f;     // depth (bits) below the running maximum at which terms are dropped
 
 struct MArgs {
   int64_t n, n_pad;
@@ -52,7 +53,7 @@ struct MArgs {
   const float* bsrc;           // [S][n_pad]: lw2_j - kap_s |m_j^s|^2, -inf for invalid sources
   const double* node;          // [3][n]
   const double* scal;          // [1] = max |x - centre|, [2] = max |f|
-  double eps_op;               // relative error of one product from operand rounding
+  double eps_g, eps_h;         // relative error of one G / H product from operand rounding
   float2* part;                // [nsplit][S][n]
   int32_t nsplit, tb_count, group_t;
   int64_t j_per_split;
@@ -203,7 +204,9 @@ __device__ inline void epilogue_target(const MArgs& a, const Rare* rare, const f
         if (self && jl == dself) e = -INFINITY;
         m = fmaxf(m, e);
       }
-    if (!(m > M[s] - kSkip)) continue;   // every term is below 2^-64 of the running maximum
+    // Every exact exponent of the slab is at most m + (margin - kSkip - 16): below
+    // 2^-(kSkip+16) of the running maximum unless m > M - margin.
+    if (!(m > M[s] - margin[s])) continue;
     float e[32];
 #pragma unroll
     for (int jb = 0; jb < kJB; ++jb)
@@ -271,7 +274,7 @@ __device__ inline void init_targets(const MArgs& a, int64_t i0, int split, float
 #pragma unroll
   for (int s = 0; s < S; ++s) {
     const double XT = X + a.taud[s] * F;
-    const double dD = (a.eps_op + gam) * 2.0 * X * XT + 16.0 * 0x1p-24 * XT * XT;
+    const double dD = 2.0 * X * ((a.eps_g + gam) * X + (a.eps_h + gam) * a.taud[s] * F) + 16.0 * 0x1p-24 * XT * XT;
     margin[s] = (float)(2.0 * a.kapd[s] * dD + (double)kSkip + 16.0);
   }
 #pragma unroll
@@ -342,13 +345,14 @@ __device__ inline void issue_stage(const unsigned char* gb, uint64_t plane_bytes
   constexpr int RPR = 64 / CPR;                // rows per 1 KB region
   constexpr int TREG = kMI / RPR, SREG = kMJ / RPR;
   constexpr int R = NTP * TREG + NSP * SREG;
-  static_assert(R % kWaves == 0, "regions per stage must split over the waves");
+  constexpr int RW = (R + kWaves - 1) / kWaves;
   const unsigned char* tb = gb + ((uint64_t)c * (uint64_t)n_pad + (uint64_t)i0) * ROWB;
   const unsigned char* sbp = gb + ((uint64_t)c * (uint64_t)n_pad + (uint64_t)j0) * ROWB;
   const int rl = lane / CPR, pc = lane % CPR;
 #pragma unroll
-  for (int u = 0; u < R / kWaves; ++u) {
+  for (int u = 0; u < RW; ++u) {
     const int q = wave + kWaves * u;   // wave-uniform
+    if (R % kWaves != 0 && q >= R) break;
     const unsigned char* src;
     int off;
     if (q < NTP * TREG) {
@@ -391,12 +395,13 @@ __device__ inline void zero_acc(f32x16_t (&G)[kIB][kJB], f32x16_t (&H)[kIB][kJB]
       }
 }
 
-// One K stage of the products on the matrix cores.
+// One K stage of the products on the matrix cores.  PASSES: 3 = split G and H,
+// 2 = split G with H hi*hi, 1 = hi*hi only.
 template <int PASSES>
 __device__ inline void mfma_stage_bf16(const unsigned char* base, f32x16_t (&G)[kIB][kJB],
                                        f32x16_t (&H)[kIB][kJB]) {
   constexpr int ROWB = 32;
-  constexpr int NTP = PASSES == 3 ? 2 : 1;
+  constexpr int NTP = PASSES >= 2 ? 2 : 1;
   constexpr int TB = NTP * kMI * ROWB;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wi = wave >> 1, wj = wave & 1, col = lane & 31, g = lane >> 5;
@@ -406,7 +411,7 @@ __device__ inline void mfma_stage_bf16(const unsigned char* base, f32x16_t (&G)[
     const int row = wi * (32 * kIB) + ib * 32 + col;
     const int off = row * ROWB + swz<2>(row, g) * 16;
     bh[ib] = *reinterpret_cast<const bf16x8_t*>(base + off);
-    if (PASSES == 3) bl[ib] = *reinterpret_cast<const bf16x8_t*>(base + kMI * ROWB + off);
+    if (PASSES >= 2) bl[ib] = *reinterpret_cast<const bf16x8_t*>(base + kMI * ROWB + off);
   }
 #pragma unroll
   for (int jb = 0; jb < kJB; ++jb) {
@@ -414,10 +419,8 @@ __device__ inline void mfma_stage_bf16(const unsigned char* base, f32x16_t (&G)[
     const int off = TB + row * ROWB + swz<2>(row, g) * 16;
     xh[jb] = *reinterpret_cast<const bf16x8_t*>(base + off);
     fh[jb] = *reinterpret_cast<const bf16x8_t*>(base + kMJ * ROWB + off);
-    if (PASSES == 3) {
-      xl[jb] = *reinterpret_cast<const bf16x8_t*>(base + 2 * kMJ * ROWB + off);
-      fl[jb] = *reinterpret_cast<const bf16x8_t*>(base + 3 * kMJ * ROWB + off);
-    }
+    if (PASSES >= 2) xl[jb] = *reinterpret_cast<const bf16x8_t*>(base + 2 * kMJ * ROWB + off);
+    if (PASSES == 3) fl[jb] = *reinterpret_cast<const bf16x8_t*>(base + 3 * kMJ * ROWB + off);
   }
 #pragma unroll
   for (int ib = 0; ib < kIB; ++ib)
@@ -425,10 +428,12 @@ __device__ inline void mfma_stage_bf16(const unsigned char* base, f32x16_t (&G)[
     for (int jb = 0; jb < kJB; ++jb) {
       G[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[jb], bh[ib], G[ib][jb], 0, 0, 0);
       H[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fh[jb], bh[ib], H[ib][jb], 0, 0, 0);
-      if (PASSES == 3) {
+      if (PASSES >= 2) {
         G[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xl[jb], bh[ib], G[ib][jb], 0, 0, 0);
-        H[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fl[jb], bh[ib], H[ib][jb], 0, 0, 0);
         G[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[jb], bl[ib], G[ib][jb], 0, 0, 0);
+      }
+      if (PASSES == 3) {
+        H[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fl[jb], bh[ib], H[ib][jb], 0, 0, 0);
         H[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fh[jb], bl[ib], H[ib][jb], 0, 0, 0);
       }
     }
@@ -471,7 +476,8 @@ __device__ inline void mfma_stage_f32(const unsigned char* base, f32x16_t (&G)[k
   }
 }
 
-// The pairwise kernel.  VAR: 3 = BF16 hi/lo split, 1 = BF16 hi only, 0 = FP32.
+// The pairwise kernel.  VAR: 3 = BF16 hi/lo split of G and H, 2 = split of G
+// only, 1 = BF16 hi only, 0 = FP32.
 // The (source tile, K chunk) steps of a block form one flat sequence, taken
 // in groups of SPB steps, one barrier per group.  The LDS ring holds NS
 // stages = NS / SPB groups: while one group is consumed the copies of the
@@ -483,11 +489,12 @@ __global__ void __launch_bounds__(kNT, 1) k_pair_mfma(MArgs a) {
   static_assert(NS % SPB == 0 && NS / SPB >= 2, "the ring holds at least two groups of stages");
   constexpr int LA = NS / SPB - 1;
   constexpr int ESZ = VAR == 0 ? 4 : 2;
-  constexpr int NTP = VAR == 3 ? 2 : 1;
-  constexpr int NSP = VAR == 3 ? 4 : 2;
+  constexpr int NTP = VAR >= 2 ? 2 : 1;
+  constexpr int NSP = VAR == 3 ? 4 : VAR == 2 ? 3 : 2;
   constexpr int ROWB = kKC * ESZ;
   constexpr int STAGE = (NTP * kMI + NSP * kMJ) * ROWB;
   constexpr int L = STAGE / 1024 / kWaves;     // copies per wave per stage
+  static_assert(LA == 1 || L * kWaves * 1024 == STAGE, "deep lookahead needs equal copies per wave");
   __shared__ __attribute__((aligned(1024))) unsigned char smem[NS * STAGE];
   __shared__ __attribute__((aligned(1024))) float sbuf[2][4 * kMJ];
 
@@ -591,7 +598,10 @@ static MArgs make_args(const PairArgs& pa, int prec, const MfmaExtra& ex) {
   m.r = pa.r;
   m.rp = pa.rp;
   m.S = pa.S;
-  m.eps_op = prec == YY_PREC_BF16X3 ? 0x1p-14 : prec == YY_PREC_BF16X1 ? 0x1p-7 : 0x1p-22;
+  // hi/lo split product: 2^-16 per operand split plus cross terms; hi only:
+  // 2^-8 per operand; FP32 operands: 2^-24 per operand (rounded up).
+  m.eps_g = prec == YY_PREC_BF16X3 || prec == YY_PREC_BF16X3G ? 0x1p-14 : prec == YY_PREC_BF16X1 ? 0x1p-7 : 0x1p-22;
+  m.eps_h = prec == YY_PREC_BF16X3 ? 0x1p-14 : prec == YY_PREC_BF16X3G || prec == YY_PREC_BF16X1 ? 0x1p-7 : 0x1p-22;
   for (int s = 0; s < pa.S; ++s) {
     const double kap = ex.kapd[s], tau = ex.taud[s];
     m.kap[s] = (float)kap;
@@ -627,6 +637,7 @@ yy_status launch_src_bias(hipStream_t st, const PairArgs& pa, const MfmaExtra& e
 template <int S>
 static yy_status launch_s(hipStream_t st, const MArgs& m, int prec, int nblocks) {
   if (prec == YY_PREC_BF16X3) k_pair_mfma<S, 3, 4, 2><<<nblocks, kNT, 0, st>>>(m);
+  else if (prec == YY_PREC_BF16X3G) k_pair_mfma<S, 2, 4, 2><<<nblocks, kNT, 0, st>>>(m);
   else if (prec == YY_PREC_BF16X1) k_pair_mfma<S, 1, 8, 4><<<nblocks, kNT, 0, st>>>(m);
   else k_pair_mfma<S, 0, 4, 2><<<nblocks, kNT, 0, st>>>(m);
   YY_LAUNCH_CHECK("k_pair_mfma");

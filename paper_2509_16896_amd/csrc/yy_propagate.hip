@@ -484,7 +484,7 @@ extern "C" yy_status yy_propagate(yy_ctx ctx, const yy_model* model, const yy_sc
   if (!x || !box_lo || !box_hi || !logw_in || !logw_out)
     return fail(YY_ERR_ARG, "yy_propagate: NULL array");
   if (logw_in == logw_out) return fail(YY_ERR_ARG, "yy_propagate: logw_in and logw_out alias");
-  if (prec < YY_PREC_AUTO || prec > YY_PREC_BF16X1) return fail(YY_ERR_ARG, "yy_propagate: bad prec");
+  if (prec < YY_PREC_AUTO || prec > YY_PREC_BF16X3G) return fail(YY_ERR_ARG, "yy_propagate: bad prec");
   const int32_t S = scales->S;
   double c[YY_MAX_SCALES + 1];
   for (int s = 0; s < S; ++s)
@@ -499,7 +499,8 @@ extern "C" yy_status yy_propagate(yy_ctx ctx, const yy_model* model, const yy_sc
   const bool mfma = prec != YY_PREC_FP32;
   YY_HIP(hipSetDevice(ctx->device));
   st = prepare_nodes(ctx, model, n, x, node_version, box_lo, box_hi,
-                     prec == YY_PREC_BF16X3 || prec == YY_PREC_BF16X1, prec == YY_PREC_FP32_MFMA);
+                     prec == YY_PREC_BF16X3 || prec == YY_PREC_BF16X3G || prec == YY_PREC_BF16X1,
+                     prec == YY_PREC_FP32_MFMA);
   if (st != YY_OK) return st;
   const Prepared& P = ctx->prep;
 

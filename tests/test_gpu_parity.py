@@ -237,7 +237,7 @@ MFMA_CASES = {
 }
 
 
-@pytest.mark.parametrize("prec", ["fp32_mfma", "bf16x3", "bf16x1"])
+@pytest.mark.parametrize("prec", ["fp32_mfma", "bf16x3", "bf16x3g", "bf16x1"])
 @pytest.mark.parametrize("name", sorted(MFMA_CASES))
 def test_propagate_mfma_parity(ctx, name, prec):
     kw = dict(MFMA_CASES[name])
