@@ -422,6 +422,8 @@ __device__ inline void mfma_stage_bf16(const unsigned char* base, f32x16_t (&G)[
     if (PASSES >= 2) xl[jb] = *reinterpret_cast<const bf16x8_t*>(base + 2 * kMJ * ROWB + off);
     if (PASSES == 3) fl[jb] = *reinterpret_cast<const bf16x8_t*>(base + 3 * kMJ * ROWB + off);
   }
+  // all fragment reads of the stage are issued before its matrix-core burst
+  __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
   for (int ib = 0; ib < kIB; ++ib)
 #pragma unroll
@@ -437,6 +439,7 @@ __device__ inline void mfma_stage_bf16(const unsigned char* base, f32x16_t (&G)[
         H[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fh[jb], bl[ib], H[ib][jb], 0, 0, 0);
       }
     }
+  __builtin_amdgcn_sched_barrier(0);
 }
 
 // FP32: within a 16-wide K stage, lane group g owns k = 8 g + t in K step t
