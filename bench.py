@@ -17,6 +17,7 @@ the host cores.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -30,6 +31,10 @@ if ROOT not in sys.path:
 METRIC = "filter steps/sec + propagation TFLOP/s at r=1000,n=65536 vs plain FP32, same error"
 PEAK_TFLOPS = {"bf16x3": 2500.0, "bf16x3g": 2500.0, "bf16x1": 2500.0, "fp32_mfma": 157.3}
 VALU_FP32_PEAK = 78.6   # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz, packed FP32 disabled
+# matrix-core products executed per algorithmic product (x.x and x.f each count once)
+EXEC_PER_ALG = {"bf16x3": 3.0, "bf16x3g": 2.0, "bf16x1": 1.0, "fp32_mfma": 1.0}
+PAIR_SRC = os.path.join(ROOT, "paper_2509_16896_amd", "csrc", "yy_pair_mfma.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pair_mfma_cubic_r1000_n65536_traffic.md")
 
 
 def log(msg):
@@ -68,6 +73,56 @@ def run_gpu(w, dys, prec, warmup, steps, timing=True):
     return f, k, t1 - t0, ms, launches
 
 
+def kernel_source_hash() -> str:
+    with open(PAIR_SRC, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def recorded_traffic(prec: str):
+    """HBM bytes per launch of the pairwise kernel from the committed counter summary, or None
+    when the summary is missing, covers another form, or the kernel source changed since."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            if line.startswith("traffic_") and "=" in line:
+                k, v = line.split("=", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("traffic_source_hash") != kernel_source_hash() or vals.get("traffic_prec") != prec:
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def traffic_probe(w, prec):
+    """Run under rocprofv3 --pmc: one device copy of exactly 1 GiB (the calibration kernel),
+    then one yy_propagate of the workload (the pairwise kernel)."""
+    import torch
+    from paper_2509_16896_amd import yy
+    from paper_2509_16896_amd.filter import GpuFilter
+
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+    from paper_2509_16896_amd import workloads as W
+
+    xs, dys = W.simulate(w)
+    f = GpuFilter(w, prec=prec)
+    f.set_observations(dys)
+    f.init()
+    out = torch.empty(w.n, dtype=torch.float64, device=f.dev)
+    yy.yy_propagate(f.ctx, f.model, f.scales, prec, w.n, f.x, f.version, f.lo, f.hi, w.dt, f.lw[f.cur], out)
+    torch.cuda.synchronize()
+    f.close()
+    log(f"[bench] traffic probe done ({prec}, source hash {kernel_source_hash()})")
+
+
 def cpu_baseline(w, f, k_last, target_s=15.0):
     """The oracle on a bounded sample of one step of the same workload: the propagation of a
     few target rows (extrapolated to all n rows) plus the full correction and normalisation."""
@@ -87,15 +142,20 @@ def cpu_baseline(w, f, k_last, target_s=15.0):
     s = np.asarray(w.scales, float)
     c = oracle.kernel_coefficients(s)
     rng = np.random.default_rng(0)
-    probe = rng.choice(w.n, 4, replace=False)
-    t0 = time.perf_counter()
-    oracle.propagate_rows(model, s, c, x, lo, hi, w.dt, lw, probe)
-    per_row = (time.perf_counter() - t0) / len(probe)
-    nrows = int(max(8, min(512, target_s / max(per_row, 1e-6))))
-    rows = np.sort(rng.choice(w.n, nrows, replace=False))
-    t0 = time.perf_counter()
-    ref_rows, _ = oracle.propagate_rows(model, s, c, x, lo, hi, w.dt, lw, rows)
-    t_rows = time.perf_counter() - t0
+    order = rng.permutation(w.n)
+    # target rows in growing batches until about target_s seconds of oracle work are done
+    done, batch, t_rows, parts = 0, 16, 0.0, []
+    while t_rows < target_s and done < w.n:
+        rows_b = np.sort(order[done:done + batch])
+        t0 = time.perf_counter()
+        ref_b, _ = oracle.propagate_rows(model, s, c, x, lo, hi, w.dt, lw, rows_b)
+        t_rows += time.perf_counter() - t0
+        parts.append((rows_b, ref_b))
+        done += len(rows_b)
+        batch *= 2
+    rows = np.concatenate([p[0] for p in parts])
+    ref_rows = np.concatenate([p[1] for p in parts])
+    nrows = len(rows)
     dy = f.dys[k_last - 1].cpu().numpy()
     t0 = time.perf_counter()
     lw2 = oracle.loglik_update(model, x, dy, w.dt, lw)
@@ -132,12 +192,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--prec", default="bf16x3", choices=["fp32", "fp32_mfma", "bf16x3", "bf16x3g", "bf16x1"])
+    ap.add_argument("--prec", default="bf16x3g", choices=["fp32", "fp32_mfma", "bf16x3", "bf16x3g", "bf16x1"])
+    ap.add_argument("--other-forms", default="bf16x3,bf16x1",
+                    help="matrix-core forms whose pairwise kernel is also timed ('none' to skip)")
     ap.add_argument("--baseline-prec", default="fp32_mfma", help="plain FP32 form timed beside ('none' to skip)")
     ap.add_argument("--baseline-steps", type=int, default=4)
     ap.add_argument("--workload", default="cubic_r1000", choices=["cubic_r1000", "cubic_r100"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="one 1 GiB copy + one yy_propagate, for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -150,6 +214,10 @@ def main():
     from paper_2509_16896_amd import workloads as W
 
     w = {"cubic_r1000": W.cubic_r1000, "cubic_r100": W.cubic_r100}[args.workload]()
+    if args.traffic_probe:
+        w.K = 2
+        traffic_probe(w, args.prec)
+        return
     total = args.warmup + args.steps
     w.K = max(w.K, total + 1)
     xs, dys = W.simulate(w)
@@ -166,9 +234,22 @@ def main():
     roofline = {"bound": "mfma" if mfma else "alu", "achieved": round(achieved, 3),
                 "peak": PEAK_TFLOPS[args.prec] if mfma else VALU_FP32_PEAK, "unit": "TFLOP/s"}
     roofline["frac"] = round(roofline["achieved"] / roofline["peak"], 4)
-    roofline["traffic"] = None
+    roofline["traffic"] = recorded_traffic(args.prec) if args.workload == "cubic_r1000" else None
     roofline["kernel"] = "k_pair_mfma" if mfma else "k_pair_valu"
     roofline["kernel_ms"] = round(1e3 * avg_kernel_s, 3)
+    if mfma:
+        # matrix-core utilisation: executed products (3 per product for the full split) / peak
+        roofline["mfma_exec_frac"] = round(roofline["frac"] * EXEC_PER_ALG[args.prec], 4)
+
+    forms = {}
+    if args.other_forms != "none":
+        for p in [x for x in args.other_forms.split(",") if x and x != args.prec]:
+            g, _, el3, ms3, l3 = run_gpu(w, dys, p, 1, 2)
+            kms = ms3 / max(l3, 1)
+            forms[p] = {"kernel_ms": round(kms, 3), "steps_per_s": round(2 / el3, 4),
+                        "tflops_alg": round(alg_flops(w) / (kms * 1e-3) / 1e12, 2)}
+            g.close()
+            log(f"[bench] form {p}: pairwise kernel {kms:.2f} ms")
 
     base = None
     if args.baseline_prec != "none" and args.baseline_prec != args.prec:
@@ -199,6 +280,7 @@ def main():
         "roofline": roofline,
         "plain_fp32": base,
         "vs_plain_fp32": None if base is None else round(steps_s / base["steps_per_s"], 3),
+        "other_forms": forms or None,
         "sampled_row_max_rel_err": parity,
         "cpu_baseline": cpu,
     }
