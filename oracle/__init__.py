@@ -28,6 +28,10 @@ Parity status of the oracle's functions (the pins live in
   ancestors, brute-force search).
 * restart -- pinned (containment, mean of the mapped reference set, prior
   closed form).
+* learned restart proposal (``proposal.py``, NumPy) -- pinned (GELU against
+  scipy's normal CDF, loss against the brute-force Gaussian log-density of
+  samples, backward against finite differences, Adam's closed-form first
+  step, checks against direct counts).
 """
 from __future__ import annotations
 
