@@ -52,6 +52,7 @@ typedef enum {
 #define YY_FLAG_CLAMPED      2u   /* a signed multi-scale sum was <= 0 and was set to -inf */
 #define YY_FLAG_RESAMPLE_ZERO 4u  /* resampling weights summed to zero */
 #define YY_FLAG_LOW_ESS      8u   /* ESS below the restart's ess_min */
+#define YY_FLAG_PROPOSAL_FALLBACK 16u /* a learned restart box failed its checks; the plain box was used */
 
 #define YY_MAX_SCALES 6
 #define YY_MAX_R 3600             /* largest state dimension with generated direction numbers */
@@ -170,29 +171,89 @@ yy_status yy_normalise_moments(yy_ctx ctx, int64_t n, int32_t r, const double* x
                                double* w, double* logZ_step, double* logZ_acc, double* mean,
                                double* cov, double* ess);
 
+/* Learned restart proposal (not in the paper; the plain restart of Sec. 6 is
+ * its fallback).  A multilayer perceptron maps the estimate x_hat (r) through
+ * Linear(r, H) -> GELU -> Linear(H, H) -> GELU -> Linear(H, 2r) to (delta, u);
+ * GELU is the exact form x Phi(x).  The proposed restart box is centred at
+ * x_hat + delta with half-width R exp(u) per coordinate, read as +-3 standard
+ * deviations of a diagonal Gaussian s = (R/3) exp(u).  Weights and arithmetic
+ * are FP32.  Parameter vector layout (device, FP32): W1 [H x r] row-major,
+ * b1 [H], W2 [H x H], b2 [H], W3 [2r x H], b3 [2r]. */
+typedef struct yy_proposal_s* yy_proposal;
+
+/* Creates a proposal network on ctx's device; it runs on ctx's stream.
+ * params: device [P] initial parameters, or NULL for the default
+ * initialisation (W1, W2 uniform in +-1/sqrt(fan_in) from SplitMix64 keyed by
+ * seed, b1 = b2 = 0, W3 = b3 = 0 so that the first proposal is the plain box).
+ * 1 <= r <= YY_MAX_R, 1 <= hidden <= 1024.  The network must be destroyed
+ * before its context. */
+yy_status yy_proposal_create(yy_ctx ctx, int32_t r, int32_t hidden, uint64_t seed, const float* params,
+                             yy_proposal* out);
+yy_status yy_proposal_destroy(yy_proposal p);
+/* Number of parameters P = H r + H + H^2 + H + 2 r H + 2 r (host scalar). */
+yy_status yy_proposal_num_params(yy_proposal p, int64_t* P);
+/* Copies the parameters to / from device [P]; set_params also resets the
+ * Adam moments and step count. */
+yy_status yy_proposal_get_params(yy_proposal p, float* params);
+yy_status yy_proposal_set_params(yy_proposal p, const float* params);
+/* Network outputs for B estimates: xhat device [B*r] (FP64, converted to
+ * FP32), out device [B*2r] (delta then u per row). */
+yy_status yy_proposal_forward(yy_proposal p, int32_t B, const double* xhat, float* out);
+/* One training step on B pairs (x_hat of a restart, per-coordinate mean mu
+ * and variance var of the posterior samples at the next restart; device
+ * [B*r] FP64 each).  Loss = mean over pairs and coordinates of
+ *   (var + 0.01 (R/3)^2 + (mu - x_hat - delta)^2) / (2 s^2) + log s,
+ * the Gaussian negative log-likelihood of the samples without the constant
+ * (1/2) log(2 pi), with a variance floor.  Writes the loss (device FP64
+ * scalar, nullable) and the gradient (device [P] FP32, nullable); when
+ * update != 0 applies one Adam step (beta1 0.9, beta2 0.999, eps 1e-8,
+ * bias-corrected) with learning rate lr. */
+yy_status yy_proposal_train_step(yy_proposal p, int32_t B, const double* xhat, const double* mu,
+                                 const double* var, double R, double lr, int32_t update, double* loss,
+                                 float* grad);
+
+/* Per-coordinate mean and (1/n) variance of the resampled nodes x[idx[t]],
+ * t < n (FP64, two passes): the posterior samples a restart produces, used as
+ * training targets of the proposal.  x: device [n*r]; idx: device [n];
+ * mean, var: device [r]. */
+yy_status yy_sample_moments(yy_ctx ctx, int64_t n, int32_t r, const double* x, const int64_t* idx,
+                            double* mean, double* var);
+
 /* Local resample-restart (Sec. 6). */
 typedef struct {
-  double R;           /* half-width of the new box [mean - R, mean + R]^r */
-  double ess_min;     /* YY_FLAG_LOW_ESS is set when ess < ess_min (ess: device scalar or NULL) */
+  double R;           /* half-width of the plain box [mean - R, mean + R]^r */
+  double ess_min;     /* YY_FLAG_LOW_ESS is set when ess < ess_min (ess: device scalar or NULL);
+                         also the learned box's minimum prior ESS */
   uint64_t seed;      /* key of the resampling random numbers */
+  yy_proposal proposal; /* NULL: plain restart; else the learned box with fallback */
+  double cover_min;   /* learned box: minimum fraction of sample coordinates inside it */
 } yy_restart_params;
 
 /* (1) Integer systematic resampling of the normalised weights w into ancestor
  *     indices idx (W_i = floor(w_i 2^53), C = prefix sums, U = 32 bits of
  *     SplitMix64 keyed by (seed, step), P_t = floor((t 2^32 + U) W / (n 2^32)),
  *     idx[t] = min{i : C_i > P_t}).  idx may be NULL to skip it.
- * (2) New box [mean - R, mean + R]^r written to box_lo/box_hi, and the new
- *     nodes x_new = the reference codes mapped to that box (the pre-generated
- *     reference set translated to the estimate, Sec. 6).
+ * (2) The new box: with params->proposal NULL, [mean - R, mean + R]^r (the
+ *     plain restart of Sec. 6).  With a proposal, the learned box is used
+ *     when (a) at least cover_min of the coordinates of the samples
+ *     x_cur[idx[t]] lie inside it, (b) the samples' mean log-density under its
+ *     Gaussian is at least that under the plain box's (s = R/3), and (c) the
+ *     prior ESS of the new nodes is at least ess_min; otherwise the plain box
+ *     is used and YY_FLAG_PROPOSAL_FALLBACK is set.  The box goes to
+ *     box_lo/box_hi, and the new nodes x_new = the reference codes mapped to
+ *     it (the pre-generated reference set translated to the estimate, Sec. 6).
  * (3) Prior logw_new[i] = -|x_new_i - mean|^2 / 2 (the initial density
  *     N(mean, I) up to a constant), -inf for boundary nodes; not normalised.
- *   codes: device [n*r]; w: device [n]; mean: device [r]; ess: device scalar
- *   or NULL; idx: device [n] int64 or NULL; box_lo/hi: device [r];
- *   x_new: device [n*r]; logw_new: device [n]. */
-yy_status yy_restart(yy_ctx ctx, int64_t n, int32_t r, const uint32_t* codes, const double* w,
-                     const double* mean, const double* ess, int64_t step,
+ *   codes: device [n*r]; x_cur: device [n*r] (needed with a proposal, may be
+ *   NULL otherwise; must not alias x_new); w: device [n]; mean: device [r];
+ *   ess: device scalar or NULL; idx: device [n] int64 (required with a
+ *   proposal) or NULL; box_lo/hi: device [r]; x_new: device [n*r];
+ *   logw_new: device [n]; used: device int32 scalar or NULL, set to 1 when the
+ *   learned box was used, else 0. */
+yy_status yy_restart(yy_ctx ctx, int64_t n, int32_t r, const uint32_t* codes, const double* x_cur,
+                     const double* w, const double* mean, const double* ess, int64_t step,
                      const yy_restart_params* params, int64_t* idx, double* box_lo, double* box_hi,
-                     double* x_new, double* logw_new);
+                     double* x_new, double* logw_new, int32_t* used);
 
 /* ------------------------------------------------------------------------ */
 /* Timing of the pairwise kernel (the dominant kernel of yy_propagate).  While

@@ -94,6 +94,19 @@ struct yy_ctx_s {
   size_t ev_used = 0;
 };
 
+// The learned restart proposal's state (yy_proposal.hip).
+struct yy_proposal_s {
+  yy_ctx ctx = nullptr;
+  int32_t r = 0, H = 0;
+  int64_t P = 0;
+  yy::DevBuf params, adam_m, adam_v, grad, work, part;
+  int64_t work_B = 0;
+  int64_t t = 0;   // Adam steps taken
+  // offsets of W1, b1, W2, b2, W3, b3 in the parameter vector
+  int64_t oW1 = 0, ob1 = 0, oW2 = 0, ob2 = 0, oW3 = 0, ob3 = 0;
+  float* pf() const { return params.as<float>(); }
+};
+
 namespace yy {
 
 // Host-side pieces shared by the call implementations.
@@ -135,5 +148,17 @@ yy_status launch_src_bias(hipStream_t st, const PairArgs& a, const MfmaExtra& ex
 yy_status launch_pair_mfma(hipStream_t st, const PairArgs& a, int prec, const MfmaExtra& ex);
 int64_t pair_mfma_npad(int64_t n);
 int pair_mfma_rp(int32_t r);
+
+// Learned restart box (yy_proposal.hip): prepare writes the box chosen by the
+// coverage and log-density checks and the decision words dec[0..2]; finish
+// applies the prior-ESS check to the nodes generated from that box, switches
+// the box back to the plain one when it fails (dec[1] = 1: regenerate), and
+// writes `used`.
+yy_status proposal_restart_prepare(yy_ctx ctx, yy_proposal p, int64_t n, int32_t r, const double* x_cur,
+                                   const int64_t* idx, const double* mean, double R, double cover_min,
+                                   double* box_lo, double* box_hi, int** dec_out);
+yy_status proposal_restart_finish(yy_ctx ctx, yy_proposal p, int64_t n, int32_t r, const double* lw_new,
+                                  const double* mean, double R, double ess_min, double* box_lo,
+                                  double* box_hi, int* dec, int32_t* used);
 
 }  // namespace yy

@@ -104,29 +104,37 @@ __global__ void __launch_bounds__(kBlock) k_rs_search(int64_t n, int nb,
   idx[t] = lo_i;
 }
 
-// New box, nodes and prior.  One wavefront per node; the box is recomputed
-// per coordinate exactly as the node map defines it (no fused multiply-add).
-__global__ void __launch_bounds__(kBlock) k_restart_nodes(int64_t n, int32_t r, double R,
-                                                          const uint32_t* __restrict__ codes,
+// The plain box [mean - R, mean + R]^r.
+__global__ void __launch_bounds__(kBlock) k_box_plain(int32_t r, double R, const double* __restrict__ mean,
+                                                      double* __restrict__ box_lo, double* __restrict__ box_hi) {
+  const int d = blockIdx.x * kBlock + threadIdx.x;
+  if (d >= r) return;
+  box_lo[d] = __dsub_rn(mean[d], R);
+  box_hi[d] = __dadd_rn(mean[d], R);
+}
+
+// Nodes and prior in the box [box_lo, box_hi].  One wavefront per node; the
+// centre and half-width are recomputed per coordinate exactly as the node
+// map defines them (no fused multiply-add).  With `pred` set the kernel runs
+// only when *pred is non-zero (the learned restart's fallback).
+__global__ void __launch_bounds__(kBlock) k_restart_nodes(int64_t n, int32_t r, const uint32_t* __restrict__ codes,
                                                           const double* __restrict__ mean,
-                                                          double* __restrict__ box_lo,
-                                                          double* __restrict__ box_hi,
+                                                          const double* __restrict__ box_lo,
+                                                          const double* __restrict__ box_hi,
+                                                          const int* __restrict__ pred,
                                                           double* __restrict__ x_new,
                                                           double* __restrict__ logw_new) {
 #pragma clang fp contract(off)
+  if (pred && *pred == 0) return;
   const int lane = threadIdx.x & 63;
   const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t wave = gt >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-  if (gt < r) {
-    box_lo[gt] = __dsub_rn(mean[gt], R);
-    box_hi[gt] = __dadd_rn(mean[gt], R);
-  }
   for (int64_t i = wave; i < n; i += nwaves) {
     double acc = 0.0;
     int b = 0;
     for (int32_t k = lane; k < r; k += 64) {
-      const double lo = __dsub_rn(mean[k], R), hi = __dadd_rn(mean[k], R);
+      const double lo = box_lo[k], hi = box_hi[k];
       const double c = __dmul_rn(0.5, __dadd_rn(lo, hi));
       const double hw = __dmul_rn(0.5, __dsub_rn(hi, lo));
       const double u = __dsub_rn((double)codes[(size_t)i * r + k] * 0x1p-31, 1.0);
@@ -150,10 +158,14 @@ __global__ void k_ess_check(const double* __restrict__ ess, double ess_min, uint
 
 using namespace yy;
 
-extern "C" yy_status yy_restart(yy_ctx ctx, int64_t n, int32_t r, const uint32_t* codes,
+__global__ void k_set_int(int32_t* p, int32_t v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
+extern "C" yy_status yy_restart(yy_ctx ctx, int64_t n, int32_t r, const uint32_t* codes, const double* x_cur,
                                 const double* w, const double* mean, const double* ess, int64_t step,
                                 const yy_restart_params* params, int64_t* idx, double* box_lo,
-                                double* box_hi, double* x_new, double* logw_new) {
+                                double* box_hi, double* x_new, double* logw_new, int32_t* used) {
   if (!ctx) return fail(YY_ERR_ARG, "yy_restart: ctx is NULL");
   if (!params) return fail(YY_ERR_ARG, "yy_restart: params is NULL");
   if (n < 1 || n > ((int64_t)1 << 32)) return fail(YY_ERR_ARG, "yy_restart: n out of range");
@@ -162,6 +174,14 @@ extern "C" yy_status yy_restart(yy_ctx ctx, int64_t n, int32_t r, const uint32_t
   if (!codes || !mean || !box_lo || !box_hi || !x_new || !logw_new)
     return fail(YY_ERR_ARG, "yy_restart: NULL array");
   if (idx && !w) return fail(YY_ERR_ARG, "yy_restart: resampling needs w");
+  yy_proposal prop = params->proposal;
+  if (prop) {
+    if (!x_cur || !idx) return fail(YY_ERR_ARG, "yy_restart: a learned proposal needs x_cur and idx");
+    if (x_cur == x_new) return fail(YY_ERR_ARG, "yy_restart: x_cur must not alias x_new");
+    if (prop->ctx != ctx || prop->r != r) return fail(YY_ERR_ARG, "yy_restart: proposal of another context or r");
+    if (!(params->cover_min >= 0.0 && params->cover_min <= 1.0))
+      return fail(YY_ERR_ARG, "yy_restart: cover_min must be in [0, 1]");
+  }
   YY_HIP(hipSetDevice(ctx->device));
   if (ess) {
     k_ess_check<<<1, 64, 0, ctx->stream>>>(ess, params->ess_min, ctx->d_flags);
@@ -186,8 +206,29 @@ extern "C" yy_status yy_restart(yy_ctx ctx, int64_t n, int32_t r, const uint32_t
   int64_t blocks = (n + 3) / 4;
   if (blocks > 16384) blocks = 16384;
   if (blocks * kBlock < r) blocks = (r + kBlock - 1) / kBlock;
-  k_restart_nodes<<<(unsigned)blocks, kBlock, 0, ctx->stream>>>(n, r, params->R, codes, mean, box_lo,
-                                                                box_hi, x_new, logw_new);
+  int* dec = nullptr;
+  if (prop) {
+    yy_status st = proposal_restart_prepare(ctx, prop, n, r, x_cur, idx, mean, params->R, params->cover_min,
+                                            box_lo, box_hi, &dec);
+    if (st != YY_OK) return st;
+  } else {
+    k_box_plain<<<(unsigned)((r + kBlock - 1) / kBlock), kBlock, 0, ctx->stream>>>(r, params->R, mean, box_lo,
+                                                                                 box_hi);
+    YY_LAUNCH_CHECK("k_box_plain");
+  }
+  k_restart_nodes<<<(unsigned)blocks, kBlock, 0, ctx->stream>>>(n, r, codes, mean, box_lo, box_hi, nullptr,
+                                                                x_new, logw_new);
   YY_LAUNCH_CHECK("k_restart_nodes");
+  if (prop) {
+    yy_status st = proposal_restart_finish(ctx, prop, n, r, logw_new, mean, params->R, params->ess_min, box_lo,
+                                           box_hi, dec, used);
+    if (st != YY_OK) return st;
+    k_restart_nodes<<<(unsigned)blocks, kBlock, 0, ctx->stream>>>(n, r, codes, mean, box_lo, box_hi, dec + 1,
+                                                                  x_new, logw_new);
+    YY_LAUNCH_CHECK("k_restart_nodes");
+  } else if (used) {
+    k_set_int<<<1, 64, 0, ctx->stream>>>(used, 0);
+    YY_LAUNCH_CHECK("k_set_int");
+  }
   return YY_OK;
 }

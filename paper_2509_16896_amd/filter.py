@@ -1,9 +1,11 @@
 """The filter's time loop on the GPU, built on the libyy calls (Sec. 2.2.2 procedure, Sec. 6 restart).
 
 Per step k: yy_propagate -> yy_loglik_update -> yy_normalise_moments, and every
-``restart_every`` steps yy_restart (resampling, new box around the estimate,
+``restart_every`` steps yy_restart (resampling, new box around the estimate --
+the plain box, or the learned proposal's box with the plain one as fallback --
 the reference codes mapped into it, the re-centred prior) followed by a
-normalisation.  The initial state is the restart map with centre 0 and
+normalisation.  Node sets are double-buffered so that a restart can read the
+current nodes (the posterior samples) while it writes the new ones.  The initial state is the restart map with centre 0 and
 half-width ``box_half``: nodes in [-box_half, box_half]^r carrying the N(0, I)
 log-density.  All buffers are allocated once; no call reads back to the host
 inside the loop.
@@ -19,7 +21,8 @@ from .workloads import Workload
 
 class GpuFilter:
     def __init__(self, w: Workload, prec: str | None = None, device: int = 0, stream=None,
-                 want_cov: bool = False, ess_min: float = 0.0):
+                 want_cov: bool = False, ess_min: float = 0.0, proposal_params=None, hidden: int = 256,
+                 cover_min: float = 0.99, collect_pairs: bool = False):
         self.w = w
         self.dev = torch.device("cuda", device)
         self.prec = prec or w.precision
@@ -30,7 +33,8 @@ class GpuFilter:
         n, r = w.n, w.r
         f64 = dict(dtype=torch.float64, device=self.dev)
         self.codes = torch.empty(n * r, dtype=torch.int32, device=self.dev)
-        self.x = torch.empty(n * r, **f64)
+        self.xbuf = [torch.empty(n * r, **f64), torch.empty(n * r, **f64)]
+        self.xi = 0
         self.lo = torch.empty(r, **f64)
         self.hi = torch.empty(r, **f64)
         self.lw = [torch.empty(n, **f64), torch.empty(n, **f64)]
@@ -50,8 +54,31 @@ class GpuFilter:
         self.ess_min = ess_min
         self.version = 0
         self.dys = None
+        # learned restart proposal (a network created on this context from trained parameters)
+        self.proposal = None
+        self.cover_min = cover_min
+        if proposal_params is not None:
+            self.proposal = yy.yy_proposal_create(self.ctx, r, hidden, 0, proposal_params)
+        self.used = torch.zeros(1, dtype=torch.int32, device=self.dev)
+        self.used_count = torch.zeros(1, dtype=torch.int64, device=self.dev)
+        self.restarts = 0
+        # training pairs: (estimate at a restart, sample mean / variance at the next restart)
+        self.collect = collect_pairs
+        npairs = max(w.K // max(w.restart_every, 1), 1)
+        self.pair_x = torch.zeros(npairs, r, **f64) if collect_pairs else None
+        self.pair_mu = torch.zeros(npairs, r, **f64) if collect_pairs else None
+        self.pair_var = torch.zeros(npairs, r, **f64) if collect_pairs else None
+        self.prev_xhat = torch.zeros(r, **f64) if collect_pairs else None
+        self.npairs = 0
+
+    @property
+    def x(self):
+        return self.xbuf[self.xi]
 
     def close(self):
+        if self.proposal is not None:
+            yy.yy_proposal_destroy(self.proposal)
+            self.proposal = None
         if self.ctx is not None:
             yy.yy_destroy(self.ctx)
             self.ctx = None
@@ -71,7 +98,7 @@ class GpuFilter:
             self.logZ_acc.zero_()
         yy.yy_nodes_sobol(self.ctx, w.r, w.n, 0, True, w.seed, None, None, self.codes, None)
         # initial density N(0, I) on [-box_half, box_half]^r: the restart map centred at 0
-        yy.yy_restart(self.ctx, w.n, w.r, self.codes, None, self.zero_r, None, 0, w.box_half, 0.0, w.seed,
+        yy.yy_restart(self.ctx, w.n, w.r, self.codes, None, None, self.zero_r, None, 0, w.box_half, 0.0, w.seed,
                       None, self.lo, self.hi, self.x, self.lw[self.cur])
         self.version += 1
         self._normalise(want_cov=False, acc=self.logZ_scratch)
@@ -101,7 +128,23 @@ class GpuFilter:
 
     def restart(self, k: int):
         w = self.w
-        yy.yy_restart(self.ctx, w.n, w.r, self.codes, self.wts, self.mean, self.ess, k, w.R, self.ess_min,
-                      w.seed, self.idx, self.lo, self.hi, self.x, self.lw[self.cur])
+        x_cur, x_new = self.xbuf[self.xi], self.xbuf[1 - self.xi]
+        yy.yy_restart(self.ctx, w.n, w.r, self.codes, x_cur, self.wts, self.mean, self.ess, k, w.R, self.ess_min,
+                      w.seed, self.idx, self.lo, self.hi, x_new, self.lw[self.cur], self.proposal, self.cover_min,
+                      self.used if self.proposal is not None else None)
+        if self.collect:
+            if self.restarts > 0 and self.npairs < self.pair_x.shape[0]:
+                j = self.npairs
+                yy.yy_sample_moments(self.ctx, w.n, w.r, x_cur, self.idx, self.pair_mu[j], self.pair_var[j])
+                with torch.cuda.stream(self.stream):
+                    self.pair_x[j].copy_(self.prev_xhat)
+                self.npairs += 1
+            with torch.cuda.stream(self.stream):
+                self.prev_xhat.copy_(self.mean)
+        if self.proposal is not None:
+            with torch.cuda.stream(self.stream):
+                self.used_count.add_(self.used)
+        self.restarts += 1
+        self.xi = 1 - self.xi
         self.version += 1
         self._normalise(want_cov=False, acc=self.logZ_scratch)

@@ -30,7 +30,9 @@ PREC_BY_NAME = {"auto": YY_PREC_AUTO, "fp32": YY_PREC_FP32, "fp32_mfma": YY_PREC
                 "bf16x3g": YY_PREC_BF16X3G}
 EXPORTED = ["yy_last_error", "yy_create", "yy_destroy", "yy_set_stream", "yy_get_status",
             "yy_kernel_coefficients", "yy_nodes_sobol", "yy_propagate", "yy_loglik_update",
-            "yy_normalise_moments", "yy_restart", "yy_timing_enable", "yy_timing_read"]
+            "yy_normalise_moments", "yy_restart", "yy_timing_enable", "yy_timing_read",
+            "yy_proposal_create", "yy_proposal_destroy", "yy_proposal_num_params", "yy_proposal_get_params",
+            "yy_proposal_set_params", "yy_proposal_forward", "yy_proposal_train_step", "yy_sample_moments"]
 
 
 class YYError(RuntimeError):
@@ -52,7 +54,8 @@ class yy_scales(ctypes.Structure):
 
 
 class yy_restart_params(ctypes.Structure):
-    _fields_ = [("R", ctypes.c_double), ("ess_min", ctypes.c_double), ("seed", ctypes.c_uint64)]
+    _fields_ = [("R", ctypes.c_double), ("ess_min", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("proposal", ctypes.c_void_p), ("cover_min", ctypes.c_double)]
 
 
 _P, _i32, _i64, _u64, _f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double
@@ -69,8 +72,16 @@ for _name, _args in {
                      _P, _P, _f64, _P, _P],
     "yy_loglik_update": [_P, ctypes.POINTER(yy_model), _i64, _P, _P, _f64, _P],
     "yy_normalise_moments": [_P, _i64, _i32, _P, _P, _P, _P, _P, _P, _P, _P],
-    "yy_restart": [_P, _i64, _i32, _P, _P, _P, _P, _i64, ctypes.POINTER(yy_restart_params), _P, _P,
-                   _P, _P, _P],
+    "yy_restart": [_P, _i64, _i32, _P, _P, _P, _P, _P, _i64, ctypes.POINTER(yy_restart_params), _P, _P,
+                   _P, _P, _P, _P],
+    "yy_proposal_create": [_P, _i32, _i32, _u64, _P, ctypes.POINTER(_P)],
+    "yy_proposal_destroy": [_P],
+    "yy_proposal_num_params": [_P, ctypes.POINTER(_i64)],
+    "yy_proposal_get_params": [_P, _P],
+    "yy_proposal_set_params": [_P, _P],
+    "yy_proposal_forward": [_P, _i32, _P, _P],
+    "yy_proposal_train_step": [_P, _i32, _P, _P, _P, _f64, _f64, _i32, _P, _P],
+    "yy_sample_moments": [_P, _i64, _i32, _P, _P, _P, _P],
     "yy_timing_enable": [_P, _i32],
     "yy_timing_read": [_P, ctypes.POINTER(_f64), ctypes.POINTER(_i64)],
 }.items():
@@ -195,14 +206,66 @@ def yy_normalise_moments(ctx, n, r, x, logw, w, logZ_step, logZ_acc, mean, cov, 
                                      _dptr(ess, torch.float64, 1, "ess")), "yy_normalise_moments")
 
 
-def yy_restart(ctx, n, r, codes, w, mean, ess, step, R, ess_min, seed, idx, box_lo, box_hi, x_new, logw_new):
-    params = yy_restart_params(float(R), float(ess_min), int(seed) & 0xFFFFFFFFFFFFFFFF)
+def yy_restart(ctx, n, r, codes, x_cur, w, mean, ess, step, R, ess_min, seed, idx, box_lo, box_hi, x_new,
+               logw_new, proposal=None, cover_min=0.99, used=None):
+    params = yy_restart_params(float(R), float(ess_min), int(seed) & 0xFFFFFFFFFFFFFFFF, proposal,
+                               float(cover_min))
     _check(_lib.yy_restart(ctx, int(n), int(r), _dptr(codes, torch.uint32, n * r, "codes"),
+                           _dptr(x_cur, torch.float64, n * r, "x_cur"),
                            _dptr(w, torch.float64, n, "w"), _dptr(mean, torch.float64, r, "mean"),
                            _dptr(ess, torch.float64, 1, "ess"), int(step), ctypes.byref(params),
                            _dptr(idx, torch.int64, n, "idx"), _dptr(box_lo, torch.float64, r, "box_lo"),
                            _dptr(box_hi, torch.float64, r, "box_hi"), _dptr(x_new, torch.float64, n * r, "x_new"),
-                           _dptr(logw_new, torch.float64, n, "logw_new")), "yy_restart")
+                           _dptr(logw_new, torch.float64, n, "logw_new"), _dptr(used, torch.int32, 1, "used")),
+           "yy_restart")
+
+
+def yy_proposal_create(ctx, r, hidden=256, seed=0, params=None):
+    out = ctypes.c_void_p()
+    _check(_lib.yy_proposal_create(ctx, int(r), int(hidden), int(seed) & 0xFFFFFFFFFFFFFFFF,
+                                   _dptr(params, torch.float32, None, "params"), ctypes.byref(out)),
+           "yy_proposal_create")
+    return out
+
+
+def yy_proposal_destroy(p):
+    _check(_lib.yy_proposal_destroy(p), "yy_proposal_destroy")
+
+
+def yy_proposal_num_params(p) -> int:
+    P = ctypes.c_int64(0)
+    _check(_lib.yy_proposal_num_params(p, ctypes.byref(P)), "yy_proposal_num_params")
+    return int(P.value)
+
+
+def yy_proposal_get_params(p, params):
+    _check(_lib.yy_proposal_get_params(p, _dptr(params, torch.float32, yy_proposal_num_params(p), "params")),
+           "yy_proposal_get_params")
+
+
+def yy_proposal_set_params(p, params):
+    _check(_lib.yy_proposal_set_params(p, _dptr(params, torch.float32, yy_proposal_num_params(p), "params")),
+           "yy_proposal_set_params")
+
+
+def yy_proposal_forward(p, B, xhat, out, r):
+    _check(_lib.yy_proposal_forward(p, int(B), _dptr(xhat, torch.float64, B * r, "xhat"),
+                                    _dptr(out, torch.float32, B * 2 * r, "out")), "yy_proposal_forward")
+
+
+def yy_proposal_train_step(p, B, xhat, mu, var, R, lr, update, loss=None, grad=None, r=None):
+    r = xhat.numel() // B if r is None else r
+    _check(_lib.yy_proposal_train_step(p, int(B), _dptr(xhat, torch.float64, B * r, "xhat"),
+                                       _dptr(mu, torch.float64, B * r, "mu"), _dptr(var, torch.float64, B * r, "var"),
+                                       float(R), float(lr), int(bool(update)),
+                                       _dptr(loss, torch.float64, 1, "loss"), _dptr(grad, torch.float32, None, "grad")),
+           "yy_proposal_train_step")
+
+
+def yy_sample_moments(ctx, n, r, x, idx, mean, var):
+    _check(_lib.yy_sample_moments(ctx, int(n), int(r), _dptr(x, torch.float64, n * r, "x"),
+                                  _dptr(idx, torch.int64, n, "idx"), _dptr(mean, torch.float64, r, "mean"),
+                                  _dptr(var, torch.float64, r, "var")), "yy_sample_moments")
 
 
 def yy_timing_enable(ctx, on: bool = True):

@@ -194,7 +194,7 @@ def test_resample_bit_exact(ctx, n):
     idx = torch.empty(n, dtype=torch.int64, device="cuda")
     codes = torch.zeros(n * r, dtype=torch.int32, device="cuda")
     tmp = {k: torch.empty(v, dtype=torch.float64, device="cuda") for k, v in dict(lo=r, hi=r, x=n * r, lw=n).items()}
-    yy.yy_restart(ctx, n, r, codes, dev(w), dev(np.zeros(r)), None, 12, 0.3, 0.0, 77, idx, tmp["lo"], tmp["hi"],
+    yy.yy_restart(ctx, n, r, codes, None, dev(w), dev(np.zeros(r)), None, 12, 0.3, 0.0, 77, idx, tmp["lo"], tmp["hi"],
                   tmp["x"], tmp["lw"])
     assert np.array_equal(host(idx), ref)
 
@@ -205,7 +205,7 @@ def test_restart_nodes_bit_exact(ctx, r, n):
     mean = np.random.default_rng(r).standard_normal(r)
     lo, hi, x, lw = oracle.restart_nodes(codes, mean, 0.3)
     t = {k: torch.empty(v, dtype=torch.float64, device="cuda") for k, v in dict(lo=r, hi=r, x=n * r, lw=n).items()}
-    yy.yy_restart(ctx, n, r, dev(codes.view(np.int32).ravel(), torch.int32), None, dev(mean), None, 1, 0.3, 0.0, 0,
+    yy.yy_restart(ctx, n, r, dev(codes.view(np.int32).ravel(), torch.int32), None, None, dev(mean), None, 1, 0.3, 0.0, 0,
                   None, t["lo"], t["hi"], t["x"], t["lw"])
     assert np.array_equal(host(t["lo"]), lo) and np.array_equal(host(t["hi"]), hi)
     assert np.array_equal(host(t["x"]).reshape(n, r), x)
