@@ -46,12 +46,12 @@ def alg_flops(w) -> float:
     return 2.0 * w.n * w.n * w.r * P
 
 
-def run_gpu(w, dys, prec, warmup, steps, timing=True):
+def run_gpu(w, dys, prec, warmup, steps, timing=True, proposal_params=None):
     import torch
     from paper_2509_16896_amd import yy
     from paper_2509_16896_amd.filter import GpuFilter
 
-    f = GpuFilter(w, prec=prec)
+    f = GpuFilter(w, prec=prec, proposal_params=proposal_params)
     f.set_observations(dys)
     f.init()
     k = 0
@@ -200,6 +200,10 @@ def main():
     ap.add_argument("--workload", default="cubic_r1000", choices=["cubic_r1000", "cubic_r100"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--proposal", default="learned", choices=["learned", "none"],
+                    help="restart box: the learned MLP proposal (trained before timing) or the plain box")
+    ap.add_argument("--train-runs", type=int, default=2, help="plain-restart runs that supply training pairs")
+    ap.add_argument("--train-steps", type=int, default=300)
     ap.add_argument("--traffic-probe", action="store_true",
                     help="one 1 GiB copy + one yy_propagate, for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE")
     args = ap.parse_args()
@@ -222,8 +226,22 @@ def main():
     w.K = max(w.K, total + 1)
     xs, dys = W.simulate(w)
     log(f"[bench] workload {w.name}: r={w.r} n={w.n} scales={w.scales} prec={args.prec} "
-        f"warmup={args.warmup} steps={args.steps}")
-    f, k_last, elapsed, ms, launches = run_gpu(w, dys, args.prec, args.warmup, args.steps)
+        f"warmup={args.warmup} steps={args.steps} proposal={args.proposal}")
+    prop_info, params = None, None
+    if args.proposal == "learned":
+        from paper_2509_16896_amd import proposal as PR
+
+        t0 = time.perf_counter()
+        X, MU, VAR = PR.collect_pairs(w, range(1000, 1000 + args.train_runs), prec=args.prec)
+        params, losses = PR.train(w, X, MU, VAR, hidden=256, steps=args.train_steps, lr=1e-3,
+                                  log_every=max(args.train_steps - 1, 1))
+        prop_info = {"train_runs": args.train_runs, "pairs": int(X.shape[0]), "train_steps": args.train_steps,
+                     "loss_first_last": [round(losses[0][1], 4), round(losses[-1][1], 4)],
+                     "setup_s": round(time.perf_counter() - t0, 2)}
+        log(f"[bench] proposal trained on {X.shape[0]} pairs in {prop_info['setup_s']} s, loss {losses}")
+    f, k_last, elapsed, ms, launches = run_gpu(w, dys, args.prec, args.warmup, args.steps, proposal_params=params)
+    if prop_info is not None:
+        prop_info["used_fraction"] = round(int(f.used_count.item()) / max(f.restarts - 0, 1), 3)
     steps_s = args.steps / elapsed
     avg_kernel_s = (ms / 1e3) / max(launches, 1)
     achieved = alg_flops(w) / avg_kernel_s / 1e12
@@ -281,6 +299,7 @@ def main():
         "plain_fp32": base,
         "vs_plain_fp32": None if base is None else round(steps_s / base["steps_per_s"], 3),
         "other_forms": forms or None,
+        "proposal": prop_info,
         "sampled_row_max_rel_err": parity,
         "cpu_baseline": cpu,
     }

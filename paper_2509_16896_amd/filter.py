@@ -22,7 +22,7 @@ from .workloads import Workload
 class GpuFilter:
     def __init__(self, w: Workload, prec: str | None = None, device: int = 0, stream=None,
                  want_cov: bool = False, ess_min: float = 0.0, proposal_params=None, hidden: int = 256,
-                 cover_min: float = 0.99, collect_pairs: bool = False):
+                 cover_min: float = 0.95, collect_pairs: bool = False):
         self.w = w
         self.dev = torch.device("cuda", device)
         self.prec = prec or w.precision

@@ -1,13 +1,16 @@
 """Training the learned restart proposal on the filter's own posterior samples.
 
 Pairs come from plain-restart runs of the filter (GpuFilter with
-collect_pairs=True): the estimate x_hat at one restart, and the sample mean
-and variance of the resampled nodes at the next restart.  Training runs on the
+collect_pairs=True) on observation paths disjoint from the evaluation paths:
+the estimate x_hat at one restart, and the sample mean and variance of the
+resampled nodes at the next restart.  Training runs on the
 GPU through yy_proposal_train_step (forward, Gaussian NLL, backward and Adam
 in libyy's kernels); the trained parameter vector is then given to the
 filters that use the proposal (each creates its own network on its context).
 """
 from __future__ import annotations
+
+import dataclasses
 
 import torch
 
@@ -16,13 +19,19 @@ from .filter import GpuFilter
 from .workloads import Workload, simulate
 
 
-def collect_pairs(w: Workload, seeds, prec: str | None = None, device: int = 0):
-    """Runs plain-restart filters on the observation paths of `seeds`; returns the stacked
-    training pairs (x_hat, mu, var) as device tensors [N x r] and the runs' mean RMSE."""
+COLLECT_R_FACTOR = 4.0   # collection runs use a plain box this many times wider than R
+
+
+def collect_pairs(w: Workload, seeds, prec: str | None = None, device: int = 0,
+                  r_factor: float = COLLECT_R_FACTOR):
+    """Runs plain-restart filters on the observation paths of `seeds`, with the plain box widened
+    to r_factor * R so that the next restart's samples are not cut off by the box they were
+    drawn in; returns the stacked training pairs (x_hat, mu, var) as device tensors [N x r]."""
+    wc = dataclasses.replace(w, R=w.R * r_factor)
     xs_all, mus, vars_ = [], [], []
     for sd in seeds:
-        xs, dys = simulate(w, seed=sd)
-        f = GpuFilter(w, prec=prec, device=device, collect_pairs=True)
+        xs, dys = simulate(wc, seed=sd)
+        f = GpuFilter(wc, prec=prec, device=device, collect_pairs=True)
         try:
             f.set_observations(dys)
             f.init()

@@ -207,7 +207,7 @@ def yy_normalise_moments(ctx, n, r, x, logw, w, logZ_step, logZ_acc, mean, cov, 
 
 
 def yy_restart(ctx, n, r, codes, x_cur, w, mean, ess, step, R, ess_min, seed, idx, box_lo, box_hi, x_new,
-               logw_new, proposal=None, cover_min=0.99, used=None):
+               logw_new, proposal=None, cover_min=0.95, used=None):
     params = yy_restart_params(float(R), float(ess_min), int(seed) & 0xFFFFFFFFFFFFFFFF, proposal,
                                float(cover_min))
     _check(_lib.yy_restart(ctx, int(n), int(r), _dptr(codes, torch.uint32, n * r, "codes"),
@@ -220,8 +220,15 @@ def yy_restart(ctx, n, r, codes, x_cur, w, mean, ess, step, R, ess_min, seed, id
            "yy_restart")
 
 
+def proposal_num_params(r: int, hidden: int) -> int:
+    """P = H r + H + H^2 + H + 2 r H + 2 r (the layout of include/yy.h)."""
+    return hidden * r + hidden + hidden * hidden + hidden + 2 * r * hidden + 2 * r
+
+
 def yy_proposal_create(ctx, r, hidden=256, seed=0, params=None):
     out = ctypes.c_void_p()
+    if params is not None and params.numel() != proposal_num_params(r, hidden):
+        raise ValueError(f"params has {params.numel()} elements, the network needs {proposal_num_params(r, hidden)}")
     _check(_lib.yy_proposal_create(ctx, int(r), int(hidden), int(seed) & 0xFFFFFFFFFFFFFFFF,
                                    _dptr(params, torch.float32, None, "params"), ctypes.byref(out)),
            "yy_proposal_create")
