@@ -256,6 +256,70 @@ yy_status yy_restart(yy_ctx ctx, int64_t n, int32_t r, const uint32_t* codes, co
                      double* x_new, double* logw_new, int32_t* used);
 
 /* ------------------------------------------------------------------------ */
+/* Autotuner of the matrix-core pairwise kernel (not in the paper).  For each
+ * shape (r[t], n[t]) it builds a synthetic node set (scrambled Sobol nodes in
+ * [-1, 1]^r, f = cos, h = x^3, q = rho2 = 0.09, dt = 0.01, uniform weights),
+ * times the pairwise kernel of yy_propagate with the given scales and form
+ * for 1, 2, 4, ... source splits (up to the number of 128-source tiles, at
+ * most 256), `reps` launches each after one warm-up, and records the fastest
+ * count in ctx's table; later yy_propagate calls whose padded shape, scale
+ * count and form match use it.  nsplit_out: host [count] or NULL.  Not while
+ * the stream is being captured. */
+yy_status yy_tune(yy_ctx ctx, int32_t count, const int32_t* r, const int64_t* n, const yy_scales* scales,
+                  int32_t prec, int32_t reps, int32_t* nsplit_out);
+
+/* ------------------------------------------------------------------------ */
+/* Batched filter (not in the paper): many independent filter runs stepped
+ * together.  Each step runs the per-run preparation, source weights and
+ * biases, then ONE matrix-core pairwise launch over the work items (run,
+ * target block, source split) of all runs in decreasing-cost order, then the
+ * per-run combination, log-likelihood update (Sec. 2.2.2), normalisation and,
+ * every restart_every steps, the plain restart (Sec. 6).  Each run owns its
+ * nodes and weights; the batch owns one context per run on ctx's stream. */
+typedef struct {
+  yy_model model;          /* f, h, noise of the run (A/H device pointers stay owned by the caller) */
+  int64_t n;               /* nodes, 1 .. 2^31 */
+  double dt;
+  double box_half;         /* initial box [-box_half, box_half]^r, density N(0, I) */
+  double R;                /* restart half-width */
+  int32_t restart_every;   /* 0: never */
+  int32_t K;               /* steps; observation increments dys: device [K*m] FP64 */
+  uint64_t seed;           /* Sobol scramble and resampling key */
+  const double* dys;
+} yy_batch_run;
+typedef struct yy_batch_s* yy_batch;
+
+/* Creates the batch and its initial state (step 0: nodes, N(0, I) prior,
+ * normalised).  prec: YY_PREC_BF16X3, BF16X3G, BF16X1 or FP32_MFMA (every run
+ * uses the matrix cores; r <= YY_MAX_R).  max_split: upper bound of the
+ * source splits per run (0: 16); yy_batch_tune can choose it. */
+yy_status yy_batch_create(yy_ctx ctx, int32_t nruns, const yy_batch_run* runs, const yy_scales* scales,
+                          int32_t prec, int32_t max_split, yy_batch* out);
+yy_status yy_batch_destroy(yy_batch b);
+/* Back to step 0 (same nodes and priors as after creation). */
+yy_status yy_batch_reset(yy_batch b);
+/* One step of every run whose step count is below its K. */
+yy_status yy_batch_step(yy_batch b);
+/* Steps every run up to step k_end (<= every K) through a HIP graph: the
+ * first call captures steps k0+1 .. k_end (k0 = the current step, which must
+ * be at least every run's restart_every so that all buffers exist) into one
+ * graph and instantiates it; every call launches it.  Later calls must start
+ * from the same step k0 with the same node versions (yy_batch_reset and k0
+ * eager steps); another (k0, k_end) recaptures.  ctx's stream must be a
+ * created stream (not the null stream). */
+yy_status yy_batch_run_graph(yy_batch b, int32_t k_end);
+/* Tries max_split = 1, 2, 4, ..., 64 on the batched pairwise launch of the
+ * current state (reps launches each after a warm-up; results discarded) and
+ * keeps the fastest; best_out: host scalar or NULL.  Drops a captured graph. */
+yy_status yy_batch_tune(yy_batch b, int32_t reps, int32_t* best_out);
+/* Results of run `run` so far: per-step posterior mean (device [K*r]), log
+ * normaliser logZ_k (device [K]) and ESS (device [K]); each nullable.  Copies
+ * on ctx's stream. */
+yy_status yy_batch_results(yy_batch b, int32_t run, double* mean_hist, double* logZ_hist, double* ess_hist);
+/* Steps taken so far (host scalar). */
+yy_status yy_batch_step_count(yy_batch b, int32_t* k);
+
+/* ------------------------------------------------------------------------ */
 /* Timing of the pairwise kernel (the dominant kernel of yy_propagate).  While
  * enabled, each yy_propagate records a pair of HIP events on the context's
  * stream around its pairwise kernel.  yy_timing_read synchronises the stream,

@@ -88,6 +88,13 @@ struct yy_ctx_s {
   yy::DevBuf red2;
   yy::DevBuf scan;                    // resampling prefix sums
   yy::DevBuf bsrc;                    // matrix-core source biases
+  // tuned source-split counts: (rp, n_pad, S, prec) -> nsplit
+  struct TuneEntry {
+    int32_t rp;
+    int64_t n_pad;
+    int32_t S, prec, nsplit;
+  };
+  std::vector<TuneEntry> tune;
   // pairwise-kernel timing
   bool timing = false;
   std::vector<hipEvent_t> ev_start, ev_stop;
@@ -146,6 +153,54 @@ struct MfmaExtra {
 };
 yy_status launch_src_bias(hipStream_t st, const PairArgs& a, const MfmaExtra& ex);
 yy_status launch_pair_mfma(hipStream_t st, const PairArgs& a, int prec, const MfmaExtra& ex);
+// Batched matrix-core kernel: `sets` is a device array of the per-set kernel
+// arguments (pair_mfma_args_bytes() each, filled by pair_mfma_fill_args);
+// items[b] = (set, target block, source split, cost).
+size_t pair_mfma_args_bytes();
+void pair_mfma_fill_args(const PairArgs& pa, int prec, const MfmaExtra& ex, void* out);
+yy_status launch_pair_mfma_batch(hipStream_t st, int S, int prec, const void* sets, const int4* items, int nitems);
+
+// (4) combination in FP64: merge the source splits, add the constants, signed
+// log-sum-exp over the scales and the identity term.
+struct CombineArgs {
+  int64_t n;
+  int32_t S, nsplit;
+  double kap[YY_MAX_SCALES];       // log|c_s| - log n - (r/2) log(2 pi q tau_s)
+  double sign[YY_MAX_SCALES + 1];  // sign(c_s), 0 for c_s = 0
+  double logc_id;                  // log|c_S|
+  const float2* part;
+  const double* scal;              // [0] = log vol(box)
+  const double* lref;              // max source log-weight
+  const double* logw_in;
+  const int* bnd;
+  double* logw_out;
+  uint32_t* flags;
+  unsigned long long* nclamped;
+};
+
+// One yy_propagate call split into its phases: begin = node preparation,
+// source weights, biases and the launch parameters; pair = the pairwise
+// kernel; end = the combination.  nsplit_override > 0 fixes the number of
+// source splits of the matrix-core kernel.
+struct PropPlan {
+  int64_t n = 0;
+  int32_t prec = 0;
+  bool mfma = false;
+  PairArgs a{};
+  MfmaExtra ex{};
+  CombineArgs cb{};
+  double taud[YY_MAX_SCALES] = {0, 0, 0, 0, 0, 0};
+  double kapd[YY_MAX_SCALES] = {0, 0, 0, 0, 0, 0};
+};
+yy_status propagate_begin(yy_ctx ctx, const yy_model* model, const yy_scales* scales, int32_t prec, int64_t n,
+                          const double* x, uint64_t node_version, const double* box_lo, const double* box_hi,
+                          double dt, const double* logw_in, double* logw_out, int nsplit_override,
+                          PropPlan& plan);
+yy_status propagate_pair(yy_ctx ctx, const PropPlan& plan);
+yy_status propagate_end(yy_ctx ctx, const PropPlan& plan);
+
+// Tuned source-split counts of the matrix-core kernel (yy_tune), 0 if none.
+int tune_lookup(yy_ctx ctx, int32_t rp, int64_t n_pad, int32_t S, int32_t prec);
 int64_t pair_mfma_npad(int64_t n);
 int pair_mfma_rp(int32_t r);
 

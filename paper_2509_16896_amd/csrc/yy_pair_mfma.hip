@@ -19,6 +19,8 @@
 //   BF16X3:  hi/lo split of both operands, hi*hi + lo*hi + hi*lo, for G and H,
 //   BF16X3G: the split for G only; H, which enters scaled by tau_s, is hi*hi,
 //   BF16X1:  hi*hi only (a screen),  FP32: v_mfma_f32_32x32x2_f32 on FP32 data.
+#include <cstring>
+
 #include "yy_common.h"
 #include "yy_internal.h"
 
@@ -487,32 +489,40 @@ __device__ inline void mfma_stage_f32(const unsigned char* base, f32x16_t (&G)[k
 // next LA = NS / SPB - 1 groups are in flight, so the pipeline keeps running
 // across tile boundaries while a tile's epilogue folds its products into the
 // running (max, sum).
+template <int VAR>
+struct StageShape {
+  static constexpr int ESZ = VAR == 0 ? 4 : 2;                       // element bytes
+  static constexpr int NTP = VAR >= 2 ? 2 : 1;                       // target planes
+  static constexpr int NSP = VAR == 3 ? 4 : VAR == 2 ? 3 : 2;        // source planes
+  static constexpr int ROWB = kKC * ESZ;
+  static constexpr int STAGE = (NTP * kMI + NSP * kMJ) * ROWB;       // bytes per LDS stage
+};
+
+// One block's work: targets [256 tb, 256 tb + 256) against the sources of split
+// `split`, partial (max, sum) to a.part.  smem, sbuf and rare are the block's
+// LDS ring, bias double buffer and rare-path parameters.
 template <int S, int VAR, int NS, int SPB>
-__global__ void __launch_bounds__(kNT, 1) k_pair_mfma(MArgs a) {
+__device__ __forceinline__ void pair_block(const MArgs& a, int tb, int split, unsigned char* smem,
+                                           float (*sbuf)[4 * kMJ], Rare& rare) {
   static_assert(NS % SPB == 0 && NS / SPB >= 2, "the ring holds at least two groups of stages");
   constexpr int LA = NS / SPB - 1;
-  constexpr int ESZ = VAR == 0 ? 4 : 2;
-  constexpr int NTP = VAR >= 2 ? 2 : 1;
-  constexpr int NSP = VAR == 3 ? 4 : VAR == 2 ? 3 : 2;
-  constexpr int ROWB = kKC * ESZ;
-  constexpr int STAGE = (NTP * kMI + NSP * kMJ) * ROWB;
+  constexpr int ESZ = StageShape<VAR>::ESZ;
+  constexpr int NTP = StageShape<VAR>::NTP;
+  constexpr int NSP = StageShape<VAR>::NSP;
+  constexpr int STAGE = StageShape<VAR>::STAGE;
   constexpr int L = STAGE / 1024 / kWaves;     // copies per wave per stage
   static_assert(LA == 1 || L * kWaves * 1024 == STAGE, "deep lookahead needs equal copies per wave");
-  __shared__ __attribute__((aligned(1024))) unsigned char smem[NS * STAGE];
-  __shared__ __attribute__((aligned(1024))) float sbuf[2][4 * kMJ];
-
-  __shared__ Rare rare;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wi = wave >> 1, wj = wave & 1, col = lane & 31, g = lane >> 5;
   if (tid == 0) fill_rare(a, rare);
-  int tb, split;
-  block_map(a, tb, split);
   const int64_t i0 = (int64_t)tb * kMI;
   const int64_t jb0 = (int64_t)split * a.j_per_split;
   const int64_t jb1 = jb0 + a.j_per_split < a.n ? jb0 + a.j_per_split : a.n;
-  const int ntiles = (int)((jb1 - jb0 + kMJ - 1) / kMJ);
-  const int nchunks = a.rp / kKC;
+  // block-uniform counts (the LDS addresses of the copies derive from them and
+  // must live in scalar registers even when `a` was read from global memory)
+  const int ntiles = __builtin_amdgcn_readfirstlane((int)((jb1 - jb0 + kMJ - 1) / kMJ));
+  const int nchunks = __builtin_amdgcn_readfirstlane(a.rp / kKC);
   const int Q = ntiles * nchunks;
   const uint64_t plane = (uint64_t)nchunks * a.n_pad * kKC * ESZ;   // bytes per global plane
   const unsigned char* gb = VAR == 0 ? reinterpret_cast<const unsigned char*>(a.f32t)
@@ -570,6 +580,29 @@ __global__ void __launch_bounds__(kNT, 1) k_pair_mfma(MArgs a) {
     __builtin_amdgcn_sched_barrier(0);
   }
   merge_and_store<S>(a, M, Ssum, i0, split, reinterpret_cast<float2*>(smem));
+}
+
+template <int S, int VAR, int NS, int SPB>
+__global__ void __launch_bounds__(kNT, 1) k_pair_mfma(MArgs a) {
+  __shared__ __attribute__((aligned(1024))) unsigned char smem[NS * StageShape<VAR>::STAGE];
+  __shared__ __attribute__((aligned(1024))) float sbuf[2][4 * kMJ];
+  __shared__ Rare rare;
+  int tb, split;
+  block_map(a, tb, split);
+  pair_block<S, VAR, NS, SPB>(a, tb, split, smem, sbuf, rare);
+}
+
+// Many node sets in one launch: block b takes work item items[b] = (set,
+// target block, source split); the items come in decreasing cost order.
+template <int S, int VAR, int NS, int SPB>
+__global__ void __launch_bounds__(kNT, 1) k_pair_mfma_batch(const MArgs* __restrict__ sets,
+                                                            const int4* __restrict__ items) {
+  __shared__ __attribute__((aligned(1024))) unsigned char smem[NS * StageShape<VAR>::STAGE];
+  __shared__ __attribute__((aligned(1024))) float sbuf[2][4 * kMJ];
+  __shared__ Rare rare;
+  const int4 it = items[blockIdx.x];
+  pair_block<S, VAR, NS, SPB>(sets[__builtin_amdgcn_readfirstlane(it.x)], __builtin_amdgcn_readfirstlane(it.y),
+                              __builtin_amdgcn_readfirstlane(it.z), smem, sbuf, rare);
 }
 
 // ---------------------------------------------------------------------------
@@ -638,6 +671,16 @@ yy_status launch_src_bias(hipStream_t st, const PairArgs& pa, const MfmaExtra& e
 }
 
 template <int S>
+static yy_status launch_batch_s(hipStream_t st, const MArgs* sets, const int4* items, int nitems, int prec) {
+  if (prec == YY_PREC_BF16X3) k_pair_mfma_batch<S, 3, 4, 2><<<nitems, kNT, 0, st>>>(sets, items);
+  else if (prec == YY_PREC_BF16X3G) k_pair_mfma_batch<S, 2, 4, 2><<<nitems, kNT, 0, st>>>(sets, items);
+  else if (prec == YY_PREC_BF16X1) k_pair_mfma_batch<S, 1, 8, 4><<<nitems, kNT, 0, st>>>(sets, items);
+  else k_pair_mfma_batch<S, 0, 4, 2><<<nitems, kNT, 0, st>>>(sets, items);
+  YY_LAUNCH_CHECK("k_pair_mfma_batch");
+  return YY_OK;
+}
+
+template <int S>
 static yy_status launch_s(hipStream_t st, const MArgs& m, int prec, int nblocks) {
   if (prec == YY_PREC_BF16X3) k_pair_mfma<S, 3, 4, 2><<<nblocks, kNT, 0, st>>>(m);
   else if (prec == YY_PREC_BF16X3G) k_pair_mfma<S, 2, 4, 2><<<nblocks, kNT, 0, st>>>(m);
@@ -655,6 +698,25 @@ yy_status launch_pair_mfma(hipStream_t st, const PairArgs& pa, int prec, const M
     case 2: return launch_s<2>(st, m, prec, nblocks);
     case 3: return launch_s<3>(st, m, prec, nblocks);
     case 4: return launch_s<4>(st, m, prec, nblocks);
+  }
+  return fail(YY_ERR_UNSUPPORTED, "the matrix-core path supports up to 4 scales");
+}
+
+size_t pair_mfma_args_bytes() { return sizeof(MArgs); }
+
+void pair_mfma_fill_args(const PairArgs& pa, int prec, const MfmaExtra& ex, void* out) {
+  const MArgs m = make_args(pa, prec, ex);
+  std::memcpy(out, &m, sizeof(MArgs));
+}
+
+yy_status launch_pair_mfma_batch(hipStream_t st, int S, int prec, const void* sets, const int4* items, int nitems) {
+  if (nitems <= 0) return YY_OK;
+  const MArgs* m = static_cast<const MArgs*>(sets);
+  switch (S) {
+    case 1: return launch_batch_s<1>(st, m, items, nitems, prec);
+    case 2: return launch_batch_s<2>(st, m, items, nitems, prec);
+    case 3: return launch_batch_s<3>(st, m, items, nitems, prec);
+    case 4: return launch_batch_s<4>(st, m, items, nitems, prec);
   }
   return fail(YY_ERR_UNSUPPORTED, "the matrix-core path supports up to 4 scales");
 }

@@ -337,21 +337,6 @@ static yy_status launch_pair_valu_d(hipStream_t st, const PairArgs& a, const dou
 // ---------------------------------------------------------------------------
 // (4) combination in FP64: merge the source splits, add the constants, signed
 // log-sum-exp over the scales and the identity term.
-struct CombineArgs {
-  int64_t n;
-  int32_t S, nsplit;
-  double kap[YY_MAX_SCALES];       // log|c_s| - log n - (r/2) log(2 pi q tau_s)
-  double sign[YY_MAX_SCALES + 1];  // sign(c_s), 0 for c_s = 0
-  double logc_id;                  // log|c_S|
-  const float2* part;
-  const double* scal;              // [0] = log vol(box)
-  const double* lref;              // max source log-weight
-  const double* logw_in;
-  const int* bnd;
-  double* logw_out;
-  uint32_t* flags;
-  unsigned long long* nclamped;
-};
 
 __global__ void __launch_bounds__(kBlock) k_combine(CombineArgs a) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -468,11 +453,14 @@ yy_status validate_model(const yy_model* m) { return check_model(m); }
 
 using namespace yy;
 
-extern "C" yy_status yy_propagate(yy_ctx ctx, const yy_model* model, const yy_scales* scales,
-                                  int32_t prec, int64_t n, const double* x, uint64_t node_version,
-                                  const double* box_lo, const double* box_hi, double dt,
-                                  const double* logw_in, double* logw_out) {
-  if (!ctx) return fail(YY_ERR_ARG, "yy_propagate: ctx is NULL");
+namespace yy {
+
+// Steps (1), (2) and the launch parameters of (3) and (4) for one call; the
+// batched step (yy_batch.hip) runs (3) for many plans in one launch.
+yy_status propagate_begin(yy_ctx ctx, const yy_model* model, const yy_scales* scales, int32_t prec, int64_t n,
+                          const double* x, uint64_t node_version, const double* box_lo, const double* box_hi,
+                          double dt, const double* logw_in, double* logw_out, int nsplit_override,
+                          PropPlan& plan) {
   yy_status st = check_model(model);
   if (st != YY_OK) return st;
   if (!scales || scales->S < 1 || scales->S > YY_MAX_SCALES || !scales->s)
@@ -480,6 +468,7 @@ extern "C" yy_status yy_propagate(yy_ctx ctx, const yy_model* model, const yy_sc
   if (n < 0) return fail(YY_ERR_ARG, "yy_propagate: n < 0");
   if (n > ((int64_t)1 << 31)) return fail(YY_ERR_UNSUPPORTED, "yy_propagate: n above 2^31");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(YY_ERR_ARG, "yy_propagate: dt must be positive");
+  plan.n = n;
   if (n == 0) return YY_OK;
   if (!x || !box_lo || !box_hi || !logw_in || !logw_out)
     return fail(YY_ERR_ARG, "yy_propagate: NULL array");
@@ -497,6 +486,9 @@ extern "C" yy_status yy_propagate(yy_ctx ctx, const yy_model* model, const yy_sc
   const int32_t r = model->r;
   if (prec == YY_PREC_AUTO) prec = r < 32 ? YY_PREC_FP32 : YY_PREC_BF16X3;
   const bool mfma = prec != YY_PREC_FP32;
+  if (mfma && S > 4) return fail(YY_ERR_UNSUPPORTED, "the matrix-core path supports up to 4 scales");
+  plan.prec = prec;
+  plan.mfma = mfma;
   YY_HIP(hipSetDevice(ctx->device));
   st = prepare_nodes(ctx, model, n, x, node_version, box_lo, box_hi,
                      prec == YY_PREC_BF16X3 || prec == YY_PREC_BF16X3G || prec == YY_PREC_BF16X1,
@@ -517,7 +509,8 @@ extern "C" yy_status yy_propagate(yy_ctx ctx, const yy_model* model, const yy_sc
   YY_LAUNCH_CHECK("k_lw_convert");
 
   // (3) pairwise partials
-  PairArgs a{};
+  PairArgs& a = plan.a;
+  a = PairArgs{};
   a.n = n;
   a.r = r;
   a.rp = P.rp;
@@ -528,6 +521,8 @@ extern "C" yy_status yy_propagate(yy_ctx ctx, const yy_model* model, const yy_sc
     kapd[s] = kLog2e / (2.0 * model->q * taud[s]);
     a.tau[s] = (float)taud[s];
     a.kap2[s] = (float)kapd[s];
+    plan.taud[s] = taud[s];
+    plan.kapd[s] = kapd[s];
   }
   a.xc = P.xc32.as<float>();
   a.f = P.f32.as<float>();
@@ -539,14 +534,23 @@ extern "C" yy_status yy_propagate(yy_ctx ctx, const yy_model* model, const yy_sc
   // enough blocks to cover the chip: split the source range when targets are few
   const int64_t ttiles = (n + kVI - 1) / kVI;
   int nsplit = 1;
-  MfmaExtra ex{};
+  MfmaExtra& ex = plan.ex;
+  ex = MfmaExtra{};
   if (mfma) {
     // the matrix-core kernel: 256-target blocks, 128-source tiles.  16 source
     // splits let one XCD (32 CUs, one block each) work on 2 target blocks at a
-    // time; small problems split further until 256 blocks cover the chip.
+    // time; small problems split further until 256 blocks cover the chip.  A
+    // tuned split count (yy_tune) or the caller's override replaces the rule.
     const int64_t n_pad = P.n_pad, tbs = n_pad / 256, jtl = (n + 127) / 128;
-    nsplit = 16;
-    while (tbs * nsplit < 256 && nsplit < 256) nsplit *= 2;
+    const int tuned = tune_lookup(ctx, P.rp, n_pad, S, prec);
+    if (nsplit_override > 0) {
+      nsplit = nsplit_override;
+    } else if (tuned > 0) {
+      nsplit = tuned;
+    } else {
+      nsplit = 16;
+      while (tbs * nsplit < 256 && nsplit < 256) nsplit *= 2;
+    }
     if (nsplit > jtl) nsplit = (int)jtl;
     ex.n_pad = n_pad;
     ex.f32t = P.have_f32t ? P.f32t.as<float>() : nullptr;
@@ -565,17 +569,10 @@ extern "C" yy_status yy_propagate(yy_ctx ctx, const yy_model* model, const yy_sc
   if ((st = ctx->part.ensure((size_t)nsplit * S * n * sizeof(float2))) != YY_OK) return st;
   a.part = ctx->part.as<float2>();
   if (mfma && (st = launch_src_bias(ctx->stream, a, ex)) != YY_OK) return st;
-  if ((st = timing_begin(ctx)) != YY_OK) return st;
-  if (mfma) {
-    st = launch_pair_mfma(ctx->stream, a, prec, ex);
-  } else {
-    st = launch_pair_valu_d(ctx->stream, a, taud, kapd);
-  }
-  if (st != YY_OK) return st;
-  if ((st = timing_end(ctx)) != YY_OK) return st;
 
-  // (4) combination
-  CombineArgs cb{};
+  // (4) combination parameters
+  CombineArgs& cb = plan.cb;
+  cb = CombineArgs{};
   cb.n = n;
   cb.S = S;
   cb.nsplit = a.nsplit;
@@ -594,7 +591,40 @@ extern "C" yy_status yy_propagate(yy_ctx ctx, const yy_model* model, const yy_sc
   cb.logw_out = logw_out;
   cb.flags = ctx->d_flags;
   cb.nclamped = ctx->d_nclamped;
-  k_combine<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, ctx->stream>>>(cb);
+  return YY_OK;
+}
+
+yy_status propagate_pair(yy_ctx ctx, const PropPlan& plan) {
+  if (plan.n == 0) return YY_OK;
+  yy_status st;
+  if ((st = timing_begin(ctx)) != YY_OK) return st;
+  if (plan.mfma) {
+    st = launch_pair_mfma(ctx->stream, plan.a, plan.prec, plan.ex);
+  } else {
+    st = launch_pair_valu_d(ctx->stream, plan.a, plan.taud, plan.kapd);
+  }
+  if (st != YY_OK) return st;
+  return timing_end(ctx);
+}
+
+yy_status propagate_end(yy_ctx ctx, const PropPlan& plan) {
+  if (plan.n == 0) return YY_OK;
+  k_combine<<<(unsigned)((plan.n + kBlock - 1) / kBlock), kBlock, 0, ctx->stream>>>(plan.cb);
   YY_LAUNCH_CHECK("k_combine");
   return YY_OK;
+}
+
+}  // namespace yy
+
+extern "C" yy_status yy_propagate(yy_ctx ctx, const yy_model* model, const yy_scales* scales,
+                                  int32_t prec, int64_t n, const double* x, uint64_t node_version,
+                                  const double* box_lo, const double* box_hi, double dt,
+                                  const double* logw_in, double* logw_out) {
+  if (!ctx) return fail(YY_ERR_ARG, "yy_propagate: ctx is NULL");
+  PropPlan plan;
+  yy_status st = propagate_begin(ctx, model, scales, prec, n, x, node_version, box_lo, box_hi, dt, logw_in,
+                                 logw_out, 0, plan);
+  if (st != YY_OK) return st;
+  if ((st = propagate_pair(ctx, plan)) != YY_OK) return st;
+  return propagate_end(ctx, plan);
 }

@@ -32,7 +32,9 @@ EXPORTED = ["yy_last_error", "yy_create", "yy_destroy", "yy_set_stream", "yy_get
             "yy_kernel_coefficients", "yy_nodes_sobol", "yy_propagate", "yy_loglik_update",
             "yy_normalise_moments", "yy_restart", "yy_timing_enable", "yy_timing_read",
             "yy_proposal_create", "yy_proposal_destroy", "yy_proposal_num_params", "yy_proposal_get_params",
-            "yy_proposal_set_params", "yy_proposal_forward", "yy_proposal_train_step", "yy_sample_moments"]
+            "yy_proposal_set_params", "yy_proposal_forward", "yy_proposal_train_step", "yy_sample_moments",
+            "yy_tune", "yy_batch_create", "yy_batch_destroy", "yy_batch_reset", "yy_batch_step",
+            "yy_batch_run_graph", "yy_batch_tune", "yy_batch_results", "yy_batch_step_count"]
 
 
 class YYError(RuntimeError):
@@ -56,6 +58,12 @@ class yy_scales(ctypes.Structure):
 class yy_restart_params(ctypes.Structure):
     _fields_ = [("R", ctypes.c_double), ("ess_min", ctypes.c_double), ("seed", ctypes.c_uint64),
                 ("proposal", ctypes.c_void_p), ("cover_min", ctypes.c_double)]
+
+
+class yy_batch_run(ctypes.Structure):
+    _fields_ = [("model", yy_model), ("n", ctypes.c_int64), ("dt", ctypes.c_double), ("box_half", ctypes.c_double),
+                ("R", ctypes.c_double), ("restart_every", ctypes.c_int32), ("K", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("dys", ctypes.c_void_p)]
 
 
 _P, _i32, _i64, _u64, _f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double
@@ -82,6 +90,17 @@ for _name, _args in {
     "yy_proposal_forward": [_P, _i32, _P, _P],
     "yy_proposal_train_step": [_P, _i32, _P, _P, _P, _f64, _f64, _i32, _P, _P],
     "yy_sample_moments": [_P, _i64, _i32, _P, _P, _P, _P],
+    "yy_tune": [_P, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i64), ctypes.POINTER(yy_scales), _i32, _i32,
+                ctypes.POINTER(_i32)],
+    "yy_batch_create": [_P, _i32, ctypes.POINTER(yy_batch_run), ctypes.POINTER(yy_scales), _i32, _i32,
+                        ctypes.POINTER(_P)],
+    "yy_batch_destroy": [_P],
+    "yy_batch_reset": [_P],
+    "yy_batch_step": [_P],
+    "yy_batch_run_graph": [_P, _i32],
+    "yy_batch_tune": [_P, _i32, ctypes.POINTER(_i32)],
+    "yy_batch_results": [_P, _i32, _P, _P, _P],
+    "yy_batch_step_count": [_P, ctypes.POINTER(_i32)],
     "yy_timing_enable": [_P, _i32],
     "yy_timing_read": [_P, ctypes.POINTER(_f64), ctypes.POINTER(_i64)],
 }.items():
@@ -285,3 +304,61 @@ def yy_timing_read(ctx):
     cnt = ctypes.c_int64(0)
     _check(_lib.yy_timing_read(ctx, ctypes.byref(ms), ctypes.byref(cnt)), "yy_timing_read")
     return float(ms.value), int(cnt.value)
+
+
+def yy_tune(ctx, shapes, scales: Scales, prec, reps=3):
+    """Tunes the matrix-core kernel's source splits for each (r, n); returns the chosen counts."""
+    prec = PREC_BY_NAME[prec] if isinstance(prec, str) else int(prec)
+    cnt = len(shapes)
+    ra = (_i32 * cnt)(*[int(r) for r, _ in shapes])
+    na = (_i64 * cnt)(*[int(n) for _, n in shapes])
+    out = (_i32 * cnt)()
+    _check(_lib.yy_tune(ctx, cnt, ra, na, ctypes.byref(scales.c), prec, int(reps), out), "yy_tune")
+    return list(out)
+
+
+def yy_batch_create(ctx, runs, scales: Scales, prec, max_split=0):
+    """runs: list of (Model, n, dt, box_half, R, restart_every, K, seed, dys device tensor [K*m])."""
+    prec = PREC_BY_NAME[prec] if isinstance(prec, str) else int(prec)
+    arr = (yy_batch_run * len(runs))()
+    for t, (model, n, dt, box_half, R, every, K, seed, dys) in enumerate(runs):
+        arr[t] = yy_batch_run(model.c, int(n), float(dt), float(box_half), float(R), int(every), int(K),
+                              int(seed) & 0xFFFFFFFFFFFFFFFF, _dptr(dys, torch.float64, K * model.m, "dys"))
+    out = ctypes.c_void_p()
+    _check(_lib.yy_batch_create(ctx, len(runs), arr, ctypes.byref(scales.c), prec, int(max_split),
+                                ctypes.byref(out)), "yy_batch_create")
+    return out
+
+
+def yy_batch_destroy(b):
+    _check(_lib.yy_batch_destroy(b), "yy_batch_destroy")
+
+
+def yy_batch_reset(b):
+    _check(_lib.yy_batch_reset(b), "yy_batch_reset")
+
+
+def yy_batch_step(b):
+    _check(_lib.yy_batch_step(b), "yy_batch_step")
+
+
+def yy_batch_run_graph(b, k_end):
+    _check(_lib.yy_batch_run_graph(b, int(k_end)), "yy_batch_run_graph")
+
+
+def yy_batch_tune(b, reps=3) -> int:
+    best = _i32(0)
+    _check(_lib.yy_batch_tune(b, int(reps), ctypes.byref(best)), "yy_batch_tune")
+    return int(best.value)
+
+
+def yy_batch_results(b, run, mean_hist=None, logZ_hist=None, ess_hist=None):
+    _check(_lib.yy_batch_results(b, int(run), _dptr(mean_hist, torch.float64, None, "mean_hist"),
+                                 _dptr(logZ_hist, torch.float64, None, "logZ_hist"),
+                                 _dptr(ess_hist, torch.float64, None, "ess_hist")), "yy_batch_results")
+
+
+def yy_batch_step_count(b) -> int:
+    k = _i32(0)
+    _check(_lib.yy_batch_step_count(b, ctypes.byref(k)), "yy_batch_step_count")
+    return int(k.value)

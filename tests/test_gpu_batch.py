@@ -1,0 +1,141 @@
+"""The batched filter (one pairwise launch for all runs per step), its HIP graph
+replay and the autotuners, against single-run filters through the same C ABI."""
+import dataclasses
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import host
+
+pytestmark = pytest.mark.gpu
+
+yy = pytest.importorskip("paper_2509_16896_amd.yy")
+from paper_2509_16896_amd import workloads as W  # noqa: E402
+from paper_2509_16896_amd.batch import Batch  # noqa: E402
+from paper_2509_16896_amd.filter import GpuFilter  # noqa: E402
+
+# uneven runs: r across the matrix-core K steps, n powers of two (a ragged tile
+# count for the smallest), restart every 2 steps
+SHAPES = [(10, 2048), (33, 1024), (64, 4096), (100, 2048), (150, 1024), (200, 8192)]
+
+
+def _workloads(K=8, shapes=SHAPES):
+    out = []
+    for b, (r, n) in enumerate(shapes):
+        out.append(W.Workload(f"batch_r{r}_n{n}", r=r, n=n, dt=0.01, K=K, drift=W.F_COS, obs=W.H_CUBE, q=0.09,
+                              rho2=0.09, scales=(1.0, 2.0, 4.0), box_half=0.3 + 0.1 * b, restart_every=2, R=0.3,
+                              seed=b + 1))
+    return out
+
+
+def _single(w, dys, prec):
+    f = GpuFilter(w, prec=prec)
+    try:
+        f.set_observations(dys)
+        f.init()
+        for k in range(1, w.K + 1):
+            f.step(k)
+        return host(f.hist), host(f.logZ_hist), host(f.ess_hist)
+    finally:
+        f.close()
+
+
+@pytest.mark.parametrize("prec", ["bf16x3g", "fp32_mfma"])
+def test_batch_matches_single_runs_exactly(prec):
+    ws = _workloads()
+    dys = [W.simulate(w)[1] for w in ws]
+    bt = Batch(ws, dys, prec=prec, max_split=16)
+    try:
+        for _ in range(ws[0].K):
+            bt.step()
+        assert bt.k == ws[0].K
+        for q, w in enumerate(ws):
+            mean, lz, ess = (host(t) for t in bt.results(q))
+            ref = _single(w, dys[q], prec)
+            assert np.array_equal(mean, ref[0]), w.name
+            assert np.array_equal(lz, ref[1]), w.name
+            assert np.array_equal(ess, ref[2]), w.name
+            assert np.all(np.isfinite(mean))
+    finally:
+        bt.close()
+
+
+def test_graph_replay_equals_eager_steps():
+    ws = _workloads(K=10)
+    dys = [W.simulate(w)[1] for w in ws]
+    a = Batch(ws, dys, prec="bf16x3g")
+    g = Batch(ws, dys, prec="bf16x3g")
+    try:
+        for _ in range(10):
+            a.step()
+        ref = [[host(t) for t in a.results(q)] for q in range(len(ws))]
+        for rep in range(2):   # the second launch reuses the captured graph
+            g.reset()
+            g.step()
+            g.step()
+            g.run_graph(10)
+            assert g.k == 10
+            torch.cuda.synchronize()
+            for q in range(len(ws)):
+                got = [host(t) for t in g.results(q)]
+                for x, y in zip(got, ref[q]):
+                    assert np.array_equal(x, y), (rep, q)
+        # eager work between replays, then a third replay
+        g.reset()
+        g.step()
+        g.step()
+        _ = torch.ones(1000, device="cuda").sum().item()
+        g.run_graph(10)
+        for q in range(len(ws)):
+            assert np.array_equal(host(g.results(q)[0]), ref[q][0])
+    finally:
+        a.close()
+        g.close()
+
+
+def test_graph_needs_eager_steps_first():
+    ws = _workloads(K=6)
+    dys = [W.simulate(w)[1] for w in ws]
+    b = Batch(ws, dys)
+    try:
+        with pytest.raises(yy.YYError):
+            b.run_graph(6)
+    finally:
+        b.close()
+
+
+def test_batch_tuner_keeps_results():
+    ws = _workloads(K=6)
+    dys = [W.simulate(w)[1] for w in ws]
+    b = Batch(ws, dys, prec="bf16x3g")
+    try:
+        b.step()
+        best = b.tune(reps=2)
+        assert best in (1, 2, 4, 8, 16, 32, 64)
+        for _ in range(5):
+            b.step()
+        for q, w in enumerate(ws):
+            mean = host(b.results(q)[0])
+            ref = _single(w, dys[q], "bf16x3g")[0]
+            # another split count changes only the summation order of the partial sums
+            assert np.allclose(mean, ref, rtol=1e-9, atol=1e-9), w.name
+    finally:
+        b.close()
+
+
+def test_single_run_tuner_table():
+    w = dataclasses.replace(_workloads()[2], K=3)
+    xs, dys = W.simulate(w)
+    ref = _single(w, dys, "bf16x3g")
+    f = GpuFilter(w, prec="bf16x3g")
+    try:
+        best = yy.yy_tune(f.ctx, [(w.r, w.n), (128, 16384)], f.scales, "bf16x3g", reps=2)
+        assert all(v in (1, 2, 4, 8, 16, 32, 64, 128, 256) for v in best)
+        f.set_observations(dys)
+        f.init()
+        for k in range(1, w.K + 1):
+            f.step(k)
+        assert np.allclose(host(f.hist), ref[0], rtol=1e-9, atol=1e-9)
+    finally:
+        f.close()
