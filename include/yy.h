@@ -270,12 +270,15 @@ yy_status yy_tune(yy_ctx ctx, int32_t count, const int32_t* r, const int64_t* n,
 
 /* ------------------------------------------------------------------------ */
 /* Batched filter (not in the paper): many independent filter runs stepped
- * together.  Each step runs the per-run preparation, source weights and
- * biases, then ONE matrix-core pairwise launch over the work items (run,
- * target block, source split) of all runs in decreasing-cost order, then the
- * per-run combination, log-likelihood update (Sec. 2.2.2), normalisation and,
- * every restart_every steps, the plain restart (Sec. 6).  Each run owns its
- * nodes and weights; the batch owns one context per run on ctx's stream. */
+ * together.  Every kernel of a step is one launch over all runs (each run's
+ * block range runs the single-run kernel on the run's arguments, so every run
+ * computes exactly what the single-run calls compute); the pairwise kernel
+ * takes the work items (run, target block, source split) of all runs in
+ * decreasing-cost order.  A step is the prediction (Sec. 4, push form), the
+ * log-likelihood update (Sec. 2.2.2), the normalisation and, every
+ * restart_every steps (not after the last), the plain restart (Sec. 6); step
+ * counters and restart flags live on the device.  The batch owns one context
+ * per run on ctx's stream. */
 typedef struct {
   yy_model model;          /* f, h, noise of the run (A/H device pointers stay owned by the caller) */
   int64_t n;               /* nodes, 1 .. 2^31 */
@@ -283,30 +286,27 @@ typedef struct {
   double box_half;         /* initial box [-box_half, box_half]^r, density N(0, I) */
   double R;                /* restart half-width */
   int32_t restart_every;   /* 0: never */
-  int32_t K;               /* steps; observation increments dys: device [K*m] FP64 */
+  int32_t K;               /* steps, the same for all runs of a batch */
   uint64_t seed;           /* Sobol scramble and resampling key */
-  const double* dys;
+  const double* dys;       /* observation increments: device [K*m] FP64 */
 } yy_batch_run;
 typedef struct yy_batch_s* yy_batch;
 
 /* Creates the batch and its initial state (step 0: nodes, N(0, I) prior,
  * normalised).  prec: YY_PREC_BF16X3, BF16X3G, BF16X1 or FP32_MFMA (every run
- * uses the matrix cores; r <= YY_MAX_R).  max_split: upper bound of the
- * source splits per run (0: 16); yy_batch_tune can choose it. */
+ * uses the matrix cores).  max_split: upper bound of the source splits per
+ * run (0: 16); yy_batch_tune can choose it. */
 yy_status yy_batch_create(yy_ctx ctx, int32_t nruns, const yy_batch_run* runs, const yy_scales* scales,
                           int32_t prec, int32_t max_split, yy_batch* out);
 yy_status yy_batch_destroy(yy_batch b);
 /* Back to step 0 (same nodes and priors as after creation). */
 yy_status yy_batch_reset(yy_batch b);
-/* One step of every run whose step count is below its K. */
+/* One step of every run (error once K steps are taken). */
 yy_status yy_batch_step(yy_batch b);
-/* Steps every run up to step k_end (<= every K) through a HIP graph: the
- * first call captures steps k0+1 .. k_end (k0 = the current step, which must
- * be at least every run's restart_every so that all buffers exist) into one
- * graph and instantiates it; every call launches it.  Later calls must start
- * from the same step k0 with the same node versions (yy_batch_reset and k0
- * eager steps); another (k0, k_end) recaptures.  ctx's stream must be a
- * created stream (not the null stream). */
+/* Steps every run up to step k_end (<= K) through a HIP graph of two
+ * consecutive steps, captured on first use (per parity of the next step) and
+ * launched (k_end - k)/2 times; an odd remainder runs eagerly.  ctx's stream
+ * must be a created stream (not the null stream) and timing must be off. */
 yy_status yy_batch_run_graph(yy_batch b, int32_t k_end);
 /* Tries max_split = 1, 2, 4, ..., 64 on the batched pairwise launch of the
  * current state (reps launches each after a warm-up; results discarded) and

@@ -2,13 +2,14 @@
 // loop replayed through a HIP graph, and the autotuner of the pairwise
 // kernel's source splits.
 //
-// A batch step runs, per run, the preparation, source weights and biases of
-// yy_propagate, then ONE matrix-core pairwise launch over the work items
-// (run, target block, source split) of every run, sorted by decreasing cost,
-// then per run the combination, the log-likelihood update, the normalisation
-// and, every restart_every steps, the plain restart.  Each run has its own
-// context (scratch, prepared nodes) on the batch's stream, so the per-run
-// arithmetic is exactly that of the single-run calls.
+// Every kernel of a batch step is ONE launch over all runs: the block range of
+// a launch is cut into one sub-range per run (the single-run call's grid), and
+// each block runs the single-run kernel's body on its run's arguments, so the
+// per-run arithmetic is exactly that of the single-run calls.  The pairwise
+// kernel takes work items (run, target block, source split) in decreasing
+// cost order.  Step counters and restart flags live on the device: restart
+// kernels return at once in runs that do not restart at this step, so two
+// consecutive steps form a graph that is captured once and replayed.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -48,41 +49,100 @@ struct BRun {
   yy_batch_run d{};
   DevBuf codes, x, lo, hi, lw[2], w, mean, ess, logZ_step, logZ_acc, logZ_scratch, hist, logZ_hist, ess_hist, idx,
       zero_r;
-  int cur = 0;
-  uint64_t version = 0;
-  int32_t k = 0;
+  int32_t k = 0;   // host mirror of the device step counter
   PropPlan plan;
 };
 
-// Host-side state that the step code advances (restored around graph launches).
-struct BRunState {
-  int cur;
-  uint64_t version;
-  int32_t k;
-  Prepared prep;
+// One batched launch: an argument set per run and the running block counts.
+template <class T>
+struct BLaunch {
+  DevBuf args, pre;
+  int nsets = 0, total = 0;
 };
+
+// Per-run control words on the device: step counter k and restart flag.
+struct BCtl {
+  int32_t k;
+  int32_t restart;
+  int32_t every;
+  int32_t K;
+};
+
+__global__ void __launch_bounds__(kBlock) k_batch_advance(int nr, BCtl* __restrict__ c) {
+  const int q = blockIdx.x * kBlock + threadIdx.x;
+  if (q >= nr) return;
+  const int32_t k = c[q].k + 1;
+  c[q].k = k;
+  c[q].restart = c[q].every > 0 && k % c[q].every == 0 && k < c[q].K;
+}
+
+struct record_args {
+  int32_t r;
+  const BCtl* ctl;
+  const double* mean;
+  const double* logZ_step;
+  const double* ess;
+  double* hist;
+  double* logZ_hist;
+  double* ess_hist;
+};
+
+// hist[k - 1] = mean, logZ_hist[k - 1] = logZ_k, ess_hist[k - 1] = ESS.
+__global__ void __launch_bounds__(kBlock) k_batch_record(const record_args* __restrict__ A,
+                                                         const int* __restrict__ pre, int nr) {
+  const int q = batch_find(pre, nr, blockIdx.x);
+  const record_args& a = A[q];
+  const int32_t k = a.ctl->k;
+  const int d = (blockIdx.x - pre[q]) * kBlock + threadIdx.x;
+  if (d < a.r) a.hist[(size_t)(k - 1) * a.r + d] = a.mean[d];
+  if (d == 0) {
+    a.logZ_hist[k - 1] = *a.logZ_step;
+    a.ess_hist[k - 1] = *a.ess;
+  }
+}
+
+static int nblk(int64_t count) { return (int)((count + kBlock - 1) / kBlock); }
 
 }  // namespace yy
 
 struct yy_batch_s {
   yy_ctx ctx = nullptr;
-  int32_t S = 0, prec = 0, max_split = 16;
+  int32_t S = 0, prec = 0, max_split = 16, K = 0;
   double s[YY_MAX_SCALES] = {0, 0, 0, 0, 0, 0};
   double c[YY_MAX_SCALES + 1] = {0, 0, 0, 0, 0, 0, 0};
   bool have_c = false;
   std::vector<yy::BRun> runs;
-  // the batched launch: per-run kernel arguments and work items
-  yy::DevBuf d_sets, d_items;
-  std::vector<unsigned char> h_sets;
-  std::vector<int> set_run;        // run of each set in the current launch
+  yy::DevBuf ctl;                  // BCtl [nruns]
   unsigned char* pinned = nullptr; // staging for uploads
   size_t pinned_bytes = 0;
+  bool built = false;
+  // the pairwise launch
+  yy::DevBuf d_sets, d_items;
   int nitems = 0;
-  // graph of steps k0+1 .. k1
+  yy::BLaunch<int> src_bias;       // argument sets = d_sets
+  // parity-dependent launches (index k % 2 of the step)
+  yy::BLaunch<yy::lw_max_args> lw_max[2];
+  yy::BLaunch<yy::lw_convert_args> lw_convert[2];
+  yy::BLaunch<yy::combine_args> combine[2];
+  yy::BLaunch<yy::loglik_args> loglik[2];
+  yy::BLaunch<yy::norm_max_args> nmax[2][2];        // [after restart][parity]
+  yy::BLaunch<yy::norm_sumexp_args> nsum[2][2];
+  yy::BLaunch<yy::norm_logz_args> nlogz[2][2];
+  yy::BLaunch<yy::norm_weights_args> nwts[2][2];
+  yy::BLaunch<yy::norm_final_args> nfin[2][2];
+  yy::BLaunch<yy::restart_nodes_args> nodes[2];
+  yy::BLaunch<yy::record_args> record;
+  yy::BLaunch<yy::rs_local_args> rs_local;
+  yy::BLaunch<yy::rs_offsets_args> rs_offsets;
+  yy::BLaunch<yy::rs_add_args> rs_add;
+  yy::BLaunch<yy::rs_search_args> rs_search;
+  yy::BLaunch<yy::box_plain_args> box;
+  yy::BLaunch<yy::prepare_args> prep;
+  yy::BLaunch<yy::prepare_scalars_args> prep_scal;
+  // graph of two consecutive steps, starting with parity g_parity
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  int32_t g_k0 = -1, g_k1 = -1;
-  std::vector<yy::BRunState> g_pre, g_post;
+  int g_parity = -1;
 };
 
 namespace yy {
@@ -105,6 +165,35 @@ static yy_status staging(yy_batch b, size_t bytes) {
   return YY_OK;
 }
 
+// Synchronous upload through pinned staging (set-up time only).
+static yy_status upload(yy_batch b, DevBuf& dst, const void* src, size_t bytes) {
+  yy_status st = dst.ensure(bytes);
+  if (st != YY_OK) return st;
+  if ((st = staging(b, bytes)) != YY_OK) return st;
+  YY_HIP(hipStreamSynchronize(b->ctx->stream));
+  std::memcpy(b->pinned, src, bytes);
+  YY_HIP(hipMemcpyAsync(dst.ptr, b->pinned, bytes, hipMemcpyHostToDevice, b->ctx->stream));
+  YY_HIP(hipStreamSynchronize(b->ctx->stream));
+  return YY_OK;
+}
+
+template <class T>
+static yy_status build_launch(yy_batch b, BLaunch<T>& L, const std::vector<T>& A, const std::vector<int>& blocks) {
+  std::vector<int> pre(blocks.size() + 1, 0);
+  for (size_t q = 0; q < blocks.size(); ++q) pre[q + 1] = pre[q] + blocks[q];
+  yy_status st;
+  if (!A.empty() && (st = upload(b, L.args, A.data(), A.size() * sizeof(T))) != YY_OK) return st;
+  if ((st = upload(b, L.pre, pre.data(), pre.size() * sizeof(int))) != YY_OK) return st;
+  L.nsets = (int)blocks.size();
+  L.total = pre.back();
+  return YY_OK;
+}
+
+template <class T>
+static yy_status run_launch(yy_batch b, const BLaunch<T>& L) {
+  return launch_batched(b->ctx->stream, L.args.template as<T>(), L.pre.template as<int>(), L.nsets, L.total);
+}
+
 // Step 0 of one run: codes, nodes in the initial box with the N(0, I) prior, normalised.
 static yy_status run_init(yy_batch b, BRun& R) {
   const yy_batch_run& d = R.d;
@@ -118,131 +207,256 @@ static yy_status run_init(yy_batch b, BRun& R) {
   yy_restart_params rp{};
   rp.R = d.box_half;
   rp.seed = d.seed;
-  R.cur = 0;
   if ((st = yy_restart(R.rc, d.n, r, R.codes.as<uint32_t>(), nullptr, nullptr, R.zero_r.as<double>(), nullptr, 0,
                        &rp, nullptr, R.lo.as<double>(), R.hi.as<double>(), R.x.as<double>(), R.lw[0].as<double>(),
                        nullptr)) != YY_OK)
     return st;
-  R.version += 1;
   R.k = 0;
   return yy_normalise_moments(R.rc, d.n, r, R.x.as<double>(), R.lw[0].as<double>(), R.w.as<double>(),
                               R.logZ_step.as<double>(), R.logZ_scratch.as<double>(), R.mean.as<double>(), nullptr,
                               R.ess.as<double>());
 }
 
-// Per-run kernel arguments and the cost-ordered work items of the active runs;
-// uploads them when they differ from the last upload.
-static yy_status prepare_launch(yy_batch b, const std::vector<int>& active) {
+static yy_status reset_ctl(yy_batch b) {
+  std::vector<BCtl> c(b->runs.size());
+  for (size_t q = 0; q < b->runs.size(); ++q) c[q] = {0, 0, b->runs[q].d.restart_every, b->runs[q].d.K};
+  return upload(b, b->ctl, c.data(), c.size() * sizeof(BCtl));
+}
+
+// All launch descriptions: per-run plans (same split rule and scratch as the
+// single-run calls), kernel argument sets for both step parities, work items.
+static yy_status build(yy_batch b) {
+  const yy_scales sc = batch_scales(b);
+  const int nr = (int)b->runs.size();
+  yy_status st;
+  for (BRun& R : b->runs) {
+    // a fixed node version: the prepared data is kept current by the batched
+    // preparation after every restart, never by this call
+    const int64_t jtl = (R.d.n + 127) / 128;
+    const int split = (int)std::max<int64_t>(1, std::min<int64_t>(b->max_split, jtl));
+    if ((st = propagate_begin(R.rc, &R.d.model, &sc, b->prec, R.d.n, R.x.as<double>(), 1, R.lo.as<double>(),
+                              R.hi.as<double>(), R.d.dt, R.lw[0].as<double>(), R.lw[1].as<double>(), split,
+                              R.plan)) != YY_OK)
+      return st;
+    // scratch of the steps that propagate_begin does not size
+    const int nbn = (int)std::min<int64_t>(nblk(R.d.n), 256);
+    if ((st = R.rc->red2.ensure(((size_t)nbn * (3 + (size_t)R.d.model.r) + 4) * sizeof(double))) != YY_OK) return st;
+    if ((st = R.rc->scan.ensure(((size_t)R.d.n + nblk(R.d.n) + 1) * sizeof(unsigned long long))) != YY_OK) return st;
+  }
+  // pairwise kernel argument sets and cost-ordered work items
   const size_t asz = pair_mfma_args_bytes();
-  std::vector<unsigned char> sets(active.size() * asz);
-  for (size_t t = 0; t < active.size(); ++t)
-    pair_mfma_fill_args(b->runs[active[t]].plan.a, b->prec, b->runs[active[t]].plan.ex, sets.data() + t * asz);
-  if (sets == b->h_sets && active == b->set_run) return YY_OK;
-  if (capturing(b->ctx->stream))
-    return fail(YY_ERR_UNSUPPORTED, "yy_batch: the batched launch changed while capturing a graph");
+  std::vector<unsigned char> sets(nr * asz);
   struct Item {
     int run, tb, split;
     int64_t cost;
   };
   std::vector<Item> items;
-  for (size_t t = 0; t < active.size(); ++t) {
-    const PropPlan& P = b->runs[active[t]].plan;
+  std::vector<int> bias_blocks(nr);
+  for (int q = 0; q < nr; ++q) {
+    const PropPlan& P = b->runs[q].plan;
+    pair_mfma_fill_args(P.a, b->prec, P.ex, sets.data() + q * asz);
+    bias_blocks[q] = nblk(P.ex.n_pad);
     const int64_t n = P.n, tbs = P.ex.n_pad / 256, jps = P.ex.j_per_split;
     for (int sp = 0; sp < P.a.nsplit; ++sp) {
       const int64_t j0 = (int64_t)sp * jps, j1 = std::min<int64_t>(j0 + jps, n);
       const int64_t cost = ((j1 - j0 + 127) / 128) * (int64_t)P.a.rp;
-      for (int64_t tb = 0; tb < tbs; ++tb) items.push_back({(int)t, (int)tb, sp, cost});
+      for (int64_t tb = 0; tb < tbs; ++tb) items.push_back({q, (int)tb, sp, cost});
     }
   }
   std::stable_sort(items.begin(), items.end(), [](const Item& x, const Item& y) { return x.cost > y.cost; });
   if (items.size() > (size_t)INT32_MAX) return fail(YY_ERR_UNSUPPORTED, "yy_batch: too many work items");
-  yy_status st;
-  if ((st = b->d_sets.ensure(sets.size())) != YY_OK) return st;
-  if ((st = b->d_items.ensure(items.size() * sizeof(int4))) != YY_OK) return st;
-  if ((st = staging(b, sets.size() + items.size() * sizeof(int4))) != YY_OK) return st;
-  // the previous upload may still be in flight from the staging buffer
-  YY_HIP(hipStreamSynchronize(b->ctx->stream));
-  std::memcpy(b->pinned, sets.data(), sets.size());
-  int4* it4 = reinterpret_cast<int4*>(b->pinned + sets.size());
-  for (size_t q = 0; q < items.size(); ++q)
-    it4[q] = make_int4(items[q].run, items[q].tb, items[q].split, (int)std::min<int64_t>(items[q].cost, INT32_MAX));
-  YY_HIP(hipMemcpyAsync(b->d_sets.ptr, b->pinned, sets.size(), hipMemcpyHostToDevice, b->ctx->stream));
-  YY_HIP(hipMemcpyAsync(b->d_items.ptr, it4, items.size() * sizeof(int4), hipMemcpyHostToDevice, b->ctx->stream));
-  YY_HIP(hipStreamSynchronize(b->ctx->stream));
-  b->h_sets.swap(sets);
-  b->set_run = active;
+  std::vector<int4> it4(items.size());
+  for (size_t t = 0; t < items.size(); ++t)
+    it4[t] = make_int4(items[t].run, items[t].tb, items[t].split, (int)std::min<int64_t>(items[t].cost, INT32_MAX));
+  if ((st = upload(b, b->d_sets, sets.data(), sets.size())) != YY_OK) return st;
+  if ((st = upload(b, b->d_items, it4.data(), it4.size() * sizeof(int4))) != YY_OK) return st;
   b->nitems = (int)items.size();
-  return YY_OK;
-}
+  if ((st = build_launch(b, b->src_bias, std::vector<int>{}, bias_blocks)) != YY_OK) return st;
 
-static int run_split(const yy_batch b, const BRun& R) {
-  const int64_t jtl = (R.d.n + 127) / 128;
-  return (int)std::max<int64_t>(1, std::min<int64_t>(b->max_split, jtl));
-}
-
-// Phase 1 for the active runs (those below their K).
-static yy_status begin_all(yy_batch b, std::vector<int>& active) {
-  const yy_scales sc = batch_scales(b);
-  active.clear();
-  for (int q = 0; q < (int)b->runs.size(); ++q) {
-    BRun& R = b->runs[q];
-    if (R.k >= R.d.K) continue;
-    yy_status st = propagate_begin(R.rc, &R.d.model, &sc, b->prec, R.d.n, R.x.as<double>(), R.version,
-                                   R.lo.as<double>(), R.hi.as<double>(), R.d.dt, R.lw[R.cur].as<double>(),
-                                   R.lw[1 - R.cur].as<double>(), run_split(b, R), R.plan);
-    if (st != YY_OK) return st;
-    active.push_back(q);
+  const BCtl* ctl = b->ctl.as<BCtl>();
+  for (int par = 0; par < 2; ++par) {
+    // step k with k % 2 == par reads lw[(k + 1) % 2] and writes lw[k % 2]
+    const int in = (par + 1) % 2, out = par;
+    std::vector<lw_max_args> A1;
+    std::vector<lw_convert_args> A2;
+    std::vector<combine_args> A3;
+    std::vector<loglik_args> A4;
+    std::vector<norm_max_args> N1[2];
+    std::vector<norm_sumexp_args> N2[2];
+    std::vector<norm_logz_args> N3[2];
+    std::vector<norm_weights_args> N4[2];
+    std::vector<norm_final_args> N5[2];
+    std::vector<restart_nodes_args> A5;
+    std::vector<int> b_parts, b_n, b_ll, b_nb, b_one, b_r, b_nodes;
+    for (int q = 0; q < nr; ++q) {
+      BRun& R = b->runs[q];
+      const yy_batch_run& d = R.d;
+      const int64_t n = d.n;
+      const int32_t r = d.model.r;
+      const int* rflag = &ctl[q].restart;
+      const Prepared& P = R.rc->prep;
+      const int nparts = (int)std::min<int64_t>(nblk(n), 1024);
+      double* d_part = R.rc->red.as<double>();
+      double* d_lref = d_part + nparts;
+      const double* lwi = R.lw[in].as<double>();
+      double* lwo = R.lw[out].as<double>();
+      A1.push_back({n, lwi, P.bnd.as<int>(), d_part, nullptr});
+      A2.push_back({n, nparts, d_part, lwi, P.bnd.as<int>(), R.rc->lw2.as<float>(), d_lref, nullptr});
+      CombineArgs cb = R.plan.cb;
+      cb.logw_in = lwi;
+      cb.logw_out = lwo;
+      A3.push_back({cb, nullptr});
+      A4.push_back({n, r, d.model.m, d.model.obs, d.model.H, d.model.h_shift, R.x.as<double>(), d.dys, d.dt,
+                    d.model.rho2, lwo, nullptr, &ctl[q].k});
+      b_parts.push_back(nparts);
+      b_n.push_back(nblk(n));
+      int64_t blocks = (n + 3) / 4;
+      if (blocks > 16384) blocks = 16384;
+      b_ll.push_back((int)blocks);
+      int64_t nb_nodes = blocks;
+      if (nb_nodes * kBlock < r) nb_nodes = nblk(r);
+      b_nodes.push_back((int)nb_nodes);
+      const int nb = (int)std::min<int64_t>(nblk(n), 256);
+      const int64_t rows = (n + nb - 1) / nb;
+      double* pmax = R.rc->red2.as<double>();
+      double* psum = pmax + nb;
+      double* pw2 = psum + nb;
+      double* pmean = pw2 + nb;
+      double* scv = pmean + (size_t)nb * r;
+      for (int post = 0; post < 2; ++post) {
+        const int* pr = post ? rflag : nullptr;
+        double* acc = post ? R.logZ_scratch.as<double>() : R.logZ_acc.as<double>();
+        N1[post].push_back({n, lwo, pmax, pr});
+        N2[post].push_back({n, nb, pmax, lwo, psum, pr});
+        N3[post].push_back({nb, pmax, psum, scv, R.logZ_step.as<double>(), acc, R.rc->d_flags, pr});
+        N4[post].push_back({n, r, rows, scv, R.x.as<double>(), lwo, R.w.as<double>(), pw2, pmean, pr});
+        N5[post].push_back({nb, r, scv, pw2, pmean, R.mean.as<double>(), R.ess.as<double>(), pr});
+      }
+      b_nb.push_back(nb);
+      b_one.push_back(1);
+      b_r.push_back(nblk(r));
+      A5.push_back({n, r, R.codes.as<uint32_t>(), R.mean.as<double>(), R.lo.as<double>(), R.hi.as<double>(), nullptr,
+                    R.x.as<double>(), lwo, rflag});
+    }
+    if ((st = build_launch(b, b->lw_max[par], A1, b_parts)) != YY_OK) return st;
+    if ((st = build_launch(b, b->lw_convert[par], A2, b_parts)) != YY_OK) return st;
+    if ((st = build_launch(b, b->combine[par], A3, b_n)) != YY_OK) return st;
+    if ((st = build_launch(b, b->loglik[par], A4, b_ll)) != YY_OK) return st;
+    for (int post = 0; post < 2; ++post) {
+      if ((st = build_launch(b, b->nmax[post][par], N1[post], b_nb)) != YY_OK) return st;
+      if ((st = build_launch(b, b->nsum[post][par], N2[post], b_nb)) != YY_OK) return st;
+      if ((st = build_launch(b, b->nlogz[post][par], N3[post], b_one)) != YY_OK) return st;
+      if ((st = build_launch(b, b->nwts[post][par], N4[post], b_nb)) != YY_OK) return st;
+      if ((st = build_launch(b, b->nfin[post][par], N5[post], b_r)) != YY_OK) return st;
+    }
+    if ((st = build_launch(b, b->nodes[par], A5, b_nodes)) != YY_OK) return st;
   }
-  return YY_OK;
-}
-
-static yy_status batch_step_impl(yy_batch b) {
-  std::vector<int> active;
-  yy_status st = begin_all(b, active);
-  if (st != YY_OK || active.empty()) return st;
-  if ((st = prepare_launch(b, active)) != YY_OK) return st;
-  if ((st = timing_begin(b->ctx)) != YY_OK) return st;
-  if ((st = launch_pair_mfma_batch(b->ctx->stream, b->S, b->prec, b->d_sets.ptr, b->d_items.as<int4>(), b->nitems)) !=
-      YY_OK)
-    return st;
-  if ((st = timing_end(b->ctx)) != YY_OK) return st;
-  hipStream_t strm = b->ctx->stream;
-  for (int q : active) {
+  // parity-independent launches
+  std::vector<record_args> Rc;
+  std::vector<rs_local_args> S1;
+  std::vector<rs_offsets_args> S2;
+  std::vector<rs_add_args> S3;
+  std::vector<rs_search_args> S4;
+  std::vector<box_plain_args> Bx;
+  std::vector<prepare_args> Pp;
+  std::vector<prepare_scalars_args> Ps;
+  std::vector<int> b_r, b_rs, b_one, b_prep;
+  for (int q = 0; q < nr; ++q) {
     BRun& R = b->runs[q];
     const yy_batch_run& d = R.d;
+    const int64_t n = d.n;
     const int32_t r = d.model.r;
-    if ((st = propagate_end(R.rc, R.plan)) != YY_OK) return st;
-    R.cur = 1 - R.cur;
-    const int32_t k = R.k + 1;
-    double* lw = R.lw[R.cur].as<double>();
-    if ((st = yy_loglik_update(R.rc, &d.model, d.n, R.x.as<double>(), d.dys + (size_t)(k - 1) * d.model.m, d.dt,
-                               lw)) != YY_OK)
-      return st;
-    if ((st = yy_normalise_moments(R.rc, d.n, r, R.x.as<double>(), lw, R.w.as<double>(), R.logZ_step.as<double>(),
-                                   R.logZ_acc.as<double>(), R.mean.as<double>(), nullptr, R.ess.as<double>())) != YY_OK)
-      return st;
-    YY_HIP(hipMemcpyAsync(R.hist.as<double>() + (size_t)(k - 1) * r, R.mean.ptr, (size_t)r * sizeof(double),
-                          hipMemcpyDeviceToDevice, strm));
-    YY_HIP(hipMemcpyAsync(R.logZ_hist.as<double>() + (k - 1), R.logZ_step.ptr, sizeof(double),
-                          hipMemcpyDeviceToDevice, strm));
-    YY_HIP(hipMemcpyAsync(R.ess_hist.as<double>() + (k - 1), R.ess.ptr, sizeof(double), hipMemcpyDeviceToDevice,
-                          strm));
-    R.k = k;
-    if (d.restart_every > 0 && k % d.restart_every == 0 && k < d.K) {
-      yy_restart_params rp{};
-      rp.R = d.R;
-      rp.seed = d.seed;
-      if ((st = yy_restart(R.rc, d.n, r, R.codes.as<uint32_t>(), nullptr, R.w.as<double>(), R.mean.as<double>(),
-                           R.ess.as<double>(), k, &rp, R.idx.as<int64_t>(), R.lo.as<double>(), R.hi.as<double>(),
-                           R.x.as<double>(), lw, nullptr)) != YY_OK)
-        return st;
-      R.version += 1;
-      if ((st = yy_normalise_moments(R.rc, d.n, r, R.x.as<double>(), lw, R.w.as<double>(), R.logZ_step.as<double>(),
-                                     R.logZ_scratch.as<double>(), R.mean.as<double>(), nullptr,
-                                     R.ess.as<double>())) != YY_OK)
-        return st;
+    const int* rflag = &ctl[q].restart;
+    Prepared& P = R.rc->prep;
+    Rc.push_back({r, &ctl[q], R.mean.as<double>(), R.logZ_step.as<double>(), R.ess.as<double>(), R.hist.as<double>(),
+                  R.logZ_hist.as<double>(), R.ess_hist.as<double>()});
+    const int nbr = nblk(n);
+    unsigned long long* C = R.rc->scan.as<unsigned long long>();
+    unsigned long long* tot = C + n;
+    S1.push_back({n, R.w.as<double>(), C, tot, rflag});
+    S2.push_back({nbr, tot, rflag});
+    S3.push_back({n, tot, C, rflag});
+    uint64_t key;
+    {  // SplitMix64(seed, 2): the resampling stream of the run (as in yy_restart)
+      uint64_t z = d.seed + 3ULL * 0x9E3779B97F4A7C15ULL;
+      z ^= z >> 30;
+      z *= 0xBF58476D1CE4E5B9ULL;
+      z ^= z >> 27;
+      z *= 0x94D049BB133111EBULL;
+      key = z ^ (z >> 31);
     }
+    S4.push_back({n, nbr, tot, C, 0, R.idx.as<int64_t>(), R.rc->d_flags, rflag, &ctl[q].k, key});
+    Bx.push_back({r, d.R, R.mean.as<double>(), R.lo.as<double>(), R.hi.as<double>(), rflag});
+    const bool bf = P.have_bf16, f32t = P.have_f32t;
+    Pp.push_back({n, P.n_pad, r, P.rp, d.model.drift, d.model.A, R.x.as<double>(), R.lo.as<double>(),
+                  R.hi.as<double>(), P.xc32.as<float>(), P.f32.as<float>(), bf ? P.bf.as<uint16_t>() : nullptr,
+                  f32t ? P.f32t.as<float>() : nullptr, P.node.as<double>(), P.bnd.as<int>(), rflag});
+    Ps.push_back({n, r, R.lo.as<double>(), R.hi.as<double>(), P.node.as<double>(), P.scal.as<double>(), rflag});
+    b_r.push_back(nblk(r));
+    b_rs.push_back(nbr);
+    b_one.push_back(1);
+    int64_t blocks = (P.n_pad + 3) / 4;
+    if (blocks > 16384) blocks = 16384;
+    b_prep.push_back((int)blocks);
   }
+  if ((st = build_launch(b, b->record, Rc, b_r)) != YY_OK) return st;
+  if ((st = build_launch(b, b->rs_local, S1, b_rs)) != YY_OK) return st;
+  if ((st = build_launch(b, b->rs_offsets, S2, b_one)) != YY_OK) return st;
+  if ((st = build_launch(b, b->rs_add, S3, b_rs)) != YY_OK) return st;
+  if ((st = build_launch(b, b->rs_search, S4, b_rs)) != YY_OK) return st;
+  if ((st = build_launch(b, b->box, Bx, b_r)) != YY_OK) return st;
+  if ((st = build_launch(b, b->prep, Pp, b_prep)) != YY_OK) return st;
+  if ((st = build_launch(b, b->prep_scal, Ps, b_one)) != YY_OK) return st;
+  b->built = true;
+  return YY_OK;
+}
+
+yy_status launch_batched(hipStream_t st, const record_args* A, const int* pre, int nr, int total) {
+  if (total <= 0) return YY_OK;
+  k_batch_record<<<total, kBlock, 0, st>>>(A, pre, nr);
+  YY_LAUNCH_CHECK("k_batch_record");
+  return YY_OK;
+}
+
+// One step of every run: 2 + 5 + 1 + 6 + 5 launches, plus 9 restart launches
+// that return at once in runs not restarting this step.
+static yy_status batch_step_impl(yy_batch b) {
+  const int par = (b->runs[0].k + 1) % 2;
+  hipStream_t strm = b->ctx->stream;
+  const int nr = (int)b->runs.size();
+  yy_status st;
+  k_batch_advance<<<nblk(nr), kBlock, 0, strm>>>(nr, b->ctl.as<BCtl>());
+  YY_LAUNCH_CHECK("k_batch_advance");
+  if ((st = run_launch(b, b->lw_max[par])) != YY_OK) return st;
+  if ((st = run_launch(b, b->lw_convert[par])) != YY_OK) return st;
+  if ((st = launch_src_bias_batch(strm, b->d_sets.ptr, b->src_bias.pre.as<int>(), b->src_bias.nsets,
+                                  b->src_bias.total)) != YY_OK)
+    return st;
+  if ((st = timing_begin(b->ctx)) != YY_OK) return st;
+  if ((st = launch_pair_mfma_batch(strm, b->S, b->prec, b->d_sets.ptr, b->d_items.as<int4>(), b->nitems)) != YY_OK)
+    return st;
+  if ((st = timing_end(b->ctx)) != YY_OK) return st;
+  if ((st = run_launch(b, b->combine[par])) != YY_OK) return st;
+  if ((st = run_launch(b, b->loglik[par])) != YY_OK) return st;
+  for (int post = 0; post < 2; ++post) {
+    if (post == 1) {   // the restart of the runs whose flag is set, then their prior's normalisation
+      if ((st = run_launch(b, b->rs_local)) != YY_OK) return st;
+      if ((st = run_launch(b, b->rs_offsets)) != YY_OK) return st;
+      if ((st = run_launch(b, b->rs_add)) != YY_OK) return st;
+      if ((st = run_launch(b, b->rs_search)) != YY_OK) return st;
+      if ((st = run_launch(b, b->box)) != YY_OK) return st;
+      if ((st = run_launch(b, b->nodes[par])) != YY_OK) return st;
+      if ((st = run_launch(b, b->prep)) != YY_OK) return st;
+      if ((st = run_launch(b, b->prep_scal)) != YY_OK) return st;
+    }
+    if ((st = run_launch(b, b->nmax[post][par])) != YY_OK) return st;
+    if ((st = run_launch(b, b->nsum[post][par])) != YY_OK) return st;
+    if ((st = run_launch(b, b->nlogz[post][par])) != YY_OK) return st;
+    if ((st = run_launch(b, b->nwts[post][par])) != YY_OK) return st;
+    if ((st = run_launch(b, b->nfin[post][par])) != YY_OK) return st;
+    if (post == 0 && (st = run_launch(b, b->record)) != YY_OK) return st;
+  }
+  for (BRun& R : b->runs) R.k += 1;
   return YY_OK;
 }
 
@@ -251,34 +465,37 @@ static void drop_graph(yy_batch b) {
   if (b->graph) (void)hipGraphDestroy(b->graph);
   b->exec = nullptr;
   b->graph = nullptr;
-  b->g_k0 = b->g_k1 = -1;
-  b->g_pre.clear();
-  b->g_post.clear();
+  b->g_parity = -1;
 }
 
-static std::vector<BRunState> snapshot(const yy_batch b) {
-  std::vector<BRunState> v;
-  for (const BRun& R : b->runs) v.push_back({R.cur, R.version, R.k, R.rc->prep});
-  return v;
-}
-
-static void restore(yy_batch b, const std::vector<BRunState>& v) {
-  for (size_t q = 0; q < v.size(); ++q) {
-    BRun& R = b->runs[q];
-    R.cur = v[q].cur;
-    R.version = v[q].version;
-    R.k = v[q].k;
-    R.rc->prep = v[q].prep;
+static void release_launches(yy_batch b) {
+  auto rel = [](auto& L) {
+    L.args.release();
+    L.pre.release();
+  };
+  rel(b->src_bias);
+  for (int p = 0; p < 2; ++p) {
+    rel(b->lw_max[p]);
+    rel(b->lw_convert[p]);
+    rel(b->combine[p]);
+    rel(b->loglik[p]);
+    rel(b->nodes[p]);
+    for (int q = 0; q < 2; ++q) {
+      rel(b->nmax[q][p]);
+      rel(b->nsum[q][p]);
+      rel(b->nlogz[q][p]);
+      rel(b->nwts[q][p]);
+      rel(b->nfin[q][p]);
+    }
   }
-}
-
-static bool same_state(const yy_batch b, const std::vector<BRunState>& v) {
-  if (v.size() != b->runs.size()) return false;
-  for (size_t q = 0; q < v.size(); ++q) {
-    const BRun& R = b->runs[q];
-    if (R.cur != v[q].cur || R.version != v[q].version || R.k != v[q].k) return false;
-  }
-  return true;
+  rel(b->record);
+  rel(b->rs_local);
+  rel(b->rs_offsets);
+  rel(b->rs_add);
+  rel(b->rs_search);
+  rel(b->box);
+  rel(b->prep);
+  rel(b->prep_scal);
 }
 
 }  // namespace yy
@@ -381,12 +598,14 @@ extern "C" yy_status yy_batch_create(yy_ctx ctx, int32_t nruns, const yy_batch_r
     if (d.n < 1 || d.n > ((int64_t)1 << 31)) return fail(YY_ERR_ARG, "yy_batch_create: n out of range");
     if (!(d.dt > 0.0) || !(d.box_half > 0.0) || !(d.R > 0.0)) return fail(YY_ERR_ARG, "yy_batch_create: dt, box, R");
     if (d.K < 1 || d.restart_every < 0 || !d.dys) return fail(YY_ERR_ARG, "yy_batch_create: K, restart, dys");
+    if (d.K != runs[0].K) return fail(YY_ERR_ARG, "yy_batch_create: all runs of a batch take the same K");
   }
   YY_HIP(hipSetDevice(ctx->device));
   yy_batch b = new yy_batch_s();
   b->ctx = ctx;
   b->S = scales->S;
   b->prec = prec;
+  b->K = runs[0].K;
   b->max_split = max_split > 0 ? max_split : 16;
   for (int s = 0; s < b->S; ++s) b->s[s] = scales->s[s];
   if (scales->c) {
@@ -410,6 +629,8 @@ extern "C" yy_status yy_batch_create(yy_ctx ctx, int32_t nruns, const yy_batch_r
     for (size_t t = 0; t < sizeof(sizes) / sizeof(sizes[0]) && st == YY_OK; ++t) st = bufs[t]->ensure(sizes[t]);
     if (st == YY_OK) st = run_init(b, R);
   }
+  if (st == YY_OK) st = reset_ctl(b);
+  if (st == YY_OK) st = build(b);   // also prepares the initial nodes
   if (st == YY_OK && hipStreamSynchronize(ctx->stream) != hipSuccess) st = fail(YY_ERR_HIP, "yy_batch_create");
   if (st != YY_OK) {
     yy_batch_destroy(b);
@@ -426,6 +647,7 @@ extern "C" yy_status yy_batch_destroy(yy_batch b) {
     (void)hipStreamSynchronize(b->ctx->stream);
   }
   drop_graph(b);
+  release_launches(b);
   for (BRun& R : b->runs) {
     DevBuf* bufs[] = {&R.codes, &R.x, &R.lo, &R.hi, &R.lw[0], &R.lw[1], &R.w, &R.mean, &R.ess, &R.logZ_step,
                       &R.logZ_acc, &R.logZ_scratch, &R.hist, &R.logZ_hist, &R.ess_hist, &R.idx, &R.zero_r};
@@ -433,6 +655,7 @@ extern "C" yy_status yy_batch_destroy(yy_batch b) {
     if (R.rc) yy_destroy(R.rc);
     R.rc = nullptr;
   }
+  b->ctl.release();
   b->d_sets.release();
   b->d_items.release();
   if (b->pinned) (void)hipHostFree(b->pinned);
@@ -443,16 +666,19 @@ extern "C" yy_status yy_batch_destroy(yy_batch b) {
 extern "C" yy_status yy_batch_reset(yy_batch b) {
   if (!b) return fail(YY_ERR_ARG, "yy_batch_reset: NULL batch");
   YY_HIP(hipSetDevice(b->ctx->device));
-  for (BRun& R : b->runs) {
-    yy_status st = run_init(b, R);
-    if (st != YY_OK) return st;
-  }
-  return YY_OK;
+  yy_status st;
+  for (BRun& R : b->runs)
+    if ((st = run_init(b, R)) != YY_OK) return st;
+  if ((st = reset_ctl(b)) != YY_OK) return st;
+  // build() prepares the initial nodes again
+  for (BRun& R : b->runs) R.rc->prep.valid = false;
+  return build(b);
 }
 
 extern "C" yy_status yy_batch_step(yy_batch b) {
   if (!b) return fail(YY_ERR_ARG, "yy_batch_step: NULL batch");
   YY_HIP(hipSetDevice(b->ctx->device));
+  if (b->runs[0].k >= b->K) return fail(YY_ERR_ARG, "yy_batch_step: every run has taken its K steps");
   return batch_step_impl(b);
 }
 
@@ -460,54 +686,39 @@ extern "C" yy_status yy_batch_run_graph(yy_batch b, int32_t k_end) {
   if (!b) return fail(YY_ERR_ARG, "yy_batch_run_graph: NULL batch");
   YY_HIP(hipSetDevice(b->ctx->device));
   const int32_t k0 = b->runs[0].k;
-  for (const BRun& R : b->runs) {
-    if (R.k != k0) return fail(YY_ERR_ARG, "yy_batch_run_graph: runs are at different steps");
-    if (k_end > R.d.K) return fail(YY_ERR_ARG, "yy_batch_run_graph: k_end beyond a run's K");
-    if (R.d.restart_every > 0 && k0 < R.d.restart_every)
-      return fail(YY_ERR_ARG, "yy_batch_run_graph: take restart_every eager steps first");
-  }
-  if (k0 < 1) return fail(YY_ERR_ARG, "yy_batch_run_graph: take eager steps first");
+  if (k_end > b->K) return fail(YY_ERR_ARG, "yy_batch_run_graph: k_end beyond K");
   if (k_end <= k0) return YY_OK;
   if (b->ctx->timing) return fail(YY_ERR_UNSUPPORTED, "yy_batch_run_graph: disable timing first");
   hipStream_t st = b->ctx->stream;
   if (st == nullptr) return fail(YY_ERR_UNSUPPORTED, "yy_batch_run_graph: graph capture needs a created stream");
-  if (!(b->exec && b->g_k0 == k0 && b->g_k1 == k_end && same_state(b, b->g_pre))) {
-    drop_graph(b);
-    // any change of the batched launch must be uploaded before the capture
-    std::vector<int> active;
-    yy_status s0 = begin_all(b, active);
-    if (s0 == YY_OK) s0 = prepare_launch(b, active);
-    if (s0 != YY_OK) return s0;
-    // the graph prepares its first step's nodes itself, so that it does not
-    // depend on what was prepared before a launch
-    for (BRun& R : b->runs) R.rc->prep.valid = false;
-    b->g_pre = snapshot(b);
-    YY_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-    yy_status s = YY_OK;
-    for (int32_t k = k0 + 1; k <= k_end && s == YY_OK; ++k) s = batch_step_impl(b);
-    hipGraph_t g = nullptr;
-    const hipError_t ec = hipStreamEndCapture(st, &g);
-    if (s != YY_OK || ec != hipSuccess) {
-      if (g) (void)hipGraphDestroy(g);
-      restore(b, b->g_pre);
-      b->g_pre.clear();
-      return s != YY_OK ? s : hip_fail(ec, "hipStreamEndCapture");
-    }
-    b->graph = g;
-    const hipError_t ei = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
-    if (ei != hipSuccess) {
-      b->exec = nullptr;
-      restore(b, b->g_pre);
+  const int pairs = (k_end - k0) / 2;
+  if (pairs > 0) {
+    const int parity = (k0 + 1) % 2;
+    if (!b->exec || b->g_parity != parity) {
       drop_graph(b);
-      return hip_fail(ei, "hipGraphInstantiate");
+      YY_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+      yy_status s = batch_step_impl(b);
+      if (s == YY_OK) s = batch_step_impl(b);
+      for (BRun& R : b->runs) R.k -= 2;   // nothing ran yet
+      hipGraph_t g = nullptr;
+      const hipError_t ec = hipStreamEndCapture(st, &g);
+      if (s != YY_OK || ec != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return s != YY_OK ? s : hip_fail(ec, "hipStreamEndCapture");
+      }
+      b->graph = g;
+      const hipError_t ei = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+      if (ei != hipSuccess) {
+        b->exec = nullptr;
+        drop_graph(b);
+        return hip_fail(ei, "hipGraphInstantiate");
+      }
+      b->g_parity = parity;
     }
-    b->g_post = snapshot(b);
-    b->g_k0 = k0;
-    b->g_k1 = k_end;
-    restore(b, b->g_pre);
+    for (int p = 0; p < pairs; ++p) YY_HIP(hipGraphLaunch(b->exec, st));
+    for (BRun& R : b->runs) R.k += 2 * pairs;
   }
-  YY_HIP(hipGraphLaunch(b->exec, st));
-  restore(b, b->g_post);
+  if ((k_end - k0) % 2) return batch_step_impl(b);
   return YY_OK;
 }
 
@@ -527,9 +738,7 @@ extern "C" yy_status yy_batch_tune(yy_batch b, int32_t reps, int32_t* best_out) 
   yy_status s = YY_OK;
   for (int cand = 1; cand <= 64 && s == YY_OK; cand *= 2) {
     b->max_split = cand;
-    std::vector<int> active;
-    if ((s = begin_all(b, active)) != YY_OK || active.empty()) break;
-    if ((s = prepare_launch(b, active)) != YY_OK) break;
+    if ((s = build(b)) != YY_OK) break;
     if ((s = launch_pair_mfma_batch(st, b->S, b->prec, b->d_sets.ptr, b->d_items.as<int4>(), b->nitems)) != YY_OK)
       break;
     if (hipEventRecord(e0, st) != hipSuccess) { s = fail(YY_ERR_HIP, "yy_batch_tune: event"); break; }
@@ -548,10 +757,13 @@ extern "C" yy_status yy_batch_tune(yy_batch b, int32_t reps, int32_t* best_out) 
     }
   }
   b->max_split = s == YY_OK ? best : keep;
+  const yy_status s2 = build(b);
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  if (s == YY_OK && best_out) *best_out = best;
-  return s;
+  if (s != YY_OK) return s;
+  if (s2 != YY_OK) return s2;
+  if (best_out) *best_out = best;
+  return YY_OK;
 }
 
 extern "C" yy_status yy_batch_results(yy_batch b, int32_t run, double* mean_hist, double* logZ_hist,
@@ -569,8 +781,6 @@ extern "C" yy_status yy_batch_results(yy_batch b, int32_t run, double* mean_hist
 
 extern "C" yy_status yy_batch_step_count(yy_batch b, int32_t* k) {
   if (!b || !k) return fail(YY_ERR_ARG, "yy_batch_step_count: NULL argument");
-  int32_t m = 0;
-  for (const BRun& R : b->runs) m = std::max(m, R.k);
-  *k = m;
+  *k = b->runs[0].k;
   return YY_OK;
 }

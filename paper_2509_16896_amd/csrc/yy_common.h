@@ -24,6 +24,19 @@ __device__ inline int wave_or(int v) {
   return v;
 }
 
+// Argument set of block b in a batched launch: pre[0] = 0 < pre[1] < ... <
+// pre[nr] are the running block counts of the sets; returns q with
+// pre[q] <= b < pre[q + 1].
+__device__ inline int batch_find(const int* __restrict__ pre, int nr, int b) {
+  int lo = 0, hi = nr;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (pre[mid] <= b) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
 // Round-to-nearest-even float -> bfloat16 bits (finite inputs).
 __device__ inline uint16_t f32_to_bf16(float v) {
   uint32_t u = __float_as_uint(v);

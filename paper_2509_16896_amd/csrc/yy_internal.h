@@ -216,4 +216,212 @@ yy_status proposal_restart_finish(yy_ctx ctx, yy_proposal p, int64_t n, int32_t 
                                   const double* mean, double R, double ess_min, double* box_lo,
                                   double* box_hi, int* dec, int32_t* used);
 
+
+// ---------------------------------------------------------------------------
+// Argument sets of the batched kernels: the single-run kernels' parameters plus
+// a predicate; one set per run, in device memory, for one launch over all runs.
+struct loglik_args {
+  int64_t n;
+  int32_t r;
+  int32_t m;
+  int32_t obs;
+  const double* H;
+  double h_shift;
+  const double* x;
+  const double* dy;         // with kstep: the increments of all steps, dy_k = dy + (k - 1) m
+  double dt;
+  double rho2;
+  double* logw;
+  const int* pred;   // run only when *pred != 0 (NULL: always)
+  const int32_t* kstep;     // device step counter k, or NULL
+};
+
+struct norm_max_args {
+  int64_t n;
+  const double* lw;
+  double* pmax;
+  const int* pred;   // run only when *pred != 0 (NULL: always)
+};
+
+struct norm_sumexp_args {
+  int64_t n;
+  int nb;
+  const double* pmax;
+  const double* lw;
+  double* psum;
+  const int* pred;   // run only when *pred != 0 (NULL: always)
+};
+
+struct norm_logz_args {
+  int nb;
+  const double* pmax;
+  const double* psum;
+  double* sc;
+  double* logZ_step;
+  double* logZ_acc;
+  uint32_t* flags;
+  const int* pred;   // run only when *pred != 0 (NULL: always)
+};
+
+struct norm_weights_args {
+  int64_t n;
+  int32_t r;
+  int64_t rows;
+  const double* sc;
+  const double* x;
+  double* lw;
+  double* w;
+  double* pw2;
+  double* pmean;
+  const int* pred;   // run only when *pred != 0 (NULL: always)
+};
+
+struct norm_final_args {
+  int nb;
+  int32_t r;
+  const double* sc;
+  const double* pw2;
+  const double* pmean;
+  double* mean;
+  double* ess;
+  const int* pred;   // run only when *pred != 0 (NULL: always)
+};
+
+struct rs_local_args {
+  int64_t n;
+  const double* w;
+  unsigned long long* C;
+  unsigned long long* tot;
+  const int* pred;   // run only when *pred != 0 (NULL: always)
+};
+
+struct rs_offsets_args {
+  int nb;
+  unsigned long long* tot;
+  const int* pred;   // run only when *pred != 0 (NULL: always)
+};
+
+struct rs_add_args {
+  int64_t n;
+  const unsigned long long* tot;
+  unsigned long long* C;
+  const int* pred;   // run only when *pred != 0 (NULL: always)
+};
+
+struct rs_search_args {
+  int64_t n;
+  int nb;
+  const unsigned long long* tot;
+  const unsigned long long* C;
+  uint64_t U;
+  int64_t* idx;
+  uint32_t* flags;
+  const int* pred;   // run only when *pred != 0 (NULL: always)
+  const int32_t* kstep;     // with a device step counter: U = SplitMix64(key, k) >> 32
+  uint64_t key;
+};
+
+struct box_plain_args {
+  int32_t r;
+  double R;
+  const double* mean;
+  double* box_lo;
+  double* box_hi;
+  const int* pred;   // run only when *pred != 0 (NULL: always)
+};
+
+struct restart_nodes_args {
+  int64_t n;
+  int32_t r;
+  const uint32_t* codes;
+  const double* mean;
+  const double* box_lo;
+  const double* box_hi;
+  const int* only_if;
+  double* x_new;
+  double* logw_new;
+  const int* pred;   // run only when *pred != 0 (NULL: always)
+};
+
+struct ess_check_args {
+  const double* ess;
+  double ess_min;
+  uint32_t* flags;
+  const int* pred;   // run only when *pred != 0 (NULL: always)
+};
+
+struct prepare_args {
+  int64_t n;
+  int64_t n_pad;
+  int32_t r;
+  int32_t rp;
+  int32_t drift;
+  const double* A;
+  const double* x;
+  const double* lo;
+  const double* hi;
+  float* xc32;
+  float* f32;
+  uint16_t* bf;
+  float* f32t;
+  double* node;
+  int* bnd;
+  const int* pred;   // run only when *pred != 0 (NULL: always)
+};
+
+struct prepare_scalars_args {
+  int64_t n;
+  int32_t r;
+  const double* lo;
+  const double* hi;
+  const double* node;
+  double* scal;
+  const int* pred;   // run only when *pred != 0 (NULL: always)
+};
+
+struct lw_max_args {
+  int64_t n;
+  const double* lw;
+  const int* bnd;
+  double* part;
+  const int* pred;   // run only when *pred != 0 (NULL: always)
+};
+
+struct lw_convert_args {
+  int64_t n;
+  int nparts;
+  const double* part;
+  const double* lw;
+  const int* bnd;
+  float* lw2;
+  double* ref_out;
+  const int* pred;   // run only when *pred != 0 (NULL: always)
+};
+
+struct combine_args {
+  CombineArgs a;
+  const int* pred;   // run only when *pred != 0 (NULL: always)
+};
+
+yy_status launch_batched(hipStream_t st, const loglik_args* A, const int* pre, int nr, int total);
+yy_status launch_batched(hipStream_t st, const norm_max_args* A, const int* pre, int nr, int total);
+yy_status launch_batched(hipStream_t st, const norm_sumexp_args* A, const int* pre, int nr, int total);
+yy_status launch_batched(hipStream_t st, const norm_logz_args* A, const int* pre, int nr, int total);
+yy_status launch_batched(hipStream_t st, const norm_weights_args* A, const int* pre, int nr, int total);
+yy_status launch_batched(hipStream_t st, const norm_final_args* A, const int* pre, int nr, int total);
+yy_status launch_batched(hipStream_t st, const rs_local_args* A, const int* pre, int nr, int total);
+yy_status launch_batched(hipStream_t st, const rs_offsets_args* A, const int* pre, int nr, int total);
+yy_status launch_batched(hipStream_t st, const rs_add_args* A, const int* pre, int nr, int total);
+yy_status launch_batched(hipStream_t st, const rs_search_args* A, const int* pre, int nr, int total);
+yy_status launch_batched(hipStream_t st, const box_plain_args* A, const int* pre, int nr, int total);
+yy_status launch_batched(hipStream_t st, const restart_nodes_args* A, const int* pre, int nr, int total);
+yy_status launch_batched(hipStream_t st, const ess_check_args* A, const int* pre, int nr, int total);
+yy_status launch_batched(hipStream_t st, const prepare_args* A, const int* pre, int nr, int total);
+yy_status launch_batched(hipStream_t st, const prepare_scalars_args* A, const int* pre, int nr, int total);
+yy_status launch_batched(hipStream_t st, const lw_max_args* A, const int* pre, int nr, int total);
+yy_status launch_batched(hipStream_t st, const lw_convert_args* A, const int* pre, int nr, int total);
+yy_status launch_batched(hipStream_t st, const combine_args* A, const int* pre, int nr, int total);
+// Source biases of many sets (the batched pairwise kernel's argument array).
+yy_status launch_src_bias_batch(hipStream_t st, const void* sets, const int* pre, int nr, int total);
+
 }  // namespace yy

@@ -607,9 +607,9 @@ __global__ void __launch_bounds__(kNT, 1) k_pair_mfma_batch(const MArgs* __restr
 
 // ---------------------------------------------------------------------------
 // Source biases b_js = lw2_j - kap_s |m_j^s|^2 (FP64 -> FP32), -inf for invalid sources.
-__global__ void __launch_bounds__(kBlock) k_src_bias(int64_t n, int64_t n_pad, int32_t S,
-                                                     MArgs a, float* __restrict__ out) {
-  const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+__device__ __forceinline__ void k_src_bias_body(int64_t n, int64_t n_pad, int32_t S,
+                                                     MArgs a, float* __restrict__ out, int bx_, int gx_) {
+  const int64_t j = (int64_t)bx_ * kBlock + threadIdx.x;
   if (j >= n_pad) return;
   for (int s = 0; s < S; ++s) {
     float v = -INFINITY;
@@ -624,6 +624,19 @@ __global__ void __launch_bounds__(kBlock) k_src_bias(int64_t n, int64_t n_pad, i
     out[(size_t)s * n_pad + j] = v;
   }
 }
+
+__global__ void __launch_bounds__(kBlock) k_src_bias(int64_t n, int64_t n_pad, int32_t S,
+                                                     MArgs a, float* __restrict__ out) {
+  k_src_bias_body(n, n_pad, S, a, out, blockIdx.x, gridDim.x);
+}
+
+__global__ void __launch_bounds__(kBlock) k_src_bias_batch(const MArgs* __restrict__ sets, const int* __restrict__ pre,
+                                                           int nr) {
+  const int q = batch_find(pre, nr, blockIdx.x);
+  const MArgs& a = sets[q];
+  k_src_bias_body(a.n, a.n_pad, a.S, a, const_cast<float*>(a.bsrc), blockIdx.x - pre[q], pre[q + 1] - pre[q]);
+}
+
 
 int64_t pair_mfma_npad(int64_t n) { return ((n + kMI - 1) / kMI) * kMI; }
 
@@ -703,6 +716,13 @@ yy_status launch_pair_mfma(hipStream_t st, const PairArgs& pa, int prec, const M
 }
 
 size_t pair_mfma_args_bytes() { return sizeof(MArgs); }
+
+yy_status launch_src_bias_batch(hipStream_t st, const void* sets, const int* pre, int nr, int total) {
+  if (total <= 0) return YY_OK;
+  k_src_bias_batch<<<total, kBlock, 0, st>>>(static_cast<const MArgs*>(sets), pre, nr);
+  YY_LAUNCH_CHECK("k_src_bias_batch");
+  return YY_OK;
+}
 
 void pair_mfma_fill_args(const PairArgs& pa, int prec, const MfmaExtra& ex, void* out) {
   const MArgs m = make_args(pa, prec, ex);

@@ -23,17 +23,17 @@ namespace yy {
 // (1) node preparation: one wavefront per node.
 // Matrix-core planes are tiled [plane][rp/16][n_pad][16] so that 16 K values
 // of consecutive nodes are contiguous; rows n..n_pad-1 are zero.
-__global__ void __launch_bounds__(kBlock) k_prepare(int64_t n, int64_t n_pad, int32_t r, int32_t rp,
+__device__ __forceinline__ void k_prepare_body(int64_t n, int64_t n_pad, int32_t r, int32_t rp,
                                                     int32_t drift, const double* __restrict__ A,
                                                     const double* __restrict__ x,
                                                     const double* __restrict__ lo,
                                                     const double* __restrict__ hi,
                                                     float* __restrict__ xc32, float* __restrict__ f32,
                                                     uint16_t* __restrict__ bf, float* __restrict__ f32t,
-                                                    double* __restrict__ node, int* __restrict__ bnd) {
+                                                    double* __restrict__ node, int* __restrict__ bnd, int bx_, int gx_) {
   const int lane = threadIdx.x & 63;
-  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  const int64_t wave = ((int64_t)bx_ * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gx_ * blockDim.x) >> 6;
   const size_t plane = (size_t)n_pad * rp;
   for (int64_t i = wave; i < n_pad; i += nwaves) {
     if (i >= n) {
@@ -101,12 +101,31 @@ __global__ void __launch_bounds__(kBlock) k_prepare(int64_t n, int64_t n_pad, in
   }
 }
 
+__global__ void __launch_bounds__(kBlock) k_prepare(int64_t n, int64_t n_pad, int32_t r, int32_t rp,
+                                                    int32_t drift, const double* __restrict__ A,
+                                                    const double* __restrict__ x,
+                                                    const double* __restrict__ lo,
+                                                    const double* __restrict__ hi,
+                                                    float* __restrict__ xc32, float* __restrict__ f32,
+                                                    uint16_t* __restrict__ bf, float* __restrict__ f32t,
+                                                    double* __restrict__ node, int* __restrict__ bnd) {
+  k_prepare_body(n, n_pad, r, rp, drift, A, x, lo, hi, xc32, f32, bf, f32t, node, bnd, blockIdx.x, gridDim.x);
+}
+
+__global__ void __launch_bounds__(kBlock) k_prepare_batch(const prepare_args* __restrict__ A, const int* __restrict__ pre, int nr) {
+  const int q = batch_find(pre, nr, blockIdx.x);
+  const prepare_args& a = A[q];
+  if (a.pred && *a.pred == 0) return;
+  k_prepare_body(a.n, a.n_pad, a.r, a.rp, a.drift, a.A, a.x, a.lo, a.hi, a.xc32, a.f32, a.bf, a.f32t, a.node, a.bnd, blockIdx.x - pre[q], pre[q + 1] - pre[q]);
+}
+
+
 // Box volume (log) and the maxima of |xc| and |f| over the nodes: one block.
-__global__ void __launch_bounds__(kBlock) k_prepare_scalars(int64_t n, int32_t r,
+__device__ __forceinline__ void k_prepare_scalars_body(int64_t n, int32_t r,
                                                             const double* __restrict__ lo,
                                                             const double* __restrict__ hi,
                                                             const double* __restrict__ node,
-                                                            double* __restrict__ scal) {
+                                                            double* __restrict__ scal, int bx_, int gx_) {
   __shared__ double sh[kBlock / 64];
   double lv = 0.0;
   for (int32_t k = threadIdx.x; k < r; k += kBlock) lv += log(hi[k] - lo[k]);
@@ -126,19 +145,66 @@ __global__ void __launch_bounds__(kBlock) k_prepare_scalars(int64_t n, int32_t r
   }
 }
 
+__global__ void __launch_bounds__(kBlock) k_prepare_scalars(int64_t n, int32_t r,
+                                                            const double* __restrict__ lo,
+                                                            const double* __restrict__ hi,
+                                                            const double* __restrict__ node,
+                                                            double* __restrict__ scal) {
+  k_prepare_scalars_body(n, r, lo, hi, node, scal, blockIdx.x, gridDim.x);
+}
+
+__global__ void __launch_bounds__(kBlock) k_prepare_scalars_batch(const prepare_scalars_args* __restrict__ A, const int* __restrict__ pre, int nr) {
+  const int q = batch_find(pre, nr, blockIdx.x);
+  const prepare_scalars_args& a = A[q];
+  if (a.pred && *a.pred == 0) return;
+  k_prepare_scalars_body(a.n, a.r, a.lo, a.hi, a.node, a.scal, blockIdx.x - pre[q], pre[q + 1] - pre[q]);
+}
+
+
 // ---------------------------------------------------------------------------
 // (2) source weights: lw2[j] = (logw[j] - max_valid logw) * log2(e), -inf for
 // boundary nodes and zero weights.  Two kernels: block maxima, then every
 // block re-reduces the (short) list of block maxima in the same order.
+__device__ __forceinline__ void k_lw_max_body(int64_t n, const double* __restrict__ lw,
+                                                   const int* __restrict__ bnd,
+                                                   double* __restrict__ part, int bx_, int gx_) {
+  __shared__ double sh[kBlock / 64];
+  double m = -INFINITY;
+  for (int64_t j = (int64_t)bx_ * kBlock + threadIdx.x; j < n; j += (int64_t)gx_ * kBlock)
+    if (!bnd[j]) m = fmax(m, lw[j]);
+  m = block_max<kBlock>(m, sh);
+  if (threadIdx.x == 0) part[bx_] = m;
+}
+
 __global__ void __launch_bounds__(kBlock) k_lw_max(int64_t n, const double* __restrict__ lw,
                                                    const int* __restrict__ bnd,
                                                    double* __restrict__ part) {
+  k_lw_max_body(n, lw, bnd, part, blockIdx.x, gridDim.x);
+}
+
+__global__ void __launch_bounds__(kBlock) k_lw_max_batch(const lw_max_args* __restrict__ A, const int* __restrict__ pre, int nr) {
+  const int q = batch_find(pre, nr, blockIdx.x);
+  const lw_max_args& a = A[q];
+  if (a.pred && *a.pred == 0) return;
+  k_lw_max_body(a.n, a.lw, a.bnd, a.part, blockIdx.x - pre[q], pre[q + 1] - pre[q]);
+}
+
+
+__device__ __forceinline__ void k_lw_convert_body(int64_t n, int nparts,
+                                                       const double* __restrict__ part,
+                                                       const double* __restrict__ lw,
+                                                       const int* __restrict__ bnd,
+                                                       float* __restrict__ lw2,
+                                                       double* __restrict__ ref_out, int bx_, int gx_) {
   __shared__ double sh[kBlock / 64];
   double m = -INFINITY;
-  for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlock)
-    if (!bnd[j]) m = fmax(m, lw[j]);
+  for (int p = threadIdx.x; p < nparts; p += kBlock) m = fmax(m, part[p]);
   m = block_max<kBlock>(m, sh);
-  if (threadIdx.x == 0) part[blockIdx.x] = m;
+  if (bx_ == 0 && threadIdx.x == 0) *ref_out = m;
+  for (int64_t j = (int64_t)bx_ * kBlock + threadIdx.x; j < n; j += (int64_t)gx_ * kBlock) {
+    const double v = lw[j];
+    lw2[j] = (bnd[j] || v == -INFINITY || m == -INFINITY) ? -INFINITY : (float)((v - m) * kLog2e);
+  }
 }
 
 __global__ void __launch_bounds__(kBlock) k_lw_convert(int64_t n, int nparts,
@@ -147,16 +213,16 @@ __global__ void __launch_bounds__(kBlock) k_lw_convert(int64_t n, int nparts,
                                                        const int* __restrict__ bnd,
                                                        float* __restrict__ lw2,
                                                        double* __restrict__ ref_out) {
-  __shared__ double sh[kBlock / 64];
-  double m = -INFINITY;
-  for (int p = threadIdx.x; p < nparts; p += kBlock) m = fmax(m, part[p]);
-  m = block_max<kBlock>(m, sh);
-  if (blockIdx.x == 0 && threadIdx.x == 0) *ref_out = m;
-  for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlock) {
-    const double v = lw[j];
-    lw2[j] = (bnd[j] || v == -INFINITY || m == -INFINITY) ? -INFINITY : (float)((v - m) * kLog2e);
-  }
+  k_lw_convert_body(n, nparts, part, lw, bnd, lw2, ref_out, blockIdx.x, gridDim.x);
 }
+
+__global__ void __launch_bounds__(kBlock) k_lw_convert_batch(const lw_convert_args* __restrict__ A, const int* __restrict__ pre, int nr) {
+  const int q = batch_find(pre, nr, blockIdx.x);
+  const lw_convert_args& a = A[q];
+  if (a.pred && *a.pred == 0) return;
+  k_lw_convert_body(a.n, a.nparts, a.part, a.lw, a.bnd, a.lw2, a.ref_out, blockIdx.x - pre[q], pre[q + 1] - pre[q]);
+}
+
 
 // ---------------------------------------------------------------------------
 // (3a) pairwise kernel on the vector ALUs (plain FP32 direct differences).
@@ -338,8 +404,8 @@ static yy_status launch_pair_valu_d(hipStream_t st, const PairArgs& a, const dou
 // (4) combination in FP64: merge the source splits, add the constants, signed
 // log-sum-exp over the scales and the identity term.
 
-__global__ void __launch_bounds__(kBlock) k_combine(CombineArgs a) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+__device__ __forceinline__ void k_combine_body(CombineArgs a, int bx_, int gx_) {
+  const int64_t i = (int64_t)bx_ * kBlock + threadIdx.x;
   if (i >= a.n) return;
   if (a.bnd[i]) {
     a.logw_out[i] = -INFINITY;
@@ -386,6 +452,18 @@ __global__ void __launch_bounds__(kBlock) k_combine(CombineArgs a) {
   }
   a.logw_out[i] = Mx + log(acc);
 }
+
+__global__ void __launch_bounds__(kBlock) k_combine(CombineArgs a) {
+  k_combine_body(a, blockIdx.x, gridDim.x);
+}
+
+__global__ void __launch_bounds__(kBlock) k_combine_batch(const combine_args* __restrict__ A, const int* __restrict__ pre, int nr) {
+  const int q = batch_find(pre, nr, blockIdx.x);
+  const combine_args& a = A[q];
+  if (a.pred && *a.pred == 0) return;
+  k_combine_body(a.a, blockIdx.x - pre[q], pre[q + 1] - pre[q]);
+}
+
 
 // ---------------------------------------------------------------------------
 int pair_mfma_rp(int32_t r) { return ((r + 63) / 64) * 64; }
@@ -448,6 +526,43 @@ static yy_status check_model(const yy_model* m) {
 }
 
 yy_status validate_model(const yy_model* m) { return check_model(m); }
+
+
+// Host launchers of the batched kernels (one block range per argument set).
+yy_status launch_batched(hipStream_t st, const prepare_args* A, const int* pre, int nr, int total) {
+  if (total <= 0) return YY_OK;
+  k_prepare_batch<<<total, kBlock, 0, st>>>(A, pre, nr);
+  YY_LAUNCH_CHECK("k_prepare_batch");
+  return YY_OK;
+}
+
+yy_status launch_batched(hipStream_t st, const prepare_scalars_args* A, const int* pre, int nr, int total) {
+  if (total <= 0) return YY_OK;
+  k_prepare_scalars_batch<<<total, kBlock, 0, st>>>(A, pre, nr);
+  YY_LAUNCH_CHECK("k_prepare_scalars_batch");
+  return YY_OK;
+}
+
+yy_status launch_batched(hipStream_t st, const lw_max_args* A, const int* pre, int nr, int total) {
+  if (total <= 0) return YY_OK;
+  k_lw_max_batch<<<total, kBlock, 0, st>>>(A, pre, nr);
+  YY_LAUNCH_CHECK("k_lw_max_batch");
+  return YY_OK;
+}
+
+yy_status launch_batched(hipStream_t st, const lw_convert_args* A, const int* pre, int nr, int total) {
+  if (total <= 0) return YY_OK;
+  k_lw_convert_batch<<<total, kBlock, 0, st>>>(A, pre, nr);
+  YY_LAUNCH_CHECK("k_lw_convert_batch");
+  return YY_OK;
+}
+
+yy_status launch_batched(hipStream_t st, const combine_args* A, const int* pre, int nr, int total) {
+  if (total <= 0) return YY_OK;
+  k_combine_batch<<<total, kBlock, 0, st>>>(A, pre, nr);
+  YY_LAUNCH_CHECK("k_combine_batch");
+  return YY_OK;
+}
 
 }  // namespace yy
 

@@ -12,6 +12,16 @@ namespace yy {
 
 static const uint64_t kDomainResample = 2ULL;
 
+// SplitMix64 (Steele, Lea, Flood 2014) at counter position `counter` of stream `seed`.
+__device__ inline uint64_t d_sm64(uint64_t seed, uint64_t counter) {
+  uint64_t z = seed + (counter + 1ULL) * 0x9E3779B97F4A7C15ULL;
+  z ^= z >> 30;
+  z *= 0xBF58476D1CE4E5B9ULL;
+  z ^= z >> 27;
+  z *= 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
 static uint64_t h_sm64(uint64_t seed, uint64_t counter) {
   uint64_t z = seed + (counter + 1ULL) * 0x9E3779B97F4A7C15ULL;
   z ^= z >> 30;
@@ -23,11 +33,11 @@ static uint64_t h_sm64(uint64_t seed, uint64_t counter) {
 
 // Integer weights W_i = floor(w_i 2^53) and their inclusive prefix sums within
 // each block of kBlock elements; block totals go to `tot`.
-__global__ void __launch_bounds__(kBlock) k_rs_local(int64_t n, const double* __restrict__ w,
+__device__ __forceinline__ void k_rs_local_body(int64_t n, const double* __restrict__ w,
                                                      unsigned long long* __restrict__ C,
-                                                     unsigned long long* __restrict__ tot) {
+                                                     unsigned long long* __restrict__ tot, int bx_, int gx_) {
   __shared__ unsigned long long s[kBlock];
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t i = (int64_t)bx_ * kBlock + threadIdx.x;
   unsigned long long v = 0;
   if (i < n) {
     const double wi = w[i] > 0.0 ? w[i] : 0.0;
@@ -42,12 +52,26 @@ __global__ void __launch_bounds__(kBlock) k_rs_local(int64_t n, const double* __
     __syncthreads();
   }
   if (i < n) C[i] = s[threadIdx.x];
-  if (threadIdx.x == kBlock - 1) tot[blockIdx.x] = s[kBlock - 1];
+  if (threadIdx.x == kBlock - 1) tot[bx_] = s[kBlock - 1];
 }
 
+__global__ void __launch_bounds__(kBlock) k_rs_local(int64_t n, const double* __restrict__ w,
+                                                     unsigned long long* __restrict__ C,
+                                                     unsigned long long* __restrict__ tot) {
+  k_rs_local_body(n, w, C, tot, blockIdx.x, gridDim.x);
+}
+
+__global__ void __launch_bounds__(kBlock) k_rs_local_batch(const rs_local_args* __restrict__ A, const int* __restrict__ pre, int nr) {
+  const int q = batch_find(pre, nr, blockIdx.x);
+  const rs_local_args& a = A[q];
+  if (a.pred && *a.pred == 0) return;
+  k_rs_local_body(a.n, a.w, a.C, a.tot, blockIdx.x - pre[q], pre[q + 1] - pre[q]);
+}
+
+
 // Exclusive offsets of the block totals (one thread, integer sums).
-__global__ void k_rs_offsets(int nb, unsigned long long* __restrict__ tot) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__device__ __forceinline__ void k_rs_offsets_body(int nb, unsigned long long* __restrict__ tot, int bx_, int gx_) {
+  if (threadIdx.x != 0 || bx_ != 0) return;
   unsigned long long run = 0;
   for (int b = 0; b < nb; ++b) {
     const unsigned long long t = tot[b];
@@ -57,21 +81,46 @@ __global__ void k_rs_offsets(int nb, unsigned long long* __restrict__ tot) {
   tot[nb] = run;  // W
 }
 
+__global__ void __launch_bounds__(kBlock) k_rs_offsets(int nb, unsigned long long* __restrict__ tot) {
+  k_rs_offsets_body(nb, tot, blockIdx.x, gridDim.x);
+}
+
+__global__ void __launch_bounds__(kBlock) k_rs_offsets_batch(const rs_offsets_args* __restrict__ A, const int* __restrict__ pre, int nr) {
+  const int q = batch_find(pre, nr, blockIdx.x);
+  const rs_offsets_args& a = A[q];
+  if (a.pred && *a.pred == 0) return;
+  k_rs_offsets_body(a.nb, a.tot, blockIdx.x - pre[q], pre[q + 1] - pre[q]);
+}
+
+
+__device__ __forceinline__ void k_rs_add_body(int64_t n, const unsigned long long* __restrict__ tot,
+                                                   unsigned long long* __restrict__ C, int bx_, int gx_) {
+  const int64_t i = (int64_t)bx_ * kBlock + threadIdx.x;
+  if (i < n) C[i] += tot[bx_];
+}
+
 __global__ void __launch_bounds__(kBlock) k_rs_add(int64_t n, const unsigned long long* __restrict__ tot,
                                                    unsigned long long* __restrict__ C) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i < n) C[i] += tot[blockIdx.x];
+  k_rs_add_body(n, tot, C, blockIdx.x, gridDim.x);
 }
+
+__global__ void __launch_bounds__(kBlock) k_rs_add_batch(const rs_add_args* __restrict__ A, const int* __restrict__ pre, int nr) {
+  const int q = batch_find(pre, nr, blockIdx.x);
+  const rs_add_args& a = A[q];
+  if (a.pred && *a.pred == 0) return;
+  k_rs_add_body(a.n, a.tot, a.C, blockIdx.x - pre[q], pre[q + 1] - pre[q]);
+}
+
 
 // P_t = floor((t 2^32 + U) W / (n 2^32)); idx[t] = min{i : C_i > P_t}.
 // The 119-bit product is formed from 64-bit halves; the quotient is taken as
 // floor(floor(A W / 2^32) / n) with a 96-by-32-bit long division.
-__global__ void __launch_bounds__(kBlock) k_rs_search(int64_t n, int nb,
+__device__ __forceinline__ void k_rs_search_body(int64_t n, int nb,
                                                       const unsigned long long* __restrict__ tot,
                                                       const unsigned long long* __restrict__ C,
                                                       uint64_t U, int64_t* __restrict__ idx,
-                                                      uint32_t* __restrict__ flags) {
-  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+                                                      uint32_t* __restrict__ flags, int bx_, int gx_) {
+  const int64_t t = (int64_t)bx_ * kBlock + threadIdx.x;
   const unsigned long long W = tot[nb];
   if (W == 0ULL) {
     if (t == 0) atomicOr(flags, YY_FLAG_RESAMPLE_ZERO);
@@ -104,32 +153,62 @@ __global__ void __launch_bounds__(kBlock) k_rs_search(int64_t n, int nb,
   idx[t] = lo_i;
 }
 
+__global__ void __launch_bounds__(kBlock) k_rs_search(int64_t n, int nb,
+                                                      const unsigned long long* __restrict__ tot,
+                                                      const unsigned long long* __restrict__ C,
+                                                      uint64_t U, int64_t* __restrict__ idx,
+                                                      uint32_t* __restrict__ flags) {
+  k_rs_search_body(n, nb, tot, C, U, idx, flags, blockIdx.x, gridDim.x);
+}
+
+__global__ void __launch_bounds__(kBlock) k_rs_search_batch(const rs_search_args* __restrict__ A, const int* __restrict__ pre, int nr) {
+  const int q = batch_find(pre, nr, blockIdx.x);
+  const rs_search_args& a = A[q];
+  if (a.pred && *a.pred == 0) return;
+  k_rs_search_body(a.n, a.nb, a.tot, a.C, a.kstep ? d_sm64(a.key, (uint64_t)*a.kstep) >> 32 : a.U, a.idx,
+                   a.flags, blockIdx.x - pre[q], pre[q + 1] - pre[q]);
+}
+
+
 // The plain box [mean - R, mean + R]^r.
-__global__ void __launch_bounds__(kBlock) k_box_plain(int32_t r, double R, const double* __restrict__ mean,
-                                                      double* __restrict__ box_lo, double* __restrict__ box_hi) {
-  const int d = blockIdx.x * kBlock + threadIdx.x;
+__device__ __forceinline__ void k_box_plain_body(int32_t r, double R, const double* __restrict__ mean,
+                                                      double* __restrict__ box_lo, double* __restrict__ box_hi, int bx_, int gx_) {
+  const int d = bx_ * kBlock + threadIdx.x;
   if (d >= r) return;
   box_lo[d] = __dsub_rn(mean[d], R);
   box_hi[d] = __dadd_rn(mean[d], R);
 }
 
+__global__ void __launch_bounds__(kBlock) k_box_plain(int32_t r, double R, const double* __restrict__ mean,
+                                                      double* __restrict__ box_lo, double* __restrict__ box_hi) {
+  k_box_plain_body(r, R, mean, box_lo, box_hi, blockIdx.x, gridDim.x);
+}
+
+__global__ void __launch_bounds__(kBlock) k_box_plain_batch(const box_plain_args* __restrict__ A, const int* __restrict__ pre, int nr) {
+  const int q = batch_find(pre, nr, blockIdx.x);
+  const box_plain_args& a = A[q];
+  if (a.pred && *a.pred == 0) return;
+  k_box_plain_body(a.r, a.R, a.mean, a.box_lo, a.box_hi, blockIdx.x - pre[q], pre[q + 1] - pre[q]);
+}
+
+
 // Nodes and prior in the box [box_lo, box_hi].  One wavefront per node; the
 // centre and half-width are recomputed per coordinate exactly as the node
-// map defines them (no fused multiply-add).  With `pred` set the kernel runs
-// only when *pred is non-zero (the learned restart's fallback).
-__global__ void __launch_bounds__(kBlock) k_restart_nodes(int64_t n, int32_t r, const uint32_t* __restrict__ codes,
+// map defines them (no fused multiply-add).  With `only_if` set the kernel
+// runs only when *only_if is non-zero (the learned restart's fallback).
+__device__ __forceinline__ void k_restart_nodes_body(int64_t n, int32_t r, const uint32_t* __restrict__ codes,
                                                           const double* __restrict__ mean,
                                                           const double* __restrict__ box_lo,
                                                           const double* __restrict__ box_hi,
-                                                          const int* __restrict__ pred,
+                                                          const int* __restrict__ only_if,
                                                           double* __restrict__ x_new,
-                                                          double* __restrict__ logw_new) {
+                                                          double* __restrict__ logw_new, int bx_, int gx_) {
 #pragma clang fp contract(off)
-  if (pred && *pred == 0) return;
+  if (only_if && *only_if == 0) return;
   const int lane = threadIdx.x & 63;
-  const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t gt = (int64_t)bx_ * blockDim.x + threadIdx.x;
   const int64_t wave = gt >> 6;
-  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  const int64_t nwaves = ((int64_t)gx_ * blockDim.x) >> 6;
   for (int64_t i = wave; i < n; i += nwaves) {
     double acc = 0.0;
     int b = 0;
@@ -150,8 +229,89 @@ __global__ void __launch_bounds__(kBlock) k_restart_nodes(int64_t n, int32_t r, 
   }
 }
 
-__global__ void k_ess_check(const double* __restrict__ ess, double ess_min, uint32_t* __restrict__ flags) {
-  if (threadIdx.x == 0 && blockIdx.x == 0 && *ess < ess_min) atomicOr(flags, YY_FLAG_LOW_ESS);
+__global__ void __launch_bounds__(kBlock) k_restart_nodes(int64_t n, int32_t r, const uint32_t* __restrict__ codes,
+                                                          const double* __restrict__ mean,
+                                                          const double* __restrict__ box_lo,
+                                                          const double* __restrict__ box_hi,
+                                                          const int* __restrict__ only_if,
+                                                          double* __restrict__ x_new,
+                                                          double* __restrict__ logw_new) {
+  k_restart_nodes_body(n, r, codes, mean, box_lo, box_hi, only_if, x_new, logw_new, blockIdx.x, gridDim.x);
+}
+
+__global__ void __launch_bounds__(kBlock) k_restart_nodes_batch(const restart_nodes_args* __restrict__ A, const int* __restrict__ pre, int nr) {
+  const int q = batch_find(pre, nr, blockIdx.x);
+  const restart_nodes_args& a = A[q];
+  if (a.pred && *a.pred == 0) return;
+  k_restart_nodes_body(a.n, a.r, a.codes, a.mean, a.box_lo, a.box_hi, a.only_if, a.x_new, a.logw_new, blockIdx.x - pre[q], pre[q + 1] - pre[q]);
+}
+
+
+__device__ __forceinline__ void k_ess_check_body(const double* __restrict__ ess, double ess_min, uint32_t* __restrict__ flags, int bx_, int gx_) {
+  if (threadIdx.x == 0 && bx_ == 0 && *ess < ess_min) atomicOr(flags, YY_FLAG_LOW_ESS);
+}
+
+__global__ void __launch_bounds__(kBlock) k_ess_check(const double* __restrict__ ess, double ess_min, uint32_t* __restrict__ flags) {
+  k_ess_check_body(ess, ess_min, flags, blockIdx.x, gridDim.x);
+}
+
+__global__ void __launch_bounds__(kBlock) k_ess_check_batch(const ess_check_args* __restrict__ A, const int* __restrict__ pre, int nr) {
+  const int q = batch_find(pre, nr, blockIdx.x);
+  const ess_check_args& a = A[q];
+  if (a.pred && *a.pred == 0) return;
+  k_ess_check_body(a.ess, a.ess_min, a.flags, blockIdx.x - pre[q], pre[q + 1] - pre[q]);
+}
+
+
+
+// Host launchers of the batched kernels (one block range per argument set).
+yy_status launch_batched(hipStream_t st, const rs_local_args* A, const int* pre, int nr, int total) {
+  if (total <= 0) return YY_OK;
+  k_rs_local_batch<<<total, kBlock, 0, st>>>(A, pre, nr);
+  YY_LAUNCH_CHECK("k_rs_local_batch");
+  return YY_OK;
+}
+
+yy_status launch_batched(hipStream_t st, const rs_offsets_args* A, const int* pre, int nr, int total) {
+  if (total <= 0) return YY_OK;
+  k_rs_offsets_batch<<<total, kBlock, 0, st>>>(A, pre, nr);
+  YY_LAUNCH_CHECK("k_rs_offsets_batch");
+  return YY_OK;
+}
+
+yy_status launch_batched(hipStream_t st, const rs_add_args* A, const int* pre, int nr, int total) {
+  if (total <= 0) return YY_OK;
+  k_rs_add_batch<<<total, kBlock, 0, st>>>(A, pre, nr);
+  YY_LAUNCH_CHECK("k_rs_add_batch");
+  return YY_OK;
+}
+
+yy_status launch_batched(hipStream_t st, const rs_search_args* A, const int* pre, int nr, int total) {
+  if (total <= 0) return YY_OK;
+  k_rs_search_batch<<<total, kBlock, 0, st>>>(A, pre, nr);
+  YY_LAUNCH_CHECK("k_rs_search_batch");
+  return YY_OK;
+}
+
+yy_status launch_batched(hipStream_t st, const box_plain_args* A, const int* pre, int nr, int total) {
+  if (total <= 0) return YY_OK;
+  k_box_plain_batch<<<total, kBlock, 0, st>>>(A, pre, nr);
+  YY_LAUNCH_CHECK("k_box_plain_batch");
+  return YY_OK;
+}
+
+yy_status launch_batched(hipStream_t st, const restart_nodes_args* A, const int* pre, int nr, int total) {
+  if (total <= 0) return YY_OK;
+  k_restart_nodes_batch<<<total, kBlock, 0, st>>>(A, pre, nr);
+  YY_LAUNCH_CHECK("k_restart_nodes_batch");
+  return YY_OK;
+}
+
+yy_status launch_batched(hipStream_t st, const ess_check_args* A, const int* pre, int nr, int total) {
+  if (total <= 0) return YY_OK;
+  k_ess_check_batch<<<total, kBlock, 0, st>>>(A, pre, nr);
+  YY_LAUNCH_CHECK("k_ess_check_batch");
+  return YY_OK;
 }
 
 }  // namespace yy

@@ -12,14 +12,14 @@ namespace yy {
 
 // ---------------------------------------------------------------------------
 // logw[i] += (h(x_i).dy - dt/2 |h(x_i)|^2) / rho2; one wavefront per node.
-__global__ void __launch_bounds__(kBlock) k_loglik(int64_t n, int32_t r, int32_t m, int32_t obs,
+__device__ __forceinline__ void k_loglik_body(int64_t n, int32_t r, int32_t m, int32_t obs,
                                                    const double* __restrict__ H, double h_shift,
                                                    const double* __restrict__ x,
                                                    const double* __restrict__ dy, double dt,
-                                                   double rho2, double* __restrict__ logw) {
+                                                   double rho2, double* __restrict__ logw, int bx_, int gx_) {
   const int lane = threadIdx.x & 63;
-  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  const int64_t wave = ((int64_t)bx_ * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gx_ * blockDim.x) >> 6;
   for (int64_t i = wave; i < n; i += nwaves) {
     const double li = logw[i];
     if (li == -INFINITY) continue;
@@ -47,41 +47,86 @@ __global__ void __launch_bounds__(kBlock) k_loglik(int64_t n, int32_t r, int32_t
   }
 }
 
+__global__ void __launch_bounds__(kBlock) k_loglik(int64_t n, int32_t r, int32_t m, int32_t obs,
+                                                   const double* __restrict__ H, double h_shift,
+                                                   const double* __restrict__ x,
+                                                   const double* __restrict__ dy, double dt,
+                                                   double rho2, double* __restrict__ logw) {
+  k_loglik_body(n, r, m, obs, H, h_shift, x, dy, dt, rho2, logw, blockIdx.x, gridDim.x);
+}
+
+__global__ void __launch_bounds__(kBlock) k_loglik_batch(const loglik_args* __restrict__ A, const int* __restrict__ pre, int nr) {
+  const int q = batch_find(pre, nr, blockIdx.x);
+  const loglik_args& a = A[q];
+  if (a.pred && *a.pred == 0) return;
+  k_loglik_body(a.n, a.r, a.m, a.obs, a.H, a.h_shift, a.x, a.kstep ? a.dy + (size_t)(*a.kstep - 1) * a.m : a.dy,
+                a.dt, a.rho2, a.logw, blockIdx.x - pre[q], pre[q + 1] - pre[q]);
+}
+
+
 // ---------------------------------------------------------------------------
 // Normalisation.  Scratch layout (doubles): pmax[nb], psum[nb], pw2[nb],
 // pmean[nb * r], sc[4] = {logZ, valid, 0, 0}.
-__global__ void __launch_bounds__(kBlock) k_norm_max(int64_t n, const double* __restrict__ lw,
-                                                     double* __restrict__ pmax) {
+__device__ __forceinline__ void k_norm_max_body(int64_t n, const double* __restrict__ lw,
+                                                     double* __restrict__ pmax, int bx_, int gx_) {
   __shared__ double sh[kBlock / 64];
   double m = -INFINITY;
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+  for (int64_t i = (int64_t)bx_ * kBlock + threadIdx.x; i < n; i += (int64_t)gx_ * kBlock)
     m = fmax(m, lw[i]);
   m = block_max<kBlock>(m, sh);
-  if (threadIdx.x == 0) pmax[blockIdx.x] = m;
+  if (threadIdx.x == 0) pmax[bx_] = m;
 }
 
-__global__ void __launch_bounds__(kBlock) k_norm_sumexp(int64_t n, int nb,
+__global__ void __launch_bounds__(kBlock) k_norm_max(int64_t n, const double* __restrict__ lw,
+                                                     double* __restrict__ pmax) {
+  k_norm_max_body(n, lw, pmax, blockIdx.x, gridDim.x);
+}
+
+__global__ void __launch_bounds__(kBlock) k_norm_max_batch(const norm_max_args* __restrict__ A, const int* __restrict__ pre, int nr) {
+  const int q = batch_find(pre, nr, blockIdx.x);
+  const norm_max_args& a = A[q];
+  if (a.pred && *a.pred == 0) return;
+  k_norm_max_body(a.n, a.lw, a.pmax, blockIdx.x - pre[q], pre[q + 1] - pre[q]);
+}
+
+
+__device__ __forceinline__ void k_norm_sumexp_body(int64_t n, int nb,
                                                         const double* __restrict__ pmax,
                                                         const double* __restrict__ lw,
-                                                        double* __restrict__ psum) {
+                                                        double* __restrict__ psum, int bx_, int gx_) {
   __shared__ double sh[kBlock / 64];
   double M = -INFINITY;
   for (int p = threadIdx.x; p < nb; p += kBlock) M = fmax(M, pmax[p]);
   M = block_max<kBlock>(M, sh);
   double s = 0.0;
   if (M != -INFINITY)
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+    for (int64_t i = (int64_t)bx_ * kBlock + threadIdx.x; i < n; i += (int64_t)gx_ * kBlock)
       s += exp(lw[i] - M);
   s = block_sum<kBlock>(s, sh);
-  if (threadIdx.x == 0) psum[blockIdx.x] = s;
+  if (threadIdx.x == 0) psum[bx_] = s;
 }
 
-__global__ void __launch_bounds__(kBlock) k_norm_logz(int nb, const double* __restrict__ pmax,
+__global__ void __launch_bounds__(kBlock) k_norm_sumexp(int64_t n, int nb,
+                                                        const double* __restrict__ pmax,
+                                                        const double* __restrict__ lw,
+                                                        double* __restrict__ psum) {
+  k_norm_sumexp_body(n, nb, pmax, lw, psum, blockIdx.x, gridDim.x);
+}
+
+__global__ void __launch_bounds__(kBlock) k_norm_sumexp_batch(const norm_sumexp_args* __restrict__ A, const int* __restrict__ pre, int nr) {
+  const int q = batch_find(pre, nr, blockIdx.x);
+  const norm_sumexp_args& a = A[q];
+  if (a.pred && *a.pred == 0) return;
+  k_norm_sumexp_body(a.n, a.nb, a.pmax, a.lw, a.psum, blockIdx.x - pre[q], pre[q + 1] - pre[q]);
+}
+
+
+__device__ __forceinline__ void k_norm_logz_body(int nb, const double* __restrict__ pmax,
                                                       const double* __restrict__ psum,
                                                       double* __restrict__ sc,
                                                       double* __restrict__ logZ_step,
                                                       double* __restrict__ logZ_acc,
-                                                      uint32_t* __restrict__ flags) {
+                                                      uint32_t* __restrict__ flags, int bx_, int gx_) {
   __shared__ double sh[kBlock / 64];
   double M = -INFINITY;
   for (int p = threadIdx.x; p < nb; p += kBlock) M = fmax(M, pmax[p]);
@@ -105,20 +150,37 @@ __global__ void __launch_bounds__(kBlock) k_norm_logz(int nb, const double* __re
   }
 }
 
+__global__ void __launch_bounds__(kBlock) k_norm_logz(int nb, const double* __restrict__ pmax,
+                                                      const double* __restrict__ psum,
+                                                      double* __restrict__ sc,
+                                                      double* __restrict__ logZ_step,
+                                                      double* __restrict__ logZ_acc,
+                                                      uint32_t* __restrict__ flags) {
+  k_norm_logz_body(nb, pmax, psum, sc, logZ_step, logZ_acc, flags, blockIdx.x, gridDim.x);
+}
+
+__global__ void __launch_bounds__(kBlock) k_norm_logz_batch(const norm_logz_args* __restrict__ A, const int* __restrict__ pre, int nr) {
+  const int q = batch_find(pre, nr, blockIdx.x);
+  const norm_logz_args& a = A[q];
+  if (a.pred && *a.pred == 0) return;
+  k_norm_logz_body(a.nb, a.pmax, a.psum, a.sc, a.logZ_step, a.logZ_acc, a.flags, blockIdx.x - pre[q], pre[q + 1] - pre[q]);
+}
+
+
 // Block b handles rows [b*rows, (b+1)*rows): normalised log-weights, weights,
 // partial sum of w^2 and partial weighted coordinate sums.
-__global__ void __launch_bounds__(kBlock) k_norm_weights(int64_t n, int32_t r, int64_t rows,
+__device__ __forceinline__ void k_norm_weights_body(int64_t n, int32_t r, int64_t rows,
                                                          const double* __restrict__ sc,
                                                          const double* __restrict__ x,
                                                          double* __restrict__ lw,
                                                          double* __restrict__ w,
                                                          double* __restrict__ pw2,
-                                                         double* __restrict__ pmean) {
+                                                         double* __restrict__ pmean, int bx_, int gx_) {
   __shared__ double sw[kBlock];
   __shared__ double sh[kBlock / 64];
   if (sc[1] == 0.0) return;
   const double lz = sc[0];
-  const int64_t b0 = (int64_t)blockIdx.x * rows;
+  const int64_t b0 = (int64_t)bx_ * rows;
   const int64_t b1 = std::min<int64_t>(b0 + rows, n);
   double w2 = 0.0;
   // per-thread accumulators for coordinates k = threadIdx.x + kBlock * c
@@ -152,11 +214,48 @@ __global__ void __launch_bounds__(kBlock) k_norm_weights(int64_t n, int32_t r, i
     }
   }
   w2 = block_sum<kBlock>(w2, sh);
-  if (threadIdx.x == 0) pw2[blockIdx.x] = w2;
+  if (threadIdx.x == 0) pw2[bx_] = w2;
 #pragma unroll
   for (int c = 0; c < kMaxC; ++c) {
     const int k = threadIdx.x + kBlock * c;
-    if (c < nc && k < r) pmean[(size_t)blockIdx.x * r + k] = acc[c];
+    if (c < nc && k < r) pmean[(size_t)bx_ * r + k] = acc[c];
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_norm_weights(int64_t n, int32_t r, int64_t rows,
+                                                         const double* __restrict__ sc,
+                                                         const double* __restrict__ x,
+                                                         double* __restrict__ lw,
+                                                         double* __restrict__ w,
+                                                         double* __restrict__ pw2,
+                                                         double* __restrict__ pmean) {
+  k_norm_weights_body(n, r, rows, sc, x, lw, w, pw2, pmean, blockIdx.x, gridDim.x);
+}
+
+__global__ void __launch_bounds__(kBlock) k_norm_weights_batch(const norm_weights_args* __restrict__ A, const int* __restrict__ pre, int nr) {
+  const int q = batch_find(pre, nr, blockIdx.x);
+  const norm_weights_args& a = A[q];
+  if (a.pred && *a.pred == 0) return;
+  k_norm_weights_body(a.n, a.r, a.rows, a.sc, a.x, a.lw, a.w, a.pw2, a.pmean, blockIdx.x - pre[q], pre[q + 1] - pre[q]);
+}
+
+
+__device__ __forceinline__ void k_norm_final_body(int nb, int32_t r, const double* __restrict__ sc,
+                                                       const double* __restrict__ pw2,
+                                                       const double* __restrict__ pmean,
+                                                       double* __restrict__ mean,
+                                                       double* __restrict__ ess, int bx_, int gx_) {
+  if (sc[1] == 0.0) return;
+  const int k = bx_ * kBlock + threadIdx.x;
+  if (k < r) {
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += pmean[(size_t)b * r + k];
+    mean[k] = s;
+  }
+  if (bx_ == 0 && threadIdx.x == 0) {
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += pw2[b];
+    *ess = 1.0 / s;
   }
 }
 
@@ -165,19 +264,16 @@ __global__ void __launch_bounds__(kBlock) k_norm_final(int nb, int32_t r, const 
                                                        const double* __restrict__ pmean,
                                                        double* __restrict__ mean,
                                                        double* __restrict__ ess) {
-  if (sc[1] == 0.0) return;
-  const int k = blockIdx.x * kBlock + threadIdx.x;
-  if (k < r) {
-    double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += pmean[(size_t)b * r + k];
-    mean[k] = s;
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += pw2[b];
-    *ess = 1.0 / s;
-  }
+  k_norm_final_body(nb, r, sc, pw2, pmean, mean, ess, blockIdx.x, gridDim.x);
 }
+
+__global__ void __launch_bounds__(kBlock) k_norm_final_batch(const norm_final_args* __restrict__ A, const int* __restrict__ pre, int nr) {
+  const int q = batch_find(pre, nr, blockIdx.x);
+  const norm_final_args& a = A[q];
+  if (a.pred && *a.pred == 0) return;
+  k_norm_final_body(a.nb, a.r, a.sc, a.pw2, a.pmean, a.mean, a.ess, blockIdx.x - pre[q], pre[q + 1] - pre[q]);
+}
+
 
 // Weighted covariance: 64 x 64 output tile per block (16 x 16 threads, 4 x 4
 // each), all n rows in chunks of 16 staged through LDS.
@@ -229,6 +325,50 @@ __global__ void __launch_bounds__(256) k_norm_cov(int64_t n, int32_t r, const do
       const int ka = a0 + ty * 4 + p, kb = b0 + tx * 4 + q;
       if (ka < r && kb < r) cov[(size_t)ka * r + kb] = acc[p][q];
     }
+}
+
+
+// Host launchers of the batched kernels (one block range per argument set).
+yy_status launch_batched(hipStream_t st, const loglik_args* A, const int* pre, int nr, int total) {
+  if (total <= 0) return YY_OK;
+  k_loglik_batch<<<total, kBlock, 0, st>>>(A, pre, nr);
+  YY_LAUNCH_CHECK("k_loglik_batch");
+  return YY_OK;
+}
+
+yy_status launch_batched(hipStream_t st, const norm_max_args* A, const int* pre, int nr, int total) {
+  if (total <= 0) return YY_OK;
+  k_norm_max_batch<<<total, kBlock, 0, st>>>(A, pre, nr);
+  YY_LAUNCH_CHECK("k_norm_max_batch");
+  return YY_OK;
+}
+
+yy_status launch_batched(hipStream_t st, const norm_sumexp_args* A, const int* pre, int nr, int total) {
+  if (total <= 0) return YY_OK;
+  k_norm_sumexp_batch<<<total, kBlock, 0, st>>>(A, pre, nr);
+  YY_LAUNCH_CHECK("k_norm_sumexp_batch");
+  return YY_OK;
+}
+
+yy_status launch_batched(hipStream_t st, const norm_logz_args* A, const int* pre, int nr, int total) {
+  if (total <= 0) return YY_OK;
+  k_norm_logz_batch<<<total, kBlock, 0, st>>>(A, pre, nr);
+  YY_LAUNCH_CHECK("k_norm_logz_batch");
+  return YY_OK;
+}
+
+yy_status launch_batched(hipStream_t st, const norm_weights_args* A, const int* pre, int nr, int total) {
+  if (total <= 0) return YY_OK;
+  k_norm_weights_batch<<<total, kBlock, 0, st>>>(A, pre, nr);
+  YY_LAUNCH_CHECK("k_norm_weights_batch");
+  return YY_OK;
+}
+
+yy_status launch_batched(hipStream_t st, const norm_final_args* A, const int* pre, int nr, int total) {
+  if (total <= 0) return YY_OK;
+  k_norm_final_batch<<<total, kBlock, 0, st>>>(A, pre, nr);
+  YY_LAUNCH_CHECK("k_norm_final_batch");
+  return YY_OK;
 }
 
 }  // namespace yy

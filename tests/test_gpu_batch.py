@@ -94,15 +94,24 @@ def test_graph_replay_equals_eager_steps():
         g.close()
 
 
-def test_graph_needs_eager_steps_first():
-    ws = _workloads(K=6)
+def test_graph_from_step_zero_with_odd_end():
+    ws = _workloads(K=7)
     dys = [W.simulate(w)[1] for w in ws]
-    b = Batch(ws, dys)
+    a = Batch(ws, dys)
+    g = Batch(ws, dys)
     try:
+        for _ in range(7):
+            a.step()
+        g.run_graph(7)          # three graph launches of two steps, then one eager step
+        assert g.k == 7
         with pytest.raises(yy.YYError):
-            b.run_graph(6)
+            g.step()            # all K steps taken
+        for q in range(len(ws)):
+            for x, y in zip(g.results(q), a.results(q)):
+                assert np.array_equal(host(x), host(y)), q
     finally:
-        b.close()
+        a.close()
+        g.close()
 
 
 def test_batch_tuner_keeps_results():
