@@ -187,6 +187,95 @@ def sampled_parity(w, f, prec, sample):
     return float(np.max(rel)) if rel.size else float("nan")
 
 
+def main_batch(args):
+    """The batch of 64 uneven cubic-sensor runs: aggregate filter steps/s of the graph-replayed
+    step loop, beside the same batch stepped eagerly and the runs filtered one after another."""
+    import numpy as np
+    import torch
+
+    from paper_2509_16896_amd import workloads as W
+    from paper_2509_16896_amd import yy
+    from paper_2509_16896_amd.batch import Batch
+    from paper_2509_16896_amd.filter import GpuFilter
+
+    ws = W.batch_runs(64, seed=0)
+    K = ws[0].K
+    dys = [W.simulate(w)[1] for w in ws]
+    alg = sum(2.0 * w.n * w.n * w.r * 2 for w in ws)   # per batched pairwise launch
+    log(f"[bench] batch of {len(ws)} runs, r in [{min(w.r for w in ws)}, {max(w.r for w in ws)}], "
+        f"n in [{min(w.n for w in ws)}, {max(w.n for w in ws)}], K={K}, prec={args.prec}")
+    bt = Batch(ws, dys, prec=args.prec)
+    t0 = time.perf_counter()
+    bt.step()
+    best = bt.tune(reps=2)
+    tune_s = time.perf_counter() - t0
+    log(f"[bench] tuned max source splits per run: {best} ({tune_s:.2f} s)")
+
+    def run_eager():
+        bt.reset()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(K):
+            bt.step()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t
+
+    def run_graph():
+        bt.reset()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        bt.step()
+        bt.step()
+        bt.run_graph(K)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t
+
+    run_graph()                       # capture + instantiate + first launch
+    t_graph = min(run_graph() for _ in range(max(1, args.steps // 10)))
+    t_eager = run_eager()
+    # the pairwise launch alone (HIP events on the batch's stream)
+    bt.reset()
+    bt.step()
+    bt.step()
+    yy.yy_timing_enable(bt.ctx, True)
+    yy.yy_timing_read(bt.ctx)
+    for _ in range(4):
+        bt.step()
+    ms, cnt = yy.yy_timing_read(bt.ctx)
+    yy.yy_timing_enable(bt.ctx, False)
+    kms = ms / max(cnt, 1)
+    bt.close()
+    # the same runs one after another through the single-run calls
+    t_seq = 0.0
+    for w, d in zip(ws, dys):
+        f = GpuFilter(w, prec=args.prec)
+        f.set_observations(d)
+        f.init()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for k in range(1, K + 1):
+            f.step(k)
+        torch.cuda.synchronize()
+        t_seq += time.perf_counter() - t
+        f.close()
+    steps = len(ws) * K
+    achieved = alg / (kms * 1e-3) / 1e12
+    line = {
+        "metric": "aggregate filter steps/s, batch of 64 uneven cubic-sensor runs", "value": round(steps / t_graph, 2),
+        "unit": "steps/s", "n_gpus": 1, "steps": K, "warmup": 2, "ms_per_step": round(1e3 * t_graph / K, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": "batch64_cubic_r10-200_n2048-32768", "runs": len(ws), "K": K,
+                   "precision": args.prec, "max_split": best},
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_TFLOPS[args.prec],
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS[args.prec], 4), "traffic": None,
+                     "kernel": "k_pair_mfma_batch", "kernel_ms": round(kms, 3)},
+        "eager_steps_per_s": round(steps / t_eager, 2),
+        "sequential_single_run_steps_per_s": round(steps / t_seq, 2),
+        "tune_s": round(tune_s, 2),
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -197,7 +286,7 @@ def main():
                     help="matrix-core forms whose pairwise kernel is also timed ('none' to skip)")
     ap.add_argument("--baseline-prec", default="fp32_mfma", help="plain FP32 form timed beside ('none' to skip)")
     ap.add_argument("--baseline-steps", type=int, default=4)
-    ap.add_argument("--workload", default="cubic_r1000", choices=["cubic_r1000", "cubic_r100"])
+    ap.add_argument("--workload", default="cubic_r1000", choices=["cubic_r1000", "cubic_r100", "batch64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--proposal", default="learned", choices=["learned", "none"],
@@ -211,6 +300,9 @@ def main():
     if args.gpus != 1 or world != 1:
         print(json.dumps({"error": "this build benchmarks one GPU only; run with --gpus 1"}))
         sys.exit(2)
+
+    if args.workload == "batch64":
+        return main_batch(args)
 
     import numpy as np
     import torch
