@@ -60,8 +60,8 @@ struct Prepared {
   int64_t n_pad = 0;        // n rounded up to the matrix-core target block
   DevBuf xc32;              // float [n*rp]  x - box centre
   DevBuf f32;               // float [n*rp]  f(x)
-  DevBuf bf;                // bf16 planes hi(xc), hi(f), lo(xc), lo(f), each [n_pad/128][rp/16][128][16]
-  DevBuf f32t;              // float planes xc, f, each [n_pad/128][rp/16][128][16]
+  DevBuf bf;                // bf16 tiled [4][rp/16][n_pad][16]: hi(xc), hi(f), lo(xc), lo(f)
+  DevBuf f32t;              // float tiled [2][rp/16][n_pad][16]: xc, f
   DevBuf node;              // double [3][n]  |xc|^2, |f|^2, xc.f
   DevBuf bnd;               // int [n]  1 = boundary node
   DevBuf scal;              // double [4]  log vol(box), max |xc|, max |f|, spare

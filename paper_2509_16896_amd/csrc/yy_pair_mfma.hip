@@ -47,8 +47,8 @@ struct MArgs {
   float tau[YY_MAX_SCALES];
   double kapd[YY_MAX_SCALES];
   double taud[YY_MAX_SCALES];
-  const uint16_t* bf;          // bf16 planes hi(x), hi(f), lo(x), lo(f): [n_pad/128][rp/16][128][16] each
-  const float* f32t;           // fp32 planes x, f: [n_pad/128][rp/16][128][16] each
+  const uint16_t* bf;          // bf16 planes [4][rp/16][n_pad][16]: hi(x), hi(f), lo(x), lo(f)
+  const float* f32t;           // fp32 planes [2][rp/16][n_pad][16]: x, f
   const float* xc;             // row-major FP32 [n][rp] (exact near pairs)
   const float* f;
   const float* lw2;            // [n]
@@ -337,12 +337,10 @@ __device__ inline void wait_vmcnt() {
 
 // Issues the copies of one K stage: target planes (rows i0..i0+255) then source
 // planes (rows j0..j0+127) of K chunk c.  ESZ = element bytes (2: bf16, 4: fp32).
-// Global planes are [n_pad/128 row blocks][chunk][128 rows][16 elements], so
-// that the whole K range of a 128-row tile is one contiguous stretch (few
-// pages per block); target planes are global planes 0 and 2, source planes
-// 0..3.
+// Global planes are [chunk][n_pad][16 elements]; target planes are global
+// planes 0 and 2, source planes 0..3.
 template <int ESZ, int NTP, int NSP>
-__device__ inline void issue_stage(const unsigned char* gb, uint64_t plane_bytes, int nchunks,
+__device__ inline void issue_stage(const unsigned char* gb, uint64_t plane_bytes, int64_t n_pad,
                                    uint32_t stage_lds, int c, int64_t i0, int64_t j0, int wave, int lane) {
   constexpr int ROWB = kKC * ESZ;              // bytes per row per stage
   constexpr int CPR = ROWB / 16;               // 16-byte chunks per row
@@ -350,10 +348,8 @@ __device__ inline void issue_stage(const unsigned char* gb, uint64_t plane_bytes
   constexpr int TREG = kMI / RPR, SREG = kMJ / RPR;
   constexpr int R = NTP * TREG + NSP * SREG;
   constexpr int RW = (R + kWaves - 1) / kWaves;
-  // byte offset of row `row0` (a multiple of RPR) of chunk c
-  auto at = [&](int64_t row0) -> uint64_t {
-    return ((uint64_t)(row0 >> 7) * (uint64_t)nchunks + (uint64_t)c) * (128 * ROWB) + (uint64_t)(row0 & 127) * ROWB;
-  };
+  const unsigned char* tb = gb + ((uint64_t)c * (uint64_t)n_pad + (uint64_t)i0) * ROWB;
+  const unsigned char* sbp = gb + ((uint64_t)c * (uint64_t)n_pad + (uint64_t)j0) * ROWB;
   const int rl = lane / CPR, pc = lane % CPR;
 #pragma unroll
   for (int u = 0; u < RW; ++u) {
@@ -363,12 +359,12 @@ __device__ inline void issue_stage(const unsigned char* gb, uint64_t plane_bytes
     int off;
     if (q < NTP * TREG) {
       const int p = q / TREG, rb = (q % TREG) * RPR, row = rb + rl;
-      src = gb + (uint64_t)(2 * p) * plane_bytes + at(i0 + rb) + rl * ROWB + swz<CPR>(row, pc) * 16;
+      src = tb + (uint64_t)(2 * p) * plane_bytes + row * ROWB + swz<CPR>(row, pc) * 16;
       off = p * (kMI * ROWB) + rb * ROWB;
     } else {
       const int q2 = q - NTP * TREG;
       const int p = q2 / SREG, rb = (q2 % SREG) * RPR, row = rb + rl;
-      src = gb + (uint64_t)p * plane_bytes + at(j0 + rb) + rl * ROWB + swz<CPR>(row, pc) * 16;
+      src = sbp + (uint64_t)p * plane_bytes + row * ROWB + swz<CPR>(row, pc) * 16;
       off = NTP * kMI * ROWB + p * (kMJ * ROWB) + rb * ROWB;
     }
     dma_1k(src, stage_lds + off);
@@ -541,7 +537,7 @@ __device__ __forceinline__ void pair_block(const MArgs& a, int tb, int split, un
   issue_bias(a, sb_lds, jb0, wave, lane);
 #pragma unroll
   for (int p = 0; p < LA * SPB; ++p)
-    if (p < Q) issue_stage<ESZ, NTP, NSP>(gb, plane, nchunks, smem_lds + p * STAGE, p % nchunks, i0,
+    if (p < Q) issue_stage<ESZ, NTP, NSP>(gb, plane, n_pad, smem_lds + p * STAGE, p % nchunks, i0,
                                           jb0 + (int64_t)(p / nchunks) * kMJ, wave, lane);
 
   for (int t = 0; t < ntiles; ++t) {
@@ -560,7 +556,7 @@ __device__ __forceinline__ void pair_block(const MArgs& a, int tb, int split, un
         const int qn = q + LA * SPB + u;
         if (qn < Q) {
           const int tn = qn / nchunks;
-          issue_stage<ESZ, NTP, NSP>(gb, plane, nchunks, smem_lds + (qn % NS) * STAGE, qn - tn * nchunks, i0,
+          issue_stage<ESZ, NTP, NSP>(gb, plane, n_pad, smem_lds + (qn % NS) * STAGE, qn - tn * nchunks, i0,
                                      jb0 + (int64_t)tn * kMJ, wave, lane);
         }
       }

@@ -21,15 +21,8 @@ namespace yy {
 
 // ---------------------------------------------------------------------------
 // (1) node preparation: one wavefront per node.
-// Element (node i, coordinate k) of a matrix-core plane: planes are
-// [n_pad/128 row blocks][rp/16 chunks][128 rows][16], so a 128-node tile's
-// whole K range is contiguous.
-__device__ inline size_t plane_index(int64_t i, int32_t k, int32_t rp) {
-  return (((size_t)(i >> 7) * (size_t)(rp >> 4) + (size_t)(k >> 4)) * 128 + (size_t)(i & 127)) * 16 + (k & 15);
-}
-
-// Matrix-core planes follow plane_index (16 K values of 128 consecutive nodes
-// contiguous, a tile's K range contiguous); rows n..n_pad-1 are zero.
+// Matrix-core planes are tiled [plane][rp/16][n_pad][16] so that 16 K values
+// of consecutive nodes are contiguous; rows n..n_pad-1 are zero.
 __device__ __forceinline__ void k_prepare_body(int64_t n, int64_t n_pad, int32_t r, int32_t rp,
                                                     int32_t drift, const double* __restrict__ A,
                                                     const double* __restrict__ x,
@@ -45,7 +38,7 @@ __device__ __forceinline__ void k_prepare_body(int64_t n, int64_t n_pad, int32_t
   for (int64_t i = wave; i < n_pad; i += nwaves) {
     if (i >= n) {
       for (int32_t k = lane; k < rp; k += 64) {
-        const size_t t = plane_index(i, k, rp);
+        const size_t t = ((size_t)(k >> 4) * n_pad + i) * 16 + (k & 15);
         if (bf) bf[t] = bf[plane + t] = bf[2 * plane + t] = bf[3 * plane + t] = 0;
         if (f32t) f32t[t] = f32t[plane + t] = 0.f;
       }
@@ -79,7 +72,7 @@ __device__ __forceinline__ void k_prepare_body(int64_t n, int64_t n_pad, int32_t
       const size_t o = (size_t)i * rp + k;
       xc32[o] = xcv;
       f32[o] = fv;
-      const size_t t = plane_index(i, k, rp);
+      const size_t t = ((size_t)(k >> 4) * n_pad + i) * 16 + (k & 15);
       if (bf) {
         const uint16_t xh = f32_to_bf16(xcv);
         const uint16_t xl = f32_to_bf16((float)(xcd - (double)bf16_to_f32(xh)));
