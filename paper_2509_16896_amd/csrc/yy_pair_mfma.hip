@@ -32,10 +32,18 @@ typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16_t;
 constexpr int kMI = 256;   // targets per block
 constexpr int kMJ = 128;   // sources per tile
 constexpr int kKC = 16;    // K per LDS stage
-constexpr int kNT = 512;   // 8 waves (2 per SIMD): 4 along targets x 2 along sources
-constexpr int kWaves = kNT / 64;
-constexpr int kIB = 2;     // 32-wide target blocks per wave (64 targets)
-constexpr int kJB = 2;     // 32-wide source blocks per wave (64 sources)
+#ifndef YY_PAIR_WAVES
+#define YY_PAIR_WAVES 8
+#endif
+// Waves per block: 8 (2 per SIMD, 64 x 64 per wave) or 4 (1 per SIMD with the
+// whole register file, 64 targets x 128 sources per wave).
+constexpr int kWaves = YY_PAIR_WAVES;
+static_assert(kWaves == 8 || kWaves == 4, "8 or 4 waves per block");
+constexpr int kNT = 64 * kWaves;
+constexpr int kWI = 4;                     // waves along targets
+constexpr int kWJ = kWaves / kWI;          // waves along sources
+constexpr int kIB = kMI / (32 * kWI);      // 32-wide target blocks per wave (64 targets)
+constexpr int kJB = kMJ / (32 * kWJ);      // 32-wide source blocks per wave
 constexpr float kSkip = 64.f;     // depth (bits) below the running maximum at which terms are dropped
 
 struct MArgs {
@@ -158,15 +166,16 @@ __device__ inline void lse2_push(float& M, float& S, float v) {
 // The rare path of a slab that reaches within 2^-64 of the running maximum:
 // exponents within `margin` of the maximum are recomputed exactly, the others
 // are summed from their approximate values.  Out of line so that the hot
-// loop's register allocation does not carry it.  e: the 32 approximate
+// loop's register allocation does not carry it.  e: the 16 kJB approximate
 // exponents (self pair already -inf); returns the new (max, sum).
+constexpr int kSlab = 16 * kJB;
 __device__ __noinline__ float2 refine_slab(const Rare* rr, int64_t i, int64_t jbase, int g, int s,
                                            float margin, const float* e, float M, float S) {
   float m = -INFINITY;
-  for (int b = 0; b < 32; ++b) m = fmaxf(m, e[b]);
+  for (int b = 0; b < kSlab; ++b) m = fmaxf(m, e[b]);
   const float thr = fmaxf(M, m) - margin;
   float m2 = -INFINITY;
-  for (int b = 0; b < 32; ++b) {
+  for (int b = 0; b < kSlab; ++b) {
     if (e[b] >= thr) {
       const int jb = b >> 4, v = b & 15;
       const int64_t j = jbase + jb * 32 + 8 * (v >> 2) + 4 * g + (v & 3);
@@ -178,7 +187,7 @@ __device__ __noinline__ float2 refine_slab(const Rare* rr, int64_t i, int64_t jb
   const float Mn = fmaxf(M, m2);
   if (Mn == -INFINITY) return make_float2(M, S);
   float sum = S * fast_exp2(M - Mn);
-  for (int b = 0; b < 32; ++b)
+  for (int b = 0; b < kSlab; ++b)
     if (e[b] < thr) sum += fast_exp2(e[b] - Mn);
   return make_float2(Mn, sum);
 }
@@ -189,7 +198,7 @@ __device__ inline void epilogue_target(const MArgs& a, const Rare* rare, const f
                                        int jl0, int g, bool diag, const float (&at)[S],
                                        const float (&margin)[S], float (&M)[S], float (&Ssum)[S]) {
   // The self pair (source j = i) is accounted for at initialisation; this
-  // lane holds it iff d = i - j0 - jl0 is in [0, 64) with bit 2 equal to g.
+  // lane holds it iff d = i - j0 - jl0 is in [0, 32 kJB) with bit 2 equal to g.
   const int64_t d = i - j0 - jl0;
   const bool self = diag && d >= 0 && d < 32 * kJB && (int)((d >> 2) & 1) == g;
   const int dself = (int)d;
@@ -209,7 +218,7 @@ __device__ inline void epilogue_target(const MArgs& a, const Rare* rare, const f
     // Every exact exponent of the slab is at most m + (margin - kSkip - 16): below
     // 2^-(kSkip+16) of the running maximum unless m > M - margin.
     if (!(m > M[s] - margin[s])) continue;
-    float e[32];
+    float e[kSlab];
 #pragma unroll
     for (int jb = 0; jb < kJB; ++jb)
 #pragma unroll
@@ -225,13 +234,14 @@ __device__ inline void epilogue_target(const MArgs& a, const Rare* rare, const f
   }
 }
 
-// Final merge: lanes l and l^32 hold the same target; waves (wi, 0) and
-// (wi, 1) hold the same targets.  Writes part[split][s][i].
+// Final merge: lanes l and l^32 hold the same target; with two waves along
+// the sources, waves (wi, 0) and (wi, 1) hold the same targets.  Writes
+// part[split][s][i].
 template <int S>
 __device__ inline void merge_and_store(const MArgs& a, float (&M)[kIB][S], float (&Ssum)[kIB][S],
                                        int64_t i0, int split, float2* xchg) {
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int wi = wave >> 1, wj = wave & 1, col = lane & 31, g = lane >> 5;
+  const int wi = wave / kWJ, wj = wave % kWJ, col = lane & 31, g = lane >> 5;
 #pragma unroll
   for (int ib = 0; ib < kIB; ++ib)
 #pragma unroll
@@ -240,23 +250,27 @@ __device__ inline void merge_and_store(const MArgs& a, float (&M)[kIB][S], float
       const float so = __shfl_xor(Ssum[ib][s], 32, 64);
       lse2_merge(M[ib][s], Ssum[ib][s], mo, so);
     }
-  __syncthreads();
-  if (wj == 1 && g == 0) {
+  if (kWJ == 2) {
+    __syncthreads();
+    if (wj == 1 && g == 0) {
 #pragma unroll
-    for (int ib = 0; ib < kIB; ++ib)
+      for (int ib = 0; ib < kIB; ++ib)
 #pragma unroll
-      for (int s = 0; s < S; ++s)
-        xchg[((wi * kIB + ib) * 32 + col) * S + s] = make_float2(M[ib][s], Ssum[ib][s]);
+        for (int s = 0; s < S; ++s)
+          xchg[((wi * kIB + ib) * 32 + col) * S + s] = make_float2(M[ib][s], Ssum[ib][s]);
+    }
+    __syncthreads();
   }
-  __syncthreads();
   if (wj == 0 && g == 0) {
 #pragma unroll
     for (int ib = 0; ib < kIB; ++ib) {
       const int64_t i = i0 + wi * (32 * kIB) + ib * 32 + col;
 #pragma unroll
       for (int s = 0; s < S; ++s) {
-        const float2 o = xchg[((wi * kIB + ib) * 32 + col) * S + s];
-        lse2_merge(M[ib][s], Ssum[ib][s], o.x, o.y);
+        if (kWJ == 2) {
+          const float2 o = xchg[((wi * kIB + ib) * 32 + col) * S + s];
+          lse2_merge(M[ib][s], Ssum[ib][s], o.x, o.y);
+        }
         if (i < a.n) a.part[((size_t)split * S + s) * a.n + i] = make_float2(M[ib][s], Ssum[ib][s]);
       }
     }
@@ -270,7 +284,7 @@ template <int S>
 __device__ inline void init_targets(const MArgs& a, int64_t i0, int split, float (&at)[kIB][S],
                                     float (&M)[kIB][S], float (&Ssum)[kIB][S], float (&margin)[S]) {
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int wi = wave >> 1, wj = wave & 1, col = lane & 31, g = lane >> 5;
+  const int wi = wave / kWJ, wj = wave % kWJ, col = lane & 31, g = lane >> 5;
   const double X = a.scal[1], F = a.scal[2];
   const double gam = a.rp * 0x1p-24;
 #pragma unroll
@@ -397,17 +411,27 @@ __device__ inline void zero_acc(f32x16_t (&G)[kIB][kJB], f32x16_t (&H)[kIB][kJB]
       }
 }
 
-// One K stage of the products on the matrix cores.  PASSES: 3 = split G and H,
-// 2 = split G with H hi*hi, 1 = hi*hi only.
+// One K stage of the products on the matrix cores, in two halves: the
+// fragment reads from LDS (into a Frag) and the matrix-core burst, so that the
+// reads of the next stage can be issued ahead of the current burst.  PASSES:
+// 3 = split G and H, 2 = split G with H hi*hi, 1 = hi*hi only.
+struct Frag {
+  bf16x8_t bh[kIB], bl[kIB], xh[kJB], xl[kJB], fh[kJB], fl[kJB];
+};
+
 template <int PASSES>
-__device__ inline void mfma_stage_bf16(const unsigned char* base, f32x16_t (&G)[kIB][kJB],
-                                       f32x16_t (&H)[kIB][kJB]) {
+__device__ inline void load_frags(const unsigned char* base, Frag& f) {
   constexpr int ROWB = 32;
   constexpr int NTP = PASSES >= 2 ? 2 : 1;
   constexpr int TB = NTP * kMI * ROWB;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int wi = wave >> 1, wj = wave & 1, col = lane & 31, g = lane >> 5;
-  bf16x8_t bh[kIB], bl[kIB], xh[kJB], xl[kJB], fh[kJB], fl[kJB];
+  const int wi = wave / kWJ, wj = wave % kWJ, col = lane & 31, g = lane >> 5;
+  bf16x8_t(&bh)[kIB] = f.bh;
+  bf16x8_t(&bl)[kIB] = f.bl;
+  bf16x8_t(&xh)[kJB] = f.xh;
+  bf16x8_t(&xl)[kJB] = f.xl;
+  bf16x8_t(&fh)[kJB] = f.fh;
+  bf16x8_t(&fl)[kJB] = f.fl;
 #pragma unroll
   for (int ib = 0; ib < kIB; ++ib) {
     const int row = wi * (32 * kIB) + ib * 32 + col;
@@ -424,8 +448,16 @@ __device__ inline void mfma_stage_bf16(const unsigned char* base, f32x16_t (&G)[
     if (PASSES >= 2) xl[jb] = *reinterpret_cast<const bf16x8_t*>(base + 2 * kMJ * ROWB + off);
     if (PASSES == 3) fl[jb] = *reinterpret_cast<const bf16x8_t*>(base + 3 * kMJ * ROWB + off);
   }
-  // all fragment reads of the stage are issued before its matrix-core burst
-  __builtin_amdgcn_sched_barrier(0);
+}
+
+template <int PASSES>
+__device__ inline void mma_frags(const Frag& f, f32x16_t (&G)[kIB][kJB], f32x16_t (&H)[kIB][kJB]) {
+  const bf16x8_t(&bh)[kIB] = f.bh;
+  const bf16x8_t(&bl)[kIB] = f.bl;
+  const bf16x8_t(&xh)[kJB] = f.xh;
+  const bf16x8_t(&xl)[kJB] = f.xl;
+  const bf16x8_t(&fh)[kJB] = f.fh;
+  const bf16x8_t(&fl)[kJB] = f.fl;
 #pragma unroll
   for (int ib = 0; ib < kIB; ++ib)
 #pragma unroll
@@ -441,7 +473,6 @@ __device__ inline void mfma_stage_bf16(const unsigned char* base, f32x16_t (&G)[
         H[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fh[jb], bl[ib], H[ib][jb], 0, 0, 0);
       }
     }
-  __builtin_amdgcn_sched_barrier(0);
 }
 
 // FP32: within a 16-wide K stage, lane group g owns k = 8 g + t in K step t
@@ -452,7 +483,7 @@ __device__ inline void mfma_stage_f32(const unsigned char* base, f32x16_t (&G)[k
   constexpr int ROWB = 64;
   constexpr int TB = kMI * ROWB;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int wi = wave >> 1, wj = wave & 1, col = lane & 31, g = lane >> 5;
+  const int wi = wave / kWJ, wj = wave % kWJ, col = lane & 31, g = lane >> 5;
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
     const int lc = 2 * g + u;
@@ -514,7 +545,7 @@ __device__ __forceinline__ void pair_block(const MArgs& a, int tb, int split, un
   static_assert(LA == 1 || L * kWaves * 1024 == STAGE, "deep lookahead needs equal copies per wave");
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int wi = wave >> 1, wj = wave & 1, col = lane & 31, g = lane >> 5;
+  const int wi = wave / kWJ, wj = wave % kWJ, col = lane & 31, g = lane >> 5;
   if (tid == 0) fill_rare(a, rare);
   const int64_t i0 = (int64_t)tb * kMI;
   const int64_t jb0 = (int64_t)split * a.j_per_split;
@@ -560,11 +591,18 @@ __device__ __forceinline__ void pair_block(const MArgs& a, int tb, int split, un
                                      jb0 + (int64_t)tn * kMJ, wave, lane);
         }
       }
+      if (VAR == 0) {
 #pragma unroll
-      for (int u = 0; u < SPB; ++u) {
-        const unsigned char* base = smem + ((q + u) % NS) * STAGE;
-        if (VAR == 0) mfma_stage_f32(base, G, H);
-        else mfma_stage_bf16<VAR>(base, G, H);
+        for (int u = 0; u < SPB; ++u) mfma_stage_f32(smem + ((q + u) % NS) * STAGE, G, H);
+      } else {
+        // fragments of stage u + 1 are read while the burst of stage u runs
+        Frag fr[2];
+        load_frags<VAR>(smem + (q % NS) * STAGE, fr[0]);
+#pragma unroll
+        for (int u = 0; u < SPB; ++u) {
+          if (u + 1 < SPB) load_frags<VAR>(smem + ((q + u + 1) % NS) * STAGE, fr[(u + 1) & 1]);
+          mma_frags<VAR>(fr[u & 1], G, H);
+        }
       }
     }
     const bool diag = j0 < i0 + kMI && i0 < j0 + kMJ;
