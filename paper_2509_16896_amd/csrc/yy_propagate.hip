@@ -30,7 +30,8 @@ __device__ __forceinline__ void k_prepare_body(int64_t n, int64_t n_pad, int32_t
                                                     const double* __restrict__ hi,
                                                     float* __restrict__ xc32, float* __restrict__ f32,
                                                     uint16_t* __restrict__ bf, float* __restrict__ f32t,
-                                                    double* __restrict__ node, int* __restrict__ bnd, int bx_, int gx_) {
+                                                    double* __restrict__ node, int* __restrict__ bnd,
+                                                    int bx_, int gx_) {
   const int lane = threadIdx.x & 63;
   const int64_t wave = ((int64_t)bx_ * blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gx_ * blockDim.x) >> 6;
@@ -112,11 +113,13 @@ __global__ void __launch_bounds__(kBlock) k_prepare(int64_t n, int64_t n_pad, in
   k_prepare_body(n, n_pad, r, rp, drift, A, x, lo, hi, xc32, f32, bf, f32t, node, bnd, blockIdx.x, gridDim.x);
 }
 
-__global__ void __launch_bounds__(kBlock) k_prepare_batch(const prepare_args* __restrict__ A, const int* __restrict__ pre, int nr) {
+__global__ void __launch_bounds__(kBlock) k_prepare_batch(const prepare_args* __restrict__ A,
+                                                          const int* __restrict__ pre, int nr) {
   const int q = batch_find(pre, nr, blockIdx.x);
   const prepare_args& a = A[q];
   if (a.pred && *a.pred == 0) return;
-  k_prepare_body(a.n, a.n_pad, a.r, a.rp, a.drift, a.A, a.x, a.lo, a.hi, a.xc32, a.f32, a.bf, a.f32t, a.node, a.bnd, blockIdx.x - pre[q], pre[q + 1] - pre[q]);
+  k_prepare_body(a.n, a.n_pad, a.r, a.rp, a.drift, a.A, a.x, a.lo, a.hi, a.xc32, a.f32, a.bf, a.f32t, a.node, a.bnd,
+                 blockIdx.x - pre[q], pre[q + 1] - pre[q]);
 }
 
 
@@ -153,7 +156,8 @@ __global__ void __launch_bounds__(kBlock) k_prepare_scalars(int64_t n, int32_t r
   k_prepare_scalars_body(n, r, lo, hi, node, scal, blockIdx.x, gridDim.x);
 }
 
-__global__ void __launch_bounds__(kBlock) k_prepare_scalars_batch(const prepare_scalars_args* __restrict__ A, const int* __restrict__ pre, int nr) {
+__global__ void __launch_bounds__(kBlock) k_prepare_scalars_batch(const prepare_scalars_args* __restrict__ A,
+                                                                  const int* __restrict__ pre, int nr) {
   const int q = batch_find(pre, nr, blockIdx.x);
   const prepare_scalars_args& a = A[q];
   if (a.pred && *a.pred == 0) return;
@@ -182,7 +186,8 @@ __global__ void __launch_bounds__(kBlock) k_lw_max(int64_t n, const double* __re
   k_lw_max_body(n, lw, bnd, part, blockIdx.x, gridDim.x);
 }
 
-__global__ void __launch_bounds__(kBlock) k_lw_max_batch(const lw_max_args* __restrict__ A, const int* __restrict__ pre, int nr) {
+__global__ void __launch_bounds__(kBlock) k_lw_max_batch(const lw_max_args* __restrict__ A,
+                                                         const int* __restrict__ pre, int nr) {
   const int q = batch_find(pre, nr, blockIdx.x);
   const lw_max_args& a = A[q];
   if (a.pred && *a.pred == 0) return;
@@ -216,7 +221,8 @@ __global__ void __launch_bounds__(kBlock) k_lw_convert(int64_t n, int nparts,
   k_lw_convert_body(n, nparts, part, lw, bnd, lw2, ref_out, blockIdx.x, gridDim.x);
 }
 
-__global__ void __launch_bounds__(kBlock) k_lw_convert_batch(const lw_convert_args* __restrict__ A, const int* __restrict__ pre, int nr) {
+__global__ void __launch_bounds__(kBlock) k_lw_convert_batch(const lw_convert_args* __restrict__ A,
+                                                             const int* __restrict__ pre, int nr) {
   const int q = batch_find(pre, nr, blockIdx.x);
   const lw_convert_args& a = A[q];
   if (a.pred && *a.pred == 0) return;
@@ -457,7 +463,8 @@ __global__ void __launch_bounds__(kBlock) k_combine(CombineArgs a) {
   k_combine_body(a, blockIdx.x, gridDim.x);
 }
 
-__global__ void __launch_bounds__(kBlock) k_combine_batch(const combine_args* __restrict__ A, const int* __restrict__ pre, int nr) {
+__global__ void __launch_bounds__(kBlock) k_combine_batch(const combine_args* __restrict__ A,
+                                                          const int* __restrict__ pre, int nr) {
   const int q = batch_find(pre, nr, blockIdx.x);
   const combine_args& a = A[q];
   if (a.pred && *a.pred == 0) return;

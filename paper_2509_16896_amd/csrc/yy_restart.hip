@@ -61,7 +61,8 @@ __global__ void __launch_bounds__(kBlock) k_rs_local(int64_t n, const double* __
   k_rs_local_body(n, w, C, tot, blockIdx.x, gridDim.x);
 }
 
-__global__ void __launch_bounds__(kBlock) k_rs_local_batch(const rs_local_args* __restrict__ A, const int* __restrict__ pre, int nr) {
+__global__ void __launch_bounds__(kBlock) k_rs_local_batch(const rs_local_args* __restrict__ A,
+                                                           const int* __restrict__ pre, int nr) {
   const int q = batch_find(pre, nr, blockIdx.x);
   const rs_local_args& a = A[q];
   if (a.pred && *a.pred == 0) return;
@@ -85,7 +86,8 @@ __global__ void __launch_bounds__(kBlock) k_rs_offsets(int nb, unsigned long lon
   k_rs_offsets_body(nb, tot, blockIdx.x, gridDim.x);
 }
 
-__global__ void __launch_bounds__(kBlock) k_rs_offsets_batch(const rs_offsets_args* __restrict__ A, const int* __restrict__ pre, int nr) {
+__global__ void __launch_bounds__(kBlock) k_rs_offsets_batch(const rs_offsets_args* __restrict__ A,
+                                                             const int* __restrict__ pre, int nr) {
   const int q = batch_find(pre, nr, blockIdx.x);
   const rs_offsets_args& a = A[q];
   if (a.pred && *a.pred == 0) return;
@@ -104,7 +106,8 @@ __global__ void __launch_bounds__(kBlock) k_rs_add(int64_t n, const unsigned lon
   k_rs_add_body(n, tot, C, blockIdx.x, gridDim.x);
 }
 
-__global__ void __launch_bounds__(kBlock) k_rs_add_batch(const rs_add_args* __restrict__ A, const int* __restrict__ pre, int nr) {
+__global__ void __launch_bounds__(kBlock) k_rs_add_batch(const rs_add_args* __restrict__ A,
+                                                         const int* __restrict__ pre, int nr) {
   const int q = batch_find(pre, nr, blockIdx.x);
   const rs_add_args& a = A[q];
   if (a.pred && *a.pred == 0) return;
@@ -161,7 +164,8 @@ __global__ void __launch_bounds__(kBlock) k_rs_search(int64_t n, int nb,
   k_rs_search_body(n, nb, tot, C, U, idx, flags, blockIdx.x, gridDim.x);
 }
 
-__global__ void __launch_bounds__(kBlock) k_rs_search_batch(const rs_search_args* __restrict__ A, const int* __restrict__ pre, int nr) {
+__global__ void __launch_bounds__(kBlock) k_rs_search_batch(const rs_search_args* __restrict__ A,
+                                                            const int* __restrict__ pre, int nr) {
   const int q = batch_find(pre, nr, blockIdx.x);
   const rs_search_args& a = A[q];
   if (a.pred && *a.pred == 0) return;
@@ -172,7 +176,8 @@ __global__ void __launch_bounds__(kBlock) k_rs_search_batch(const rs_search_args
 
 // The plain box [mean - R, mean + R]^r.
 __device__ __forceinline__ void k_box_plain_body(int32_t r, double R, const double* __restrict__ mean,
-                                                      double* __restrict__ box_lo, double* __restrict__ box_hi, int bx_, int gx_) {
+                                                      double* __restrict__ box_lo,
+                                                      double* __restrict__ box_hi, int bx_, int gx_) {
   const int d = bx_ * kBlock + threadIdx.x;
   if (d >= r) return;
   box_lo[d] = __dsub_rn(mean[d], R);
@@ -184,7 +189,8 @@ __global__ void __launch_bounds__(kBlock) k_box_plain(int32_t r, double R, const
   k_box_plain_body(r, R, mean, box_lo, box_hi, blockIdx.x, gridDim.x);
 }
 
-__global__ void __launch_bounds__(kBlock) k_box_plain_batch(const box_plain_args* __restrict__ A, const int* __restrict__ pre, int nr) {
+__global__ void __launch_bounds__(kBlock) k_box_plain_batch(const box_plain_args* __restrict__ A,
+                                                            const int* __restrict__ pre, int nr) {
   const int q = batch_find(pre, nr, blockIdx.x);
   const box_plain_args& a = A[q];
   if (a.pred && *a.pred == 0) return;
@@ -239,23 +245,28 @@ __global__ void __launch_bounds__(kBlock) k_restart_nodes(int64_t n, int32_t r, 
   k_restart_nodes_body(n, r, codes, mean, box_lo, box_hi, only_if, x_new, logw_new, blockIdx.x, gridDim.x);
 }
 
-__global__ void __launch_bounds__(kBlock) k_restart_nodes_batch(const restart_nodes_args* __restrict__ A, const int* __restrict__ pre, int nr) {
+__global__ void __launch_bounds__(kBlock) k_restart_nodes_batch(const restart_nodes_args* __restrict__ A,
+                                                                const int* __restrict__ pre, int nr) {
   const int q = batch_find(pre, nr, blockIdx.x);
   const restart_nodes_args& a = A[q];
   if (a.pred && *a.pred == 0) return;
-  k_restart_nodes_body(a.n, a.r, a.codes, a.mean, a.box_lo, a.box_hi, a.only_if, a.x_new, a.logw_new, blockIdx.x - pre[q], pre[q + 1] - pre[q]);
+  k_restart_nodes_body(a.n, a.r, a.codes, a.mean, a.box_lo, a.box_hi, a.only_if, a.x_new, a.logw_new,
+                       blockIdx.x - pre[q], pre[q + 1] - pre[q]);
 }
 
 
-__device__ __forceinline__ void k_ess_check_body(const double* __restrict__ ess, double ess_min, uint32_t* __restrict__ flags, int bx_, int gx_) {
+__device__ __forceinline__ void k_ess_check_body(const double* __restrict__ ess, double ess_min,
+                                                 uint32_t* __restrict__ flags, int bx_, int gx_) {
   if (threadIdx.x == 0 && bx_ == 0 && *ess < ess_min) atomicOr(flags, YY_FLAG_LOW_ESS);
 }
 
-__global__ void __launch_bounds__(kBlock) k_ess_check(const double* __restrict__ ess, double ess_min, uint32_t* __restrict__ flags) {
+__global__ void __launch_bounds__(kBlock) k_ess_check(const double* __restrict__ ess, double ess_min,
+                                                      uint32_t* __restrict__ flags) {
   k_ess_check_body(ess, ess_min, flags, blockIdx.x, gridDim.x);
 }
 
-__global__ void __launch_bounds__(kBlock) k_ess_check_batch(const ess_check_args* __restrict__ A, const int* __restrict__ pre, int nr) {
+__global__ void __launch_bounds__(kBlock) k_ess_check_batch(const ess_check_args* __restrict__ A,
+                                                            const int* __restrict__ pre, int nr) {
   const int q = batch_find(pre, nr, blockIdx.x);
   const ess_check_args& a = A[q];
   if (a.pred && *a.pred == 0) return;

@@ -55,7 +55,8 @@ __global__ void __launch_bounds__(kBlock) k_loglik(int64_t n, int32_t r, int32_t
   k_loglik_body(n, r, m, obs, H, h_shift, x, dy, dt, rho2, logw, blockIdx.x, gridDim.x);
 }
 
-__global__ void __launch_bounds__(kBlock) k_loglik_batch(const loglik_args* __restrict__ A, const int* __restrict__ pre, int nr) {
+__global__ void __launch_bounds__(kBlock) k_loglik_batch(const loglik_args* __restrict__ A,
+                                                         const int* __restrict__ pre, int nr) {
   const int q = batch_find(pre, nr, blockIdx.x);
   const loglik_args& a = A[q];
   if (a.pred && *a.pred == 0) return;
@@ -82,7 +83,8 @@ __global__ void __launch_bounds__(kBlock) k_norm_max(int64_t n, const double* __
   k_norm_max_body(n, lw, pmax, blockIdx.x, gridDim.x);
 }
 
-__global__ void __launch_bounds__(kBlock) k_norm_max_batch(const norm_max_args* __restrict__ A, const int* __restrict__ pre, int nr) {
+__global__ void __launch_bounds__(kBlock) k_norm_max_batch(const norm_max_args* __restrict__ A,
+                                                           const int* __restrict__ pre, int nr) {
   const int q = batch_find(pre, nr, blockIdx.x);
   const norm_max_args& a = A[q];
   if (a.pred && *a.pred == 0) return;
@@ -113,7 +115,8 @@ __global__ void __launch_bounds__(kBlock) k_norm_sumexp(int64_t n, int nb,
   k_norm_sumexp_body(n, nb, pmax, lw, psum, blockIdx.x, gridDim.x);
 }
 
-__global__ void __launch_bounds__(kBlock) k_norm_sumexp_batch(const norm_sumexp_args* __restrict__ A, const int* __restrict__ pre, int nr) {
+__global__ void __launch_bounds__(kBlock) k_norm_sumexp_batch(const norm_sumexp_args* __restrict__ A,
+                                                              const int* __restrict__ pre, int nr) {
   const int q = batch_find(pre, nr, blockIdx.x);
   const norm_sumexp_args& a = A[q];
   if (a.pred && *a.pred == 0) return;
@@ -159,11 +162,13 @@ __global__ void __launch_bounds__(kBlock) k_norm_logz(int nb, const double* __re
   k_norm_logz_body(nb, pmax, psum, sc, logZ_step, logZ_acc, flags, blockIdx.x, gridDim.x);
 }
 
-__global__ void __launch_bounds__(kBlock) k_norm_logz_batch(const norm_logz_args* __restrict__ A, const int* __restrict__ pre, int nr) {
+__global__ void __launch_bounds__(kBlock) k_norm_logz_batch(const norm_logz_args* __restrict__ A,
+                                                            const int* __restrict__ pre, int nr) {
   const int q = batch_find(pre, nr, blockIdx.x);
   const norm_logz_args& a = A[q];
   if (a.pred && *a.pred == 0) return;
-  k_norm_logz_body(a.nb, a.pmax, a.psum, a.sc, a.logZ_step, a.logZ_acc, a.flags, blockIdx.x - pre[q], pre[q + 1] - pre[q]);
+  k_norm_logz_body(a.nb, a.pmax, a.psum, a.sc, a.logZ_step, a.logZ_acc, a.flags, blockIdx.x - pre[q],
+                   pre[q + 1] - pre[q]);
 }
 
 
@@ -232,7 +237,8 @@ __global__ void __launch_bounds__(kBlock) k_norm_weights(int64_t n, int32_t r, i
   k_norm_weights_body(n, r, rows, sc, x, lw, w, pw2, pmean, blockIdx.x, gridDim.x);
 }
 
-__global__ void __launch_bounds__(kBlock) k_norm_weights_batch(const norm_weights_args* __restrict__ A, const int* __restrict__ pre, int nr) {
+__global__ void __launch_bounds__(kBlock) k_norm_weights_batch(const norm_weights_args* __restrict__ A,
+                                                               const int* __restrict__ pre, int nr) {
   const int q = batch_find(pre, nr, blockIdx.x);
   const norm_weights_args& a = A[q];
   if (a.pred && *a.pred == 0) return;
@@ -267,7 +273,8 @@ __global__ void __launch_bounds__(kBlock) k_norm_final(int nb, int32_t r, const 
   k_norm_final_body(nb, r, sc, pw2, pmean, mean, ess, blockIdx.x, gridDim.x);
 }
 
-__global__ void __launch_bounds__(kBlock) k_norm_final_batch(const norm_final_args* __restrict__ A, const int* __restrict__ pre, int nr) {
+__global__ void __launch_bounds__(kBlock) k_norm_final_batch(const norm_final_args* __restrict__ A,
+                                                             const int* __restrict__ pre, int nr) {
   const int q = batch_find(pre, nr, blockIdx.x);
   const norm_final_args& a = A[q];
   if (a.pred && *a.pred == 0) return;
