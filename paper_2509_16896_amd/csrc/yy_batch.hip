@@ -239,7 +239,7 @@ static yy_status build(yy_batch b) {
                               R.plan)) != YY_OK)
       return st;
     // scratch of the steps that propagate_begin does not size
-    const int nbn = (int)std::min<int64_t>(nblk(R.d.n), 256);
+    const int nbn = norm_blocks(R.d.n);
     if ((st = R.rc->red2.ensure(((size_t)nbn * (3 + (size_t)R.d.model.r) + 4) * sizeof(double))) != YY_OK) return st;
     if ((st = R.rc->scan.ensure(((size_t)R.d.n + nblk(R.d.n) + 1) * sizeof(unsigned long long))) != YY_OK) return st;
   }
@@ -316,7 +316,7 @@ static yy_status build(yy_batch b) {
       int64_t nb_nodes = blocks;
       if (nb_nodes * kBlock < r) nb_nodes = nblk(r);
       b_nodes.push_back((int)nb_nodes);
-      const int nb = (int)std::min<int64_t>(nblk(n), 256);
+      const int nb = norm_blocks(n);
       const int64_t rows = (n + nb - 1) / nb;
       double* pmax = R.rc->red2.as<double>();
       double* psum = pmax + nb;
@@ -566,7 +566,7 @@ extern "C" yy_status yy_tune(yy_ctx ctx, int32_t count, const int32_t* r, const 
       }
     }
     if (st == YY_OK) {
-      tune_store(ctx, pair_mfma_rp(r[t]), pair_mfma_npad(n[t]), scales->S, prec, best);
+      tune_store(ctx, pair_mfma_rp(r[t], prec), pair_mfma_npad(n[t]), scales->S, prec, best);
       if (nsplit_out) nsplit_out[t] = best;
     }
     (void)hipStreamSynchronize(ctx->stream);

@@ -120,7 +120,7 @@ namespace yy {
 yy_status sobol_prepare_dirs(yy_ctx ctx, int32_t r, int32_t scramble, uint64_t seed);
 yy_status prepare_nodes(yy_ctx ctx, const yy_model* model, int64_t n, const double* x,
                         uint64_t version, const double* lo, const double* hi, bool want_bf16,
-                        bool want_f32t);
+                        bool want_f32t, int32_t prec);
 yy_status coefficients_cramer(int32_t S, const double* s, double* c);
 yy_status validate_model(const yy_model* m);
 yy_status timing_begin(yy_ctx ctx);
@@ -199,10 +199,14 @@ yy_status propagate_begin(yy_ctx ctx, const yy_model* model, const yy_scales* sc
 yy_status propagate_pair(yy_ctx ctx, const PropPlan& plan);
 yy_status propagate_end(yy_ctx ctx, const PropPlan& plan);
 
+// Blocks of the normalisation kernels for n nodes (64 rows per block, at most
+// 1024 blocks): enough blocks to stream the n x r coordinates at full bandwidth.
+inline int norm_blocks(int64_t n) { return (int)((n + 63) / 64 < 1024 ? (n + 63) / 64 : 1024); }
+
 // Tuned source-split counts of the matrix-core kernel (yy_tune), 0 if none.
 int tune_lookup(yy_ctx ctx, int32_t rp, int64_t n_pad, int32_t S, int32_t prec);
 int64_t pair_mfma_npad(int64_t n);
-int pair_mfma_rp(int32_t r);
+int pair_mfma_rp(int32_t r, int32_t prec);
 
 // Learned restart box (yy_proposal.hip): prepare writes the box chosen by the
 // coverage and log-density checks and the decision words dec[0..2]; finish

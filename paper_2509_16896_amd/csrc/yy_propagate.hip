@@ -473,17 +473,23 @@ __global__ void __launch_bounds__(kBlock) k_combine_batch(const combine_args* __
 
 
 // ---------------------------------------------------------------------------
-int pair_mfma_rp(int32_t r) { return ((r + 63) / 64) * 64; }
+// K of the prepared node set: r zero-padded to whole groups of 16-wide K
+// stages of the pairwise kernel (2 stages per barrier; 4 for BF16X1 and the
+// vector-ALU form).
+int pair_mfma_rp(int32_t r, int32_t prec) {
+  const int q = (prec == YY_PREC_BF16X1 || prec == YY_PREC_FP32) ? 64 : 32;
+  return ((r + q - 1) / q) * q;
+}
 
 yy_status prepare_nodes(yy_ctx ctx, const yy_model* m, int64_t n, const double* x,
                         uint64_t version, const double* lo, const double* hi, bool want_bf16,
-                        bool want_f32t) {
+                        bool want_f32t, int32_t prec) {
   Prepared& P = ctx->prep;
-  const bool same = P.valid && P.x == x && P.n == n && P.r == m->r && P.drift == m->drift &&
+  const int32_t rp = pair_mfma_rp(m->r, prec);
+  const bool same = P.valid && P.x == x && P.n == n && P.r == m->r && P.rp == rp && P.drift == m->drift &&
                     P.A == m->A && P.version == version && P.lo == lo && P.hi == hi &&
                     (P.have_bf16 || !want_bf16) && (P.have_f32t || !want_f32t);
   if (same) return YY_OK;
-  const int32_t rp = pair_mfma_rp(m->r);
   const int64_t n_pad = pair_mfma_npad(n);
   yy_status st;
   if ((st = P.xc32.ensure((size_t)n * rp * sizeof(float))) != YY_OK) return st;
@@ -614,7 +620,7 @@ yy_status propagate_begin(yy_ctx ctx, const yy_model* model, const yy_scales* sc
   YY_HIP(hipSetDevice(ctx->device));
   st = prepare_nodes(ctx, model, n, x, node_version, box_lo, box_hi,
                      prec == YY_PREC_BF16X3 || prec == YY_PREC_BF16X3G || prec == YY_PREC_BF16X1,
-                     prec == YY_PREC_FP32_MFMA);
+                     prec == YY_PREC_FP32_MFMA, prec);
   if (st != YY_OK) return st;
   const Prepared& P = ctx->prep;
 

@@ -410,7 +410,7 @@ extern "C" yy_status yy_normalise_moments(yy_ctx ctx, int64_t n, int32_t r, cons
   if (!x || !logw || !logZ_step || !logZ_acc || !mean || !ess)
     return fail(YY_ERR_ARG, "yy_normalise_moments: NULL array");
   YY_HIP(hipSetDevice(ctx->device));
-  const int nb = (int)std::min<int64_t>((n + kBlock - 1) / kBlock, 256);
+  const int nb = norm_blocks(n);
   const int64_t rows = (n + nb - 1) / nb;
   const size_t need = (size_t)nb * (3 + (size_t)r) + 4 + (cov && !w ? (size_t)n : 0);
   yy_status st = ctx->red2.ensure(need * sizeof(double));
