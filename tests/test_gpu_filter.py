@@ -25,6 +25,8 @@ def _run_gpu(w, dys, prec):
 
 CASES = {
     "cubic_r2_n1024_K20": (W.shrink(W.cubic_r2(), K=20), "fp32"),
+    # the plain cubic-sensor configuration in full: r=2, n=1024 on [-4,4]^2, 100 steps, scales {1,2}
+    "cubic_r2_n1024_K100_full": (W.cubic_r2(), "fp32"),
     "linear_r10_n2048_K10_restart": (W.shrink(W.linear_r10(), n=2048, K=10), "fp32"),
     "cubic_r20_n1024_K6_restart_s124": (W.shrink(W.cubic_r100(), r=20, n=1024, K=6), "fp32"),
 }

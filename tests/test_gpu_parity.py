@@ -234,6 +234,16 @@ MFMA_CASES = {
                                  seed=16, lw_kind="sparse"),
     "cos_r64_n512_unscrambled_boundary": dict(r=64, n=512, drift=oracle.F_COS, scales=(1.0, 2.0, 4.0), q=0.09,
                                               dt=0.005, half=0.3, seed=17, scramble=False),
+    # edges: r = 1 (K padded from 1), r at the K padding boundaries, the largest r, four scales, two nodes
+    "cos_r1_n300_s12_dense": dict(r=1, n=300, drift=oracle.F_COS, scales=(1.0, 2.0), q=1.0, dt=0.02, half=2.0,
+                                  seed=19),
+    "cos_r31_n400_s124": dict(r=31, n=400, drift=oracle.F_COS, scales=(1.0, 2.0, 4.0), q=0.3, dt=0.02, half=0.5,
+                              seed=20),
+    "cos_r65_n300_s1248": dict(r=65, n=300, drift=oracle.F_COS, scales=(1.0, 2.0, 4.0, 8.0), q=0.2, dt=0.02,
+                               half=0.4, seed=21),
+    "cos_r3600_n160_s12_max_r": dict(r=3600, n=160, drift=oracle.F_COS, scales=(1.0, 2.0), q=0.09, dt=0.005,
+                                     half=0.05, seed=22),
+    "zero_r96_n2_s1": dict(r=96, n=2, drift=oracle.F_ZERO, scales=(1.0,), q=1.0, dt=0.05, half=0.5, seed=23),
 }
 
 
@@ -257,3 +267,25 @@ def test_propagate_mfma_parity(ctx, name, prec):
     f = np.isfinite(plain)
     assert np.array_equal(np.isfinite(got), f)
     assert np.max(np.abs(got[f] - plain[f]) / np.maximum(1.0, np.abs(plain[f]))) < 2e-6
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp32_mfma", "bf16x3", "bf16x3g", "bf16x1"])
+def test_propagate_single_node_raw_value(ctx, prec):
+    """One node: the only source is the target itself, so the raw (unnormalised) value is
+    the signed combination of the self-pair Gaussian densities -- constants included."""
+    for r in (1, 40, 200):
+        case = _prop_case(r, 1, oracle.F_COS, (1.0, 2.0, 4.0), 0.09, 0.005, 0.3, 30 + r)
+        got = _gpu_prop(ctx, case, prec)
+        ref = case["ref"]
+        assert np.isfinite(ref[0]) == np.isfinite(got[0])
+        if np.isfinite(ref[0]):
+            assert abs(got[0] - ref[0]) <= 1e-5 * max(1.0, abs(ref[0])), (r, got[0], ref[0])
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3g"])
+def test_propagate_empty_input(ctx, prec):
+    gm = yy.Model(8, 8, yy.YY_F_COS, None, yy.YY_H_IDENTITY, None, 0.0, 0.1, 1.0)
+    z = torch.zeros(8, dtype=torch.float64, device="cuda")
+    e = torch.empty(0, dtype=torch.float64, device="cuda")
+    yy.yy_propagate(ctx, gm, yy.Scales((1.0,)), prec, 0, e, next_version(), z, z + 1.0, 0.01, e, e)
+
