@@ -29,9 +29,11 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "filter steps/sec + propagation TFLOP/s at r=1000,n=65536 vs plain FP32, same error"
-PEAK_TFLOPS = {"bf16x3": 2500.0, "bf16x3g": 2500.0, "bf16x1": 2500.0, "fp32_mfma": 157.3}
+PEAK_TFLOPS = {"bf16x3": 2500.0, "bf16x3g": 2500.0, "bf16x3s": 2500.0, "bf16x1": 2500.0, "fp32_mfma": 157.3}
 VALU_FP32_PEAK = 78.6   # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz, packed FP32 disabled
-# matrix-core products executed per algorithmic product (x.x and x.f each count once)
+# matrix-core products executed per algorithmic product (x.x and x.f each count once); the
+# screened split form executes one per product everywhere plus the split form's two on the
+# tiles its screen flags (counted after the run)
 EXEC_PER_ALG = {"bf16x3": 3.0, "bf16x3g": 2.0, "bf16x1": 1.0, "fp32_mfma": 1.0}
 PAIR_SRC = os.path.join(ROOT, "paper_2509_16896_amd", "csrc", "yy_pair_mfma.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pair_mfma_cubic_r1000_n65536_traffic.md")
@@ -281,8 +283,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--prec", default="bf16x3g", choices=["fp32", "fp32_mfma", "bf16x3", "bf16x3g", "bf16x1"])
-    ap.add_argument("--other-forms", default="bf16x3,bf16x1",
+    ap.add_argument("--prec", default="bf16x3s",
+                    choices=["fp32", "fp32_mfma", "bf16x3", "bf16x3g", "bf16x3s", "bf16x1"])
+    ap.add_argument("--other-forms", default="bf16x3g,bf16x3,bf16x1",
                     help="matrix-core forms whose pairwise kernel is also timed ('none' to skip)")
     ap.add_argument("--baseline-prec", default="fp32_mfma", help="plain FP32 form timed beside ('none' to skip)")
     ap.add_argument("--baseline-steps", type=int, default=4)
@@ -347,6 +350,15 @@ def main():
     roofline["traffic"] = recorded_traffic(args.prec) if args.workload == "cubic_r1000" else None
     roofline["kernel"] = "k_pair_mfma" if mfma else "k_pair_valu"
     roofline["kernel_ms"] = round(1e3 * avg_kernel_s, 3)
+    screen = None
+    if args.prec == "bf16x3s":
+        # the pairwise time is the screen plus the split pass over the flagged tiles
+        from paper_2509_16896_amd import yy
+        flagged, tiles = yy.yy_screen_count(f.ctx)
+        screen = {"flagged_tiles": flagged, "tiles": tiles}
+        roofline["kernel"] = "k_pair_mfma (screen, then split form on flagged tiles)"
+        EXEC_PER_ALG["bf16x3s"] = 1.0 + 2.0 * flagged / max(tiles, 1)
+        log(f"[bench] screen flagged {flagged} of {tiles} tiles for the split form")
     if mfma:
         # matrix-core utilisation: executed products (3 per product for the full split) / peak
         roofline["mfma_exec_frac"] = round(roofline["frac"] * EXEC_PER_ALG[args.prec], 4)
@@ -378,7 +390,8 @@ def main():
         log(f"[bench] oracle {cpu['value']:.3g} steps/s on {cpu['cores']} threads; sampled rows max rel err {parity:.3g}")
     f.close()
 
-    dtype = {"fp32": "f32", "fp32_mfma": "f32", "bf16x3": "bf16", "bf16x3g": "bf16", "bf16x1": "bf16"}[args.prec]
+    dtype = {"fp32": "f32", "fp32_mfma": "f32", "bf16x3": "bf16", "bf16x3g": "bf16", "bf16x3s": "bf16",
+             "bf16x1": "bf16"}[args.prec]
     line = {
         "metric": METRIC, "value": round(steps_s, 4), "unit": "steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed / args.steps, 3),
@@ -388,6 +401,7 @@ def main():
                    "restart_every": w.restart_every, "R": w.R, "precision": args.prec},
         "propagation_tflops": round(prop_tflops, 3),
         "roofline": roofline,
+        "screen": screen,
         "plain_fp32": base,
         "vs_plain_fp32": None if base is None else round(steps_s / base["steps_per_s"], 3),
         "other_forms": forms or None,

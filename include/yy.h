@@ -121,7 +121,8 @@ typedef enum {
   YY_PREC_FP32_MFMA = 2, /* FP32 matrix cores for the distance expansion + exact near pairs */
   YY_PREC_BF16X3 = 3,    /* BF16 hi/lo split (3 products) on matrix cores + exact near pairs */
   YY_PREC_BF16X1 = 4,    /* one BF16 product on matrix cores as a screen + exact near pairs */
-  YY_PREC_BF16X3G = 5    /* BF16X3 for x_i.x_j, one BF16 product for the tau-scaled x_i.f_j */
+  YY_PREC_BF16X3G = 5,   /* BF16X3 for x_i.x_j, one BF16 product for the tau-scaled x_i.f_j */
+  YY_PREC_BF16X3S = 6    /* BF16X3G on the tiles that a BF16X1 screen cannot rule out */
 } yy_prec;
 
 /* ------------------------------------------------------------------------ */
@@ -328,6 +329,13 @@ yy_status yy_batch_step_count(yy_batch b, int32_t* k);
  * graph is being captured. */
 yy_status yy_timing_enable(yy_ctx ctx, int32_t on);
 yy_status yy_timing_read(yy_ctx ctx, double* ms, int64_t* launches);
+
+/* The screen of the last BF16X3S propagation on this context (a diagnostic of
+ * the screened split form): *tiles = (256-target block, 128-source tile)
+ * pairs, *flagged = those recomputed in the split form because some pair in
+ * them may lie within 2^-80 of its row maximum.  Synchronises the context's
+ * stream; YY_ERR_ARG if no BF16X3S propagation ran on it. */
+yy_status yy_screen_count(yy_ctx ctx, int64_t* flagged, int64_t* tiles);
 
 #ifdef __cplusplus
 }

@@ -274,6 +274,7 @@ yy_status yy_destroy(yy_ctx ctx) {
   ctx->prep.bf.release();
   ctx->prep.f32t.release();
   ctx->bsrc.release();
+  ctx->sflags.release();
   ctx->prep.node.release();
   ctx->prep.bnd.release();
   ctx->prep.scal.release();

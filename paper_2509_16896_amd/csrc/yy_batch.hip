@@ -35,7 +35,8 @@ static void tune_store(yy_ctx ctx, int32_t rp, int64_t n_pad, int32_t S, int32_t
 }
 
 static bool is_mfma_prec(int32_t p) {
-  return p == YY_PREC_BF16X3 || p == YY_PREC_BF16X3G || p == YY_PREC_BF16X1 || p == YY_PREC_FP32_MFMA;
+  return p == YY_PREC_BF16X3 || p == YY_PREC_BF16X3G || p == YY_PREC_BF16X3S || p == YY_PREC_BF16X1 ||
+         p == YY_PREC_FP32_MFMA;
 }
 
 static bool capturing(hipStream_t st) {

@@ -88,6 +88,8 @@ struct yy_ctx_s {
   yy::DevBuf red2;
   yy::DevBuf scan;                    // resampling prefix sums
   yy::DevBuf bsrc;                    // matrix-core source biases
+  yy::DevBuf sflags;                  // screen verdicts of the screened split form
+  int64_t sflags_tbs = 0, sflags_jtl = 0;   // their shape at the last screened propagation
   // tuned source-split counts: (rp, n_pad, S, prec) -> nsplit
   struct TuneEntry {
     int32_t rp;
@@ -150,6 +152,7 @@ struct MfmaExtra {
   int64_t j_per_split;
   double kapd[YY_MAX_SCALES];
   double taud[YY_MAX_SCALES];
+  uint8_t* flags;              // screened split form: [n_pad/256][ceil(n/128)][8] screen verdicts
 };
 yy_status launch_src_bias(hipStream_t st, const PairArgs& a, const MfmaExtra& ex);
 yy_status launch_pair_mfma(hipStream_t st, const PairArgs& a, int prec, const MfmaExtra& ex);

@@ -64,9 +64,12 @@ struct MArgs {
   const double* node;          // [3][n]
   const double* scal;          // [1] = max |x - centre|, [2] = max |f|
   double eps_g, eps_h;         // relative error of one G / H product from operand rounding
+  double eps_g1, eps_h1;       // the same for the screen of the screened split form
   float2* part;                // [nsplit][S][n]
   int32_t nsplit, tb_count, group_t;
   int64_t j_per_split;
+  uint8_t* flags;              // screen verdicts [tb_count][jtl][8 waves] (screened split form)
+  int64_t jtl;                 // source tiles of 128
 };
 
 // Physical 16-byte chunk of logical chunk c in LDS row `row` (bank-conflict swizzle).
@@ -201,7 +204,8 @@ __device__ inline void epilogue_target(const MArgs& a, const Rare* rare, const f
   // lane holds it iff d = i - j0 - jl0 is in [0, 32 kJB) with bit 2 equal to g.
   const int64_t d = i - j0 - jl0;
   const bool self = diag && d >= 0 && d < 32 * kJB && (int)((d >> 2) & 1) == g;
-  const int dself = (int)d;
+  // slab index jb * 16 + v of the self pair in this lane (-1: none)
+  const int bself = self ? (int)((d >> 5) * 16 + ((d >> 3) & 3) * 4 + (d & 3)) : -1;
 #pragma unroll
   for (int s = 0; s < S; ++s) {
     const float c1 = a.c1[s], c2 = a.c2[s];
@@ -212,7 +216,7 @@ __device__ inline void epilogue_target(const MArgs& a, const Rare* rare, const f
       for (int v = 0; v < 16; ++v) {
         const int jl = jb * 32 + 8 * (v >> 2) + 4 * g + (v & 3);
         float e = fmaf(c2, H[jb][v], fmaf(c1, G[jb][v], at[s] + sb[s * kMJ + jl0 + jl]));
-        if (self && jl == dself) e = -INFINITY;
+        if (jb * 16 + v == bself) e = -INFINITY;
         m = fmaxf(m, e);
       }
     // Every exact exponent of the slab is at most m + (margin - kSkip - 16): below
@@ -225,7 +229,7 @@ __device__ inline void epilogue_target(const MArgs& a, const Rare* rare, const f
       for (int v = 0; v < 16; ++v) {
         const int jl = jb * 32 + 8 * (v >> 2) + 4 * g + (v & 3);
         float x = fmaf(c2, H[jb][v], fmaf(c1, G[jb][v], at[s] + sb[s * kMJ + jl0 + jl]));
-        if (self && jl == dself) x = -INFINITY;
+        if (jb * 16 + v == bself) x = -INFINITY;
         e[jb * 16 + v] = x;
       }
     const float2 r = refine_slab(rare, i, j0 + jl0, g, s, margin[s], e, M[s], Ssum[s]);
@@ -280,7 +284,7 @@ __device__ inline void merge_and_store(const MArgs& a, float (&M)[kIB][S], float
 // Rigorous bound on |e_approx - e_exact| in base-2 units: operand rounding,
 // worst-case FP32 accumulation over rp products, FP32 evaluation of e; the
 // margin adds the skip depth and 16 bits of safety.
-template <int S>
+template <int S, bool SCREEN>
 __device__ inline void init_targets(const MArgs& a, int64_t i0, int split, float (&at)[kIB][S],
                                     float (&M)[kIB][S], float (&Ssum)[kIB][S], float (&margin)[S]) {
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -290,7 +294,8 @@ __device__ inline void init_targets(const MArgs& a, int64_t i0, int split, float
 #pragma unroll
   for (int s = 0; s < S; ++s) {
     const double XT = X + a.taud[s] * F;
-    const double dD = 2.0 * X * ((a.eps_g + gam) * X + (a.eps_h + gam) * a.taud[s] * F) + 16.0 * 0x1p-24 * XT * XT;
+    const double eg = SCREEN ? a.eps_g1 : a.eps_g, eh = SCREEN ? a.eps_h1 : a.eps_h;
+    const double dD = 2.0 * X * ((eg + gam) * X + (eh + gam) * a.taud[s] * F) + 16.0 * 0x1p-24 * XT * XT;
     margin[s] = (float)(2.0 * a.kapd[s] * dD + (double)kSkip + 16.0);
   }
 #pragma unroll
@@ -385,9 +390,20 @@ __device__ inline void issue_stage(const unsigned char* gb, uint64_t plane_bytes
   }
 }
 
+// The lane index, recomputed where it is used: the compiler may neither merge
+// nor hoist the asm statement, so addresses derived from it are not kept live
+// (or spilled) across the main loop; a spill reload would wait for every copy
+// in flight, since it shares their vmcnt counter.
+__device__ inline int fresh_lane() {
+  int l;
+  asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(l));
+  return l;
+}
+
 // Source biases of tile j0 -> sb (wave 0 only): [S][128] floats, lane-ordered.
-__device__ inline void issue_bias(const MArgs& a, uint32_t sb_lds, int64_t j0, int wave, int lane) {
+__device__ inline void issue_bias(const MArgs& a, uint32_t sb_lds, int64_t j0, int wave) {
   if (wave != 0) return;
+  const int lane = fresh_lane();
   const int regions = (a.S * kMJ * 4 + 1023) / 1024;
   for (int u = 0; u < regions; ++u) {
     const int idx = 256 * u + 4 * lane;
@@ -529,12 +545,58 @@ struct StageShape {
   static constexpr int STAGE = (NTP * kMI + NSP * kMJ) * ROWB;       // bytes per LDS stage
 };
 
+// The screen's verdict on one finished tile for this wave (MODE 1): does any
+// slab of the wave's 64 targets x 64 sources reach within the margin of the
+// running lower bound of its row maximum?  The bound rises to every slab's
+// approximate maximum less the rigorous error of an approximate exponent.
+template <int S>
+__device__ __forceinline__ bool screen_tile(const MArgs& a, const f32x16_t (&G)[kIB][kJB],
+                                            const f32x16_t (&H)[kIB][kJB], const float* sb, int64_t i0,
+                                            int64_t j0, int wi, int wj, int col, int g, const float (&at)[kIB][S],
+                                            const float (&margin)[S], float (&M)[kIB][S]) {
+  const bool diag = j0 < i0 + kMI && i0 < j0 + kMJ;
+  const int jl0 = wj * (32 * kJB);
+  bool need = false;
+#pragma unroll
+  for (int ib = 0; ib < kIB; ++ib) {
+    const int64_t i = i0 + wi * (32 * kIB) + ib * 32 + col;
+    const int64_t d = i - j0 - jl0;
+    const bool self = diag && d >= 0 && d < 32 * kJB && (int)((d >> 2) & 1) == g;
+    const int bself = self ? (int)((d >> 5) * 16 + ((d >> 3) & 3) * 4 + (d & 3)) : -1;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const float c1 = a.c1[s], c2 = a.c2[s];
+      float m = -INFINITY;
+#pragma unroll
+      for (int jb = 0; jb < kJB; ++jb)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int jl = jb * 32 + 8 * (v >> 2) + 4 * g + (v & 3);
+          float e = fmaf(c2, H[ib][jb][v], fmaf(c1, G[ib][jb][v], at[ib][s] + sb[s * kMJ + jl0 + jl]));
+          if (jb * 16 + v == bself) e = -INFINITY;
+          m = fmaxf(m, e);
+        }
+      need |= m > M[ib][s] - margin[s];
+      // margin - kSkip - 16 is the error bound; one more bit of slack
+      M[ib][s] = fmaxf(M[ib][s], m - (margin[s] - kSkip - 15.f));
+    }
+  }
+  return __any(need);
+}
+
 // One block's work: targets [256 tb, 256 tb + 256) against the sources of split
-// `split`, partial (max, sum) to a.part.  smem, sbuf and rare are the block's
-// LDS ring, bias double buffer and rare-path parameters.
-template <int S, int VAR, int NS, int SPB>
+// `split`, partial (max, sum) to a.part.  smem, sbuf, rare and tl are the
+// block's LDS ring, bias buffers, rare-path parameters and tile list.
+// MODE 0: every tile.  MODE 1 (the screen): the products of every tile, no
+// partial results; one flag byte per (target block, source tile, wave) says
+// whether any of the wave's pairs may lie within the margin of its row
+// maximum.  MODE 2: only the tiles flagged by the screen, taken in windows of
+// kTileWindow tiles; the others hold no pair within 2^-80 of a row maximum.
+constexpr int kTileWindow = 64;
+
+template <int S, int VAR, int NS, int SPB, int MODE>
 __device__ __forceinline__ void pair_block(const MArgs& a, int tb, int split, unsigned char* smem,
-                                           float (*sbuf)[4 * kMJ], Rare& rare) {
+                                           float (*sbuf)[4 * kMJ], Rare& rare, int* tl) {
   static_assert(NS % SPB == 0 && NS / SPB >= 2, "the ring holds at least two groups of stages");
   constexpr int LA = NS / SPB - 1;
   constexpr int ESZ = StageShape<VAR>::ESZ;
@@ -552,9 +614,9 @@ __device__ __forceinline__ void pair_block(const MArgs& a, int tb, int split, un
   const int64_t jb1 = jb0 + a.j_per_split < a.n ? jb0 + a.j_per_split : a.n;
   // block-uniform counts (the LDS addresses of the copies derive from them and
   // must live in scalar registers even when `a` was read from global memory)
-  const int ntiles = __builtin_amdgcn_readfirstlane((int)((jb1 - jb0 + kMJ - 1) / kMJ));
+  const int ntiles_all = __builtin_amdgcn_readfirstlane((int)((jb1 - jb0 + kMJ - 1) / kMJ));
   const int nchunks = __builtin_amdgcn_readfirstlane(a.rp / kKC);
-  const int Q = ntiles * nchunks;
+  const int64_t jt0 = jb0 / kMJ;   // global index of the split's first source tile
   const uint64_t plane = (uint64_t)nchunks * a.n_pad * kKC * ESZ;   // bytes per global plane
   const unsigned char* gb = VAR == 0 ? reinterpret_cast<const unsigned char*>(a.f32t)
                                      : reinterpret_cast<const unsigned char*>(a.bf);
@@ -563,84 +625,116 @@ __device__ __forceinline__ void pair_block(const MArgs& a, int tb, int split, un
   const uint32_t sb_lds = __builtin_amdgcn_readfirstlane(lds_addr(&sbuf[0][0]));
 
   float at[kIB][S], M[kIB][S], Ssum[kIB][S], margin[S];
-  init_targets<S>(a, i0, split, at, M, Ssum, margin);
+  init_targets<S, MODE == 1>(a, i0, split, at, M, Ssum, margin);
 
-  issue_bias(a, sb_lds, jb0, wave, lane);
-#pragma unroll
-  for (int p = 0; p < LA * SPB; ++p)
-    if (p < Q) issue_stage<ESZ, NTP, NSP>(gb, plane, n_pad, smem_lds + p * STAGE, p % nchunks, i0,
-                                          jb0 + (int64_t)(p / nchunks) * kMJ, wave, lane);
-
-  for (int t = 0; t < ntiles; ++t) {
-    const int64_t j0 = jb0 + (int64_t)t * kMJ;
-    f32x16_t G[kIB][kJB], H[kIB][kJB];
-    zero_acc<S>(G, H);
-    for (int c = 0; c < nchunks; c += SPB) {
-      const int q = t * nchunks + c;
-      // this wave's copies of steps q .. q+SPB-1 have landed (the later groups may still fly) ...
-      if (q + LA * SPB - 1 < Q) wait_vmcnt<(LA - 1) * SPB * L>();
-      else wait_vmcnt<0>();
-      __syncthreads();   // ... for every wave; the previous group's stages are free again
-      if (c == 0 && t + 1 < ntiles) issue_bias(a, sb_lds + ((t + 1) & 1) * (4 * kMJ * 4), j0 + kMJ, wave, lane);
-#pragma unroll
-      for (int u = 0; u < SPB; ++u) {
-        const int qn = q + LA * SPB + u;
-        if (qn < Q) {
-          const int tn = qn / nchunks;
-          issue_stage<ESZ, NTP, NSP>(gb, plane, n_pad, smem_lds + (qn % NS) * STAGE, qn - tn * nchunks, i0,
-                                     jb0 + (int64_t)tn * kMJ, wave, lane);
-        }
+  for (int w0 = 0; w0 < ntiles_all; w0 += MODE == 2 ? kTileWindow : ntiles_all) {
+    int ntiles = ntiles_all;
+    if (MODE == 2) {
+      // the window's flagged tiles, in order
+      const int wn = ntiles_all - w0 < kTileWindow ? ntiles_all - w0 : kTileWindow;
+      __syncthreads();   // the previous window is done with the ring, the bias buffers and the list
+      if (wave == 0) {
+        const bool f = lane < wn &&
+                       *reinterpret_cast<const uint64_t*>(a.flags + ((size_t)tb * a.jtl + jt0 + w0 + lane) * 8) != 0;
+        const uint64_t mask = __ballot(f);
+        if (f) tl[__popcll(mask & ((1ull << lane) - 1))] = w0 + lane;
+        if (lane == 0) tl[kTileWindow] = __popcll(mask);
       }
-      if (VAR == 0) {
+      __syncthreads();
+      ntiles = __builtin_amdgcn_readfirstlane(tl[kTileWindow]);
+      if (ntiles == 0) continue;
+    }
+    // first source of the window's tile t
+    auto tile_j0 = [&](int t) -> int64_t {
+      return jb0 + (int64_t)(MODE == 2 ? __builtin_amdgcn_readfirstlane(tl[t]) : t) * kMJ;
+    };
+    const int Q = ntiles * nchunks;
+
+    issue_bias(a, sb_lds, tile_j0(0), wave);
 #pragma unroll
-        for (int u = 0; u < SPB; ++u) mfma_stage_f32(smem + ((q + u) % NS) * STAGE, G, H);
-      } else {
-        // fragments of stage u + 1 are read while the burst of stage u runs
-        Frag fr[2];
-        load_frags<VAR>(smem + (q % NS) * STAGE, fr[0]);
+    for (int p = 0; p < LA * SPB; ++p)
+      if (p < Q) issue_stage<ESZ, NTP, NSP>(gb, plane, n_pad, smem_lds + p * STAGE, p % nchunks, i0,
+                                            tile_j0(p / nchunks), wave, lane);
+
+    for (int t = 0; t < ntiles; ++t) {
+      const int64_t j0 = tile_j0(t);
+      f32x16_t G[kIB][kJB], H[kIB][kJB];
+      zero_acc<S>(G, H);
+      for (int c = 0; c < nchunks; c += SPB) {
+        const int q = t * nchunks + c;
+        // this wave's copies of steps q .. q+SPB-1 have landed (the later groups may still fly) ...
+        if (q + LA * SPB - 1 < Q) wait_vmcnt<(LA - 1) * SPB * L>();
+        else wait_vmcnt<0>();
+        __syncthreads();   // ... for every wave; the previous group's stages are free again
+        if (c == 0 && t + 1 < ntiles)
+          issue_bias(a, sb_lds + ((t + 1) & 1) * (4 * kMJ * 4), tile_j0(t + 1), wave);
 #pragma unroll
         for (int u = 0; u < SPB; ++u) {
-          if (u + 1 < SPB) load_frags<VAR>(smem + ((q + u + 1) % NS) * STAGE, fr[(u + 1) & 1]);
-          mma_frags<VAR>(fr[u & 1], G, H);
+          const int qn = q + LA * SPB + u;
+          if (qn < Q) {
+            const int tn = qn / nchunks;
+            issue_stage<ESZ, NTP, NSP>(gb, plane, n_pad, smem_lds + (qn % NS) * STAGE, qn - tn * nchunks, i0,
+                                       tile_j0(tn), wave, lane);
+          }
+        }
+        if (VAR == 0) {
+#pragma unroll
+          for (int u = 0; u < SPB; ++u) mfma_stage_f32(smem + ((q + u) % NS) * STAGE, G, H);
+        } else {
+          // fragments of stage u + 1 are read while the burst of stage u runs
+          Frag fr[2];
+          load_frags<VAR>(smem + (q % NS) * STAGE, fr[0]);
+#pragma unroll
+          for (int u = 0; u < SPB; ++u) {
+            if (u + 1 < SPB) load_frags<VAR>(smem + ((q + u + 1) % NS) * STAGE, fr[(u + 1) & 1]);
+            mma_frags<VAR>(fr[u & 1], G, H);
+          }
         }
       }
-    }
-    const bool diag = j0 < i0 + kMI && i0 < j0 + kMJ;
-    const float* sb = &sbuf[t & 1][0];
+      const float* sb = &sbuf[t & 1][0];
+      if (MODE == 1) {
+        const bool flag = screen_tile<S>(a, G, H, sb, i0, j0, wi, wj, col, g, at, margin, M);
+        if (lane == 0) a.flags[((size_t)tb * a.jtl + jt0 + t) * 8 + wave] = flag ? 1 : 0;
+      } else {
+        const bool diag = j0 < i0 + kMI && i0 < j0 + kMJ;
 #pragma unroll
-    for (int ib = 0; ib < kIB; ++ib) {
-      const int64_t i = i0 + wi * (32 * kIB) + ib * 32 + col;
-      // keep one target's accumulators in flight at a time (register pressure)
+        for (int ib = 0; ib < kIB; ++ib) {
+          const int64_t i = i0 + wi * (32 * kIB) + ib * 32 + col;
+          // keep one target's accumulators in flight at a time (register pressure)
+          __builtin_amdgcn_sched_barrier(0);
+          epilogue_target<S>(a, &rare, G[ib], H[ib], sb, i, j0, wj * (32 * kJB), g, diag, at[ib], margin, M[ib],
+                             Ssum[ib]);
+        }
+      }
       __builtin_amdgcn_sched_barrier(0);
-      epilogue_target<S>(a, &rare, G[ib], H[ib], sb, i, j0, wj * (32 * kJB), g, diag, at[ib], margin, M[ib],
-                         Ssum[ib]);
     }
-    __builtin_amdgcn_sched_barrier(0);
   }
-  merge_and_store<S>(a, M, Ssum, i0, split, reinterpret_cast<float2*>(smem));
+  if (MODE != 1) merge_and_store<S>(a, M, Ssum, i0, split, reinterpret_cast<float2*>(smem));
 }
 
-template <int S, int VAR, int NS, int SPB>
+template <int S, int VAR, int NS, int SPB, int MODE>
 __global__ void __launch_bounds__(kNT, 1) k_pair_mfma(MArgs a) {
   __shared__ __attribute__((aligned(1024))) unsigned char smem[NS * StageShape<VAR>::STAGE];
   __shared__ __attribute__((aligned(1024))) float sbuf[2][4 * kMJ];
   __shared__ Rare rare;
+  __shared__ int tl[MODE == 2 ? kTileWindow + 1 : 1];
   int tb, split;
   block_map(a, tb, split);
-  pair_block<S, VAR, NS, SPB>(a, tb, split, smem, sbuf, rare);
+  pair_block<S, VAR, NS, SPB, MODE>(a, tb, split, smem, sbuf, rare, tl);
 }
 
 // Many node sets in one launch: block b takes work item items[b] = (set,
 // target block, source split); the items come in decreasing cost order.
-template <int S, int VAR, int NS, int SPB>
+template <int S, int VAR, int NS, int SPB, int MODE>
 __global__ void __launch_bounds__(kNT, 1) k_pair_mfma_batch(const MArgs* __restrict__ sets,
                                                             const int4* __restrict__ items) {
   __shared__ __attribute__((aligned(1024))) unsigned char smem[NS * StageShape<VAR>::STAGE];
   __shared__ __attribute__((aligned(1024))) float sbuf[2][4 * kMJ];
   __shared__ Rare rare;
+  __shared__ int tl[MODE == 2 ? kTileWindow + 1 : 1];
   const int4 it = items[blockIdx.x];
-  pair_block<S, VAR, NS, SPB>(sets[__builtin_amdgcn_readfirstlane(it.x)], __builtin_amdgcn_readfirstlane(it.y),
-                              __builtin_amdgcn_readfirstlane(it.z), smem, sbuf, rare);
+  pair_block<S, VAR, NS, SPB, MODE>(sets[__builtin_amdgcn_readfirstlane(it.x)], __builtin_amdgcn_readfirstlane(it.y),
+                                    __builtin_amdgcn_readfirstlane(it.z), smem, sbuf, rare, tl);
 }
 
 // ---------------------------------------------------------------------------
@@ -687,8 +781,13 @@ static MArgs make_args(const PairArgs& pa, int prec, const MfmaExtra& ex) {
   m.S = pa.S;
   // hi/lo split product: 2^-16 per operand split plus cross terms; hi only:
   // 2^-8 per operand; FP32 operands: 2^-24 per operand (rounded up).
-  m.eps_g = prec == YY_PREC_BF16X3 || prec == YY_PREC_BF16X3G ? 0x1p-14 : prec == YY_PREC_BF16X1 ? 0x1p-7 : 0x1p-22;
-  m.eps_h = prec == YY_PREC_BF16X3 ? 0x1p-14 : prec == YY_PREC_BF16X3G || prec == YY_PREC_BF16X1 ? 0x1p-7 : 0x1p-22;
+  // The screened split form: the BF16X3G bounds, and the BF16X1 bounds for its screen.
+  const bool split_g = prec == YY_PREC_BF16X3 || prec == YY_PREC_BF16X3G || prec == YY_PREC_BF16X3S;
+  const bool hi_h = prec == YY_PREC_BF16X3G || prec == YY_PREC_BF16X3S || prec == YY_PREC_BF16X1;
+  m.eps_g = split_g ? 0x1p-14 : prec == YY_PREC_BF16X1 ? 0x1p-7 : 0x1p-22;
+  m.eps_h = prec == YY_PREC_BF16X3 ? 0x1p-14 : hi_h ? 0x1p-7 : 0x1p-22;
+  m.eps_g1 = 0x1p-7;
+  m.eps_h1 = 0x1p-7;
   for (int s = 0; s < pa.S; ++s) {
     const double kap = ex.kapd[s], tau = ex.taud[s];
     m.kap[s] = (float)kap;
@@ -711,6 +810,8 @@ static MArgs make_args(const PairArgs& pa, int prec, const MfmaExtra& ex) {
   m.tb_count = (int)(ex.n_pad / kMI);
   m.group_t = 2;
   m.j_per_split = ex.j_per_split;
+  m.flags = ex.flags;
+  m.jtl = (pa.n + kMJ - 1) / kMJ;
   return m;
 }
 
@@ -723,20 +824,39 @@ yy_status launch_src_bias(hipStream_t st, const PairArgs& pa, const MfmaExtra& e
 
 template <int S>
 static yy_status launch_batch_s(hipStream_t st, const MArgs* sets, const int4* items, int nitems, int prec) {
-  if (prec == YY_PREC_BF16X3) k_pair_mfma_batch<S, 3, 4, 2><<<nitems, kNT, 0, st>>>(sets, items);
-  else if (prec == YY_PREC_BF16X3G) k_pair_mfma_batch<S, 2, 4, 2><<<nitems, kNT, 0, st>>>(sets, items);
-  else if (prec == YY_PREC_BF16X1) k_pair_mfma_batch<S, 1, 8, 4><<<nitems, kNT, 0, st>>>(sets, items);
-  else k_pair_mfma_batch<S, 0, 4, 2><<<nitems, kNT, 0, st>>>(sets, items);
+  if (prec == YY_PREC_BF16X3) {
+    k_pair_mfma_batch<S, 3, 4, 2, 0><<<nitems, kNT, 0, st>>>(sets, items);
+  } else if (prec == YY_PREC_BF16X3G) {
+    k_pair_mfma_batch<S, 2, 4, 2, 0><<<nitems, kNT, 0, st>>>(sets, items);
+  } else if (prec == YY_PREC_BF16X3S) {
+    k_pair_mfma_batch<S, 1, 8, 4, 1><<<nitems, kNT, 0, st>>>(sets, items);
+    YY_LAUNCH_CHECK("k_pair_mfma_batch (screen)");
+    k_pair_mfma_batch<S, 2, 4, 2, 2><<<nitems, kNT, 0, st>>>(sets, items);
+  } else if (prec == YY_PREC_BF16X1) {
+    k_pair_mfma_batch<S, 1, 8, 4, 0><<<nitems, kNT, 0, st>>>(sets, items);
+  } else {
+    k_pair_mfma_batch<S, 0, 4, 2, 0><<<nitems, kNT, 0, st>>>(sets, items);
+  }
   YY_LAUNCH_CHECK("k_pair_mfma_batch");
   return YY_OK;
 }
 
 template <int S>
 static yy_status launch_s(hipStream_t st, const MArgs& m, int prec, int nblocks) {
-  if (prec == YY_PREC_BF16X3) k_pair_mfma<S, 3, 4, 2><<<nblocks, kNT, 0, st>>>(m);
-  else if (prec == YY_PREC_BF16X3G) k_pair_mfma<S, 2, 4, 2><<<nblocks, kNT, 0, st>>>(m);
-  else if (prec == YY_PREC_BF16X1) k_pair_mfma<S, 1, 8, 4><<<nblocks, kNT, 0, st>>>(m);
-  else k_pair_mfma<S, 0, 4, 2><<<nblocks, kNT, 0, st>>>(m);
+  if (prec == YY_PREC_BF16X3) {
+    k_pair_mfma<S, 3, 4, 2, 0><<<nblocks, kNT, 0, st>>>(m);
+  } else if (prec == YY_PREC_BF16X3G) {
+    k_pair_mfma<S, 2, 4, 2, 0><<<nblocks, kNT, 0, st>>>(m);
+  } else if (prec == YY_PREC_BF16X3S) {
+    // the screen over every tile, then the split form over the flagged tiles
+    k_pair_mfma<S, 1, 8, 4, 1><<<nblocks, kNT, 0, st>>>(m);
+    YY_LAUNCH_CHECK("k_pair_mfma (screen)");
+    k_pair_mfma<S, 2, 4, 2, 2><<<nblocks, kNT, 0, st>>>(m);
+  } else if (prec == YY_PREC_BF16X1) {
+    k_pair_mfma<S, 1, 8, 4, 0><<<nblocks, kNT, 0, st>>>(m);
+  } else {
+    k_pair_mfma<S, 0, 4, 2, 0><<<nblocks, kNT, 0, st>>>(m);
+  }
   YY_LAUNCH_CHECK("k_pair_mfma");
   return YY_OK;
 }

@@ -14,6 +14,8 @@
 #include <algorithm>
 #include <cmath>
 
+#include <vector>
+
 #include "yy_common.h"
 #include "yy_internal.h"
 
@@ -474,10 +476,10 @@ __global__ void __launch_bounds__(kBlock) k_combine_batch(const combine_args* __
 
 // ---------------------------------------------------------------------------
 // K of the prepared node set: r zero-padded to whole groups of 16-wide K
-// stages of the pairwise kernel (2 stages per barrier; 4 for BF16X1 and the
-// vector-ALU form).
+// stages of the pairwise kernel (2 stages per barrier; 4 for BF16X1, the
+// screen of BF16X3S and the vector-ALU form).
 int pair_mfma_rp(int32_t r, int32_t prec) {
-  const int q = (prec == YY_PREC_BF16X1 || prec == YY_PREC_FP32) ? 64 : 32;
+  const int q = (prec == YY_PREC_BF16X1 || prec == YY_PREC_BF16X3S || prec == YY_PREC_FP32) ? 64 : 32;
   return ((r + q - 1) / q) * q;
 }
 
@@ -601,7 +603,7 @@ yy_status propagate_begin(yy_ctx ctx, const yy_model* model, const yy_scales* sc
   if (!x || !box_lo || !box_hi || !logw_in || !logw_out)
     return fail(YY_ERR_ARG, "yy_propagate: NULL array");
   if (logw_in == logw_out) return fail(YY_ERR_ARG, "yy_propagate: logw_in and logw_out alias");
-  if (prec < YY_PREC_AUTO || prec > YY_PREC_BF16X3G) return fail(YY_ERR_ARG, "yy_propagate: bad prec");
+  if (prec < YY_PREC_AUTO || prec > YY_PREC_BF16X3S) return fail(YY_ERR_ARG, "yy_propagate: bad prec");
   const int32_t S = scales->S;
   double c[YY_MAX_SCALES + 1];
   for (int s = 0; s < S; ++s)
@@ -619,7 +621,8 @@ yy_status propagate_begin(yy_ctx ctx, const yy_model* model, const yy_scales* sc
   plan.mfma = mfma;
   YY_HIP(hipSetDevice(ctx->device));
   st = prepare_nodes(ctx, model, n, x, node_version, box_lo, box_hi,
-                     prec == YY_PREC_BF16X3 || prec == YY_PREC_BF16X3G || prec == YY_PREC_BF16X1,
+                     prec == YY_PREC_BF16X3 || prec == YY_PREC_BF16X3G || prec == YY_PREC_BF16X1 ||
+                         prec == YY_PREC_BF16X3S,
                      prec == YY_PREC_FP32_MFMA, prec);
   if (st != YY_OK) return st;
   const Prepared& P = ctx->prep;
@@ -690,6 +693,12 @@ yy_status propagate_begin(yy_ctx ctx, const yy_model* model, const yy_scales* sc
     }
     if ((st = ctx->bsrc.ensure((size_t)S * n_pad * sizeof(float))) != YY_OK) return st;
     ex.bsrc = ctx->bsrc.as<float>();
+    if (prec == YY_PREC_BF16X3S) {
+      if ((st = ctx->sflags.ensure((size_t)tbs * jtl * 8)) != YY_OK) return st;
+      ex.flags = ctx->sflags.as<uint8_t>();
+      ctx->sflags_tbs = tbs;
+      ctx->sflags_jtl = jtl;
+    }
   } else {
     while (ttiles * nsplit < 512 && nsplit < 64 && (int64_t)nsplit * kVJ * 2 <= n) nsplit *= 2;
   }
@@ -755,4 +764,20 @@ extern "C" yy_status yy_propagate(yy_ctx ctx, const yy_model* model, const yy_sc
   if (st != YY_OK) return st;
   if ((st = propagate_pair(ctx, plan)) != YY_OK) return st;
   return propagate_end(ctx, plan);
+}
+
+extern "C" yy_status yy_screen_count(yy_ctx ctx, int64_t* flagged, int64_t* tiles) {
+  if (!ctx) return fail(YY_ERR_ARG, "yy_screen_count: ctx is NULL");
+  if (!flagged || !tiles) return fail(YY_ERR_ARG, "yy_screen_count: NULL output");
+  if (ctx->sflags_tbs <= 0) return fail(YY_ERR_ARG, "yy_screen_count: no screened propagation on this context");
+  YY_HIP(hipSetDevice(ctx->device));
+  YY_HIP(hipStreamSynchronize(ctx->stream));
+  const int64_t t = ctx->sflags_tbs * ctx->sflags_jtl;
+  std::vector<uint64_t> h((size_t)t);
+  YY_HIP(hipMemcpy(h.data(), ctx->sflags.ptr, (size_t)t * 8, hipMemcpyDeviceToHost));
+  int64_t c = 0;
+  for (uint64_t v : h) c += v != 0;
+  *flagged = c;
+  *tiles = t;
+  return YY_OK;
 }

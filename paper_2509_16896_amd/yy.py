@@ -24,13 +24,14 @@ YY_OK, YY_ERR_ARG, YY_ERR_ALLOC, YY_ERR_HIP, YY_ERR_NUMERIC, YY_ERR_UNSUPPORTED 
 YY_FLAG_ALL_ZERO, YY_FLAG_CLAMPED, YY_FLAG_RESAMPLE_ZERO, YY_FLAG_LOW_ESS = 1, 2, 4, 8
 YY_F_ZERO, YY_F_COS, YY_F_LINEAR = 0, 1, 2
 YY_H_IDENTITY, YY_H_CUBE, YY_H_LINEAR = 0, 1, 2
-YY_PREC_AUTO, YY_PREC_FP32, YY_PREC_FP32_MFMA, YY_PREC_BF16X3, YY_PREC_BF16X1, YY_PREC_BF16X3G = 0, 1, 2, 3, 4, 5
+YY_PREC_AUTO, YY_PREC_FP32, YY_PREC_FP32_MFMA, YY_PREC_BF16X3, YY_PREC_BF16X1, YY_PREC_BF16X3G, YY_PREC_BF16X3S = \
+    0, 1, 2, 3, 4, 5, 6
 PREC_BY_NAME = {"auto": YY_PREC_AUTO, "fp32": YY_PREC_FP32, "fp32_mfma": YY_PREC_FP32_MFMA,
                 "bf16x3": YY_PREC_BF16X3, "bf16x1": YY_PREC_BF16X1,
-                "bf16x3g": YY_PREC_BF16X3G}
+                "bf16x3g": YY_PREC_BF16X3G, "bf16x3s": YY_PREC_BF16X3S}
 EXPORTED = ["yy_last_error", "yy_create", "yy_destroy", "yy_set_stream", "yy_get_status",
             "yy_kernel_coefficients", "yy_nodes_sobol", "yy_propagate", "yy_loglik_update",
-            "yy_normalise_moments", "yy_restart", "yy_timing_enable", "yy_timing_read",
+            "yy_normalise_moments", "yy_restart", "yy_timing_enable", "yy_timing_read", "yy_screen_count",
             "yy_proposal_create", "yy_proposal_destroy", "yy_proposal_num_params", "yy_proposal_get_params",
             "yy_proposal_set_params", "yy_proposal_forward", "yy_proposal_train_step", "yy_sample_moments",
             "yy_tune", "yy_batch_create", "yy_batch_destroy", "yy_batch_reset", "yy_batch_step",
@@ -103,6 +104,7 @@ for _name, _args in {
     "yy_batch_step_count": [_P, ctypes.POINTER(_i32)],
     "yy_timing_enable": [_P, _i32],
     "yy_timing_read": [_P, ctypes.POINTER(_f64), ctypes.POINTER(_i64)],
+    "yy_screen_count": [_P, ctypes.POINTER(_i64), ctypes.POINTER(_i64)],
 }.items():
     _fn = getattr(_lib, _name)
     _fn.argtypes = _args
@@ -304,6 +306,14 @@ def yy_timing_read(ctx):
     cnt = ctypes.c_int64(0)
     _check(_lib.yy_timing_read(ctx, ctypes.byref(ms), ctypes.byref(cnt)), "yy_timing_read")
     return float(ms.value), int(cnt.value)
+
+
+def yy_screen_count(ctx):
+    """(flagged tiles, tiles) of the last BF16X3S propagation on ctx."""
+    fl = ctypes.c_int64(0)
+    t = ctypes.c_int64(0)
+    _check(_lib.yy_screen_count(ctx, ctypes.byref(fl), ctypes.byref(t)), "yy_screen_count")
+    return int(fl.value), int(t.value)
 
 
 def yy_tune(ctx, shapes, scales: Scales, prec, reps=3):

@@ -41,7 +41,7 @@ def _single(w, dys, prec):
         f.close()
 
 
-@pytest.mark.parametrize("prec", ["bf16x3g", "fp32_mfma"])
+@pytest.mark.parametrize("prec", ["bf16x3g", "bf16x3s", "fp32_mfma"])
 def test_batch_matches_single_runs_exactly(prec):
     ws = _workloads()
     dys = [W.simulate(w)[1] for w in ws]

@@ -1,0 +1,123 @@
+"""The screened split form (BF16X3S): a one-product BF16 screen over every tile,
+the split form over the tiles it cannot rule out.
+
+Against the oracle on sampled rows at sizes where the screen flags some tiles
+and passes others, against the unscreened split form (BF16X3G) everywhere, and
+through the tile windows of a source range longer than 64 tiles (one split).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_util import dev, host, next_version
+
+pytestmark = pytest.mark.gpu
+
+yy = pytest.importorskip("paper_2509_16896_amd.yy")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = yy.yy_create(0, torch.cuda.current_stream())
+    yield c
+    yy.yy_destroy(c)
+
+
+def _case(r, n, q, dt, half, seed, scales=(1.0, 2.0, 4.0)):
+    rng = np.random.default_rng(seed)
+    lo, hi = -half * np.ones(r), half * np.ones(r)
+    codes = oracle.sobol_codes(r, n, 0, True, seed)
+    x = oracle.codes_to_points(codes, lo, hi)
+    lw = -3.0 * rng.random(n) - 0.5 * np.sum((x / half) ** 2, axis=1)
+    gm = yy.Model(r, r, yy.YY_F_COS, None, yy.YY_H_IDENTITY, None, 0.0, q, 1.0)
+    om = oracle.OModel(r, r, oracle.F_COS, None, oracle.H_IDENTITY, None, 0.0, q, 1.0)
+    return dict(r=r, n=n, x=x, lo=lo, hi=hi, lw=lw, gm=gm, om=om, dt=dt, scales=scales)
+
+
+def _run(ctx, c, prec):
+    out = torch.empty(c["n"], dtype=torch.float64, device="cuda")
+    yy.yy_propagate(ctx, c["gm"], yy.Scales(c["scales"]), prec, c["n"], dev(c["x"].ravel()), next_version(),
+                    dev(c["lo"]), dev(c["hi"]), c["dt"], dev(c["lw"]), out)
+    return host(out)
+
+
+# Kernel widths from "every tile holds near pairs" to "only the self pairs are near";
+# n spans several 256-target blocks and 128-source tiles with a ragged tail.
+CASES = {
+    "r64_n4000_wide": dict(r=64, n=4000, q=2.0, dt=0.05, half=0.25, seed=41),
+    "r96_n6000_mid": dict(r=96, n=6000, q=0.3, dt=0.02, half=0.3, seed=42),
+    "r200_n5000_narrow": dict(r=200, n=5000, q=0.09, dt=0.005, half=0.3, seed=43),
+    "r33_n3000_s1": dict(r=33, n=3000, q=0.5, dt=0.02, half=0.5, seed=44),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_screened_matches_split_form_and_oracle_rows(ctx, name):
+    c = _case(**CASES[name])
+    got = _run(ctx, c, "bf16x3s")
+    ref = _run(ctx, c, "bf16x3g")
+    f = np.isfinite(ref)
+    assert np.array_equal(np.isfinite(got), f)
+    # both forms keep every pair within 2^-80 of a row maximum exactly: they agree to FP32 rounding
+    rel = np.abs(got[f] - ref[f]) / np.maximum(1.0, np.abs(ref[f]))
+    print(f"{name}: max |x3s - x3g| / max(1, |x3g|) = {rel.max():.3g}")
+    assert rel.max() < 2e-6
+    assert np.array_equal(_run(ctx, c, "bf16x3s"), got)   # deterministic
+    flagged, tiles = yy.yy_screen_count(ctx)
+    n = c["n"]
+    assert tiles == ((n + 255) // 256) * ((n + 127) // 128)
+    assert 0 <= flagged <= tiles
+    print(f"{name}: screen flagged {flagged} of {tiles} tiles")
+    # sampled rows against the oracle
+    rng = np.random.default_rng(1)
+    rows = np.unique(np.concatenate([[0, c["n"] - 1], rng.choice(c["n"], 24, replace=False)]))
+    s = np.asarray(c["scales"])
+    lo = oracle.propagate_rows(c["om"], s, oracle.kernel_coefficients(s), c["x"], c["lo"], c["hi"], c["dt"],
+                               c["lw"], rows)[0]
+    g = got[rows]
+    ok = np.isfinite(lo)
+    assert np.array_equal(np.isfinite(g), ok)
+    z = np.log(np.sum(np.exp(got[f] - np.max(got[f])))) + np.max(got[f])
+    err = np.abs(g[ok] - lo[ok]) / np.maximum(1.0, np.abs(lo[ok] - z))
+    assert err.max() <= 1e-5, (name, err.max())
+
+
+def test_screen_count_needs_a_screened_run():
+    c = yy.yy_create(0, torch.cuda.current_stream())
+    try:
+        with pytest.raises(yy.YYError):
+            yy.yy_screen_count(c)
+    finally:
+        yy.yy_destroy(c)
+
+
+def test_screened_long_source_range_windows(ctx):
+    """One source split of 160 tiles (three windows of the filtered pass, the last one
+    ragged), through the batch call's split cap, against the single-run call."""
+    from paper_2509_16896_amd import workloads as W
+    from paper_2509_16896_amd.batch import Batch
+    from paper_2509_16896_amd.filter import GpuFilter
+    w = W.Workload("win_r64_n20480", r=64, n=20480, dt=0.01, K=2, drift=W.F_COS, obs=W.H_CUBE, q=0.09, rho2=0.09,
+                   scales=(1.0, 2.0, 4.0), box_half=0.6, restart_every=2, R=0.3, seed=5)
+    dys = W.simulate(w)[1]
+    b = Batch([w], [dys], prec="bf16x3s", max_split=1)
+    try:
+        for _ in range(w.K):
+            b.step()
+        got = [host(t) for t in b.results(0)]
+    finally:
+        b.close()
+    f = GpuFilter(w, prec="bf16x3s")
+    try:
+        f.set_observations(dys)
+        f.init()
+        for k in range(1, w.K + 1):
+            f.step(k)
+        ref = [host(f.hist), host(f.logZ_hist), host(f.ess_hist)]
+    finally:
+        f.close()
+    for a, r in zip(got, ref):
+        assert np.all(np.isfinite(a))
+        # another split count changes only the summation order of the partial sums
+        assert np.allclose(a, r, rtol=1e-9, atol=1e-9)
