@@ -335,7 +335,7 @@ static yy_status build(yy_batch b) {
       }
       b_nb.push_back(nb);
       b_one.push_back(1);
-      b_r.push_back(nblk(r));
+      b_r.push_back(norm_final_blocks(r));
       A5.push_back({n, r, R.codes.as<uint32_t>(), R.mean.as<double>(), R.lo.as<double>(), R.hi.as<double>(), nullptr,
                     R.x.as<double>(), lwo, rflag});
     }

@@ -416,6 +416,7 @@ yy_status launch_batched(hipStream_t st, const norm_sumexp_args* A, const int* p
 yy_status launch_batched(hipStream_t st, const norm_logz_args* A, const int* pre, int nr, int total);
 yy_status launch_batched(hipStream_t st, const norm_weights_args* A, const int* pre, int nr, int total);
 yy_status launch_batched(hipStream_t st, const norm_final_args* A, const int* pre, int nr, int total);
+int norm_final_blocks(int32_t r);   // blocks of one k_norm_final launch
 yy_status launch_batched(hipStream_t st, const rs_local_args* A, const int* pre, int nr, int total);
 yy_status launch_batched(hipStream_t st, const rs_offsets_args* A, const int* pre, int nr, int total);
 yy_status launch_batched(hipStream_t st, const rs_add_args* A, const int* pre, int nr, int total);

@@ -246,22 +246,42 @@ __global__ void __launch_bounds__(kBlock) k_norm_weights_batch(const norm_weight
 }
 
 
+// Sums of the per-block partials in a fixed order: block bx_ takes coordinates
+// [kNormFinalK bx_, kNormFinalK (bx_ + 1)); its kNormFinalParts thread groups sum
+// interleaved partial rows, and the group sums are added in group order.
+constexpr int kNormFinalK = 32;
+constexpr int kNormFinalParts = kBlock / kNormFinalK;
+int norm_final_blocks(int32_t r) { return (r + kNormFinalK - 1) / kNormFinalK; }
+
 __device__ __forceinline__ void k_norm_final_body(int nb, int32_t r, const double* __restrict__ sc,
                                                        const double* __restrict__ pw2,
                                                        const double* __restrict__ pmean,
                                                        double* __restrict__ mean,
                                                        double* __restrict__ ess, int bx_, int gx_) {
+  __shared__ double sm[kNormFinalParts][kNormFinalK];
+  __shared__ double se[kBlock];
   if (sc[1] == 0.0) return;
-  const int k = bx_ * kBlock + threadIdx.x;
-  if (k < r) {
-    double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += pmean[(size_t)b * r + k];
-    mean[k] = s;
+  const int kk = threadIdx.x % kNormFinalK, part = threadIdx.x / kNormFinalK;
+  const int k = bx_ * kNormFinalK + kk;
+  double s = 0.0;
+  if (k < r)
+    for (int b = part; b < nb; b += kNormFinalParts) s += pmean[(size_t)b * r + k];
+  sm[part][kk] = s;
+  if (bx_ == 0) {
+    double e = 0.0;
+    for (int b = threadIdx.x; b < nb; b += kBlock) e += pw2[b];
+    se[threadIdx.x] = e;
+  }
+  __syncthreads();
+  if (part == 0 && k < r) {
+    double t = 0.0;
+    for (int p = 0; p < kNormFinalParts; ++p) t += sm[p][kk];
+    mean[k] = t;
   }
   if (bx_ == 0 && threadIdx.x == 0) {
-    double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += pw2[b];
-    *ess = 1.0 / s;
+    double t = 0.0;
+    for (int p = 0; p < kBlock; ++p) t += se[p];
+    *ess = 1.0 / t;
   }
 }
 
@@ -429,7 +449,7 @@ extern "C" yy_status yy_normalise_moments(yy_ctx ctx, int64_t n, int32_t r, cons
   YY_LAUNCH_CHECK("k_norm_logz");
   k_norm_weights<<<nb, kBlock, 0, ctx->stream>>>(n, r, rows, sc, x, logw, wbuf, pw2, pmean);
   YY_LAUNCH_CHECK("k_norm_weights");
-  k_norm_final<<<(r + kBlock - 1) / kBlock, kBlock, 0, ctx->stream>>>(nb, r, sc, pw2, pmean, mean, ess);
+  k_norm_final<<<norm_final_blocks(r), kBlock, 0, ctx->stream>>>(nb, r, sc, pw2, pmean, mean, ess);
   YY_LAUNCH_CHECK("k_norm_final");
   if (cov) {
     dim3 grid((r + 63) / 64, (r + 63) / 64);
