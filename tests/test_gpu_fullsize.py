@@ -7,6 +7,10 @@
   against the oracle's filter, and its RMSE beside the Kalman filter's.
 * Cubic sensor r=100, n=16384, a few steps with a restart: the chosen
   mixed-precision form and the FP32 form against the oracle's filter.
+* Cubic sensor r=1000, n=65536, four steps with two restarts: the chosen form's
+  posterior means against the plain FP32 form's (the oracle's filter takes
+  minutes per step at this size; the FP32 form matches it to 1e-5 on the
+  smaller workloads above).
 """
 import numpy as np
 import pytest
@@ -97,3 +101,22 @@ def test_cubic_r100_n16384_short_run():
         err = np.max(np.abs(means - ref["means"]))
         print(f"{prec}: max |mean - oracle| = {err:.3g}")
         assert err <= tol
+
+
+def test_cubic_r1000_n65536_chosen_form_means():
+    w = W.shrink(W.cubic_r1000(), K=4)
+    xs, dys = W.simulate(w)
+    fs = _gpu_filter(w, dys, "bf16x3s", w.K)
+    try:
+        got = fs.hist.cpu().numpy()
+    finally:
+        fs.close()
+    fp = _gpu_filter(w, dys, "fp32", w.K)
+    try:
+        ref = fp.hist.cpu().numpy()
+    finally:
+        fp.close()
+    err = np.max(np.abs(got - ref))
+    print(f"r=1000, n=65536, 4 steps: max |mean(bf16x3s) - mean(fp32)| = {err:.3g}")
+    assert np.all(np.isfinite(got))
+    assert err <= 1e-3

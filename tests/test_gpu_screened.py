@@ -24,12 +24,16 @@ def ctx():
     yy.yy_destroy(c)
 
 
-def _case(r, n, q, dt, half, seed, scales=(1.0, 2.0, 4.0)):
+def _case(r, n, q, dt, half, seed, scales=(1.0, 2.0, 4.0), stripes=0):
     rng = np.random.default_rng(seed)
     lo, hi = -half * np.ones(r), half * np.ones(r)
     codes = oracle.sobol_codes(r, n, 0, True, seed)
     x = oracle.codes_to_points(codes, lo, hi)
     lw = -3.0 * rng.random(n) - 0.5 * np.sum((x / half) ** 2, axis=1)
+    if stripes:
+        # every other run of `stripes` nodes 3000 below the rest: the screen rules out the tiles
+        # of heavy targets against light sources and keeps the others, an irregular tile pattern
+        lw -= 3000.0 * ((np.arange(n) // stripes) % 2)
     gm = yy.Model(r, r, yy.YY_F_COS, None, yy.YY_H_IDENTITY, None, 0.0, q, 1.0)
     om = oracle.OModel(r, r, oracle.F_COS, None, oracle.H_IDENTITY, None, 0.0, q, 1.0)
     return dict(r=r, n=n, x=x, lo=lo, hi=hi, lw=lw, gm=gm, om=om, dt=dt, scales=scales)
@@ -49,6 +53,8 @@ CASES = {
     "r96_n6000_mid": dict(r=96, n=6000, q=0.3, dt=0.02, half=0.3, seed=42),
     "r200_n5000_narrow": dict(r=200, n=5000, q=0.09, dt=0.005, half=0.3, seed=43),
     "r33_n3000_s1": dict(r=33, n=3000, q=0.5, dt=0.02, half=0.5, seed=44),
+    # a partial screen over source ranges longer than a 64-tile window (16 splits of 69 tiles)
+    "r32_n140000_stripes": dict(r=32, n=140000, q=1.0, dt=0.05, half=0.25, seed=45, stripes=2560),
 }
 
 
@@ -69,6 +75,8 @@ def test_screened_matches_split_form_and_oracle_rows(ctx, name):
     assert tiles == ((n + 255) // 256) * ((n + 127) // 128)
     assert 0 <= flagged <= tiles
     print(f"{name}: screen flagged {flagged} of {tiles} tiles")
+    if "stripes" in CASES[name]:
+        assert 0.2 * tiles < flagged < 0.9 * tiles
     # sampled rows against the oracle
     rng = np.random.default_rng(1)
     rows = np.unique(np.concatenate([[0, c["n"] - 1], rng.choice(c["n"], 24, replace=False)]))
