@@ -32,8 +32,9 @@ METRIC = "filter steps/sec + propagation TFLOP/s at r=1000,n=65536 vs plain FP32
 PEAK_TFLOPS = {"bf16x3": 2500.0, "bf16x3g": 2500.0, "bf16x3s": 2500.0, "bf16x1": 2500.0, "fp32_mfma": 157.3}
 VALU_FP32_PEAK = 78.6   # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz, packed FP32 disabled
 # matrix-core products executed per algorithmic product (x.x and x.f each count once); the
-# screened split form executes one per product everywhere plus the split form's two on the
-# tiles its screen flags (counted after the run)
+# screened split form's screen executes x.x only (the x.f term is bounded), half a product per
+# algorithmic product, plus the split form's two on the tiles the screen flags (counted after
+# the run)
 EXEC_PER_ALG = {"bf16x3": 3.0, "bf16x3g": 2.0, "bf16x1": 1.0, "fp32_mfma": 1.0}
 PAIR_SRC = os.path.join(ROOT, "paper_2509_16896_amd", "csrc", "yy_pair_mfma.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pair_mfma_cubic_r1000_n65536_traffic.md")
@@ -356,8 +357,8 @@ def main():
         from paper_2509_16896_amd import yy
         flagged, tiles = yy.yy_screen_count(f.ctx)
         screen = {"flagged_tiles": flagged, "tiles": tiles}
-        roofline["kernel"] = "k_pair_mfma (screen, then split form on flagged tiles)"
-        EXEC_PER_ALG["bf16x3s"] = 1.0 + 2.0 * flagged / max(tiles, 1)
+        roofline["kernel"] = "k_pair_screen, then k_pair_mfma (split form) on flagged tiles"
+        EXEC_PER_ALG["bf16x3s"] = 0.5 + 2.0 * flagged / max(tiles, 1)
         log(f"[bench] screen flagged {flagged} of {tiles} tiles for the split form")
     if mfma:
         # matrix-core utilisation: executed products (3 per product for the full split) / peak

@@ -64,12 +64,14 @@ struct MArgs {
   const double* node;          // [3][n]
   const double* scal;          // [1] = max |x - centre|, [2] = max |f|
   double eps_g, eps_h;         // relative error of one G / H product from operand rounding
-  double eps_g1, eps_h1;       // the same for the screen of the screened split form
+  double eps_g1;               // the same for G in the screen of the screened split form
   float2* part;                // [nsplit][S][n]
   int32_t nsplit, tb_count, group_t;
   int64_t j_per_split;
-  uint8_t* flags;              // screen verdicts [tb_count][jtl][8 waves] (screened split form)
+  uint8_t* flags;              // screen verdicts [tb_count][jtl][8]: byte w < 4 for targets 64w..64w+63, 4..7 zero
   int64_t jtl;                 // source tiles of 128
+  int32_t s_nsplit;            // the screen's source splits (of s_jps sources, a multiple of 256)
+  int64_t s_jps;
 };
 
 // Physical 16-byte chunk of logical chunk c in LDS row `row` (bank-conflict swizzle).
@@ -284,7 +286,7 @@ __device__ inline void merge_and_store(const MArgs& a, float (&M)[kIB][S], float
 // Rigorous bound on |e_approx - e_exact| in base-2 units: operand rounding,
 // worst-case FP32 accumulation over rp products, FP32 evaluation of e; the
 // margin adds the skip depth and 16 bits of safety.
-template <int S, bool SCREEN>
+template <int S>
 __device__ inline void init_targets(const MArgs& a, int64_t i0, int split, float (&at)[kIB][S],
                                     float (&M)[kIB][S], float (&Ssum)[kIB][S], float (&margin)[S]) {
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -294,8 +296,7 @@ __device__ inline void init_targets(const MArgs& a, int64_t i0, int split, float
 #pragma unroll
   for (int s = 0; s < S; ++s) {
     const double XT = X + a.taud[s] * F;
-    const double eg = SCREEN ? a.eps_g1 : a.eps_g, eh = SCREEN ? a.eps_h1 : a.eps_h;
-    const double dD = 2.0 * X * ((eg + gam) * X + (eh + gam) * a.taud[s] * F) + 16.0 * 0x1p-24 * XT * XT;
+    const double dD = 2.0 * X * ((a.eps_g + gam) * X + (a.eps_h + gam) * a.taud[s] * F) + 16.0 * 0x1p-24 * XT * XT;
     margin[s] = (float)(2.0 * a.kapd[s] * dD + (double)kSkip + 16.0);
   }
 #pragma unroll
@@ -545,53 +546,12 @@ struct StageShape {
   static constexpr int STAGE = (NTP * kMI + NSP * kMJ) * ROWB;       // bytes per LDS stage
 };
 
-// The screen's verdict on one finished tile for this wave (MODE 1): does any
-// slab of the wave's 64 targets x 64 sources reach within the margin of the
-// running lower bound of its row maximum?  The bound rises to every slab's
-// approximate maximum less the rigorous error of an approximate exponent.
-template <int S>
-__device__ __forceinline__ bool screen_tile(const MArgs& a, const f32x16_t (&G)[kIB][kJB],
-                                            const f32x16_t (&H)[kIB][kJB], const float* sb, int64_t i0,
-                                            int64_t j0, int wi, int wj, int col, int g, const float (&at)[kIB][S],
-                                            const float (&margin)[S], float (&M)[kIB][S]) {
-  const bool diag = j0 < i0 + kMI && i0 < j0 + kMJ;
-  const int jl0 = wj * (32 * kJB);
-  bool need = false;
-#pragma unroll
-  for (int ib = 0; ib < kIB; ++ib) {
-    const int64_t i = i0 + wi * (32 * kIB) + ib * 32 + col;
-    const int64_t d = i - j0 - jl0;
-    const bool self = diag && d >= 0 && d < 32 * kJB && (int)((d >> 2) & 1) == g;
-    const int bself = self ? (int)((d >> 5) * 16 + ((d >> 3) & 3) * 4 + (d & 3)) : -1;
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-      const float c1 = a.c1[s], c2 = a.c2[s];
-      float m = -INFINITY;
-#pragma unroll
-      for (int jb = 0; jb < kJB; ++jb)
-#pragma unroll
-        for (int v = 0; v < 16; ++v) {
-          const int jl = jb * 32 + 8 * (v >> 2) + 4 * g + (v & 3);
-          float e = fmaf(c2, H[ib][jb][v], fmaf(c1, G[ib][jb][v], at[ib][s] + sb[s * kMJ + jl0 + jl]));
-          if (jb * 16 + v == bself) e = -INFINITY;
-          m = fmaxf(m, e);
-        }
-      need |= m > M[ib][s] - margin[s];
-      // margin - kSkip - 16 is the error bound; one more bit of slack
-      M[ib][s] = fmaxf(M[ib][s], m - (margin[s] - kSkip - 15.f));
-    }
-  }
-  return __any(need);
-}
-
 // One block's work: targets [256 tb, 256 tb + 256) against the sources of split
 // `split`, partial (max, sum) to a.part.  smem, sbuf, rare and tl are the
 // block's LDS ring, bias buffers, rare-path parameters and tile list.
-// MODE 0: every tile.  MODE 1 (the screen): the products of every tile, no
-// partial results; one flag byte per (target block, source tile, wave) says
-// whether any of the wave's pairs may lie within the margin of its row
-// maximum.  MODE 2: only the tiles flagged by the screen, taken in windows of
-// kTileWindow tiles; the others hold no pair within 2^-80 of a row maximum.
+// MODE 0: every tile.  MODE 2: only the tiles flagged by the screen
+// (k_pair_screen below), taken in windows of kTileWindow tiles; the others
+// hold no pair within 2^-80 of a row maximum.
 constexpr int kTileWindow = 64;
 
 template <int S, int VAR, int NS, int SPB, int MODE>
@@ -625,7 +585,7 @@ __device__ __forceinline__ void pair_block(const MArgs& a, int tb, int split, un
   const uint32_t sb_lds = __builtin_amdgcn_readfirstlane(lds_addr(&sbuf[0][0]));
 
   float at[kIB][S], M[kIB][S], Ssum[kIB][S], margin[S];
-  init_targets<S, MODE == 1>(a, i0, split, at, M, Ssum, margin);
+  init_targets<S>(a, i0, split, at, M, Ssum, margin);
 
   for (int w0 = 0; w0 < ntiles_all; w0 += MODE == 2 ? kTileWindow : ntiles_all) {
     int ntiles = ntiles_all;
@@ -692,24 +652,19 @@ __device__ __forceinline__ void pair_block(const MArgs& a, int tb, int split, un
         }
       }
       const float* sb = &sbuf[t & 1][0];
-      if (MODE == 1) {
-        const bool flag = screen_tile<S>(a, G, H, sb, i0, j0, wi, wj, col, g, at, margin, M);
-        if (lane == 0) a.flags[((size_t)tb * a.jtl + jt0 + t) * 8 + wave] = flag ? 1 : 0;
-      } else {
-        const bool diag = j0 < i0 + kMI && i0 < j0 + kMJ;
+      const bool diag = j0 < i0 + kMI && i0 < j0 + kMJ;
 #pragma unroll
-        for (int ib = 0; ib < kIB; ++ib) {
-          const int64_t i = i0 + wi * (32 * kIB) + ib * 32 + col;
-          // keep one target's accumulators in flight at a time (register pressure)
-          __builtin_amdgcn_sched_barrier(0);
-          epilogue_target<S>(a, &rare, G[ib], H[ib], sb, i, j0, wj * (32 * kJB), g, diag, at[ib], margin, M[ib],
-                             Ssum[ib]);
-        }
+      for (int ib = 0; ib < kIB; ++ib) {
+        const int64_t i = i0 + wi * (32 * kIB) + ib * 32 + col;
+        // keep one target's accumulators in flight at a time (register pressure)
+        __builtin_amdgcn_sched_barrier(0);
+        epilogue_target<S>(a, &rare, G[ib], H[ib], sb, i, j0, wj * (32 * kJB), g, diag, at[ib], margin, M[ib],
+                           Ssum[ib]);
       }
       __builtin_amdgcn_sched_barrier(0);
     }
   }
-  if (MODE != 1) merge_and_store<S>(a, M, Ssum, i0, split, reinterpret_cast<float2*>(smem));
+  merge_and_store<S>(a, M, Ssum, i0, split, reinterpret_cast<float2*>(smem));
 }
 
 template <int S, int VAR, int NS, int SPB, int MODE>
@@ -735,6 +690,247 @@ __global__ void __launch_bounds__(kNT, 1) k_pair_mfma_batch(const MArgs* __restr
   const int4 it = items[blockIdx.x];
   pair_block<S, VAR, NS, SPB, MODE>(sets[__builtin_amdgcn_readfirstlane(it.x)], __builtin_amdgcn_readfirstlane(it.y),
                                     __builtin_amdgcn_readfirstlane(it.z), smem, sbuf, rare, tl);
+}
+
+// ---------------------------------------------------------------------------
+// The screen of the screened split form, on G = X X^T alone.  The tau-scaled
+// term is bounded instead of computed: |2 kap_s tau_s x_i.f_j| <= hx_i F with
+// hx_i = (log2 e / q) |x_i| (kap_s tau_s does not depend on s) and F = max_j
+// |f_j| (Cauchy-Schwarz), so
+//   e_exact <= a_i + hx_i F + b_js + 2 kap_s G~_ij + err_G,
+// err_G the rigorous error of the one-product G (operand rounding, FP32
+// accumulation and evaluation).  Without the H accumulators a wave holds 64
+// targets x 128 sources, so a block tile is 256 x 256 and one 16-wide K stage
+// (the hi planes of x only) is 16 KB: half the bytes and half the products per
+// pair of a screen that also forms H.  A wave's 64 x 128 sub-tile is one
+// 128-source tile of the split pass, whose flag byte the wave writes.
+constexpr int kSJ = 256;                      // sources per screen tile
+constexpr int kSJB = kSJ / (32 * kWJ);        // 32-wide source blocks per wave
+constexpr int kSStage = (kMI + kSJ) * 32;     // bytes per LDS stage (hi(x) of targets and sources)
+constexpr int kSBRows = 4;                    // bias rows per screen tile (up to 4 scales)
+static_assert(kWaves == 8, "the screen tile assumes 8 waves");
+
+struct SFrag {
+  bf16x8_t bh[kIB], xh[kSJB];
+};
+
+__device__ inline void screen_load_frags(const unsigned char* base, SFrag& f, int wave) {
+  constexpr int ROWB = 32;
+  const int lane = fresh_lane();
+  const int wi = wave / kWJ, wj = wave % kWJ, col = lane & 31, g = lane >> 5;
+#pragma unroll
+  for (int ib = 0; ib < kIB; ++ib) {
+    const int row = wi * (32 * kIB) + ib * 32 + col;
+    f.bh[ib] = *reinterpret_cast<const bf16x8_t*>(base + row * ROWB + swz<2>(row, g) * 16);
+  }
+#pragma unroll
+  for (int jb = 0; jb < kSJB; ++jb) {
+    const int row = wj * (32 * kSJB) + jb * 32 + col;
+    f.xh[jb] = *reinterpret_cast<const bf16x8_t*>(base + kMI * ROWB + row * ROWB + swz<2>(row, g) * 16);
+  }
+}
+
+__device__ inline void screen_mma(const SFrag& f, f32x16_t (&G)[kIB][kSJB]) {
+#pragma unroll
+  for (int ib = 0; ib < kIB; ++ib)
+#pragma unroll
+    for (int jb = 0; jb < kSJB; ++jb)
+      G[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.xh[jb], f.bh[ib], G[ib][jb], 0, 0, 0);
+}
+
+// One screen stage: 8 target and 8 source regions of 1 KB (32 rows of hi(x)),
+// two per wave.
+__device__ inline void screen_issue_stage(const unsigned char* gb, int64_t n_pad, uint32_t stage_lds, int c,
+                                          int64_t i0, int64_t j0, int wave) {
+  constexpr int ROWB = 32;
+  const int lane = fresh_lane(), rl = lane >> 1, pc = lane & 1;
+  const int loff = rl * ROWB + swz<2>(rl, pc) * 16;
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int q = wave + 8 * u;   // wave-uniform: 0..7 targets, 8..15 sources
+    const int64_t row0 = (u == 0 ? i0 : j0) + (q & 7) * 32;
+    dma_1k(gb + ((uint64_t)c * (uint64_t)n_pad + (uint64_t)row0) * ROWB + loff, stage_lds + q * 1024);
+  }
+}
+
+// Source biases of the S scales of screen tile j0 (wave 0): [S][256] floats.
+__device__ inline void screen_issue_bias(const MArgs& a, uint32_t sb_lds, int64_t j0, int wave) {
+  if (wave != 0) return;
+  const int lane = fresh_lane();
+  for (int s = 0; s < a.S; ++s) dma_1k(a.bsrc + (size_t)s * a.n_pad + j0 + 4 * lane, sb_lds + s * 1024);
+}
+
+template <int S, int NS, int SPB>
+__device__ __forceinline__ void screen_block(const MArgs& a, int tb, int split, unsigned char* smem,
+                                             float (*sbuf)[kSBRows * kSJ]) {
+  static_assert(NS % SPB == 0 && NS / SPB >= 2, "the ring holds at least two groups of stages");
+  constexpr int LA = NS / SPB - 1;
+  constexpr int L = 2;   // copies per wave per stage
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wi = wave / kWJ, wj = wave % kWJ, col = lane & 31, g = lane >> 5;
+  const int64_t i0 = (int64_t)tb * kMI;
+  const int64_t jb0 = (int64_t)split * a.s_jps;
+  const int64_t jb1 = jb0 + a.s_jps < a.n ? jb0 + a.s_jps : a.n;
+  const int ntiles = __builtin_amdgcn_readfirstlane(jb1 > jb0 ? (int)((jb1 - jb0 + kSJ - 1) / kSJ) : 0);
+  if (ntiles == 0) return;
+  const int nchunks = __builtin_amdgcn_readfirstlane(a.rp / kKC);
+  const int Q = ntiles * nchunks;
+  const unsigned char* gb = reinterpret_cast<const unsigned char*>(a.bf);
+  const int64_t n_pad = a.n_pad;
+  const uint32_t smem_lds = __builtin_amdgcn_readfirstlane(lds_addr(smem));
+  const uint32_t sb_lds = __builtin_amdgcn_readfirstlane(lds_addr(&sbuf[0][0]));
+  constexpr uint32_t kSbBytes = kSBRows * kSJ * 4;
+
+  // per target and scale: a_i + hx_i F, the running lower bound of the row
+  // maximum (the exact self-pair exponent to start) and the slack of its
+  // update (the error of G and twice the bound of the x.f term); per scale the
+  // margin (the error of G, the skip depth and 16 bits)
+  const double X = a.scal[1], F = a.scal[2];
+  const double gam = a.rp * 0x1p-24;
+  float at[kIB][S], M[kIB][S], margin[S], slack[kIB][S];
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const double XT = X + a.taud[s] * F;
+    const double dD = 2.0 * X * (a.eps_g1 + gam) * X + 16.0 * 0x1p-24 * XT * XT;
+    margin[s] = (float)(2.0 * a.kapd[s] * dD + (double)kSkip + 16.0);
+  }
+#pragma unroll
+  for (int ib = 0; ib < kIB; ++ib) {
+    const int64_t i = i0 + wi * (32 * kIB) + ib * 32 + col;
+    const bool valid = i < a.n;
+    const double nx = valid ? a.node[i] : 0.0;
+    const double nf = valid ? a.node[a.n + i] : 0.0;
+    const float li = valid ? a.lw2[i] : -INFINITY;
+    // hx_i F with 2 kap_s tau_s = log2(e) / q for every s, rounded up
+    const double hF = 2.0 * a.kapd[0] * a.taud[0] * sqrt(nx) * F * (1.0 + 0x1p-20);
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      at[ib][s] = valid ? (float)(-a.kapd[s] * nx + hF) : -INFINITY;
+      M[ib][s] = (valid && li != -INFINITY) ? li - (float)(a.kapd[s] * a.taud[s] * a.taud[s] * nf) : -INFINITY;
+      slack[ib][s] = (float)((double)margin[s] - kSkip - 15.0 + 2.0 * hF);
+    }
+  }
+
+  screen_issue_bias(a, sb_lds, jb0, wave);
+#pragma unroll
+  for (int p = 0; p < LA * SPB; ++p)
+    if (p < Q) screen_issue_stage(gb, n_pad, smem_lds + p * kSStage, p % nchunks, i0, jb0 + (int64_t)(p / nchunks) * kSJ,
+                                  wave);
+
+  for (int t = 0; t < ntiles; ++t) {
+    const int64_t j0 = jb0 + (int64_t)t * kSJ;
+    f32x16_t G[kIB][kSJB];
+#pragma unroll
+    for (int x = 0; x < kIB; ++x)
+#pragma unroll
+      for (int y = 0; y < kSJB; ++y)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) G[x][y][v] = 0.f;
+    for (int c = 0; c < nchunks; c += SPB) {
+      const int q = t * nchunks + c;
+      if (q + LA * SPB - 1 < Q) wait_vmcnt<(LA - 1) * SPB * L>();
+      else wait_vmcnt<0>();
+      __syncthreads();
+      if (c == 0 && t + 1 < ntiles) screen_issue_bias(a, sb_lds + ((t + 1) & 1) * kSbBytes, j0 + kSJ, wave);
+#pragma unroll
+      for (int u = 0; u < SPB; ++u) {
+        const int qn = q + LA * SPB + u;
+        if (qn < Q) {
+          const int tn = qn / nchunks;
+          screen_issue_stage(gb, n_pad, smem_lds + (qn % NS) * kSStage, qn - tn * nchunks, i0,
+                             jb0 + (int64_t)tn * kSJ, wave);
+        }
+      }
+      SFrag fr[2];
+      screen_load_frags(smem + (q % NS) * kSStage, fr[0], wave);
+#pragma unroll
+      for (int u = 0; u < SPB; ++u) {
+        if (u + 1 < SPB) screen_load_frags(smem + ((q + u + 1) % NS) * kSStage, fr[(u + 1) & 1], wave);
+        screen_mma(fr[u & 1], G);
+      }
+    }
+    // the verdict on this wave's 64 x 128 sub-tile
+    const float* sb = &sbuf[t & 1][0];
+    const bool diag = j0 < i0 + kMI && i0 < j0 + kSJ;
+    const int jl0 = wj * (32 * kSJB);
+    bool need = false;
+    int bself[kIB];   // slab index jb * 16 + v of the self pair in this lane (-1: none)
+#pragma unroll
+    for (int ib = 0; ib < kIB; ++ib) {
+      const int64_t d = i0 + wi * (32 * kIB) + ib * 32 + col - j0 - jl0;
+      const bool self = diag && d >= 0 && d < 32 * kSJB && (int)((d >> 2) & 1) == g;
+      bself[ib] = self ? (int)((d >> 5) * 16 + ((d >> 3) & 3) * 4 + (d & 3)) : -1;
+    }
+    // scales outermost: each source bias is read once for both target blocks
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const float c1 = a.c1[s];
+      float m[kIB];
+#pragma unroll
+      for (int ib = 0; ib < kIB; ++ib) m[ib] = -INFINITY;
+#pragma unroll
+      for (int jb = 0; jb < kSJB; ++jb) {
+        __builtin_amdgcn_sched_barrier(0);   // one 32-source block's biases in flight at a time
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const float bj = sb[s * kSJ + jl0 + jb * 32 + 8 * (v >> 2) + 4 * g + (v & 3)];
+#pragma unroll
+          for (int ib = 0; ib < kIB; ++ib) {
+            float e = fmaf(c1, G[ib][jb][v], at[ib][s] + bj);
+            if (jb * 16 + v == bself[ib]) e = -INFINITY;
+            m[ib] = fmaxf(m[ib], e);
+          }
+        }
+      }
+#pragma unroll
+      for (int ib = 0; ib < kIB; ++ib) {
+        need |= m[ib] > M[ib][s] - margin[s];
+        M[ib][s] = fmaxf(M[ib][s], m[ib] - slack[ib][s]);
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    const bool flag = __any(need);
+    const int64_t jt = j0 / kMJ + wj;   // the split pass's 128-source tile of this sub-tile
+    if (lane == 0 && jt < a.jtl) {
+      a.flags[((size_t)tb * a.jtl + jt) * 8 + wi] = flag ? 1 : 0;
+      a.flags[((size_t)tb * a.jtl + jt) * 8 + 4 + wi] = 0;
+    }
+  }
+}
+
+__device__ inline void screen_block_map(const MArgs& a, int& tb, int& split) {
+  const int b = blockIdx.x;
+  const int per_xcd = a.tb_count / 8;
+  if (a.group_t > 0 && per_xcd > 0 && per_xcd * 8 == a.tb_count && per_xcd % a.group_t == 0) {
+    const int xcd = b % 8, slot = b / 8;
+    const int gsz = a.group_t * a.s_nsplit;
+    const int grp = slot / gsz, rem = slot % gsz;
+    tb = xcd * per_xcd + grp * a.group_t + rem % a.group_t;
+    split = rem / a.group_t;
+  } else {
+    tb = b / a.s_nsplit;
+    split = b % a.s_nsplit;
+  }
+}
+
+template <int S, int NS, int SPB>
+__global__ void __launch_bounds__(kNT, 1) k_pair_screen(MArgs a) {
+  __shared__ __attribute__((aligned(1024))) unsigned char smem[NS * kSStage];
+  __shared__ __attribute__((aligned(1024))) float sbuf[2][kSBRows * kSJ];
+  int tb, split;
+  screen_block_map(a, tb, split);
+  screen_block<S, NS, SPB>(a, tb, split, smem, sbuf);
+}
+
+template <int S, int NS, int SPB>
+__global__ void __launch_bounds__(kNT, 1) k_pair_screen_batch(const MArgs* __restrict__ sets,
+                                                              const int4* __restrict__ items) {
+  __shared__ __attribute__((aligned(1024))) unsigned char smem[NS * kSStage];
+  __shared__ __attribute__((aligned(1024))) float sbuf[2][kSBRows * kSJ];
+  const int4 it = items[blockIdx.x];
+  screen_block<S, NS, SPB>(sets[__builtin_amdgcn_readfirstlane(it.x)], __builtin_amdgcn_readfirstlane(it.y),
+                           __builtin_amdgcn_readfirstlane(it.z), smem, sbuf);
 }
 
 // ---------------------------------------------------------------------------
@@ -781,13 +977,12 @@ static MArgs make_args(const PairArgs& pa, int prec, const MfmaExtra& ex) {
   m.S = pa.S;
   // hi/lo split product: 2^-16 per operand split plus cross terms; hi only:
   // 2^-8 per operand; FP32 operands: 2^-24 per operand (rounded up).
-  // The screened split form: the BF16X3G bounds, and the BF16X1 bounds for its screen.
+  // The screened split form: the BF16X3G bounds, and the one-product bound of G for its screen.
   const bool split_g = prec == YY_PREC_BF16X3 || prec == YY_PREC_BF16X3G || prec == YY_PREC_BF16X3S;
   const bool hi_h = prec == YY_PREC_BF16X3G || prec == YY_PREC_BF16X3S || prec == YY_PREC_BF16X1;
   m.eps_g = split_g ? 0x1p-14 : prec == YY_PREC_BF16X1 ? 0x1p-7 : 0x1p-22;
   m.eps_h = prec == YY_PREC_BF16X3 ? 0x1p-14 : hi_h ? 0x1p-7 : 0x1p-22;
   m.eps_g1 = 0x1p-7;
-  m.eps_h1 = 0x1p-7;
   for (int s = 0; s < pa.S; ++s) {
     const double kap = ex.kapd[s], tau = ex.taud[s];
     m.kap[s] = (float)kap;
@@ -812,6 +1007,8 @@ static MArgs make_args(const PairArgs& pa, int prec, const MfmaExtra& ex) {
   m.j_per_split = ex.j_per_split;
   m.flags = ex.flags;
   m.jtl = (pa.n + kMJ - 1) / kMJ;
+  m.s_nsplit = pa.nsplit;
+  m.s_jps = ((ex.j_per_split + kSJ - 1) / kSJ) * kSJ;
   return m;
 }
 
@@ -829,7 +1026,7 @@ static yy_status launch_batch_s(hipStream_t st, const MArgs* sets, const int4* i
   } else if (prec == YY_PREC_BF16X3G) {
     k_pair_mfma_batch<S, 2, 4, 2, 0><<<nitems, kNT, 0, st>>>(sets, items);
   } else if (prec == YY_PREC_BF16X3S) {
-    k_pair_mfma_batch<S, 1, 8, 4, 1><<<nitems, kNT, 0, st>>>(sets, items);
+    k_pair_screen_batch<S, 8, 4><<<nitems, kNT, 0, st>>>(sets, items);
     YY_LAUNCH_CHECK("k_pair_mfma_batch (screen)");
     k_pair_mfma_batch<S, 2, 4, 2, 2><<<nitems, kNT, 0, st>>>(sets, items);
   } else if (prec == YY_PREC_BF16X1) {
@@ -849,7 +1046,7 @@ static yy_status launch_s(hipStream_t st, const MArgs& m, int prec, int nblocks)
     k_pair_mfma<S, 2, 4, 2, 0><<<nblocks, kNT, 0, st>>>(m);
   } else if (prec == YY_PREC_BF16X3S) {
     // the screen over every tile, then the split form over the flagged tiles
-    k_pair_mfma<S, 1, 8, 4, 1><<<nblocks, kNT, 0, st>>>(m);
+    k_pair_screen<S, 8, 4><<<nblocks, kNT, 0, st>>>(m);
     YY_LAUNCH_CHECK("k_pair_mfma (screen)");
     k_pair_mfma<S, 2, 4, 2, 2><<<nblocks, kNT, 0, st>>>(m);
   } else if (prec == YY_PREC_BF16X1) {
