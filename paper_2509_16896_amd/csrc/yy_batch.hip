@@ -120,6 +120,7 @@ struct yy_batch_s {
   // the pairwise launch
   yy::DevBuf d_sets, d_items;
   int nitems = 0;
+  bool k64 = true;                 // every run's K padding is a multiple of 64
   yy::BLaunch<int> src_bias;       // argument sets = d_sets
   // parity-dependent launches (index k % 2 of the step)
   yy::BLaunch<yy::lw_max_args> lw_max[2];
@@ -272,6 +273,8 @@ static yy_status build(yy_batch b) {
   if ((st = upload(b, b->d_sets, sets.data(), sets.size())) != YY_OK) return st;
   if ((st = upload(b, b->d_items, it4.data(), it4.size() * sizeof(int4))) != YY_OK) return st;
   b->nitems = (int)items.size();
+  b->k64 = true;
+  for (const BRun& R : b->runs) b->k64 = b->k64 && R.plan.a.rp % 64 == 0;
   if ((st = build_launch(b, b->src_bias, std::vector<int>{}, bias_blocks)) != YY_OK) return st;
 
   const BCtl* ctl = b->ctl.as<BCtl>();
@@ -434,7 +437,7 @@ static yy_status batch_step_impl(yy_batch b) {
                                   b->src_bias.total)) != YY_OK)
     return st;
   if ((st = timing_begin(b->ctx)) != YY_OK) return st;
-  if ((st = launch_pair_mfma_batch(strm, b->S, b->prec, b->d_sets.ptr, b->d_items.as<int4>(), b->nitems)) != YY_OK)
+  if ((st = launch_pair_mfma_batch(strm, b->S, b->prec, b->d_sets.ptr, b->d_items.as<int4>(), b->nitems, b->k64)) != YY_OK)
     return st;
   if ((st = timing_end(b->ctx)) != YY_OK) return st;
   if ((st = run_launch(b, b->combine[par])) != YY_OK) return st;
@@ -740,11 +743,11 @@ extern "C" yy_status yy_batch_tune(yy_batch b, int32_t reps, int32_t* best_out) 
   for (int cand = 1; cand <= 64 && s == YY_OK; cand *= 2) {
     b->max_split = cand;
     if ((s = build(b)) != YY_OK) break;
-    if ((s = launch_pair_mfma_batch(st, b->S, b->prec, b->d_sets.ptr, b->d_items.as<int4>(), b->nitems)) != YY_OK)
+    if ((s = launch_pair_mfma_batch(st, b->S, b->prec, b->d_sets.ptr, b->d_items.as<int4>(), b->nitems, b->k64)) != YY_OK)
       break;
     if (hipEventRecord(e0, st) != hipSuccess) { s = fail(YY_ERR_HIP, "yy_batch_tune: event"); break; }
     for (int q = 0; q < reps && s == YY_OK; ++q)
-      s = launch_pair_mfma_batch(st, b->S, b->prec, b->d_sets.ptr, b->d_items.as<int4>(), b->nitems);
+      s = launch_pair_mfma_batch(st, b->S, b->prec, b->d_sets.ptr, b->d_items.as<int4>(), b->nitems, b->k64);
     if (s != YY_OK) break;
     if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
       s = fail(YY_ERR_HIP, "yy_batch_tune: event");

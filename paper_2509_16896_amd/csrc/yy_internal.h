@@ -161,7 +161,9 @@ yy_status launch_pair_mfma(hipStream_t st, const PairArgs& a, int prec, const Mf
 // items[b] = (set, target block, source split, cost).
 size_t pair_mfma_args_bytes();
 void pair_mfma_fill_args(const PairArgs& pa, int prec, const MfmaExtra& ex, void* out);
-yy_status launch_pair_mfma_batch(hipStream_t st, int S, int prec, const void* sets, const int4* items, int nitems);
+// k64: every set's K padding is a multiple of 64 (the screen's four-stage groups)
+yy_status launch_pair_mfma_batch(hipStream_t st, int S, int prec, const void* sets, const int4* items, int nitems,
+                                 bool k64);
 
 // (4) combination in FP64: merge the source splits, add the constants, signed
 // log-sum-exp over the scales and the identity term.

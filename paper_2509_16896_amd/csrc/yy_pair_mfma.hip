@@ -622,8 +622,10 @@ __device__ __forceinline__ void pair_block(const MArgs& a, int tb, int split, un
       zero_acc<S>(G, H);
       for (int c = 0; c < nchunks; c += SPB) {
         const int q = t * nchunks + c;
-        // this wave's copies of steps q .. q+SPB-1 have landed (the later groups may still fly) ...
-        if (q + LA * SPB - 1 < Q) wait_vmcnt<(LA - 1) * SPB * L>();
+        // this wave's copies of steps q .. q+SPB-1 have landed (the later groups
+        // may still fly, unless a tile has so few groups that the copies waited
+        // for here were issued before the biases of the tile ending here) ...
+        if (q + LA * SPB - 1 < Q && 2 * (nchunks / SPB) - 1 >= LA) wait_vmcnt<(LA - 1) * SPB * L>();
         else wait_vmcnt<0>();
         __syncthreads();   // ... for every wave; the previous group's stages are free again
         if (c == 0 && t + 1 < ntiles)
@@ -829,9 +831,12 @@ __device__ __forceinline__ void screen_block(const MArgs& a, int tb, int split, 
         for (int v = 0; v < 16; ++v) G[x][y][v] = 0.f;
     for (int c = 0; c < nchunks; c += SPB) {
       const int q = t * nchunks + c;
-      if (q + LA * SPB - 1 < Q) wait_vmcnt<(LA - 1) * SPB * L>();
+      // this wave's copies of the group have landed (later groups may still fly,
+      // unless a tile has so few groups that the copies waited for here were
+      // issued before the biases of the tile ending at this group) ...
+      if (q + LA * SPB - 1 < Q && 2 * (nchunks / SPB) - 1 >= LA) wait_vmcnt<(LA - 1) * SPB * L>();
       else wait_vmcnt<0>();
-      __syncthreads();
+      __syncthreads();   // ... for every wave
       if (c == 0 && t + 1 < ntiles) screen_issue_bias(a, sb_lds + ((t + 1) & 1) * kSbBytes, j0 + kSJ, wave);
 #pragma unroll
       for (int u = 0; u < SPB; ++u) {
@@ -1020,13 +1025,16 @@ yy_status launch_src_bias(hipStream_t st, const PairArgs& pa, const MfmaExtra& e
 }
 
 template <int S>
-static yy_status launch_batch_s(hipStream_t st, const MArgs* sets, const int4* items, int nitems, int prec) {
+static yy_status launch_batch_s(hipStream_t st, const MArgs* sets, const int4* items, int nitems, int prec,
+                                bool k64) {
   if (prec == YY_PREC_BF16X3) {
     k_pair_mfma_batch<S, 3, 4, 2, 0><<<nitems, kNT, 0, st>>>(sets, items);
   } else if (prec == YY_PREC_BF16X3G) {
     k_pair_mfma_batch<S, 2, 4, 2, 0><<<nitems, kNT, 0, st>>>(sets, items);
   } else if (prec == YY_PREC_BF16X3S) {
-    k_pair_screen_batch<S, 8, 4><<<nitems, kNT, 0, st>>>(sets, items);
+    // four K stages per barrier when every K padding allows it, else two
+    if (k64) k_pair_screen_batch<S, 8, 4><<<nitems, kNT, 0, st>>>(sets, items);
+    else k_pair_screen_batch<S, 8, 2><<<nitems, kNT, 0, st>>>(sets, items);
     YY_LAUNCH_CHECK("k_pair_mfma_batch (screen)");
     k_pair_mfma_batch<S, 2, 4, 2, 2><<<nitems, kNT, 0, st>>>(sets, items);
   } else if (prec == YY_PREC_BF16X1) {
@@ -1046,7 +1054,9 @@ static yy_status launch_s(hipStream_t st, const MArgs& m, int prec, int nblocks)
     k_pair_mfma<S, 2, 4, 2, 0><<<nblocks, kNT, 0, st>>>(m);
   } else if (prec == YY_PREC_BF16X3S) {
     // the screen over every tile, then the split form over the flagged tiles
-    k_pair_screen<S, 8, 4><<<nblocks, kNT, 0, st>>>(m);
+    // four K stages per barrier when the K padding allows it, else two
+    if (m.rp % 64 == 0) k_pair_screen<S, 8, 4><<<nblocks, kNT, 0, st>>>(m);
+    else k_pair_screen<S, 8, 2><<<nblocks, kNT, 0, st>>>(m);
     YY_LAUNCH_CHECK("k_pair_mfma (screen)");
     k_pair_mfma<S, 2, 4, 2, 2><<<nblocks, kNT, 0, st>>>(m);
   } else if (prec == YY_PREC_BF16X1) {
@@ -1084,14 +1094,15 @@ void pair_mfma_fill_args(const PairArgs& pa, int prec, const MfmaExtra& ex, void
   std::memcpy(out, &m, sizeof(MArgs));
 }
 
-yy_status launch_pair_mfma_batch(hipStream_t st, int S, int prec, const void* sets, const int4* items, int nitems) {
+yy_status launch_pair_mfma_batch(hipStream_t st, int S, int prec, const void* sets, const int4* items, int nitems,
+                                 bool k64) {
   if (nitems <= 0) return YY_OK;
   const MArgs* m = static_cast<const MArgs*>(sets);
   switch (S) {
-    case 1: return launch_batch_s<1>(st, m, items, nitems, prec);
-    case 2: return launch_batch_s<2>(st, m, items, nitems, prec);
-    case 3: return launch_batch_s<3>(st, m, items, nitems, prec);
-    case 4: return launch_batch_s<4>(st, m, items, nitems, prec);
+    case 1: return launch_batch_s<1>(st, m, items, nitems, prec, k64);
+    case 2: return launch_batch_s<2>(st, m, items, nitems, prec, k64);
+    case 3: return launch_batch_s<3>(st, m, items, nitems, prec, k64);
+    case 4: return launch_batch_s<4>(st, m, items, nitems, prec, k64);
   }
   return fail(YY_ERR_UNSUPPORTED, "the matrix-core path supports up to 4 scales");
 }

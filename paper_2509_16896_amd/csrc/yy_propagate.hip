@@ -477,9 +477,10 @@ __global__ void __launch_bounds__(kBlock) k_combine_batch(const combine_args* __
 // ---------------------------------------------------------------------------
 // K of the prepared node set: r zero-padded to whole groups of 16-wide K
 // stages of the pairwise kernel (2 stages per barrier; 4 for BF16X1, the
-// screen of BF16X3S and the vector-ALU form).
+// vector-ALU form and the screen of BF16X3S at r > 256, where the padding to 64
+// costs at most a few percent).
 int pair_mfma_rp(int32_t r, int32_t prec) {
-  const int q = (prec == YY_PREC_BF16X1 || prec == YY_PREC_BF16X3S || prec == YY_PREC_FP32) ? 64 : 32;
+  const int q = (prec == YY_PREC_BF16X1 || prec == YY_PREC_FP32 || (prec == YY_PREC_BF16X3S && r > 256)) ? 64 : 32;
   return ((r + q - 1) / q) * q;
 }
 
