@@ -20,6 +20,7 @@
 //   BF16X3G: the split for G only; H, which enters scaled by tau_s, is hi*hi,
 //   BF16X1:  hi*hi only (a screen),  FP32: v_mfma_f32_32x32x2_f32 on FP32 data.
 #include <cstring>
+#include <type_traits>
 
 #include "yy_common.h"
 #include "yy_internal.h"
@@ -867,32 +868,66 @@ __device__ __forceinline__ void screen_block(const MArgs& a, int tb, int split, 
       const bool self = diag && d >= 0 && d < 32 * kSJB && (int)((d >> 2) & 1) == g;
       bself[ib] = self ? (int)((d >> 5) * 16 + ((d >> 3) & 3) * 4 + (d & 3)) : -1;
     }
-    // scales outermost: each source bias is read once for both target blocks
+    // scales outermost: each source bias is read once for both target blocks;
+    // the per-target term a_i + hx_i F is added after the maximum, and only a
+    // tile that holds self pairs compares slab indices
+    auto scan = [&](auto with_self) {
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
-      const float c1 = a.c1[s];
-      float m[kIB];
+      for (int s = 0; s < S; ++s) {
+        const float c1 = a.c1[s];
+        float m[kIB];
 #pragma unroll
-      for (int ib = 0; ib < kIB; ++ib) m[ib] = -INFINITY;
+        for (int ib = 0; ib < kIB; ++ib) m[ib] = -INFINITY;
 #pragma unroll
-      for (int jb = 0; jb < kSJB; ++jb) {
-        __builtin_amdgcn_sched_barrier(0);   // one 32-source block's biases in flight at a time
+        for (int jb = 0; jb < kSJB; ++jb) {
+          __builtin_amdgcn_sched_barrier(0);   // one 32-source block's biases in flight at a time
 #pragma unroll
-        for (int v = 0; v < 16; ++v) {
-          const float bj = sb[s * kSJ + jl0 + jb * 32 + 8 * (v >> 2) + 4 * g + (v & 3)];
+          for (int v = 0; v < 16; ++v) {
+            const float bj = sb[s * kSJ + jl0 + jb * 32 + 8 * (v >> 2) + 4 * g + (v & 3)];
 #pragma unroll
-          for (int ib = 0; ib < kIB; ++ib) {
-            float e = fmaf(c1, G[ib][jb][v], at[ib][s] + bj);
-            if (jb * 16 + v == bself[ib]) e = -INFINITY;
-            m[ib] = fmaxf(m[ib], e);
+            for (int ib = 0; ib < kIB; ++ib) {
+              float e = fmaf(c1, G[ib][jb][v], bj);
+              if (decltype(with_self)::value && jb * 16 + v == bself[ib]) e = -INFINITY;
+              m[ib] = fmaxf(m[ib], e);
+            }
           }
         }
-      }
 #pragma unroll
-      for (int ib = 0; ib < kIB; ++ib) {
-        need |= m[ib] > M[ib][s] - margin[s];
-        M[ib][s] = fmaxf(M[ib][s], m[ib] - slack[ib][s]);
+        for (int ib = 0; ib < kIB; ++ib) {
+          const float mt = m[ib] + at[ib][s];
+          need |= mt > M[ib][s] - margin[s];
+          M[ib][s] = fmaxf(M[ib][s], mt - slack[ib][s]);
+        }
       }
+    };
+    // A coarse bound first: max_j (c1 G_ij + b_js) <= c1 max_j G_ij + max_j b_js
+    // over the wave's 128 sources; the slab scan runs only if it leaves a doubt
+    // in some lane (always on a tile holding self pairs, whose G_ii dominates).
+    float gmax[kIB];
+#pragma unroll
+    for (int ib = 0; ib < kIB; ++ib) {
+      float m = -INFINITY;
+#pragma unroll
+      for (int jb = 0; jb < kSJB; ++jb)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) m = fmaxf(m, G[ib][jb][v]);
+      gmax[ib] = m;
+    }
+    // (read through the scalar cache: the address is wave-uniform, and a vector
+    // load would make its wait count the stage copies in flight)
+    typedef const __attribute__((address_space(4))) float* const_f32_ptr;
+    const const_f32_ptr bmax =
+        (const_f32_ptr)(a.bsrc + (size_t)S * n_pad + (size_t)(j0 / kMJ + wj));   // scale s at s (n_pad / 128)
+    bool doubt = false;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const float bm = bmax[(size_t)s * (n_pad / kMJ)];
+#pragma unroll
+      for (int ib = 0; ib < kIB; ++ib) doubt |= fmaf(a.c1[s], gmax[ib], bm) + at[ib][s] > M[ib][s] - margin[s];
+    }
+    if (__any(doubt)) {
+      if (diag) scan(std::true_type{});
+      else scan(std::false_type{});
     }
     __builtin_amdgcn_sched_barrier(0);
     const bool flag = __any(need);
@@ -939,11 +974,14 @@ __global__ void __launch_bounds__(kNT, 1) k_pair_screen_batch(const MArgs* __res
 }
 
 // ---------------------------------------------------------------------------
-// Source biases b_js = lw2_j - kap_s |m_j^s|^2 (FP64 -> FP32), -inf for invalid sources.
+// Source biases b_js = lw2_j - kap_s |m_j^s|^2 (FP64 -> FP32), -inf for invalid
+// sources: out[s][n_pad]; then the maximum over each 128 consecutive sources,
+// out[S n_pad + s (n_pad / 128) + block] (the screen's coarse bound).  n_pad is
+// a multiple of the 256 threads of a block.
 __device__ __forceinline__ void k_src_bias_body(int64_t n, int64_t n_pad, int32_t S,
                                                      MArgs a, float* __restrict__ out, int bx_, int gx_) {
+  __shared__ double sh[kBlock / 64];
   const int64_t j = (int64_t)bx_ * kBlock + threadIdx.x;
-  if (j >= n_pad) return;
   for (int s = 0; s < S; ++s) {
     float v = -INFINITY;
     if (j < n) {
@@ -954,7 +992,14 @@ __device__ __forceinline__ void k_src_bias_body(int64_t n, int64_t n_pad, int32_
         v = (float)((double)l - a.kapd[s] * nm);
       }
     }
-    out[(size_t)s * n_pad + j] = v;
+    if (j < n_pad) out[(size_t)s * n_pad + j] = v;
+    const double wm = wave_max((double)v);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = wm;
+    __syncthreads();
+    if (threadIdx.x < 2 && (int64_t)bx_ * kBlock + 128 * threadIdx.x < n_pad)
+      out[(size_t)S * n_pad + (size_t)s * (n_pad / 128) + (size_t)bx_ * 2 + threadIdx.x] =
+          (float)fmax(sh[2 * threadIdx.x], sh[2 * threadIdx.x + 1]);
+    __syncthreads();
   }
 }
 

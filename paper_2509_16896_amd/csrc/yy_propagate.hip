@@ -692,7 +692,7 @@ yy_status propagate_begin(yy_ctx ctx, const yy_model* model, const yy_scales* sc
       ex.kapd[s] = kapd[s];
       ex.taud[s] = taud[s];
     }
-    if ((st = ctx->bsrc.ensure((size_t)S * n_pad * sizeof(float))) != YY_OK) return st;
+    if ((st = ctx->bsrc.ensure((size_t)S * (n_pad + n_pad / 128) * sizeof(float))) != YY_OK) return st;
     ex.bsrc = ctx->bsrc.as<float>();
     if (prec == YY_PREC_BF16X3S) {
       if ((st = ctx->sflags.ensure((size_t)tbs * jtl * 8)) != YY_OK) return st;

@@ -61,11 +61,12 @@ def test_batch_matches_single_runs_exactly(prec):
         bt.close()
 
 
-def test_graph_replay_equals_eager_steps():
+@pytest.mark.parametrize("prec", ["bf16x3g", "bf16x3s"])
+def test_graph_replay_equals_eager_steps(prec):
     ws = _workloads(K=10)
     dys = [W.simulate(w)[1] for w in ws]
-    a = Batch(ws, dys, prec="bf16x3g")
-    g = Batch(ws, dys, prec="bf16x3g")
+    a = Batch(ws, dys, prec=prec)
+    g = Batch(ws, dys, prec=prec)
     try:
         for _ in range(10):
             a.step()
