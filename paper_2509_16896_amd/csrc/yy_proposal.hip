@@ -241,11 +241,14 @@ static yy_status backward(yy_proposal p, int32_t B, const Work& w, float* g) {
 // ---------------------------------------------------------------------------
 // Restart checks.  dec[0] = learned box passed coverage and log-density,
 // dec[1] = the plain nodes must be regenerated (the ESS check failed),
-// dec[2] = the learned box was used.  box (device [4r] doubles): learned
-// lo, hi, then the centre and half-width of the learned box.
+// dec[2] = the learned box was used.  box (device [5r] doubles): learned
+// lo, hi, then the centre, the half-width and kappa / half-width (the inverse
+// standard deviation) of the learned box.
 
-// One wavefront per sample t: counts of coordinates inside the learned box
-// and the two log-densities (constant terms dropped); per-block partials.
+// One wavefront per sample t: counts of coordinates inside the learned box and
+// the sums of squared standardised deviations under both boxes (the log terms
+// of the densities do not depend on t and are added once in k_prop_decide);
+// per-block partials.
 __global__ void __launch_bounds__(kBlock) k_prop_checks(int64_t n, int32_t r, const double* __restrict__ x,
                                                         const int64_t* __restrict__ idx,
                                                         const double* __restrict__ mean, double R,
@@ -258,19 +261,20 @@ __global__ void __launch_bounds__(kBlock) k_prop_checks(int64_t n, int32_t r, co
   const int64_t nwaves = ((int64_t)gridDim.x * kBlock) >> 6;
   const double* c = box + 2 * r;
   const double* hw = box + 3 * r;
-  const double sP = R / kKappa;
-  double cov = 0.0, ldL = 0.0, ldP = 0.0;
+  const double* isL = box + 4 * r;
+  const double isP = kKappa / R;
+  double cov = 0.0, qL = 0.0, qP = 0.0;
   for (int64_t t = wave; t < n; t += nwaves) {
     const double* y = x + (size_t)idx[t] * r;
     for (int32_t d = lane; d < r; d += 64) {
       const double yd = y[d];
-      const double sL = hw[d] / kKappa;
-      const double zl = (yd - c[d]) / sL, zp = (yd - mean[d]) / sP;
+      const double zl = (yd - c[d]) * isL[d], zp = (yd - mean[d]) * isP;
       cov += fabs(yd - c[d]) <= hw[d] ? 1.0 : 0.0;
-      ldL += -0.5 * zl * zl - log(sL);
-      ldP += -0.5 * zp * zp - log(sP);
+      qL = fma(zl, zl, qL);
+      qP = fma(zp, zp, qP);
     }
   }
+  const double ldL = qL, ldP = qP;
   const double a = block_sum<kBlock>(cov, sh);
   const double b = block_sum<kBlock>(ldL, sh);
   const double e = block_sum<kBlock>(ldP, sh);
@@ -293,6 +297,7 @@ __global__ void __launch_bounds__(kBlock) k_prop_box(int32_t r, const float* __r
   box[r + d] = c + hw;
   box[2 * r + d] = c;
   box[3 * r + d] = hw;
+  box[4 * r + d] = kKappa / hw;
 }
 
 // Decision on coverage and log-density; writes the chosen box.
@@ -303,14 +308,35 @@ __global__ void __launch_bounds__(kBlock) k_prop_decide(int nb, int64_t n, int32
                                                         double* __restrict__ box_lo, double* __restrict__ box_hi,
                                                         int* __restrict__ dec) {
   __shared__ int ok;
+  __shared__ double sa[kBlock], sq[kBlock], sp[kBlock], sl[kBlock];
+  // partial sums in a fixed order: thread k takes partials k, k + kBlock, ...
+  // (and coordinates k, k + kBlock, ... of the log standard deviations), then
+  // thread 0 adds the thread sums in thread order
+  double a = 0.0, qL = 0.0, qP = 0.0, lg = 0.0;
+  for (int k = threadIdx.x; k < nb; k += kBlock) {
+    a += part[3 * k];
+    qL += part[3 * k + 1];
+    qP += part[3 * k + 2];
+  }
+  for (int d = threadIdx.x; d < r; d += kBlock) lg += log(box[3 * r + d] / kKappa);
+  sa[threadIdx.x] = a;
+  sq[threadIdx.x] = qL;
+  sp[threadIdx.x] = qP;
+  sl[threadIdx.x] = lg;
+  __syncthreads();
   if (threadIdx.x == 0) {
-    double a = 0.0, b = 0.0, e = 0.0;
-    for (int k = 0; k < nb; ++k) {
-      a += part[3 * k];
-      b += part[3 * k + 1];
-      e += part[3 * k + 2];
+    double A = 0.0, QL = 0.0, QP = 0.0, LG = 0.0;
+    for (int k = 0; k < kBlock; ++k) {
+      A += sa[k];
+      QL += sq[k];
+      QP += sp[k];
+      LG += sl[k];
     }
-    ok = (a / ((double)n * (double)r) >= cover_min) && (b >= e);
+    // mean log-densities of the samples under the two diagonal Gaussians,
+    // constant terms common to both dropped
+    const double b = -0.5 * QL - (double)n * LG;
+    const double e = -0.5 * QP - (double)n * (double)r * log(R / kKappa);
+    ok = (A / ((double)n * (double)r) >= cover_min) && (b >= e);
     dec[0] = ok;
     dec[1] = 0;
     dec[2] = 0;
@@ -428,11 +454,11 @@ yy_status proposal_restart_prepare(yy_ctx ctx, yy_proposal p, int64_t n, int32_t
   if (s != YY_OK) return s;
   int nb = (int)((n * 64 + kBlock - 1) / kBlock);
   if (nb > 2048) nb = 2048;
-  // part: box [4r] + check partials [3 nb] + ESS partials [3 nb] + decision ints
-  const size_t need = (4 * (size_t)r + 6 * (size_t)nb + 4) * sizeof(double);
+  // part: box [5r] + check partials [3 nb] + ESS partials [3 nb] + decision ints
+  const size_t need = (5 * (size_t)r + 6 * (size_t)nb + 4) * sizeof(double);
   if ((s = p->part.ensure(need)) != YY_OK) return s;
   double* box = p->part.as<double>();
-  double* cpart = box + 4 * (size_t)r;
+  double* cpart = box + 5 * (size_t)r;
   int* dec = reinterpret_cast<int*>(cpart + 6 * (size_t)nb);
   if ((s = forward(p, 1, mean, w)) != YY_OK) return s;
   k_prop_box<<<nblk(r), kBlock, 0, st>>>(r, w.O, mean, R, box);
@@ -451,7 +477,7 @@ yy_status proposal_restart_finish(yy_ctx ctx, yy_proposal p, int64_t n, int32_t 
   hipStream_t st = ctx->stream;
   int nb = (int)((n + kBlock - 1) / kBlock);
   if (nb > 1024) nb = 1024;
-  double* part = p->part.as<double>() + 4 * (size_t)r;   // reuses the check partials (3 nb >= nb + 2 nb)
+  double* part = p->part.as<double>() + 5 * (size_t)r;   // reuses the check partials (3 nb >= nb + 2 nb)
   k_prior_max<<<nb, kBlock, 0, st>>>(n, lw_new, part);
   YY_LAUNCH_CHECK("k_prior_max");
   k_prior_sums<<<nb, kBlock, 0, st>>>(n, nb, lw_new, part);
