@@ -5,7 +5,7 @@
 //   G = X X^T,  H = X F^T,  m_j^s = x_j + tau_s f_j,
 // so one pass of two matrix products serves every scale s.  Each block owns
 // 256 targets and a range of sources; per 128-source tile it accumulates G and
-// H over K = r (zero padded to a multiple of 64) with MFMA 32x32 instructions
+// H over K = r (zero padded to a multiple of 32 or 64) with MFMA 32x32 instructions
 // (sources on the A side, targets on the B side, so every lane ends with one
 // target and 16 sources per 32x32 block), then turns them into base-2
 // exponents e = a_i + b_j + 2 kap_s G + 2 kap_s tau_s H and folds them into a
@@ -18,7 +18,10 @@
 // 2^-80 below the maximum.  Variants:
 //   BF16X3:  hi/lo split of both operands, hi*hi + lo*hi + hi*lo, for G and H,
 //   BF16X3G: the split for G only; H, which enters scaled by tau_s, is hi*hi,
-//   BF16X1:  hi*hi only (a screen),  FP32: v_mfma_f32_32x32x2_f32 on FP32 data.
+//   BF16X1:  hi*hi only (a screen),  FP32: v_mfma_f32_32x32x2_f32 on FP32 data,
+//   BF16X3S: a screen on G alone (k_pair_screen: H bounded, not computed) flags
+//            the tiles that may hold a pair within 2^-80 of a row maximum;
+//            BF16X3G then runs over the flagged tiles only.
 #include <cstring>
 #include <type_traits>
 
@@ -550,12 +553,12 @@ struct StageShape {
 // One block's work: targets [256 tb, 256 tb + 256) against the sources of split
 // `split`, partial (max, sum) to a.part.  smem, sbuf, rare and tl are the
 // block's LDS ring, bias buffers, rare-path parameters and tile list.
-// MODE 0: every tile.  MODE 2: only the tiles flagged by the screen
-// (k_pair_screen below), taken in windows of kTileWindow tiles; the others
-// hold no pair within 2^-80 of a row maximum.
+// FLAGGED: only the tiles flagged by the screen (k_pair_screen below), taken
+// in windows of kTileWindow tiles; the others hold no pair within 2^-80 of a
+// row maximum.
 constexpr int kTileWindow = 64;
 
-template <int S, int VAR, int NS, int SPB, int MODE>
+template <int S, int VAR, int NS, int SPB, bool FLAGGED>
 __device__ __forceinline__ void pair_block(const MArgs& a, int tb, int split, unsigned char* smem,
                                            float (*sbuf)[4 * kMJ], Rare& rare, int* tl) {
   static_assert(NS % SPB == 0 && NS / SPB >= 2, "the ring holds at least two groups of stages");
@@ -588,9 +591,9 @@ __device__ __forceinline__ void pair_block(const MArgs& a, int tb, int split, un
   float at[kIB][S], M[kIB][S], Ssum[kIB][S], margin[S];
   init_targets<S>(a, i0, split, at, M, Ssum, margin);
 
-  for (int w0 = 0; w0 < ntiles_all; w0 += MODE == 2 ? kTileWindow : ntiles_all) {
+  for (int w0 = 0; w0 < ntiles_all; w0 += FLAGGED ? kTileWindow : ntiles_all) {
     int ntiles = ntiles_all;
-    if (MODE == 2) {
+    if (FLAGGED) {
       // the window's flagged tiles, in order
       const int wn = ntiles_all - w0 < kTileWindow ? ntiles_all - w0 : kTileWindow;
       __syncthreads();   // the previous window is done with the ring, the bias buffers and the list
@@ -607,7 +610,7 @@ __device__ __forceinline__ void pair_block(const MArgs& a, int tb, int split, un
     }
     // first source of the window's tile t
     auto tile_j0 = [&](int t) -> int64_t {
-      return jb0 + (int64_t)(MODE == 2 ? __builtin_amdgcn_readfirstlane(tl[t]) : t) * kMJ;
+      return jb0 + (int64_t)(FLAGGED ? __builtin_amdgcn_readfirstlane(tl[t]) : t) * kMJ;
     };
     const int Q = ntiles * nchunks;
 
@@ -670,28 +673,28 @@ __device__ __forceinline__ void pair_block(const MArgs& a, int tb, int split, un
   merge_and_store<S>(a, M, Ssum, i0, split, reinterpret_cast<float2*>(smem));
 }
 
-template <int S, int VAR, int NS, int SPB, int MODE>
+template <int S, int VAR, int NS, int SPB, bool FLAGGED>
 __global__ void __launch_bounds__(kNT, 1) k_pair_mfma(MArgs a) {
   __shared__ __attribute__((aligned(1024))) unsigned char smem[NS * StageShape<VAR>::STAGE];
   __shared__ __attribute__((aligned(1024))) float sbuf[2][4 * kMJ];
   __shared__ Rare rare;
-  __shared__ int tl[MODE == 2 ? kTileWindow + 1 : 1];
+  __shared__ int tl[FLAGGED ? kTileWindow + 1 : 1];
   int tb, split;
   block_map(a, tb, split);
-  pair_block<S, VAR, NS, SPB, MODE>(a, tb, split, smem, sbuf, rare, tl);
+  pair_block<S, VAR, NS, SPB, FLAGGED>(a, tb, split, smem, sbuf, rare, tl);
 }
 
 // Many node sets in one launch: block b takes work item items[b] = (set,
 // target block, source split); the items come in decreasing cost order.
-template <int S, int VAR, int NS, int SPB, int MODE>
+template <int S, int VAR, int NS, int SPB, bool FLAGGED>
 __global__ void __launch_bounds__(kNT, 1) k_pair_mfma_batch(const MArgs* __restrict__ sets,
                                                             const int4* __restrict__ items) {
   __shared__ __attribute__((aligned(1024))) unsigned char smem[NS * StageShape<VAR>::STAGE];
   __shared__ __attribute__((aligned(1024))) float sbuf[2][4 * kMJ];
   __shared__ Rare rare;
-  __shared__ int tl[MODE == 2 ? kTileWindow + 1 : 1];
+  __shared__ int tl[FLAGGED ? kTileWindow + 1 : 1];
   const int4 it = items[blockIdx.x];
-  pair_block<S, VAR, NS, SPB, MODE>(sets[__builtin_amdgcn_readfirstlane(it.x)], __builtin_amdgcn_readfirstlane(it.y),
+  pair_block<S, VAR, NS, SPB, FLAGGED>(sets[__builtin_amdgcn_readfirstlane(it.x)], __builtin_amdgcn_readfirstlane(it.y),
                                     __builtin_amdgcn_readfirstlane(it.z), smem, sbuf, rare, tl);
 }
 
@@ -1073,19 +1076,19 @@ template <int S>
 static yy_status launch_batch_s(hipStream_t st, const MArgs* sets, const int4* items, int nitems, int prec,
                                 bool k64) {
   if (prec == YY_PREC_BF16X3) {
-    k_pair_mfma_batch<S, 3, 4, 2, 0><<<nitems, kNT, 0, st>>>(sets, items);
+    k_pair_mfma_batch<S, 3, 4, 2, false><<<nitems, kNT, 0, st>>>(sets, items);
   } else if (prec == YY_PREC_BF16X3G) {
-    k_pair_mfma_batch<S, 2, 4, 2, 0><<<nitems, kNT, 0, st>>>(sets, items);
+    k_pair_mfma_batch<S, 2, 4, 2, false><<<nitems, kNT, 0, st>>>(sets, items);
   } else if (prec == YY_PREC_BF16X3S) {
     // four K stages per barrier when every K padding allows it, else two
     if (k64) k_pair_screen_batch<S, 8, 4><<<nitems, kNT, 0, st>>>(sets, items);
     else k_pair_screen_batch<S, 8, 2><<<nitems, kNT, 0, st>>>(sets, items);
     YY_LAUNCH_CHECK("k_pair_mfma_batch (screen)");
-    k_pair_mfma_batch<S, 2, 4, 2, 2><<<nitems, kNT, 0, st>>>(sets, items);
+    k_pair_mfma_batch<S, 2, 4, 2, true><<<nitems, kNT, 0, st>>>(sets, items);
   } else if (prec == YY_PREC_BF16X1) {
-    k_pair_mfma_batch<S, 1, 8, 4, 0><<<nitems, kNT, 0, st>>>(sets, items);
+    k_pair_mfma_batch<S, 1, 8, 4, false><<<nitems, kNT, 0, st>>>(sets, items);
   } else {
-    k_pair_mfma_batch<S, 0, 4, 2, 0><<<nitems, kNT, 0, st>>>(sets, items);
+    k_pair_mfma_batch<S, 0, 4, 2, false><<<nitems, kNT, 0, st>>>(sets, items);
   }
   YY_LAUNCH_CHECK("k_pair_mfma_batch");
   return YY_OK;
@@ -1094,20 +1097,20 @@ static yy_status launch_batch_s(hipStream_t st, const MArgs* sets, const int4* i
 template <int S>
 static yy_status launch_s(hipStream_t st, const MArgs& m, int prec, int nblocks) {
   if (prec == YY_PREC_BF16X3) {
-    k_pair_mfma<S, 3, 4, 2, 0><<<nblocks, kNT, 0, st>>>(m);
+    k_pair_mfma<S, 3, 4, 2, false><<<nblocks, kNT, 0, st>>>(m);
   } else if (prec == YY_PREC_BF16X3G) {
-    k_pair_mfma<S, 2, 4, 2, 0><<<nblocks, kNT, 0, st>>>(m);
+    k_pair_mfma<S, 2, 4, 2, false><<<nblocks, kNT, 0, st>>>(m);
   } else if (prec == YY_PREC_BF16X3S) {
     // the screen over every tile, then the split form over the flagged tiles
     // four K stages per barrier when the K padding allows it, else two
     if (m.rp % 64 == 0) k_pair_screen<S, 8, 4><<<nblocks, kNT, 0, st>>>(m);
     else k_pair_screen<S, 8, 2><<<nblocks, kNT, 0, st>>>(m);
     YY_LAUNCH_CHECK("k_pair_mfma (screen)");
-    k_pair_mfma<S, 2, 4, 2, 2><<<nblocks, kNT, 0, st>>>(m);
+    k_pair_mfma<S, 2, 4, 2, true><<<nblocks, kNT, 0, st>>>(m);
   } else if (prec == YY_PREC_BF16X1) {
-    k_pair_mfma<S, 1, 8, 4, 0><<<nblocks, kNT, 0, st>>>(m);
+    k_pair_mfma<S, 1, 8, 4, false><<<nblocks, kNT, 0, st>>>(m);
   } else {
-    k_pair_mfma<S, 0, 4, 2, 0><<<nblocks, kNT, 0, st>>>(m);
+    k_pair_mfma<S, 0, 4, 2, false><<<nblocks, kNT, 0, st>>>(m);
   }
   YY_LAUNCH_CHECK("k_pair_mfma");
   return YY_OK;
