@@ -122,8 +122,14 @@ typedef enum {
   YY_PREC_BF16X3 = 3,    /* BF16 hi/lo split (3 products) on matrix cores + exact near pairs */
   YY_PREC_BF16X1 = 4,    /* one BF16 product on matrix cores as a screen + exact near pairs */
   YY_PREC_BF16X3G = 5,   /* BF16X3 for x_i.x_j, one BF16 product for the tau-scaled x_i.f_j */
-  YY_PREC_BF16X3S = 6    /* BF16X3G on the tiles that a BF16X1 screen cannot rule out */
+  YY_PREC_BF16X3S = 6    /* BF16X3G on the tiles that a screen cannot rule out (below) */
 } yy_prec;
+/* Every matrix-core form keeps each pair whose exponent may lie within 2^-80
+ * of its row maximum exact (FP32 direct differences) and drops the others, so
+ * all forms agree with YY_PREC_FP32 to FP32 rounding.  BF16X3S first runs a
+ * screen that forms x_i.x_j with one BF16 product and bounds the tau-scaled
+ * x_i.f_j term by |x_i| max_j |f_j|; the split form then visits only the
+ * 256-target x 128-source tiles the screen could not rule out. */
 
 /* ------------------------------------------------------------------------ */
 /* Sobol nodes (Appendix A; Sec. 2.2.1 state sampling; Sec. 6 reference set).
