@@ -215,19 +215,44 @@ __device__ __forceinline__ void k_restart_nodes_body(int64_t n, int32_t r, const
   const int64_t gt = (int64_t)bx_ * blockDim.x + threadIdx.x;
   const int64_t wave = gt >> 6;
   const int64_t nwaves = ((int64_t)gx_ * blockDim.x) >> 6;
+  // coordinate k of node i from its code (the same arithmetic as the Sobol mapping)
+  auto node = [&](uint32_t code, double lo, double hi, double mk, double& xv, double& acc, int& b) {
+    const double c = __dmul_rn(0.5, __dadd_rn(lo, hi));
+    const double hw = __dmul_rn(0.5, __dsub_rn(hi, lo));
+    const double u = __dsub_rn((double)code * 0x1p-31, 1.0);
+    xv = __dadd_rn(c, __dmul_rn(hw, u));
+    b |= (fabs(xv - lo) <= kBoundaryTol) || (fabs(hi - xv) <= kBoundaryTol);
+    const double dv = __dsub_rn(xv, mk);
+    acc = __dadd_rn(acc, __dmul_rn(dv, dv));
+  };
+  // 8- and 16-byte accesses to pairs of coordinates when the rows allow it
+  const bool pairs = (r & 1) == 0 && ((reinterpret_cast<uintptr_t>(codes) & 7) |
+                                      ((reinterpret_cast<uintptr_t>(x_new) | reinterpret_cast<uintptr_t>(box_lo) |
+                                        reinterpret_cast<uintptr_t>(box_hi) | reinterpret_cast<uintptr_t>(mean)) &
+                                       15)) == 0;
   for (int64_t i = wave; i < n; i += nwaves) {
     double acc = 0.0;
     int b = 0;
-    for (int32_t k = lane; k < r; k += 64) {
-      const double lo = box_lo[k], hi = box_hi[k];
-      const double c = __dmul_rn(0.5, __dadd_rn(lo, hi));
-      const double hw = __dmul_rn(0.5, __dsub_rn(hi, lo));
-      const double u = __dsub_rn((double)codes[(size_t)i * r + k] * 0x1p-31, 1.0);
-      const double xv = __dadd_rn(c, __dmul_rn(hw, u));
-      x_new[(size_t)i * r + k] = xv;
-      b |= (fabs(xv - lo) <= kBoundaryTol) || (fabs(hi - xv) <= kBoundaryTol);
-      const double dv = __dsub_rn(xv, mean[k]);
-      acc = __dadd_rn(acc, __dmul_rn(dv, dv));
+    if (pairs) {
+      const uint2* c2 = reinterpret_cast<const uint2*>(codes + (size_t)i * r);
+      double2* x2 = reinterpret_cast<double2*>(x_new + (size_t)i * r);
+      const double2* lo2 = reinterpret_cast<const double2*>(box_lo);
+      const double2* hi2 = reinterpret_cast<const double2*>(box_hi);
+      const double2* m2 = reinterpret_cast<const double2*>(mean);
+      for (int32_t kk = lane; kk < r / 2; kk += 64) {
+        const uint2 cd = c2[kk];
+        const double2 lo = lo2[kk], hi = hi2[kk], mk = m2[kk];
+        double2 xv;
+        node(cd.x, lo.x, hi.x, mk.x, xv.x, acc, b);
+        node(cd.y, lo.y, hi.y, mk.y, xv.y, acc, b);
+        x2[kk] = xv;
+      }
+    } else {
+      for (int32_t k = lane; k < r; k += 64) {
+        double xv;
+        node(codes[(size_t)i * r + k], box_lo[k], box_hi[k], mean[k], xv, acc, b);
+        x_new[(size_t)i * r + k] = xv;
+      }
     }
     acc = wave_sum(acc);
     b = wave_or(b);

@@ -25,6 +25,29 @@ __device__ __forceinline__ void k_loglik_body(int64_t n, int32_t r, int32_t m, i
     if (li == -INFINITY) continue;
     const double* xi = x + (size_t)i * r;
     double dot = 0.0, hh = 0.0;
+    if (obs != YY_H_LINEAR && m == r && (r & 1) == 0 &&
+        ((reinterpret_cast<uintptr_t>(xi) | reinterpret_cast<uintptr_t>(dy)) & 15) == 0) {
+      // componentwise h on 16-byte pairs of coordinates
+      const double2* x2 = reinterpret_cast<const double2*>(xi);
+      const double2* d2 = reinterpret_cast<const double2*>(dy);
+      for (int32_t k = lane; k < m / 2; k += 64) {
+        const double2 v = x2[k], d = d2[k];
+        double h0 = v.x, h1 = v.y;
+        if (obs == YY_H_CUBE) {
+          const double t0 = h0 - h_shift, t1 = h1 - h_shift;
+          h0 = t0 * t0 * t0;
+          h1 = t1 * t1 * t1;
+        }
+        dot = fma(h0, d.x, dot);
+        hh = fma(h0, h0, hh);
+        dot = fma(h1, d.y, dot);
+        hh = fma(h1, h1, hh);
+      }
+      dot = wave_sum(dot);
+      hh = wave_sum(hh);
+      if (lane == 0) logw[i] = li + (dot - 0.5 * dt * hh) / rho2;
+      continue;
+    }
     for (int32_t k = lane; k < m; k += 64) {
       double h;
       if (obs == YY_H_IDENTITY) {
@@ -194,6 +217,7 @@ __device__ __forceinline__ void k_norm_weights_body(int64_t n, int32_t r, int64_
 #pragma unroll
   for (int c = 0; c < kMaxC; ++c) acc[c] = 0.0;
   const int nc = (r + kBlock - 1) / kBlock;
+  const bool pairs = (r & 1) == 0 && (reinterpret_cast<uintptr_t>(x) & 15) == 0;
   for (int64_t c0 = b0; c0 < b1; c0 += kBlock) {
     const int64_t i = c0 + threadIdx.x;
     double wi = 0.0;
@@ -208,22 +232,51 @@ __device__ __forceinline__ void k_norm_weights_body(int64_t n, int32_t r, int64_
     sw[threadIdx.x] = wi;
     __syncthreads();
     const int64_t cnt = std::min<int64_t>(kBlock, b1 - c0);
-    for (int64_t t = 0; t < cnt; ++t) {
-      const double wt = sw[t];
-      const double* xr = x + (size_t)(c0 + t) * r;
+    if (pairs) {
+      // 16-byte loads: thread j takes coordinates 2 (j + kBlock c) and 2 (j + kBlock c) + 1
+      // (the same additions per coordinate in the same order as the scalar loop)
+      for (int64_t t = 0; t < cnt; ++t) {
+        const double wt = sw[t];
+        const double2* xr = reinterpret_cast<const double2*>(x + (size_t)(c0 + t) * r);
 #pragma unroll
-      for (int c = 0; c < kMaxC; ++c) {
-        const int k = threadIdx.x + kBlock * c;
-        if (c < nc && k < r) acc[c] = fma(wt, xr[k], acc[c]);
+        for (int c = 0; c < kMaxC / 2; ++c) {
+          const int kk = threadIdx.x + kBlock * c;
+          if (kk < r / 2) {
+            const double2 v = xr[kk];
+            acc[2 * c] = fma(wt, v.x, acc[2 * c]);
+            acc[2 * c + 1] = fma(wt, v.y, acc[2 * c + 1]);
+          }
+        }
+      }
+    } else {
+      for (int64_t t = 0; t < cnt; ++t) {
+        const double wt = sw[t];
+        const double* xr = x + (size_t)(c0 + t) * r;
+#pragma unroll
+        for (int c = 0; c < kMaxC; ++c) {
+          const int k = threadIdx.x + kBlock * c;
+          if (c < nc && k < r) acc[c] = fma(wt, xr[k], acc[c]);
+        }
       }
     }
   }
   w2 = block_sum<kBlock>(w2, sh);
   if (threadIdx.x == 0) pw2[bx_] = w2;
+  if (pairs) {
 #pragma unroll
-  for (int c = 0; c < kMaxC; ++c) {
-    const int k = threadIdx.x + kBlock * c;
-    if (c < nc && k < r) pmean[(size_t)bx_ * r + k] = acc[c];
+    for (int c = 0; c < kMaxC / 2; ++c) {
+      const int kk = threadIdx.x + kBlock * c;
+      if (kk < r / 2) {
+        pmean[(size_t)bx_ * r + 2 * kk] = acc[2 * c];
+        pmean[(size_t)bx_ * r + 2 * kk + 1] = acc[2 * c + 1];
+      }
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < kMaxC; ++c) {
+      const int k = threadIdx.x + kBlock * c;
+      if (c < nc && k < r) pmean[(size_t)bx_ * r + k] = acc[c];
+    }
   }
 }
 
