@@ -29,7 +29,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "filter steps/sec + propagation TFLOP/s at r=1000,n=65536 vs plain FP32, same error"
-PEAK_TFLOPS = {"bf16x3": 2500.0, "bf16x3g": 2500.0, "bf16x3s": 2500.0, "bf16x1": 2500.0, "fp32_mfma": 157.3}
+PEAK_TFLOPS = {"bf16x3": 2500.0, "bf16x3g": 2500.0, "bf16x3s": 2500.0, "bf16x3p": 2500.0, "bf16x1": 2500.0,
+               "fp32_mfma": 157.3}
 VALU_FP32_PEAK = 78.6   # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz, packed FP32 disabled
 # matrix-core products executed per algorithmic product (x.x and x.f each count once); the
 # screened split form's screen executes x.x only (the x.f term is bounded), half a product per
@@ -285,7 +286,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--prec", default="bf16x3s",
-                    choices=["fp32", "fp32_mfma", "bf16x3", "bf16x3g", "bf16x3s", "bf16x1"])
+                    choices=["fp32", "fp32_mfma", "bf16x3", "bf16x3g", "bf16x3s", "bf16x3p", "bf16x1"])
     ap.add_argument("--other-forms", default="bf16x3g,bf16x3,bf16x1",
                     help="matrix-core forms whose pairwise kernel is also timed ('none' to skip)")
     ap.add_argument("--baseline-prec", default="fp32_mfma", help="plain FP32 form timed beside ('none' to skip)")
@@ -352,13 +353,15 @@ def main():
     roofline["kernel"] = "k_pair_mfma" if mfma else "k_pair_valu"
     roofline["kernel_ms"] = round(1e3 * avg_kernel_s, 3)
     screen = None
-    if args.prec == "bf16x3s":
+    if args.prec in ("bf16x3s", "bf16x3p"):
         # the pairwise time is the screen plus the split pass over the flagged tiles
         from paper_2509_16896_amd import yy
         flagged, tiles = yy.yy_screen_count(f.ctx)
         screen = {"flagged_tiles": flagged, "tiles": tiles}
         roofline["kernel"] = "k_pair_screen, then k_pair_mfma (split form) on flagged tiles"
-        EXEC_PER_ALG["bf16x3s"] = 0.5 + 2.0 * flagged / max(tiles, 1)
+        # the partial-distance screen forms x.x over the first 64 coordinates only
+        frac_k = 1.0 if args.prec == "bf16x3s" else min(64, w.r) / w.r
+        EXEC_PER_ALG[args.prec] = 0.5 * frac_k + 2.0 * flagged / max(tiles, 1)
         log(f"[bench] screen flagged {flagged} of {tiles} tiles for the split form")
     if mfma:
         # matrix-core utilisation: executed products (3 per product for the full split) / peak
@@ -392,7 +395,7 @@ def main():
     f.close()
 
     dtype = {"fp32": "f32", "fp32_mfma": "f32", "bf16x3": "bf16", "bf16x3g": "bf16", "bf16x3s": "bf16",
-             "bf16x1": "bf16"}[args.prec]
+             "bf16x3p": "bf16", "bf16x1": "bf16"}[args.prec]
     line = {
         "metric": METRIC, "value": round(steps_s, 4), "unit": "steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed / args.steps, 3),

@@ -122,14 +122,22 @@ typedef enum {
   YY_PREC_BF16X3 = 3,    /* BF16 hi/lo split (3 products) on matrix cores + exact near pairs */
   YY_PREC_BF16X1 = 4,    /* one BF16 product on matrix cores as a screen + exact near pairs */
   YY_PREC_BF16X3G = 5,   /* BF16X3 for x_i.x_j, one BF16 product for the tau-scaled x_i.f_j */
-  YY_PREC_BF16X3S = 6    /* BF16X3G on the tiles that a screen cannot rule out (below) */
+  YY_PREC_BF16X3S = 6,   /* BF16X3G on the tiles that a screen cannot rule out (below) */
+  YY_PREC_BF16X3P = 7    /* BF16X3G on the tiles that a screen on the first 64 coordinates cannot rule out */
 } yy_prec;
 /* Every matrix-core form keeps each pair whose exponent may lie within 2^-80
  * of its row maximum exact (FP32 direct differences) and drops the others, so
  * all forms agree with YY_PREC_FP32 to FP32 rounding.  BF16X3S first runs a
  * screen that forms x_i.x_j with one BF16 product and bounds the tau-scaled
  * x_i.f_j term by |x_i| max_j |f_j|; the split form then visits only the
- * 256-target x 128-source tiles the screen could not rule out. */
+ * 256-target x 128-source tiles the screen could not rule out.  BF16X3P
+ * screens on the first 64 coordinates alone: a sum of squares over some of
+ * the coordinates is a lower bound of the squared distance over all of them,
+ * so a pair whose partial distance already puts it 2^-80 below the exact
+ * self-pair exponent of its row is negligible.  Its screen moves and
+ * multiplies 64 of the r coordinates; where the partial distance does not
+ * separate the nodes it flags more tiles than the BF16X3S screen, and the
+ * result is the same. */
 
 /* ------------------------------------------------------------------------ */
 /* Sobol nodes (Appendix A; Sec. 2.2.1 state sampling; Sec. 6 reference set).
@@ -336,11 +344,12 @@ yy_status yy_batch_step_count(yy_batch b, int32_t* k);
 yy_status yy_timing_enable(yy_ctx ctx, int32_t on);
 yy_status yy_timing_read(yy_ctx ctx, double* ms, int64_t* launches);
 
-/* The screen of the last BF16X3S propagation on this context (a diagnostic of
- * the screened split form): *tiles = (256-target block, 128-source tile)
- * pairs, *flagged = those recomputed in the split form because some pair in
- * them may lie within 2^-80 of its row maximum.  Synchronises the context's
- * stream; YY_ERR_ARG if no BF16X3S propagation ran on it. */
+/* The screen of the last BF16X3S or BF16X3P propagation on this context (a
+ * diagnostic of the screened split forms): *tiles = (256-target block,
+ * 128-source tile) pairs, *flagged = those recomputed in the split form
+ * because some pair in them may lie within 2^-80 of its row maximum.
+ * Synchronises the context's stream; YY_ERR_ARG if no screened propagation
+ * ran on it. */
 yy_status yy_screen_count(yy_ctx ctx, int64_t* flagged, int64_t* tiles);
 
 #ifdef __cplusplus

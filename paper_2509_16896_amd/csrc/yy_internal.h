@@ -16,6 +16,7 @@ constexpr int kWave = 64;            // CDNA wavefront width
 constexpr double kBoundaryTol = 1e-12;  // distance to a face that marks a boundary node
 constexpr double kLog2e = 1.4426950408889634073599246810019;
 constexpr double kLn2 = 0.69314718055994530941723212145818;
+constexpr int kPreK = 64;             // coordinates of the partial-distance screen (BF16X3P)
 
 // Sets the thread-local error text and returns `st`.
 yy_status fail(yy_status st, const std::string& msg);
@@ -152,7 +153,8 @@ struct MfmaExtra {
   int64_t j_per_split;
   double kapd[YY_MAX_SCALES];
   double taud[YY_MAX_SCALES];
-  uint8_t* flags;              // screened split form: [n_pad/256][ceil(n/128)][8] screen verdicts
+  uint8_t* flags;              // screened split forms: [n_pad/256][ceil(n/128)][8] screen verdicts
+  float* bpre;                 // BF16X3P: source biases over the first kPreK coordinates, laid out as bsrc
 };
 yy_status launch_src_bias(hipStream_t st, const PairArgs& a, const MfmaExtra& ex);
 yy_status launch_pair_mfma(hipStream_t st, const PairArgs& a, int prec, const MfmaExtra& ex);

@@ -22,6 +22,7 @@
 //   BF16X3S: a screen on G alone (k_pair_screen: H bounded, not computed) flags
 //            the tiles that may hold a pair within 2^-80 of a row maximum;
 //            BF16X3G then runs over the flagged tiles only.
+#include <algorithm>
 #include <cstring>
 #include <type_traits>
 
@@ -65,8 +66,10 @@ struct MArgs {
   const float* f;
   const float* lw2;            // [n]
   const float* bsrc;           // [S][n_pad]: lw2_j - kap_s |m_j^s|^2, -inf for invalid sources
-  const double* node;          // [3][n]
-  const double* scal;          // [1] = max |x - centre|, [2] = max |f|
+  const float* bpre;           // the same over the first kPreK coordinates (BF16X3P), or null
+  const double* node;          // [6][n]: |x|^2, |f|^2, x.f, then the same over the first kPreK coordinates
+  const double* scal;          // [1] = max |x - centre|, [2] = max |f|, [4], [5]: the same over kPreK
+  const int* bnd;              // [n] boundary flags
   double eps_g, eps_h;         // relative error of one G / H product from operand rounding
   double eps_g1;               // the same for G in the screen of the screened split form
   float2* part;                // [nsplit][S][n]
@@ -76,6 +79,7 @@ struct MArgs {
   int64_t jtl;                 // source tiles of 128
   int32_t s_nsplit;            // the screen's source splits (of s_jps sources, a multiple of 256)
   int64_t s_jps;
+  int32_t pre_chunks;          // 16-wide K stages of the partial-distance screen
 };
 
 // Physical 16-byte chunk of logical chunk c in LDS row `row` (bank-conflict swizzle).
@@ -759,14 +763,20 @@ __device__ inline void screen_issue_stage(const unsigned char* gb, int64_t n_pad
   }
 }
 
-// Source biases of the S scales of screen tile j0 (wave 0): [S][256] floats.
-__device__ inline void screen_issue_bias(const MArgs& a, uint32_t sb_lds, int64_t j0, int wave) {
+// Source biases bs of the S scales of screen tile j0 (wave 0): [S][256] floats.
+__device__ inline void screen_issue_bias(const MArgs& a, const float* bs, uint32_t sb_lds, int64_t j0, int wave) {
   if (wave != 0) return;
   const int lane = fresh_lane();
-  for (int s = 0; s < a.S; ++s) dma_1k(a.bsrc + (size_t)s * a.n_pad + j0 + 4 * lane, sb_lds + s * 1024);
+  for (int s = 0; s < a.S; ++s) dma_1k(bs + (size_t)s * a.n_pad + j0 + 4 * lane, sb_lds + s * 1024);
 }
 
-template <int S, int NS, int SPB>
+// PRE: the partial-distance screen of BF16X3P.  Over the first kPreK
+// coordinates (superscript p), |x_i - m_j|^2 >= |x_i^p - m_j^p|^2, so the same
+// bound with G, the norms and F taken over those coordinates bounds the exact
+// exponent from above.  It is no lower bound of the row maximum, so M stays at
+// the exact self-pair exponent; boundary targets, whose result is -inf
+// whatever the sum, are not flagged.
+template <int S, int NS, int SPB, bool PRE>
 __device__ __forceinline__ void screen_block(const MArgs& a, int tb, int split, unsigned char* smem,
                                              float (*sbuf)[kSBRows * kSJ]) {
   static_assert(NS % SPB == 0 && NS / SPB >= 2, "the ring holds at least two groups of stages");
@@ -780,20 +790,21 @@ __device__ __forceinline__ void screen_block(const MArgs& a, int tb, int split, 
   const int64_t jb1 = jb0 + a.s_jps < a.n ? jb0 + a.s_jps : a.n;
   const int ntiles = __builtin_amdgcn_readfirstlane(jb1 > jb0 ? (int)((jb1 - jb0 + kSJ - 1) / kSJ) : 0);
   if (ntiles == 0) return;
-  const int nchunks = __builtin_amdgcn_readfirstlane(a.rp / kKC);
+  const int nchunks = __builtin_amdgcn_readfirstlane(PRE ? a.pre_chunks : a.rp / kKC);
   const int Q = ntiles * nchunks;
   const unsigned char* gb = reinterpret_cast<const unsigned char*>(a.bf);
   const int64_t n_pad = a.n_pad;
   const uint32_t smem_lds = __builtin_amdgcn_readfirstlane(lds_addr(smem));
   const uint32_t sb_lds = __builtin_amdgcn_readfirstlane(lds_addr(&sbuf[0][0]));
   constexpr uint32_t kSbBytes = kSBRows * kSJ * 4;
+  const float* bs = PRE ? a.bpre : a.bsrc;
 
   // per target and scale: a_i + hx_i F, the running lower bound of the row
   // maximum (the exact self-pair exponent to start) and the slack of its
   // update (the error of G and twice the bound of the x.f term); per scale the
   // margin (the error of G, the skip depth and 16 bits)
-  const double X = a.scal[1], F = a.scal[2];
-  const double gam = a.rp * 0x1p-24;
+  const double X = PRE ? a.scal[4] : a.scal[1], F = PRE ? a.scal[5] : a.scal[2];
+  const double gam = nchunks * kKC * 0x1p-24;
   float at[kIB][S], M[kIB][S], margin[S], slack[kIB][S];
 #pragma unroll
   for (int s = 0; s < S; ++s) {
@@ -804,8 +815,8 @@ __device__ __forceinline__ void screen_block(const MArgs& a, int tb, int split, 
 #pragma unroll
   for (int ib = 0; ib < kIB; ++ib) {
     const int64_t i = i0 + wi * (32 * kIB) + ib * 32 + col;
-    const bool valid = i < a.n;
-    const double nx = valid ? a.node[i] : 0.0;
+    const bool valid = i < a.n && !(PRE && a.bnd[i]);
+    const double nx = valid ? a.node[(PRE ? 3 * a.n : 0) + i] : 0.0;
     const double nf = valid ? a.node[a.n + i] : 0.0;
     const float li = valid ? a.lw2[i] : -INFINITY;
     // hx_i F with 2 kap_s tau_s = log2(e) / q for every s, rounded up
@@ -818,7 +829,7 @@ __device__ __forceinline__ void screen_block(const MArgs& a, int tb, int split, 
     }
   }
 
-  screen_issue_bias(a, sb_lds, jb0, wave);
+  screen_issue_bias(a, bs, sb_lds, jb0, wave);
 #pragma unroll
   for (int p = 0; p < LA * SPB; ++p)
     if (p < Q) screen_issue_stage(gb, n_pad, smem_lds + p * kSStage, p % nchunks, i0, jb0 + (int64_t)(p / nchunks) * kSJ,
@@ -841,7 +852,7 @@ __device__ __forceinline__ void screen_block(const MArgs& a, int tb, int split, 
       if (q + LA * SPB - 1 < Q && 2 * (nchunks / SPB) - 1 >= LA) wait_vmcnt<(LA - 1) * SPB * L>();
       else wait_vmcnt<0>();
       __syncthreads();   // ... for every wave
-      if (c == 0 && t + 1 < ntiles) screen_issue_bias(a, sb_lds + ((t + 1) & 1) * kSbBytes, j0 + kSJ, wave);
+      if (c == 0 && t + 1 < ntiles) screen_issue_bias(a, bs, sb_lds + ((t + 1) & 1) * kSbBytes, j0 + kSJ, wave);
 #pragma unroll
       for (int u = 0; u < SPB; ++u) {
         const int qn = q + LA * SPB + u;
@@ -899,7 +910,7 @@ __device__ __forceinline__ void screen_block(const MArgs& a, int tb, int split, 
         for (int ib = 0; ib < kIB; ++ib) {
           const float mt = m[ib] + at[ib][s];
           need |= mt > M[ib][s] - margin[s];
-          M[ib][s] = fmaxf(M[ib][s], mt - slack[ib][s]);
+          if (!PRE) M[ib][s] = fmaxf(M[ib][s], mt - slack[ib][s]);
         }
       }
     };
@@ -920,7 +931,7 @@ __device__ __forceinline__ void screen_block(const MArgs& a, int tb, int split, 
     // load would make its wait count the stage copies in flight)
     typedef const __attribute__((address_space(4))) float* const_f32_ptr;
     const const_f32_ptr bmax =
-        (const_f32_ptr)(a.bsrc + (size_t)S * n_pad + (size_t)(j0 / kMJ + wj));   // scale s at s (n_pad / 128)
+        (const_f32_ptr)(bs + (size_t)S * n_pad + (size_t)(j0 / kMJ + wj));   // scale s at s (n_pad / 128)
     bool doubt = false;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
@@ -957,13 +968,13 @@ __device__ inline void screen_block_map(const MArgs& a, int& tb, int& split) {
   }
 }
 
-template <int S, int NS, int SPB>
+template <int S, int NS, int SPB, bool PRE>
 __global__ void __launch_bounds__(kNT, 1) k_pair_screen(MArgs a) {
   __shared__ __attribute__((aligned(1024))) unsigned char smem[NS * kSStage];
   __shared__ __attribute__((aligned(1024))) float sbuf[2][kSBRows * kSJ];
   int tb, split;
   screen_block_map(a, tb, split);
-  screen_block<S, NS, SPB>(a, tb, split, smem, sbuf);
+  screen_block<S, NS, SPB, PRE>(a, tb, split, smem, sbuf);
 }
 
 template <int S, int NS, int SPB>
@@ -972,37 +983,42 @@ __global__ void __launch_bounds__(kNT, 1) k_pair_screen_batch(const MArgs* __res
   __shared__ __attribute__((aligned(1024))) unsigned char smem[NS * kSStage];
   __shared__ __attribute__((aligned(1024))) float sbuf[2][kSBRows * kSJ];
   const int4 it = items[blockIdx.x];
-  screen_block<S, NS, SPB>(sets[__builtin_amdgcn_readfirstlane(it.x)], __builtin_amdgcn_readfirstlane(it.y),
+  screen_block<S, NS, SPB, false>(sets[__builtin_amdgcn_readfirstlane(it.x)], __builtin_amdgcn_readfirstlane(it.y),
                            __builtin_amdgcn_readfirstlane(it.z), smem, sbuf);
 }
 
 // ---------------------------------------------------------------------------
 // Source biases b_js = lw2_j - kap_s |m_j^s|^2 (FP64 -> FP32), -inf for invalid
 // sources: out[s][n_pad]; then the maximum over each 128 consecutive sources,
-// out[S n_pad + s (n_pad / 128) + block] (the screen's coarse bound).  n_pad is
-// a multiple of the 256 threads of a block.
+// out[S n_pad + s (n_pad / 128) + block] (the screen's coarse bound).  With
+// a.bpre the same over the first kPreK coordinates, to a.bpre in the same
+// layout.  n_pad is a multiple of the 256 threads of a block.
 __device__ __forceinline__ void k_src_bias_body(int64_t n, int64_t n_pad, int32_t S,
                                                      MArgs a, float* __restrict__ out, int bx_, int gx_) {
   __shared__ double sh[kBlock / 64];
   const int64_t j = (int64_t)bx_ * kBlock + threadIdx.x;
-  for (int s = 0; s < S; ++s) {
-    float v = -INFINITY;
-    if (j < n) {
-      const float l = a.lw2[j];
-      if (l != -INFINITY) {
-        const double t = a.taud[s];
-        const double nm = a.node[j] + 2.0 * t * a.node[2 * n + j] + t * t * a.node[n + j];
-        v = (float)((double)l - a.kapd[s] * nm);
+  for (int part = 0; part < (a.bpre ? 2 : 1); ++part) {
+    float* o = part == 0 ? out : const_cast<float*>(a.bpre);
+    const double* nd = a.node + (part == 0 ? 0 : 3 * n);
+    for (int s = 0; s < S; ++s) {
+      float v = -INFINITY;
+      if (j < n) {
+        const float l = a.lw2[j];
+        if (l != -INFINITY) {
+          const double t = a.taud[s];
+          const double nm = nd[j] + 2.0 * t * nd[2 * n + j] + t * t * nd[n + j];
+          v = (float)((double)l - a.kapd[s] * nm);
+        }
       }
+      if (j < n_pad) o[(size_t)s * n_pad + j] = v;
+      const double wm = wave_max((double)v);
+      if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = wm;
+      __syncthreads();
+      if (threadIdx.x < 2 && (int64_t)bx_ * kBlock + 128 * threadIdx.x < n_pad)
+        o[(size_t)S * n_pad + (size_t)s * (n_pad / 128) + (size_t)bx_ * 2 + threadIdx.x] =
+            (float)fmax(sh[2 * threadIdx.x], sh[2 * threadIdx.x + 1]);
+      __syncthreads();
     }
-    if (j < n_pad) out[(size_t)s * n_pad + j] = v;
-    const double wm = wave_max((double)v);
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = wm;
-    __syncthreads();
-    if (threadIdx.x < 2 && (int64_t)bx_ * kBlock + 128 * threadIdx.x < n_pad)
-      out[(size_t)S * n_pad + (size_t)s * (n_pad / 128) + (size_t)bx_ * 2 + threadIdx.x] =
-          (float)fmax(sh[2 * threadIdx.x], sh[2 * threadIdx.x + 1]);
-    __syncthreads();
   }
 }
 
@@ -1031,8 +1047,9 @@ static MArgs make_args(const PairArgs& pa, int prec, const MfmaExtra& ex) {
   // hi/lo split product: 2^-16 per operand split plus cross terms; hi only:
   // 2^-8 per operand; FP32 operands: 2^-24 per operand (rounded up).
   // The screened split form: the BF16X3G bounds, and the one-product bound of G for its screen.
-  const bool split_g = prec == YY_PREC_BF16X3 || prec == YY_PREC_BF16X3G || prec == YY_PREC_BF16X3S;
-  const bool hi_h = prec == YY_PREC_BF16X3G || prec == YY_PREC_BF16X3S || prec == YY_PREC_BF16X1;
+  const bool screened = prec == YY_PREC_BF16X3S || prec == YY_PREC_BF16X3P;
+  const bool split_g = prec == YY_PREC_BF16X3 || prec == YY_PREC_BF16X3G || screened;
+  const bool hi_h = prec == YY_PREC_BF16X3G || screened || prec == YY_PREC_BF16X1;
   m.eps_g = split_g ? 0x1p-14 : prec == YY_PREC_BF16X1 ? 0x1p-7 : 0x1p-22;
   m.eps_h = prec == YY_PREC_BF16X3 ? 0x1p-14 : hi_h ? 0x1p-7 : 0x1p-22;
   m.eps_g1 = 0x1p-7;
@@ -1051,7 +1068,9 @@ static MArgs make_args(const PairArgs& pa, int prec, const MfmaExtra& ex) {
   m.f = pa.f;
   m.lw2 = pa.lw2;
   m.bsrc = ex.bsrc;
+  m.bpre = ex.bpre;
   m.node = pa.node;
+  m.bnd = pa.bnd;
   m.scal = pa.scal;
   m.part = pa.part;
   m.nsplit = pa.nsplit;
@@ -1062,6 +1081,7 @@ static MArgs make_args(const PairArgs& pa, int prec, const MfmaExtra& ex) {
   m.jtl = (pa.n + kMJ - 1) / kMJ;
   m.s_nsplit = pa.nsplit;
   m.s_jps = ((ex.j_per_split + kSJ - 1) / kSJ) * kSJ;
+  m.pre_chunks = std::min(kPreK, (int)pa.rp) / kKC;
   return m;
 }
 
@@ -1103,9 +1123,16 @@ static yy_status launch_s(hipStream_t st, const MArgs& m, int prec, int nblocks)
   } else if (prec == YY_PREC_BF16X3S) {
     // the screen over every tile, then the split form over the flagged tiles
     // four K stages per barrier when the K padding allows it, else two
-    if (m.rp % 64 == 0) k_pair_screen<S, 8, 4><<<nblocks, kNT, 0, st>>>(m);
-    else k_pair_screen<S, 8, 2><<<nblocks, kNT, 0, st>>>(m);
+    if (m.rp % 64 == 0) k_pair_screen<S, 8, 4, false><<<nblocks, kNT, 0, st>>>(m);
+    else k_pair_screen<S, 8, 2, false><<<nblocks, kNT, 0, st>>>(m);
     YY_LAUNCH_CHECK("k_pair_mfma (screen)");
+    k_pair_mfma<S, 2, 4, 2, true><<<nblocks, kNT, 0, st>>>(m);
+  } else if (prec == YY_PREC_BF16X3P) {
+    // the partial-distance screen (2 or 4 K stages, all in one barrier group),
+    // then the split form over the flagged tiles
+    if (m.pre_chunks % 4 == 0) k_pair_screen<S, 8, 4, true><<<nblocks, kNT, 0, st>>>(m);
+    else k_pair_screen<S, 8, 2, true><<<nblocks, kNT, 0, st>>>(m);
+    YY_LAUNCH_CHECK("k_pair_mfma (partial-distance screen)");
     k_pair_mfma<S, 2, 4, 2, true><<<nblocks, kNT, 0, st>>>(m);
   } else if (prec == YY_PREC_BF16X1) {
     k_pair_mfma<S, 1, 8, 4, false><<<nblocks, kNT, 0, st>>>(m);

@@ -49,6 +49,7 @@ __device__ __forceinline__ void k_prepare_body(int64_t n, int64_t n_pad, int32_t
     }
     const double* xi = x + (size_t)i * r;
     double sxx = 0.0, sff = 0.0, sxf = 0.0;
+    double pxx = 0.0, pff = 0.0, pxf = 0.0;   // over the first kPreK coordinates
     int b = 0;
     for (int32_t k = lane; k < rp; k += 64) {
       float xcv = 0.f, fv = 0.f;
@@ -71,6 +72,11 @@ __device__ __forceinline__ void k_prepare_body(int64_t n, int64_t n_pad, int32_t
         sxf = fma(xcd, fd, sxf);
         xcv = (float)xcd;
         fv = (float)fd;
+        if (k < kPreK) {
+          pxx = sxx;
+          pff = sff;
+          pxf = sxf;
+        }
       }
       const size_t o = (size_t)i * rp + k;
       xc32[o] = xcv;
@@ -91,14 +97,21 @@ __device__ __forceinline__ void k_prepare_body(int64_t n, int64_t n_pad, int32_t
         f32t[plane + t] = fv;
       }
     }
+    static_assert(kPreK <= 64, "one coordinate of the prefix per lane");
     sxx = wave_sum(sxx);
     sff = wave_sum(sff);
     sxf = wave_sum(sxf);
+    pxx = wave_sum(pxx);
+    pff = wave_sum(pff);
+    pxf = wave_sum(pxf);
     b = wave_or(b);
     if (lane == 0) {
       node[i] = sxx;
       node[n + i] = sff;
       node[2 * n + i] = sxf;
+      node[3 * n + i] = pxx;
+      node[4 * n + i] = pff;
+      node[5 * n + i] = pxf;
       bnd[i] = b;
     }
   }
@@ -135,18 +148,24 @@ __device__ __forceinline__ void k_prepare_scalars_body(int64_t n, int32_t r,
   double lv = 0.0;
   for (int32_t k = threadIdx.x; k < r; k += kBlock) lv += log(hi[k] - lo[k]);
   lv = block_sum<kBlock>(lv, sh);
-  double mx = 0.0, mf = 0.0;
+  double mx = 0.0, mf = 0.0, px = 0.0, pf = 0.0;
   for (int64_t i = threadIdx.x; i < n; i += kBlock) {
     mx = fmax(mx, node[i]);
     mf = fmax(mf, node[n + i]);
+    px = fmax(px, node[3 * n + i]);
+    pf = fmax(pf, node[4 * n + i]);
   }
   mx = block_max<kBlock>(mx, sh);
   mf = block_max<kBlock>(mf, sh);
+  px = block_max<kBlock>(px, sh);
+  pf = block_max<kBlock>(pf, sh);
   if (threadIdx.x == 0) {
     scal[0] = lv;
     scal[1] = sqrt(mx);
     scal[2] = sqrt(mf);
     scal[3] = 0.0;
+    scal[4] = sqrt(px);
+    scal[5] = sqrt(pf);
   }
 }
 
@@ -477,10 +496,11 @@ __global__ void __launch_bounds__(kBlock) k_combine_batch(const combine_args* __
 // ---------------------------------------------------------------------------
 // K of the prepared node set: r zero-padded to whole groups of 16-wide K
 // stages of the pairwise kernel (2 stages per barrier; 4 for BF16X1, the
-// vector-ALU form and the screen of BF16X3S at r > 256, where the padding to 64
-// costs at most a few percent).
+// vector-ALU form and the screens of BF16X3S and BF16X3P at r > 256, where the
+// padding to 64 costs at most a few percent).
 int pair_mfma_rp(int32_t r, int32_t prec) {
-  const int q = (prec == YY_PREC_BF16X1 || prec == YY_PREC_FP32 || (prec == YY_PREC_BF16X3S && r > 256)) ? 64 : 32;
+  const bool screened = prec == YY_PREC_BF16X3S || prec == YY_PREC_BF16X3P;
+  const int q = (prec == YY_PREC_BF16X1 || prec == YY_PREC_FP32 || (screened && r > 256)) ? 64 : 32;
   return ((r + q - 1) / q) * q;
 }
 
@@ -499,7 +519,7 @@ yy_status prepare_nodes(yy_ctx ctx, const yy_model* m, int64_t n, const double* 
   if ((st = P.f32.ensure((size_t)n * rp * sizeof(float))) != YY_OK) return st;
   if (want_bf16 && (st = P.bf.ensure((size_t)4 * n_pad * rp * sizeof(uint16_t))) != YY_OK) return st;
   if (want_f32t && (st = P.f32t.ensure((size_t)2 * n_pad * rp * sizeof(float))) != YY_OK) return st;
-  if ((st = P.node.ensure((size_t)3 * n * sizeof(double))) != YY_OK) return st;
+  if ((st = P.node.ensure((size_t)6 * n * sizeof(double))) != YY_OK) return st;
   if ((st = P.bnd.ensure((size_t)n * sizeof(int))) != YY_OK) return st;
   if ((st = P.scal.ensure(8 * sizeof(double))) != YY_OK) return st;
   int64_t blocks = (n_pad + 3) / 4;
@@ -604,7 +624,7 @@ yy_status propagate_begin(yy_ctx ctx, const yy_model* model, const yy_scales* sc
   if (!x || !box_lo || !box_hi || !logw_in || !logw_out)
     return fail(YY_ERR_ARG, "yy_propagate: NULL array");
   if (logw_in == logw_out) return fail(YY_ERR_ARG, "yy_propagate: logw_in and logw_out alias");
-  if (prec < YY_PREC_AUTO || prec > YY_PREC_BF16X3S) return fail(YY_ERR_ARG, "yy_propagate: bad prec");
+  if (prec < YY_PREC_AUTO || prec > YY_PREC_BF16X3P) return fail(YY_ERR_ARG, "yy_propagate: bad prec");
   const int32_t S = scales->S;
   double c[YY_MAX_SCALES + 1];
   for (int s = 0; s < S; ++s)
@@ -623,7 +643,7 @@ yy_status propagate_begin(yy_ctx ctx, const yy_model* model, const yy_scales* sc
   YY_HIP(hipSetDevice(ctx->device));
   st = prepare_nodes(ctx, model, n, x, node_version, box_lo, box_hi,
                      prec == YY_PREC_BF16X3 || prec == YY_PREC_BF16X3G || prec == YY_PREC_BF16X1 ||
-                         prec == YY_PREC_BF16X3S,
+                         prec == YY_PREC_BF16X3S || prec == YY_PREC_BF16X3P,
                      prec == YY_PREC_FP32_MFMA, prec);
   if (st != YY_OK) return st;
   const Prepared& P = ctx->prep;
@@ -692,9 +712,12 @@ yy_status propagate_begin(yy_ctx ctx, const yy_model* model, const yy_scales* sc
       ex.kapd[s] = kapd[s];
       ex.taud[s] = taud[s];
     }
-    if ((st = ctx->bsrc.ensure((size_t)S * (n_pad + n_pad / 128) * sizeof(float))) != YY_OK) return st;
+    // (BF16X3P: the biases over the first kPreK coordinates follow in the same layout)
+    const size_t bsz = (size_t)S * (n_pad + n_pad / 128);
+    if ((st = ctx->bsrc.ensure((prec == YY_PREC_BF16X3P ? 2 : 1) * bsz * sizeof(float))) != YY_OK) return st;
     ex.bsrc = ctx->bsrc.as<float>();
-    if (prec == YY_PREC_BF16X3S) {
+    ex.bpre = prec == YY_PREC_BF16X3P ? ex.bsrc + bsz : nullptr;
+    if (prec == YY_PREC_BF16X3S || prec == YY_PREC_BF16X3P) {
       if ((st = ctx->sflags.ensure((size_t)tbs * jtl * 8)) != YY_OK) return st;
       ex.flags = ctx->sflags.as<uint8_t>();
       ctx->sflags_tbs = tbs;

@@ -24,11 +24,11 @@ YY_OK, YY_ERR_ARG, YY_ERR_ALLOC, YY_ERR_HIP, YY_ERR_NUMERIC, YY_ERR_UNSUPPORTED 
 YY_FLAG_ALL_ZERO, YY_FLAG_CLAMPED, YY_FLAG_RESAMPLE_ZERO, YY_FLAG_LOW_ESS = 1, 2, 4, 8
 YY_F_ZERO, YY_F_COS, YY_F_LINEAR = 0, 1, 2
 YY_H_IDENTITY, YY_H_CUBE, YY_H_LINEAR = 0, 1, 2
-YY_PREC_AUTO, YY_PREC_FP32, YY_PREC_FP32_MFMA, YY_PREC_BF16X3, YY_PREC_BF16X1, YY_PREC_BF16X3G, YY_PREC_BF16X3S = \
-    0, 1, 2, 3, 4, 5, 6
+(YY_PREC_AUTO, YY_PREC_FP32, YY_PREC_FP32_MFMA, YY_PREC_BF16X3, YY_PREC_BF16X1, YY_PREC_BF16X3G, YY_PREC_BF16X3S,
+ YY_PREC_BF16X3P) = 0, 1, 2, 3, 4, 5, 6, 7
 PREC_BY_NAME = {"auto": YY_PREC_AUTO, "fp32": YY_PREC_FP32, "fp32_mfma": YY_PREC_FP32_MFMA,
                 "bf16x3": YY_PREC_BF16X3, "bf16x1": YY_PREC_BF16X1,
-                "bf16x3g": YY_PREC_BF16X3G, "bf16x3s": YY_PREC_BF16X3S}
+                "bf16x3g": YY_PREC_BF16X3G, "bf16x3s": YY_PREC_BF16X3S, "bf16x3p": YY_PREC_BF16X3P}
 EXPORTED = ["yy_last_error", "yy_create", "yy_destroy", "yy_set_stream", "yy_get_status",
             "yy_kernel_coefficients", "yy_nodes_sobol", "yy_propagate", "yy_loglik_update",
             "yy_normalise_moments", "yy_restart", "yy_timing_enable", "yy_timing_read", "yy_screen_count",
@@ -309,7 +309,7 @@ def yy_timing_read(ctx):
 
 
 def yy_screen_count(ctx):
-    """(flagged tiles, tiles) of the last BF16X3S propagation on ctx."""
+    """(flagged tiles, tiles) of the last BF16X3S or BF16X3P propagation on ctx."""
     fl = ctypes.c_int64(0)
     t = ctypes.c_int64(0)
     _check(_lib.yy_screen_count(ctx, ctypes.byref(fl), ctypes.byref(t)), "yy_screen_count")

@@ -36,7 +36,7 @@ def _gpu_filter(w, dys, prec, steps):
     return f
 
 
-@pytest.mark.parametrize("prec,tol", [("bf16x3s", 1e-5), ("bf16x3g", 1e-5), ("bf16x3", 1e-5), ("bf16x1", 1e-5),
+@pytest.mark.parametrize("prec,tol", [("bf16x3p", 1e-5), ("bf16x3s", 1e-5), ("bf16x3g", 1e-5), ("bf16x3", 1e-5), ("bf16x1", 1e-5),
                                       ("fp32_mfma", 1e-5)])
 def test_cubic_r1000_n65536_sampled_rows(prec, tol):
     from paper_2509_16896_amd import yy
@@ -92,7 +92,7 @@ def test_cubic_r100_n16384_short_run():
     w = W.shrink(W.cubic_r100(), K=3)
     xs, dys = W.simulate(w)
     ref = ofilter.run_filter(w, dys)
-    for prec, tol in [("bf16x3s", 1e-3), ("bf16x3g", 1e-3), ("fp32", 1e-5)]:
+    for prec, tol in [("bf16x3p", 1e-3), ("bf16x3s", 1e-3), ("bf16x3g", 1e-3), ("fp32", 1e-5)]:
         f = _gpu_filter(w, dys, prec, w.K)
         try:
             means = f.hist.cpu().numpy()
@@ -103,10 +103,11 @@ def test_cubic_r100_n16384_short_run():
         assert err <= tol
 
 
-def test_cubic_r1000_n65536_chosen_form_means():
+@pytest.mark.parametrize("prec", ["bf16x3p", "bf16x3s"])
+def test_cubic_r1000_n65536_chosen_form_means(prec):
     w = W.shrink(W.cubic_r1000(), K=4)
     xs, dys = W.simulate(w)
-    fs = _gpu_filter(w, dys, "bf16x3s", w.K)
+    fs = _gpu_filter(w, dys, prec, w.K)
     try:
         got = fs.hist.cpu().numpy()
     finally:
@@ -117,6 +118,6 @@ def test_cubic_r1000_n65536_chosen_form_means():
     finally:
         fp.close()
     err = np.max(np.abs(got - ref))
-    print(f"r=1000, n=65536, 4 steps: max |mean(bf16x3s) - mean(fp32)| = {err:.3g}")
+    print(f"r=1000, n=65536, 4 steps: max |mean({prec}) - mean(fp32)| = {err:.3g}")
     assert np.all(np.isfinite(got))
     assert err <= 1e-3

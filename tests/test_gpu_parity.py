@@ -247,7 +247,7 @@ MFMA_CASES = {
 }
 
 
-@pytest.mark.parametrize("prec", ["fp32_mfma", "bf16x3", "bf16x3g", "bf16x3s", "bf16x1"])
+@pytest.mark.parametrize("prec", ["fp32_mfma", "bf16x3", "bf16x3g", "bf16x3s", "bf16x3p", "bf16x1"])
 @pytest.mark.parametrize("name", sorted(MFMA_CASES))
 def test_propagate_mfma_parity(ctx, name, prec):
     kw = dict(MFMA_CASES[name])
@@ -269,7 +269,7 @@ def test_propagate_mfma_parity(ctx, name, prec):
     assert np.max(np.abs(got[f] - plain[f]) / np.maximum(1.0, np.abs(plain[f]))) < 2e-6
 
 
-@pytest.mark.parametrize("prec", ["fp32", "fp32_mfma", "bf16x3", "bf16x3g", "bf16x3s", "bf16x1"])
+@pytest.mark.parametrize("prec", ["fp32", "fp32_mfma", "bf16x3", "bf16x3g", "bf16x3s", "bf16x3p", "bf16x1"])
 def test_propagate_single_node_raw_value(ctx, prec):
     """One node: the only source is the target itself, so the raw (unnormalised) value is
     the signed combination of the self-pair Gaussian densities -- constants included."""
@@ -282,7 +282,7 @@ def test_propagate_single_node_raw_value(ctx, prec):
             assert abs(got[0] - ref[0]) <= 1e-5 * max(1.0, abs(ref[0])), (r, got[0], ref[0])
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x3g", "bf16x3s"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3g", "bf16x3s", "bf16x3p"])
 def test_propagate_empty_input(ctx, prec):
     gm = yy.Model(8, 8, yy.YY_F_COS, None, yy.YY_H_IDENTITY, None, 0.0, 0.1, 1.0)
     z = torch.zeros(8, dtype=torch.float64, device="cuda")

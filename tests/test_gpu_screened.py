@@ -1,5 +1,6 @@
-"""The screened split form (BF16X3S): a one-product BF16 screen over every tile,
-the split form over the tiles it cannot rule out.
+"""The screened split forms: a one-product BF16 screen over every tile (on all
+coordinates for BF16X3S, on the first 64 for BF16X3P), the split form over the
+tiles it cannot rule out.
 
 Against the oracle on sampled rows at sizes where the screen flags some tiles
 and passes others, against the unscreened split form (BF16X3G) everywhere, and
@@ -58,23 +59,24 @@ CASES = {
 }
 
 
+@pytest.mark.parametrize("form", ["bf16x3s", "bf16x3p"])
 @pytest.mark.parametrize("name", sorted(CASES))
-def test_screened_matches_split_form_and_oracle_rows(ctx, name):
+def test_screened_matches_split_form_and_oracle_rows(ctx, name, form):
     c = _case(**CASES[name])
-    got = _run(ctx, c, "bf16x3s")
+    got = _run(ctx, c, form)
     ref = _run(ctx, c, "bf16x3g")
     f = np.isfinite(ref)
     assert np.array_equal(np.isfinite(got), f)
     # both forms keep every pair within 2^-80 of a row maximum exactly: they agree to FP32 rounding
     rel = np.abs(got[f] - ref[f]) / np.maximum(1.0, np.abs(ref[f]))
-    print(f"{name}: max |x3s - x3g| / max(1, |x3g|) = {rel.max():.3g}")
+    print(f"{name}: max |{form} - x3g| / max(1, |x3g|) = {rel.max():.3g}")
     assert rel.max() < 2e-6
-    assert np.array_equal(_run(ctx, c, "bf16x3s"), got)   # deterministic
+    assert np.array_equal(_run(ctx, c, form), got)   # deterministic
     flagged, tiles = yy.yy_screen_count(ctx)
     n = c["n"]
     assert tiles == ((n + 255) // 256) * ((n + 127) // 128)
     assert 0 <= flagged <= tiles
-    print(f"{name}: screen flagged {flagged} of {tiles} tiles")
+    print(f"{name}: {form} screen flagged {flagged} of {tiles} tiles")
     if "stripes" in CASES[name]:
         assert 0.2 * tiles < flagged < 0.9 * tiles
     # sampled rows against the oracle
