@@ -32,11 +32,9 @@ METRIC = "filter steps/sec + propagation TFLOP/s at r=1000,n=65536 vs plain FP32
 PEAK_TFLOPS = {"bf16x3": 2500.0, "bf16x3g": 2500.0, "bf16x3s": 2500.0, "bf16x3p": 2500.0, "bf16x1": 2500.0,
                "fp32_mfma": 157.3}
 VALU_FP32_PEAK = 78.6   # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz, packed FP32 disabled
-# matrix-core products executed per algorithmic product (x.x and x.f each count once); the
-# screened split form's screen executes x.x only (the x.f term is bounded), half a product per
-# algorithmic product, plus the split form's two on the tiles the screen flags (counted after
-# the run)
+# matrix-core products executed per algorithmic product (x.x and x.f each count once)
 EXEC_PER_ALG = {"bf16x3": 3.0, "bf16x3g": 2.0, "bf16x1": 1.0, "fp32_mfma": 1.0}
+PRE_K = 64   # coordinates of the partial-distance screen (BF16X3P)
 PAIR_SRC = os.path.join(ROOT, "paper_2509_16896_amd", "csrc", "yy_pair_mfma.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pair_mfma_cubic_r1000_n65536_traffic.md")
 
@@ -46,8 +44,21 @@ def log(msg):
 
 
 def alg_flops(w) -> float:
+    """The method's pairwise products per propagation: 2 n^2 r per product, x.x and (S > 1) x.f."""
     P = 1 if len(w.scales) == 1 else 2
     return 2.0 * w.n * w.n * w.r * P
+
+
+def screened_work(w, prec, flagged, tiles):
+    """(algorithmic, executed) matrix-core flop of one propagation in a screened form: the
+    screen's product x.x for every pair over the coordinates it uses (all r for BF16X3S, the
+    first 64 for BF16X3P; the x.f term is bounded, not formed), plus the method's products on
+    the flagged tiles, which the split form executes twice over (three BF16 products for x.x,
+    one for x.f)."""
+    k = w.r if prec == "bf16x3s" else min(PRE_K, w.r)
+    screen = 2.0 * w.n * w.n * k
+    split = alg_flops(w) * flagged / max(tiles, 1)
+    return screen + split, screen + 2.0 * split
 
 
 def run_gpu(w, dys, prec, warmup, steps, timing=True, proposal_params=None):
@@ -285,9 +296,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--prec", default="bf16x3s",
-                    choices=["fp32", "fp32_mfma", "bf16x3", "bf16x3g", "bf16x3s", "bf16x3p", "bf16x1"])
-    ap.add_argument("--other-forms", default="bf16x3g,bf16x3,bf16x1",
+    ap.add_argument("--prec", default=None,
+                    choices=["fp32", "fp32_mfma", "bf16x3", "bf16x3g", "bf16x3s", "bf16x3p", "bf16x1"],
+                    help="form of the pairwise sum (default: bf16x3p; bf16x3s for the batch, which "
+                         "has no partial-distance screen)")
+    ap.add_argument("--other-forms", default="bf16x3s,bf16x3g,bf16x3,bf16x1",
                     help="matrix-core forms whose pairwise kernel is also timed ('none' to skip)")
     ap.add_argument("--baseline-prec", default="fp32_mfma", help="plain FP32 form timed beside ('none' to skip)")
     ap.add_argument("--baseline-steps", type=int, default=4)
@@ -306,6 +319,8 @@ def main():
         print(json.dumps({"error": "this build benchmarks one GPU only; run with --gpus 1"}))
         sys.exit(2)
 
+    if args.prec is None:
+        args.prec = "bf16x3s" if args.workload == "batch64" else "bf16x3p"
     if args.workload == "batch64":
         return main_batch(args)
 
@@ -341,31 +356,35 @@ def main():
         prop_info["used_fraction"] = round(int(f.used_count.item()) / max(f.restarts - 0, 1), 3)
     steps_s = args.steps / elapsed
     avg_kernel_s = (ms / 1e3) / max(launches, 1)
-    achieved = alg_flops(w) / avg_kernel_s / 1e12
+    # the method's products per second of pairwise time, as if every pair were formed
+    dense_tflops = alg_flops(w) / avg_kernel_s / 1e12
     prop_tflops = alg_flops(w) * args.steps / elapsed / 1e12
-    log(f"[bench] {steps_s:.3f} steps/s, pairwise kernel {1e3 * avg_kernel_s:.2f} ms/launch "
-        f"({launches} launches), {achieved:.1f} TFLOP/s algorithmic")
     mfma = args.prec != "fp32"
-    roofline = {"bound": "mfma" if mfma else "alu", "achieved": round(achieved, 3),
-                "peak": PEAK_TFLOPS[args.prec] if mfma else VALU_FP32_PEAK, "unit": "TFLOP/s"}
-    roofline["frac"] = round(roofline["achieved"] / roofline["peak"], 4)
-    roofline["traffic"] = recorded_traffic(args.prec) if args.workload == "cubic_r1000" else None
-    roofline["kernel"] = "k_pair_mfma" if mfma else "k_pair_valu"
-    roofline["kernel_ms"] = round(1e3 * avg_kernel_s, 3)
+    alg, executed = alg_flops(w), alg_flops(w) * EXEC_PER_ALG.get(args.prec, 1.0)
     screen = None
+    kernel = "k_pair_mfma" if mfma else "k_pair_valu"
     if args.prec in ("bf16x3s", "bf16x3p"):
         # the pairwise time is the screen plus the split pass over the flagged tiles
         from paper_2509_16896_amd import yy
         flagged, tiles = yy.yy_screen_count(f.ctx)
         screen = {"flagged_tiles": flagged, "tiles": tiles}
-        roofline["kernel"] = "k_pair_screen, then k_pair_mfma (split form) on flagged tiles"
-        # the partial-distance screen forms x.x over the first 64 coordinates only
-        frac_k = 1.0 if args.prec == "bf16x3s" else min(64, w.r) / w.r
-        EXEC_PER_ALG[args.prec] = 0.5 * frac_k + 2.0 * flagged / max(tiles, 1)
+        alg, executed = screened_work(w, args.prec, flagged, tiles)
+        kernel = ("k_pair_prescreen" if args.prec == "bf16x3p" else "k_pair_screen") + \
+            ", then k_pair_mfma (split form) on flagged tiles"
         log(f"[bench] screen flagged {flagged} of {tiles} tiles for the split form")
+    achieved = alg / avg_kernel_s / 1e12
+    log(f"[bench] {steps_s:.3f} steps/s, pairwise kernels {1e3 * avg_kernel_s:.3f} ms per propagation "
+        f"({launches} launches), {achieved:.1f} TFLOP/s algorithmic, {dense_tflops:.1f} dense-equivalent")
+    roofline = {"bound": "mfma" if mfma else "alu", "achieved": round(achieved, 3),
+                "peak": PEAK_TFLOPS[args.prec] if mfma else VALU_FP32_PEAK, "unit": "TFLOP/s"}
+    roofline["frac"] = round(roofline["achieved"] / roofline["peak"], 4)
+    roofline["traffic"] = recorded_traffic(args.prec) if args.workload == "cubic_r1000" else None
+    roofline["kernel"] = kernel
+    roofline["kernel_ms"] = round(1e3 * avg_kernel_s, 3)
     if mfma:
-        # matrix-core utilisation: executed products (3 per product for the full split) / peak
-        roofline["mfma_exec_frac"] = round(roofline["frac"] * EXEC_PER_ALG[args.prec], 4)
+        # matrix-core utilisation: executed products (3 BF16 products per split product) / peak
+        roofline["mfma_exec_frac"] = round(executed / avg_kernel_s / 1e12 / roofline["peak"], 4)
+    roofline["dense_equivalent_tflops"] = round(dense_tflops, 2)
 
     forms = {}
     if args.other_forms != "none":

@@ -399,9 +399,7 @@ static yy_status build(yy_batch b) {
     b_r.push_back(nblk(r));
     b_rs.push_back(nbr);
     b_one.push_back(1);
-    int64_t blocks = (P.n_pad + 3) / 4;
-    if (blocks > 16384) blocks = 16384;
-    b_prep.push_back((int)blocks);
+    b_prep.push_back(prepare_blocks(P.n_pad));
   }
   if ((st = build_launch(b, b->record, Rc, b_r)) != YY_OK) return st;
   if ((st = build_launch(b, b->rs_local, S1, b_rs)) != YY_OK) return st;

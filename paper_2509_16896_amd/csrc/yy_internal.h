@@ -156,6 +156,8 @@ struct MfmaExtra {
   uint8_t* flags;              // screened split forms: [n_pad/256][ceil(n/128)][8] screen verdicts
   float* bpre;                 // BF16X3P: source biases over the first kPreK coordinates, laid out as bsrc
 };
+// blocks of the node preparation kernel (one wave per 4 nodes, grid-stride)
+int prepare_blocks(int64_t n_pad);
 yy_status launch_src_bias(hipStream_t st, const PairArgs& a, const MfmaExtra& ex);
 yy_status launch_pair_mfma(hipStream_t st, const PairArgs& a, int prec, const MfmaExtra& ex);
 // Batched matrix-core kernel: `sets` is a device array of the per-set kernel

@@ -21,7 +21,10 @@
 //   BF16X1:  hi*hi only (a screen),  FP32: v_mfma_f32_32x32x2_f32 on FP32 data,
 //   BF16X3S: a screen on G alone (k_pair_screen: H bounded, not computed) flags
 //            the tiles that may hold a pair within 2^-80 of a row maximum;
-//            BF16X3G then runs over the flagged tiles only.
+//            BF16X3G then runs over the flagged tiles only,
+//   BF16X3P: the same with a screen on the first 64 coordinates only
+//            (k_pair_prescreen), whose partial squared distance bounds the
+//            full one from below.
 #include <algorithm>
 #include <cstring>
 #include <type_traits>
@@ -770,13 +773,7 @@ __device__ inline void screen_issue_bias(const MArgs& a, const float* bs, uint32
   for (int s = 0; s < a.S; ++s) dma_1k(bs + (size_t)s * a.n_pad + j0 + 4 * lane, sb_lds + s * 1024);
 }
 
-// PRE: the partial-distance screen of BF16X3P.  Over the first kPreK
-// coordinates (superscript p), |x_i - m_j|^2 >= |x_i^p - m_j^p|^2, so the same
-// bound with G, the norms and F taken over those coordinates bounds the exact
-// exponent from above.  It is no lower bound of the row maximum, so M stays at
-// the exact self-pair exponent; boundary targets, whose result is -inf
-// whatever the sum, are not flagged.
-template <int S, int NS, int SPB, bool PRE>
+template <int S, int NS, int SPB>
 __device__ __forceinline__ void screen_block(const MArgs& a, int tb, int split, unsigned char* smem,
                                              float (*sbuf)[kSBRows * kSJ]) {
   static_assert(NS % SPB == 0 && NS / SPB >= 2, "the ring holds at least two groups of stages");
@@ -790,21 +787,21 @@ __device__ __forceinline__ void screen_block(const MArgs& a, int tb, int split, 
   const int64_t jb1 = jb0 + a.s_jps < a.n ? jb0 + a.s_jps : a.n;
   const int ntiles = __builtin_amdgcn_readfirstlane(jb1 > jb0 ? (int)((jb1 - jb0 + kSJ - 1) / kSJ) : 0);
   if (ntiles == 0) return;
-  const int nchunks = __builtin_amdgcn_readfirstlane(PRE ? a.pre_chunks : a.rp / kKC);
+  const int nchunks = __builtin_amdgcn_readfirstlane(a.rp / kKC);
   const int Q = ntiles * nchunks;
   const unsigned char* gb = reinterpret_cast<const unsigned char*>(a.bf);
   const int64_t n_pad = a.n_pad;
   const uint32_t smem_lds = __builtin_amdgcn_readfirstlane(lds_addr(smem));
   const uint32_t sb_lds = __builtin_amdgcn_readfirstlane(lds_addr(&sbuf[0][0]));
   constexpr uint32_t kSbBytes = kSBRows * kSJ * 4;
-  const float* bs = PRE ? a.bpre : a.bsrc;
+  const float* bs = a.bsrc;
 
   // per target and scale: a_i + hx_i F, the running lower bound of the row
   // maximum (the exact self-pair exponent to start) and the slack of its
   // update (the error of G and twice the bound of the x.f term); per scale the
   // margin (the error of G, the skip depth and 16 bits)
-  const double X = PRE ? a.scal[4] : a.scal[1], F = PRE ? a.scal[5] : a.scal[2];
-  const double gam = nchunks * kKC * 0x1p-24;
+  const double X = a.scal[1], F = a.scal[2];
+  const double gam = a.rp * 0x1p-24;
   float at[kIB][S], M[kIB][S], margin[S], slack[kIB][S];
 #pragma unroll
   for (int s = 0; s < S; ++s) {
@@ -815,8 +812,8 @@ __device__ __forceinline__ void screen_block(const MArgs& a, int tb, int split, 
 #pragma unroll
   for (int ib = 0; ib < kIB; ++ib) {
     const int64_t i = i0 + wi * (32 * kIB) + ib * 32 + col;
-    const bool valid = i < a.n && !(PRE && a.bnd[i]);
-    const double nx = valid ? a.node[(PRE ? 3 * a.n : 0) + i] : 0.0;
+    const bool valid = i < a.n;
+    const double nx = valid ? a.node[i] : 0.0;
     const double nf = valid ? a.node[a.n + i] : 0.0;
     const float li = valid ? a.lw2[i] : -INFINITY;
     // hx_i F with 2 kap_s tau_s = log2(e) / q for every s, rounded up
@@ -910,7 +907,7 @@ __device__ __forceinline__ void screen_block(const MArgs& a, int tb, int split, 
         for (int ib = 0; ib < kIB; ++ib) {
           const float mt = m[ib] + at[ib][s];
           need |= mt > M[ib][s] - margin[s];
-          if (!PRE) M[ib][s] = fmaxf(M[ib][s], mt - slack[ib][s]);
+          M[ib][s] = fmaxf(M[ib][s], mt - slack[ib][s]);
         }
       }
     };
@@ -968,13 +965,207 @@ __device__ inline void screen_block_map(const MArgs& a, int& tb, int& split) {
   }
 }
 
-template <int S, int NS, int SPB, bool PRE>
+// ---------------------------------------------------------------------------
+// The partial-distance screen of BF16X3P as a pipeline of its own.  Its K
+// range is PC stages (the first kPreK coordinates), so a wave keeps the hi(x)
+// fragments of its 64 targets in registers for the whole block and only the
+// sources stream through LDS: one 8 KB stage (256 sources x 16 K values) per
+// K chunk, PC stages per tile, a ring of NS stages with LA = NS / PC - 1 tiles
+// in flight.
+// The bound: over the first kPreK coordinates (superscript p),
+// |x_i - m_j|^2 >= |x_i^p - m_j^p|^2, so the bound of screen_block with G, the
+// norms and F taken over those coordinates (a_i^p, b_js^p in a.bpre, F^p)
+// bounds the exact exponent from above.  Being no lower bound of the row
+// maximum, it leaves M at the exact self-pair exponent; boundary targets,
+// whose result is -inf whatever the sum, are not flagged.  The source biases
+// of a tile are read (through the scalar cache) only when its coarse bound
+// leaves a doubt.
+constexpr int kPStage = kSJ * 32;   // bytes per stage of the partial-distance screen
+
+__device__ inline void prescreen_issue(const unsigned char* gb, int64_t n_pad, uint32_t stage_lds, int c,
+                                       int64_t j0, int wave) {
+  const int lane = fresh_lane(), rl = lane >> 1, pc = lane & 1;
+  const int loff = rl * 32 + swz<2>(rl, pc) * 16;
+  dma_1k(gb + ((uint64_t)c * (uint64_t)n_pad + (uint64_t)(j0 + wave * 32)) * 32 + loff, stage_lds + wave * 1024);
+}
+
+template <int S, int PC, int NS>
+__device__ __forceinline__ void prescreen_block(const MArgs& a, int tb, int split, unsigned char* smem) {
+  static_assert(NS % PC == 0 && NS / PC >= 2, "the ring holds at least two tiles");
+  static_assert(PC * kKC <= kPreK, "the screen covers the first kPreK coordinates");
+  constexpr int LA = NS / PC - 1;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wi = wave / kWJ, wj = wave % kWJ, col = lane & 31, g = lane >> 5;
+  const int64_t i0 = (int64_t)tb * kMI;
+  const int64_t jb0 = (int64_t)split * a.s_jps;
+  const int64_t jb1 = jb0 + a.s_jps < a.n ? jb0 + a.s_jps : a.n;
+  const int ntiles = __builtin_amdgcn_readfirstlane(jb1 > jb0 ? (int)((jb1 - jb0 + kSJ - 1) / kSJ) : 0);
+  if (ntiles == 0) return;
+  const unsigned char* gb = reinterpret_cast<const unsigned char*>(a.bf);
+  const int64_t n_pad = a.n_pad;
+  const uint32_t smem_lds = __builtin_amdgcn_readfirstlane(lds_addr(smem));
+
+  // per target and scale: a_i^p + hx_i^p F^p and the exact self-pair exponent;
+  // per scale the margin (as in screen_block, over the first PC stages)
+  const double X = a.scal[4], F = a.scal[5];
+  const double gam = PC * kKC * 0x1p-24;
+  float at[kIB][S], M[kIB][S], margin[S];
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const double XT = X + a.taud[s] * F;
+    const double dD = 2.0 * X * (a.eps_g1 + gam) * X + 16.0 * 0x1p-24 * XT * XT;
+    margin[s] = (float)(2.0 * a.kapd[s] * dD + (double)kSkip + 16.0);
+  }
+  // the targets' fragments, all PC stages (rows i0 .. i0 + 255 < n_pad)
+  bf16x8_t bt[PC][kIB];
+#pragma unroll
+  for (int ib = 0; ib < kIB; ++ib) {
+    const int64_t i = i0 + wi * (32 * kIB) + ib * 32 + col;
+    const bool valid = i < a.n && !a.bnd[i];
+    const double nx = valid ? a.node[3 * a.n + i] : 0.0;
+    const double nf = valid ? a.node[a.n + i] : 0.0;
+    const float li = valid ? a.lw2[i] : -INFINITY;
+    const double hF = 2.0 * a.kapd[0] * a.taud[0] * sqrt(nx) * F * (1.0 + 0x1p-20);
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      at[ib][s] = valid ? (float)(-a.kapd[s] * nx + hF) : -INFINITY;
+      M[ib][s] = (valid && li != -INFINITY) ? li - (float)(a.kapd[s] * a.taud[s] * a.taud[s] * nf) : -INFINITY;
+    }
+#pragma unroll
+    for (int c = 0; c < PC; ++c)
+      bt[c][ib] = *reinterpret_cast<const bf16x8_t*>(gb + ((size_t)c * n_pad + i) * 32 + g * 16);
+  }
+  wait_vmcnt<0>();   // before the first copy: the waits below count copies only
+
+#pragma unroll
+  for (int p = 0; p < LA; ++p)
+    if (p < ntiles)
+#pragma unroll
+      for (int u = 0; u < PC; ++u)
+        prescreen_issue(gb, n_pad, smem_lds + ((p * PC + u) % NS) * kPStage, u, jb0 + (int64_t)p * kSJ, wave);
+
+  for (int t = 0; t < ntiles; ++t) {
+    const int64_t j0 = jb0 + (int64_t)t * kSJ;
+    // this wave's copies of tile t have landed (those of the next LA - 1 tiles may still fly) ...
+    if (t + LA - 1 < ntiles) wait_vmcnt<(LA - 1) * PC>();
+    else wait_vmcnt<0>();
+    __syncthreads();   // ... for every wave; the slots of tile t - 1 are free again
+    if (t + LA < ntiles)
+#pragma unroll
+      for (int u = 0; u < PC; ++u)
+        prescreen_issue(gb, n_pad, smem_lds + (((t + LA) * PC + u) % NS) * kPStage, u, j0 + (int64_t)LA * kSJ,
+                        wave);
+    f32x16_t G[kIB][kSJB];
+#pragma unroll
+    for (int x = 0; x < kIB; ++x)
+#pragma unroll
+      for (int y = 0; y < kSJB; ++y)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) G[x][y][v] = 0.f;
+#pragma unroll
+    for (int u = 0; u < PC; ++u) {
+      const unsigned char* base = smem + ((t * PC + u) % NS) * kPStage;
+      const int ln = fresh_lane(), cl = ln & 31, gl = ln >> 5;
+      bf16x8_t xh[kSJB];
+#pragma unroll
+      for (int jb = 0; jb < kSJB; ++jb) {
+        const int row = wj * (32 * kSJB) + jb * 32 + cl;
+        xh[jb] = *reinterpret_cast<const bf16x8_t*>(base + row * 32 + swz<2>(row, gl) * 16);
+      }
+#pragma unroll
+      for (int ib = 0; ib < kIB; ++ib)
+#pragma unroll
+        for (int jb = 0; jb < kSJB; ++jb)
+          G[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[jb], bt[u][ib], G[ib][jb], 0, 0, 0);
+    }
+    // the verdict on this wave's 64 x 128 sub-tile: the coarse bound, then the
+    // per-pair bound where it leaves a doubt
+    const bool diag = j0 < i0 + kMI && i0 < j0 + kSJ;
+    const int jl0 = wj * (32 * kSJB);
+    float gmax[kIB];
+#pragma unroll
+    for (int ib = 0; ib < kIB; ++ib) {
+      float m = -INFINITY;
+#pragma unroll
+      for (int jb = 0; jb < kSJB; ++jb)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) m = fmaxf(m, G[ib][jb][v]);
+      gmax[ib] = m;
+    }
+    typedef const __attribute__((address_space(4))) float* const_f32_ptr;
+    const const_f32_ptr bmax = (const_f32_ptr)(a.bpre + (size_t)S * n_pad + (size_t)(j0 / kMJ + wj));
+    bool doubt = false;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const float bm = bmax[(size_t)s * (n_pad / kMJ)];
+#pragma unroll
+      for (int ib = 0; ib < kIB; ++ib) doubt |= fmaf(a.c1[s], gmax[ib], bm) + at[ib][s] > M[ib][s] - margin[s];
+    }
+    bool need = false;
+    if (__any(doubt)) {
+      int bself[kIB];   // slab index jb * 16 + v of the self pair in this lane (-1: none)
+#pragma unroll
+      for (int ib = 0; ib < kIB; ++ib) {
+        const int64_t d = i0 + wi * (32 * kIB) + ib * 32 + col - j0 - jl0;
+        const bool self = diag && d >= 0 && d < 32 * kSJB && (int)((d >> 2) & 1) == g;
+        bself[ib] = self ? (int)((d >> 5) * 16 + ((d >> 3) & 3) * 4 + (d & 3)) : -1;
+      }
+      // (the biases through the scalar cache: the addresses are wave-uniform
+      // up to the lane half g, and a vector load would wait for the copies)
+      typedef float f32x8_t __attribute__((ext_vector_type(8)));
+      typedef const __attribute__((address_space(4))) f32x8_t* const_f32x8_ptr;
+      const const_f32x8_ptr bs = (const_f32x8_ptr)(a.bpre + j0 + jl0);   // 8 sources per element
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const float c1 = a.c1[s];
+        float m[kIB];
+#pragma unroll
+        for (int ib = 0; ib < kIB; ++ib) m[ib] = -INFINITY;
+#pragma unroll
+        for (int jb = 0; jb < kSJB; ++jb) {
+#pragma unroll
+          for (int v = 0; v < 16; ++v) {
+            // sources 8 (v >> 2) + 4 g + (v & 3) of the 32-source block jb
+            const f32x8_t q = bs[((size_t)s * n_pad) / 8 + jb * 4 + (v >> 2)];
+            const float bj = g ? q[4 + (v & 3)] : q[v & 3];
+#pragma unroll
+            for (int ib = 0; ib < kIB; ++ib) {
+              float e = fmaf(c1, G[ib][jb][v], bj);
+              if (jb * 16 + v == bself[ib]) e = -INFINITY;
+              m[ib] = fmaxf(m[ib], e);
+            }
+          }
+        }
+#pragma unroll
+        for (int ib = 0; ib < kIB; ++ib) need |= m[ib] + at[ib][s] > M[ib][s] - margin[s];
+      }
+    }
+    const bool flag = __any(need);
+    const int64_t jt = j0 / kMJ + wj;   // the split pass's 128-source tile of this sub-tile
+    if (lane == 0 && jt < a.jtl) {
+      a.flags[((size_t)tb * a.jtl + jt) * 8 + wi] = flag ? 1 : 0;
+      a.flags[((size_t)tb * a.jtl + jt) * 8 + 4 + wi] = 0;
+    }
+  }
+}
+
+template <int S, int PC, int NS>
+__global__ void __launch_bounds__(kNT, 1) k_pair_prescreen(MArgs a) {
+  __shared__ __attribute__((aligned(1024))) unsigned char smem[NS * kPStage];
+  int tb, split;
+  screen_block_map(a, tb, split);
+  prescreen_block<S, PC, NS>(a, tb, split, smem);
+}
+
+
+template <int S, int NS, int SPB>
 __global__ void __launch_bounds__(kNT, 1) k_pair_screen(MArgs a) {
   __shared__ __attribute__((aligned(1024))) unsigned char smem[NS * kSStage];
   __shared__ __attribute__((aligned(1024))) float sbuf[2][kSBRows * kSJ];
   int tb, split;
   screen_block_map(a, tb, split);
-  screen_block<S, NS, SPB, PRE>(a, tb, split, smem, sbuf);
+  screen_block<S, NS, SPB>(a, tb, split, smem, sbuf);
 }
 
 template <int S, int NS, int SPB>
@@ -983,7 +1174,7 @@ __global__ void __launch_bounds__(kNT, 1) k_pair_screen_batch(const MArgs* __res
   __shared__ __attribute__((aligned(1024))) unsigned char smem[NS * kSStage];
   __shared__ __attribute__((aligned(1024))) float sbuf[2][kSBRows * kSJ];
   const int4 it = items[blockIdx.x];
-  screen_block<S, NS, SPB, false>(sets[__builtin_amdgcn_readfirstlane(it.x)], __builtin_amdgcn_readfirstlane(it.y),
+  screen_block<S, NS, SPB>(sets[__builtin_amdgcn_readfirstlane(it.x)], __builtin_amdgcn_readfirstlane(it.y),
                            __builtin_amdgcn_readfirstlane(it.z), smem, sbuf);
 }
 
@@ -1123,15 +1314,15 @@ static yy_status launch_s(hipStream_t st, const MArgs& m, int prec, int nblocks)
   } else if (prec == YY_PREC_BF16X3S) {
     // the screen over every tile, then the split form over the flagged tiles
     // four K stages per barrier when the K padding allows it, else two
-    if (m.rp % 64 == 0) k_pair_screen<S, 8, 4, false><<<nblocks, kNT, 0, st>>>(m);
-    else k_pair_screen<S, 8, 2, false><<<nblocks, kNT, 0, st>>>(m);
+    if (m.rp % 64 == 0) k_pair_screen<S, 8, 4><<<nblocks, kNT, 0, st>>>(m);
+    else k_pair_screen<S, 8, 2><<<nblocks, kNT, 0, st>>>(m);
     YY_LAUNCH_CHECK("k_pair_mfma (screen)");
     k_pair_mfma<S, 2, 4, 2, true><<<nblocks, kNT, 0, st>>>(m);
   } else if (prec == YY_PREC_BF16X3P) {
-    // the partial-distance screen (2 or 4 K stages, all in one barrier group),
-    // then the split form over the flagged tiles
-    if (m.pre_chunks % 4 == 0) k_pair_screen<S, 8, 4, true><<<nblocks, kNT, 0, st>>>(m);
-    else k_pair_screen<S, 8, 2, true><<<nblocks, kNT, 0, st>>>(m);
+    // the partial-distance screen (2 or 4 K stages), then the split form over
+    // the flagged tiles
+    if (m.pre_chunks == 4) k_pair_prescreen<S, 4, 16><<<nblocks, kNT, 0, st>>>(m);
+    else k_pair_prescreen<S, 2, 16><<<nblocks, kNT, 0, st>>>(m);
     YY_LAUNCH_CHECK("k_pair_mfma (partial-distance screen)");
     k_pair_mfma<S, 2, 4, 2, true><<<nblocks, kNT, 0, st>>>(m);
   } else if (prec == YY_PREC_BF16X1) {

@@ -22,9 +22,17 @@
 namespace yy {
 
 // ---------------------------------------------------------------------------
-// (1) node preparation: one wavefront per node.
+// (1) node preparation: one wavefront per 4 consecutive nodes, 16 lanes per
+// node, one 16-wide K chunk per step, so that each step writes whole 128-byte
+// lines of the tiled planes (4 nodes x 16 K values).
 // Matrix-core planes are tiled [plane][rp/16][n_pad][16] so that 16 K values
 // of consecutive nodes are contiguous; rows n..n_pad-1 are zero.
+__device__ inline double sum16(double v) {
+#pragma unroll
+  for (int off = 8; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
 __device__ __forceinline__ void k_prepare_body(int64_t n, int64_t n_pad, int32_t r, int32_t rp,
                                                     int32_t drift, const double* __restrict__ A,
                                                     const double* __restrict__ x,
@@ -34,27 +42,23 @@ __device__ __forceinline__ void k_prepare_body(int64_t n, int64_t n_pad, int32_t
                                                     uint16_t* __restrict__ bf, float* __restrict__ f32t,
                                                     double* __restrict__ node, int* __restrict__ bnd,
                                                     int bx_, int gx_) {
-  const int lane = threadIdx.x & 63;
+  static_assert(kPreK % 16 == 0, "the prefix is whole K chunks");
+  const int lane = threadIdx.x & 63, sub = lane >> 4, kl = lane & 15;
   const int64_t wave = ((int64_t)bx_ * blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gx_ * blockDim.x) >> 6;
   const size_t plane = (size_t)n_pad * rp;
-  for (int64_t i = wave; i < n_pad; i += nwaves) {
-    if (i >= n) {
-      for (int32_t k = lane; k < rp; k += 64) {
-        const size_t t = ((size_t)(k >> 4) * n_pad + i) * 16 + (k & 15);
-        if (bf) bf[t] = bf[plane + t] = bf[2 * plane + t] = bf[3 * plane + t] = 0;
-        if (f32t) f32t[t] = f32t[plane + t] = 0.f;
-      }
-      continue;
-    }
-    const double* xi = x + (size_t)i * r;
+  for (int64_t i4 = wave * 4; i4 < n_pad; i4 += nwaves * 4) {
+    const int64_t i = i4 + sub;   // n_pad is a multiple of 4
+    const bool real = i < n;
+    const double* xi = x + (size_t)(real ? i : 0) * r;
     double sxx = 0.0, sff = 0.0, sxf = 0.0;
     double pxx = 0.0, pff = 0.0, pxf = 0.0;   // over the first kPreK coordinates
     int b = 0;
-    for (int32_t k = lane; k < rp; k += 64) {
+    for (int32_t k0 = 0; k0 < rp; k0 += 16) {
+      const int32_t k = k0 + kl;
       float xcv = 0.f, fv = 0.f;
       double xcd = 0.0, fd = 0.0;
-      if (k < r) {
+      if (real && k < r) {
         const double xv = xi[k];
         const double c = 0.5 * (lo[k] + hi[k]);
         xcd = xv - c;
@@ -72,16 +76,18 @@ __device__ __forceinline__ void k_prepare_body(int64_t n, int64_t n_pad, int32_t
         sxf = fma(xcd, fd, sxf);
         xcv = (float)xcd;
         fv = (float)fd;
-        if (k < kPreK) {
-          pxx = sxx;
-          pff = sff;
-          pxf = sxf;
-        }
       }
-      const size_t o = (size_t)i * rp + k;
-      xc32[o] = xcv;
-      f32[o] = fv;
-      const size_t t = ((size_t)(k >> 4) * n_pad + i) * 16 + (k & 15);
+      if (k0 < kPreK) {
+        pxx = sxx;
+        pff = sff;
+        pxf = sxf;
+      }
+      if (real) {
+        const size_t o = (size_t)i * rp + k;
+        xc32[o] = xcv;
+        f32[o] = fv;
+      }
+      const size_t t = ((size_t)(k0 >> 4) * n_pad + i) * 16 + kl;
       if (bf) {
         const uint16_t xh = f32_to_bf16(xcv);
         const uint16_t xl = f32_to_bf16((float)(xcd - (double)bf16_to_f32(xh)));
@@ -97,15 +103,15 @@ __device__ __forceinline__ void k_prepare_body(int64_t n, int64_t n_pad, int32_t
         f32t[plane + t] = fv;
       }
     }
-    static_assert(kPreK <= 64, "one coordinate of the prefix per lane");
-    sxx = wave_sum(sxx);
-    sff = wave_sum(sff);
-    sxf = wave_sum(sxf);
-    pxx = wave_sum(pxx);
-    pff = wave_sum(pff);
-    pxf = wave_sum(pxf);
-    b = wave_or(b);
-    if (lane == 0) {
+    sxx = sum16(sxx);
+    sff = sum16(sff);
+    sxf = sum16(sxf);
+    pxx = sum16(pxx);
+    pff = sum16(pff);
+    pxf = sum16(pxf);
+#pragma unroll
+    for (int off = 8; off > 0; off >>= 1) b |= __shfl_xor(b, off, 64);
+    if (kl == 0 && real) {
       node[i] = sxx;
       node[n + i] = sff;
       node[2 * n + i] = sxf;
@@ -116,6 +122,8 @@ __device__ __forceinline__ void k_prepare_body(int64_t n, int64_t n_pad, int32_t
     }
   }
 }
+
+int prepare_blocks(int64_t n_pad) { return (int)std::min<int64_t>((n_pad + 15) / 16, 16384); }
 
 __global__ void __launch_bounds__(kBlock) k_prepare(int64_t n, int64_t n_pad, int32_t r, int32_t rp,
                                                     int32_t drift, const double* __restrict__ A,
@@ -149,11 +157,25 @@ __device__ __forceinline__ void k_prepare_scalars_body(int64_t n, int32_t r,
   for (int32_t k = threadIdx.x; k < r; k += kBlock) lv += log(hi[k] - lo[k]);
   lv = block_sum<kBlock>(lv, sh);
   double mx = 0.0, mf = 0.0, px = 0.0, pf = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += kBlock) {
-    mx = fmax(mx, node[i]);
-    mf = fmax(mf, node[n + i]);
-    px = fmax(px, node[3 * n + i]);
-    pf = fmax(pf, node[4 * n + i]);
+  // 8 rows per thread in flight (the loop is bound by load latency)
+  for (int64_t i0 = threadIdx.x; i0 < n; i0 += 8 * kBlock) {
+    double v[8][4];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t i = i0 + (int64_t)u * kBlock;
+      const bool ok = i < n;
+      v[u][0] = ok ? node[i] : 0.0;
+      v[u][1] = ok ? node[n + i] : 0.0;
+      v[u][2] = ok ? node[3 * n + i] : 0.0;
+      v[u][3] = ok ? node[4 * n + i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      mx = fmax(mx, v[u][0]);
+      mf = fmax(mf, v[u][1]);
+      px = fmax(px, v[u][2]);
+      pf = fmax(pf, v[u][3]);
+    }
   }
   mx = block_max<kBlock>(mx, sh);
   mf = block_max<kBlock>(mf, sh);
@@ -522,9 +544,7 @@ yy_status prepare_nodes(yy_ctx ctx, const yy_model* m, int64_t n, const double* 
   if ((st = P.node.ensure((size_t)6 * n * sizeof(double))) != YY_OK) return st;
   if ((st = P.bnd.ensure((size_t)n * sizeof(int))) != YY_OK) return st;
   if ((st = P.scal.ensure(8 * sizeof(double))) != YY_OK) return st;
-  int64_t blocks = (n_pad + 3) / 4;
-  if (blocks > 16384) blocks = 16384;
-  k_prepare<<<(unsigned)blocks, kBlock, 0, ctx->stream>>>(
+  k_prepare<<<(unsigned)prepare_blocks(n_pad), kBlock, 0, ctx->stream>>>(
       n, n_pad, m->r, rp, m->drift, m->A, x, lo, hi, P.xc32.as<float>(), P.f32.as<float>(),
       want_bf16 ? P.bf.as<uint16_t>() : nullptr, want_f32t ? P.f32t.as<float>() : nullptr,
       P.node.as<double>(), P.bnd.as<int>());
