@@ -179,7 +179,8 @@ yy_status yy_loglik_update(yy_ctx ctx, const yy_model* model, int64_t n, const d
  *   mean = sum_i w_i x_i;  cov = sum_i w_i (x_i - mean)(x_i - mean)^T;
  *   ess = 1 / sum_i w_i^2;  *logZ_acc += logZ.
  *   w: device [n] or NULL; logZ_step, logZ_acc (read-modify-write), ess:
- *   device scalars; mean: device [r]; cov: device [r*r] or NULL.
+ *   device scalars; mean: device [r] or NULL (then x is not read, and cov
+ *   must be NULL); cov: device [r*r] or NULL.
  * If every weight is -inf, YY_FLAG_ALL_ZERO is set and the outputs are left
  * unchanged except logZ_step = -inf. */
 yy_status yy_normalise_moments(yy_ctx ctx, int64_t n, int32_t r, const double* x, double* logw,

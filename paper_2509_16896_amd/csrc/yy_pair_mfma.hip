@@ -969,9 +969,11 @@ __device__ inline void screen_block_map(const MArgs& a, int& tb, int& split) {
 // The partial-distance screen of BF16X3P as a pipeline of its own.  Its K
 // range is PC stages (the first kPreK coordinates), so a wave keeps the hi(x)
 // fragments of its 64 targets in registers for the whole block and only the
-// sources stream through LDS: one 8 KB stage (256 sources x 16 K values) per
+// sources stream through LDS: one 4 KB stage (128 sources x 16 K values) per
 // K chunk, PC stages per tile, a ring of NS stages with LA = NS / PC - 1 tiles
-// in flight.
+// in flight.  A block is 4 waves (256 targets x 128 sources per tile) and a CU
+// runs two: the blocks do not wait for each other at the per-tile barrier, so
+// one block's verdict (vector ALU) overlaps the other's products.
 // The bound: over the first kPreK coordinates (superscript p),
 // |x_i - m_j|^2 >= |x_i^p - m_j^p|^2, so the bound of screen_block with G, the
 // norms and F taken over those coordinates (a_i^p, b_js^p in a.bpre, F^p)
@@ -980,7 +982,9 @@ __device__ inline void screen_block_map(const MArgs& a, int& tb, int& split) {
 // whose result is -inf whatever the sum, are not flagged.  The source biases
 // of a tile are read (through the scalar cache) only when its coarse bound
 // leaves a doubt.
-constexpr int kPStage = kSJ * 32;   // bytes per stage of the partial-distance screen
+constexpr int kPJ = 128;              // sources per tile of the partial-distance screen
+constexpr int kPW = kMI / (32 * kIB); // its waves per block (64 targets each)
+constexpr int kPStage = kPJ * 32;     // bytes per stage
 
 __device__ inline void prescreen_issue(const unsigned char* gb, int64_t n_pad, uint32_t stage_lds, int c,
                                        int64_t j0, int wave) {
@@ -993,14 +997,15 @@ template <int S, int PC, int NS>
 __device__ __forceinline__ void prescreen_block(const MArgs& a, int tb, int split, unsigned char* smem) {
   static_assert(NS % PC == 0 && NS / PC >= 2, "the ring holds at least two tiles");
   static_assert(PC * kKC <= kPreK, "the screen covers the first kPreK coordinates");
+  static_assert(kPW * 32 == kPJ && kSJB * 32 == kPJ, "one 1 KB copy per wave per stage; a wave spans the tile");
   constexpr int LA = NS / PC - 1;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int wi = wave / kWJ, wj = wave % kWJ, col = lane & 31, g = lane >> 5;
+  const int wi = wave, col = lane & 31, g = lane >> 5;
   const int64_t i0 = (int64_t)tb * kMI;
   const int64_t jb0 = (int64_t)split * a.s_jps;
   const int64_t jb1 = jb0 + a.s_jps < a.n ? jb0 + a.s_jps : a.n;
-  const int ntiles = __builtin_amdgcn_readfirstlane(jb1 > jb0 ? (int)((jb1 - jb0 + kSJ - 1) / kSJ) : 0);
+  const int ntiles = __builtin_amdgcn_readfirstlane(jb1 > jb0 ? (int)((jb1 - jb0 + kPJ - 1) / kPJ) : 0);
   if (ntiles == 0) return;
   const unsigned char* gb = reinterpret_cast<const unsigned char*>(a.bf);
   const int64_t n_pad = a.n_pad;
@@ -1043,10 +1048,10 @@ __device__ __forceinline__ void prescreen_block(const MArgs& a, int tb, int spli
     if (p < ntiles)
 #pragma unroll
       for (int u = 0; u < PC; ++u)
-        prescreen_issue(gb, n_pad, smem_lds + ((p * PC + u) % NS) * kPStage, u, jb0 + (int64_t)p * kSJ, wave);
+        prescreen_issue(gb, n_pad, smem_lds + ((p * PC + u) % NS) * kPStage, u, jb0 + (int64_t)p * kPJ, wave);
 
   for (int t = 0; t < ntiles; ++t) {
-    const int64_t j0 = jb0 + (int64_t)t * kSJ;
+    const int64_t j0 = jb0 + (int64_t)t * kPJ;
     // this wave's copies of tile t have landed (those of the next LA - 1 tiles may still fly) ...
     if (t + LA - 1 < ntiles) wait_vmcnt<(LA - 1) * PC>();
     else wait_vmcnt<0>();
@@ -1054,7 +1059,7 @@ __device__ __forceinline__ void prescreen_block(const MArgs& a, int tb, int spli
     if (t + LA < ntiles)
 #pragma unroll
       for (int u = 0; u < PC; ++u)
-        prescreen_issue(gb, n_pad, smem_lds + (((t + LA) * PC + u) % NS) * kPStage, u, j0 + (int64_t)LA * kSJ,
+        prescreen_issue(gb, n_pad, smem_lds + (((t + LA) * PC + u) % NS) * kPStage, u, j0 + (int64_t)LA * kPJ,
                         wave);
     f32x16_t G[kIB][kSJB];
 #pragma unroll
@@ -1070,7 +1075,7 @@ __device__ __forceinline__ void prescreen_block(const MArgs& a, int tb, int spli
       bf16x8_t xh[kSJB];
 #pragma unroll
       for (int jb = 0; jb < kSJB; ++jb) {
-        const int row = wj * (32 * kSJB) + jb * 32 + cl;
+        const int row = jb * 32 + cl;
         xh[jb] = *reinterpret_cast<const bf16x8_t*>(base + row * 32 + swz<2>(row, gl) * 16);
       }
 #pragma unroll
@@ -1081,8 +1086,7 @@ __device__ __forceinline__ void prescreen_block(const MArgs& a, int tb, int spli
     }
     // the verdict on this wave's 64 x 128 sub-tile: the coarse bound, then the
     // per-pair bound where it leaves a doubt
-    const bool diag = j0 < i0 + kMI && i0 < j0 + kSJ;
-    const int jl0 = wj * (32 * kSJB);
+    const bool diag = j0 < i0 + kMI && i0 < j0 + kPJ;
     float gmax[kIB];
 #pragma unroll
     for (int ib = 0; ib < kIB; ++ib) {
@@ -1094,7 +1098,7 @@ __device__ __forceinline__ void prescreen_block(const MArgs& a, int tb, int spli
       gmax[ib] = m;
     }
     typedef const __attribute__((address_space(4))) float* const_f32_ptr;
-    const const_f32_ptr bmax = (const_f32_ptr)(a.bpre + (size_t)S * n_pad + (size_t)(j0 / kMJ + wj));
+    const const_f32_ptr bmax = (const_f32_ptr)(a.bpre + (size_t)S * n_pad + (size_t)(j0 / kMJ));
     bool doubt = false;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
@@ -1107,7 +1111,7 @@ __device__ __forceinline__ void prescreen_block(const MArgs& a, int tb, int spli
       int bself[kIB];   // slab index jb * 16 + v of the self pair in this lane (-1: none)
 #pragma unroll
       for (int ib = 0; ib < kIB; ++ib) {
-        const int64_t d = i0 + wi * (32 * kIB) + ib * 32 + col - j0 - jl0;
+        const int64_t d = i0 + wi * (32 * kIB) + ib * 32 + col - j0;
         const bool self = diag && d >= 0 && d < 32 * kSJB && (int)((d >> 2) & 1) == g;
         bself[ib] = self ? (int)((d >> 5) * 16 + ((d >> 3) & 3) * 4 + (d & 3)) : -1;
       }
@@ -1115,7 +1119,7 @@ __device__ __forceinline__ void prescreen_block(const MArgs& a, int tb, int spli
       // up to the lane half g, and a vector load would wait for the copies)
       typedef float f32x8_t __attribute__((ext_vector_type(8)));
       typedef const __attribute__((address_space(4))) f32x8_t* const_f32x8_ptr;
-      const const_f32x8_ptr bs = (const_f32x8_ptr)(a.bpre + j0 + jl0);   // 8 sources per element
+      const const_f32x8_ptr bs = (const_f32x8_ptr)(a.bpre + j0);   // 8 sources per element
 #pragma unroll
       for (int s = 0; s < S; ++s) {
         const float c1 = a.c1[s];
@@ -1142,7 +1146,7 @@ __device__ __forceinline__ void prescreen_block(const MArgs& a, int tb, int spli
       }
     }
     const bool flag = __any(need);
-    const int64_t jt = j0 / kMJ + wj;   // the split pass's 128-source tile of this sub-tile
+    const int64_t jt = j0 / kMJ;   // the split pass's 128-source tile
     if (lane == 0 && jt < a.jtl) {
       a.flags[((size_t)tb * a.jtl + jt) * 8 + wi] = flag ? 1 : 0;
       a.flags[((size_t)tb * a.jtl + jt) * 8 + 4 + wi] = 0;
@@ -1151,7 +1155,7 @@ __device__ __forceinline__ void prescreen_block(const MArgs& a, int tb, int spli
 }
 
 template <int S, int PC, int NS>
-__global__ void __launch_bounds__(kNT, 1) k_pair_prescreen(MArgs a) {
+__global__ void __launch_bounds__(kPW * 64, 2) k_pair_prescreen(MArgs a) {
   __shared__ __attribute__((aligned(1024))) unsigned char smem[NS * kPStage];
   int tb, split;
   screen_block_map(a, tb, split);
@@ -1320,9 +1324,17 @@ static yy_status launch_s(hipStream_t st, const MArgs& m, int prec, int nblocks)
     k_pair_mfma<S, 2, 4, 2, true><<<nblocks, kNT, 0, st>>>(m);
   } else if (prec == YY_PREC_BF16X3P) {
     // the partial-distance screen (2 or 4 K stages), then the split form over
-    // the flagged tiles
-    if (m.pre_chunks == 4) k_pair_prescreen<S, 4, 16><<<nblocks, kNT, 0, st>>>(m);
-    else k_pair_prescreen<S, 2, 16><<<nblocks, kNT, 0, st>>>(m);
+    // the flagged tiles.  The screen splits the sources only as far as the
+    // target blocks leave CUs idle (two blocks per CU): the blocks an XCD runs
+    // at a time then stream the same sources through its L2.
+    MArgs mp = m;
+    int ps = 1;
+    const int64_t stiles = (m.n + kPJ - 1) / kPJ;
+    while ((int64_t)m.tb_count * ps < 512 && ps < 64 && 2 * ps <= stiles) ps *= 2;
+    mp.s_nsplit = ps;
+    mp.s_jps = ((stiles + ps - 1) / ps) * kPJ;
+    if (m.pre_chunks == 4) k_pair_prescreen<S, 4, 16><<<m.tb_count * ps, kPW * 64, 0, st>>>(mp);
+    else k_pair_prescreen<S, 2, 16><<<m.tb_count * ps, kPW * 64, 0, st>>>(mp);
     YY_LAUNCH_CHECK("k_pair_mfma (partial-distance screen)");
     k_pair_mfma<S, 2, 4, 2, true><<<nblocks, kNT, 0, st>>>(m);
   } else if (prec == YY_PREC_BF16X1) {

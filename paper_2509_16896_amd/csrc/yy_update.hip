@@ -218,6 +218,8 @@ __device__ __forceinline__ void k_norm_weights_body(int64_t n, int32_t r, int64_
   for (int c = 0; c < kMaxC; ++c) acc[c] = 0.0;
   const int nc = (r + kBlock - 1) / kBlock;
   const bool pairs = (r & 1) == 0 && (reinterpret_cast<uintptr_t>(x) & 15) == 0;
+  // x NULL: no mean wanted, the pass over the coordinates is skipped
+  const int64_t rows_x = x ? kBlock : 0;
   for (int64_t c0 = b0; c0 < b1; c0 += kBlock) {
     const int64_t i = c0 + threadIdx.x;
     double wi = 0.0;
@@ -231,7 +233,7 @@ __device__ __forceinline__ void k_norm_weights_body(int64_t n, int32_t r, int64_
     __syncthreads();
     sw[threadIdx.x] = wi;
     __syncthreads();
-    const int64_t cnt = std::min<int64_t>(kBlock, b1 - c0);
+    const int64_t cnt = std::min<int64_t>(rows_x, b1 - c0);
     if (pairs) {
       // 16-byte loads: thread j takes coordinates 2 (j + kBlock c) and 2 (j + kBlock c) + 1
       // (the same additions per coordinate in the same order as the scalar loop)
@@ -262,6 +264,7 @@ __device__ __forceinline__ void k_norm_weights_body(int64_t n, int32_t r, int64_
   }
   w2 = block_sum<kBlock>(w2, sh);
   if (threadIdx.x == 0) pw2[bx_] = w2;
+  if (!x) return;
   if (pairs) {
 #pragma unroll
     for (int c = 0; c < kMaxC / 2; ++c) {
@@ -317,7 +320,7 @@ __device__ __forceinline__ void k_norm_final_body(int nb, int32_t r, const doubl
   const int kk = threadIdx.x % kNormFinalK, part = threadIdx.x / kNormFinalK;
   const int k = bx_ * kNormFinalK + kk;
   double s = 0.0;
-  if (k < r)
+  if (mean && k < r)
     for (int b = part; b < nb; b += kNormFinalParts) s += pmean[(size_t)b * r + k];
   sm[part][kk] = s;
   if (bx_ == 0) {
@@ -326,7 +329,7 @@ __device__ __forceinline__ void k_norm_final_body(int nb, int32_t r, const doubl
     se[threadIdx.x] = e;
   }
   __syncthreads();
-  if (part == 0 && k < r) {
+  if (mean && part == 0 && k < r) {
     double t = 0.0;
     for (int p = 0; p < kNormFinalParts; ++p) t += sm[p][kk];
     mean[k] = t;
@@ -480,8 +483,8 @@ extern "C" yy_status yy_normalise_moments(yy_ctx ctx, int64_t n, int32_t r, cons
   if (!ctx) return fail(YY_ERR_ARG, "yy_normalise_moments: ctx is NULL");
   if (n < 1) return fail(YY_ERR_ARG, "yy_normalise_moments: n < 1");
   if (r < 1 || r > 4096) return fail(YY_ERR_ARG, "yy_normalise_moments: r out of range");
-  if (!x || !logw || !logZ_step || !logZ_acc || !mean || !ess)
-    return fail(YY_ERR_ARG, "yy_normalise_moments: NULL array");
+  if (!x || !logw || !logZ_step || !logZ_acc || !ess) return fail(YY_ERR_ARG, "yy_normalise_moments: NULL array");
+  if (!mean && cov) return fail(YY_ERR_ARG, "yy_normalise_moments: cov needs mean");
   YY_HIP(hipSetDevice(ctx->device));
   const int nb = norm_blocks(n);
   const int64_t rows = (n + nb - 1) / nb;
@@ -500,9 +503,9 @@ extern "C" yy_status yy_normalise_moments(yy_ctx ctx, int64_t n, int32_t r, cons
   YY_LAUNCH_CHECK("k_norm_sumexp");
   k_norm_logz<<<1, kBlock, 0, ctx->stream>>>(nb, pmax, psum, sc, logZ_step, logZ_acc, ctx->d_flags);
   YY_LAUNCH_CHECK("k_norm_logz");
-  k_norm_weights<<<nb, kBlock, 0, ctx->stream>>>(n, r, rows, sc, x, logw, wbuf, pw2, pmean);
+  k_norm_weights<<<nb, kBlock, 0, ctx->stream>>>(n, r, rows, sc, mean ? x : nullptr, logw, wbuf, pw2, pmean);
   YY_LAUNCH_CHECK("k_norm_weights");
-  k_norm_final<<<norm_final_blocks(r), kBlock, 0, ctx->stream>>>(nb, r, sc, pw2, pmean, mean, ess);
+  k_norm_final<<<mean ? norm_final_blocks(r) : 1, kBlock, 0, ctx->stream>>>(nb, r, sc, pw2, pmean, mean, ess);
   YY_LAUNCH_CHECK("k_norm_final");
   if (cov) {
     dim3 grid((r + 63) / 64, (r + 63) / 64);

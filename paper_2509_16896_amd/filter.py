@@ -103,10 +103,11 @@ class GpuFilter:
         self.version += 1
         self._normalise(want_cov=False, acc=self.logZ_scratch)
 
-    def _normalise(self, want_cov, acc):
+    def _normalise(self, want_cov, acc, moments=True):
         w = self.w
-        yy.yy_normalise_moments(self.ctx, w.n, w.r, self.x, self.lw[self.cur], self.wts, self.logZ_step,
-                                acc, self.mean, self.cov if want_cov else None, self.ess)
+        yy.yy_normalise_moments(self.ctx, w.n, w.r, self.x, self.lw[self.cur], self.wts if moments else None,
+                                self.logZ_step, acc, self.mean if moments else None,
+                                self.cov if want_cov else None, self.ess)
 
     def step(self, k: int, restart: bool | None = None, want_cov: bool = False):
         """Filter step k (1-based) with observation increment dys[k-1]."""
@@ -147,4 +148,5 @@ class GpuFilter:
         self.restarts += 1
         self.xi = 1 - self.xi
         self.version += 1
-        self._normalise(want_cov=False, acc=self.logZ_scratch)
+        # the new prior: normalised log-weights only (the next step recomputes the moments)
+        self._normalise(want_cov=False, acc=self.logZ_scratch, moments=False)

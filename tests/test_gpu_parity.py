@@ -171,6 +171,30 @@ def test_normalise_parity(ctx, n, r):
     assert abs(host(d["ess"])[0] - ref["ess"]) <= 1e-11 * ref["ess"]
 
 
+@pytest.mark.parametrize("n,r", [(300, 5), (70001, 3)])
+def test_normalise_without_moments(ctx, n, r):
+    """mean = NULL: the log-weights, logZ and ESS of the full call, x never read."""
+    rng = np.random.default_rng(n + 3 * r)
+    x = rng.standard_normal((n, r))
+    lw = rng.standard_normal(n) * 4 - 20.0
+    lw[::5] = -np.inf
+    ref = oracle.normalise_moments(x, lw, logZ_acc=1.5)
+    d = {k: torch.zeros(v, dtype=torch.float64, device="cuda") for k, v in dict(lz=1, acc=1, ess=1).items()}
+    d["acc"].fill_(1.5)
+    g = dev(lw)
+    nan_x = torch.full((n * r,), float("nan"), dtype=torch.float64, device="cuda")   # would poison a mean
+    yy.yy_normalise_moments(ctx, n, r, nan_x, g, None, d["lz"], d["acc"], None, None, d["ess"])
+    f = np.isfinite(lw)
+    assert np.array_equal(np.isfinite(host(g)), f)
+    assert np.allclose(host(g)[f], ref["logw"][f], rtol=0, atol=1e-12)
+    assert abs(host(d["lz"])[0] - ref["logZ_step"]) < 1e-12
+    assert abs(host(d["acc"])[0] - ref["logZ_acc"]) < 1e-12
+    assert abs(host(d["ess"])[0] - ref["ess"]) <= 1e-11 * ref["ess"]
+    with pytest.raises(yy.YYError):
+        cov = torch.zeros(r * r, dtype=torch.float64, device="cuda")
+        yy.yy_normalise_moments(ctx, n, r, nan_x, g, None, d["lz"], d["acc"], None, cov, d["ess"])
+
+
 def test_normalise_flags_all_zero(ctx):
     n, r = 100, 2
     d = {k: torch.zeros(v, dtype=torch.float64, device="cuda") for k, v in dict(lz=1, acc=1, mean=r, ess=1).items()}
