@@ -1333,7 +1333,8 @@ static yy_status launch_s(hipStream_t st, const MArgs& m, int prec, int nblocks)
     while ((int64_t)m.tb_count * ps < 512 && ps < 64 && 2 * ps <= stiles) ps *= 2;
     mp.s_nsplit = ps;
     mp.s_jps = ((stiles + ps - 1) / ps) * kPJ;
-    if (m.pre_chunks == 4) k_pair_prescreen<S, 4, 16><<<m.tb_count * ps, kPW * 64, 0, st>>>(mp);
+    constexpr int kPC = kPreK / kKC;   // K stages of the screen (fewer when r_p < kPreK: 2)
+    if (m.pre_chunks == kPC) k_pair_prescreen<S, kPC, 16><<<m.tb_count * ps, kPW * 64, 0, st>>>(mp);
     else k_pair_prescreen<S, 2, 16><<<m.tb_count * ps, kPW * 64, 0, st>>>(mp);
     YY_LAUNCH_CHECK("k_pair_mfma (partial-distance screen)");
     k_pair_mfma<S, 2, 4, 2, true><<<nblocks, kNT, 0, st>>>(m);

@@ -320,8 +320,12 @@ __device__ __forceinline__ void k_norm_final_body(int nb, int32_t r, const doubl
   const int kk = threadIdx.x % kNormFinalK, part = threadIdx.x / kNormFinalK;
   const int k = bx_ * kNormFinalK + kk;
   double s = 0.0;
-  if (mean && k < r)
+  if (mean && k < r) {
+    // (unrolled so that the loads of 8 partial rows are in flight at once; the
+    // additions keep their order)
+#pragma unroll 8
     for (int b = part; b < nb; b += kNormFinalParts) s += pmean[(size_t)b * r + k];
+  }
   sm[part][kk] = s;
   if (bx_ == 0) {
     double e = 0.0;
