@@ -579,7 +579,6 @@ __device__ __forceinline__ void pair_block(const MArgs& a, int tb, int split, un
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wi = wave / kWJ, wj = wave % kWJ, col = lane & 31, g = lane >> 5;
-  if (tid == 0) fill_rare(a, rare);
   const int64_t i0 = (int64_t)tb * kMI;
   const int64_t jb0 = (int64_t)split * a.j_per_split;
   const int64_t jb1 = jb0 + a.j_per_split < a.n ? jb0 + a.j_per_split : a.n;
@@ -588,6 +587,38 @@ __device__ __forceinline__ void pair_block(const MArgs& a, int tb, int split, un
   const int ntiles_all = __builtin_amdgcn_readfirstlane((int)((jb1 - jb0 + kMJ - 1) / kMJ));
   const int nchunks = __builtin_amdgcn_readfirstlane(a.rp / kKC);
   const int64_t jt0 = jb0 / kMJ;   // global index of the split's first source tile
+  if (FLAGGED) {
+    // A source range without a flagged tile leaves every partial state as it
+    // starts (the self-pair exponent; sum 1 in the split that holds the self
+    // pair, else 0): those are written directly, the value merge_and_store
+    // would produce.
+    if (wave == 0) {
+      bool any = false;
+      for (int w0 = 0; w0 < ntiles_all; w0 += 64)
+        any |= w0 + lane < ntiles_all &&
+               *reinterpret_cast<const uint64_t*>(a.flags + ((size_t)tb * a.jtl + jt0 + w0 + lane) * 8) != 0;
+      any = __any(any);
+      if (lane == 0) tl[kTileWindow] = any ? 1 : 0;
+    }
+    __syncthreads();
+    if (tl[kTileWindow] == 0) {
+      if (tid < kMI) {
+        const int64_t i = i0 + tid;
+        if (i < a.n) {
+          const float li = a.lw2[i];
+          const double nf = a.node[a.n + i];
+          const bool own = (int64_t)split == i / a.j_per_split;
+#pragma unroll
+          for (int s = 0; s < S; ++s) {
+            const float M0 = li != -INFINITY ? li - (float)(a.kapd[s] * a.taud[s] * a.taud[s] * nf) : -INFINITY;
+            a.part[((size_t)split * S + s) * a.n + i] = make_float2(M0, (own && M0 != -INFINITY) ? 1.f : 0.f);
+          }
+        }
+      }
+      return;
+    }
+  }
+  if (tid == 0) fill_rare(a, rare);
   const uint64_t plane = (uint64_t)nchunks * a.n_pad * kKC * ESZ;   // bytes per global plane
   const unsigned char* gb = VAR == 0 ? reinterpret_cast<const unsigned char*>(a.f32t)
                                      : reinterpret_cast<const unsigned char*>(a.bf);
