@@ -79,10 +79,41 @@ __global__ void __launch_bounds__(256) k_gemm(int M, int N, int K, const float* 
     }
 }
 
+// One row (M = 1) with A and the columns of B contiguous in k: a wave per
+// output, its lanes striding over k (the forward pass of one restart).
+template <int EPI>
+__global__ void __launch_bounds__(256) k_gemv(int N, int K, const float* __restrict__ A,
+                                              const float* __restrict__ B, int64_t sbn,
+                                              const float* __restrict__ bias, float* __restrict__ C,
+                                              float* __restrict__ Z) {
+  const int lane = threadIdx.x & 63;
+  const int nn = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (nn >= N) return;
+  const float* b = B + (int64_t)nn * sbn;
+  float acc = 0.f;
+  for (int k = lane; k < K; k += 64) acc = fmaf(A[k], b[k], acc);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if (lane == 0) {
+    float v = acc;
+    if (EPI >= 1) v += bias[nn];
+    if (EPI == 2) {
+      Z[nn] = v;
+      v = gelu_f(v);
+    }
+    C[nn] = v;
+  }
+}
+
 template <int EPI>
 static yy_status gemm(hipStream_t st, int M, int N, int K, const float* A, int64_t sam, int64_t sak,
                       const float* B, int64_t sbk, int64_t sbn, const float* bias, float* C, int64_t ldc,
                       float* Z = nullptr) {
+  if (M == 1 && sak == 1 && sbk == 1) {
+    k_gemv<EPI><<<(unsigned)((N + 3) / 4), 256, 0, st>>>(N, K, A, B, sbn, bias, C, Z);
+    YY_LAUNCH_CHECK("k_gemv");
+    return YY_OK;
+  }
   dim3 grid((unsigned)((N + kGT - 1) / kGT), (unsigned)((M + kGT - 1) / kGT));
   k_gemm<EPI><<<grid, 256, 0, st>>>(M, N, K, A, sam, sak, B, sbk, sbn, bias, C, ldc, Z);
   YY_LAUNCH_CHECK("k_gemm");
@@ -264,14 +295,28 @@ __global__ void __launch_bounds__(kBlock) k_prop_checks(int64_t n, int32_t r, co
   const double* isL = box + 4 * r;
   const double isP = kKappa / R;
   double cov = 0.0, qL = 0.0, qP = 0.0;
+  auto coord = [&](double yd, double cd, double hd, double id, double md) {
+    const double zl = (yd - cd) * id, zp = (yd - md) * isP;
+    cov += fabs(yd - cd) <= hd ? 1.0 : 0.0;
+    qL = fma(zl, zl, qL);
+    qP = fma(zp, zp, qP);
+  };
+  // 16-byte accesses to pairs of coordinates when the rows allow it
+  const bool pairs = (r & 1) == 0 && ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(box) |
+                                       reinterpret_cast<uintptr_t>(mean)) & 15) == 0;
   for (int64_t t = wave; t < n; t += nwaves) {
     const double* y = x + (size_t)idx[t] * r;
-    for (int32_t d = lane; d < r; d += 64) {
-      const double yd = y[d];
-      const double zl = (yd - c[d]) * isL[d], zp = (yd - mean[d]) * isP;
-      cov += fabs(yd - c[d]) <= hw[d] ? 1.0 : 0.0;
-      qL = fma(zl, zl, qL);
-      qP = fma(zp, zp, qP);
+    if (pairs) {
+      const double2* y2 = reinterpret_cast<const double2*>(y);
+      for (int32_t d = lane; d < r / 2; d += 64) {
+        const double2 yd = y2[d], cd = reinterpret_cast<const double2*>(c)[d];
+        const double2 hd = reinterpret_cast<const double2*>(hw)[d], id = reinterpret_cast<const double2*>(isL)[d];
+        const double2 md = reinterpret_cast<const double2*>(mean)[d];
+        coord(yd.x, cd.x, hd.x, id.x, md.x);
+        coord(yd.y, cd.y, hd.y, id.y, md.y);
+      }
+    } else {
+      for (int32_t d = lane; d < r; d += 64) coord(y[d], c[d], hw[d], isL[d], mean[d]);
     }
   }
   const double ldL = qL, ldP = qP;
