@@ -259,6 +259,15 @@ def main_batch(args):
     ms, cnt = yy.yy_timing_read(bt.ctx)
     yy.yy_timing_enable(bt.ctx, False)
     kms = ms / max(cnt, 1)
+    kernel = "k_pair_mfma_batch"
+    dense = alg
+    if args.prec in ("bf16x3s", "bf16x3p"):
+        # each run's screen products plus the method's products on its flagged tiles
+        counts = [bt.screen_count(q) for q in range(len(ws))]
+        alg = sum(screened_work(w, args.prec, fl, tl)[0] for w, (fl, tl) in zip(ws, counts))
+        kernel = ("k_pair_prescreen_batch" if args.prec == "bf16x3p" else "k_pair_screen_batch") + \
+            ", then k_pair_mfma_batch (split form) on flagged tiles"
+        log(f"[bench] screens flagged {sum(c[0] for c in counts)} of {sum(c[1] for c in counts)} tiles")
     bt.close()
     # the same runs one after another through the single-run calls
     t_seq = 0.0
@@ -283,7 +292,8 @@ def main_batch(args):
                    "precision": args.prec, "max_split": best},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_TFLOPS[args.prec],
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS[args.prec], 4), "traffic": None,
-                     "kernel": "k_pair_mfma_batch", "kernel_ms": round(kms, 3)},
+                     "kernel": kernel, "kernel_ms": round(kms, 3),
+                     "dense_equivalent_tflops": round(dense / (kms * 1e-3) / 1e12, 2)},
         "eager_steps_per_s": round(steps / t_eager, 2),
         "sequential_single_run_steps_per_s": round(steps / t_seq, 2),
         "tune_s": round(tune_s, 2),
@@ -298,8 +308,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--prec", default=None,
                     choices=["fp32", "fp32_mfma", "bf16x3", "bf16x3g", "bf16x3s", "bf16x3p", "bf16x1"],
-                    help="form of the pairwise sum (default: bf16x3p; bf16x3s for the batch, which "
-                         "has no partial-distance screen)")
+                    help="form of the pairwise sum (default: bf16x3p)")
     ap.add_argument("--other-forms", default="bf16x3s,bf16x3g,bf16x3,bf16x1",
                     help="matrix-core forms whose pairwise kernel is also timed ('none' to skip)")
     ap.add_argument("--baseline-prec", default="fp32_mfma", help="plain FP32 form timed beside ('none' to skip)")
@@ -320,7 +329,7 @@ def main():
         sys.exit(2)
 
     if args.prec is None:
-        args.prec = "bf16x3s" if args.workload == "batch64" else "bf16x3p"
+        args.prec = "bf16x3p"
     if args.workload == "batch64":
         return main_batch(args)
 

@@ -309,8 +309,8 @@ typedef struct {
 typedef struct yy_batch_s* yy_batch;
 
 /* Creates the batch and its initial state (step 0: nodes, N(0, I) prior,
- * normalised).  prec: YY_PREC_BF16X3, BF16X3G, BF16X1 or FP32_MFMA (every run
- * uses the matrix cores).  max_split: upper bound of the source splits per
+ * normalised).  prec: a matrix-core form (YY_PREC_FP32_MFMA, BF16X3, BF16X3G,
+ * BF16X3S, BF16X3P or BF16X1; every run uses it).  max_split: upper bound of the source splits per
  * run (0: 16); yy_batch_tune can choose it. */
 yy_status yy_batch_create(yy_ctx ctx, int32_t nruns, const yy_batch_run* runs, const yy_scales* scales,
                           int32_t prec, int32_t max_split, yy_batch* out);
@@ -334,6 +334,10 @@ yy_status yy_batch_tune(yy_batch b, int32_t reps, int32_t* best_out);
 yy_status yy_batch_results(yy_batch b, int32_t run, double* mean_hist, double* logZ_hist, double* ess_hist);
 /* Steps taken so far (host scalar). */
 yy_status yy_batch_step_count(yy_batch b, int32_t* k);
+/* yy_screen_count for run `run` of a batch in a screened form (its last
+ * propagation).  Synchronises the stream; YY_ERR_ARG for a bad run or a form
+ * without a screen. */
+yy_status yy_batch_screen_count(yy_batch b, int32_t run, int64_t* flagged, int64_t* tiles);
 
 /* ------------------------------------------------------------------------ */
 /* Timing of the pairwise kernel (the dominant kernel of yy_propagate).  While

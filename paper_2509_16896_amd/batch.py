@@ -63,6 +63,10 @@ class Batch:
     def k(self) -> int:
         return yy.yy_batch_step_count(self.b)
 
+    def screen_count(self, run: int):
+        """(flagged tiles, tiles) of run `run`'s last screen (screened forms only)."""
+        return yy.yy_batch_screen_count(self.b, run)
+
     def results(self, run: int):
         w = self.workloads[run]
         mean = torch.empty(w.K * w.r, dtype=torch.float64, device=self.dev)

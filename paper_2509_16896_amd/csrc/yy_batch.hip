@@ -35,8 +35,8 @@ static void tune_store(yy_ctx ctx, int32_t rp, int64_t n_pad, int32_t S, int32_t
 }
 
 static bool is_mfma_prec(int32_t p) {
-  return p == YY_PREC_BF16X3 || p == YY_PREC_BF16X3G || p == YY_PREC_BF16X3S || p == YY_PREC_BF16X1 ||
-         p == YY_PREC_FP32_MFMA;
+  return p == YY_PREC_BF16X3 || p == YY_PREC_BF16X3G || p == YY_PREC_BF16X3S || p == YY_PREC_BF16X3P ||
+         p == YY_PREC_BF16X1 || p == YY_PREC_FP32_MFMA;
 }
 
 static bool capturing(hipStream_t st) {
@@ -779,6 +779,11 @@ extern "C" yy_status yy_batch_results(yy_batch b, int32_t run, double* mean_hist
   if (logZ_hist) YY_HIP(hipMemcpyAsync(logZ_hist, R.logZ_hist.ptr, K * 8, hipMemcpyDeviceToDevice, st));
   if (ess_hist) YY_HIP(hipMemcpyAsync(ess_hist, R.ess_hist.ptr, K * 8, hipMemcpyDeviceToDevice, st));
   return YY_OK;
+}
+
+extern "C" yy_status yy_batch_screen_count(yy_batch b, int32_t run, int64_t* flagged, int64_t* tiles) {
+  if (!b || run < 0 || run >= (int32_t)b->runs.size()) return fail(YY_ERR_ARG, "yy_batch_screen_count: bad run");
+  return yy_screen_count(b->runs[run].rc, flagged, tiles);
 }
 
 extern "C" yy_status yy_batch_step_count(yy_batch b, int32_t* k) {

@@ -1193,6 +1193,20 @@ __global__ void __launch_bounds__(kPW * 64, 2) k_pair_prescreen(MArgs a) {
   prescreen_block<S, PC, NS>(a, tb, split, smem);
 }
 
+// Many node sets: block b takes work item items[b] = (set, target block,
+// source split) of the split pass; 4 or 2 K stages as the set's K padding
+// allows, 3 tiles in flight either way.
+template <int S>
+__global__ void __launch_bounds__(kPW * 64, 2) k_pair_prescreen_batch(const MArgs* __restrict__ sets,
+                                                                      const int4* __restrict__ items) {
+  __shared__ __attribute__((aligned(1024))) unsigned char smem[16 * kPStage];
+  const int4 it = items[blockIdx.x];
+  const MArgs& a = sets[__builtin_amdgcn_readfirstlane(it.x)];
+  const int tb = __builtin_amdgcn_readfirstlane(it.y), split = __builtin_amdgcn_readfirstlane(it.z);
+  if (__builtin_amdgcn_readfirstlane(a.pre_chunks) == 4) prescreen_block<S, 4, 16>(a, tb, split, smem);
+  else prescreen_block<S, 2, 8>(a, tb, split, smem);
+}
+
 
 template <int S, int NS, int SPB>
 __global__ void __launch_bounds__(kNT, 1) k_pair_screen(MArgs a) {
@@ -1331,6 +1345,11 @@ static yy_status launch_batch_s(hipStream_t st, const MArgs* sets, const int4* i
     else k_pair_screen_batch<S, 8, 2><<<nitems, kNT, 0, st>>>(sets, items);
     YY_LAUNCH_CHECK("k_pair_mfma_batch (screen)");
     k_pair_mfma_batch<S, 2, 4, 2, true><<<nitems, kNT, 0, st>>>(sets, items);
+  } else if (prec == YY_PREC_BF16X3P) {
+    // the partial-distance screen over the split pass's work items, then the split pass
+    k_pair_prescreen_batch<S><<<nitems, kPW * 64, 0, st>>>(sets, items);
+    YY_LAUNCH_CHECK("k_pair_mfma_batch (partial-distance screen)");
+    k_pair_mfma_batch<S, 2, 4, 2, true><<<nitems, kNT, 0, st>>>(sets, items);
   } else if (prec == YY_PREC_BF16X1) {
     k_pair_mfma_batch<S, 1, 8, 4, false><<<nitems, kNT, 0, st>>>(sets, items);
   } else {
@@ -1364,9 +1383,9 @@ static yy_status launch_s(hipStream_t st, const MArgs& m, int prec, int nblocks)
     while ((int64_t)m.tb_count * ps < 512 && ps < 64 && 2 * ps <= stiles) ps *= 2;
     mp.s_nsplit = ps;
     mp.s_jps = ((stiles + ps - 1) / ps) * kPJ;
-    constexpr int kPC = kPreK / kKC;   // K stages of the screen (fewer when r_p < kPreK: 2)
-    if (m.pre_chunks == kPC) k_pair_prescreen<S, kPC, 16><<<m.tb_count * ps, kPW * 64, 0, st>>>(mp);
-    else k_pair_prescreen<S, 2, 16><<<m.tb_count * ps, kPW * 64, 0, st>>>(mp);
+    static_assert(kPreK == 64, "4 K stages, or 2 where r_p = 32");
+    if (m.pre_chunks == 4) k_pair_prescreen<S, 4, 16><<<m.tb_count * ps, kPW * 64, 0, st>>>(mp);
+    else k_pair_prescreen<S, 2, 8><<<m.tb_count * ps, kPW * 64, 0, st>>>(mp);
     YY_LAUNCH_CHECK("k_pair_mfma (partial-distance screen)");
     k_pair_mfma<S, 2, 4, 2, true><<<nblocks, kNT, 0, st>>>(m);
   } else if (prec == YY_PREC_BF16X1) {

@@ -35,7 +35,8 @@ EXPORTED = ["yy_last_error", "yy_create", "yy_destroy", "yy_set_stream", "yy_get
             "yy_proposal_create", "yy_proposal_destroy", "yy_proposal_num_params", "yy_proposal_get_params",
             "yy_proposal_set_params", "yy_proposal_forward", "yy_proposal_train_step", "yy_sample_moments",
             "yy_tune", "yy_batch_create", "yy_batch_destroy", "yy_batch_reset", "yy_batch_step",
-            "yy_batch_run_graph", "yy_batch_tune", "yy_batch_results", "yy_batch_step_count"]
+            "yy_batch_run_graph", "yy_batch_tune", "yy_batch_results", "yy_batch_step_count",
+            "yy_batch_screen_count"]
 
 
 class YYError(RuntimeError):
@@ -102,6 +103,7 @@ for _name, _args in {
     "yy_batch_tune": [_P, _i32, ctypes.POINTER(_i32)],
     "yy_batch_results": [_P, _i32, _P, _P, _P],
     "yy_batch_step_count": [_P, ctypes.POINTER(_i32)],
+    "yy_batch_screen_count": [_P, _i32, ctypes.POINTER(_i64), ctypes.POINTER(_i64)],
     "yy_timing_enable": [_P, _i32],
     "yy_timing_read": [_P, ctypes.POINTER(_f64), ctypes.POINTER(_i64)],
     "yy_screen_count": [_P, ctypes.POINTER(_i64), ctypes.POINTER(_i64)],
@@ -366,6 +368,13 @@ def yy_batch_results(b, run, mean_hist=None, logZ_hist=None, ess_hist=None):
     _check(_lib.yy_batch_results(b, int(run), _dptr(mean_hist, torch.float64, None, "mean_hist"),
                                  _dptr(logZ_hist, torch.float64, None, "logZ_hist"),
                                  _dptr(ess_hist, torch.float64, None, "ess_hist")), "yy_batch_results")
+
+
+def yy_batch_screen_count(b, run):
+    """(flagged tiles, tiles) of the last propagation of run `run` of a batch in a screened form."""
+    f, t = _i64(0), _i64(0)
+    _check(_lib.yy_batch_screen_count(b, int(run), ctypes.byref(f), ctypes.byref(t)), "yy_batch_screen_count")
+    return int(f.value), int(t.value)
 
 
 def yy_batch_step_count(b) -> int:

@@ -41,7 +41,7 @@ def _single(w, dys, prec):
         f.close()
 
 
-@pytest.mark.parametrize("prec", ["bf16x3g", "bf16x3s", "fp32_mfma"])
+@pytest.mark.parametrize("prec", ["bf16x3g", "bf16x3s", "bf16x3p", "fp32_mfma"])
 def test_batch_matches_single_runs_exactly(prec):
     ws = _workloads()
     dys = [W.simulate(w)[1] for w in ws]
@@ -57,11 +57,14 @@ def test_batch_matches_single_runs_exactly(prec):
             assert np.array_equal(lz, ref[1]), w.name
             assert np.array_equal(ess, ref[2]), w.name
             assert np.all(np.isfinite(mean))
+            if prec in ("bf16x3s", "bf16x3p"):
+                flagged, tiles = bt.screen_count(q)
+                assert tiles == ((w.n + 255) // 256) * ((w.n + 127) // 128) and 0 <= flagged <= tiles
     finally:
         bt.close()
 
 
-@pytest.mark.parametrize("prec", ["bf16x3g", "bf16x3s"])
+@pytest.mark.parametrize("prec", ["bf16x3g", "bf16x3s", "bf16x3p"])
 def test_graph_replay_equals_eager_steps(prec):
     ws = _workloads(K=10)
     dys = [W.simulate(w)[1] for w in ws]
