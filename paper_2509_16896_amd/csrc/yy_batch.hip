@@ -395,7 +395,8 @@ static yy_status build(yy_batch b) {
     Pp.push_back({n, P.n_pad, r, P.rp, d.model.drift, d.model.A, R.x.as<double>(), R.lo.as<double>(),
                   R.hi.as<double>(), P.xc32.as<float>(), P.f32.as<float>(), bf ? P.bf.as<uint16_t>() : nullptr,
                   f32t ? P.f32t.as<float>() : nullptr, P.node.as<double>(), P.bnd.as<int>(), rflag});
-    Ps.push_back({n, r, R.lo.as<double>(), R.hi.as<double>(), P.node.as<double>(), P.scal.as<double>(), rflag});
+    Ps.push_back({n, r, prepare_blocks(P.n_pad), R.lo.as<double>(), R.hi.as<double>(), P.node.as<double>(),
+                  P.scal.as<double>(), rflag});
     b_r.push_back(nblk(r));
     b_rs.push_back(nbr);
     b_one.push_back(1);

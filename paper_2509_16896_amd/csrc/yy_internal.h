@@ -63,9 +63,10 @@ struct Prepared {
   DevBuf f32;               // float [n*rp]  f(x)
   DevBuf bf;                // bf16 tiled [4][rp/16][n_pad][16]: hi(xc), hi(f), lo(xc), lo(f)
   DevBuf f32t;              // float tiled [2][rp/16][n_pad][16]: xc, f
-  DevBuf node;              // double [3][n]  |xc|^2, |f|^2, xc.f
+  DevBuf node;              // double [6][n]  |xc|^2, |f|^2, xc.f, the same over the first kPreK
+                            // coordinates; then 4 maxima per preparation block
   DevBuf bnd;               // int [n]  1 = boundary node
-  DevBuf scal;              // double [4]  log vol(box), max |xc|, max |f|, spare
+  DevBuf scal;              // double [6]  log vol(box), max |xc|, max |f|, spare, the maxima over kPreK
 };
 
 }  // namespace yy
@@ -385,6 +386,7 @@ struct prepare_args {
 struct prepare_scalars_args {
   int64_t n;
   int32_t r;
+  int32_t nparts;    // per-block maxima written by the preparation (its block count)
   const double* lo;
   const double* hi;
   const double* node;

@@ -1003,8 +1003,7 @@ __device__ inline void screen_block_map(const MArgs& a, int& tb, int& split) {
 // sources stream through LDS: one 4 KB stage (128 sources x 16 K values) per
 // K chunk, PC stages per tile, a ring of NS stages with LA = NS / PC - 1 tiles
 // in flight.  A block is 4 waves (256 targets x 128 sources per tile) and a CU
-// runs two: the blocks do not wait for each other at the per-tile barrier, so
-// one block's verdict (vector ALU) overlaps the other's products.
+// runs two, which do not wait for each other at the per-tile barrier.
 // The bound: over the first kPreK coordinates (superscript p),
 // |x_i - m_j|^2 >= |x_i^p - m_j^p|^2, so the bound of screen_block with G, the
 // norms and F taken over those coordinates (a_i^p, b_js^p in a.bpre, F^p)

@@ -47,6 +47,7 @@ __device__ __forceinline__ void k_prepare_body(int64_t n, int64_t n_pad, int32_t
   const int64_t wave = ((int64_t)bx_ * blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gx_ * blockDim.x) >> 6;
   const size_t plane = (size_t)n_pad * rp;
+  double mx[4] = {0.0, 0.0, 0.0, 0.0};   // running maxima of the norms (all >= 0)
   for (int64_t i4 = wave * 4; i4 < n_pad; i4 += nwaves * 4) {
     const int64_t i = i4 + sub;   // n_pad is a multiple of 4
     const bool real = i < n;
@@ -120,6 +121,20 @@ __device__ __forceinline__ void k_prepare_body(int64_t n, int64_t n_pad, int32_t
       node[5 * n + i] = pxf;
       bnd[i] = b;
     }
+    if (real) {
+      mx[0] = fmax(mx[0], sxx);
+      mx[1] = fmax(mx[1], sff);
+      mx[2] = fmax(mx[2], pxx);
+      mx[3] = fmax(mx[3], pff);
+    }
+  }
+  // the block's maxima of |xc|^2, |f|^2 and their first-kPreK parts, to
+  // node[6 n + 4 bx + c] (k_prepare_scalars reduces them)
+  __shared__ double sh[kBlock / 64];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const double v = block_max<kBlock>(mx[c], sh);
+    if (threadIdx.x == 0) node[6 * n + 4 * (int64_t)bx_ + c] = v;
   }
 }
 
@@ -146,8 +161,9 @@ __global__ void __launch_bounds__(kBlock) k_prepare_batch(const prepare_args* __
 }
 
 
-// Box volume (log) and the maxima of |xc| and |f| over the nodes: one block.
-__device__ __forceinline__ void k_prepare_scalars_body(int64_t n, int32_t r,
+// Box volume (log) and the maxima of |xc| and |f| (all coordinates and the
+// first kPreK) from the nparts per-block maxima of k_prepare: one block.
+__device__ __forceinline__ void k_prepare_scalars_body(int64_t n, int32_t r, int32_t nparts,
                                                             const double* __restrict__ lo,
                                                             const double* __restrict__ hi,
                                                             const double* __restrict__ node,
@@ -156,47 +172,29 @@ __device__ __forceinline__ void k_prepare_scalars_body(int64_t n, int32_t r,
   double lv = 0.0;
   for (int32_t k = threadIdx.x; k < r; k += kBlock) lv += log(hi[k] - lo[k]);
   lv = block_sum<kBlock>(lv, sh);
-  double mx = 0.0, mf = 0.0, px = 0.0, pf = 0.0;
-  // 8 rows per thread in flight (the loop is bound by load latency)
-  for (int64_t i0 = threadIdx.x; i0 < n; i0 += 8 * kBlock) {
-    double v[8][4];
+  const double* part = node + 6 * n;
+  double m[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int32_t p = threadIdx.x; p < nparts; p += kBlock)
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int64_t i = i0 + (int64_t)u * kBlock;
-      const bool ok = i < n;
-      v[u][0] = ok ? node[i] : 0.0;
-      v[u][1] = ok ? node[n + i] : 0.0;
-      v[u][2] = ok ? node[3 * n + i] : 0.0;
-      v[u][3] = ok ? node[4 * n + i] : 0.0;
-    }
+    for (int c = 0; c < 4; ++c) m[c] = fmax(m[c], part[4 * (int64_t)p + c]);
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      mx = fmax(mx, v[u][0]);
-      mf = fmax(mf, v[u][1]);
-      px = fmax(px, v[u][2]);
-      pf = fmax(pf, v[u][3]);
-    }
-  }
-  mx = block_max<kBlock>(mx, sh);
-  mf = block_max<kBlock>(mf, sh);
-  px = block_max<kBlock>(px, sh);
-  pf = block_max<kBlock>(pf, sh);
+  for (int c = 0; c < 4; ++c) m[c] = block_max<kBlock>(m[c], sh);
   if (threadIdx.x == 0) {
     scal[0] = lv;
-    scal[1] = sqrt(mx);
-    scal[2] = sqrt(mf);
+    scal[1] = sqrt(m[0]);
+    scal[2] = sqrt(m[1]);
     scal[3] = 0.0;
-    scal[4] = sqrt(px);
-    scal[5] = sqrt(pf);
+    scal[4] = sqrt(m[2]);
+    scal[5] = sqrt(m[3]);
   }
 }
 
-__global__ void __launch_bounds__(kBlock) k_prepare_scalars(int64_t n, int32_t r,
+__global__ void __launch_bounds__(kBlock) k_prepare_scalars(int64_t n, int32_t r, int32_t nparts,
                                                             const double* __restrict__ lo,
                                                             const double* __restrict__ hi,
                                                             const double* __restrict__ node,
                                                             double* __restrict__ scal) {
-  k_prepare_scalars_body(n, r, lo, hi, node, scal, blockIdx.x, gridDim.x);
+  k_prepare_scalars_body(n, r, nparts, lo, hi, node, scal, blockIdx.x, gridDim.x);
 }
 
 __global__ void __launch_bounds__(kBlock) k_prepare_scalars_batch(const prepare_scalars_args* __restrict__ A,
@@ -204,7 +202,7 @@ __global__ void __launch_bounds__(kBlock) k_prepare_scalars_batch(const prepare_
   const int q = batch_find(pre, nr, blockIdx.x);
   const prepare_scalars_args& a = A[q];
   if (a.pred && *a.pred == 0) return;
-  k_prepare_scalars_body(a.n, a.r, a.lo, a.hi, a.node, a.scal, blockIdx.x - pre[q], pre[q + 1] - pre[q]);
+  k_prepare_scalars_body(a.n, a.r, a.nparts, a.lo, a.hi, a.node, a.scal, blockIdx.x - pre[q], pre[q + 1] - pre[q]);
 }
 
 
@@ -541,15 +539,16 @@ yy_status prepare_nodes(yy_ctx ctx, const yy_model* m, int64_t n, const double* 
   if ((st = P.f32.ensure((size_t)n * rp * sizeof(float))) != YY_OK) return st;
   if (want_bf16 && (st = P.bf.ensure((size_t)4 * n_pad * rp * sizeof(uint16_t))) != YY_OK) return st;
   if (want_f32t && (st = P.f32t.ensure((size_t)2 * n_pad * rp * sizeof(float))) != YY_OK) return st;
-  if ((st = P.node.ensure((size_t)6 * n * sizeof(double))) != YY_OK) return st;
+  const int nparts = prepare_blocks(n_pad);
+  if ((st = P.node.ensure(((size_t)6 * n + 4 * (size_t)nparts) * sizeof(double))) != YY_OK) return st;
   if ((st = P.bnd.ensure((size_t)n * sizeof(int))) != YY_OK) return st;
   if ((st = P.scal.ensure(8 * sizeof(double))) != YY_OK) return st;
-  k_prepare<<<(unsigned)prepare_blocks(n_pad), kBlock, 0, ctx->stream>>>(
+  k_prepare<<<(unsigned)nparts, kBlock, 0, ctx->stream>>>(
       n, n_pad, m->r, rp, m->drift, m->A, x, lo, hi, P.xc32.as<float>(), P.f32.as<float>(),
       want_bf16 ? P.bf.as<uint16_t>() : nullptr, want_f32t ? P.f32t.as<float>() : nullptr,
       P.node.as<double>(), P.bnd.as<int>());
   YY_LAUNCH_CHECK("k_prepare");
-  k_prepare_scalars<<<1, kBlock, 0, ctx->stream>>>(n, m->r, lo, hi, P.node.as<double>(),
+  k_prepare_scalars<<<1, kBlock, 0, ctx->stream>>>(n, m->r, nparts, lo, hi, P.node.as<double>(),
                                                    P.scal.as<double>());
   YY_LAUNCH_CHECK("k_prepare_scalars");
   P.valid = true;
