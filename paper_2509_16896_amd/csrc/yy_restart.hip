@@ -70,16 +70,30 @@ __global__ void __launch_bounds__(kBlock) k_rs_local_batch(const rs_local_args* 
 }
 
 
-// Exclusive offsets of the block totals (one thread, integer sums).
+// Exclusive offsets of the block totals (one block; integer sums, so any
+// order of the additions gives the same offsets): 256 totals at a time, a
+// scan in LDS, the running carry across the rounds.
 __device__ __forceinline__ void k_rs_offsets_body(int nb, unsigned long long* __restrict__ tot, int bx_, int gx_) {
-  if (threadIdx.x != 0 || bx_ != 0) return;
-  unsigned long long run = 0;
-  for (int b = 0; b < nb; ++b) {
-    const unsigned long long t = tot[b];
-    tot[b] = run;
-    run += t;
+  __shared__ unsigned long long s[kBlock];
+  if (bx_ != 0) return;
+  const int tid = threadIdx.x;
+  unsigned long long carry = 0;
+  for (int base = 0; base < nb; base += kBlock) {
+    const int b = base + tid;
+    const unsigned long long v = b < nb ? tot[b] : 0ULL;
+    s[tid] = v;
+    __syncthreads();
+    for (int off = 1; off < kBlock; off <<= 1) {
+      const unsigned long long t = tid >= off ? s[tid - off] : 0ULL;
+      __syncthreads();
+      s[tid] += t;
+      __syncthreads();
+    }
+    if (b < nb) tot[b] = carry + s[tid] - v;
+    carry += s[kBlock - 1];
+    __syncthreads();
   }
-  tot[nb] = run;  // W
+  if (tid == 0) tot[nb] = carry;  // W
 }
 
 __global__ void __launch_bounds__(kBlock) k_rs_offsets(int nb, unsigned long long* __restrict__ tot) {
@@ -391,7 +405,7 @@ extern "C" yy_status yy_restart(yy_ctx ctx, int64_t n, int32_t r, const uint32_t
     unsigned long long* tot = C + n;
     k_rs_local<<<nb, kBlock, 0, ctx->stream>>>(n, w, C, tot);
     YY_LAUNCH_CHECK("k_rs_local");
-    k_rs_offsets<<<1, 64, 0, ctx->stream>>>(nb, tot);
+    k_rs_offsets<<<1, kBlock, 0, ctx->stream>>>(nb, tot);
     YY_LAUNCH_CHECK("k_rs_offsets");
     k_rs_add<<<nb, kBlock, 0, ctx->stream>>>(n, tot, C);
     YY_LAUNCH_CHECK("k_rs_add");
