@@ -25,7 +25,7 @@ def ctx():
     yy.yy_destroy(c)
 
 
-def _case(r, n, q, dt, half, seed, scales=(1.0, 2.0, 4.0), stripes=0):
+def _case(r, n, q, dt, half, seed, scales=(1.0, 2.0, 4.0), stripes=0, zero_every=0):
     rng = np.random.default_rng(seed)
     lo, hi = -half * np.ones(r), half * np.ones(r)
     codes = oracle.sobol_codes(r, n, 0, True, seed)
@@ -35,6 +35,10 @@ def _case(r, n, q, dt, half, seed, scales=(1.0, 2.0, 4.0), stripes=0):
         # every other run of `stripes` nodes 3000 below the rest: the screen rules out the tiles
         # of heavy targets against light sources and keeps the others, an irregular tile pattern
         lw -= 3000.0 * ((np.arange(n) // stripes) % 2)
+    if zero_every:
+        # nodes of weight zero: as targets they still receive mass, and their self pair gives no
+        # lower bound of their row maximum
+        lw[::zero_every] = -np.inf
     gm = yy.Model(r, r, yy.YY_F_COS, None, yy.YY_H_IDENTITY, None, 0.0, q, 1.0)
     om = oracle.OModel(r, r, oracle.F_COS, None, oracle.H_IDENTITY, None, 0.0, q, 1.0)
     return dict(r=r, n=n, x=x, lo=lo, hi=hi, lw=lw, gm=gm, om=om, dt=dt, scales=scales)
@@ -56,6 +60,7 @@ CASES = {
     "r33_n3000_s1": dict(r=33, n=3000, q=0.5, dt=0.02, half=0.5, seed=44),
     # a partial screen over source ranges longer than a 64-tile window (16 splits of 69 tiles)
     "r32_n140000_stripes": dict(r=32, n=140000, q=1.0, dt=0.05, half=0.25, seed=45, stripes=2560),
+    "r100_n3000_zero_weights": dict(r=100, n=3000, q=0.3, dt=0.02, half=0.3, seed=46, zero_every=7),
 }
 
 
