@@ -1,0 +1,59 @@
+"""Host logic of the benchmark line: the work each form is charged with, the
+traffic record's validity check and the one-GPU contract (no GPU needed)."""
+import dataclasses
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+from paper_2509_16896_amd import workloads as W  # noqa: E402
+
+
+def test_algorithmic_flops_of_the_method():
+    w = W.cubic_r1000()
+    # two products (x.x and x.f) of r multiply-adds for every ordered pair
+    assert bench.alg_flops(w) == 2.0 * 65536 * 65536 * 1000 * 2
+    w1 = dataclasses.replace(w, scales=(1.0,))
+    assert bench.alg_flops(w1) == 2.0 * 65536 * 65536 * 1000
+
+
+def test_screened_work():
+    w = W.cubic_r1000()
+    n2 = 65536.0 * 65536.0
+    # nothing flagged: only the screen's product, over the coordinates it uses
+    alg, ex = bench.screened_work(w, "bf16x3p", 0, 131072)
+    assert alg == ex == 2.0 * n2 * 64
+    alg, ex = bench.screened_work(w, "bf16x3s", 0, 131072)
+    assert alg == ex == 2.0 * n2 * 1000
+    # every tile flagged: the method's products on top, executed twice over by the split form
+    alg, ex = bench.screened_work(w, "bf16x3p", 131072, 131072)
+    assert alg == 2.0 * n2 * 64 + bench.alg_flops(w)
+    assert ex == 2.0 * n2 * 64 + 2.0 * bench.alg_flops(w)
+    # a run narrower than the prefix screens all its coordinates
+    small = W.shrink(w, r=20, n=1024)
+    assert bench.screened_work(small, "bf16x3p", 0, 32)[0] == 2.0 * 1024 * 1024 * 20
+
+
+def test_traffic_record_needs_matching_form_and_source(tmp_path, monkeypatch):
+    f = tmp_path / "traffic.md"
+    f.write_text("traffic_prec = bf16x3p\ntraffic_source_hash = %s\ntraffic_bytes_per_launch = 1.5e+08\n"
+                 % bench.kernel_source_hash())
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
+    assert bench.recorded_traffic("bf16x3p") == 1.5e8
+    assert bench.recorded_traffic("bf16x3s") is None
+    f.write_text("traffic_prec = bf16x3p\ntraffic_source_hash = 0000\ntraffic_bytes_per_launch = 1.5e+08\n")
+    assert bench.recorded_traffic("bf16x3p") is None
+
+
+def test_more_than_one_gpu_is_refused():
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert p.returncode != 0
+    line = json.loads(p.stdout.strip().splitlines()[-1])
+    assert "one GPU" in line["error"]
