@@ -35,6 +35,8 @@ VALU_FP32_PEAK = 78.6   # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz, packed FP3
 # matrix-core products executed per algorithmic product (x.x and x.f each count once)
 EXEC_PER_ALG = {"bf16x3": 3.0, "bf16x3g": 2.0, "bf16x1": 1.0, "fp32_mfma": 1.0}
 PRE_K = 64   # coordinates of the partial-distance screen (BF16X3P)
+# (r, n) of the paper's large-scale test (the workloads module holds the same list)
+PAPER_E1 = ((10, 100), (50, 300), (100, 500), (300, 800), (600, 1000), (1000, 2000))
 PAIR_SRC = os.path.join(ROOT, "paper_2509_16896_amd", "csrc", "yy_pair_mfma.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pair_mfma_cubic_r1000_n65536_traffic.md")
 
@@ -313,7 +315,8 @@ def main():
                     help="matrix-core forms whose pairwise kernel is also timed ('none' to skip)")
     ap.add_argument("--baseline-prec", default="fp32_mfma", help="plain FP32 form timed beside ('none' to skip)")
     ap.add_argument("--baseline-steps", type=int, default=4)
-    ap.add_argument("--workload", default="cubic_r1000", choices=["cubic_r1000", "cubic_r100", "batch64"])
+    ap.add_argument("--workload", default="cubic_r1000",
+                    choices=["cubic_r1000", "cubic_r100", "batch64"] + [f"paper_e1_r{r}" for r, _ in PAPER_E1])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--proposal", default="learned", choices=["learned", "none"],
@@ -338,7 +341,10 @@ def main():
 
     from paper_2509_16896_amd import workloads as W
 
-    w = {"cubic_r1000": W.cubic_r1000, "cubic_r100": W.cubic_r100}[args.workload]()
+    if args.workload.startswith("paper_e1_r"):
+        w = W.paper_e1(int(args.workload[len("paper_e1_r"):]))
+    else:
+        w = {"cubic_r1000": W.cubic_r1000, "cubic_r100": W.cubic_r100}[args.workload]()
     if args.traffic_probe:
         w.K = 2
         traffic_probe(w, args.prec)
@@ -441,6 +447,9 @@ def main():
         "sampled_row_max_rel_err": parity,
         "cpu_baseline": cpu,
     }
+    if args.workload.startswith("paper_e1_r"):
+        # the paper's runs take 1000 steps of this workload
+        line["time_for_1000_steps_s"] = round(1000.0 / steps_s, 4)
     print(json.dumps(line), flush=True)
 
 

@@ -78,7 +78,12 @@ yy_status yy_get_status(yy_ctx ctx, uint32_t* flags, int64_t* nclamped);
 typedef enum {
   YY_F_ZERO = 0,    /* f(x) = 0 */
   YY_F_COS = 1,     /* f_k(x) = cos(x_k) */
-  YY_F_LINEAR = 2   /* f(x) = A x, A device row-major [r x r] */
+  YY_F_LINEAR = 2,  /* f(x) = A x, A device row-major [r x r] */
+  YY_F_PAPER_SINMIX = 3 /* the drift of the large-scale cubic sensor test (Sec. 11,
+                         * eq. A&A1): f(x) = sin(x) (A x) + sin(2x) (A1 x) elementwise,
+                         * A and A1 upper bidiagonal with diagonal -0.5 / -0.3 and
+                         * superdiagonal 0.1 / 0.3: f_k = sin(x_k)(-0.5 x_k + 0.1 x_{k+1})
+                         * + sin(2 x_k)(-0.3 x_k + 0.3 x_{k+1}), x_r = 0 */
 } yy_drift;
 
 typedef enum {

@@ -45,7 +45,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libyyo.so")
 _lib = None
 
-F_ZERO, F_COS, F_LINEAR = 0, 1, 2
+F_ZERO, F_COS, F_LINEAR, F_PAPER_SINMIX = 0, 1, 2, 3
 H_IDENTITY, H_CUBE, H_LINEAR = 0, 1, 2
 
 

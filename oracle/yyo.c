@@ -251,6 +251,13 @@ void yyo_drift(const yyo_model* mdl, const double* xi, double* fi) {
       fi[k] = 0.0;
     } else if (mdl->drift == YYO_F_COS) {
       fi[k] = cos(xi[k]);
+    } else if (mdl->drift == YYO_F_PAPER_SINMIX) {
+      /* Sec. 11, large-scale test: sin(x) (A x) + sin(2x) (A1 x) with the
+       * bidiagonal A (-0.5 on the diagonal, 0.1 above) and A1 (-0.3, 0.3) */
+      const double next = k + 1 < r ? xi[k + 1] : 0.0;
+      const double ax = -0.5 * xi[k] + 0.1 * next;
+      const double a1x = -0.3 * xi[k] + 0.3 * next;
+      fi[k] = sin(xi[k]) * ax + sin(2.0 * xi[k]) * a1x;
     } else {
       double acc = 0.0;
       for (int32_t l = 0; l < r; ++l) acc += mdl->A[(size_t)k * r + l] * xi[l];

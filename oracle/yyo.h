@@ -27,7 +27,7 @@ extern "C" {
 /* Problem statement dx = f(x)dt + sqrt(q) dV, dy = h(x)dt + sqrt(rho2) dW
  * (Sec. 2.1, eq. NonlinearFilter; constant isotropic noise a = qI, b = rho2 I
  * of Table tab:generalformulas). */
-enum { YYO_F_ZERO = 0, YYO_F_COS = 1, YYO_F_LINEAR = 2 };
+enum { YYO_F_ZERO = 0, YYO_F_COS = 1, YYO_F_LINEAR = 2, YYO_F_PAPER_SINMIX = 3 };
 enum { YYO_H_IDENTITY = 0, YYO_H_CUBE = 1, YYO_H_LINEAR = 2 };
 
 typedef struct {

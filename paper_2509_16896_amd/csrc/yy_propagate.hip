@@ -71,6 +71,9 @@ __device__ __forceinline__ void k_prepare_body(int64_t n, int64_t n_pad, int32_t
           double acc = 0.0;
           for (int32_t l = 0; l < r; ++l) acc = fma(Ak[l], xi[l], acc);
           fd = acc;
+        } else if (drift == YY_F_PAPER_SINMIX) {
+          const double xn = k + 1 < r ? xi[k + 1] : 0.0;
+          fd = sin(xv) * (-0.5 * xv + 0.1 * xn) + sin(2.0 * xv) * (-0.3 * xv + 0.3 * xn);
         }
         sxx = fma(xcd, xcd, sxx);
         sff = fma(fd, fd, sff);
@@ -570,7 +573,7 @@ yy_status prepare_nodes(yy_ctx ctx, const yy_model* m, int64_t n, const double* 
 static yy_status check_model(const yy_model* m) {
   if (!m) return fail(YY_ERR_ARG, "model is NULL");
   if (m->r < 1 || m->r > YY_MAX_R) return fail(YY_ERR_ARG, "model r out of range");
-  if (m->drift < YY_F_ZERO || m->drift > YY_F_LINEAR) return fail(YY_ERR_ARG, "unknown drift");
+  if (m->drift < YY_F_ZERO || m->drift > YY_F_PAPER_SINMIX) return fail(YY_ERR_ARG, "unknown drift");
   if (m->drift == YY_F_LINEAR && !m->A) return fail(YY_ERR_ARG, "linear drift needs A");
   if (m->obs < YY_H_IDENTITY || m->obs > YY_H_LINEAR) return fail(YY_ERR_ARG, "unknown observation");
   if (m->obs == YY_H_LINEAR && !m->H) return fail(YY_ERR_ARG, "linear observation needs H");

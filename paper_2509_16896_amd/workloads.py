@@ -17,7 +17,7 @@ import math
 
 import numpy as np
 
-F_ZERO, F_COS, F_LINEAR = 0, 1, 2
+F_ZERO, F_COS, F_LINEAR, F_PAPER_SINMIX = 0, 1, 2, 3
 H_IDENTITY, H_CUBE, H_LINEAR = 0, 1, 2
 
 
@@ -81,6 +81,20 @@ def cubic_r1000() -> Workload:
                     seed=0)
 
 
+# (r, n) pairs of the paper's large-scale test
+PAPER_E1_SIZES = ((10, 100), (50, 300), (100, 500), (300, 800), (600, 1000), (1000, 2000))
+
+
+def paper_e1(r: int, seed: int = 0) -> Workload:
+    """The paper's large-scale cubic sensor test: f = sin(x)(Ax) + sin(2x)(A1 x) with its bidiagonal A and
+    A1, h = (x - 100)^3, unit noise, dt = 0.01, 1000 steps, restarts of half-width 0.3 every 2 steps, n as
+    the paper pairs it with r; scales {1,2,4} and an initial box of half-width 3 around the prior N(0, I)."""
+    n = dict(PAPER_E1_SIZES)[r]
+    return Workload(f"paper_e1_r{r}_n{n}", r=r, n=n, dt=0.01, K=1000, drift=F_PAPER_SINMIX, obs=H_CUBE, q=1.0,
+                    rho2=1.0, scales=(1.0, 2.0, 4.0), box_half=3.0, restart_every=2, R=0.3, seed=seed,
+                    h_shift=100.0, precision="bf16x3p")
+
+
 def batch_runs(count: int = 64, seed: int = 0):
     """Batch of independent cubic-sensor runs: r ~ U{10..200}, n = 2^U{11..15}, dt=0.01, 100 steps."""
     rng = np.random.default_rng(seed)
@@ -114,6 +128,9 @@ def _drift_np(w: Workload, x: np.ndarray) -> np.ndarray:
         return np.zeros_like(x)
     if w.drift == F_COS:
         return np.cos(x)
+    if w.drift == F_PAPER_SINMIX:
+        nxt = np.concatenate([x[..., 1:], np.zeros_like(x[..., :1])], axis=-1)   # x_{k+1}, 0 past the last
+        return np.sin(x) * (-0.5 * x + 0.1 * nxt) + np.sin(2.0 * x) * (-0.3 * x + 0.3 * nxt)
     return x @ w.A.T
 
 

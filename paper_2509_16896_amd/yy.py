@@ -22,7 +22,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 YY_OK, YY_ERR_ARG, YY_ERR_ALLOC, YY_ERR_HIP, YY_ERR_NUMERIC, YY_ERR_UNSUPPORTED = range(6)
 YY_FLAG_ALL_ZERO, YY_FLAG_CLAMPED, YY_FLAG_RESAMPLE_ZERO, YY_FLAG_LOW_ESS = 1, 2, 4, 8
-YY_F_ZERO, YY_F_COS, YY_F_LINEAR = 0, 1, 2
+YY_F_ZERO, YY_F_COS, YY_F_LINEAR, YY_F_PAPER_SINMIX = 0, 1, 2, 3
 YY_H_IDENTITY, YY_H_CUBE, YY_H_LINEAR = 0, 1, 2
 (YY_PREC_AUTO, YY_PREC_FP32, YY_PREC_FP32_MFMA, YY_PREC_BF16X3, YY_PREC_BF16X1, YY_PREC_BF16X3G, YY_PREC_BF16X3S,
  YY_PREC_BF16X3P) = 0, 1, 2, 3, 4, 5, 6, 7

@@ -40,6 +40,13 @@ def test_screened_work():
     assert bench.screened_work(small, "bf16x3p", 0, 32)[0] == 2.0 * 1024 * 1024 * 20
 
 
+def test_paper_sizes_match_the_workloads():
+    assert tuple(bench.PAPER_E1) == W.PAPER_E1_SIZES
+    for r, n in W.PAPER_E1_SIZES:
+        w = W.paper_e1(r)
+        assert (w.r, w.n, w.K, w.dt, w.h_shift, w.R, w.restart_every) == (r, n, 1000, 0.01, 100.0, 0.3, 2)
+
+
 def test_traffic_record_needs_matching_form_and_source(tmp_path, monkeypatch):
     f = tmp_path / "traffic.md"
     f.write_text("traffic_prec = bf16x3p\ntraffic_source_hash = %s\ntraffic_bytes_per_launch = 1.5e+08\n"

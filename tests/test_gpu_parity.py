@@ -90,6 +90,9 @@ PROP_CASES = {
                                lw_kind="sparse"),
     "cos_r2_unscrambled_boundary": dict(r=2, n=256, drift=oracle.F_COS, scales=(1.0,), q=1.0, dt=0.02, half=2.0,
                                         seed=6, scramble=False),
+    # the paper's large-scale drift (bidiagonal sin mix), its r=10 size and unit noise
+    "sinmix_r10_n100_s124": dict(r=10, n=100, drift=oracle.F_PAPER_SINMIX, scales=(1.0, 2.0, 4.0), q=1.0, dt=0.01,
+                                 half=0.3, seed=7),
 }
 
 
@@ -242,6 +245,8 @@ def test_restart_nodes_bit_exact(ctx, r, n):
 # ---------------------------------------------------------------- matrix-core propagation
 MFMA_CASES = {
     # r >= 32: the distance expansion runs on the matrix cores, near pairs exactly
+    "sinmix_r50_n300_s124": dict(r=50, n=300, drift=oracle.F_PAPER_SINMIX, scales=(1.0, 2.0, 4.0), q=1.0, dt=0.01,
+                                 half=0.3, seed=13),
     "cos_r64_n512_s124": dict(r=64, n=512, drift=oracle.F_COS, scales=(1.0, 2.0, 4.0), q=0.09, dt=0.005, half=0.3,
                               seed=11),
     "cos_r100_n1000_ragged_s124": dict(r=100, n=1000, drift=oracle.F_COS, scales=(1.0, 2.0, 4.0), q=0.09, dt=0.005,
