@@ -10,7 +10,8 @@
 * Cubic sensor r=1000, n=65536, four steps with two restarts: the chosen form's
   posterior means against the plain FP32 form's (the oracle's filter takes
   minutes per step at this size; the FP32 form matches it to 1e-5 on the
-  smaller workloads above).
+  smaller workloads above); and all 50 steps in the chosen form against the
+  plain FP32 matrix-core form, with their RMSEs to the true path.
 """
 import numpy as np
 import pytest
@@ -121,3 +122,25 @@ def test_cubic_r1000_n65536_chosen_form_means(prec):
     print(f"r=1000, n=65536, 4 steps: max |mean({prec}) - mean(fp32)| = {err:.3g}")
     assert np.all(np.isfinite(got))
     assert err <= 1e-3
+
+
+def test_cubic_r1000_n65536_full_run_chosen_form():
+    """All 50 steps (24 restarts, learned proposal off) in the chosen form against the plain FP32 form:
+    the posterior means agree to 1e-3 at every step, and so do their RMSEs to the true path."""
+    w = W.cubic_r1000()
+    xs, dys = W.simulate(w)
+    out = {}
+    for prec in ("bf16x3p", "fp32_mfma"):
+        f = _gpu_filter(w, dys, prec, w.K)
+        try:
+            out[prec] = f.hist.cpu().numpy()
+        finally:
+            f.close()
+    got, ref = out["bf16x3p"], out["fp32_mfma"]
+    err = float(np.max(np.abs(got - ref)))
+    rg, rr = W.rmse(got, xs[1:]), W.rmse(ref, xs[1:])
+    print(f"r=1000, n=65536, {w.K} steps: max |mean(bf16x3p) - mean(fp32_mfma)| = {err:.3g}; "
+          f"RMSE to truth {rg:.4f} against {rr:.4f}")
+    assert np.all(np.isfinite(got))
+    assert err <= 1e-3
+    assert abs(rg - rr) <= 1e-3 * max(rr, 1e-12) + 1e-6
