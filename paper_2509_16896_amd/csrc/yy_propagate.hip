@@ -23,8 +23,10 @@ namespace yy {
 
 // ---------------------------------------------------------------------------
 // (1) node preparation: one wavefront per 4 consecutive nodes, 16 lanes per
-// node, one 16-wide K chunk per step, so that each step writes whole 128-byte
-// lines of the tiled planes (4 nodes x 16 K values).
+// node.  Rows of even length take two 32-wide K ranges per step, a coordinate
+// pair per lane in each (whole 128-byte lines of the row-major planes, and of
+// the tiled planes: 4 nodes x 16 K values per chunk); other rows one 16-wide K
+// chunk per step, a coordinate per lane.
 // Matrix-core planes are tiled [plane][rp/16][n_pad][16] so that 16 K values
 // of consecutive nodes are contiguous; rows n..n_pad-1 are zero.
 __device__ inline double sum16(double v) {
@@ -42,12 +44,30 @@ __device__ __forceinline__ void k_prepare_body(int64_t n, int64_t n_pad, int32_t
                                                     uint16_t* __restrict__ bf, float* __restrict__ f32t,
                                                     double* __restrict__ node, int* __restrict__ bnd,
                                                     int bx_, int gx_) {
-  static_assert(kPreK % 16 == 0, "the prefix is whole K chunks");
   const int lane = threadIdx.x & 63, sub = lane >> 4, kl = lane & 15;
   const int64_t wave = ((int64_t)bx_ * blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gx_ * blockDim.x) >> 6;
   const size_t plane = (size_t)n_pad * rp;
+  static_assert(kPreK % 64 == 0, "the prefix is whole 64-coordinate steps of the paired path");
   double mx[4] = {0.0, 0.0, 0.0, 0.0};   // running maxima of the norms (all >= 0)
+  // Rows of even length with 16-byte aligned x, lo and hi take the paired path: each lane handles
+  // the coordinate pairs k0 + 2 kl and k0 + 32 + 2 kl (16-byte loads, 8-byte stores), 64
+  // coordinates per step; the linear drift keeps one coordinate per lane.
+  const bool pairs = (r & 1) == 0 && drift != YY_F_LINEAR &&
+                     ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(lo) |
+                       reinterpret_cast<uintptr_t>(hi)) & 15) == 0;
+  auto near_box = [](double xv, double l, double h) {
+    return (int)((fabs(xv - l) <= kBoundaryTol) || (fabs(h - xv) <= kBoundaryTol));
+  };
+  auto sinmix = [](double xv, double xn) {
+    return sin(xv) * (-0.5 * xv + 0.1 * xn) + sin(2.0 * xv) * (-0.3 * xv + 0.3 * xn);
+  };
+  // BF16 hi part of v (the FP32 value of d) and the BF16 of what it leaves of d
+  auto split = [](double d, float v, uint32_t& h, uint32_t& l) {
+    const uint16_t hv = f32_to_bf16(v);
+    h = hv;
+    l = f32_to_bf16((float)(d - (double)bf16_to_f32(hv)));
+  };
   for (int64_t i4 = wave * 4; i4 < n_pad; i4 += nwaves * 4) {
     const int64_t i = i4 + sub;   // n_pad is a multiple of 4
     const bool real = i < n;
@@ -55,56 +75,115 @@ __device__ __forceinline__ void k_prepare_body(int64_t n, int64_t n_pad, int32_t
     double sxx = 0.0, sff = 0.0, sxf = 0.0;
     double pxx = 0.0, pff = 0.0, pxf = 0.0;   // over the first kPreK coordinates
     int b = 0;
-    for (int32_t k0 = 0; k0 < rp; k0 += 16) {
-      const int32_t k = k0 + kl;
-      float xcv = 0.f, fv = 0.f;
-      double xcd = 0.0, fd = 0.0;
-      if (real && k < r) {
-        const double xv = xi[k];
-        const double c = 0.5 * (lo[k] + hi[k]);
-        xcd = xv - c;
-        b |= (fabs(xv - lo[k]) <= kBoundaryTol) || (fabs(hi[k] - xv) <= kBoundaryTol);
-        if (drift == YY_F_COS) {
-          fd = cos(xv);
-        } else if (drift == YY_F_LINEAR) {
-          const double* Ak = A + (size_t)k * r;
-          double acc = 0.0;
-          for (int32_t l = 0; l < r; ++l) acc = fma(Ak[l], xi[l], acc);
-          fd = acc;
-        } else if (drift == YY_F_PAPER_SINMIX) {
-          const double xn = k + 1 < r ? xi[k + 1] : 0.0;
-          fd = sin(xv) * (-0.5 * xv + 0.1 * xn) + sin(2.0 * xv) * (-0.3 * xv + 0.3 * xn);
+    if (pairs) {
+      for (int32_t k0 = 0; k0 < rp; k0 += 64) {
+#pragma unroll 1
+        for (int half = 0; half < 2; ++half) {
+          const int32_t k = k0 + 32 * half + 2 * kl;
+          double xc0 = 0.0, xc1 = 0.0, f0 = 0.0, f1 = 0.0;
+          if (real && k < r) {   // r is even: both coordinates of the pair are inside
+            const double2 xv = *reinterpret_cast<const double2*>(xi + k);
+            const double2 l2 = *reinterpret_cast<const double2*>(lo + k);
+            const double2 h2 = *reinterpret_cast<const double2*>(hi + k);
+            xc0 = xv.x - 0.5 * (l2.x + h2.x);
+            xc1 = xv.y - 0.5 * (l2.y + h2.y);
+            b |= near_box(xv.x, l2.x, h2.x) | near_box(xv.y, l2.y, h2.y);
+            if (drift == YY_F_COS) {
+              f0 = cos(xv.x);
+              f1 = cos(xv.y);
+            } else if (drift == YY_F_PAPER_SINMIX) {
+              f0 = sinmix(xv.x, xv.y);
+              f1 = sinmix(xv.y, k + 2 < r ? xi[k + 2] : 0.0);
+            }
+            sxx = fma(xc0, xc0, sxx);
+            sff = fma(f0, f0, sff);
+            sxf = fma(xc0, f0, sxf);
+            sxx = fma(xc1, xc1, sxx);
+            sff = fma(f1, f1, sff);
+            sxf = fma(xc1, f1, sxf);
+          }
+          if (k < rp) {   // rp is a multiple of 32: the pair is inside or outside as a whole
+            const float a0 = (float)xc0, a1 = (float)xc1, g0 = (float)f0, g1 = (float)f1;
+            if (real) {
+              const size_t o = (size_t)i * rp + k;
+              *reinterpret_cast<float2*>(xc32 + o) = make_float2(a0, a1);
+              *reinterpret_cast<float2*>(f32 + o) = make_float2(g0, g1);
+            }
+            const size_t t = ((size_t)(k >> 4) * n_pad + i) * 16 + (k & 15);
+            if (bf) {
+              uint32_t xh0, xl0, xh1, xl1, fh0, fl0, fh1, fl1;
+              split(xc0, a0, xh0, xl0);
+              split(xc1, a1, xh1, xl1);
+              split(f0, g0, fh0, fl0);
+              split(f1, g1, fh1, fl1);
+              *reinterpret_cast<uint32_t*>(bf + t) = xh0 | (xh1 << 16);
+              *reinterpret_cast<uint32_t*>(bf + plane + t) = fh0 | (fh1 << 16);
+              *reinterpret_cast<uint32_t*>(bf + 2 * plane + t) = xl0 | (xl1 << 16);
+              *reinterpret_cast<uint32_t*>(bf + 3 * plane + t) = fl0 | (fl1 << 16);
+            }
+            if (f32t) {
+              *reinterpret_cast<float2*>(f32t + t) = make_float2(a0, a1);
+              *reinterpret_cast<float2*>(f32t + plane + t) = make_float2(g0, g1);
+            }
+          }
         }
-        sxx = fma(xcd, xcd, sxx);
-        sff = fma(fd, fd, sff);
-        sxf = fma(xcd, fd, sxf);
-        xcv = (float)xcd;
-        fv = (float)fd;
+        if (k0 < kPreK) {
+          pxx = sxx;
+          pff = sff;
+          pxf = sxf;
+        }
       }
-      if (k0 < kPreK) {
-        pxx = sxx;
-        pff = sff;
-        pxf = sxf;
-      }
-      if (real) {
-        const size_t o = (size_t)i * rp + k;
-        xc32[o] = xcv;
-        f32[o] = fv;
-      }
-      const size_t t = ((size_t)(k0 >> 4) * n_pad + i) * 16 + kl;
-      if (bf) {
-        const uint16_t xh = f32_to_bf16(xcv);
-        const uint16_t xl = f32_to_bf16((float)(xcd - (double)bf16_to_f32(xh)));
-        const uint16_t fh = f32_to_bf16(fv);
-        const uint16_t fl = f32_to_bf16((float)(fd - (double)bf16_to_f32(fh)));
-        bf[t] = xh;
-        bf[plane + t] = fh;
-        bf[2 * plane + t] = xl;
-        bf[3 * plane + t] = fl;
-      }
-      if (f32t) {
-        f32t[t] = xcv;
-        f32t[plane + t] = fv;
+    } else {
+      for (int32_t k0 = 0; k0 < rp; k0 += 16) {
+        const int32_t k = k0 + kl;
+        float xcv = 0.f, fv = 0.f;
+        double xcd = 0.0, fd = 0.0;
+        if (real && k < r) {
+          const double xv = xi[k];
+          const double c = 0.5 * (lo[k] + hi[k]);
+          xcd = xv - c;
+          b |= near_box(xv, lo[k], hi[k]);
+          if (drift == YY_F_COS) {
+            fd = cos(xv);
+          } else if (drift == YY_F_LINEAR) {
+            const double* Ak = A + (size_t)k * r;
+            double acc = 0.0;
+            for (int32_t l = 0; l < r; ++l) acc = fma(Ak[l], xi[l], acc);
+            fd = acc;
+          } else if (drift == YY_F_PAPER_SINMIX) {
+            fd = sinmix(xv, k + 1 < r ? xi[k + 1] : 0.0);
+          }
+          sxx = fma(xcd, xcd, sxx);
+          sff = fma(fd, fd, sff);
+          sxf = fma(xcd, fd, sxf);
+          xcv = (float)xcd;
+          fv = (float)fd;
+        }
+        if (k0 < kPreK) {
+          pxx = sxx;
+          pff = sff;
+          pxf = sxf;
+        }
+        if (real) {
+          const size_t o = (size_t)i * rp + k;
+          xc32[o] = xcv;
+          f32[o] = fv;
+        }
+        const size_t t = ((size_t)(k0 >> 4) * n_pad + i) * 16 + kl;
+        if (bf) {
+          const uint16_t xh = f32_to_bf16(xcv);
+          const uint16_t xl = f32_to_bf16((float)(xcd - (double)bf16_to_f32(xh)));
+          const uint16_t fh = f32_to_bf16(fv);
+          const uint16_t fl = f32_to_bf16((float)(fd - (double)bf16_to_f32(fh)));
+          bf[t] = xh;
+          bf[plane + t] = fh;
+          bf[2 * plane + t] = xl;
+          bf[3 * plane + t] = fl;
+        }
+        if (f32t) {
+          f32t[t] = xcv;
+          f32t[plane + t] = fv;
+        }
       }
     }
     sxx = sum16(sxx);
@@ -143,7 +222,7 @@ __device__ __forceinline__ void k_prepare_body(int64_t n, int64_t n_pad, int32_t
 
 int prepare_blocks(int64_t n_pad) { return (int)std::min<int64_t>((n_pad + 15) / 16, 16384); }
 
-__global__ void __launch_bounds__(kBlock) k_prepare(int64_t n, int64_t n_pad, int32_t r, int32_t rp,
+__global__ void __launch_bounds__(kBlock, 4) k_prepare(int64_t n, int64_t n_pad, int32_t r, int32_t rp,
                                                     int32_t drift, const double* __restrict__ A,
                                                     const double* __restrict__ x,
                                                     const double* __restrict__ lo,
@@ -154,7 +233,7 @@ __global__ void __launch_bounds__(kBlock) k_prepare(int64_t n, int64_t n_pad, in
   k_prepare_body(n, n_pad, r, rp, drift, A, x, lo, hi, xc32, f32, bf, f32t, node, bnd, blockIdx.x, gridDim.x);
 }
 
-__global__ void __launch_bounds__(kBlock) k_prepare_batch(const prepare_args* __restrict__ A,
+__global__ void __launch_bounds__(kBlock, 4) k_prepare_batch(const prepare_args* __restrict__ A,
                                                           const int* __restrict__ pre, int nr) {
   const int q = batch_find(pre, nr, blockIdx.x);
   const prepare_args& a = A[q];
