@@ -252,6 +252,7 @@ yy_status yy_create(yy_ctx* out, int device, void* stream) {
     return hip_fail(e, "hipMalloc(status)");
   }
   ctx->d_nclamped = reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(ctx->d_flags) + 8);
+  ctx->d_defer = reinterpret_cast<int*>(reinterpret_cast<char*>(ctx->d_flags) + 16);
   e = hipMemsetAsync(ctx->d_flags, 0, 64, ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) {

@@ -45,8 +45,24 @@ struct DevBuf {
 };
 
 // The node set as the pairwise kernels consume it; rebuilt when the nodes change.
+// BF16X3P on one run: the preparation writes only what the partial-distance
+// screen reads (the node norms, the boundary flags and hi(xc) over the first
+// kPreK coordinates); the remaining planes are written after the screen, and
+// only once it has flagged a tile for this node set.
+struct DeferredPrep {
+  int64_t n, n_pad;
+  int32_t r, rp, drift;
+  const double *A, *x, *lo, *hi;
+  float *xc32, *f32;
+  uint16_t* bf;
+  int* defer;   // device int[2]: [0] the screen flagged a tile in this call, [1] the planes are complete
+};
+yy_status launch_prepare_rest(hipStream_t st, const DeferredPrep& d);
+
 struct Prepared {
   bool valid = false;
+  bool deferred = false;    // the planes beyond the screen's prefix wait for a flagged tile (dp)
+  DeferredPrep dp{};
   const double* x = nullptr;
   int64_t n = 0;
   int32_t r = 0;
@@ -76,6 +92,7 @@ struct yy_ctx_s {
   hipStream_t stream = nullptr;
   uint32_t* d_flags = nullptr;        // status word
   unsigned long long* d_nclamped = nullptr;
+  int* d_defer = nullptr;             // int[2] of the deferred planes (DeferredPrep::defer)
   // Sobol direction numbers (host, unscrambled) for dimensions < dir_r.
   std::vector<uint32_t> dirs;
   int32_t dir_r = 0;
@@ -124,7 +141,7 @@ namespace yy {
 yy_status sobol_prepare_dirs(yy_ctx ctx, int32_t r, int32_t scramble, uint64_t seed);
 yy_status prepare_nodes(yy_ctx ctx, const yy_model* model, int64_t n, const double* x,
                         uint64_t version, const double* lo, const double* hi, bool want_bf16,
-                        bool want_f32t, int32_t prec);
+                        bool want_f32t, int32_t prec, bool defer_planes);
 yy_status coefficients_cramer(int32_t S, const double* s, double* c);
 yy_status validate_model(const yy_model* m);
 yy_status timing_begin(yy_ctx ctx);
@@ -156,6 +173,7 @@ struct MfmaExtra {
   double taud[YY_MAX_SCALES];
   uint8_t* flags;              // screened split forms: [n_pad/256][ceil(n/128)][8] screen verdicts
   float* bpre;                 // BF16X3P: source biases over the first kPreK coordinates, laid out as bsrc
+  const DeferredPrep* deferred;   // BF16X3P on one run with deferred planes, else null
 };
 // blocks of the node preparation kernel (one wave per 4 nodes, grid-stride)
 int prepare_blocks(int64_t n_pad);
@@ -186,6 +204,7 @@ struct CombineArgs {
   double* logw_out;
   uint32_t* flags;
   unsigned long long* nclamped;
+  int* defer;                      // deferred planes: marked complete when the screen flagged a tile
 };
 
 // One yy_propagate call split into its phases: begin = node preparation,
@@ -205,7 +224,7 @@ struct PropPlan {
 yy_status propagate_begin(yy_ctx ctx, const yy_model* model, const yy_scales* scales, int32_t prec, int64_t n,
                           const double* x, uint64_t node_version, const double* box_lo, const double* box_hi,
                           double dt, const double* logw_in, double* logw_out, int nsplit_override,
-                          PropPlan& plan);
+                          PropPlan& plan, bool defer_planes = false);
 yy_status propagate_pair(yy_ctx ctx, const PropPlan& plan);
 yy_status propagate_end(yy_ctx ctx, const PropPlan& plan);
 

@@ -83,6 +83,7 @@ struct MArgs {
   int32_t s_nsplit;            // the screen's source splits (of s_jps sources, a multiple of 256)
   int64_t s_jps;
   int32_t pre_chunks;          // 16-wide K stages of the partial-distance screen
+  int* any_flag;               // deferred planes: k_src_bias clears it, the screen sets it on a flagged tile
 };
 
 // Physical 16-byte chunk of logical chunk c in LDS row `row` (bank-conflict swizzle).
@@ -1180,6 +1181,7 @@ __device__ __forceinline__ void prescreen_block(const MArgs& a, int tb, int spli
     if (lane == 0 && jt < a.jtl) {
       a.flags[((size_t)tb * a.jtl + jt) * 8 + wi] = flag ? 1 : 0;
       a.flags[((size_t)tb * a.jtl + jt) * 8 + 4 + wi] = 0;
+      if (flag && a.any_flag) *a.any_flag = 1;
     }
   }
 }
@@ -1236,6 +1238,7 @@ __device__ __forceinline__ void k_src_bias_body(int64_t n, int64_t n_pad, int32_
                                                      MArgs a, float* __restrict__ out, int bx_, int gx_) {
   __shared__ double sh[kBlock / 64];
   const int64_t j = (int64_t)bx_ * kBlock + threadIdx.x;
+  if (a.any_flag && bx_ == 0 && threadIdx.x == 0) *a.any_flag = 0;
   for (int part = 0; part < (a.bpre ? 2 : 1); ++part) {
     float* o = part == 0 ? out : const_cast<float*>(a.bpre);
     const double* nd = a.node + (part == 0 ? 0 : 3 * n);
@@ -1321,6 +1324,7 @@ static MArgs make_args(const PairArgs& pa, int prec, const MfmaExtra& ex) {
   m.s_nsplit = pa.nsplit;
   m.s_jps = ((ex.j_per_split + kSJ - 1) / kSJ) * kSJ;
   m.pre_chunks = std::min(kPreK, (int)pa.rp) / kKC;
+  m.any_flag = ex.deferred ? ex.deferred->defer : nullptr;
   return m;
 }
 
@@ -1359,7 +1363,7 @@ static yy_status launch_batch_s(hipStream_t st, const MArgs* sets, const int4* i
 }
 
 template <int S>
-static yy_status launch_s(hipStream_t st, const MArgs& m, int prec, int nblocks) {
+static yy_status launch_s(hipStream_t st, const MArgs& m, int prec, int nblocks, const DeferredPrep* dp) {
   if (prec == YY_PREC_BF16X3) {
     k_pair_mfma<S, 3, 4, 2, false><<<nblocks, kNT, 0, st>>>(m);
   } else if (prec == YY_PREC_BF16X3G) {
@@ -1386,6 +1390,11 @@ static yy_status launch_s(hipStream_t st, const MArgs& m, int prec, int nblocks)
     if (m.pre_chunks == 4) k_pair_prescreen<S, 4, 16><<<m.tb_count * ps, kPW * 64, 0, st>>>(mp);
     else k_pair_prescreen<S, 2, 8><<<m.tb_count * ps, kPW * 64, 0, st>>>(mp);
     YY_LAUNCH_CHECK("k_pair_mfma (partial-distance screen)");
+    if (dp) {
+      // the planes beyond the screen's prefix, if it flagged a tile and they are not yet written
+      const yy_status rs = launch_prepare_rest(st, *dp);
+      if (rs != YY_OK) return rs;
+    }
     k_pair_mfma<S, 2, 4, 2, true><<<nblocks, kNT, 0, st>>>(m);
   } else if (prec == YY_PREC_BF16X1) {
     k_pair_mfma<S, 1, 8, 4, false><<<nblocks, kNT, 0, st>>>(m);
@@ -1400,10 +1409,10 @@ yy_status launch_pair_mfma(hipStream_t st, const PairArgs& pa, int prec, const M
   const MArgs m = make_args(pa, prec, ex);
   const int nblocks = m.tb_count * m.nsplit;
   switch (pa.S) {
-    case 1: return launch_s<1>(st, m, prec, nblocks);
-    case 2: return launch_s<2>(st, m, prec, nblocks);
-    case 3: return launch_s<3>(st, m, prec, nblocks);
-    case 4: return launch_s<4>(st, m, prec, nblocks);
+    case 1: return launch_s<1>(st, m, prec, nblocks, ex.deferred);
+    case 2: return launch_s<2>(st, m, prec, nblocks, ex.deferred);
+    case 3: return launch_s<3>(st, m, prec, nblocks, ex.deferred);
+    case 4: return launch_s<4>(st, m, prec, nblocks, ex.deferred);
   }
   return fail(YY_ERR_UNSUPPORTED, "the matrix-core path supports up to 4 scales");
 }

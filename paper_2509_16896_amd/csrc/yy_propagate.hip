@@ -35,6 +35,10 @@ __device__ inline double sum16(double v) {
   return v;
 }
 
+// MODE 0 writes everything; MODE 1 (BF16X3P, deferred planes) the node norms, the
+// boundary flags, the maxima and hi(xc) over the first kPreK coordinates; MODE 2
+// the planes and rows only (the rest of a MODE 1 preparation).
+template <int MODE>
 __device__ __forceinline__ void k_prepare_body(int64_t n, int64_t n_pad, int32_t r, int32_t rp,
                                                     int32_t drift, const double* __restrict__ A,
                                                     const double* __restrict__ x,
@@ -102,8 +106,16 @@ __device__ __forceinline__ void k_prepare_body(int64_t n, int64_t n_pad, int32_t
             sff = fma(f1, f1, sff);
             sxf = fma(xc1, f1, sxf);
           }
-          if (k < rp) {   // rp is a multiple of 32: the pair is inside or outside as a whole
+          // rp is a multiple of 32: the pair is inside or outside as a whole
+          if (k < (MODE == 1 ? min(rp, kPreK) : rp)) {
             const float a0 = (float)xc0, a1 = (float)xc1, g0 = (float)f0, g1 = (float)f1;
+            if (MODE == 1) {
+              uint32_t xh0, xl0, xh1, xl1;
+              split(xc0, a0, xh0, xl0);
+              split(xc1, a1, xh1, xl1);
+              *reinterpret_cast<uint32_t*>(bf + ((size_t)(k >> 4) * n_pad + i) * 16 + (k & 15)) = xh0 | (xh1 << 16);
+              continue;
+            }
             if (real) {
               const size_t o = (size_t)i * rp + k;
               *reinterpret_cast<float2*>(xc32 + o) = make_float2(a0, a1);
@@ -164,12 +176,16 @@ __device__ __forceinline__ void k_prepare_body(int64_t n, int64_t n_pad, int32_t
           pff = sff;
           pxf = sxf;
         }
+        const size_t t = ((size_t)(k0 >> 4) * n_pad + i) * 16 + kl;
+        if (MODE == 1) {
+          if (k0 < kPreK) bf[t] = f32_to_bf16(xcv);
+          continue;
+        }
         if (real) {
           const size_t o = (size_t)i * rp + k;
           xc32[o] = xcv;
           f32[o] = fv;
         }
-        const size_t t = ((size_t)(k0 >> 4) * n_pad + i) * 16 + kl;
         if (bf) {
           const uint16_t xh = f32_to_bf16(xcv);
           const uint16_t xl = f32_to_bf16((float)(xcd - (double)bf16_to_f32(xh)));
@@ -186,6 +202,7 @@ __device__ __forceinline__ void k_prepare_body(int64_t n, int64_t n_pad, int32_t
         }
       }
     }
+    if (MODE == 2) continue;
     sxx = sum16(sxx);
     sff = sum16(sff);
     sxf = sum16(sxf);
@@ -210,6 +227,7 @@ __device__ __forceinline__ void k_prepare_body(int64_t n, int64_t n_pad, int32_t
       mx[3] = fmax(mx[3], pff);
     }
   }
+  if (MODE == 2) return;
   // the block's maxima of |xc|^2, |f|^2 and their first-kPreK parts, to
   // node[6 n + 4 bx + c] (k_prepare_scalars reduces them)
   __shared__ double sh[kBlock / 64];
@@ -222,15 +240,35 @@ __device__ __forceinline__ void k_prepare_body(int64_t n, int64_t n_pad, int32_t
 
 int prepare_blocks(int64_t n_pad) { return (int)std::min<int64_t>((n_pad + 15) / 16, 16384); }
 
+// MODE 1 marks the deferred planes as not yet written (defer[1] = 0).
+template <int MODE>
 __global__ void __launch_bounds__(kBlock, 4) k_prepare(int64_t n, int64_t n_pad, int32_t r, int32_t rp,
-                                                    int32_t drift, const double* __restrict__ A,
-                                                    const double* __restrict__ x,
-                                                    const double* __restrict__ lo,
-                                                    const double* __restrict__ hi,
-                                                    float* __restrict__ xc32, float* __restrict__ f32,
-                                                    uint16_t* __restrict__ bf, float* __restrict__ f32t,
-                                                    double* __restrict__ node, int* __restrict__ bnd) {
-  k_prepare_body(n, n_pad, r, rp, drift, A, x, lo, hi, xc32, f32, bf, f32t, node, bnd, blockIdx.x, gridDim.x);
+                                                       int32_t drift, const double* __restrict__ A,
+                                                       const double* __restrict__ x,
+                                                       const double* __restrict__ lo,
+                                                       const double* __restrict__ hi,
+                                                       float* __restrict__ xc32, float* __restrict__ f32,
+                                                       uint16_t* __restrict__ bf, float* __restrict__ f32t,
+                                                       double* __restrict__ node, int* __restrict__ bnd,
+                                                       int* __restrict__ defer) {
+  if (MODE == 1 && blockIdx.x == 0 && threadIdx.x == 0) defer[1] = 0;
+  k_prepare_body<MODE>(n, n_pad, r, rp, drift, A, x, lo, hi, xc32, f32, bf, f32t, node, bnd, blockIdx.x,
+                       gridDim.x);
+}
+
+// The rest of a MODE 1 preparation, after the screen: every block returns at
+// once unless the screen flagged a tile in this call and the planes are not
+// yet complete (k_combine then marks them complete).
+__global__ void __launch_bounds__(kBlock, 4) k_prepare_rest(DeferredPrep d) {
+  if (d.defer[0] == 0 || d.defer[1] != 0) return;
+  k_prepare_body<2>(d.n, d.n_pad, d.r, d.rp, d.drift, d.A, d.x, d.lo, d.hi, d.xc32, d.f32, d.bf, nullptr,
+                    nullptr, nullptr, blockIdx.x, gridDim.x);
+}
+
+yy_status launch_prepare_rest(hipStream_t st, const DeferredPrep& d) {
+  k_prepare_rest<<<(unsigned)prepare_blocks(d.n_pad), kBlock, 0, st>>>(d);
+  YY_LAUNCH_CHECK("k_prepare_rest");
+  return YY_OK;
 }
 
 __global__ void __launch_bounds__(kBlock, 4) k_prepare_batch(const prepare_args* __restrict__ A,
@@ -238,7 +276,7 @@ __global__ void __launch_bounds__(kBlock, 4) k_prepare_batch(const prepare_args*
   const int q = batch_find(pre, nr, blockIdx.x);
   const prepare_args& a = A[q];
   if (a.pred && *a.pred == 0) return;
-  k_prepare_body(a.n, a.n_pad, a.r, a.rp, a.drift, a.A, a.x, a.lo, a.hi, a.xc32, a.f32, a.bf, a.f32t, a.node, a.bnd,
+  k_prepare_body<0>(a.n, a.n_pad, a.r, a.rp, a.drift, a.A, a.x, a.lo, a.hi, a.xc32, a.f32, a.bf, a.f32t, a.node, a.bnd,
                  blockIdx.x - pre[q], pre[q + 1] - pre[q]);
 }
 
@@ -536,6 +574,8 @@ static yy_status launch_pair_valu_d(hipStream_t st, const PairArgs& a, const dou
 __device__ __forceinline__ void k_combine_body(CombineArgs a, int bx_, int gx_) {
   const int64_t i = (int64_t)bx_ * kBlock + threadIdx.x;
   if (i >= a.n) return;
+  // deferred planes: written in this call when the screen flagged a tile
+  if (a.defer && i == 0 && a.defer[0]) a.defer[1] = 1;
   if (a.bnd[i]) {
     a.logw_out[i] = -INFINITY;
     return;
@@ -608,12 +648,13 @@ int pair_mfma_rp(int32_t r, int32_t prec) {
 
 yy_status prepare_nodes(yy_ctx ctx, const yy_model* m, int64_t n, const double* x,
                         uint64_t version, const double* lo, const double* hi, bool want_bf16,
-                        bool want_f32t, int32_t prec) {
+                        bool want_f32t, int32_t prec, bool defer_planes) {
   Prepared& P = ctx->prep;
   const int32_t rp = pair_mfma_rp(m->r, prec);
+  const bool defer = defer_planes && prec == YY_PREC_BF16X3P && want_bf16 && !want_f32t;
   const bool same = P.valid && P.x == x && P.n == n && P.r == m->r && P.rp == rp && P.drift == m->drift &&
                     P.A == m->A && P.version == version && P.lo == lo && P.hi == hi &&
-                    (P.have_bf16 || !want_bf16) && (P.have_f32t || !want_f32t);
+                    (P.have_bf16 || !want_bf16) && (P.have_f32t || !want_f32t) && (!P.deferred || defer);
   if (same) return YY_OK;
   const int64_t n_pad = pair_mfma_npad(n);
   yy_status st;
@@ -625,10 +666,16 @@ yy_status prepare_nodes(yy_ctx ctx, const yy_model* m, int64_t n, const double* 
   if ((st = P.node.ensure(((size_t)6 * n + 4 * (size_t)nparts) * sizeof(double))) != YY_OK) return st;
   if ((st = P.bnd.ensure((size_t)n * sizeof(int))) != YY_OK) return st;
   if ((st = P.scal.ensure(8 * sizeof(double))) != YY_OK) return st;
-  k_prepare<<<(unsigned)nparts, kBlock, 0, ctx->stream>>>(
-      n, n_pad, m->r, rp, m->drift, m->A, x, lo, hi, P.xc32.as<float>(), P.f32.as<float>(),
-      want_bf16 ? P.bf.as<uint16_t>() : nullptr, want_f32t ? P.f32t.as<float>() : nullptr,
-      P.node.as<double>(), P.bnd.as<int>());
+  if (defer) {
+    k_prepare<1><<<(unsigned)nparts, kBlock, 0, ctx->stream>>>(
+        n, n_pad, m->r, rp, m->drift, m->A, x, lo, hi, nullptr, nullptr, P.bf.as<uint16_t>(), nullptr,
+        P.node.as<double>(), P.bnd.as<int>(), ctx->d_defer);
+  } else {
+    k_prepare<0><<<(unsigned)nparts, kBlock, 0, ctx->stream>>>(
+        n, n_pad, m->r, rp, m->drift, m->A, x, lo, hi, P.xc32.as<float>(), P.f32.as<float>(),
+        want_bf16 ? P.bf.as<uint16_t>() : nullptr, want_f32t ? P.f32t.as<float>() : nullptr,
+        P.node.as<double>(), P.bnd.as<int>(), nullptr);
+  }
   YY_LAUNCH_CHECK("k_prepare");
   k_prepare_scalars<<<1, kBlock, 0, ctx->stream>>>(n, m->r, nparts, lo, hi, P.node.as<double>(),
                                                    P.scal.as<double>());
@@ -646,6 +693,9 @@ yy_status prepare_nodes(yy_ctx ctx, const yy_model* m, int64_t n, const double* 
   P.hi = hi;
   P.have_bf16 = want_bf16;
   P.have_f32t = want_f32t;
+  P.deferred = defer;
+  P.dp = DeferredPrep{n, n_pad, m->r, rp, m->drift, m->A, x, lo, hi, P.xc32.as<float>(), P.f32.as<float>(),
+                      P.bf.as<uint16_t>(), ctx->d_defer};
   return YY_OK;
 }
 
@@ -712,7 +762,7 @@ namespace yy {
 yy_status propagate_begin(yy_ctx ctx, const yy_model* model, const yy_scales* scales, int32_t prec, int64_t n,
                           const double* x, uint64_t node_version, const double* box_lo, const double* box_hi,
                           double dt, const double* logw_in, double* logw_out, int nsplit_override,
-                          PropPlan& plan) {
+                          PropPlan& plan, bool defer_planes) {
   yy_status st = check_model(model);
   if (st != YY_OK) return st;
   if (!scales || scales->S < 1 || scales->S > YY_MAX_SCALES || !scales->s)
@@ -745,7 +795,7 @@ yy_status propagate_begin(yy_ctx ctx, const yy_model* model, const yy_scales* sc
   st = prepare_nodes(ctx, model, n, x, node_version, box_lo, box_hi,
                      prec == YY_PREC_BF16X3 || prec == YY_PREC_BF16X3G || prec == YY_PREC_BF16X1 ||
                          prec == YY_PREC_BF16X3S || prec == YY_PREC_BF16X3P,
-                     prec == YY_PREC_FP32_MFMA, prec);
+                     prec == YY_PREC_FP32_MFMA, prec, defer_planes);
   if (st != YY_OK) return st;
   const Prepared& P = ctx->prep;
 
@@ -818,6 +868,7 @@ yy_status propagate_begin(yy_ctx ctx, const yy_model* model, const yy_scales* sc
     if ((st = ctx->bsrc.ensure((prec == YY_PREC_BF16X3P ? 2 : 1) * bsz * sizeof(float))) != YY_OK) return st;
     ex.bsrc = ctx->bsrc.as<float>();
     ex.bpre = prec == YY_PREC_BF16X3P ? ex.bsrc + bsz : nullptr;
+    ex.deferred = P.deferred ? &P.dp : nullptr;
     if (prec == YY_PREC_BF16X3S || prec == YY_PREC_BF16X3P) {
       if ((st = ctx->sflags.ensure((size_t)tbs * jtl * 8)) != YY_OK) return st;
       ex.flags = ctx->sflags.as<uint8_t>();
@@ -853,6 +904,7 @@ yy_status propagate_begin(yy_ctx ctx, const yy_model* model, const yy_scales* sc
   cb.logw_out = logw_out;
   cb.flags = ctx->d_flags;
   cb.nclamped = ctx->d_nclamped;
+  cb.defer = P.deferred ? ctx->d_defer : nullptr;
   return YY_OK;
 }
 
@@ -885,7 +937,7 @@ extern "C" yy_status yy_propagate(yy_ctx ctx, const yy_model* model, const yy_sc
   if (!ctx) return fail(YY_ERR_ARG, "yy_propagate: ctx is NULL");
   PropPlan plan;
   yy_status st = propagate_begin(ctx, model, scales, prec, n, x, node_version, box_lo, box_hi, dt, logw_in,
-                                 logw_out, 0, plan);
+                                 logw_out, 0, plan, true);
   if (st != YY_OK) return st;
   if ((st = propagate_pair(ctx, plan)) != YY_OK) return st;
   return propagate_end(ctx, plan);

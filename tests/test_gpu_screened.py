@@ -136,3 +136,48 @@ def test_screened_long_source_range_windows(ctx):
         assert np.all(np.isfinite(a))
         # another split count changes only the summation order of the partial sums
         assert np.allclose(a, r, rtol=1e-9, atol=1e-9)
+
+
+def test_deferred_planes_across_calls_on_one_node_set():
+    """BF16X3P on one run writes the planes beyond its screen's first 64 coordinates only
+    once the screen flags a tile for the node set.  Calls on one node set (same device array
+    and version): source weights that flag no tile, then weights that flag some (the planes
+    are written), then other flagging weights (the planes are reused), then a new node set
+    in the same array under a new version (written again); each against the split form
+    BF16X3G on another context."""
+    c = _case(**CASES["r200_n5000_narrow"])
+    n = c["n"]
+    # light stripes far below the gap to their nearest neighbour (about 2e4 bits at this
+    # kernel width): their rows' maxima come from heavy sources, so their tiles are flagged
+    stripe = lambda w: 1e5 * ((np.arange(n) // w) % 2)
+    seq = [(0, c["lw"]), (0, c["lw"] - stripe(640)), (0, c["lw"] - stripe(384)), (1, c["lw"] - stripe(640))]
+    c1 = _case(**dict(CASES["r200_n5000_narrow"], seed=47))
+    xs = [c["x"], c1["x"]]
+    a = yy.yy_create(0, torch.cuda.current_stream())
+    b = yy.yy_create(0, torch.cuda.current_stream())
+    try:
+        x = dev(xs[0].ravel())
+        lo, hi = dev(c["lo"]), dev(c["hi"])
+        versions = [next_version(), next_version()]
+        counts = []
+        for node_set, lw in seq:
+            if node_set == 1:
+                x.copy_(dev(xs[1].ravel()))
+            out = torch.empty(n, dtype=torch.float64, device="cuda")
+            yy.yy_propagate(a, c["gm"], yy.Scales(c["scales"]), "bf16x3p", n, x, versions[node_set], lo, hi,
+                            c["dt"], dev(lw), out)
+            got = host(out)
+            counts.append(yy.yy_screen_count(a)[0])
+            ref_out = torch.empty(n, dtype=torch.float64, device="cuda")
+            yy.yy_propagate(b, c["gm"], yy.Scales(c["scales"]), "bf16x3g", n, dev(xs[node_set].ravel()),
+                            next_version(), dev(c["lo"]), dev(c["hi"]), c["dt"], dev(lw), ref_out)
+            ref = host(ref_out)
+            f = np.isfinite(ref)
+            assert np.array_equal(np.isfinite(got), f)
+            rel = np.abs(got[f] - ref[f]) / np.maximum(1.0, np.abs(ref[f]))
+            assert rel.max() < 2e-6, (len(counts), counts[-1], rel.max())
+        print(f"flagged tiles per call: {counts}")
+        assert counts[0] == 0 and min(counts[1:]) > 0
+    finally:
+        yy.yy_destroy(a)
+        yy.yy_destroy(b)
