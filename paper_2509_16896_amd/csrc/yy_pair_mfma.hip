@@ -1072,6 +1072,19 @@ __device__ __forceinline__ void prescreen_block(const MArgs& a, int tb, int spli
     for (int c = 0; c < PC; ++c)
       bt[c][ib] = *reinterpret_cast<const bf16x8_t*>(gb + ((size_t)c * n_pad + i) * 32 + g * 16);
   }
+  // per scale the largest prefix bias over the block's source range (the tiles' maxima, lane-parallel):
+  // a coarse bound that needs no load inside the tile loop
+  typedef const __attribute__((address_space(4))) float* const_f32_ptr;
+  const float* tmax = a.bpre + (size_t)S * n_pad;   // [S][n_pad / 128] the tiles' maxima
+  float bblk[S];
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    float m = -INFINITY;
+    for (int t = lane; t < ntiles; t += 64) m = fmaxf(m, tmax[(size_t)s * (n_pad / kMJ) + (size_t)(jb0 / kMJ) + t]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+    bblk[s] = m;
+  }
   wait_vmcnt<0>();   // before the first copy: the waits below count copies only
 
 #pragma unroll
@@ -1128,14 +1141,21 @@ __device__ __forceinline__ void prescreen_block(const MArgs& a, int tb, int spli
         for (int v = 0; v < 16; ++v) m = fmaxf(m, G[ib][jb][v]);
       gmax[ib] = m;
     }
-    typedef const __attribute__((address_space(4))) float* const_f32_ptr;
-    const const_f32_ptr bmax = (const_f32_ptr)(a.bpre + (size_t)S * n_pad + (size_t)(j0 / kMJ));
+    // the coarse bound with the block's largest bias first, then with the tile's
     bool doubt = false;
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
-      const float bm = bmax[(size_t)s * (n_pad / kMJ)];
+    for (int s = 0; s < S; ++s)
 #pragma unroll
-      for (int ib = 0; ib < kIB; ++ib) doubt |= fmaf(a.c1[s], gmax[ib], bm) + at[ib][s] > M[ib][s] - margin[s];
+      for (int ib = 0; ib < kIB; ++ib) doubt |= fmaf(a.c1[s], gmax[ib], bblk[s]) + at[ib][s] > M[ib][s] - margin[s];
+    if (__any(doubt)) {
+      const const_f32_ptr bmax = (const_f32_ptr)(tmax + (size_t)(j0 / kMJ));
+      doubt = false;
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const float bm = bmax[(size_t)s * (n_pad / kMJ)];
+#pragma unroll
+        for (int ib = 0; ib < kIB; ++ib) doubt |= fmaf(a.c1[s], gmax[ib], bm) + at[ib][s] > M[ib][s] - margin[s];
+      }
     }
     bool need = false;
     if (__any(doubt)) {

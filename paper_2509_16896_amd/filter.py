@@ -40,7 +40,8 @@ class GpuFilter:
         self.lw = [torch.empty(n, **f64), torch.empty(n, **f64)]
         self.cur = 0
         self.wts = torch.empty(n, **f64)
-        self.mean = torch.zeros(r, **f64)
+        self.mean_buf = torch.zeros(r, **f64)
+        self.mean = self.mean_buf   # the latest posterior mean (a history row after a step)
         self.cov = torch.empty(r * r, **f64) if want_cov else None
         self.logZ_step = torch.zeros(1, **f64)
         self.logZ_acc = torch.zeros(1, **f64)
@@ -48,7 +49,8 @@ class GpuFilter:
         self.hist = torch.zeros(max(w.K, 1), r, **f64)
         self.logZ_hist = torch.zeros(max(w.K, 1), **f64)
         self.ess_hist = torch.zeros(max(w.K, 1), **f64)
-        self.ess = torch.zeros(1, **f64)
+        self.ess_buf = torch.zeros(1, **f64)
+        self.ess = self.ess_buf     # the latest ESS
         self.idx = torch.empty(n, dtype=torch.int64, device=self.dev)
         self.zero_r = torch.zeros(r, **f64)
         self.ess_min = ess_min
@@ -103,11 +105,20 @@ class GpuFilter:
         self.version += 1
         self._normalise(want_cov=False, acc=self.logZ_scratch)
 
-    def _normalise(self, want_cov, acc, moments=True):
+    def _normalise(self, want_cov, acc, moments=True, row=None):
+        """Normalise the current log-weights.  With `row`, the step's mean, logZ and ESS go straight
+        into that row of the histories (self.mean and self.ess then refer to it); otherwise into the
+        filter's own buffers."""
         w = self.w
+        if row is None:
+            mean, logz, ess = self.mean_buf, self.logZ_step, self.ess_buf
+        else:
+            mean, logz, ess = self.hist[row], self.logZ_hist[row:row + 1], self.ess_hist[row:row + 1]
         yy.yy_normalise_moments(self.ctx, w.n, w.r, self.x, self.lw[self.cur], self.wts if moments else None,
-                                self.logZ_step, acc, self.mean if moments else None,
-                                self.cov if want_cov else None, self.ess)
+                                logz, acc, mean if moments else None, self.cov if want_cov else None, ess)
+        if moments:
+            self.mean = mean
+        self.ess = ess
 
     def step(self, k: int, restart: bool | None = None, want_cov: bool = False):
         """Filter step k (1-based) with observation increment dys[k-1]."""
@@ -117,11 +128,7 @@ class GpuFilter:
                         self.hi, w.dt, src, dst)
         self.cur = 1 - self.cur
         yy.yy_loglik_update(self.ctx, self.model, w.n, self.x, self.dys[k - 1], w.dt, dst)
-        self._normalise(want_cov, acc=self.logZ_acc)
-        with torch.cuda.stream(self.stream):
-            self.hist[k - 1].copy_(self.mean)
-            self.logZ_hist[k - 1].copy_(self.logZ_step[0])
-            self.ess_hist[k - 1].copy_(self.ess[0])
+        self._normalise(want_cov, acc=self.logZ_acc, row=k - 1)
         if restart is None:
             restart = bool(w.restart_every) and k % w.restart_every == 0 and k < w.K
         if restart:
