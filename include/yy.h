@@ -192,6 +192,19 @@ yy_status yy_normalise_moments(yy_ctx ctx, int64_t n, int32_t r, const double* x
                                double* w, double* logZ_step, double* logZ_acc, double* mean,
                                double* cov, double* ess);
 
+/* The correction and the normalisation of one step in one call (Sec. 2.2.2
+ * steps 3 and 4): the results of yy_loglik_update followed by
+ * yy_normalise_moments with cov = NULL.  Where h is componentwise (m = r), r
+ * is even and at most 1024 and x and dy are 16-byte aligned, x is read once:
+ * each node's updated log-weight enters the weight and mean sums at once,
+ * relative to a running maximum (the log-weights are those of
+ * yy_loglik_update; logZ, w, mean and ess agree with the two calls to FP64
+ * rounding).  Otherwise the call makes the two calls.  Arguments as there;
+ * mean and ess are required, w may be NULL. */
+yy_status yy_loglik_normalise(yy_ctx ctx, const yy_model* model, int64_t n, const double* x,
+                              const double* dy, double dt, double* logw, double* w, double* logZ_step,
+                              double* logZ_acc, double* mean, double* ess);
+
 /* Learned restart proposal (not in the paper; the plain restart of Sec. 6 is
  * its fallback).  A multilayer perceptron maps the estimate x_hat (r) through
  * Linear(r, H) -> GELU -> Linear(H, H) -> GELU -> Linear(H, 2r) to (delta, u);

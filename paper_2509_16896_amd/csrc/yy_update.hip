@@ -458,6 +458,207 @@ yy_status launch_batched(hipStream_t st, const norm_final_args* A, const int* pr
   return YY_OK;
 }
 
+
+// ---------------------------------------------------------------------------
+// The correction and the normalisation in one pass over x (componentwise h,
+// rows of even length): each wave takes rows of its block in turn, lane l
+// holding the coordinate pairs l + 64 c (c < C) of the row in registers.  The
+// row's log-likelihood term is summed in the order of k_loglik (the same
+// updated log-weight), and its weight enters running sums relative to the
+// wave's largest updated log-weight so far (rescaled when that grows).  Per
+// block: its largest log-weight m_b, sum_i e^(l_i - m_b), sum_i e^(2(l_i - m_b))
+// and sum_i e^(l_i - m_b) x_i, to part[b][3 + r].
+template <int C>
+__global__ void __launch_bounds__(kBlock) k_ln_partials(int64_t n, int32_t r, int64_t rows, int32_t obs,
+                                                        double h_shift, const double* __restrict__ x,
+                                                        const double* __restrict__ dy, double dt, double rho2,
+                                                        double* __restrict__ logw, double* __restrict__ part) {
+  constexpr int W = kBlock / 64;
+  __shared__ double2 sdy[64 * C];
+  __shared__ double red[W][2 * C * 64];
+  __shared__ double sm[W][3];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int P = r >> 1;
+  const double2* d2 = reinterpret_cast<const double2*>(dy);
+  for (int p = threadIdx.x; p < 64 * C; p += kBlock) sdy[p] = p < P ? d2[p] : make_double2(0.0, 0.0);
+  __syncthreads();
+  const int64_t b0 = (int64_t)blockIdx.x * rows;
+  const int64_t b1 = b0 + rows < n ? b0 + rows : n;
+  double acc[2 * C];
+#pragma unroll
+  for (int j = 0; j < 2 * C; ++j) acc[j] = 0.0;
+  double m = -INFINITY, s = 0.0, s2 = 0.0;
+  double2 v[C], vn[C];
+  auto load = [&](int64_t i, double2(&o)[C]) {
+    const double2* x2 = reinterpret_cast<const double2*>(x + (size_t)i * r);
+#pragma unroll
+    for (int c = 0; c < C; ++c) o[c] = lane + 64 * c < P ? x2[lane + 64 * c] : make_double2(0.0, 0.0);
+  };
+  int64_t i = b0 + wv;
+  if (i < b1) load(i, v);
+  for (; i < b1; i += W) {
+    if (i + W < b1) load(i + W, vn);   // the wave's next row, in flight during this one
+    const double li = logw[i];
+    double dot = 0.0, hh = 0.0;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      double h0 = v[c].x, h1 = v[c].y;
+      if (obs == YY_H_CUBE) {
+        const double t0 = h0 - h_shift, t1 = h1 - h_shift;
+        h0 = t0 * t0 * t0;
+        h1 = t1 * t1 * t1;
+      }
+      if (lane + 64 * c >= P) {   // past the row: no term (h(0) need not vanish)
+        h0 = 0.0;
+        h1 = 0.0;
+      }
+      const double2 d = sdy[lane + 64 * c];
+      dot = fma(h0, d.x, dot);
+      hh = fma(h0, h0, hh);
+      dot = fma(h1, d.y, dot);
+      hh = fma(h1, h1, hh);
+    }
+    dot = wave_sum(dot);   // every lane holds the same sums
+    hh = wave_sum(hh);
+    if (li != -INFINITY) {
+      const double l = li + (dot - 0.5 * dt * hh) / rho2;
+      if (lane == 0) logw[i] = l;
+      if (l > m) {
+        const double f = exp(m - l);
+        s *= f;
+        s2 *= f * f;
+#pragma unroll
+        for (int j = 0; j < 2 * C; ++j) acc[j] *= f;
+        m = l;
+      }
+      const double e = exp(l - m);
+      s += e;
+      s2 = fma(e, e, s2);
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        acc[2 * c] = fma(e, v[c].x, acc[2 * c]);
+        acc[2 * c + 1] = fma(e, v[c].y, acc[2 * c + 1]);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) v[c] = vn[c];
+  }
+  // the block's sums relative to its largest log-weight, waves added in order
+  if (lane == 0) sm[wv][0] = m;
+  __syncthreads();
+  double mb = -INFINITY;
+#pragma unroll
+  for (int w = 0; w < W; ++w) mb = fmax(mb, sm[w][0]);
+  const double f = m == -INFINITY ? 0.0 : exp(m - mb);
+#pragma unroll
+  for (int j = 0; j < 2 * C; ++j) red[wv][j * 64 + lane] = acc[j] * f;
+  __syncthreads();
+  if (lane == 0) {
+    sm[wv][1] = s * f;
+    sm[wv][2] = s2 * f * f;
+  }
+  __syncthreads();
+  double* pb = part + (size_t)blockIdx.x * (3 + r);
+  if (threadIdx.x == 0) {
+    double a1 = 0.0, a2 = 0.0;
+    for (int w = 0; w < W; ++w) {
+      a1 += sm[w][1];
+      a2 += sm[w][2];
+    }
+    pb[0] = mb;
+    pb[1] = a1;
+    pb[2] = a2;
+  }
+  for (int e = threadIdx.x; e < 2 * C * 64; e += kBlock) {
+    const int j = e >> 6, l = e & 63;
+    const int k = 2 * (l + 64 * (j >> 1)) + (j & 1);   // coordinate of accumulator j of lane l
+    if (k < r) {
+      double t = 0.0;
+      for (int w = 0; w < W; ++w) t += red[w][e];
+      pb[3 + k] = t;
+    }
+  }
+}
+
+// logZ = M + log Z with M = max_b m_b and Z = sum_b e^(m_b - M) S_b; the ESS is
+// Z^2 / sum_b e^(2(m_b - M)) S2_b.  sc = {logZ, valid, M, Z, then the factors
+// e^(m_b - M) of the nb blocks}.
+__global__ void __launch_bounds__(kBlock) k_ln_logz(int nb, int32_t r, const double* __restrict__ part,
+                                                    double* __restrict__ sc, double* __restrict__ logZ_step,
+                                                    double* __restrict__ logZ_acc, double* __restrict__ ess,
+                                                    uint32_t* __restrict__ flags) {
+  __shared__ double sh[kBlock / 64];
+  const size_t stride = 3 + (size_t)r;
+  double M = -INFINITY;
+  for (int b = threadIdx.x; b < nb; b += kBlock) M = fmax(M, part[b * stride]);
+  M = block_max<kBlock>(M, sh);
+  if (M == -INFINITY) {
+    if (threadIdx.x == 0) {
+      sc[0] = -INFINITY;
+      sc[1] = 0.0;
+      *logZ_step = -INFINITY;
+      atomicOr(flags, YY_FLAG_ALL_ZERO);
+    }
+    return;
+  }
+  double z = 0.0, z2 = 0.0;
+  for (int b = threadIdx.x; b < nb; b += kBlock) {
+    const double g = exp(part[b * stride] - M);
+    sc[4 + b] = g;
+    z = fma(g, part[b * stride + 1], z);
+    z2 = fma(g * g, part[b * stride + 2], z2);
+  }
+  z = block_sum<kBlock>(z, sh);
+  z2 = block_sum<kBlock>(z2, sh);
+  if (threadIdx.x == 0) {
+    const double lz = M + log(z);
+    sc[0] = lz;
+    sc[1] = 1.0;
+    sc[2] = M;
+    sc[3] = z;
+    *logZ_step = lz;
+    *logZ_acc += lz;
+    *ess = z * z / z2;
+  }
+}
+
+// Blocks [0, nfb): mean[k] = sum_b e^(m_b - M) part[b][3 + k] / Z in a fixed
+// order (as k_norm_final); the others: logw -= logZ in place, w = e^logw.
+__global__ void __launch_bounds__(kBlock) k_ln_final(int64_t n, int nb, int32_t r, int nfb,
+                                                     const double* __restrict__ part,
+                                                     const double* __restrict__ sc, double* __restrict__ mean,
+                                                     double* __restrict__ logw, double* __restrict__ w) {
+  __shared__ double smn[kNormFinalParts][kNormFinalK];
+  if (sc[1] == 0.0) return;
+  if ((int)blockIdx.x >= nfb) {
+    const double lz = sc[0];
+    const int64_t nwb = (int64_t)gridDim.x - nfb;
+    for (int64_t i = ((int64_t)blockIdx.x - nfb) * kBlock + threadIdx.x; i < n; i += nwb * kBlock) {
+      const double l = logw[i] - lz;
+      logw[i] = l;
+      if (w) w[i] = exp(l);
+    }
+    return;
+  }
+  const size_t stride = 3 + (size_t)r;
+  const double z = sc[3];
+  const int kk = threadIdx.x % kNormFinalK, pp = threadIdx.x / kNormFinalK;
+  const int k = blockIdx.x * kNormFinalK + kk;
+  double t = 0.0;
+  if (k < r) {
+    // (unrolled so that the loads of 8 partial rows are in flight at once; the additions keep their order)
+#pragma unroll 8
+    for (int b = pp; b < nb; b += kNormFinalParts) t = fma(sc[4 + b], part[b * stride + 3 + k], t);
+  }
+  smn[pp][kk] = t;
+  __syncthreads();
+  if (pp == 0 && k < r) {
+    double u = 0.0;
+    for (int q = 0; q < kNormFinalParts; ++q) u += smn[q][kk];
+    mean[k] = u / z;
+  }
+}
+
 }  // namespace yy
 
 using namespace yy;
@@ -516,5 +717,49 @@ extern "C" yy_status yy_normalise_moments(yy_ctx ctx, int64_t n, int32_t r, cons
     k_norm_cov<<<grid, 256, 0, ctx->stream>>>(n, r, sc, x, wbuf, mean, cov);
     YY_LAUNCH_CHECK("k_norm_cov");
   }
+  return YY_OK;
+}
+
+extern "C" yy_status yy_loglik_normalise(yy_ctx ctx, const yy_model* model, int64_t n, const double* x,
+                                         const double* dy, double dt, double* logw, double* w,
+                                         double* logZ_step, double* logZ_acc, double* mean, double* ess) {
+  if (!ctx) return fail(YY_ERR_ARG, "yy_loglik_normalise: ctx is NULL");
+  yy_status st = validate_model(model);
+  if (st != YY_OK) return st;
+  if (n < 1) return fail(YY_ERR_ARG, "yy_loglik_normalise: n < 1");
+  if (!(dt > 0.0)) return fail(YY_ERR_ARG, "yy_loglik_normalise: dt must be positive");
+  if (!x || !dy || !logw || !logZ_step || !logZ_acc || !mean || !ess)
+    return fail(YY_ERR_ARG, "yy_loglik_normalise: NULL array");
+  const int32_t r = model->r;
+  const bool one_pass = model->obs != YY_H_LINEAR && model->m == r && (r & 1) == 0 && r <= 1024 &&
+                        ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(dy)) & 15) == 0;
+  if (!one_pass) {
+    if ((st = yy_loglik_update(ctx, model, n, x, dy, dt, logw)) != YY_OK) return st;
+    return yy_normalise_moments(ctx, n, r, x, logw, w, logZ_step, logZ_acc, mean, nullptr, ess);
+  }
+  YY_HIP(hipSetDevice(ctx->device));
+  const int nb = norm_blocks(n);
+  const int64_t rows = (n + nb - 1) / nb;
+  if ((st = ctx->red2.ensure(((size_t)nb * (4 + (size_t)r) + 4) * sizeof(double))) != YY_OK) return st;
+  double* part = ctx->red2.as<double>();
+  double* sc = part + (size_t)nb * (3 + r);
+  const int P = r / 2;
+  if (P <= 128) {
+    k_ln_partials<2><<<nb, kBlock, 0, ctx->stream>>>(n, r, rows, model->obs, model->h_shift, x, dy, dt, model->rho2,
+                                                     logw, part);
+  } else if (P <= 256) {
+    k_ln_partials<4><<<nb, kBlock, 0, ctx->stream>>>(n, r, rows, model->obs, model->h_shift, x, dy, dt, model->rho2,
+                                                     logw, part);
+  } else {
+    k_ln_partials<8><<<nb, kBlock, 0, ctx->stream>>>(n, r, rows, model->obs, model->h_shift, x, dy, dt, model->rho2,
+                                                     logw, part);
+  }
+  YY_LAUNCH_CHECK("k_ln_partials");
+  k_ln_logz<<<1, kBlock, 0, ctx->stream>>>(nb, r, part, sc, logZ_step, logZ_acc, ess, ctx->d_flags);
+  YY_LAUNCH_CHECK("k_ln_logz");
+  const int nfb = norm_final_blocks(r);
+  const int nwb = (int)std::min<int64_t>((n + kBlock - 1) / kBlock, 1024);
+  k_ln_final<<<nfb + nwb, kBlock, 0, ctx->stream>>>(n, nb, r, nfb, part, sc, mean, logw, w);
+  YY_LAUNCH_CHECK("k_ln_final");
   return YY_OK;
 }

@@ -22,8 +22,12 @@ from .workloads import Workload
 class GpuFilter:
     def __init__(self, w: Workload, prec: str | None = None, device: int = 0, stream=None,
                  want_cov: bool = False, ess_min: float = 0.0, proposal_params=None, hidden: int = 256,
-                 cover_min: float = 0.95, collect_pairs: bool = False):
+                 cover_min: float = 0.95, collect_pairs: bool = False, one_pass: bool = True):
+        """one_pass: each step's correction and normalisation through yy_loglik_normalise (x read
+        once where it can); False makes the two calls yy_loglik_update and yy_normalise_moments, the
+        sequence the batched step reproduces bit for bit."""
         self.w = w
+        self.one_pass = one_pass
         self.dev = torch.device("cuda", device)
         self.prec = prec or w.precision
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.dev)
@@ -127,8 +131,15 @@ class GpuFilter:
         yy.yy_propagate(self.ctx, self.model, self.scales, self.prec, w.n, self.x, self.version, self.lo,
                         self.hi, w.dt, src, dst)
         self.cur = 1 - self.cur
-        yy.yy_loglik_update(self.ctx, self.model, w.n, self.x, self.dys[k - 1], w.dt, dst)
-        self._normalise(want_cov, acc=self.logZ_acc, row=k - 1)
+        row = k - 1
+        if self.one_pass and not want_cov:
+            yy.yy_loglik_normalise(self.ctx, self.model, w.n, self.x, self.dys[row], w.dt, dst, self.wts,
+                                   self.logZ_hist[row:row + 1], self.logZ_acc, self.hist[row],
+                                   self.ess_hist[row:row + 1])
+            self.mean, self.ess = self.hist[row], self.ess_hist[row:row + 1]
+        else:
+            yy.yy_loglik_update(self.ctx, self.model, w.n, self.x, self.dys[row], w.dt, dst)
+            self._normalise(want_cov, acc=self.logZ_acc, row=row)
         if restart is None:
             restart = bool(w.restart_every) and k % w.restart_every == 0 and k < w.K
         if restart:

@@ -31,7 +31,7 @@ PREC_BY_NAME = {"auto": YY_PREC_AUTO, "fp32": YY_PREC_FP32, "fp32_mfma": YY_PREC
                 "bf16x3g": YY_PREC_BF16X3G, "bf16x3s": YY_PREC_BF16X3S, "bf16x3p": YY_PREC_BF16X3P}
 EXPORTED = ["yy_last_error", "yy_create", "yy_destroy", "yy_set_stream", "yy_get_status",
             "yy_kernel_coefficients", "yy_nodes_sobol", "yy_propagate", "yy_loglik_update",
-            "yy_normalise_moments", "yy_restart", "yy_timing_enable", "yy_timing_read", "yy_screen_count",
+            "yy_normalise_moments", "yy_loglik_normalise", "yy_restart", "yy_timing_enable", "yy_timing_read", "yy_screen_count",
             "yy_proposal_create", "yy_proposal_destroy", "yy_proposal_num_params", "yy_proposal_get_params",
             "yy_proposal_set_params", "yy_proposal_forward", "yy_proposal_train_step", "yy_sample_moments",
             "yy_tune", "yy_batch_create", "yy_batch_destroy", "yy_batch_reset", "yy_batch_step",
@@ -82,6 +82,7 @@ for _name, _args in {
                      _P, _P, _f64, _P, _P],
     "yy_loglik_update": [_P, ctypes.POINTER(yy_model), _i64, _P, _P, _f64, _P],
     "yy_normalise_moments": [_P, _i64, _i32, _P, _P, _P, _P, _P, _P, _P, _P],
+    "yy_loglik_normalise": [_P, ctypes.POINTER(yy_model), _i64, _P, _P, _f64, _P, _P, _P, _P, _P, _P],
     "yy_restart": [_P, _i64, _i32, _P, _P, _P, _P, _P, _i64, ctypes.POINTER(yy_restart_params), _P, _P,
                    _P, _P, _P, _P],
     "yy_proposal_create": [_P, _i32, _i32, _u64, _P, ctypes.POINTER(_P)],
@@ -218,6 +219,16 @@ def yy_loglik_update(ctx, model: Model, n, x, dy, dt, logw):
     _check(_lib.yy_loglik_update(ctx, ctypes.byref(model.c), int(n), _dptr(x, torch.float64, n * model.r, "x"),
                                  _dptr(dy, torch.float64, model.m, "dy"), float(dt),
                                  _dptr(logw, torch.float64, n, "logw")), "yy_loglik_update")
+
+
+def yy_loglik_normalise(ctx, model: Model, n, x, dy, dt, logw, w, logZ_step, logZ_acc, mean, ess):
+    _check(_lib.yy_loglik_normalise(ctx, ctypes.byref(model.c), int(n), _dptr(x, torch.float64, n * model.r, "x"),
+                                    _dptr(dy, torch.float64, model.m, "dy"), float(dt),
+                                    _dptr(logw, torch.float64, n, "logw"), _dptr(w, torch.float64, n, "w"),
+                                    _dptr(logZ_step, torch.float64, 1, "logZ_step"),
+                                    _dptr(logZ_acc, torch.float64, 1, "logZ_acc"),
+                                    _dptr(mean, torch.float64, model.r, "mean"),
+                                    _dptr(ess, torch.float64, 1, "ess")), "yy_loglik_normalise")
 
 
 def yy_normalise_moments(ctx, n, r, x, logw, w, logZ_step, logZ_acc, mean, cov, ess):

@@ -209,6 +209,67 @@ def test_normalise_flags_all_zero(ctx):
     assert host(d["lz"])[0] == -np.inf and host(d["acc"])[0] == 0.0
 
 
+@pytest.mark.parametrize("n,r,obs", [(1, 2, "cube"), (777, 64, "identity"), (3000, 300, "cube"),
+                                     (5001, 1000, "cube"), (700, 33, "cube"), (300, 2048, "identity")])
+def test_loglik_normalise_one_call(ctx, n, r, obs):
+    """yy_loglik_normalise against yy_loglik_update + yy_normalise_moments and against the oracle's
+    two steps (one pass over x for even r up to 1024; the two calls for r = 33 and r = 2048)."""
+    rng = np.random.default_rng(n + r)
+    code = {"identity": 0, "cube": 1}[obs]
+    x = rng.standard_normal((n, r)) * 0.4 + 0.2
+    dy = rng.standard_normal(r) * 0.05
+    lw = rng.standard_normal(n) * 3 - 10.0
+    if n > 10:
+        lw[::9] = -np.inf
+    dt, rho2 = 0.005, 0.09
+    gm = yy.Model(r, r, 0, None, code, None, 0.1, 1.0, rho2)
+    xd, dyd = dev(x.ravel()), dev(dy)
+
+    def run(one):
+        d = {k: torch.zeros(v, dtype=torch.float64, device="cuda") for k, v in
+             dict(w=n, lz=1, acc=1, mean=r, ess=1).items()}
+        d["acc"].fill_(0.5)
+        g = dev(lw)
+        if one:
+            yy.yy_loglik_normalise(ctx, gm, n, xd, dyd, dt, g, d["w"], d["lz"], d["acc"], d["mean"], d["ess"])
+        else:
+            yy.yy_loglik_update(ctx, gm, n, xd, dyd, dt, g)
+            yy.yy_normalise_moments(ctx, n, r, xd, g, d["w"], d["lz"], d["acc"], d["mean"], None, d["ess"])
+        out = {k: host(v) for k, v in d.items()}
+        out["logw"] = host(g)
+        return out
+
+    a, b = run(True), run(False)
+    om = oracle.OModel(r, r, 0, None, code, None, 0.1, 1.0, rho2)
+    o = oracle.normalise_moments(x, oracle.loglik_update(om, x, dy, dt, lw), logZ_acc=0.5, want_cov=False)
+    ref = dict(w=o["w"], lz=[o["logZ_step"]], acc=[o["logZ_acc"]], mean=o["mean"], ess=[o["ess"]], logw=o["logw"])
+    f = np.isfinite(lw)
+    for other in (b, ref):
+        assert np.array_equal(np.isfinite(a["logw"]), f)
+        assert np.allclose(a["logw"][f], np.asarray(other["logw"])[f], rtol=0, atol=1e-12)
+        assert np.allclose(a["w"], other["w"], rtol=1e-11, atol=1e-300)
+        assert abs(a["lz"][0] - other["lz"][0]) < 1e-12
+        assert abs(a["acc"][0] - other["acc"][0]) < 1e-12
+        assert np.allclose(a["mean"], other["mean"], rtol=0, atol=1e-13)
+        assert abs(a["ess"][0] - other["ess"][0]) <= 1e-11 * other["ess"][0]
+    yy.yy_get_status(ctx)
+
+
+def test_loglik_normalise_all_zero(ctx):
+    n, r = 100, 4
+    gm = yy.Model(r, r, 0, None, 1, None, 0.0, 1.0, 0.09)
+    d = {k: torch.zeros(v, dtype=torch.float64, device="cuda") for k, v in dict(lz=1, acc=1, mean=r, ess=1).items()}
+    d["mean"].fill_(7.0)
+    yy.yy_get_status(ctx)
+    g = dev(np.full(n, -np.inf))
+    yy.yy_loglik_normalise(ctx, gm, n, dev(np.zeros(n * r)), dev(np.zeros(r)), 0.01, g, None, d["lz"], d["acc"],
+                           d["mean"], d["ess"])
+    flags, _ = yy.yy_get_status(ctx)
+    assert flags & yy.YY_FLAG_ALL_ZERO
+    assert host(d["lz"])[0] == -np.inf and host(d["acc"])[0] == 0.0
+    assert np.all(host(d["mean"]) == 7.0) and np.all(host(g) == -np.inf)
+
+
 # ---------------------------------------------------------------- resampling / restart
 @pytest.mark.parametrize("n", [1, 255, 256, 4099, 65536])
 def test_resample_bit_exact(ctx, n):
