@@ -304,9 +304,30 @@ __global__ void __launch_bounds__(kBlock) k_prop_checks(int64_t n, int32_t r, co
   // 16-byte accesses to pairs of coordinates when the rows allow it
   const bool pairs = (r & 1) == 0 && ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(box) |
                                        reinterpret_cast<uintptr_t>(mean)) & 15) == 0;
+  // the box and the mean staged in LDS for rows of up to 2 kStagePairs coordinates (every
+  // resampled row reads them all)
+  constexpr int kStagePairs = 512;
+  __shared__ double2 s_c[kStagePairs], s_h[kStagePairs], s_i[kStagePairs], s_m[kStagePairs];
+  const bool staged = pairs && r <= 2 * kStagePairs;
+  if (staged) {
+    for (int p = threadIdx.x; p < r / 2; p += kBlock) {
+      s_c[p] = reinterpret_cast<const double2*>(c)[p];
+      s_h[p] = reinterpret_cast<const double2*>(hw)[p];
+      s_i[p] = reinterpret_cast<const double2*>(isL)[p];
+      s_m[p] = reinterpret_cast<const double2*>(mean)[p];
+    }
+    __syncthreads();
+  }
   for (int64_t t = wave; t < n; t += nwaves) {
     const double* y = x + (size_t)idx[t] * r;
-    if (pairs) {
+    if (staged) {
+      const double2* y2 = reinterpret_cast<const double2*>(y);
+      for (int32_t d = lane; d < r / 2; d += 64) {
+        const double2 yd = y2[d], cd = s_c[d], hd = s_h[d], id = s_i[d], md = s_m[d];
+        coord(yd.x, cd.x, hd.x, id.x, md.x);
+        coord(yd.y, cd.y, hd.y, id.y, md.y);
+      }
+    } else if (pairs) {
       const double2* y2 = reinterpret_cast<const double2*>(y);
       for (int32_t d = lane; d < r / 2; d += 64) {
         const double2 yd = y2[d], cd = reinterpret_cast<const double2*>(c)[d];

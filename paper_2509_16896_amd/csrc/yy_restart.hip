@@ -244,18 +244,32 @@ __device__ __forceinline__ void k_restart_nodes_body(int64_t n, int32_t r, const
                                       ((reinterpret_cast<uintptr_t>(x_new) | reinterpret_cast<uintptr_t>(box_lo) |
                                         reinterpret_cast<uintptr_t>(box_hi) | reinterpret_cast<uintptr_t>(mean)) &
                                        15)) == 0;
+  // the box and the mean staged in LDS for rows of up to 2 kStagePairs coordinates (every
+  // row reads them all; from LDS they leave the vector memory path to the codes and the nodes)
+  constexpr int kStagePairs = 512;
+  __shared__ double2 s_lo[kStagePairs], s_hi[kStagePairs], s_mk[kStagePairs];
+  const double2* lo2 = reinterpret_cast<const double2*>(box_lo);
+  const double2* hi2 = reinterpret_cast<const double2*>(box_hi);
+  const double2* m2 = reinterpret_cast<const double2*>(mean);
+  const bool staged = pairs && r <= 2 * kStagePairs;
+  if (staged) {
+    for (int p = threadIdx.x; p < r / 2; p += blockDim.x) {
+      s_lo[p] = lo2[p];
+      s_hi[p] = hi2[p];
+      s_mk[p] = m2[p];
+    }
+    __syncthreads();
+  }
   for (int64_t i = wave; i < n; i += nwaves) {
     double acc = 0.0;
     int b = 0;
     if (pairs) {
       const uint2* c2 = reinterpret_cast<const uint2*>(codes + (size_t)i * r);
       double2* x2 = reinterpret_cast<double2*>(x_new + (size_t)i * r);
-      const double2* lo2 = reinterpret_cast<const double2*>(box_lo);
-      const double2* hi2 = reinterpret_cast<const double2*>(box_hi);
-      const double2* m2 = reinterpret_cast<const double2*>(mean);
       for (int32_t kk = lane; kk < r / 2; kk += 64) {
         const uint2 cd = c2[kk];
-        const double2 lo = lo2[kk], hi = hi2[kk], mk = m2[kk];
+        const double2 lo = staged ? s_lo[kk] : lo2[kk], hi = staged ? s_hi[kk] : hi2[kk];
+        const double2 mk = staged ? s_mk[kk] : m2[kk];
         double2 xv;
         node(cd.x, lo.x, hi.x, mk.x, xv.x, acc, b);
         node(cd.y, lo.y, hi.y, mk.y, xv.y, acc, b);
