@@ -11,6 +11,7 @@
  *     propagate  (yy_propagate)          multi-scale Gaussian kernel sum
  *     correct    (yy_loglik_update)      h(x).dy - dt/2 |h(x)|^2, scaled by 1/rho2
  *     normalise  (yy_normalise_moments)  logZ, weights, posterior mean/covariance, ESS
+ *     (correct and normalise in one pass over x: yy_loglik_normalise)
  *     restart    (yy_restart)            every few steps, Sec. 6 local restart
  * with nodes from yy_nodes_sobol (Appendix A, Sobol sequence).
  *
