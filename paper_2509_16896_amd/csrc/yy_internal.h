@@ -205,6 +205,7 @@ struct CombineArgs {
   uint32_t* flags;
   unsigned long long* nclamped;
   int* defer;                      // deferred planes: marked complete when the screen flagged a tile
+  int64_t j_per_split;             // sources per split of the matrix-core kernel
 };
 
 // One yy_propagate call split into its phases: begin = node preparation,

@@ -582,15 +582,21 @@ __device__ __forceinline__ void k_combine_body(CombineArgs a, int bx_, int gx_) 
   }
   const double logvol = a.scal[0];
   const double lref = *a.lref;
+  // deferred planes and no tile flagged in this call: every split's state is the self pair's
+  // exponent with sum 1 in the split that holds the self pair and 0 elsewhere, so that split alone
+  // gives the same (max, sum); the split pass writes only it
+  const bool owner_only = a.defer && a.defer[0] == 0;
+  const int p0 = owner_only ? (int)(i / a.j_per_split) : 0;
+  const int p1 = owner_only ? p0 + 1 : a.nsplit;
   double T[YY_MAX_SCALES + 1], sg[YY_MAX_SCALES + 1];
   int nt = 0;
   for (int s = 0; s < a.S; ++s) {
     if (a.sign[s] == 0.0 || lref == -INFINITY) continue;
     float M = -INFINITY;
-    for (int p = 0; p < a.nsplit; ++p) M = fmaxf(M, a.part[((size_t)p * a.S + s) * a.n + i].x);
+    for (int p = p0; p < p1; ++p) M = fmaxf(M, a.part[((size_t)p * a.S + s) * a.n + i].x);
     if (M == -INFINITY) continue;
     double sum = 0.0;
-    for (int p = 0; p < a.nsplit; ++p) {
+    for (int p = p0; p < p1; ++p) {
       const float2 v = a.part[((size_t)p * a.S + s) * a.n + i];
       if (v.x != -INFINITY) sum += (double)v.y * exp2((double)v.x - (double)M);
     }
@@ -904,7 +910,8 @@ yy_status propagate_begin(yy_ctx ctx, const yy_model* model, const yy_scales* sc
   cb.logw_out = logw_out;
   cb.flags = ctx->d_flags;
   cb.nclamped = ctx->d_nclamped;
-  cb.defer = P.deferred ? ctx->d_defer : nullptr;
+  cb.defer = P.deferred && mfma ? ctx->d_defer : nullptr;
+  cb.j_per_split = ex.j_per_split;
   return YY_OK;
 }
 
