@@ -9,29 +9,41 @@ Kalman filter in ``kalman.py``; this module only marshals numpy arrays into it.
 Every function below mirrors one C function; see ``yyo.h`` for the passage of
 the paper each one follows.
 
-Parity status of the oracle's functions (the pins live in
-``tests/test_oracle_*.py``):
+Parity status of the oracle's functions and the tests that pin each one:
 
-* Sobol codes / points -- pinned (van der Corput closed form, Pascal matrix
+* SplitMix64 -- pinned: the published reference outputs for states 0 and
+  1234567 (test_oracle_bruteforce.py::test_splitmix64_published_outputs).
+* Sobol codes / points -- pinned: van der Corput closed form, Pascal matrix
   of the second dimension, scipy's unscrambled Sobol for dimensions 1-2,
-  (0,m,2)-net and dyadic stratification invariants).
-* kernel coefficients -- pinned (the printed alpha, beta, gamma of
-  Theorem thm:2ndorderkernel; exact closed form for scales {1,2,4}).
-* propagation -- pinned (single-source closed form with scipy's Gaussian
-  log-density, linear drift orientation, mass conservation, first-order
-  consistency; Kalman filter limit end to end).
-* log-likelihood update -- pinned (Gaussian likelihood closed form, Ito
-  unbiasedness by Monte Carlo).
-* normalisation / moments -- pinned (numpy weighted average / covariance,
-  shift invariance).
-* resampling -- pinned (systematic-resampling count bounds, monotone
-  ancestors, brute-force search).
-* restart -- pinned (containment, mean of the mapped reference set, prior
-  closed form).
-* learned restart proposal (``proposal.py``, NumPy) -- pinned (GELU against
+  (0,m,2)-net and dyadic stratification invariants (test_oracle_sobol.py).
+* kernel coefficients -- pinned: the printed alpha, beta, gamma of
+  Theorem thm:2ndorderkernel; exact closed form for scales {1,2,4}
+  (test_oracle_coefficients.py).
+* propagation -- pinned: 50-digit linear-domain double sums for n <= 64,
+  r in {1, 3}, one to three signed scales, boundary nodes, -inf weights and
+  clamped rows (test_oracle_bruteforce.py::test_prediction_equals_50_digit_double_sum);
+  linearity in the weights with three signed scales (::test_linearity_...);
+  second-order consistency with scales {1,2,4} and first-order with one
+  (::test_three_scales_are_second_order_consistent,
+  test_oracle_propagate.py::test_first_order_consistency); single-source
+  closed form with scipy's Gaussian log-density, mass conservation
+  (test_oracle_propagate.py); Kalman filter limit end to end
+  (test_oracle_kalman.py).
+* log-likelihood update -- pinned: Gaussian likelihood closed form, Ito
+  unbiasedness by Monte Carlo (test_oracle_update.py).
+* normalisation / moments -- pinned: numpy weighted average / covariance,
+  scipy's logsumexp, shift invariance (test_oracle_update.py).
+* resampling -- pinned: exhaustive search with exact integers
+  (test_oracle_bruteforce.py::test_resampling_equals_exhaustive_search),
+  systematic-resampling count bounds and monotone ancestors
+  (test_oracle_update.py).
+* restart -- pinned: the reference set translated by the estimate and its
+  mean (test_oracle_bruteforce.py::test_restart_translates_the_reference_set),
+  containment and the prior's closed form (test_oracle_update.py).
+* learned restart proposal (``proposal.py``, NumPy) -- pinned: GELU against
   scipy's normal CDF, loss against the brute-force Gaussian log-density of
   samples, backward against finite differences, Adam's closed-form first
-  step, checks against direct counts).
+  step, checks against direct counts (test_oracle_proposal.py).
 """
 from __future__ import annotations
 
