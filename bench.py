@@ -8,11 +8,15 @@ yy_loglik_update, yy_normalise_moments and, every second step, yy_restart with
 its normalisation.  Inputs (nodes, weights, observation increments) are
 resident in HBM before the timed region starts.
 
-Prints one JSON line: steps/s, propagation TFLOP/s (algorithmic 2 n^2 r P per
-step, P = 2 products x.x and x.f for several scales), the roofline of the
-pairwise kernel (timed with HIP events on its own stream), the plain FP32 form
-timed beside it, and the FP64 oracle on a bounded sample of the same step on
-the host cores.
+Prints one JSON line: steps/s; the propagation's matrix-core work per second
+on the work it executes (in the screened forms: the screen's products for
+every pair plus the method's products 2 n^2 r P on the tiles the screen
+keeps, P = 2 products x.x and x.f for several scales); the roofline of the
+pairwise kernel on that basis (timed with HIP events on the library's
+stream) beside the method's own work 2 n^2 r P expressed as the time a dense
+evaluation would take at the matrix-core peak; a second roofline record for
+the split form on every tile (BF16X3G); the plain FP32 form timed beside it;
+and the FP64 oracle on a bounded sample of the same step on the host cores.
 """
 from __future__ import annotations
 
@@ -38,7 +42,22 @@ PRE_K = 64   # coordinates of the partial-distance screen (BF16X3P)
 # (r, n) of the paper's large-scale test (the workloads module holds the same list)
 PAPER_E1 = ((10, 100), (50, 300), (100, 500), (300, 800), (600, 1000), (1000, 2000))
 PAIR_SRC = os.path.join(ROOT, "paper_2509_16896_amd", "csrc", "yy_pair_mfma.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pair_mfma_cubic_r1000_n65536_traffic.md")
+TRAFFIC_FILES = {
+    "bf16x3p": os.path.join(ROOT, "profiles", "k_pair_mfma_cubic_r1000_n65536_traffic.md"),
+    "bf16x3g": os.path.join(ROOT, "profiles", "k_pair_mfma_bf16x3g_cubic_r1000_n65536_traffic.md"),
+}
+DENSE_FORM = "bf16x3g"   # the split form on every tile: the second roofline record
+
+
+def host_cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def log(msg):
@@ -98,10 +117,11 @@ def kernel_source_hash() -> str:
 def recorded_traffic(prec: str):
     """HBM bytes per launch of the pairwise kernel from the committed counter summary, or None
     when the summary is missing, covers another form, or the kernel source changed since."""
-    if not os.path.exists(TRAFFIC_FILE):
+    path = TRAFFIC_FILES.get(prec)
+    if path is None or not os.path.exists(path):
         return None
     vals = {}
-    with open(TRAFFIC_FILE) as fh:
+    with open(path) as fh:
         for line in fh:
             if line.startswith("traffic_") and "=" in line:
                 k, v = line.split("=", 1)
@@ -179,7 +199,8 @@ def cpu_baseline(w, f, k_last, target_s=15.0):
     oracle.normalise_moments(x, lw2, 0.0, want_cov=False)
     t_rest = time.perf_counter() - t0
     t_step = t_rows * (w.n / nrows) + t_rest
-    return dict(value=1.0 / t_step, unit="steps/s", cores=threads, kind="oracle",
+    return dict(value=1.0 / t_step, unit="steps/s", cores=threads, kind="oracle", cpu_model=host_cpu_model(),
+                logical_cpus=os.cpu_count(),
                 sample=f"FP64 oracle: propagation of {nrows} of {w.n} target rows of one step "
                        f"({t_rows:.1f} s, extrapolated to all rows) + full correction/normalisation "
                        f"({t_rest:.2f} s)"), (rows, ref_rows, x, lw, lo, hi)
@@ -295,7 +316,9 @@ def main_batch(args):
         "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_TFLOPS[args.prec],
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS[args.prec], 4), "traffic": None,
                      "kernel": kernel, "kernel_ms": round(kms, 3),
-                     "dense_equivalent_tflops": round(dense / (kms * 1e-3) / 1e12, 2)},
+                     "work_basis": "each run's screen products plus 2 n^2 r P on its flagged tiles"
+                     if args.prec in ("bf16x3s", "bf16x3p") else "2 n^2 r P of every run",
+                     "method_dense_at_peak_ms": round(dense / (PEAK_TFLOPS[args.prec] * 1e12) * 1e3, 4)},
         "eager_steps_per_s": round(steps / t_eager, 2),
         "sequential_single_run_steps_per_s": round(steps / t_seq, 2),
         "tune_s": round(tune_s, 2),
@@ -371,13 +394,12 @@ def main():
         prop_info["used_fraction"] = round(int(f.used_count.item()) / max(f.restarts - 0, 1), 3)
     steps_s = args.steps / elapsed
     avg_kernel_s = (ms / 1e3) / max(launches, 1)
-    # the method's products per second of pairwise time, as if every pair were formed
-    dense_tflops = alg_flops(w) / avg_kernel_s / 1e12
-    prop_tflops = alg_flops(w) * args.steps / elapsed / 1e12
     mfma = args.prec != "fp32"
-    alg, executed = alg_flops(w), alg_flops(w) * EXEC_PER_ALG.get(args.prec, 1.0)
+    method = alg_flops(w)
+    alg, executed = method, method * EXEC_PER_ALG.get(args.prec, 1.0)
     screen = None
     kernel = "k_pair_mfma" if mfma else "k_pair_valu"
+    basis = "2 n^2 r P: the method's products x.x and x.f for every pair"
     if args.prec in ("bf16x3s", "bf16x3p"):
         # the pairwise time is the screen plus the split pass over the flagged tiles
         from paper_2509_16896_amd import yy
@@ -386,28 +408,52 @@ def main():
         alg, executed = screened_work(w, args.prec, flagged, tiles)
         kernel = ("k_pair_prescreen" if args.prec == "bf16x3p" else "k_pair_screen") + \
             ", then k_pair_mfma (split form) on flagged tiles"
+        basis = (f"the screen's x.x over the first {min(PRE_K, w.r)} coordinates for every pair, plus 2 r P "
+                 f"per pair of the flagged tiles ({flagged} of {tiles})" if args.prec == "bf16x3p" else
+                 f"the screen's x.x over all r coordinates for every pair, plus 2 r P per pair of the "
+                 f"flagged tiles ({flagged} of {tiles})")
         log(f"[bench] screen flagged {flagged} of {tiles} tiles for the split form")
     achieved = alg / avg_kernel_s / 1e12
+    peak = PEAK_TFLOPS[args.prec] if mfma else VALU_FP32_PEAK
     log(f"[bench] {steps_s:.3f} steps/s, pairwise kernels {1e3 * avg_kernel_s:.3f} ms per propagation "
-        f"({launches} launches), {achieved:.1f} TFLOP/s algorithmic, {dense_tflops:.1f} dense-equivalent")
-    roofline = {"bound": "mfma" if mfma else "alu", "achieved": round(achieved, 3),
-                "peak": PEAK_TFLOPS[args.prec] if mfma else VALU_FP32_PEAK, "unit": "TFLOP/s"}
+        f"({launches} launches), {achieved:.1f} TFLOP/s on the executed work")
+    roofline = {"bound": "mfma" if mfma else "alu", "achieved": round(achieved, 3), "peak": peak,
+                "unit": "TFLOP/s"}
     roofline["frac"] = round(roofline["achieved"] / roofline["peak"], 4)
     roofline["traffic"] = recorded_traffic(args.prec) if args.workload == "cubic_r1000" else None
+    roofline["work_basis"] = basis
+    roofline["work_flop_per_launch"] = alg
     roofline["kernel"] = kernel
     roofline["kernel_ms"] = round(1e3 * avg_kernel_s, 3)
     if mfma:
         # matrix-core utilisation: executed products (3 BF16 products per split product) / peak
-        roofline["mfma_exec_frac"] = round(executed / avg_kernel_s / 1e12 / roofline["peak"], 4)
-    roofline["dense_equivalent_tflops"] = round(dense_tflops, 2)
+        roofline["mfma_exec_frac"] = round(executed / avg_kernel_s / 1e12 / peak, 4)
+    # the method's work 2 n^2 r P per propagation, every pair formed: a dense evaluation at the peak
+    # needs method / peak; the ratio to the measured time is the method-basis fraction (above 1 when
+    # the screen rules pairs out -- it is no hardware rate)
+    dense_at_peak_ms = method / (peak * 1e12) * 1e3
+    roofline["method_work_flop_per_launch"] = method
+    roofline["method_dense_at_peak_ms"] = round(dense_at_peak_ms, 4)
+    roofline["frac_method_basis"] = round(dense_at_peak_ms / (1e3 * avg_kernel_s), 4)
 
     forms = {}
     if args.other_forms != "none":
         for p in [x for x in args.other_forms.split(",") if x and x != args.prec]:
             g, _, el3, ms3, l3 = run_gpu(w, dys, p, 1, 2)
             kms = ms3 / max(l3, 1)
-            forms[p] = {"kernel_ms": round(kms, 3), "steps_per_s": round(2 / el3, 4),
-                        "tflops_alg": round(alg_flops(w) / (kms * 1e-3) / 1e12, 2)}
+            entry = {"kernel_ms": round(kms, 3), "steps_per_s": round(2 / el3, 4)}
+            if p in ("bf16x3s", "bf16x3p"):
+                from paper_2509_16896_amd import yy
+                fl, tl = yy.yy_screen_count(g.ctx)
+                a3, e3 = screened_work(w, p, fl, tl)
+                entry.update(flagged_tiles=fl, tiles=tl)
+            else:
+                a3, e3 = method, method * EXEC_PER_ALG.get(p, 1.0)
+                entry["method_tflops"] = round(method / (kms * 1e-3) / 1e12, 2)
+                entry["frac_method"] = round(entry["method_tflops"] / PEAK_TFLOPS[p], 4)
+            entry["executed_tflops"] = round(e3 / (kms * 1e-3) / 1e12, 2)
+            entry["mfma_exec_frac"] = round(entry["executed_tflops"] / PEAK_TFLOPS[p], 4)
+            forms[p] = entry
             g.close()
             log(f"[bench] form {p}: pairwise kernel {kms:.2f} ms")
 
@@ -418,6 +464,21 @@ def main():
                 "kernel_ms": round(ms2 / max(l2, 1), 3)}
         g.close()
         log(f"[bench] plain {args.baseline_prec}: {base['steps_per_s']} steps/s")
+    # the same algorithm (every pair formed) against the plain FP32 form: pairwise-time ratios
+    equal_alg = None
+    if base is not None and forms:
+        equal_alg = {p: round(base["kernel_ms"] / forms[p]["kernel_ms"], 3)
+                     for p in ("bf16x3", "bf16x3g", "bf16x1") if p in forms}
+    # second roofline record: the split form on every tile (the method's products for every pair)
+    roofline_dense = None
+    if DENSE_FORM in forms and args.workload == "cubic_r1000":
+        d = forms[DENSE_FORM]
+        roofline_dense = {"bound": "mfma", "achieved": d["method_tflops"], "peak": PEAK_TFLOPS[DENSE_FORM],
+                          "unit": "TFLOP/s", "frac": d["frac_method"],
+                          "traffic": recorded_traffic(DENSE_FORM),
+                          "work_basis": "2 n^2 r P: the method's products x.x and x.f for every pair",
+                          "kernel": "k_pair_mfma (BF16X3G split form, every tile)", "kernel_ms": d["kernel_ms"],
+                          "mfma_exec_frac": d["mfma_exec_frac"]}
 
     cpu = None
     parity = None
@@ -437,11 +498,13 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "r": w.r, "n": w.n, "dt": w.dt, "scales": list(w.scales),
                    "restart_every": w.restart_every, "R": w.R, "precision": args.prec},
-        "propagation_tflops": round(prop_tflops, 3),
+        "propagation_tflops_executed": round(alg * args.steps / elapsed / 1e12, 3),
         "roofline": roofline,
+        "roofline_dense": roofline_dense,
         "screen": screen,
         "plain_fp32": base,
         "vs_plain_fp32": None if base is None else round(steps_s / base["steps_per_s"], 3),
+        "vs_plain_fp32_equal_algorithm_pairwise": equal_alg,
         "other_forms": forms or None,
         "proposal": prop_info,
         "sampled_row_max_rel_err": parity,

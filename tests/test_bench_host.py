@@ -51,9 +51,10 @@ def test_traffic_record_needs_matching_form_and_source(tmp_path, monkeypatch):
     f = tmp_path / "traffic.md"
     f.write_text("traffic_prec = bf16x3p\ntraffic_source_hash = %s\ntraffic_bytes_per_launch = 1.5e+08\n"
                  % bench.kernel_source_hash())
-    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
+    monkeypatch.setattr(bench, "TRAFFIC_FILES", {"bf16x3p": str(f), "bf16x3g": str(f)})
     assert bench.recorded_traffic("bf16x3p") == 1.5e8
     assert bench.recorded_traffic("bf16x3s") is None
+    assert bench.recorded_traffic("bf16x3g") is None     # the record covers another form
     f.write_text("traffic_prec = bf16x3p\ntraffic_source_hash = 0000\ntraffic_bytes_per_launch = 1.5e+08\n")
     assert bench.recorded_traffic("bf16x3p") is None
 
