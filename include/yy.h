@@ -193,6 +193,21 @@ yy_status yy_normalise_moments(yy_ctx ctx, int64_t n, int32_t r, const double* x
                                double* w, double* logZ_step, double* logZ_acc, double* mean,
                                double* cov, double* ess);
 
+/* yy_normalise_moments without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, kernels and results (bit for bit) as
+ * yy_normalise_moments; its per-block partial sums live in a static device
+ * array of (1024 (3 + YY_NOALLOC_MAX_R) + 4) doubles (about 8 MiB), one per
+ * GPU, held until the process ends.  Limits: r <= YY_NOALLOC_MAX_R
+ * (YY_ERR_UNSUPPORTED otherwise, nothing launched); cov requires the caller's
+ * w.  Every call on a GPU shares that GPU's array, so calls on one GPU whose
+ * work overlaps (different streams or threads) race; calls ordered on one
+ * stream do not.  The array is located at yy_create. */
+#define YY_NOALLOC_MAX_R 1024
+yy_status yy_normalise_moments_noalloc(yy_ctx ctx, int64_t n, int32_t r, const double* x, double* logw,
+                                       double* w, double* logZ_step, double* logZ_acc, double* mean,
+                                       double* cov, double* ess);
+
 /* The correction and the normalisation of one step in one call (Sec. 2.2.2
  * steps 3 and 4): the results of yy_loglik_update followed by
  * yy_normalise_moments with cov = NULL.  Where h is componentwise (m = r), r

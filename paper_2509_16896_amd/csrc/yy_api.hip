@@ -242,6 +242,10 @@ yy_status yy_create(yy_ctx* out, int device, void* stream) {
   YY_HIP(hipGetDeviceCount(&count));
   if (device < 0 || device >= count) return fail(YY_ERR_ARG, "yy_create: no such device");
   YY_HIP(hipSetDevice(device));
+  {
+    yy_status st = noalloc_scratch_init(device);
+    if (st != YY_OK) return st;
+  }
   yy_ctx ctx = new (std::nothrow) yy_ctx_s();
   if (!ctx) return fail(YY_ERR_ALLOC, "yy_create: out of host memory");
   ctx->device = device;

@@ -146,6 +146,8 @@ yy_status coefficients_cramer(int32_t S, const double* s, double* c);
 yy_status validate_model(const yy_model* m);
 yy_status timing_begin(yy_ctx ctx);
 yy_status timing_end(yy_ctx ctx);
+// Locates the no-allocation scratch of the current device (yy_update.hip); called by yy_create.
+yy_status noalloc_scratch_init(int device);
 
 // Pairwise kernel launchers (per-(target, scale) partial max/sum in base 2).
 struct PairArgs {

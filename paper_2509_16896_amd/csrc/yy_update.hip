@@ -3,7 +3,9 @@
 // step 4, Sec. 9 normalisation), all in double precision with fixed-order
 // reductions (no floating-point atomics), so repeated calls are bitwise equal.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <string>
 
 #include "yy_common.h"
 #include "yy_internal.h"
@@ -681,22 +683,20 @@ extern "C" yy_status yy_loglik_update(yy_ctx ctx, const yy_model* model, int64_t
   return YY_OK;
 }
 
-extern "C" yy_status yy_normalise_moments(yy_ctx ctx, int64_t n, int32_t r, const double* x,
-                                          double* logw, double* w, double* logZ_step,
-                                          double* logZ_acc, double* mean, double* cov,
-                                          double* ess) {
-  if (!ctx) return fail(YY_ERR_ARG, "yy_normalise_moments: ctx is NULL");
-  if (n < 1) return fail(YY_ERR_ARG, "yy_normalise_moments: n < 1");
-  if (r < 1 || r > 4096) return fail(YY_ERR_ARG, "yy_normalise_moments: r out of range");
-  if (!x || !logw || !logZ_step || !logZ_acc || !ess) return fail(YY_ERR_ARG, "yy_normalise_moments: NULL array");
-  if (!mean && cov) return fail(YY_ERR_ARG, "yy_normalise_moments: cov needs mean");
-  YY_HIP(hipSetDevice(ctx->device));
+namespace yy {
+
+// The normalisation's launch sequence on a scratch area `red` of at least
+// normalise_scratch_doubles(n, r, cov && !w) doubles (arguments checked by the caller).
+static size_t normalise_scratch_doubles(int64_t n, int32_t r, bool own_w) {
+  return (size_t)norm_blocks(n) * (3 + (size_t)r) + 4 + (own_w ? (size_t)n : 0);
+}
+
+static yy_status normalise_launch(yy_ctx ctx, int64_t n, int32_t r, const double* x, double* logw, double* w,
+                                  double* logZ_step, double* logZ_acc, double* mean, double* cov, double* ess,
+                                  double* red) {
   const int nb = norm_blocks(n);
   const int64_t rows = (n + nb - 1) / nb;
-  const size_t need = (size_t)nb * (3 + (size_t)r) + 4 + (cov && !w ? (size_t)n : 0);
-  yy_status st = ctx->red2.ensure(need * sizeof(double));
-  if (st != YY_OK) return st;
-  double* pmax = ctx->red2.as<double>();
+  double* pmax = red;
   double* psum = pmax + nb;
   double* pw2 = psum + nb;
   double* pmean = pw2 + nb;
@@ -718,6 +718,75 @@ extern "C" yy_status yy_normalise_moments(yy_ctx ctx, int64_t n, int32_t r, cons
     YY_LAUNCH_CHECK("k_norm_cov");
   }
   return YY_OK;
+}
+
+static yy_status normalise_check(const char* who, yy_ctx ctx, int64_t n, int32_t r, const double* x,
+                                 const double* logw, const double* logZ_step, const double* logZ_acc,
+                                 const double* mean, const double* cov, const double* ess) {
+  const std::string w(who);
+  if (!ctx) return fail(YY_ERR_ARG, w + ": ctx is NULL");
+  if (n < 1) return fail(YY_ERR_ARG, w + ": n < 1");
+  if (r < 1 || r > 4096) return fail(YY_ERR_ARG, w + ": r out of range");
+  if (!x || !logw || !logZ_step || !logZ_acc || !ess) return fail(YY_ERR_ARG, w + ": NULL array");
+  if (!mean && cov) return fail(YY_ERR_ARG, w + ": cov needs mean");
+  return YY_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Scratch of yy_normalise_moments_noalloc: the normalisation's per-block
+// partial results (maximum, sum, sum of squared weights, weighted coordinate
+// sums) and four scalars, for at most 1024 blocks and r <= YY_NOALLOC_MAX_R.
+// One copy per GPU, held until the process ends.  Host code never passes
+// `scratch` itself to a kernel: it uses the device address that
+// hipGetSymbolAddress returns for the current device (noalloc_scratch_init).
+constexpr size_t kNoallocDoubles = (size_t)1024 * (3 + YY_NOALLOC_MAX_R) + 4;
+static __device__ __align__(256) double scratch[kNoallocDoubles];
+
+constexpr int kNoallocDevices = 64;
+static std::atomic<double*> g_scratch_ptr[kNoallocDevices];
+
+yy_status noalloc_scratch_init(int device) {
+  if (device < 0 || device >= kNoallocDevices) return YY_OK;   // the entry point reports it
+  if (g_scratch_ptr[device].load(std::memory_order_acquire)) return YY_OK;
+  void* p = nullptr;
+  hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p) return hip_fail(e == hipSuccess ? hipErrorInvalidSymbol : e, "hipGetSymbolAddress(scratch)");
+  g_scratch_ptr[device].store(static_cast<double*>(p), std::memory_order_release);
+  return YY_OK;
+}
+
+}  // namespace yy
+
+extern "C" yy_status yy_normalise_moments(yy_ctx ctx, int64_t n, int32_t r, const double* x,
+                                          double* logw, double* w, double* logZ_step,
+                                          double* logZ_acc, double* mean, double* cov,
+                                          double* ess) {
+  yy_status st = normalise_check("yy_normalise_moments", ctx, n, r, x, logw, logZ_step, logZ_acc, mean, cov, ess);
+  if (st != YY_OK) return st;
+  YY_HIP(hipSetDevice(ctx->device));
+  if ((st = ctx->red2.ensure(normalise_scratch_doubles(n, r, cov && !w) * sizeof(double))) != YY_OK) return st;
+  return normalise_launch(ctx, n, r, x, logw, w, logZ_step, logZ_acc, mean, cov, ess, ctx->red2.as<double>());
+}
+
+extern "C" yy_status yy_normalise_moments_noalloc(yy_ctx ctx, int64_t n, int32_t r, const double* x,
+                                                  double* logw, double* w, double* logZ_step,
+                                                  double* logZ_acc, double* mean, double* cov,
+                                                  double* ess) {
+  yy_status st =
+      normalise_check("yy_normalise_moments_noalloc", ctx, n, r, x, logw, logZ_step, logZ_acc, mean, cov, ess);
+  if (st != YY_OK) return st;
+  if (r > YY_NOALLOC_MAX_R)
+    return fail(YY_ERR_UNSUPPORTED, "yy_normalise_moments_noalloc: r = " + std::to_string(r) +
+                                        " exceeds the static scratch's maximum " + std::to_string(YY_NOALLOC_MAX_R));
+  if (cov && !w) return fail(YY_ERR_ARG, "yy_normalise_moments_noalloc: cov needs the caller's w");
+  if (ctx->device < 0 || ctx->device >= kNoallocDevices)
+    return fail(YY_ERR_UNSUPPORTED, "yy_normalise_moments_noalloc: device index beyond the scratch table");
+  double* red = g_scratch_ptr[ctx->device].load(std::memory_order_acquire);
+  if (!red) return fail(YY_ERR_HIP, "yy_normalise_moments_noalloc: static scratch not set up on this device");
+  if (normalise_scratch_doubles(n, r, false) > kNoallocDoubles)
+    return fail(YY_ERR_UNSUPPORTED, "yy_normalise_moments_noalloc: scratch too small");
+  YY_HIP(hipSetDevice(ctx->device));
+  return normalise_launch(ctx, n, r, x, logw, w, logZ_step, logZ_acc, mean, cov, ess, red);
 }
 
 extern "C" yy_status yy_loglik_normalise(yy_ctx ctx, const yy_model* model, int64_t n, const double* x,

@@ -31,7 +31,7 @@ PREC_BY_NAME = {"auto": YY_PREC_AUTO, "fp32": YY_PREC_FP32, "fp32_mfma": YY_PREC
                 "bf16x3g": YY_PREC_BF16X3G, "bf16x3s": YY_PREC_BF16X3S, "bf16x3p": YY_PREC_BF16X3P}
 EXPORTED = ["yy_last_error", "yy_create", "yy_destroy", "yy_set_stream", "yy_get_status",
             "yy_kernel_coefficients", "yy_nodes_sobol", "yy_propagate", "yy_loglik_update",
-            "yy_normalise_moments", "yy_loglik_normalise", "yy_restart", "yy_timing_enable", "yy_timing_read", "yy_screen_count",
+            "yy_normalise_moments", "yy_normalise_moments_noalloc", "yy_loglik_normalise", "yy_restart", "yy_timing_enable", "yy_timing_read", "yy_screen_count",
             "yy_proposal_create", "yy_proposal_destroy", "yy_proposal_num_params", "yy_proposal_get_params",
             "yy_proposal_set_params", "yy_proposal_forward", "yy_proposal_train_step", "yy_sample_moments",
             "yy_tune", "yy_batch_create", "yy_batch_destroy", "yy_batch_reset", "yy_batch_step",
@@ -82,6 +82,7 @@ for _name, _args in {
                      _P, _P, _f64, _P, _P],
     "yy_loglik_update": [_P, ctypes.POINTER(yy_model), _i64, _P, _P, _f64, _P],
     "yy_normalise_moments": [_P, _i64, _i32, _P, _P, _P, _P, _P, _P, _P, _P],
+    "yy_normalise_moments_noalloc": [_P, _i64, _i32, _P, _P, _P, _P, _P, _P, _P, _P],
     "yy_loglik_normalise": [_P, ctypes.POINTER(yy_model), _i64, _P, _P, _f64, _P, _P, _P, _P, _P, _P],
     "yy_restart": [_P, _i64, _i32, _P, _P, _P, _P, _P, _i64, ctypes.POINTER(yy_restart_params), _P, _P,
                    _P, _P, _P, _P],
@@ -238,6 +239,15 @@ def yy_normalise_moments(ctx, n, r, x, logw, w, logZ_step, logZ_acc, mean, cov, 
                                      _dptr(logZ_acc, torch.float64, 1, "logZ_acc"),
                                      _dptr(mean, torch.float64, r, "mean"), _dptr(cov, torch.float64, r * r, "cov"),
                                      _dptr(ess, torch.float64, 1, "ess")), "yy_normalise_moments")
+
+
+def yy_normalise_moments_noalloc(ctx, n, r, x, logw, w, logZ_step, logZ_acc, mean, cov, ess):
+    _check(_lib.yy_normalise_moments_noalloc(
+        ctx, int(n), int(r), _dptr(x, torch.float64, n * r, "x"), _dptr(logw, torch.float64, n, "logw"),
+        _dptr(w, torch.float64, n, "w"), _dptr(logZ_step, torch.float64, 1, "logZ_step"),
+        _dptr(logZ_acc, torch.float64, 1, "logZ_acc"), _dptr(mean, torch.float64, r, "mean"),
+        _dptr(cov, torch.float64, r * r, "cov"), _dptr(ess, torch.float64, 1, "ess")),
+        "yy_normalise_moments_noalloc")
 
 
 def yy_restart(ctx, n, r, codes, x_cur, w, mean, ess, step, R, ess_min, seed, idx, box_lo, box_hi, x_new,
