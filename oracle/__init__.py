@@ -59,6 +59,10 @@ _lib = None
 
 F_ZERO, F_COS, F_LINEAR, F_PAPER_SINMIX = 0, 1, 2, 3
 H_IDENTITY, H_CUBE, H_LINEAR = 0, 1, 2
+FORM_PUSH, FORM_PULL = 0, 1
+DIV_CLOSED, DIV_COMPLEX_STEP = 0, 1
+# eigenvalues of a noise coefficient a = U U^T at or below this fraction of the largest count as zero
+PINV_RTOL = 1e-10
 
 
 def build(force: bool = True) -> str:
@@ -109,6 +113,15 @@ def _load():
     lib.yyo_propagate_rows.argtypes = [ctypes.POINTER(Model), i32, P, P, i64, P, P, P, f64, P, i64, P, P]
     lib.yyo_propagate_rows.restype = i64
     lib.yyo_loglik_update.argtypes = [ctypes.POINTER(Model), i64, P, P, f64, P]
+    lib.yyo_divergence.argtypes = [ctypes.POINTER(Model), P, i32, f64]
+    lib.yyo_divergence.restype = f64
+    lib.yyo_propagate_ex.argtypes = [ctypes.POINTER(Model), ctypes.POINTER(Kernel), i32, P, P, i64, P, P, P, f64,
+                                     P, P]
+    lib.yyo_propagate_ex.restype = i64
+    lib.yyo_propagate_rows_ex.argtypes = [ctypes.POINTER(Model), ctypes.POINTER(Kernel), i32, P, P, i64, P, P, P,
+                                          f64, P, i64, P, P]
+    lib.yyo_propagate_rows_ex.restype = i64
+    lib.yyo_loglik_update_ex.argtypes = [ctypes.POINTER(Model), i64, P, P, f64, P, P]
     lib.yyo_normalise_moments.argtypes = [i64, i32, P, P, P, P, P, P, P, P]
     lib.yyo_normalise_moments.restype = ctypes.c_int
     lib.yyo_resample.argtypes = [i64, P, u64, i64, P]
@@ -124,6 +137,11 @@ def _ptr(a: np.ndarray | None):
 
 def _f64(a) -> np.ndarray:
     return np.ascontiguousarray(a, dtype=np.float64)
+
+
+class Kernel(ctypes.Structure):
+    _fields_ = [("form", ctypes.c_int32), ("div_mode", ctypes.c_int32), ("cs_step", ctypes.c_double),
+                ("apinv", ctypes.c_void_p), ("logdet_a", ctypes.c_double)]
 
 
 class OModel:
@@ -232,6 +250,66 @@ def propagate_rows(model: OModel, s, c, x, lo, hi, dt, logw_in, rows):
                                      _ptr(lo), _ptr(hi), float(dt), _ptr(lw), len(rows), _ptr(rows),
                                      _ptr(out))
     return out, int(ncl)
+
+
+def noise_pinv(U):
+    """Sec. 7: a = U U^T, its eigen-decomposition a = Q diag(lam) Q^T, the pseudo-inverse
+    a^+ = Q diag(1/lam_i for lam_i > 0, else 0) Q^T and log det_+ a = sum of log lam_i over the
+    positive eigenvalues (those above PINV_RTOL times the largest).  Returns (a^+, log det_+ a, rank)."""
+    U = np.atleast_2d(np.asarray(U, dtype=np.float64))
+    a = U @ U.T
+    lam, Q = np.linalg.eigh(0.5 * (a + a.T))
+    pos = lam > PINV_RTOL * max(float(lam.max()), 0.0)
+    inv = np.zeros_like(lam)
+    inv[pos] = 1.0 / lam[pos]
+    return (Q * inv) @ Q.T, float(np.sum(np.log(lam[pos]))), int(pos.sum())
+
+
+def divergence(model: OModel, x, mode: int = DIV_CLOSED, h: float = 1e-20) -> np.ndarray:
+    x = _f64(np.atleast_2d(x))
+    lib = _load()
+    return np.array([lib.yyo_divergence(ctypes.byref(model.c), _ptr(np.ascontiguousarray(x[i])), int(mode),
+                                        float(h)) for i in range(x.shape[0])])
+
+
+def _kernel(form, div_mode, cs_step, apinv, logdet_a):
+    ap = None if apinv is None else _f64(apinv)
+    k = Kernel(int(form), int(div_mode), float(cs_step), _ptr(ap), float(logdet_a))
+    return k, ap
+
+
+def propagate_ex(model: OModel, s, c, x, lo, hi, dt, logw_in, form=FORM_PUSH, div_mode=DIV_CLOSED,
+                 cs_step=1e-20, apinv=None, logdet_a=0.0):
+    """The prediction with the pull form and/or general process noise (a^+, log det_+ a); returns
+    (logw_out, nclamped)."""
+    s, c, x, lo, hi, lw = _f64(s), _f64(c), _f64(x), _f64(lo), _f64(hi), _f64(logw_in)
+    k, keep = _kernel(form, div_mode, cs_step, apinv, logdet_a)
+    n = x.shape[0]
+    out = np.zeros(n)
+    ncl = _load().yyo_propagate_ex(ctypes.byref(model.c), ctypes.byref(k), len(s), _ptr(s), _ptr(c), n, _ptr(x),
+                                   _ptr(lo), _ptr(hi), float(dt), _ptr(lw), _ptr(out))
+    del keep
+    return out, int(ncl)
+
+
+def propagate_rows_ex(model: OModel, s, c, x, lo, hi, dt, logw_in, rows, form=FORM_PUSH, div_mode=DIV_CLOSED,
+                      cs_step=1e-20, apinv=None, logdet_a=0.0):
+    s, c, x, lo, hi, lw = _f64(s), _f64(c), _f64(x), _f64(lo), _f64(hi), _f64(logw_in)
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    k, keep = _kernel(form, div_mode, cs_step, apinv, logdet_a)
+    out = np.zeros(len(rows))
+    ncl = _load().yyo_propagate_rows_ex(ctypes.byref(model.c), ctypes.byref(k), len(s), _ptr(s), _ptr(c),
+                                        x.shape[0], _ptr(x), _ptr(lo), _ptr(hi), float(dt), _ptr(lw), len(rows),
+                                        _ptr(rows), _ptr(out))
+    del keep
+    return out, int(ncl)
+
+
+def loglik_update_ex(model: OModel, x, dy, dt, bpinv, logw) -> np.ndarray:
+    x, dy, bp = _f64(x), _f64(dy), _f64(bpinv)
+    lw = _f64(logw).copy()
+    _load().yyo_loglik_update_ex(ctypes.byref(model.c), x.shape[0], _ptr(x), _ptr(dy), float(dt), _ptr(bp), _ptr(lw))
+    return lw
 
 
 def loglik_update(model: OModel, x, dy, dt, logw) -> np.ndarray:

@@ -8,6 +8,7 @@
  */
 #include "yyo.h"
 
+#include <complex.h>
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -282,15 +283,57 @@ void yyo_obs(const yyo_model* mdl, const double* xi, double* hi) {
 }
 
 /* ------------------------------------------------------------------------- */
-/* Prediction of one target row (Sec. 4.1-4.3 kernel operator in push form,
- * Sec. 9 log-domain prediction).  For scale s the kernel is the Gaussian
- * density N(x_i; x_j + tau_s f(x_j), q tau_s I) with tau_s = dt/s; the
- * quadrature weight of every source is dV = vol(box)/n.                     */
-static double propagate_row(const yyo_model* mdl, int32_t S, const double* s, const double* c,
-                            int64_t n, const double* x, const double* F, const char* bnd,
-                            double logdV, double dt, const double* logw_in, int64_t i,
-                            double* a, int* clamped) {
+/* Divergence of the drift (needed by the pull-form kernel, eq. kernel).      */
+static double complex drift_component_cplx(const yyo_model* mdl, const double* xi, int32_t k, double h) {
+  /* f_k at x + i h e_k: only coordinate k carries the imaginary step */
   int32_t r = mdl->r;
+  double complex z = xi[k] + I * h;
+  if (mdl->drift == YYO_F_ZERO) return 0.0;
+  if (mdl->drift == YYO_F_COS) return ccos(z);
+  if (mdl->drift == YYO_F_PAPER_SINMIX) {
+    const double next = k + 1 < r ? xi[k + 1] : 0.0;
+    return csin(z) * (-0.5 * z + 0.1 * next) + csin(2.0 * z) * (-0.3 * z + 0.3 * next);
+  }
+  double complex acc = 0.0;
+  for (int32_t l = 0; l < r; ++l) acc += mdl->A[(size_t)k * r + l] * (l == k ? z : (double complex)xi[l]);
+  return acc;
+}
+
+double yyo_divergence(const yyo_model* mdl, const double* xi, int32_t mode, double h) {
+  int32_t r = mdl->r;
+  double div = 0.0;
+  for (int32_t k = 0; k < r; ++k) {
+    if (mode == YYO_DIV_COMPLEX_STEP) {
+      div += cimag(drift_component_cplx(mdl, xi, k, h)) / h;
+    } else if (mdl->drift == YYO_F_COS) {
+      div += -sin(xi[k]);
+    } else if (mdl->drift == YYO_F_PAPER_SINMIX) {
+      /* d/dx_k of sin(x_k)(-0.5 x_k + 0.1 x_{k+1}) + sin(2 x_k)(-0.3 x_k + 0.3 x_{k+1}) */
+      const double next = k + 1 < r ? xi[k + 1] : 0.0;
+      div += cos(xi[k]) * (-0.5 * xi[k] + 0.1 * next) - 0.5 * sin(xi[k]) +
+             2.0 * cos(2.0 * xi[k]) * (-0.3 * xi[k] + 0.3 * next) - 0.3 * sin(2.0 * xi[k]);
+    } else if (mdl->drift == YYO_F_LINEAR) {
+      div += mdl->A[(size_t)k * r + k];
+    }
+  }
+  return div;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Prediction of one target row (Sec. 4.1-4.3 kernel operator, Sec. 9 log-domain
+ * prediction).  For scale s the kernel has variance tau_s a (tau_s = dt/s) and
+ * is centred at x_j + tau_s f(x_j) (push form) or, as a function of the
+ * source x_j, at x_i - tau_s f(x_i) with the factor exp(-tau_s div f(x_i))
+ * (pull form, eq. kernel).  The quadrature weight of every source is
+ * dV = vol(box)/n.                                                          */
+static const yyo_kernel kDefaultKernel = {YYO_FORM_PUSH, YYO_DIV_CLOSED, 1e-20, NULL, 0.0};
+
+static double propagate_row(const yyo_model* mdl, const yyo_kernel* kn, int32_t S, const double* s,
+                            const double* c, int64_t n, const double* x, const double* F,
+                            const double* div, const char* bnd, double logdV, double dt,
+                            const double* logw_in, int64_t i, double* a, double* d, int* clamped) {
+  int32_t r = mdl->r;
+  const int pull = kn->form == YYO_FORM_PULL;
   *clamped = 0;
   if (bnd[i]) return -INFINITY;
   double T[17];
@@ -298,7 +341,6 @@ static double propagate_row(const yyo_model* mdl, int32_t S, const double* s, co
   int nt = 0;
   for (int32_t sc = 0; sc < S; ++sc) {
     double tau = dt / s[sc];
-    double var = mdl->q * tau;
     /* LSE over sources (definition of LSE in Sec. 9): max, then sum. */
     double mx = -INFINITY;
     for (int64_t j = 0; j < n; ++j) {
@@ -306,13 +348,26 @@ static double propagate_row(const yyo_model* mdl, int32_t S, const double* s, co
         a[j] = -INFINITY;
         continue;
       }
-      double D = 0.0;
+      /* displacement of the pair: push x_i - x_j - tau f(x_j); pull x_j - x_i + tau f(x_i) */
       for (int32_t k = 0; k < r; ++k) {
-        double d = x[(size_t)i * r + k] - x[(size_t)j * r + k];
-        double e = d - tau * F[(size_t)j * r + k];
-        D += e * e;
+        if (pull)
+          d[k] = (x[(size_t)j * r + k] - x[(size_t)i * r + k]) + tau * F[(size_t)i * r + k];
+        else
+          d[k] = (x[(size_t)i * r + k] - x[(size_t)j * r + k]) - tau * F[(size_t)j * r + k];
       }
-      a[j] = -D / (2.0 * var) + logw_in[j];
+      if (kn->apinv) {
+        double Q = 0.0;   /* d^T a^+ d */
+        for (int32_t k = 0; k < r; ++k) {
+          double row = 0.0;
+          for (int32_t l = 0; l < r; ++l) row += kn->apinv[(size_t)k * r + l] * d[l];
+          Q += d[k] * row;
+        }
+        a[j] = -Q / (2.0 * tau) + logw_in[j];
+      } else {
+        double D = 0.0;   /* |d|^2, variance q tau */
+        for (int32_t k = 0; k < r; ++k) D += d[k] * d[k];
+        a[j] = -D / (2.0 * (mdl->q * tau)) + logw_in[j];
+      }
       if (a[j] > mx) mx = a[j];
     }
     if (mx == -INFINITY || c[sc] == 0.0) continue;
@@ -320,7 +375,10 @@ static double propagate_row(const yyo_model* mdl, int32_t S, const double* s, co
     for (int64_t j = 0; j < n; ++j)
       if (a[j] != -INFINITY) sum += exp(a[j] - mx);
     double L = mx + log(sum);
-    T[nt] = log(fabs(c[sc])) + logdV - 0.5 * r * log(2.0 * M_PI * var) + L;
+    double logconst = kn->apinv ? -0.5 * r * log(2.0 * M_PI * tau) - 0.5 * kn->logdet_a
+                                : -0.5 * r * log(2.0 * M_PI * (mdl->q * tau));
+    if (pull) logconst -= tau * div[i];
+    T[nt] = log(fabs(c[sc])) + logdV + logconst + L;
     sign[nt] = c[sc] > 0 ? 1.0 : -1.0;
     ++nt;
   }
@@ -343,13 +401,16 @@ static double propagate_row(const yyo_model* mdl, int32_t S, const double* s, co
   return Mx + log(acc);
 }
 
-static void propagate_setup(const yyo_model* mdl, int64_t n, const double* x, const double* lo,
-                            const double* hi, double** F, char** bnd, double* logdV) {
+static void propagate_setup(const yyo_model* mdl, const yyo_kernel* kn, int64_t n, const double* x,
+                            const double* lo, const double* hi, double** F, double** div, char** bnd,
+                            double* logdV) {
   int32_t r = mdl->r;
   *F = (double*)malloc(sizeof(double) * (size_t)n * (size_t)r);
-  *bnd = (char*)malloc((size_t)n);
+  *div = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+  *bnd = (char*)malloc((size_t)(n > 0 ? n : 1));
   for (int64_t j = 0; j < n; ++j) {
     yyo_drift(mdl, x + (size_t)j * r, *F + (size_t)j * r);
+    (*div)[j] = kn->form == YYO_FORM_PULL ? yyo_divergence(mdl, x + (size_t)j * r, kn->div_mode, kn->cs_step) : 0.0;
     (*bnd)[j] = (char)yyo_is_boundary(r, x + (size_t)j * r, lo, hi);
   }
   double lv = 0.0;
@@ -357,53 +418,74 @@ static void propagate_setup(const yyo_model* mdl, int64_t n, const double* x, co
   *logdV = lv - log((double)n);
 }
 
-int64_t yyo_propagate(const yyo_model* mdl, int32_t S, const double* s, const double* c, int64_t n,
-                      const double* x, const double* lo, const double* hi, double dt,
-                      const double* logw_in, double* logw_out) {
-  double* F;
+int64_t yyo_propagate_rows_ex(const yyo_model* mdl, const yyo_kernel* kn, int32_t S, const double* s,
+                              const double* c, int64_t n, const double* x, const double* lo,
+                              const double* hi, double dt, const double* logw_in, int64_t nrows,
+                              const int64_t* rows, double* out_rows) {
+  if (!kn) kn = &kDefaultKernel;
+  double *F, *div;
   char* bnd;
   double logdV;
-  propagate_setup(mdl, n, x, lo, hi, &F, &bnd, &logdV);
+  propagate_setup(mdl, kn, n, x, lo, hi, &F, &div, &bnd, &logdV);
   int64_t nclamped = 0;
 #pragma omp parallel reduction(+ : nclamped)
   {
     double* a = (double*)malloc(sizeof(double) * (size_t)n);
-#pragma omp for schedule(dynamic, 16)
-    for (int64_t i = 0; i < n; ++i) {
+    double* d = (double*)malloc(sizeof(double) * (size_t)mdl->r);
+#pragma omp for schedule(dynamic, 1)
+    for (int64_t t = 0; t < nrows; ++t) {
       int cl;
-      logw_out[i] = propagate_row(mdl, S, s, c, n, x, F, bnd, logdV, dt, logw_in, i, a, &cl);
+      out_rows[t] = propagate_row(mdl, kn, S, s, c, n, x, F, div, bnd, logdV, dt, logw_in, rows[t], a, d, &cl);
       nclamped += cl;
     }
     free(a);
+    free(d);
   }
   free(F);
+  free(div);
   free(bnd);
   return nclamped;
+}
+
+int64_t yyo_propagate_ex(const yyo_model* mdl, const yyo_kernel* kn, int32_t S, const double* s,
+                         const double* c, int64_t n, const double* x, const double* lo, const double* hi,
+                         double dt, const double* logw_in, double* logw_out) {
+  if (!kn) kn = &kDefaultKernel;
+  double *F, *div;
+  char* bnd;
+  double logdV;
+  propagate_setup(mdl, kn, n, x, lo, hi, &F, &div, &bnd, &logdV);
+  int64_t nclamped = 0;
+#pragma omp parallel reduction(+ : nclamped)
+  {
+    double* a = (double*)malloc(sizeof(double) * (size_t)n);
+    double* d = (double*)malloc(sizeof(double) * (size_t)mdl->r);
+#pragma omp for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n; ++i) {
+      int cl;
+      logw_out[i] = propagate_row(mdl, kn, S, s, c, n, x, F, div, bnd, logdV, dt, logw_in, i, a, d, &cl);
+      nclamped += cl;
+    }
+    free(a);
+    free(d);
+  }
+  free(F);
+  free(div);
+  free(bnd);
+  return nclamped;
+}
+
+int64_t yyo_propagate(const yyo_model* mdl, int32_t S, const double* s, const double* c, int64_t n,
+                      const double* x, const double* lo, const double* hi, double dt,
+                      const double* logw_in, double* logw_out) {
+  return yyo_propagate_ex(mdl, NULL, S, s, c, n, x, lo, hi, dt, logw_in, logw_out);
 }
 
 int64_t yyo_propagate_rows(const yyo_model* mdl, int32_t S, const double* s, const double* c,
                            int64_t n, const double* x, const double* lo, const double* hi,
                            double dt, const double* logw_in, int64_t nrows, const int64_t* rows,
                            double* out_rows) {
-  double* F;
-  char* bnd;
-  double logdV;
-  propagate_setup(mdl, n, x, lo, hi, &F, &bnd, &logdV);
-  int64_t nclamped = 0;
-#pragma omp parallel reduction(+ : nclamped)
-  {
-    double* a = (double*)malloc(sizeof(double) * (size_t)n);
-#pragma omp for schedule(dynamic, 1)
-    for (int64_t t = 0; t < nrows; ++t) {
-      int cl;
-      out_rows[t] = propagate_row(mdl, S, s, c, n, x, F, bnd, logdV, dt, logw_in, rows[t], a, &cl);
-      nclamped += cl;
-    }
-    free(a);
-  }
-  free(F);
-  free(bnd);
-  return nclamped;
+  return yyo_propagate_rows_ex(mdl, NULL, S, s, c, n, x, lo, hi, dt, logw_in, nrows, rows, out_rows);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -419,6 +501,30 @@ void yyo_loglik_update(const yyo_model* mdl, int64_t n, const double* x, const d
     for (int32_t k = 0; k < mdl->m; ++k) dot += h[k] * dy[k];
     for (int32_t k = 0; k < mdl->m; ++k) hh += h[k] * h[k];
     logw[i] += (dot - 0.5 * dt * hh) / mdl->rho2;
+  }
+  free(h);
+}
+
+/* Online update with observation noise b = V V^T (Table tab:generalformulas):
+ * h^T b^+ dy - dt/2 h^T b^+ h, with the pseudo-inverse b^+ given.            */
+void yyo_loglik_update_ex(const yyo_model* mdl, int64_t n, const double* x, const double* dy, double dt,
+                          const double* bpinv, double* logw) {
+  int32_t m = mdl->m;
+  double* h = (double*)malloc(sizeof(double) * (size_t)m);
+  for (int64_t i = 0; i < n; ++i) {
+    if (logw[i] == -INFINITY) continue;
+    yyo_obs(mdl, x + (size_t)i * mdl->r, h);
+    double lin = 0.0, quad = 0.0;
+    for (int32_t k = 0; k < m; ++k) {
+      double bdy = 0.0, bh = 0.0;
+      for (int32_t l = 0; l < m; ++l) {
+        bdy += bpinv[(size_t)k * m + l] * dy[l];
+        bh += bpinv[(size_t)k * m + l] * h[l];
+      }
+      lin += h[k] * bdy;
+      quad += h[k] * bh;
+    }
+    logw[i] += lin - 0.5 * dt * quad;
   }
   free(h);
 }

@@ -83,6 +83,42 @@ int64_t yyo_propagate_rows(const yyo_model* mdl, int32_t S, const double* s, con
                            int64_t n, const double* x, const double* lo, const double* hi,
                            double dt, const double* logw_in, int64_t nrows, const int64_t* rows,
                            double* out_rows);
+/* ---- kernel options: pull form (Sec. 4.1) and general noise coefficients (Sec. 7) ---- */
+enum { YYO_FORM_PUSH = 0, YYO_FORM_PULL = 1 };
+enum { YYO_DIV_CLOSED = 0, YYO_DIV_COMPLEX_STEP = 1 };
+typedef struct {
+  int32_t form;          /* PUSH: N(x_i; x_j + tau f(x_j), tau a).  PULL: the kernel of Theorem
+                            thm:1storderkernel (eq. kernel) with the noise of Table tab:generalformulas:
+                            K_tau(x_i, x_j) = (2 pi tau)^{-r/2} det(a)^{-1/2}
+                              exp(-|x_j - x_i + tau f(x_i)|^2_{a^+} / (2 tau) - tau div f(x_i)) */
+  int32_t div_mode;      /* PULL: CLOSED (closed-form divergence) or COMPLEX_STEP (Sec. 8) */
+  double cs_step;        /* complex step h of Sec. 8 */
+  const double* apinv;   /* NULL: a = q I.  Else a^+ (row-major r x r), the Moore-Penrose pseudo-inverse of
+                            a = U U^T (its inverse when a is invertible), Sec. 7 */
+  double logdet_a;       /* with apinv: log det_+ a, the log of the product of a's positive eigenvalues */
+} yyo_kernel;
+
+/* Divergence of the drift at xi: the closed form (mode CLOSED) or the complex-step sum
+ * sum_k Im f_k(x + i h e_k) / h of Sec. 8 (mode COMPLEX_STEP). */
+double yyo_divergence(const yyo_model* mdl, const double* xi, int32_t mode, double h);
+
+/* Prediction with the kernel options k (NULL: push form, a = q I, which is yyo_propagate):
+ *   logw_out_i = log( sum_s c_s dV sum_j K_{tau_s}(x_i, x_j) e^{logw_in_j} + c_{S+1} e^{logw_in_i} ),
+ * K the push or pull kernel with variance tau a (a = q I or the given a^+, det_+ a).  The normalising
+ * constant is (2 pi tau)^{-r/2} det_+(a)^{-1/2} in both the invertible and the singular case, as the
+ * table writes it.  Boundary targets and non-positive sums give -inf; returns the clamped rows. */
+int64_t yyo_propagate_ex(const yyo_model* mdl, const yyo_kernel* k, int32_t S, const double* s,
+                         const double* c, int64_t n, const double* x, const double* lo, const double* hi,
+                         double dt, const double* logw_in, double* logw_out);
+int64_t yyo_propagate_rows_ex(const yyo_model* mdl, const yyo_kernel* k, int32_t S, const double* s,
+                              const double* c, int64_t n, const double* x, const double* lo,
+                              const double* hi, double dt, const double* logw_in, int64_t nrows,
+                              const int64_t* rows, double* out_rows);
+/* Correction with observation noise b = V V^T (Table tab:generalformulas, online update):
+ *   logw_i += h(x_i)^T b^+ dy - dt/2 h(x_i)^T b^+ h(x_i),   bpinv = b^+ row-major m x m. */
+void yyo_loglik_update_ex(const yyo_model* mdl, int64_t n, const double* x, const double* dy, double dt,
+                          const double* bpinv, double* logw);
+
 /* Correction: logw_i += (h(x_i).dy - dt/2 |h(x_i)|^2) / rho2. */
 void yyo_loglik_update(const yyo_model* mdl, int64_t n, const double* x, const double* dy,
                        double dt, double* logw);
