@@ -109,11 +109,29 @@ typedef struct {
  *   K = sum_{j<S} c_j K_{dt/s_j} + c_S delta.
  * s: host array of S distinct positive scale divisors (paper: 1, 2, 4, ...).
  * c: host array of S+1 coefficients, or NULL to solve V c = d with the error
- *    exponents mu_k = (k+2)/2 (the paper's mu_1 = 3/2, mu_2 = 2). */
+ *    exponents mu_k = (k+2)/2 (the paper's mu_1 = 3/2, mu_2 = 2).
+ * form: the first-order kernel K_tau.  YY_FORM_PUSH (0): the Gaussian
+ *    N(x_i; x_j + tau f(x_j), tau a) of each source (the transition density of
+ *    an Euler step).  YY_FORM_PULL (1): the kernel of Theorem
+ *    thm:1storderkernel (eq. kernel, Table tab:generalformulas),
+ *    (2 pi tau)^{-r/2} det(a)^{-1/2} exp(-|x_j - x_i + tau f(x_i)|^2_{a^-1} / (2 tau)
+ *    - tau div f(x_i)): centred, as a function of the source, at
+ *    x_i - tau f(x_i), with the divergence of f at the target.  Both are first
+ *    order consistent; the screened forms (BF16X3S, BF16X3P) and the batched
+ *    step are push-form only (YY_ERR_UNSUPPORTED).
+ * div: pull form: YY_DIV_CLOSED (0) the closed form of the drift's divergence,
+ *    YY_DIV_COMPLEX_STEP (1) the complex-step sum of Sec. 8,
+ *    sum_k Im f_k(x + i h e_k) / h with h = 1e-20. */
+#define YY_FORM_PUSH 0
+#define YY_FORM_PULL 1
+#define YY_DIV_CLOSED 0
+#define YY_DIV_COMPLEX_STEP 1
 typedef struct {
   int32_t S;          /* 1 <= S <= YY_MAX_SCALES */
   const double* s;    /* host [S] */
   const double* c;    /* host [S+1] or NULL */
+  int32_t form;       /* YY_FORM_PUSH or YY_FORM_PULL */
+  int32_t div;        /* YY_DIV_CLOSED or YY_DIV_COMPLEX_STEP (pull form) */
 } yy_scales;
 
 /* Solves V c = d of Sec. 4.3.3 on the host (Cramer's rule, as the paper

@@ -10,8 +10,8 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import (OModel, codes_to_points, is_boundary, kernel_coefficients, loglik_update,
-               normalise_moments, propagate, resample, restart_nodes, sobol_codes)
+from . import (DIV_CLOSED, FORM_PUSH, OModel, codes_to_points, is_boundary, kernel_coefficients, loglik_update,
+               loglik_update_ex, normalise_moments, propagate_ex, resample, restart_nodes, sobol_codes)
 
 
 def model_of(w) -> OModel:
@@ -28,8 +28,13 @@ def initial_state(w, codes):
     return lo, hi, x, lw
 
 
-def run_filter(w, dys, steps=None, codes=None, want_cov=False):
-    """Returns dict with per-step means, logZ, ESS, resample indices and the final state."""
+def run_filter(w, dys, steps=None, codes=None, want_cov=False, form=FORM_PUSH, div_mode=DIV_CLOSED, apinv=None,
+               logdet_a=0.0, bpinv=None):
+    """Returns dict with per-step means, logZ, ESS, resample indices and the final state.
+
+    form / div_mode: the first-order kernel (push form, or the pull form of eq. kernel with its
+    divergence); apinv, logdet_a: general process noise (a^+, log det_+ a; default a = q I);
+    bpinv: general observation noise b^+ (default b = rho2 I)."""
     model = model_of(w)
     K = w.K if steps is None else steps
     s = np.asarray(w.scales, dtype=np.float64)
@@ -42,8 +47,12 @@ def run_filter(w, dys, steps=None, codes=None, want_cov=False):
     logZ_acc = 0.0
     means, logZs, esss, clamps, idxs, covs = [], [], [], [], [], []
     for k in range(1, K + 1):
-        lw, ncl = propagate(model, s, c, x, lo, hi, w.dt, lw)
-        lw = loglik_update(model, x, dys[k - 1], w.dt, lw)
+        lw, ncl = propagate_ex(model, s, c, x, lo, hi, w.dt, lw, form=form, div_mode=div_mode, apinv=apinv,
+                               logdet_a=logdet_a)
+        if bpinv is None:
+            lw = loglik_update(model, x, dys[k - 1], w.dt, lw)
+        else:
+            lw = loglik_update_ex(model, x, dys[k - 1], w.dt, bpinv, lw)
         st = normalise_moments(x, lw, logZ_acc, want_cov=want_cov)
         if st["status"] != 0:
             raise FloatingPointError(f"all weights vanished at step {k}")

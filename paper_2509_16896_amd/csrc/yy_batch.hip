@@ -593,6 +593,7 @@ extern "C" yy_status yy_batch_create(yy_ctx ctx, int32_t nruns, const yy_batch_r
   if (nruns < 1 || nruns > 4096) return fail(YY_ERR_ARG, "yy_batch_create: nruns out of range");
   if (!is_mfma_prec(prec)) return fail(YY_ERR_ARG, "yy_batch_create: prec must be a matrix-core form");
   if (scales->S < 1 || scales->S > 4 || !scales->s) return fail(YY_ERR_ARG, "yy_batch_create: 1 to 4 scales");
+  if (scales->form != YY_FORM_PUSH) return fail(YY_ERR_UNSUPPORTED, "yy_batch_create: the batched step is push-form only");
   if (max_split < 0 || max_split > 256) return fail(YY_ERR_ARG, "yy_batch_create: max_split out of range");
   for (int32_t q = 0; q < nruns; ++q) {
     const yy_batch_run& d = runs[q];

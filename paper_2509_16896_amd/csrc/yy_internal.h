@@ -83,6 +83,8 @@ struct Prepared {
                             // coordinates; then 4 maxima per preparation block
   DevBuf bnd;               // int [n]  1 = boundary node
   DevBuf scal;              // double [6]  log vol(box), max |xc|, max |f|, spare, the maxima over kPreK
+  DevBuf div;               // double [n]  div f(x_i) (pull form), valid for (version, div_mode)
+  int32_t div_mode = -1;    // the divergence computed in div, -1: none
 };
 
 }  // namespace yy
@@ -164,6 +166,7 @@ struct PairArgs {
   const double* scal;
   float2* part;                // [nsplit][S][n]
   int32_t nsplit;
+  int32_t pull;                // pull-form kernel (eq. kernel) instead of the push form
 };
 // Extra inputs of the matrix-core kernel.
 struct MfmaExtra {
@@ -208,6 +211,8 @@ struct CombineArgs {
   unsigned long long* nclamped;
   int* defer;                      // deferred planes: marked complete when the screen flagged a tile
   int64_t j_per_split;             // sources per split of the matrix-core kernel
+  const double* div;               // pull form: div f(x_i) [n]; its factor exp(-tau_s div) per scale, else null
+  double taud[YY_MAX_SCALES];      // tau_s
 };
 
 // One yy_propagate call split into its phases: begin = node preparation,

@@ -25,6 +25,11 @@
 //   BF16X3P: the same with a screen on the first 64 coordinates only
 //            (k_pair_prescreen), whose partial squared distance bounds the
 //            full one from below.
+// Pull form (eq. kernel): the kernel is centred, as a function of the source,
+// at x_i - tau_s f_i, so |x_i - tau_s f_i - x_j|^2 = |p_i^s|^2 + |x_j|^2
+// - 2 (G_ij - tau_s H'_ij) with H' = F X^T: the targets carry the x and f
+// planes, the sources only x, the target bias holds |p_i^s|^2 and the source
+// bias |x_j|^2 (the factor exp(-tau_s div f(x_i)) enters in the combination).
 #include <algorithm>
 #include <cstring>
 #include <type_traits>
@@ -84,6 +89,7 @@ struct MArgs {
   int64_t s_jps;
   int32_t pre_chunks;          // 16-wide K stages of the partial-distance screen
   int* any_flag;               // deferred planes: k_src_bias clears it, the screen sets it on a flagged tile
+  int32_t pull;                // pull-form kernel (biases and the sign of c2 follow it)
 };
 
 // Physical 16-byte chunk of logical chunk c in LDS row `row` (bank-conflict swizzle).
@@ -143,11 +149,13 @@ __device__ inline void fill_rare(const MArgs& a, Rare& rr) {
 }
 
 // Exact base-2 exponent of a pair j != i by FP32 direct differences, summed in
-// k order (zero-padded K adds exact zeros), the vector-ALU kernel's arithmetic.
+// k order (zero-padded K adds exact zeros), the vector-ALU kernel's arithmetic:
+// x_i - x_j - tau f_j (push form) or x_i - x_j - tau f_i (pull form).
+template <bool PULL>
 __device__ inline float exact_pair(const Rare& a, int64_t i, int64_t j, int s) {
   const float4* xi = reinterpret_cast<const float4*>(a.xc + (size_t)i * a.rp);
   const float4* xj = reinterpret_cast<const float4*>(a.xc + (size_t)j * a.rp);
-  const float4* fj = reinterpret_cast<const float4*>(a.f + (size_t)j * a.rp);
+  const float4* fj = reinterpret_cast<const float4*>(a.f + (size_t)(PULL ? i : j) * a.rp);
   const float t = a.tau[s];
   float acc = 0.f;
   const int nq = a.rp >> 2;
@@ -186,6 +194,7 @@ __device__ inline void lse2_push(float& M, float& S, float v) {
 // loop's register allocation does not carry it.  e: the 16 kJB approximate
 // exponents (self pair already -inf); returns the new (max, sum).
 constexpr int kSlab = 16 * kJB;
+template <bool PULL>
 __device__ __noinline__ float2 refine_slab(const Rare* rr, int64_t i, int64_t jbase, int g, int s,
                                            float margin, const float* e, float M, float S) {
   float m = -INFINITY;
@@ -196,7 +205,7 @@ __device__ __noinline__ float2 refine_slab(const Rare* rr, int64_t i, int64_t jb
     if (e[b] >= thr) {
       const int jb = b >> 4, v = b & 15;
       const int64_t j = jbase + jb * 32 + 8 * (v >> 2) + 4 * g + (v & 3);
-      lse2_push(M, S, exact_pair(*rr, i, j, s));
+      lse2_push(M, S, exact_pair<PULL>(*rr, i, j, s));
     } else {
       m2 = fmaxf(m2, e[b]);
     }
@@ -209,7 +218,7 @@ __device__ __noinline__ float2 refine_slab(const Rare* rr, int64_t i, int64_t jb
   return make_float2(Mn, sum);
 }
 
-template <int S>
+template <int S, bool PULL>
 __device__ inline void epilogue_target(const MArgs& a, const Rare* rare, const f32x16_t (&G)[kJB],
                                        const f32x16_t (&H)[kJB], const float* sb, int64_t i, int64_t j0,
                                        int jl0, int g, bool diag, const float (&at)[S],
@@ -246,7 +255,7 @@ __device__ inline void epilogue_target(const MArgs& a, const Rare* rare, const f
         if (jb * 16 + v == bself) x = -INFINITY;
         e[jb * 16 + v] = x;
       }
-    const float2 r = refine_slab(rare, i, j0 + jl0, g, s, margin[s], e, M[s], Ssum[s]);
+    const float2 r = refine_slab<PULL>(rare, i, j0 + jl0, g, s, margin[s], e, M[s], Ssum[s]);
     M[s] = r.x;
     Ssum[s] = r.y;
   }
@@ -317,6 +326,7 @@ __device__ inline void init_targets(const MArgs& a, int64_t i0, int split, float
     const bool valid = i < a.n;
     const double nx = valid ? a.node[i] : 0.0;
     const double nf = valid ? a.node[a.n + i] : 0.0;
+    const double nxf = valid ? a.node[2 * a.n + i] : 0.0;
     const float li = valid ? a.lw2[i] : -INFINITY;
     // The self pair is one of the terms, so its exact exponent bounds the row
     // maximum from below: every partial state starts at it (tiles far below
@@ -326,7 +336,9 @@ __device__ inline void init_targets(const MArgs& a, int64_t i0, int split, float
                        g == (int)((i >> 2) & 1);
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-      at[ib][s] = valid ? (float)(-a.kapd[s] * nx) : -INFINITY;
+      // target term: -kap |x_i|^2 (push), -kap |x_i - tau f_i|^2 (pull)
+      const double t = a.taud[s];
+      at[ib][s] = valid ? (float)(-a.kapd[s] * (a.pull ? nx - 2.0 * t * nxf + t * t * nf : nx)) : -INFINITY;
       M[ib][s] = (valid && li != -INFINITY) ? li - (float)(a.kapd[s] * a.taud[s] * a.taud[s] * nf) : -INFINITY;
       Ssum[ib][s] = (owner && M[ib][s] != -INFINITY) ? 1.f : 0.f;
     }
@@ -369,9 +381,10 @@ __device__ inline void wait_vmcnt() {
 
 // Issues the copies of one K stage: target planes (rows i0..i0+255) then source
 // planes (rows j0..j0+127) of K chunk c.  ESZ = element bytes (2: bf16, 4: fp32).
-// Global planes are [chunk][n_pad][16 elements]; target planes are global
-// planes 0 and 2, source planes 0..3.
-template <int ESZ, int NTP, int NSP>
+// Global planes are [chunk][n_pad][16 elements] (hi(x), hi(f), lo(x), lo(f));
+// push form: target planes are global planes 0 and 2, source planes 0..3; pull
+// form the other way round.
+template <int ESZ, int NTP, int NSP, bool PULL = false>
 __device__ inline void issue_stage(const unsigned char* gb, uint64_t plane_bytes, int64_t n_pad,
                                    uint32_t stage_lds, int c, int64_t i0, int64_t j0, int wave, int lane) {
   constexpr int ROWB = kKC * ESZ;              // bytes per row per stage
@@ -391,12 +404,12 @@ __device__ inline void issue_stage(const unsigned char* gb, uint64_t plane_bytes
     int off;
     if (q < NTP * TREG) {
       const int p = q / TREG, rb = (q % TREG) * RPR, row = rb + rl;
-      src = tb + (uint64_t)(2 * p) * plane_bytes + row * ROWB + swz<CPR>(row, pc) * 16;
+      src = tb + (uint64_t)(PULL ? p : 2 * p) * plane_bytes + row * ROWB + swz<CPR>(row, pc) * 16;
       off = p * (kMI * ROWB) + rb * ROWB;
     } else {
       const int q2 = q - NTP * TREG;
       const int p = q2 / SREG, rb = (q2 % SREG) * RPR, row = rb + rl;
-      src = sbp + (uint64_t)p * plane_bytes + row * ROWB + swz<CPR>(row, pc) * 16;
+      src = sbp + (uint64_t)(PULL ? 2 * p : p) * plane_bytes + row * ROWB + swz<CPR>(row, pc) * 16;
       off = NTP * kMI * ROWB + p * (kMJ * ROWB) + rb * ROWB;
     }
     dma_1k(src, stage_lds + off);
@@ -504,30 +517,84 @@ __device__ inline void mma_frags(const Frag& f, f32x16_t (&G)[kIB][kJB], f32x16_
     }
 }
 
+// Pull form: the target side carries hi(x), hi(f), lo(x), lo(f) (as many as
+// the variant needs, in that order), the source side hi(x), lo(x).
+struct FragP {
+  bf16x8_t bh[kIB], bfh[kIB], bl[kIB], bfl[kIB], xh[kJB], xl[kJB];
+};
+
+template <int PASSES>
+__device__ inline void load_frags_pull(const unsigned char* base, FragP& f) {
+  constexpr int ROWB = 32;
+  constexpr int NTP = PASSES == 3 ? 4 : PASSES == 2 ? 3 : 2;
+  constexpr int TB = NTP * kMI * ROWB;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wi = wave / kWJ, wj = wave % kWJ, col = lane & 31, g = lane >> 5;
+#pragma unroll
+  for (int ib = 0; ib < kIB; ++ib) {
+    const int row = wi * (32 * kIB) + ib * 32 + col;
+    const int off = row * ROWB + swz<2>(row, g) * 16;
+    f.bh[ib] = *reinterpret_cast<const bf16x8_t*>(base + off);
+    f.bfh[ib] = *reinterpret_cast<const bf16x8_t*>(base + kMI * ROWB + off);
+    if (PASSES >= 2) f.bl[ib] = *reinterpret_cast<const bf16x8_t*>(base + 2 * kMI * ROWB + off);
+    if (PASSES == 3) f.bfl[ib] = *reinterpret_cast<const bf16x8_t*>(base + 3 * kMI * ROWB + off);
+  }
+#pragma unroll
+  for (int jb = 0; jb < kJB; ++jb) {
+    const int row = wj * (32 * kJB) + jb * 32 + col;
+    const int off = TB + row * ROWB + swz<2>(row, g) * 16;
+    f.xh[jb] = *reinterpret_cast<const bf16x8_t*>(base + off);
+    if (PASSES >= 2) f.xl[jb] = *reinterpret_cast<const bf16x8_t*>(base + kMJ * ROWB + off);
+  }
+}
+
+// G = X X^T as in the push form; H'_ij = x_j . f_i (sources x on the A side, target f on the B side)
+template <int PASSES>
+__device__ inline void mma_frags_pull(const FragP& f, f32x16_t (&G)[kIB][kJB], f32x16_t (&H)[kIB][kJB]) {
+#pragma unroll
+  for (int ib = 0; ib < kIB; ++ib)
+#pragma unroll
+    for (int jb = 0; jb < kJB; ++jb) {
+      G[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.xh[jb], f.bh[ib], G[ib][jb], 0, 0, 0);
+      H[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.xh[jb], f.bfh[ib], H[ib][jb], 0, 0, 0);
+      if (PASSES >= 2) {
+        G[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.xl[jb], f.bh[ib], G[ib][jb], 0, 0, 0);
+        G[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.xh[jb], f.bl[ib], G[ib][jb], 0, 0, 0);
+      }
+      if (PASSES == 3) {
+        H[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.xl[jb], f.bfh[ib], H[ib][jb], 0, 0, 0);
+        H[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.xh[jb], f.bfl[ib], H[ib][jb], 0, 0, 0);
+      }
+    }
+}
+
 // FP32: within a 16-wide K stage, lane group g owns k = 8 g + t in K step t
 // (any fixed assignment of k to steps is valid when both operands use it), so
 // a lane reads two consecutive 16-byte chunks of its row.
+template <bool PULL = false>
 __device__ inline void mfma_stage_f32(const unsigned char* base, f32x16_t (&G)[kIB][kJB],
                                       f32x16_t (&H)[kIB][kJB]) {
   constexpr int ROWB = 64;
-  constexpr int TB = kMI * ROWB;
+  constexpr int TB = (PULL ? 2 : 1) * kMI * ROWB;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wi = wave / kWJ, wj = wave % kWJ, col = lane & 31, g = lane >> 5;
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
     const int lc = 2 * g + u;
-    float4 bt[kIB], xs[kJB], fs[kJB];
+    float4 bt[kIB], bf[kIB], xs[kJB], fs[kJB];
 #pragma unroll
     for (int ib = 0; ib < kIB; ++ib) {
       const int row = wi * (32 * kIB) + ib * 32 + col;
-      bt[ib] = *reinterpret_cast<const float4*>(base + row * ROWB + swz<4>(row, lc) * 16);
+      const int off = row * ROWB + swz<4>(row, lc) * 16;
+      bt[ib] = *reinterpret_cast<const float4*>(base + off);
+      if (PULL) bf[ib] = *reinterpret_cast<const float4*>(base + kMI * ROWB + off);
     }
 #pragma unroll
     for (int jb = 0; jb < kJB; ++jb) {
       const int row = wj * (32 * kJB) + jb * 32 + col;
       const int off = TB + row * ROWB + swz<4>(row, lc) * 16;
       xs[jb] = *reinterpret_cast<const float4*>(base + off);
-      fs[jb] = *reinterpret_cast<const float4*>(base + kMJ * ROWB + off);
+      if (!PULL) fs[jb] = *reinterpret_cast<const float4*>(base + kMJ * ROWB + off);
     }
 #pragma unroll
     for (int e = 0; e < 4; ++e)
@@ -536,7 +603,10 @@ __device__ inline void mfma_stage_f32(const unsigned char* base, f32x16_t (&G)[k
 #pragma unroll
         for (int jb = 0; jb < kJB; ++jb) {
           G[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x2f32(xs[jb][e], bt[ib][e], G[ib][jb], 0, 0, 0);
-          H[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x2f32(fs[jb][e], bt[ib][e], H[ib][jb], 0, 0, 0);
+          if (PULL)
+            H[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x2f32(xs[jb][e], bf[ib][e], H[ib][jb], 0, 0, 0);
+          else
+            H[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x2f32(fs[jb][e], bt[ib][e], H[ib][jb], 0, 0, 0);
         }
   }
 }
@@ -549,11 +619,13 @@ __device__ inline void mfma_stage_f32(const unsigned char* base, f32x16_t (&G)[k
 // next LA = NS / SPB - 1 groups are in flight, so the pipeline keeps running
 // across tile boundaries while a tile's epilogue folds its products into the
 // running (max, sum).
-template <int VAR>
+template <int VAR, bool PULL = false>
 struct StageShape {
   static constexpr int ESZ = VAR == 0 ? 4 : 2;                       // element bytes
-  static constexpr int NTP = VAR >= 2 ? 2 : 1;                       // target planes
-  static constexpr int NSP = VAR == 3 ? 4 : VAR == 2 ? 3 : 2;        // source planes
+  static constexpr int XP = VAR >= 2 ? 2 : 1;                        // planes of the side without f
+  static constexpr int FP = VAR == 3 ? 4 : VAR == 2 ? 3 : 2;         // planes of the side with f
+  static constexpr int NTP = PULL ? FP : XP;                         // target planes
+  static constexpr int NSP = PULL ? XP : FP;                         // source planes
   static constexpr int ROWB = kKC * ESZ;
   static constexpr int STAGE = (NTP * kMI + NSP * kMJ) * ROWB;       // bytes per LDS stage
 };
@@ -566,15 +638,16 @@ struct StageShape {
 // row maximum.
 constexpr int kTileWindow = 64;
 
-template <int S, int VAR, int NS, int SPB, bool FLAGGED>
+template <int S, int VAR, int NS, int SPB, bool FLAGGED, bool PULL = false>
 __device__ __forceinline__ void pair_block(const MArgs& a, int tb, int split, unsigned char* smem,
                                            float (*sbuf)[4 * kMJ], Rare& rare, int* tl) {
   static_assert(NS % SPB == 0 && NS / SPB >= 2, "the ring holds at least two groups of stages");
+  static_assert(!(PULL && FLAGGED), "the screened forms are push-form only");
   constexpr int LA = NS / SPB - 1;
-  constexpr int ESZ = StageShape<VAR>::ESZ;
-  constexpr int NTP = StageShape<VAR>::NTP;
-  constexpr int NSP = StageShape<VAR>::NSP;
-  constexpr int STAGE = StageShape<VAR>::STAGE;
+  constexpr int ESZ = StageShape<VAR, PULL>::ESZ;
+  constexpr int NTP = StageShape<VAR, PULL>::NTP;
+  constexpr int NSP = StageShape<VAR, PULL>::NSP;
+  constexpr int STAGE = StageShape<VAR, PULL>::STAGE;
   constexpr int L = STAGE / 1024 / kWaves;     // copies per wave per stage
   static_assert(LA == 1 || L * kWaves * 1024 == STAGE, "deep lookahead needs equal copies per wave");
   const int tid = threadIdx.x, lane = tid & 63;
@@ -665,8 +738,8 @@ __device__ __forceinline__ void pair_block(const MArgs& a, int tb, int split, un
     issue_bias(a, sb_lds, tile_j0(0), wave);
 #pragma unroll
     for (int p = 0; p < LA * SPB; ++p)
-      if (p < Q) issue_stage<ESZ, NTP, NSP>(gb, plane, n_pad, smem_lds + p * STAGE, p % nchunks, i0,
-                                            tile_j0(p / nchunks), wave, lane);
+      if (p < Q) issue_stage<ESZ, NTP, NSP, PULL>(gb, plane, n_pad, smem_lds + p * STAGE, p % nchunks, i0,
+                                                  tile_j0(p / nchunks), wave, lane);
 
     for (int t = 0; t < ntiles; ++t) {
       const int64_t j0 = tile_j0(t);
@@ -687,13 +760,21 @@ __device__ __forceinline__ void pair_block(const MArgs& a, int tb, int split, un
           const int qn = q + LA * SPB + u;
           if (qn < Q) {
             const int tn = qn / nchunks;
-            issue_stage<ESZ, NTP, NSP>(gb, plane, n_pad, smem_lds + (qn % NS) * STAGE, qn - tn * nchunks, i0,
-                                       tile_j0(tn), wave, lane);
+            issue_stage<ESZ, NTP, NSP, PULL>(gb, plane, n_pad, smem_lds + (qn % NS) * STAGE, qn - tn * nchunks,
+                                             i0, tile_j0(tn), wave, lane);
           }
         }
         if (VAR == 0) {
 #pragma unroll
-          for (int u = 0; u < SPB; ++u) mfma_stage_f32(smem + ((q + u) % NS) * STAGE, G, H);
+          for (int u = 0; u < SPB; ++u) mfma_stage_f32<PULL>(smem + ((q + u) % NS) * STAGE, G, H);
+        } else if (PULL) {
+          FragP fr[2];
+          load_frags_pull<VAR>(smem + (q % NS) * STAGE, fr[0]);
+#pragma unroll
+          for (int u = 0; u < SPB; ++u) {
+            if (u + 1 < SPB) load_frags_pull<VAR>(smem + ((q + u + 1) % NS) * STAGE, fr[(u + 1) & 1]);
+            mma_frags_pull<VAR>(fr[u & 1], G, H);
+          }
         } else {
           // fragments of stage u + 1 are read while the burst of stage u runs
           Frag fr[2];
@@ -712,8 +793,8 @@ __device__ __forceinline__ void pair_block(const MArgs& a, int tb, int split, un
         const int64_t i = i0 + wi * (32 * kIB) + ib * 32 + col;
         // keep one target's accumulators in flight at a time (register pressure)
         __builtin_amdgcn_sched_barrier(0);
-        epilogue_target<S>(a, &rare, G[ib], H[ib], sb, i, j0, wj * (32 * kJB), g, diag, at[ib], margin, M[ib],
-                           Ssum[ib]);
+        epilogue_target<S, PULL>(a, &rare, G[ib], H[ib], sb, i, j0, wj * (32 * kJB), g, diag, at[ib], margin,
+                                 M[ib], Ssum[ib]);
       }
       __builtin_amdgcn_sched_barrier(0);
     }
@@ -721,15 +802,15 @@ __device__ __forceinline__ void pair_block(const MArgs& a, int tb, int split, un
   merge_and_store<S>(a, M, Ssum, i0, split, reinterpret_cast<float2*>(smem));
 }
 
-template <int S, int VAR, int NS, int SPB, bool FLAGGED>
+template <int S, int VAR, int NS, int SPB, bool FLAGGED, bool PULL = false>
 __global__ void __launch_bounds__(kNT, 1) k_pair_mfma(MArgs a) {
-  __shared__ __attribute__((aligned(1024))) unsigned char smem[NS * StageShape<VAR>::STAGE];
+  __shared__ __attribute__((aligned(1024))) unsigned char smem[NS * StageShape<VAR, PULL>::STAGE];
   __shared__ __attribute__((aligned(1024))) float sbuf[2][4 * kMJ];
   __shared__ Rare rare;
   __shared__ int tl[FLAGGED ? kTileWindow + 1 : 1];
   int tb, split;
   block_map(a, tb, split);
-  pair_block<S, VAR, NS, SPB, FLAGGED>(a, tb, split, smem, sbuf, rare, tl);
+  pair_block<S, VAR, NS, SPB, FLAGGED, PULL>(a, tb, split, smem, sbuf, rare, tl);
 }
 
 // Many node sets in one launch: block b takes work item items[b] = (set,
@@ -856,6 +937,7 @@ __device__ __forceinline__ void screen_block(const MArgs& a, int tb, int split, 
     const bool valid = i < a.n;
     const double nx = valid ? a.node[i] : 0.0;
     const double nf = valid ? a.node[a.n + i] : 0.0;
+    const double nxf = valid ? a.node[2 * a.n + i] : 0.0;
     const float li = valid ? a.lw2[i] : -INFINITY;
     // hx_i F with 2 kap_s tau_s = log2(e) / q for every s, rounded up
     const double hF = 2.0 * a.kapd[0] * a.taud[0] * sqrt(nx) * F * (1.0 + 0x1p-20);
@@ -1258,7 +1340,8 @@ __global__ void __launch_bounds__(kNT, 1) k_pair_screen_batch(const MArgs* __res
 }
 
 // ---------------------------------------------------------------------------
-// Source biases b_js = lw2_j - kap_s |m_j^s|^2 (FP64 -> FP32), -inf for invalid
+// Source biases b_js = lw2_j - kap_s |m_j^s|^2 (push form; pull form lw2_j -
+// kap_s |x_j|^2) (FP64 -> FP32), -inf for invalid
 // sources: out[s][n_pad]; then the maximum over each 128 consecutive sources,
 // out[S n_pad + s (n_pad / 128) + block] (the screen's coarse bound).  With
 // a.bpre the same over the first kPreK coordinates, to a.bpre in the same
@@ -1277,7 +1360,7 @@ __device__ __forceinline__ void k_src_bias_body(int64_t n, int64_t n_pad, int32_
         const float l = a.lw2[j];
         if (l != -INFINITY) {
           const double t = a.taud[s];
-          const double nm = nd[j] + 2.0 * t * nd[2 * n + j] + t * t * nd[n + j];
+          const double nm = a.pull ? nd[j] : nd[j] + 2.0 * t * nd[2 * n + j] + t * t * nd[n + j];
           v = (float)((double)l - a.kapd[s] * nm);
         }
       }
@@ -1310,6 +1393,7 @@ int64_t pair_mfma_npad(int64_t n) { return ((n + kMI - 1) / kMI) * kMI; }
 
 static MArgs make_args(const PairArgs& pa, int prec, const MfmaExtra& ex) {
   MArgs m{};
+  m.pull = pa.pull;
   m.n = pa.n;
   m.n_pad = ex.n_pad;
   m.r = pa.r;
@@ -1328,7 +1412,8 @@ static MArgs make_args(const PairArgs& pa, int prec, const MfmaExtra& ex) {
     const double kap = ex.kapd[s], tau = ex.taud[s];
     m.kap[s] = (float)kap;
     m.c1[s] = (float)(2.0 * kap);
-    m.c2[s] = (float)(2.0 * kap * tau);
+    // H = X F^T (push) enters with +2 kap tau; H' = F X^T (pull) with -2 kap tau
+    m.c2[s] = (float)((pa.pull ? -2.0 : 2.0) * kap * tau);
     m.tau[s] = (float)tau;
     m.kapd[s] = kap;
     m.taud[s] = tau;
@@ -1391,8 +1476,28 @@ static yy_status launch_batch_s(hipStream_t st, const MArgs* sets, const int4* i
   return YY_OK;
 }
 
+// Pull form: the target side carries the f planes, so the stages are larger
+// (BF16X3 40 KB, BF16X3G 32 KB, BF16X1 20 KB, FP32 40 KB) and the rings shorter.
+template <int S>
+static yy_status launch_pull_s(hipStream_t st, const MArgs& m, int prec, int nblocks) {
+  if (prec == YY_PREC_BF16X3) {
+    k_pair_mfma<S, 3, 2, 1, false, true><<<nblocks, kNT, 0, st>>>(m);
+  } else if (prec == YY_PREC_BF16X3G) {
+    k_pair_mfma<S, 2, 4, 2, false, true><<<nblocks, kNT, 0, st>>>(m);
+  } else if (prec == YY_PREC_BF16X1) {
+    k_pair_mfma<S, 1, 4, 2, false, true><<<nblocks, kNT, 0, st>>>(m);
+  } else if (prec == YY_PREC_FP32_MFMA) {
+    k_pair_mfma<S, 0, 2, 1, false, true><<<nblocks, kNT, 0, st>>>(m);
+  } else {
+    return fail(YY_ERR_UNSUPPORTED, "the pull form has no screened matrix-core form");
+  }
+  YY_LAUNCH_CHECK("k_pair_mfma (pull form)");
+  return YY_OK;
+}
+
 template <int S>
 static yy_status launch_s(hipStream_t st, const MArgs& m, int prec, int nblocks, const DeferredPrep* dp) {
+  if (m.pull) return launch_pull_s<S>(st, m, prec, nblocks);
   if (prec == YY_PREC_BF16X3) {
     k_pair_mfma<S, 3, 4, 2, false><<<nblocks, kNT, 0, st>>>(m);
   } else if (prec == YY_PREC_BF16X3G) {

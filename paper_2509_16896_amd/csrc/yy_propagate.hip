@@ -399,7 +399,9 @@ __global__ void __launch_bounds__(kBlock) k_lw_convert_batch(const lw_convert_ar
 // its source tiles; the 16 threads that share targets merge at the end.
 constexpr int kVI = 64, kVJ = 64;
 
-template <int S, int KC>
+// Push form: |x_i - x_j - tau f_j|^2; pull form: |x_i - tau f_i - x_j|^2 (the
+// f rows of the targets instead of the sources).
+template <int S, int KC, bool PULL>
 __global__ void __launch_bounds__(256) k_pair_valu(PairArgs a, int64_t j_per_split,
                                                    double tau0, double tau1, double tau2, double tau3,
                                                    double tau4, double tau5, double kd0, double kd1,
@@ -449,17 +451,19 @@ __global__ void __launch_bounds__(256) k_pair_valu(PairArgs a, int64_t j_per_spl
         const int row = e / KC, kk = e % KC;
         const int k = k0 + kk;
         const int64_t gi = i0 + row, gj = j0 + row;
-        sxi[kk][row] = (gi < n && k < a.r) ? a.xc[(size_t)gi * a.rp + k] : 0.f;
+        const bool vi = (gi < n && k < a.r);
+        sxi[kk][row] = vi ? a.xc[(size_t)gi * a.rp + k] : 0.f;
         const bool vj = (gj < je && k < a.r);
         sxj[kk][row] = vj ? a.xc[(size_t)gj * a.rp + k] : 0.f;
-        sfj[kk][row] = vj ? a.f[(size_t)gj * a.rp + k] : 0.f;
+        if (PULL) sfj[kk][row] = vi ? a.f[(size_t)gi * a.rp + k] : 0.f;   // the targets' f rows
+        else sfj[kk][row] = vj ? a.f[(size_t)gj * a.rp + k] : 0.f;
       }
       __syncthreads();
 #pragma unroll
       for (int kk = 0; kk < KC; ++kk) {
         const float4 xi = *reinterpret_cast<const float4*>(&sxi[kk][ti * 4]);
         const float4 xj = *reinterpret_cast<const float4*>(&sxj[kk][tj * 4]);
-        const float4 fj = *reinterpret_cast<const float4*>(&sfj[kk][tj * 4]);
+        const float4 fj = *reinterpret_cast<const float4*>(&sfj[kk][(PULL ? ti : tj) * 4]);
         const float xia[4] = {xi.x, xi.y, xi.z, xi.w};
         const float xja[4] = {xj.x, xj.y, xj.z, xj.w};
         const float fja[4] = {fj.x, fj.y, fj.z, fj.w};
@@ -470,7 +474,7 @@ __global__ void __launch_bounds__(256) k_pair_valu(PairArgs a, int64_t j_per_spl
             const float d = xia[p] - xja[q];
 #pragma unroll
             for (int s = 0; s < S; ++s) {
-              const float e = fmaf(-tau[s], fja[q], d);
+              const float e = fmaf(-tau[s], fja[PULL ? p : q], d);
               acc[p][q][s] = fmaf(e, e, acc[p][q][s]);
             }
           }
@@ -541,10 +545,17 @@ static yy_status launch_valu_s(hipStream_t st, const PairArgs& a, const double* 
   const int64_t jtiles = (a.n + kVJ - 1) / kVJ;
   const int64_t per = ((jtiles + a.nsplit - 1) / a.nsplit) * kVJ;
   dim3 grid((unsigned)tiles, (unsigned)a.nsplit);
-#define YY_VALU_LAUNCH(KC)                                                                      \
-  k_pair_valu<S, KC><<<grid, 256, 0, st>>>(a, per, taud[0], taud[1], taud[2], taud[3], taud[4], \
-                                           taud[5], kapd[0], kapd[1], kapd[2], kapd[3], kapd[4], \
-                                           kapd[5])
+#define YY_VALU_LAUNCH(KC)                                                                              \
+  do {                                                                                                  \
+    if (a.pull)                                                                                         \
+      k_pair_valu<S, KC, true><<<grid, 256, 0, st>>>(a, per, taud[0], taud[1], taud[2], taud[3], taud[4], \
+                                                     taud[5], kapd[0], kapd[1], kapd[2], kapd[3], kapd[4], \
+                                                     kapd[5]);                                          \
+    else                                                                                                \
+      k_pair_valu<S, KC, false><<<grid, 256, 0, st>>>(a, per, taud[0], taud[1], taud[2], taud[3], taud[4], \
+                                                      taud[5], kapd[0], kapd[1], kapd[2], kapd[3], kapd[4], \
+                                                      kapd[5]);                                         \
+  } while (0)
   if (a.r <= 2) YY_VALU_LAUNCH(2);
   else if (a.r <= 4) YY_VALU_LAUNCH(4);
   else if (a.r <= 8) YY_VALU_LAUNCH(8);
@@ -565,6 +576,56 @@ static yy_status launch_pair_valu_d(hipStream_t st, const PairArgs& a, const dou
     case 6: return launch_valu_s<6>(st, a, taud, kapd);
   }
   return fail(YY_ERR_ARG, "bad scale count");
+}
+
+// ---------------------------------------------------------------------------
+// Divergence of the drift at every node (the pull-form kernel's factor
+// exp(-tau div f(x_i)), eq. kernel): closed form, or the complex-step sum of
+// Sec. 8, sum_k Im f_k(x + i h e_k) / h, with complex arithmetic on (re, im)
+// pairs: sin(a + i b) = sin a cosh b + i cos a sinh b, cos(a + i b) =
+// cos a cosh b - i sin a sinh b.  One thread per node, FP64.
+struct cplx {
+  double re, im;
+};
+__device__ inline cplx c_mul(cplx u, cplx v) { return {u.re * v.re - u.im * v.im, u.re * v.im + u.im * v.re}; }
+__device__ inline cplx c_sin(cplx z) { return {sin(z.re) * cosh(z.im), cos(z.re) * sinh(z.im)}; }
+__device__ inline cplx c_cos(cplx z) { return {cos(z.re) * cosh(z.im), -sin(z.re) * sinh(z.im)}; }
+
+__global__ void __launch_bounds__(kBlock) k_divergence(int64_t n, int32_t r, int32_t drift,
+                                                       const double* __restrict__ A,
+                                                       const double* __restrict__ x, int32_t mode, double h,
+                                                       double* __restrict__ div) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const double* xi = x + (size_t)i * r;
+  double acc = 0.0;
+  for (int32_t k = 0; k < r; ++k) {
+    const double xk = xi[k], nxt = k + 1 < r ? xi[k + 1] : 0.0;
+    if (drift == YY_F_ZERO) continue;
+    if (mode == YY_DIV_COMPLEX_STEP) {
+      const cplx z = {xk, h};
+      cplx f;
+      if (drift == YY_F_COS) {
+        f = c_cos(z);
+      } else if (drift == YY_F_PAPER_SINMIX) {
+        const cplx z2 = {2.0 * xk, 2.0 * h};
+        const cplx u = c_mul(c_sin(z), cplx{-0.5 * z.re + 0.1 * nxt, -0.5 * z.im});
+        const cplx v = c_mul(c_sin(z2), cplx{-0.3 * z.re + 0.3 * nxt, -0.3 * z.im});
+        f = {u.re + v.re, u.im + v.im};
+      } else {   // linear: only the diagonal entry meets the imaginary step
+        f = {0.0, A[(size_t)k * r + k] * h};
+      }
+      acc += f.im / h;
+    } else if (drift == YY_F_COS) {
+      acc += -sin(xk);
+    } else if (drift == YY_F_PAPER_SINMIX) {
+      acc += cos(xk) * (-0.5 * xk + 0.1 * nxt) - 0.5 * sin(xk) + 2.0 * cos(2.0 * xk) * (-0.3 * xk + 0.3 * nxt) -
+             0.3 * sin(2.0 * xk);
+    } else {
+      acc += A[(size_t)k * r + k];
+    }
+  }
+  div[i] = acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -602,6 +663,7 @@ __device__ __forceinline__ void k_combine_body(CombineArgs a, int bx_, int gx_) 
     }
     const double L = ((double)M + log2(sum)) * kLn2 + lref;
     T[nt] = a.kap[s] + logvol + L;
+    if (a.div) T[nt] -= a.taud[s] * a.div[i];   // pull form: exp(-tau_s div f(x_i))
     sg[nt] = a.sign[s];
     ++nt;
   }
@@ -662,6 +724,7 @@ yy_status prepare_nodes(yy_ctx ctx, const yy_model* m, int64_t n, const double* 
                     P.A == m->A && P.version == version && P.lo == lo && P.hi == hi &&
                     (P.have_bf16 || !want_bf16) && (P.have_f32t || !want_f32t) && (!P.deferred || defer);
   if (same) return YY_OK;
+  P.div_mode = -1;
   const int64_t n_pad = pair_mfma_npad(n);
   yy_status st;
   if ((st = P.xc32.ensure((size_t)n * rp * sizeof(float))) != YY_OK) return st;
@@ -794,6 +857,13 @@ yy_status propagate_begin(yy_ctx ctx, const yy_model* model, const yy_scales* sc
   const int32_t r = model->r;
   if (prec == YY_PREC_AUTO) prec = r < 32 ? YY_PREC_FP32 : YY_PREC_BF16X3;
   const bool mfma = prec != YY_PREC_FP32;
+  if (scales->form != YY_FORM_PUSH && scales->form != YY_FORM_PULL)
+    return fail(YY_ERR_ARG, "yy_propagate: unknown kernel form");
+  const bool pull = scales->form == YY_FORM_PULL;
+  if (pull && scales->div != YY_DIV_CLOSED && scales->div != YY_DIV_COMPLEX_STEP)
+    return fail(YY_ERR_ARG, "yy_propagate: unknown divergence mode");
+  if (pull && (prec == YY_PREC_BF16X3S || prec == YY_PREC_BF16X3P))
+    return fail(YY_ERR_UNSUPPORTED, "yy_propagate: the screened forms are push-form only");
   if (mfma && S > 4) return fail(YY_ERR_UNSUPPORTED, "the matrix-core path supports up to 4 scales");
   plan.prec = prec;
   plan.mfma = mfma;
@@ -803,7 +873,15 @@ yy_status propagate_begin(yy_ctx ctx, const yy_model* model, const yy_scales* sc
                          prec == YY_PREC_BF16X3S || prec == YY_PREC_BF16X3P,
                      prec == YY_PREC_FP32_MFMA, prec, defer_planes);
   if (st != YY_OK) return st;
-  const Prepared& P = ctx->prep;
+  Prepared& P = ctx->prep;
+  if (pull && P.div_mode != scales->div) {
+    // the divergence of f at every node, once per node set and mode
+    if ((st = P.div.ensure((size_t)n * sizeof(double))) != YY_OK) return st;
+    k_divergence<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, ctx->stream>>>(
+        n, r, model->drift, model->A, x, scales->div, 1e-20, P.div.as<double>());
+    YY_LAUNCH_CHECK("k_divergence");
+    P.div_mode = scales->div;
+  }
 
   // (2) source weights relative to their maximum
   const int nparts = (int)std::min<int64_t>((n + kBlock - 1) / kBlock, 1024);
@@ -824,6 +902,7 @@ yy_status propagate_begin(yy_ctx ctx, const yy_model* model, const yy_scales* sc
   a.r = r;
   a.rp = P.rp;
   a.S = S;
+  a.pull = pull ? 1 : 0;
   double taud[6] = {0, 0, 0, 0, 0, 0}, kapd[6] = {0, 0, 0, 0, 0, 0};
   for (int s = 0; s < S; ++s) {
     taud[s] = dt / scales->s[s];
@@ -912,6 +991,8 @@ yy_status propagate_begin(yy_ctx ctx, const yy_model* model, const yy_scales* sc
   cb.nclamped = ctx->d_nclamped;
   cb.defer = P.deferred && mfma ? ctx->d_defer : nullptr;
   cb.j_per_split = ex.j_per_split;
+  cb.div = pull ? P.div.as<double>() : nullptr;
+  for (int s = 0; s < S; ++s) cb.taud[s] = taud[s];
   return YY_OK;
 }
 

@@ -22,10 +22,12 @@ from .workloads import Workload
 class GpuFilter:
     def __init__(self, w: Workload, prec: str | None = None, device: int = 0, stream=None,
                  want_cov: bool = False, ess_min: float = 0.0, proposal_params=None, hidden: int = 256,
-                 cover_min: float = 0.95, collect_pairs: bool = False, one_pass: bool = True):
+                 cover_min: float = 0.95, collect_pairs: bool = False, one_pass: bool = True,
+                 form: str = "push", div: int = 0):
         """one_pass: each step's correction and normalisation through yy_loglik_normalise (x read
         once where it can); False makes the two calls yy_loglik_update and yy_normalise_moments, the
-        sequence the batched step reproduces bit for bit."""
+        sequence the batched step reproduces bit for bit.  form: the first-order kernel, "push" or
+        "pull" (eq. kernel, with the divergence in closed form, div = 0, or by complex step, div = 1)."""
         self.w = w
         self.one_pass = one_pass
         self.dev = torch.device("cuda", device)
@@ -33,7 +35,7 @@ class GpuFilter:
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.dev)
         self.ctx = yy.yy_create(device, self.stream)
         self.model = yy.Model(w.r, w.m, w.drift, w.A, w.obs, w.H, w.h_shift, w.q, w.rho2, device=self.dev)
-        self.scales = yy.Scales(w.scales)
+        self.scales = yy.Scales(w.scales, form=form, div=div)
         n, r = w.n, w.r
         f64 = dict(dtype=torch.float64, device=self.dev)
         self.codes = torch.empty(n * r, dtype=torch.int32, device=self.dev)

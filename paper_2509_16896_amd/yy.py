@@ -54,7 +54,7 @@ class yy_model(ctypes.Structure):
 
 class yy_scales(ctypes.Structure):
     _fields_ = [("S", ctypes.c_int32), ("s", ctypes.POINTER(ctypes.c_double)),
-                ("c", ctypes.POINTER(ctypes.c_double))]
+                ("c", ctypes.POINTER(ctypes.c_double)), ("form", ctypes.c_int32), ("div", ctypes.c_int32)]
 
 
 class yy_restart_params(ctypes.Structure):
@@ -161,11 +161,19 @@ class Model:
         return self.c.m
 
 
+YY_FORM_PUSH, YY_FORM_PULL = 0, 1
+YY_DIV_CLOSED, YY_DIV_COMPLEX_STEP = 0, 1
+FORM_BY_NAME = {"push": YY_FORM_PUSH, "pull": YY_FORM_PULL}
+
+
 class Scales:
-    def __init__(self, s, c=None):
+    """The kernel operator: scale divisors, optional coefficients, the first-order kernel's form
+    ("push" or "pull") and, for the pull form, how the divergence is evaluated."""
+
+    def __init__(self, s, c=None, form="push", div=YY_DIV_CLOSED):
         self._s = (ctypes.c_double * len(s))(*[float(v) for v in s])
         self._c = None if c is None else (ctypes.c_double * (len(s) + 1))(*[float(v) for v in c])
-        self.c = yy_scales(len(s), self._s, self._c)
+        self.c = yy_scales(len(s), self._s, self._c, FORM_BY_NAME.get(form, form), int(div))
 
 
 def yy_kernel_coefficients(s) -> list:
