@@ -93,6 +93,10 @@ typedef enum {
   YY_H_LINEAR = 2    /* h(x) = H x, H device row-major [m x r] */
 } yy_obs;
 
+/* General noise coefficients (Sec. 7, eq. NonlinearFilter_noise, Table tab:generalformulas), created by
+ * yy_noise_create; NULL in the model keeps a = q I and b = rho2 I. */
+typedef struct yy_noise_s* yy_noise;
+
 typedef struct {
   int32_t r;          /* state dimension, 1 <= r <= YY_MAX_R */
   int32_t m;          /* observation dimension */
@@ -101,9 +105,25 @@ typedef struct {
   int32_t obs;        /* yy_obs */
   const double* H;    /* device, used when obs == YY_H_LINEAR */
   double h_shift;
-  double q;           /* process-noise variance (> 0) */
-  double rho2;        /* observation-noise variance (> 0) */
+  double q;           /* process-noise variance (> 0; unused where noise gives a) */
+  double rho2;        /* observation-noise variance (> 0; unused where noise gives b) */
+  yy_noise noise;     /* NULL, or general coefficients a = U U^T and/or b = V V^T */
 } yy_model;
+
+/* General noise coefficients for dx = f dt + U dV, dy = h dt + V dW with constant U (r x r) and V
+ * (m x m): a = U U^T, b = V V^T, invertible or singular.  Following Sec. 7, the kernel's
+ * |.|^2_{a^-1} becomes |.|^2_{a^+} with the Moore-Penrose pseudo-inverse and det a becomes det_+ a
+ * (the product of the positive eigenvalues, those above 1e-10 times the largest); the Gaussian
+ * constant stays (2 pi tau)^{-r/2} det_+(a)^{-1/2} as the table writes it; the correction becomes
+ * h^T b^+ dy - dt/2 h^T b^+ h.  The eigen-decompositions run on the host here, once.  U, V: host
+ * row-major [r*r], [m*m], either may be NULL (that coefficient stays isotropic).  The object
+ * belongs to ctx's device and must outlive every model that points to it; destroy it before the
+ * context.  yy_propagate and yy_loglik_update accept such a model (the batched step does not:
+ * YY_ERR_UNSUPPORTED); yy_loglik_normalise then makes the two calls. */
+yy_status yy_noise_create(yy_ctx ctx, int32_t r, const double* U, int32_t m, const double* V, yy_noise* out);
+yy_status yy_noise_destroy(yy_noise noise);
+/* Ranks of a and b (0 where the coefficient stays isotropic) and log det_+ of each; any pointer may be NULL. */
+yy_status yy_noise_info(yy_noise noise, int32_t* rank_a, double* logdet_a, int32_t* rank_b, double* logdet_b);
 
 /* Multi-time-scale kernel (Sec. 4.3.3, eq. general_kernel):
  *   K = sum_{j<S} c_j K_{dt/s_j} + c_S delta.

@@ -283,6 +283,11 @@ yy_status yy_destroy(yy_ctx ctx) {
   ctx->prep.node.release();
   ctx->prep.bnd.release();
   ctx->prep.scal.release();
+  ctx->prep.div.release();
+  ctx->prep.wtmp.release();
+  ctx->prep.wnodes.release();
+  ctx->prep.wbnd.release();
+  ctx->obsw.release();
   ctx->lw2.release();
   ctx->part.release();
   ctx->red.release();

@@ -599,6 +599,7 @@ extern "C" yy_status yy_batch_create(yy_ctx ctx, int32_t nruns, const yy_batch_r
     const yy_batch_run& d = runs[q];
     yy_status st = validate_model(&d.model);
     if (st != YY_OK) return st;
+    if (d.model.noise) return fail(YY_ERR_UNSUPPORTED, "yy_batch_create: general noise coefficients are single-run only");
     if (d.n < 1 || d.n > ((int64_t)1 << 31)) return fail(YY_ERR_ARG, "yy_batch_create: n out of range");
     if (!(d.dt > 0.0) || !(d.box_half > 0.0) || !(d.R > 0.0)) return fail(YY_ERR_ARG, "yy_batch_create: dt, box, R");
     if (d.K < 1 || d.restart_every < 0 || !d.dys) return fail(YY_ERR_ARG, "yy_batch_create: K, restart, dys");

@@ -17,6 +17,8 @@ constexpr double kBoundaryTol = 1e-12;  // distance to a face that marks a bound
 constexpr double kLog2e = 1.4426950408889634073599246810019;
 constexpr double kLn2 = 0.69314718055994530941723212145818;
 constexpr int kPreK = 64;             // coordinates of the partial-distance screen (BF16X3P)
+constexpr double kNoisePinvRtol = 1e-10;  // eigenvalues of a, b at or below this fraction of the largest are zero
+constexpr int32_t kDriftGiven = 100;  // internal drift code: f(x) read from a precomputed array
 
 // Sets the thread-local error text and returns `st`.
 yy_status fail(yy_status st, const std::string& msg);
@@ -85,6 +87,21 @@ struct Prepared {
   DevBuf scal;              // double [6]  log vol(box), max |xc|, max |f|, spare, the maxima over kPreK
   DevBuf div;               // double [n]  div f(x_i) (pull form), valid for (version, div_mode)
   int32_t div_mode = -1;    // the divergence computed in div, -1: none
+  // general process noise: centred nodes and drift values in the original coordinates, then
+  // their whitened images W x, W f (the pairwise kernels' inputs), and the boundary flags
+  DevBuf wtmp;              // double [2][n][r]
+  DevBuf wnodes;            // double [2][n][k]
+  DevBuf wbnd;              // int [n]
+  const void* noise = nullptr;
+};
+
+// Whitened node set of a model with general process noise (noise_whiten_nodes).
+struct WhiteNodes {
+  const double* x;      // [n][k]  W (x - centre)
+  const double* f;      // [n][k]  W f(x)
+  const int* bnd;       // [n]     boundary flags from the original coordinates and box
+  const double* zeros;  // [>= k]  zero vector (the whitened box centre)
+  int32_t k;
 };
 
 }  // namespace yy
@@ -110,6 +127,7 @@ struct yy_ctx_s {
   yy::DevBuf scan;                    // resampling prefix sums
   yy::DevBuf bsrc;                    // matrix-core source biases
   yy::DevBuf sflags;                  // screen verdicts of the screened split form
+  yy::DevBuf obsw;                    // general observation noise: h(x) rows, W_b h(x) rows, W_b dy
   int64_t sflags_tbs = 0, sflags_jtl = 0;   // their shape at the last screened propagation
   // tuned source-split counts: (rp, n_pad, S, prec) -> nsplit
   struct TuneEntry {
@@ -122,6 +140,16 @@ struct yy_ctx_s {
   bool timing = false;
   std::vector<hipEvent_t> ev_start, ev_stop;
   size_t ev_used = 0;
+};
+
+// General noise coefficients (yy_noise.hip): whitening rows W_a (rank_a x r)
+// and W_b (rank_b x m) with W^T W the pseudo-inverse, and log det_+.
+struct yy_noise_s {
+  yy_ctx ctx = nullptr;
+  int32_t r = 0, m = 0;
+  int32_t rank_a = 0, rank_b = 0;   // 0: isotropic (q I, rho2 I from the model)
+  double logdet_a = 0.0, logdet_b = 0.0;
+  yy::DevBuf Wa, Wb, zeros;
 };
 
 // The learned restart proposal's state (yy_proposal.hip).
@@ -150,6 +178,13 @@ yy_status timing_begin(yy_ctx ctx);
 yy_status timing_end(yy_ctx ctx);
 // Locates the no-allocation scratch of the current device (yy_update.hip); called by yy_create.
 yy_status noalloc_scratch_init(int device);
+// General noise (yy_noise.hip): the whitened node set, and the correction with b^+.
+yy_status noise_whiten_nodes(yy_ctx ctx, const yy_model* m, int64_t n, const double* x, const double* lo,
+                             const double* hi, WhiteNodes& out);
+yy_status noise_loglik(yy_ctx ctx, const yy_model* m, int64_t n, const double* x, const double* dy, double dt,
+                       double* logw);
+inline bool noise_a(const yy_model* m) { return m->noise && m->noise->rank_a > 0; }
+inline bool noise_b(const yy_model* m) { return m->noise && m->noise->rank_b > 0; }
 
 // Pairwise kernel launchers (per-(target, scale) partial max/sum in base 2).
 struct PairArgs {

@@ -47,7 +47,10 @@ __device__ __forceinline__ void k_prepare_body(int64_t n, int64_t n_pad, int32_t
                                                     float* __restrict__ xc32, float* __restrict__ f32,
                                                     uint16_t* __restrict__ bf, float* __restrict__ f32t,
                                                     double* __restrict__ node, int* __restrict__ bnd,
-                                                    int bx_, int gx_) {
+                                                    int bx_, int gx_, const double* __restrict__ fgiven = nullptr,
+                                                    const int* __restrict__ bnd_given = nullptr) {
+  // fgiven: drift values [n][r] when drift == kDriftGiven (a whitened node set); bnd_given: the
+  // boundary flags, when the box test does not apply to these coordinates
   const int lane = threadIdx.x & 63, sub = lane >> 4, kl = lane & 15;
   const int64_t wave = ((int64_t)bx_ * blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gx_ * blockDim.x) >> 6;
@@ -59,7 +62,7 @@ __device__ __forceinline__ void k_prepare_body(int64_t n, int64_t n_pad, int32_t
   // coordinates per step; the linear drift keeps one coordinate per lane.
   const bool pairs = (r & 1) == 0 && drift != YY_F_LINEAR &&
                      ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(lo) |
-                       reinterpret_cast<uintptr_t>(hi)) & 15) == 0;
+                       reinterpret_cast<uintptr_t>(hi) | reinterpret_cast<uintptr_t>(fgiven)) & 15) == 0;
   auto near_box = [](double xv, double l, double h) {
     return (int)((fabs(xv - l) <= kBoundaryTol) || (fabs(h - xv) <= kBoundaryTol));
   };
@@ -91,13 +94,17 @@ __device__ __forceinline__ void k_prepare_body(int64_t n, int64_t n_pad, int32_t
             const double2 h2 = *reinterpret_cast<const double2*>(hi + k);
             xc0 = xv.x - 0.5 * (l2.x + h2.x);
             xc1 = xv.y - 0.5 * (l2.y + h2.y);
-            b |= near_box(xv.x, l2.x, h2.x) | near_box(xv.y, l2.y, h2.y);
+            if (!bnd_given) b |= near_box(xv.x, l2.x, h2.x) | near_box(xv.y, l2.y, h2.y);
             if (drift == YY_F_COS) {
               f0 = cos(xv.x);
               f1 = cos(xv.y);
             } else if (drift == YY_F_PAPER_SINMIX) {
               f0 = sinmix(xv.x, xv.y);
               f1 = sinmix(xv.y, k + 2 < r ? xi[k + 2] : 0.0);
+            } else if (drift == kDriftGiven) {
+              const double2 fv = *reinterpret_cast<const double2*>(fgiven + (size_t)i * r + k);
+              f0 = fv.x;
+              f1 = fv.y;
             }
             sxx = fma(xc0, xc0, sxx);
             sff = fma(f0, f0, sff);
@@ -154,9 +161,11 @@ __device__ __forceinline__ void k_prepare_body(int64_t n, int64_t n_pad, int32_t
           const double xv = xi[k];
           const double c = 0.5 * (lo[k] + hi[k]);
           xcd = xv - c;
-          b |= near_box(xv, lo[k], hi[k]);
+          if (!bnd_given) b |= near_box(xv, lo[k], hi[k]);
           if (drift == YY_F_COS) {
             fd = cos(xv);
+          } else if (drift == kDriftGiven) {
+            fd = fgiven[(size_t)i * r + k];
           } else if (drift == YY_F_LINEAR) {
             const double* Ak = A + (size_t)k * r;
             double acc = 0.0;
@@ -211,6 +220,7 @@ __device__ __forceinline__ void k_prepare_body(int64_t n, int64_t n_pad, int32_t
     pxf = sum16(pxf);
 #pragma unroll
     for (int off = 8; off > 0; off >>= 1) b |= __shfl_xor(b, off, 64);
+    if (bnd_given && real) b = bnd_given[i];
     if (kl == 0 && real) {
       node[i] = sxx;
       node[n + i] = sff;
@@ -250,10 +260,11 @@ __global__ void __launch_bounds__(kBlock, 4) k_prepare(int64_t n, int64_t n_pad,
                                                        float* __restrict__ xc32, float* __restrict__ f32,
                                                        uint16_t* __restrict__ bf, float* __restrict__ f32t,
                                                        double* __restrict__ node, int* __restrict__ bnd,
-                                                       int* __restrict__ defer) {
+                                                       int* __restrict__ defer, const double* __restrict__ fgiven,
+                                                       const int* __restrict__ bnd_given) {
   if (MODE == 1 && blockIdx.x == 0 && threadIdx.x == 0) defer[1] = 0;
   k_prepare_body<MODE>(n, n_pad, r, rp, drift, A, x, lo, hi, xc32, f32, bf, f32t, node, bnd, blockIdx.x,
-                       gridDim.x);
+                       gridDim.x, fgiven, bnd_given);
 }
 
 // The rest of a MODE 1 preparation, after the screen: every block returns at
@@ -718,11 +729,15 @@ yy_status prepare_nodes(yy_ctx ctx, const yy_model* m, int64_t n, const double* 
                         uint64_t version, const double* lo, const double* hi, bool want_bf16,
                         bool want_f32t, int32_t prec, bool defer_planes) {
   Prepared& P = ctx->prep;
-  const int32_t rp = pair_mfma_rp(m->r, prec);
-  const bool defer = defer_planes && prec == YY_PREC_BF16X3P && want_bf16 && !want_f32t;
+  // general process noise: the kernels run on the whitened coordinates W (x - c), W f(x) (k of them)
+  const bool white = noise_a(m);
+  const int32_t rk = white ? m->noise->rank_a : m->r;
+  const int32_t rp = pair_mfma_rp(rk, prec);
+  const bool defer = defer_planes && prec == YY_PREC_BF16X3P && want_bf16 && !want_f32t && !white;
   const bool same = P.valid && P.x == x && P.n == n && P.r == m->r && P.rp == rp && P.drift == m->drift &&
                     P.A == m->A && P.version == version && P.lo == lo && P.hi == hi &&
-                    (P.have_bf16 || !want_bf16) && (P.have_f32t || !want_f32t) && (!P.deferred || defer);
+                    (P.have_bf16 || !want_bf16) && (P.have_f32t || !want_f32t) && (!P.deferred || defer) &&
+                    P.noise == (const void*)(white ? m->noise : nullptr);
   if (same) return YY_OK;
   P.div_mode = -1;
   const int64_t n_pad = pair_mfma_npad(n);
@@ -735,17 +750,25 @@ yy_status prepare_nodes(yy_ctx ctx, const yy_model* m, int64_t n, const double* 
   if ((st = P.node.ensure(((size_t)6 * n + 4 * (size_t)nparts) * sizeof(double))) != YY_OK) return st;
   if ((st = P.bnd.ensure((size_t)n * sizeof(int))) != YY_OK) return st;
   if ((st = P.scal.ensure(8 * sizeof(double))) != YY_OK) return st;
+  WhiteNodes wn{};
+  if (white && (st = noise_whiten_nodes(ctx, m, n, x, lo, hi, wn)) != YY_OK) return st;
+  // the whitened coordinates are centred already: a zero box centre, the boundary flags given
+  const double* px = white ? wn.x : x;
+  const double* plo = white ? wn.zeros : lo;
+  const double* phi = white ? wn.zeros : hi;
+  const int32_t pdrift = white ? kDriftGiven : m->drift;
   if (defer) {
     k_prepare<1><<<(unsigned)nparts, kBlock, 0, ctx->stream>>>(
         n, n_pad, m->r, rp, m->drift, m->A, x, lo, hi, nullptr, nullptr, P.bf.as<uint16_t>(), nullptr,
-        P.node.as<double>(), P.bnd.as<int>(), ctx->d_defer);
+        P.node.as<double>(), P.bnd.as<int>(), ctx->d_defer, nullptr, nullptr);
   } else {
     k_prepare<0><<<(unsigned)nparts, kBlock, 0, ctx->stream>>>(
-        n, n_pad, m->r, rp, m->drift, m->A, x, lo, hi, P.xc32.as<float>(), P.f32.as<float>(),
+        n, n_pad, rk, rp, pdrift, m->A, px, plo, phi, P.xc32.as<float>(), P.f32.as<float>(),
         want_bf16 ? P.bf.as<uint16_t>() : nullptr, want_f32t ? P.f32t.as<float>() : nullptr,
-        P.node.as<double>(), P.bnd.as<int>(), nullptr);
+        P.node.as<double>(), P.bnd.as<int>(), nullptr, white ? wn.f : nullptr, white ? wn.bnd : nullptr);
   }
   YY_LAUNCH_CHECK("k_prepare");
+  // (the box volume from the original box)
   k_prepare_scalars<<<1, kBlock, 0, ctx->stream>>>(n, m->r, nparts, lo, hi, P.node.as<double>(),
                                                    P.scal.as<double>());
   YY_LAUNCH_CHECK("k_prepare_scalars");
@@ -763,6 +786,7 @@ yy_status prepare_nodes(yy_ctx ctx, const yy_model* m, int64_t n, const double* 
   P.have_bf16 = want_bf16;
   P.have_f32t = want_f32t;
   P.deferred = defer;
+  P.noise = white ? m->noise : nullptr;
   P.dp = DeferredPrep{n, n_pad, m->r, rp, m->drift, m->A, x, lo, hi, P.xc32.as<float>(), P.f32.as<float>(),
                       P.bf.as<uint16_t>(), ctx->d_defer};
   return YY_OK;
@@ -778,6 +802,10 @@ static yy_status check_model(const yy_model* m) {
   if (m->obs != YY_H_LINEAR && m->m != m->r) return fail(YY_ERR_ARG, "m must equal r for this h");
   if (m->m < 1) return fail(YY_ERR_ARG, "m must be positive");
   if (!(m->q > 0.0) || !(m->rho2 > 0.0)) return fail(YY_ERR_ARG, "noise variances must be positive");
+  if (m->noise) {
+    if (m->noise->rank_a > 0 && m->noise->r != m->r) return fail(YY_ERR_ARG, "noise: U is not r x r");
+    if (m->noise->rank_b > 0 && m->noise->m != m->m) return fail(YY_ERR_ARG, "noise: V is not m x m");
+  }
   return YY_OK;
 }
 
@@ -898,15 +926,17 @@ yy_status propagate_begin(yy_ctx ctx, const yy_model* model, const yy_scales* sc
   // (3) pairwise partials
   PairArgs& a = plan.a;
   a = PairArgs{};
+  const bool white = noise_a(model);
+  const double qk = white ? 1.0 : model->q;   // the whitened coordinates have unit variance per unit time
   a.n = n;
-  a.r = r;
+  a.r = white ? model->noise->rank_a : r;
   a.rp = P.rp;
   a.S = S;
   a.pull = pull ? 1 : 0;
   double taud[6] = {0, 0, 0, 0, 0, 0}, kapd[6] = {0, 0, 0, 0, 0, 0};
   for (int s = 0; s < S; ++s) {
     taud[s] = dt / scales->s[s];
-    kapd[s] = kLog2e / (2.0 * model->q * taud[s]);
+    kapd[s] = kLog2e / (2.0 * qk * taud[s]);
     a.tau[s] = (float)taud[s];
     a.kap2[s] = (float)kapd[s];
     plan.taud[s] = taud[s];
@@ -975,8 +1005,10 @@ yy_status propagate_begin(yy_ctx ctx, const yy_model* model, const yy_scales* sc
   cb.S = S;
   cb.nsplit = a.nsplit;
   for (int s = 0; s < S; ++s) {
+    // Gaussian constant: (2 pi q tau)^{-r/2}, or (2 pi tau)^{-r/2} det_+(a)^{-1/2} for general noise
     cb.kap[s] = (c[s] != 0.0 ? std::log(std::fabs(c[s])) : 0.0) - std::log((double)n) -
-                0.5 * r * std::log(2.0 * M_PI * model->q * taud[s]);
+                (white ? 0.5 * r * std::log(2.0 * M_PI * taud[s]) + 0.5 * model->noise->logdet_a
+                       : 0.5 * r * std::log(2.0 * M_PI * model->q * taud[s]));
     cb.sign[s] = c[s] > 0 ? 1.0 : (c[s] < 0 ? -1.0 : 0.0);
   }
   cb.sign[S] = c[S] > 0 ? 1.0 : (c[S] < 0 ? -1.0 : 0.0);

@@ -675,6 +675,7 @@ extern "C" yy_status yy_loglik_update(yy_ctx ctx, const yy_model* model, int64_t
   if (n == 0) return YY_OK;
   if (!x || !dy || !logw) return fail(YY_ERR_ARG, "yy_loglik_update: NULL array");
   YY_HIP(hipSetDevice(ctx->device));
+  if (noise_b(model)) return noise_loglik(ctx, model, n, x, dy, dt, logw);   // b = V V^T (Sec. 7)
   int64_t blocks = (n + 3) / 4;
   if (blocks > 16384) blocks = 16384;
   k_loglik<<<(unsigned)blocks, kBlock, 0, ctx->stream>>>(n, model->r, model->m, model->obs, model->H,
@@ -800,7 +801,7 @@ extern "C" yy_status yy_loglik_normalise(yy_ctx ctx, const yy_model* model, int6
   if (!x || !dy || !logw || !logZ_step || !logZ_acc || !mean || !ess)
     return fail(YY_ERR_ARG, "yy_loglik_normalise: NULL array");
   const int32_t r = model->r;
-  const bool one_pass = model->obs != YY_H_LINEAR && model->m == r && (r & 1) == 0 && r <= 1024 &&
+  const bool one_pass = model->obs != YY_H_LINEAR && model->m == r && (r & 1) == 0 && r <= 1024 && !noise_b(model) &&
                         ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(dy)) & 15) == 0;
   if (!one_pass) {
     if ((st = yy_loglik_update(ctx, model, n, x, dy, dt, logw)) != YY_OK) return st;

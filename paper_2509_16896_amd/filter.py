@@ -34,7 +34,12 @@ class GpuFilter:
         self.prec = prec or w.precision
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.dev)
         self.ctx = yy.yy_create(device, self.stream)
-        self.model = yy.Model(w.r, w.m, w.drift, w.A, w.obs, w.H, w.h_shift, w.q, w.rho2, device=self.dev)
+        # general noise coefficients a = U U^T, b = V V^T (Sec. 7), when the workload gives them
+        self.noise = None
+        if w.U is not None or w.V is not None:
+            self.noise = yy.yy_noise_create(self.ctx, w.r, w.U, w.m, w.V)
+        self.model = yy.Model(w.r, w.m, w.drift, w.A, w.obs, w.H, w.h_shift, w.q, w.rho2, device=self.dev,
+                              noise=self.noise)
         self.scales = yy.Scales(w.scales, form=form, div=div)
         n, r = w.n, w.r
         f64 = dict(dtype=torch.float64, device=self.dev)
@@ -87,6 +92,9 @@ class GpuFilter:
         if self.proposal is not None:
             yy.yy_proposal_destroy(self.proposal)
             self.proposal = None
+        if getattr(self, "noise", None) is not None:
+            yy.yy_noise_destroy(self.noise)
+            self.noise = None
         if self.ctx is not None:
             yy.yy_destroy(self.ctx)
             self.ctx = None

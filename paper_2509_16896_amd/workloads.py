@@ -41,6 +41,8 @@ class Workload:
     A: np.ndarray | None = None
     H: np.ndarray | None = None
     precision: str = "bf16x3"
+    U: np.ndarray | None = None   # general process-noise coefficient (a = U U^T), else sqrt(q) I
+    V: np.ndarray | None = None   # general observation-noise coefficient (b = V V^T), else sqrt(rho2) I
 
     @property
     def m(self) -> int:
@@ -149,9 +151,12 @@ def simulate(w: Workload, seed: int | None = None):
     xs = [x.copy()]
     dys = []
     sq, so = math.sqrt(w.q * w.dt), math.sqrt(w.rho2 * w.dt)
+    sdt = math.sqrt(w.dt)
     for _ in range(w.K):
-        x = x + _drift_np(w, x[None, :])[0] * w.dt + sq * rng.standard_normal(w.r)
-        dy = _obs_np(w, x[None, :])[0] * w.dt + so * rng.standard_normal(w.m)
+        xi = rng.standard_normal(w.r)
+        x = x + _drift_np(w, x[None, :])[0] * w.dt + (sq * xi if w.U is None else sdt * (w.U @ xi))
+        eta = rng.standard_normal(w.m)
+        dy = _obs_np(w, x[None, :])[0] * w.dt + (so * eta if w.V is None else sdt * (w.V @ eta))
         xs.append(x.copy())
         dys.append(dy)
     return np.array(xs), np.array(dys)

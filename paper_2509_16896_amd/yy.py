@@ -31,7 +31,8 @@ PREC_BY_NAME = {"auto": YY_PREC_AUTO, "fp32": YY_PREC_FP32, "fp32_mfma": YY_PREC
                 "bf16x3g": YY_PREC_BF16X3G, "bf16x3s": YY_PREC_BF16X3S, "bf16x3p": YY_PREC_BF16X3P}
 EXPORTED = ["yy_last_error", "yy_create", "yy_destroy", "yy_set_stream", "yy_get_status",
             "yy_kernel_coefficients", "yy_nodes_sobol", "yy_propagate", "yy_loglik_update",
-            "yy_normalise_moments", "yy_normalise_moments_noalloc", "yy_loglik_normalise", "yy_restart", "yy_timing_enable", "yy_timing_read", "yy_screen_count",
+            "yy_normalise_moments", "yy_normalise_moments_noalloc", "yy_loglik_normalise",
+            "yy_noise_create", "yy_noise_destroy", "yy_noise_info", "yy_restart", "yy_timing_enable", "yy_timing_read", "yy_screen_count",
             "yy_proposal_create", "yy_proposal_destroy", "yy_proposal_num_params", "yy_proposal_get_params",
             "yy_proposal_set_params", "yy_proposal_forward", "yy_proposal_train_step", "yy_sample_moments",
             "yy_tune", "yy_batch_create", "yy_batch_destroy", "yy_batch_reset", "yy_batch_step",
@@ -49,7 +50,8 @@ class YYError(RuntimeError):
 class yy_model(ctypes.Structure):
     _fields_ = [("r", ctypes.c_int32), ("m", ctypes.c_int32), ("drift", ctypes.c_int32),
                 ("A", ctypes.c_void_p), ("obs", ctypes.c_int32), ("H", ctypes.c_void_p),
-                ("h_shift", ctypes.c_double), ("q", ctypes.c_double), ("rho2", ctypes.c_double)]
+                ("h_shift", ctypes.c_double), ("q", ctypes.c_double), ("rho2", ctypes.c_double),
+                ("noise", ctypes.c_void_p)]
 
 
 class yy_scales(ctypes.Structure):
@@ -83,6 +85,9 @@ for _name, _args in {
     "yy_loglik_update": [_P, ctypes.POINTER(yy_model), _i64, _P, _P, _f64, _P],
     "yy_normalise_moments": [_P, _i64, _i32, _P, _P, _P, _P, _P, _P, _P, _P],
     "yy_normalise_moments_noalloc": [_P, _i64, _i32, _P, _P, _P, _P, _P, _P, _P, _P],
+    "yy_noise_create": [_P, _i32, _P, _i32, _P, ctypes.POINTER(_P)],
+    "yy_noise_destroy": [_P],
+    "yy_noise_info": [_P, ctypes.POINTER(_i32), ctypes.POINTER(_f64), ctypes.POINTER(_i32), ctypes.POINTER(_f64)],
     "yy_loglik_normalise": [_P, ctypes.POINTER(yy_model), _i64, _P, _P, _f64, _P, _P, _P, _P, _P, _P],
     "yy_restart": [_P, _i64, _i32, _P, _P, _P, _P, _P, _i64, ctypes.POINTER(yy_restart_params), _P, _P,
                    _P, _P, _P, _P],
@@ -145,12 +150,14 @@ class Model:
     """Host description of yy_model; keeps A/H device tensors alive."""
 
     def __init__(self, r, m=None, drift=YY_F_COS, A=None, obs=YY_H_CUBE, H=None, h_shift=0.0, q=1.0,
-                 rho2=1.0, device="cuda"):
+                 rho2=1.0, device="cuda", noise=None):
         self.A = None if A is None else torch.as_tensor(A, dtype=torch.float64, device=device).contiguous()
         self.H = None if H is None else torch.as_tensor(H, dtype=torch.float64, device=device).contiguous()
         m = int(m if m is not None else (self.H.shape[0] if self.H is not None else r))
+        self.noise = noise     # a yy_noise handle (yy_noise_create), kept alive by the caller
         self.c = yy_model(int(r), m, int(drift), None if self.A is None else self.A.data_ptr(), int(obs),
-                          None if self.H is None else self.H.data_ptr(), float(h_shift), float(q), float(rho2))
+                          None if self.H is None else self.H.data_ptr(), float(h_shift), float(q), float(rho2),
+                          noise)
 
     @property
     def r(self):
@@ -247,6 +254,31 @@ def yy_normalise_moments(ctx, n, r, x, logw, w, logZ_step, logZ_acc, mean, cov, 
                                      _dptr(logZ_acc, torch.float64, 1, "logZ_acc"),
                                      _dptr(mean, torch.float64, r, "mean"), _dptr(cov, torch.float64, r * r, "cov"),
                                      _dptr(ess, torch.float64, 1, "ess")), "yy_normalise_moments")
+
+
+def yy_noise_create(ctx, r, U=None, m=None, V=None):
+    """General noise coefficients a = U U^T (r x r) and/or b = V V^T (m x m), host arrays; returns a handle."""
+    import numpy as np
+    m = r if m is None else m
+    Ua = None if U is None else np.ascontiguousarray(U, dtype=np.float64).reshape(r, r)
+    Va = None if V is None else np.ascontiguousarray(V, dtype=np.float64).reshape(m, m)
+    out = ctypes.c_void_p()
+    _check(_lib.yy_noise_create(ctx, int(r), None if Ua is None else Ua.ctypes.data_as(ctypes.c_void_p), int(m),
+                                None if Va is None else Va.ctypes.data_as(ctypes.c_void_p), ctypes.byref(out)),
+           "yy_noise_create")
+    return out
+
+
+def yy_noise_destroy(noise):
+    _check(_lib.yy_noise_destroy(noise), "yy_noise_destroy")
+
+
+def yy_noise_info(noise):
+    ra, rb = ctypes.c_int32(), ctypes.c_int32()
+    la, lb = ctypes.c_double(), ctypes.c_double()
+    _check(_lib.yy_noise_info(noise, ctypes.byref(ra), ctypes.byref(la), ctypes.byref(rb), ctypes.byref(lb)),
+           "yy_noise_info")
+    return ra.value, la.value, rb.value, lb.value
 
 
 def yy_normalise_moments_noalloc(ctx, n, r, x, logw, w, logZ_step, logZ_acc, mean, cov, ess):
