@@ -210,6 +210,27 @@ yy_status yy_propagate(yy_ctx ctx, const yy_model* model, const yy_scales* scale
                        int64_t n, const double* x, uint64_t node_version, const double* box_lo,
                        const double* box_hi, double dt, const double* logw_in, double* logw_out);
 
+/* The prediction as a stored operator: the offline / online split of Sec. 10 (the operator
+ * matrix of Sec. 4.2, steps 2-3, assembled once; step 5, its product with the weights, every
+ * step), in the log domain of Sec. 9.
+ * yy_operator_build stores, for the node set x (and model, scales, dt, box as yy_propagate takes
+ * them, push or pull form, isotropic or general noise), every kernel value per scale as an FP32
+ * base-2 exponent without the weights, E[s][i][j] (FP32 direct differences, the arithmetic of
+ * YY_PREC_FP32): S n ceil(n/64)*64 x 4 bytes of device memory (yy_operator_info).  *op: NULL to
+ * create a new operator, or one built before on this context to rebuild in place (its memory is
+ * reused when large enough).  yy_operator_apply then gives exactly the prediction yy_propagate
+ * computes (same combination, constants, boundary rows and clamp; FP32 rounding of the stored
+ * exponents), reading the stored operator once: logw_in, logw_out device [n], must not alias.
+ * The operator must be destroyed before its context. */
+typedef struct yy_operator_s* yy_operator;
+yy_status yy_operator_build(yy_ctx ctx, const yy_model* model, const yy_scales* scales, int64_t n, const double* x,
+                            uint64_t node_version, const double* box_lo, const double* box_hi, double dt,
+                            yy_operator* op);
+yy_status yy_operator_apply(yy_operator op, const double* logw_in, double* logw_out);
+/* Nodes, scales and device bytes of the stored exponents; any pointer may be NULL. */
+yy_status yy_operator_info(yy_operator op, int64_t* n, int32_t* S, int64_t* bytes);
+yy_status yy_operator_destroy(yy_operator op);
+
 /* Correction with the Ito term (Sec. 2.2 online stage; Sec. 9 observation
  * update; 1/rho2 from Table tab:generalformulas), in place:
  *   logw[i] += ( h(x_i) . dy - dt/2 |h(x_i)|^2 ) / rho2      (-inf stays -inf)

@@ -11,7 +11,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libyy.so")
 SOURCES = ["yy_api.hip", "yy_sobol.hip", "yy_propagate.hip", "yy_pair_mfma.hip", "yy_update.hip",
-           "yy_restart.hip", "yy_proposal.hip", "yy_batch.hip", "yy_noise.hip"]
+           "yy_restart.hip", "yy_proposal.hip", "yy_batch.hip", "yy_noise.hip",
+           "yy_operator.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Wall", "-Wno-unused-function",
          # packed FP32 instructions stay off (hipcc's host pass warns it does not know the feature)

@@ -270,6 +270,10 @@ yy_status propagate_begin(yy_ctx ctx, const yy_model* model, const yy_scales* sc
                           PropPlan& plan, bool defer_planes = false);
 yy_status propagate_pair(yy_ctx ctx, const PropPlan& plan);
 yy_status propagate_end(yy_ctx ctx, const PropPlan& plan);
+// Step (2) alone (lw2 and the device address of the weights' maximum, in ctx->red) and step (4)'s launch.
+yy_status source_weights(yy_ctx ctx, int64_t n, const double* logw_in, const int* bnd, float* lw2,
+                         double** lref_out);
+yy_status launch_combine(hipStream_t st, const CombineArgs& cb);
 
 // Blocks of the normalisation kernels for n nodes (64 rows per block, at most
 // 1024 blocks): enough blocks to stream the n x r coordinates at full bandwidth.

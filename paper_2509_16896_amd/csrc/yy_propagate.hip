@@ -854,6 +854,30 @@ using namespace yy;
 
 namespace yy {
 
+// Source weights relative to their maximum (step 2): lw2 [n] and the device
+// address of the maximum (in ctx->red).
+yy_status source_weights(yy_ctx ctx, int64_t n, const double* logw_in, const int* bnd, float* lw2,
+                         double** lref_out) {
+  const int nparts = (int)std::min<int64_t>((n + kBlock - 1) / kBlock, 1024);
+  yy_status st;
+  if ((st = ctx->red.ensure((size_t)(nparts + 8) * sizeof(double))) != YY_OK) return st;
+  double* d_part = ctx->red.as<double>();
+  double* d_lref = d_part + nparts;
+  k_lw_max<<<nparts, kBlock, 0, ctx->stream>>>(n, logw_in, bnd, d_part);
+  YY_LAUNCH_CHECK("k_lw_max");
+  k_lw_convert<<<nparts, kBlock, 0, ctx->stream>>>(n, nparts, d_part, logw_in, bnd, lw2, d_lref);
+  YY_LAUNCH_CHECK("k_lw_convert");
+  *lref_out = d_lref;
+  return YY_OK;
+}
+
+yy_status launch_combine(hipStream_t st, const CombineArgs& cb) {
+  if (cb.n == 0) return YY_OK;
+  k_combine<<<(unsigned)((cb.n + kBlock - 1) / kBlock), kBlock, 0, st>>>(cb);
+  YY_LAUNCH_CHECK("k_combine");
+  return YY_OK;
+}
+
 // Steps (1), (2) and the launch parameters of (3) and (4) for one call; the
 // batched step (yy_batch.hip) runs (3) for many plans in one launch.
 yy_status propagate_begin(yy_ctx ctx, const yy_model* model, const yy_scales* scales, int32_t prec, int64_t n,
@@ -912,16 +936,9 @@ yy_status propagate_begin(yy_ctx ctx, const yy_model* model, const yy_scales* sc
   }
 
   // (2) source weights relative to their maximum
-  const int nparts = (int)std::min<int64_t>((n + kBlock - 1) / kBlock, 1024);
-  if ((st = ctx->red.ensure((size_t)(nparts + 8) * sizeof(double))) != YY_OK) return st;
   if ((st = ctx->lw2.ensure((size_t)n * sizeof(float))) != YY_OK) return st;
-  double* d_part = ctx->red.as<double>();
-  double* d_lref = d_part + nparts;
-  k_lw_max<<<nparts, kBlock, 0, ctx->stream>>>(n, logw_in, P.bnd.as<int>(), d_part);
-  YY_LAUNCH_CHECK("k_lw_max");
-  k_lw_convert<<<nparts, kBlock, 0, ctx->stream>>>(n, nparts, d_part, logw_in, P.bnd.as<int>(),
-                                                   ctx->lw2.as<float>(), d_lref);
-  YY_LAUNCH_CHECK("k_lw_convert");
+  double* d_lref = nullptr;
+  if ((st = source_weights(ctx, n, logw_in, P.bnd.as<int>(), ctx->lw2.as<float>(), &d_lref)) != YY_OK) return st;
 
   // (3) pairwise partials
   PairArgs& a = plan.a;
@@ -1043,9 +1060,7 @@ yy_status propagate_pair(yy_ctx ctx, const PropPlan& plan) {
 
 yy_status propagate_end(yy_ctx ctx, const PropPlan& plan) {
   if (plan.n == 0) return YY_OK;
-  k_combine<<<(unsigned)((plan.n + kBlock - 1) / kBlock), kBlock, 0, ctx->stream>>>(plan.cb);
-  YY_LAUNCH_CHECK("k_combine");
-  return YY_OK;
+  return launch_combine(ctx->stream, plan.cb);
 }
 
 }  // namespace yy

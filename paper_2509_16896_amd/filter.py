@@ -23,11 +23,14 @@ class GpuFilter:
     def __init__(self, w: Workload, prec: str | None = None, device: int = 0, stream=None,
                  want_cov: bool = False, ess_min: float = 0.0, proposal_params=None, hidden: int = 256,
                  cover_min: float = 0.95, collect_pairs: bool = False, one_pass: bool = True,
-                 form: str = "push", div: int = 0):
+                 form: str = "push", div: int = 0, operator: bool = False):
         """one_pass: each step's correction and normalisation through yy_loglik_normalise (x read
         once where it can); False makes the two calls yy_loglik_update and yy_normalise_moments, the
         sequence the batched step reproduces bit for bit.  form: the first-order kernel, "push" or
-        "pull" (eq. kernel, with the divergence in closed form, div = 0, or by complex step, div = 1)."""
+        "pull" (eq. kernel, with the divergence in closed form, div = 0, or by complex step, div = 1).
+        operator: predict with the stored operator (Sec. 10 offline/online split) -- built once per
+        node set by yy_operator_build, applied every step by yy_operator_apply -- instead of
+        yy_propagate's recomputation."""
         self.w = w
         self.one_pass = one_pass
         self.dev = torch.device("cuda", device)
@@ -67,6 +70,9 @@ class GpuFilter:
         self.ess_min = ess_min
         self.version = 0
         self.dys = None
+        self.use_operator = operator
+        self.op = None
+        self.op_version = -1
         # learned restart proposal (a network created on this context from trained parameters)
         self.proposal = None
         self.cover_min = cover_min
@@ -92,6 +98,9 @@ class GpuFilter:
         if self.proposal is not None:
             yy.yy_proposal_destroy(self.proposal)
             self.proposal = None
+        if getattr(self, "op", None) is not None:
+            yy.yy_operator_destroy(self.op)
+            self.op = None
         if getattr(self, "noise", None) is not None:
             yy.yy_noise_destroy(self.noise)
             self.noise = None
@@ -138,8 +147,15 @@ class GpuFilter:
         """Filter step k (1-based) with observation increment dys[k-1]."""
         w = self.w
         src, dst = self.lw[self.cur], self.lw[1 - self.cur]
-        yy.yy_propagate(self.ctx, self.model, self.scales, self.prec, w.n, self.x, self.version, self.lo,
-                        self.hi, w.dt, src, dst)
+        if self.use_operator:
+            if self.op_version != self.version:   # offline stage: once per node set
+                self.op = yy.yy_operator_build(self.ctx, self.model, self.scales, w.n, self.x, self.version, self.lo,
+                                               self.hi, w.dt, self.op)
+                self.op_version = self.version
+            yy.yy_operator_apply(self.op, src, dst)
+        else:
+            yy.yy_propagate(self.ctx, self.model, self.scales, self.prec, w.n, self.x, self.version, self.lo,
+                            self.hi, w.dt, src, dst)
         self.cur = 1 - self.cur
         row = k - 1
         if self.one_pass and not want_cov:

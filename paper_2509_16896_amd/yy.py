@@ -32,7 +32,8 @@ PREC_BY_NAME = {"auto": YY_PREC_AUTO, "fp32": YY_PREC_FP32, "fp32_mfma": YY_PREC
 EXPORTED = ["yy_last_error", "yy_create", "yy_destroy", "yy_set_stream", "yy_get_status",
             "yy_kernel_coefficients", "yy_nodes_sobol", "yy_propagate", "yy_loglik_update",
             "yy_normalise_moments", "yy_normalise_moments_noalloc", "yy_loglik_normalise",
-            "yy_noise_create", "yy_noise_destroy", "yy_noise_info", "yy_restart", "yy_timing_enable", "yy_timing_read", "yy_screen_count",
+            "yy_noise_create", "yy_noise_destroy", "yy_noise_info",
+            "yy_operator_build", "yy_operator_apply", "yy_operator_info", "yy_operator_destroy", "yy_restart", "yy_timing_enable", "yy_timing_read", "yy_screen_count",
             "yy_proposal_create", "yy_proposal_destroy", "yy_proposal_num_params", "yy_proposal_get_params",
             "yy_proposal_set_params", "yy_proposal_forward", "yy_proposal_train_step", "yy_sample_moments",
             "yy_tune", "yy_batch_create", "yy_batch_destroy", "yy_batch_reset", "yy_batch_step",
@@ -86,6 +87,11 @@ for _name, _args in {
     "yy_normalise_moments": [_P, _i64, _i32, _P, _P, _P, _P, _P, _P, _P, _P],
     "yy_normalise_moments_noalloc": [_P, _i64, _i32, _P, _P, _P, _P, _P, _P, _P, _P],
     "yy_noise_create": [_P, _i32, _P, _i32, _P, ctypes.POINTER(_P)],
+    "yy_operator_build": [_P, ctypes.POINTER(yy_model), ctypes.POINTER(yy_scales), _i64, _P, _u64, _P, _P, _f64,
+                          ctypes.POINTER(_P)],
+    "yy_operator_apply": [_P, _P, _P],
+    "yy_operator_info": [_P, ctypes.POINTER(_i64), ctypes.POINTER(_i32), ctypes.POINTER(_i64)],
+    "yy_operator_destroy": [_P],
     "yy_noise_destroy": [_P],
     "yy_noise_info": [_P, ctypes.POINTER(_i32), ctypes.POINTER(_f64), ctypes.POINTER(_i32), ctypes.POINTER(_f64)],
     "yy_loglik_normalise": [_P, ctypes.POINTER(yy_model), _i64, _P, _P, _f64, _P, _P, _P, _P, _P, _P],
@@ -279,6 +285,34 @@ def yy_noise_info(noise):
     _check(_lib.yy_noise_info(noise, ctypes.byref(ra), ctypes.byref(la), ctypes.byref(rb), ctypes.byref(lb)),
            "yy_noise_info")
     return ra.value, la.value, rb.value, lb.value
+
+
+def yy_operator_build(ctx, model, scales, n, x, node_version, box_lo, box_hi, dt, op=None):
+    """Builds (or, given op, rebuilds in place) the stored operator; returns the handle."""
+    h = op if op is not None else ctypes.c_void_p()
+    r = model.r
+    _check(_lib.yy_operator_build(ctx, ctypes.byref(model.c), ctypes.byref(scales.c), int(n),
+                                  _dptr(x, torch.float64, n * r, "x"), int(node_version) & 0xFFFFFFFFFFFFFFFF,
+                                  _dptr(box_lo, torch.float64, r, "box_lo"), _dptr(box_hi, torch.float64, r, "box_hi"),
+                                  float(dt), ctypes.byref(h)), "yy_operator_build")
+    return h
+
+
+def yy_operator_apply(op, logw_in, logw_out):
+    n = ctypes.c_int64()
+    _check(_lib.yy_operator_info(op, ctypes.byref(n), None, None), "yy_operator_info")
+    _check(_lib.yy_operator_apply(op, _dptr(logw_in, torch.float64, n.value, "logw_in"),
+                                  _dptr(logw_out, torch.float64, n.value, "logw_out")), "yy_operator_apply")
+
+
+def yy_operator_info(op):
+    n, S, b = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int64()
+    _check(_lib.yy_operator_info(op, ctypes.byref(n), ctypes.byref(S), ctypes.byref(b)), "yy_operator_info")
+    return n.value, S.value, b.value
+
+
+def yy_operator_destroy(op):
+    _check(_lib.yy_operator_destroy(op), "yy_operator_destroy")
 
 
 def yy_normalise_moments_noalloc(ctx, n, r, x, logw, w, logZ_step, logZ_acc, mean, cov, ess):
