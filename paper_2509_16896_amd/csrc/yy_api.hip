@@ -288,6 +288,8 @@ yy_status yy_destroy(yy_ctx ctx) {
   ctx->prep.wnodes.release();
   ctx->prep.wbnd.release();
   ctx->obsw.release();
+  ctx->rref.release();
+  ctx->fstar.release();
   ctx->lw2.release();
   ctx->part.release();
   ctx->red.release();

@@ -141,6 +141,7 @@ struct yy_batch_s {
   yy::BLaunch<yy::box_plain_args> box;
   yy::BLaunch<yy::prepare_args> prep;
   yy::BLaunch<yy::prepare_scalars_args> prep_scal;
+  yy::BLaunch<yy::RowRefArgs> rowref;
   // graph of two consecutive steps, starting with parity g_parity
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -305,7 +306,8 @@ static yy_status build(yy_batch b) {
       const double* lwi = R.lw[in].as<double>();
       double* lwo = R.lw[out].as<double>();
       A1.push_back({n, lwi, P.bnd.as<int>(), d_part, nullptr});
-      A2.push_back({n, nparts, d_part, lwi, P.bnd.as<int>(), R.rc->lw2.as<float>(), d_lref, nullptr});
+      A2.push_back({n, nparts, d_part, lwi, P.bnd.as<int>(), R.rc->lw2.as<float>(), d_lref, nullptr,
+                    reinterpret_cast<long long*>(d_part + nparts + 8)});
       CombineArgs cb = R.plan.cb;
       cb.logw_in = lwi;
       cb.logw_out = lwo;
@@ -364,7 +366,8 @@ static yy_status build(yy_batch b) {
   std::vector<box_plain_args> Bx;
   std::vector<prepare_args> Pp;
   std::vector<prepare_scalars_args> Ps;
-  std::vector<int> b_r, b_rs, b_one, b_prep;
+  std::vector<RowRefArgs> Rr;
+  std::vector<int> b_r, b_rs, b_one, b_prep, b_rr;
   for (int q = 0; q < nr; ++q) {
     BRun& R = b->runs[q];
     const yy_batch_run& d = R.d;
@@ -401,6 +404,32 @@ static yy_status build(yy_batch b) {
     b_rs.push_back(nbr);
     b_one.push_back(1);
     b_prep.push_back(prepare_blocks(P.n_pad));
+    // the rows' lower bounds from this step's weights (as yy_propagate computes them)
+    RowRefArgs ra{};
+    ra.n = n;
+    ra.r = r;
+    ra.S = b->S;
+    ra.drift = d.model.drift;
+    ra.A = d.model.A;
+    ra.x = R.x.as<double>();
+    ra.fw = nullptr;
+    ra.lw2 = R.rc->lw2.as<float>();
+    ra.node = P.node.as<double>();
+    ra.bnd = P.bnd.as<int>();
+    const int nparts = (int)std::min<int64_t>(nblk(n), 1024);
+    double* rbase = R.rc->red.as<double>();
+    ra.heavy = reinterpret_cast<const long long*>(rbase + nparts + 8);
+    ra.nheavy = nparts;
+    ra.jstar = reinterpret_cast<long long*>(rbase + nparts + 1);
+    if ((st = R.rc->fstar.ensure((size_t)r * sizeof(double))) != YY_OK) return st;
+    ra.fstar = R.rc->fstar.as<double>();
+    for (int s2 = 0; s2 < b->S; ++s2) {
+      ra.kapd[s2] = R.plan.kapd[s2];
+      ra.taud[s2] = R.plan.taud[s2];
+    }
+    ra.rref = R.rc->rref.as<float>();
+    Rr.push_back(ra);
+    b_rr.push_back((int)((n + 15) / 16));
   }
   if ((st = build_launch(b, b->record, Rc, b_r)) != YY_OK) return st;
   if ((st = build_launch(b, b->rs_local, S1, b_rs)) != YY_OK) return st;
@@ -410,6 +439,7 @@ static yy_status build(yy_batch b) {
   if ((st = build_launch(b, b->box, Bx, b_r)) != YY_OK) return st;
   if ((st = build_launch(b, b->prep, Pp, b_prep)) != YY_OK) return st;
   if ((st = build_launch(b, b->prep_scal, Ps, b_one)) != YY_OK) return st;
+  if ((st = build_launch(b, b->rowref, Rr, b_rr)) != YY_OK) return st;
   b->built = true;
   return YY_OK;
 }
@@ -435,6 +465,7 @@ static yy_status batch_step_impl(yy_batch b) {
   if ((st = launch_src_bias_batch(strm, b->d_sets.ptr, b->src_bias.pre.as<int>(), b->src_bias.nsets,
                                   b->src_bias.total)) != YY_OK)
     return st;
+  if ((st = run_launch(b, b->rowref)) != YY_OK) return st;
   if ((st = timing_begin(b->ctx)) != YY_OK) return st;
   if ((st = launch_pair_mfma_batch(strm, b->S, b->prec, b->d_sets.ptr, b->d_items.as<int4>(), b->nitems, b->k64)) != YY_OK)
     return st;
@@ -499,6 +530,7 @@ static void release_launches(yy_batch b) {
   rel(b->box);
   rel(b->prep);
   rel(b->prep_scal);
+  rel(b->rowref);
 }
 
 }  // namespace yy

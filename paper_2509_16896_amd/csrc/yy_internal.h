@@ -128,6 +128,8 @@ struct yy_ctx_s {
   yy::DevBuf bsrc;                    // matrix-core source biases
   yy::DevBuf sflags;                  // screen verdicts of the screened split form
   yy::DevBuf obsw;                    // general observation noise: h(x) rows, W_b h(x) rows, W_b dy
+  yy::DevBuf rref;                    // float [S][n]: lower bounds of the pairwise rows' maxima
+  yy::DevBuf fstar;                   // double [r]: f at the heaviest source
   int64_t sflags_tbs = 0, sflags_jtl = 0;   // their shape at the last screened propagation
   // tuned source-split counts: (rp, n_pad, S, prec) -> nsplit
   struct TuneEntry {
@@ -214,6 +216,7 @@ struct MfmaExtra {
   uint8_t* flags;              // screened split forms: [n_pad/256][ceil(n/128)][8] screen verdicts
   float* bpre;                 // BF16X3P: source biases over the first kPreK coordinates, laid out as bsrc
   const DeferredPrep* deferred;   // BF16X3P on one run with deferred planes, else null
+  const float* rref = nullptr;     // [S][n] lower bounds of the row maxima (push form), or null: self pairs
 };
 // blocks of the node preparation kernel (one wave per 4 nodes, grid-stride)
 int prepare_blocks(int64_t n_pad);
@@ -272,7 +275,7 @@ yy_status propagate_pair(yy_ctx ctx, const PropPlan& plan);
 yy_status propagate_end(yy_ctx ctx, const PropPlan& plan);
 // Step (2) alone (lw2 and the device address of the weights' maximum, in ctx->red) and step (4)'s launch.
 yy_status source_weights(yy_ctx ctx, int64_t n, const double* logw_in, const int* bnd, float* lw2,
-                         double** lref_out);
+                         double** lref_out, long long** heavy_out = nullptr);
 yy_status launch_combine(hipStream_t st, const CombineArgs& cb);
 
 // Blocks of the normalisation kernels for n nodes (64 rows per block, at most
@@ -477,6 +480,25 @@ struct lw_convert_args {
   float* lw2;
   double* ref_out;
   const int* pred;   // run only when *pred != 0 (NULL: always)
+  long long* heavy;  // the heaviest source's index, or NULL
+};
+
+// Lower bounds of the pairwise rows' maxima (k_row_ref, yy_propagate.hip).
+struct RowRefArgs {
+  int64_t n;
+  int32_t r, S, drift;
+  const double* A;
+  const double* x;
+  const double* fw;       // whitened f rows [n][r], or null (then f from the drift)
+  const float* lw2;
+  const double* node;     // |f_i|^2 at node[n + i]
+  const int* bnd;
+  const long long* heavy; // [nheavy] the conversion blocks' candidates for j*
+  int nheavy;
+  long long* jstar;       // j*, the first valid source of maximal weight (-1: none)
+  double* fstar;          // [r] f(x_j*)
+  double kapd[YY_MAX_SCALES], taud[YY_MAX_SCALES];
+  float* rref;            // [S][n]
 };
 
 struct combine_args {
@@ -502,6 +524,7 @@ yy_status launch_batched(hipStream_t st, const prepare_args* A, const int* pre, 
 yy_status launch_batched(hipStream_t st, const prepare_scalars_args* A, const int* pre, int nr, int total);
 yy_status launch_batched(hipStream_t st, const lw_max_args* A, const int* pre, int nr, int total);
 yy_status launch_batched(hipStream_t st, const lw_convert_args* A, const int* pre, int nr, int total);
+yy_status launch_batched(hipStream_t st, const RowRefArgs* A, const int* pre, int nr, int total);
 yy_status launch_batched(hipStream_t st, const combine_args* A, const int* pre, int nr, int total);
 // Source biases of many sets (the batched pairwise kernel's argument array).
 yy_status launch_src_bias_batch(hipStream_t st, const void* sets, const int* pre, int nr, int total);

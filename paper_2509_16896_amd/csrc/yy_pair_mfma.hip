@@ -90,6 +90,7 @@ struct MArgs {
   int32_t pre_chunks;          // 16-wide K stages of the partial-distance screen
   int* any_flag;               // deferred planes: k_src_bias clears it, the screen sets it on a flagged tile
   int32_t pull;                // pull-form kernel (biases and the sign of c2 follow it)
+  const float* rref;           // [S][n] lower bounds of the row maxima (>= the self-pair exponent), or null
 };
 
 // Physical 16-byte chunk of logical chunk c in LDS row `row` (bank-conflict swizzle).
@@ -339,8 +340,12 @@ __device__ inline void init_targets(const MArgs& a, int64_t i0, int split, float
       // target term: -kap |x_i|^2 (push), -kap |x_i - tau f_i|^2 (pull)
       const double t = a.taud[s];
       at[ib][s] = valid ? (float)(-a.kapd[s] * (a.pull ? nx - 2.0 * t * nxf + t * t * nf : nx)) : -INFINITY;
-      M[ib][s] = (valid && li != -INFINITY) ? li - (float)(a.kapd[s] * a.taud[s] * a.taud[s] * nf) : -INFINITY;
-      Ssum[ib][s] = (owner && M[ib][s] != -INFINITY) ? 1.f : 0.f;
+      // the running maximum starts at the row's lower bound (the self pair, or the exact term of
+      // the heaviest source where that is larger); the owner counts the self term relative to it
+      const float self = (valid && li != -INFINITY) ? li - (float)(a.kapd[s] * a.taud[s] * a.taud[s] * nf) : -INFINITY;
+      const float ref = (valid && a.rref) ? a.rref[(size_t)s * a.n + i] : self;
+      M[ib][s] = ref;
+      Ssum[ib][s] = (owner && self != -INFINITY) ? (self == ref ? 1.f : fast_exp2(self - ref)) : 0.f;
     }
   }
 }
@@ -693,8 +698,10 @@ __device__ __forceinline__ void pair_block(const MArgs& a, int tb, int split, un
           const double nf = a.node[a.n + i];
 #pragma unroll
           for (int s = 0; s < S; ++s) {
-            const float M0 = li != -INFINITY ? li - (float)(a.kapd[s] * a.taud[s] * a.taud[s] * nf) : -INFINITY;
-            a.part[((size_t)split * S + s) * a.n + i] = make_float2(M0, (own && M0 != -INFINITY) ? 1.f : 0.f);
+            const float self = li != -INFINITY ? li - (float)(a.kapd[s] * a.taud[s] * a.taud[s] * nf) : -INFINITY;
+            const float M0 = a.rref ? a.rref[(size_t)s * a.n + i] : self;
+            a.part[((size_t)split * S + s) * a.n + i] =
+                make_float2(M0, (own && self != -INFINITY) ? (self == M0 ? 1.f : fast_exp2(self - M0)) : 0.f);
           }
         }
       }
@@ -944,7 +951,8 @@ __device__ __forceinline__ void screen_block(const MArgs& a, int tb, int split, 
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       at[ib][s] = valid ? (float)(-a.kapd[s] * nx + hF) : -INFINITY;
-      M[ib][s] = (valid && li != -INFINITY) ? li - (float)(a.kapd[s] * a.taud[s] * a.taud[s] * nf) : -INFINITY;
+      const float self = (valid && li != -INFINITY) ? li - (float)(a.kapd[s] * a.taud[s] * a.taud[s] * nf) : -INFINITY;
+      M[ib][s] = (valid && a.rref) ? a.rref[(size_t)s * a.n + i] : self;
       slack[ib][s] = (float)((double)margin[s] - kSkip - 15.0 + 2.0 * hF);
     }
   }
@@ -1100,7 +1108,8 @@ __device__ inline void screen_block_map(const MArgs& a, int& tb, int& split) {
 // |x_i - m_j|^2 >= |x_i^p - m_j^p|^2, so the bound of screen_block with G, the
 // norms and F taken over those coordinates (a_i^p, b_js^p in a.bpre, F^p)
 // bounds the exact exponent from above.  Being no lower bound of the row
-// maximum, it leaves M at the exact self-pair exponent; boundary targets,
+// maximum, it leaves M at the row's exact lower bound (the self pair, or the
+// pair with the heaviest source where that is larger); boundary targets,
 // whose result is -inf whatever the sum, are not flagged.  The source biases
 // of a tile are read (through the scalar cache) only when its coarse bound
 // leaves a doubt.
@@ -1157,7 +1166,8 @@ __device__ __forceinline__ void prescreen_block(const MArgs& a, int tb, int spli
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       at[ib][s] = valid ? (float)(-a.kapd[s] * nx + hF) : -INFINITY;
-      M[ib][s] = (valid && li != -INFINITY) ? li - (float)(a.kapd[s] * a.taud[s] * a.taud[s] * nf) : -INFINITY;
+      const float self = (valid && li != -INFINITY) ? li - (float)(a.kapd[s] * a.taud[s] * a.taud[s] * nf) : -INFINITY;
+      M[ib][s] = (valid && a.rref) ? a.rref[(size_t)s * a.n + i] : self;
     }
 #pragma unroll
     for (int c = 0; c < PC; ++c)
@@ -1439,6 +1449,7 @@ static MArgs make_args(const PairArgs& pa, int prec, const MfmaExtra& ex) {
   m.s_jps = ((ex.j_per_split + kSJ - 1) / kSJ) * kSJ;
   m.pre_chunks = std::min(kPreK, (int)pa.rp) / kKC;
   m.any_flag = ex.deferred ? ex.deferred->defer : nullptr;
+  m.rref = pa.pull ? nullptr : ex.rref;
   return m;
 }
 

@@ -12,6 +12,7 @@
 // combination of the scales with the Gaussian constants, the quadrature
 // weight and the identity term.
 #include <algorithm>
+#include <climits>
 #include <cmath>
 
 #include <vector>
@@ -372,15 +373,28 @@ __device__ __forceinline__ void k_lw_convert_body(int64_t n, int nparts,
                                                        const double* __restrict__ lw,
                                                        const int* __restrict__ bnd,
                                                        float* __restrict__ lw2,
-                                                       double* __restrict__ ref_out, int bx_, int gx_) {
+                                                       double* __restrict__ ref_out, int bx_, int gx_,
+                                                       long long* __restrict__ heavy = nullptr) {
   __shared__ double sh[kBlock / 64];
   double m = -INFINITY;
   for (int p = threadIdx.x; p < nparts; p += kBlock) m = fmax(m, part[p]);
   m = block_max<kBlock>(m, sh);
   if (bx_ == 0 && threadIdx.x == 0) *ref_out = m;
+  long long cand = LLONG_MAX;   // this thread's first valid source attaining the maximum
   for (int64_t j = (int64_t)bx_ * kBlock + threadIdx.x; j < n; j += (int64_t)gx_ * kBlock) {
     const double v = lw[j];
-    lw2[j] = (bnd[j] || v == -INFINITY || m == -INFINITY) ? -INFINITY : (float)((v - m) * kLog2e);
+    const bool valid = !bnd[j] && v != -INFINITY && m != -INFINITY;
+    lw2[j] = valid ? (float)((v - m) * kLog2e) : -INFINITY;
+    if (valid && v == m && cand == LLONG_MAX) cand = j;
+  }
+  if (heavy) {
+    // per block: the smallest such index (heavy[bx], LLONG_MAX for none); k_heavy reduces them
+    __shared__ long long sj;
+    if (threadIdx.x == 0) sj = LLONG_MAX;
+    __syncthreads();
+    if (cand != LLONG_MAX) atomicMin(&sj, cand);
+    __syncthreads();
+    if (threadIdx.x == 0) heavy[bx_] = sj;
   }
 }
 
@@ -389,8 +403,120 @@ __global__ void __launch_bounds__(kBlock) k_lw_convert(int64_t n, int nparts,
                                                        const double* __restrict__ lw,
                                                        const int* __restrict__ bnd,
                                                        float* __restrict__ lw2,
-                                                       double* __restrict__ ref_out) {
-  k_lw_convert_body(n, nparts, part, lw, bnd, lw2, ref_out, blockIdx.x, gridDim.x);
+                                                       double* __restrict__ ref_out,
+                                                       long long* __restrict__ heavy) {
+  k_lw_convert_body(n, nparts, part, lw, bnd, lw2, ref_out, blockIdx.x, gridDim.x, heavy);
+}
+
+// ---------------------------------------------------------------------------
+// Lower bound of every (scale, target) row maximum for the matrix-core forms
+// (push form): the larger of the exact self-pair exponent and the exact
+// exponent of the pair with the heaviest source j* (a term of the row, in FP64
+// direct differences: lw2_j* = 0, d = x_i - x_j* - tau_s f(x_j*)).  The second
+// is formed only for rows whose self term lies more than kRowRefGap bits below
+// the heaviest weight; elsewhere the self term is within kRowRefGap bits of
+// any term the heaviest source could give.  Rows: x (the nodes, or with
+// general noise their whitened images; the box centre cancels in the
+// differences).  k_heavy (one block) reduces the conversion blocks' candidates
+// to j* (the first valid source of maximal weight) and evaluates f(x_j*) once;
+// k_row_ref takes 16 targets per block, a wave per target at a time with the
+// lanes across the coordinates.
+constexpr float kRowRefGap = 160.f;
+constexpr int kRowRefTargets = 16;
+
+__device__ __forceinline__ void k_heavy_body(const RowRefArgs& a) {
+  __shared__ long long sj;
+  if (threadIdx.x == 0) sj = LLONG_MAX;
+  __syncthreads();
+  long long m = LLONG_MAX;
+  for (int p = threadIdx.x; p < a.nheavy; p += kBlock) m = a.heavy[p] < m ? a.heavy[p] : m;
+  if (m != LLONG_MAX) atomicMin(&sj, m);
+  __syncthreads();
+  const long long js = sj == LLONG_MAX ? -1 : sj;
+  if (threadIdx.x == 0) *a.jstar = js;
+  if (js < 0) return;
+  const double* xj = a.x + (size_t)js * a.r;
+  for (int32_t k = threadIdx.x; k < a.r; k += kBlock) {
+    double fk = 0.0;
+    if (a.fw) {
+      fk = a.fw[(size_t)js * a.r + k];
+    } else if (a.drift == YY_F_COS) {
+      fk = cos(xj[k]);
+    } else if (a.drift == YY_F_PAPER_SINMIX) {
+      const double xv = xj[k], xn = k + 1 < a.r ? xj[k + 1] : 0.0;
+      fk = sin(xv) * (-0.5 * xv + 0.1 * xn) + sin(2.0 * xv) * (-0.3 * xv + 0.3 * xn);
+    } else if (a.drift == YY_F_LINEAR) {
+      double acc = 0.0;
+      for (int32_t l = 0; l < a.r; ++l) acc = fma(a.A[(size_t)k * a.r + l], xj[l], acc);
+      fk = acc;
+    }
+    a.fstar[k] = fk;
+  }
+}
+
+__device__ __forceinline__ void k_row_ref_body(const RowRefArgs& a, int bx_) {
+  __shared__ float sself[YY_MAX_SCALES][kRowRefTargets];
+  __shared__ int sneed[kRowRefTargets];
+  const int64_t i0 = (int64_t)bx_ * kRowRefTargets;
+  const long long js = *a.jstar;
+  if (threadIdx.x < kRowRefTargets) {
+    const int64_t i = i0 + threadIdx.x;
+    bool need = false;
+    if (i < a.n) {
+      const float li = a.lw2[i];
+      const double nf = a.node[a.n + i];
+      for (int s = 0; s < a.S; ++s) {
+        const float self = (li != -INFINITY && !a.bnd[i]) ? li - (float)(a.kapd[s] * a.taud[s] * a.taud[s] * nf)
+                                                          : -INFINITY;
+        sself[s][threadIdx.x] = self;
+        need |= self < -kRowRefGap;
+      }
+      need = need && js >= 0 && js != i && !a.bnd[i];
+    }
+    sneed[threadIdx.x] = need;
+  }
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int u = wave; u < kRowRefTargets; u += kBlock / 64) {
+    const int64_t i = i0 + u;
+    if (i >= a.n) break;
+    float ref[YY_MAX_SCALES];
+    for (int s = 0; s < a.S; ++s) ref[s] = sself[s][u];
+    if (sneed[u]) {
+      const double* xi = a.x + (size_t)i * a.r;
+      const double* xj = a.x + (size_t)js * a.r;
+      double D[YY_MAX_SCALES] = {0, 0, 0, 0, 0, 0};
+      for (int32_t k = lane; k < a.r; k += 64) {
+        const double d = xi[k] - xj[k], fk = a.fstar[k];
+        for (int s = 0; s < a.S; ++s) {
+          const double e = d - a.taud[s] * fk;
+          D[s] = fma(e, e, D[s]);
+        }
+      }
+      for (int s = 0; s < a.S; ++s) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) D[s] += __shfl_xor(D[s], off, 64);
+        ref[s] = fmaxf(ref[s], (float)(-a.kapd[s] * D[s]));
+      }
+    }
+    if (lane == 0)
+      for (int s = 0; s < a.S; ++s) a.rref[(size_t)s * a.n + i] = ref[s];
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_heavy(RowRefArgs a) { k_heavy_body(a); }
+__global__ void __launch_bounds__(kBlock) k_row_ref(RowRefArgs a) { k_row_ref_body(a, blockIdx.x); }
+
+// batched: the first block of each run's range evaluates its heavy source, the rows follow in a second launch
+__global__ void __launch_bounds__(kBlock) k_heavy_batch(const RowRefArgs* __restrict__ A, const int* __restrict__ pre,
+                                                        int nr) {
+  k_heavy_body(A[blockIdx.x]);
+}
+
+__global__ void __launch_bounds__(kBlock) k_row_ref_batch(const RowRefArgs* __restrict__ A, const int* __restrict__ pre,
+                                                          int nr) {
+  const int q = batch_find(pre, nr, blockIdx.x);
+  k_row_ref_body(A[q], blockIdx.x - pre[q]);
 }
 
 __global__ void __launch_bounds__(kBlock) k_lw_convert_batch(const lw_convert_args* __restrict__ A,
@@ -398,7 +524,8 @@ __global__ void __launch_bounds__(kBlock) k_lw_convert_batch(const lw_convert_ar
   const int q = batch_find(pre, nr, blockIdx.x);
   const lw_convert_args& a = A[q];
   if (a.pred && *a.pred == 0) return;
-  k_lw_convert_body(a.n, a.nparts, a.part, a.lw, a.bnd, a.lw2, a.ref_out, blockIdx.x - pre[q], pre[q + 1] - pre[q]);
+  k_lw_convert_body(a.n, a.nparts, a.part, a.lw, a.bnd, a.lw2, a.ref_out, blockIdx.x - pre[q], pre[q + 1] - pre[q],
+                    a.heavy);
 }
 
 
@@ -841,6 +968,15 @@ yy_status launch_batched(hipStream_t st, const lw_convert_args* A, const int* pr
   return YY_OK;
 }
 
+yy_status launch_batched(hipStream_t st, const RowRefArgs* A, const int* pre, int nr, int total) {
+  if (total <= 0) return YY_OK;
+  k_heavy_batch<<<nr, kBlock, 0, st>>>(A, pre, nr);
+  YY_LAUNCH_CHECK("k_heavy_batch");
+  k_row_ref_batch<<<total, kBlock, 0, st>>>(A, pre, nr);
+  YY_LAUNCH_CHECK("k_row_ref_batch");
+  return YY_OK;
+}
+
 yy_status launch_batched(hipStream_t st, const combine_args* A, const int* pre, int nr, int total) {
   if (total <= 0) return YY_OK;
   k_combine_batch<<<total, kBlock, 0, st>>>(A, pre, nr);
@@ -857,15 +993,19 @@ namespace yy {
 // Source weights relative to their maximum (step 2): lw2 [n] and the device
 // address of the maximum (in ctx->red).
 yy_status source_weights(yy_ctx ctx, int64_t n, const double* logw_in, const int* bnd, float* lw2,
-                         double** lref_out) {
+                         double** lref_out, long long** heavy_out) {
   const int nparts = (int)std::min<int64_t>((n + kBlock - 1) / kBlock, 1024);
   yy_status st;
-  if ((st = ctx->red.ensure((size_t)(nparts + 8) * sizeof(double))) != YY_OK) return st;
+  if ((st = ctx->red.ensure((size_t)(2 * nparts + 8) * sizeof(double))) != YY_OK) return st;
   double* d_part = ctx->red.as<double>();
   double* d_lref = d_part + nparts;
+  // [nparts + 1]: j* (k_heavy); [nparts + 8 ..]: the conversion blocks' candidates
+  long long* d_heavy = reinterpret_cast<long long*>(d_part + nparts + 8);
+  if (heavy_out) *heavy_out = d_heavy;
   k_lw_max<<<nparts, kBlock, 0, ctx->stream>>>(n, logw_in, bnd, d_part);
   YY_LAUNCH_CHECK("k_lw_max");
-  k_lw_convert<<<nparts, kBlock, 0, ctx->stream>>>(n, nparts, d_part, logw_in, bnd, lw2, d_lref);
+  k_lw_convert<<<nparts, kBlock, 0, ctx->stream>>>(n, nparts, d_part, logw_in, bnd, lw2, d_lref,
+                                                   heavy_out ? d_heavy : nullptr);
   YY_LAUNCH_CHECK("k_lw_convert");
   *lref_out = d_lref;
   return YY_OK;
@@ -938,7 +1078,9 @@ yy_status propagate_begin(yy_ctx ctx, const yy_model* model, const yy_scales* sc
   // (2) source weights relative to their maximum
   if ((st = ctx->lw2.ensure((size_t)n * sizeof(float))) != YY_OK) return st;
   double* d_lref = nullptr;
-  if ((st = source_weights(ctx, n, logw_in, P.bnd.as<int>(), ctx->lw2.as<float>(), &d_lref)) != YY_OK) return st;
+  long long* d_heavy = nullptr;
+  if ((st = source_weights(ctx, n, logw_in, P.bnd.as<int>(), ctx->lw2.as<float>(), &d_lref, &d_heavy)) != YY_OK)
+    return st;
 
   // (3) pairwise partials
   PairArgs& a = plan.a;
@@ -1014,6 +1156,36 @@ yy_status propagate_begin(yy_ctx ctx, const yy_model* model, const yy_scales* sc
   if ((st = ctx->part.ensure((size_t)nsplit * S * n * sizeof(float2))) != YY_OK) return st;
   a.part = ctx->part.as<float2>();
   if (mfma && (st = launch_src_bias(ctx->stream, a, ex)) != YY_OK) return st;
+  if (mfma && !pull) {
+    // a lower bound of every row maximum: the self pair, or the pair with the heaviest source
+    if ((st = ctx->rref.ensure((size_t)S * n * sizeof(float))) != YY_OK) return st;
+    RowRefArgs ra{};
+    ra.n = n;
+    ra.r = a.r;
+    ra.S = S;
+    ra.drift = model->drift;
+    ra.A = model->A;
+    ra.x = white ? static_cast<const double*>(P.wnodes.ptr) : x;
+    ra.fw = white ? static_cast<const double*>(P.wnodes.ptr) + (size_t)n * a.r : nullptr;
+    ra.lw2 = a.lw2;
+    ra.node = a.node;
+    ra.bnd = a.bnd;
+    ra.heavy = d_heavy;
+    ra.nheavy = (int)std::min<int64_t>((n + kBlock - 1) / kBlock, 1024);
+    ra.jstar = reinterpret_cast<long long*>(d_lref + 1);
+    if ((st = ctx->fstar.ensure((size_t)a.r * sizeof(double))) != YY_OK) return st;
+    ra.fstar = ctx->fstar.as<double>();
+    for (int s = 0; s < S; ++s) {
+      ra.kapd[s] = kapd[s];
+      ra.taud[s] = taud[s];
+    }
+    ra.rref = ctx->rref.as<float>();
+    k_heavy<<<1, kBlock, 0, ctx->stream>>>(ra);
+    YY_LAUNCH_CHECK("k_heavy");
+    k_row_ref<<<(unsigned)((n + kRowRefTargets - 1) / kRowRefTargets), kBlock, 0, ctx->stream>>>(ra);
+    YY_LAUNCH_CHECK("k_row_ref");
+    ex.rref = ra.rref;
+  }
 
   // (4) combination parameters
   CombineArgs& cb = plan.cb;
