@@ -276,10 +276,11 @@ static yy_status backward(yy_proposal p, int32_t B, const Work& w, float* g) {
 // lo, hi, then the centre, the half-width and kappa / half-width (the inverse
 // standard deviation) of the learned box.
 
-// One wavefront per sample t: counts of coordinates inside the learned box and
-// the sums of squared standardised deviations under both boxes (the log terms
-// of the densities do not depend on t and are added once in k_prop_decide);
-// per-block partials.
+// One wavefront per distinct resampled node (a run of equal ancestors), its
+// terms counted with the run's length: counts of coordinates inside the
+// learned box and the sums of squared standardised deviations under both boxes
+// (the log terms of the densities do not depend on the sample and are added
+// once in k_prop_decide); per-block partials.
 __global__ void __launch_bounds__(kBlock) k_prop_checks(int64_t n, int32_t r, const double* __restrict__ x,
                                                         const int64_t* __restrict__ idx,
                                                         const double* __restrict__ mean, double R,
@@ -295,11 +296,12 @@ __global__ void __launch_bounds__(kBlock) k_prop_checks(int64_t n, int32_t r, co
   const double* isL = box + 4 * r;
   const double isP = kKappa / R;
   double cov = 0.0, qL = 0.0, qP = 0.0;
+  double c1 = 0.0, l1 = 0.0, p1 = 0.0;   // one sample's terms
   auto coord = [&](double yd, double cd, double hd, double id, double md) {
     const double zl = (yd - cd) * id, zp = (yd - md) * isP;
-    cov += fabs(yd - cd) <= hd ? 1.0 : 0.0;
-    qL = fma(zl, zl, qL);
-    qP = fma(zp, zp, qP);
+    c1 += fabs(yd - cd) <= hd ? 1.0 : 0.0;
+    l1 = fma(zl, zl, l1);
+    p1 = fma(zp, zp, p1);
   };
   // 16-byte accesses to pairs of coordinates when the rows allow it
   const bool pairs = (r & 1) == 0 && ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(box) |
@@ -318,8 +320,23 @@ __global__ void __launch_bounds__(kBlock) k_prop_checks(int64_t n, int32_t r, co
     }
     __syncthreads();
   }
+  // The systematic resampling's ancestors are non-decreasing, so equal ones are contiguous: each
+  // distinct ancestor is read once and its terms count with their multiplicity (the first sample of
+  // a run finds the run's end by bisection).
   for (int64_t t = wave; t < n; t += nwaves) {
-    const double* y = x + (size_t)idx[t] * r;
+    const int64_t it = idx[t];
+    if (t > 0 && idx[t - 1] == it) continue;
+    int64_t lo = t + 1, hi = n;
+    while (lo < hi) {
+      const int64_t mid = lo + (hi - lo) / 2;
+      if (idx[mid] == it) lo = mid + 1;
+      else hi = mid;
+    }
+    const double mult = (double)(lo - t);
+    const double* y = x + (size_t)it * r;
+    c1 = 0.0;
+    l1 = 0.0;
+    p1 = 0.0;
     if (staged) {
       const double2* y2 = reinterpret_cast<const double2*>(y);
       for (int32_t d = lane; d < r / 2; d += 64) {
@@ -339,6 +356,9 @@ __global__ void __launch_bounds__(kBlock) k_prop_checks(int64_t n, int32_t r, co
     } else {
       for (int32_t d = lane; d < r; d += 64) coord(y[d], c[d], hw[d], isL[d], mean[d]);
     }
+    cov = fma(mult, c1, cov);
+    qL = fma(mult, l1, qL);
+    qP = fma(mult, p1, qP);
   }
   const double ldL = qL, ldP = qP;
   const double a = block_sum<kBlock>(cov, sh);
