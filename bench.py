@@ -82,12 +82,12 @@ def screened_work(w, prec, flagged, tiles):
     return screen + split, screen + 2.0 * split
 
 
-def run_gpu(w, dys, prec, warmup, steps, timing=True, proposal_params=None):
+def run_gpu(w, dys, prec, warmup, steps, timing=True, proposal_params=None, form="push", operator=False):
     import torch
     from paper_2509_16896_amd import yy
     from paper_2509_16896_amd.filter import GpuFilter
 
-    f = GpuFilter(w, prec=prec, proposal_params=proposal_params)
+    f = GpuFilter(w, prec=prec, proposal_params=proposal_params, form=form, operator=operator)
     f.set_observations(dys)
     f.init()
     k = 0
@@ -160,7 +160,7 @@ def traffic_probe(w, prec):
     log(f"[bench] traffic probe done ({prec}, source hash {kernel_source_hash()})")
 
 
-def cpu_baseline(w, f, k_last, target_s=15.0):
+def cpu_baseline(w, f, k_last, target_s=15.0, form="push"):
     """The oracle on a bounded sample of one step of the same workload: the propagation of a
     few target rows (extrapolated to all n rows) plus the full correction and normalisation."""
     import numpy as np
@@ -178,6 +178,7 @@ def cpu_baseline(w, f, k_last, target_s=15.0):
     model = ofilter.model_of(w)
     s = np.asarray(w.scales, float)
     c = oracle.kernel_coefficients(s)
+    oform = oracle.FORM_PULL if form == "pull" else oracle.FORM_PUSH
     rng = np.random.default_rng(0)
     order = rng.permutation(w.n)
     # target rows in growing batches until about target_s seconds of oracle work are done
@@ -185,7 +186,7 @@ def cpu_baseline(w, f, k_last, target_s=15.0):
     while t_rows < target_s and done < w.n:
         rows_b = np.sort(order[done:done + batch])
         t0 = time.perf_counter()
-        ref_b, _ = oracle.propagate_rows(model, s, c, x, lo, hi, w.dt, lw, rows_b)
+        ref_b, _ = oracle.propagate_rows_ex(model, s, c, x, lo, hi, w.dt, lw, rows_b, form=oform)
         t_rows += time.perf_counter() - t0
         parts.append((rows_b, ref_b))
         done += len(rows_b)
@@ -348,6 +349,12 @@ def main():
                          "passed, so the default step does not pay for it")
     ap.add_argument("--train-runs", type=int, default=2, help="plain-restart runs that supply training pairs")
     ap.add_argument("--train-steps", type=int, default=300)
+    ap.add_argument("--form", default="push", choices=["push", "pull"],
+                    help="first-order kernel: push form (default) or the pull form of eq. kernel (its "
+                         "divergence in closed form); the screened forms are push-form only")
+    ap.add_argument("--operator", action="store_true",
+                    help="predict with the stored operator (Sec. 10 offline/online split): built once per node "
+                         "set inside the timed loop, applied every step; the roofline is the apply's HBM stream")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="one 1 GiB copy + one yy_propagate, for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE")
     args = ap.parse_args()
@@ -357,7 +364,7 @@ def main():
         sys.exit(2)
 
     if args.prec is None:
-        args.prec = "bf16x3p"
+        args.prec = "bf16x3g" if args.form == "pull" else ("fp32" if args.operator else "bf16x3p")
     if args.workload == "batch64":
         return main_batch(args)
 
@@ -391,7 +398,8 @@ def main():
                      "loss_first_last": [round(losses[0][1], 4), round(losses[-1][1], 4)],
                      "setup_s": round(time.perf_counter() - t0, 2)}
         log(f"[bench] proposal trained on {X.shape[0]} pairs in {prop_info['setup_s']} s, loss {losses}")
-    f, k_last, elapsed, ms, launches = run_gpu(w, dys, args.prec, args.warmup, args.steps, proposal_params=params)
+    f, k_last, elapsed, ms, launches = run_gpu(w, dys, args.prec, args.warmup, args.steps, proposal_params=params,
+                                               form=args.form, operator=args.operator)
     if prop_info is not None:
         prop_info["used_fraction"] = round(int(f.used_count.item()) / max(f.restarts - 0, 1), 3)
     steps_s = args.steps / elapsed
@@ -437,6 +445,21 @@ def main():
     roofline["method_work_flop_per_launch"] = method
     roofline["method_dense_at_peak_ms"] = round(dense_at_peak_ms, 4)
     roofline["frac_method_basis"] = round(dense_at_peak_ms / (1e3 * avg_kernel_s), 4)
+    op_info = None
+    if args.operator:
+        # the online stage streams the stored exponents once: S n ld FP32 values, the n FP32 source
+        # weights, and S n partial (max, sum) pairs written
+        from paper_2509_16896_amd import yy
+        nn, S, ebytes = yy.yy_operator_info(f.op)
+        nbytes = ebytes + 4 * nn + 8 * S * nn
+        gbs = nbytes / avg_kernel_s / 1e9
+        roofline = {"bound": "hbm", "achieved": round(gbs, 2), "peak": 8000.0, "unit": "GB/s",
+                    "frac": round(gbs / 8000.0, 4), "traffic": None,
+                    "work_basis": "bytes per apply: S n ceil(n/64)*64 stored FP32 exponents + 4 n + 8 S n",
+                    "work_bytes_per_launch": nbytes, "kernel": "k_op_apply", "kernel_ms": round(1e3 * avg_kernel_s, 4)}
+        op_info = {"stored_bytes": ebytes, "builds_in_timed_steps": int(sum(
+            1 for k in range(k_last - args.steps + 1, k_last + 1) if w.restart_every and k % w.restart_every == 1))}
+        log(f"[bench] operator apply {1e3 * avg_kernel_s:.4f} ms, {gbs:.0f} GB/s of {nbytes / 1e6:.1f} MB")
 
     forms = {}
     if args.other_forms != "none":
@@ -486,7 +509,7 @@ def main():
     parity = None
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on a sample of the step ...")
-        cpu, sample = cpu_baseline(w, f, k_last, args.cpu_seconds)
+        cpu, sample = cpu_baseline(w, f, k_last, args.cpu_seconds, form=args.form)
         parity = sampled_parity(w, f, args.prec, sample)
         log(f"[bench] oracle {cpu['value']:.3g} steps/s on {cpu['cores']} threads; sampled rows max rel err {parity:.3g}")
     f.close()
@@ -499,7 +522,8 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
         "data": "synthetic",
         "config": {"workload": w.name, "r": w.r, "n": w.n, "dt": w.dt, "scales": list(w.scales),
-                   "restart_every": w.restart_every, "R": w.R, "precision": args.prec},
+                   "restart_every": w.restart_every, "R": w.R, "precision": args.prec, "form": args.form,
+                   "operator": args.operator},
         "propagation_tflops_executed": round(alg * args.steps / elapsed / 1e12, 3),
         "roofline": roofline,
         "roofline_dense": roofline_dense,
@@ -509,6 +533,7 @@ def main():
         "vs_plain_fp32_equal_algorithm_pairwise": equal_alg,
         "other_forms": forms or None,
         "proposal": prop_info,
+        "operator": op_info,
         "sampled_row_max_rel_err": parity,
         "cpu_baseline": cpu,
     }

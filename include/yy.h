@@ -171,7 +171,11 @@ typedef enum {
 } yy_prec;
 /* Every matrix-core form keeps each pair whose exponent may lie within 2^-80
  * of its row maximum exact (FP32 direct differences) and drops the others, so
- * all forms agree with YY_PREC_FP32 to FP32 rounding.  BF16X3S first runs a
+ * all forms agree with YY_PREC_FP32 to FP32 rounding.  In the push form, a row
+ * whose self term lies more than 160 bits below the heaviest source weight
+ * takes its pair with the heaviest source j* (the first source of maximal
+ * weight) in FP64 direct differences, counted once at the start of the row's
+ * sum and left out of the tiles and screens.  BF16X3S first runs a
  * screen that forms x_i.x_j with one BF16 product and bounds the tau-scaled
  * x_i.f_j term by |x_i| max_j |f_j|; the split form then visits only the
  * 256-target x 128-source tiles the screen could not rule out.  BF16X3P

@@ -428,6 +428,7 @@ static yy_status build(yy_batch b) {
       ra.taud[s2] = R.plan.taud[s2];
     }
     ra.rref = R.rc->rref.as<float>();
+    ra.rhv = ra.rref + (size_t)b->S * n;
     Rr.push_back(ra);
     b_rr.push_back((int)((n + 15) / 16));
   }
@@ -734,9 +735,13 @@ extern "C" yy_status yy_batch_run_graph(yy_batch b, int32_t k_end) {
     if (!b->exec || b->g_parity != parity) {
       drop_graph(b);
       YY_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+      // the captured steps advance the host-side step counters, but nothing runs until a replay: put
+      // every counter back as it was, whether or not both steps were recorded
+      std::vector<int32_t> k_saved(b->runs.size());
+      for (size_t i = 0; i < b->runs.size(); ++i) k_saved[i] = b->runs[i].k;
       yy_status s = batch_step_impl(b);
       if (s == YY_OK) s = batch_step_impl(b);
-      for (BRun& R : b->runs) R.k -= 2;   // nothing ran yet
+      for (size_t i = 0; i < b->runs.size(); ++i) b->runs[i].k = k_saved[i];
       hipGraph_t g = nullptr;
       const hipError_t ec = hipStreamEndCapture(st, &g);
       if (s != YY_OK || ec != hipSuccess) {

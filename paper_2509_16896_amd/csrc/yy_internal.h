@@ -128,7 +128,7 @@ struct yy_ctx_s {
   yy::DevBuf bsrc;                    // matrix-core source biases
   yy::DevBuf sflags;                  // screen verdicts of the screened split form
   yy::DevBuf obsw;                    // general observation noise: h(x) rows, W_b h(x) rows, W_b dy
-  yy::DevBuf rref;                    // float [S][n]: lower bounds of the pairwise rows' maxima
+  yy::DevBuf rref;                    // float [2][S][n]: lower bounds of the pairwise rows' maxima, heavy-pair terms
   yy::DevBuf fstar;                   // double [r]: f at the heaviest source
   int64_t sflags_tbs = 0, sflags_jtl = 0;   // their shape at the last screened propagation
   // tuned source-split counts: (rp, n_pad, S, prec) -> nsplit
@@ -217,6 +217,8 @@ struct MfmaExtra {
   float* bpre;                 // BF16X3P: source biases over the first kPreK coordinates, laid out as bsrc
   const DeferredPrep* deferred;   // BF16X3P on one run with deferred planes, else null
   const float* rref = nullptr;     // [S][n] lower bounds of the row maxima (push form), or null: self pairs
+  const float* rhv = nullptr;      // [S][n] the pair (i, j*) counted apart (exact term), or -inf; with rref
+  const long long* jstar = nullptr;   // j*, the heaviest source (-1: none); with rref
 };
 // blocks of the node preparation kernel (one wave per 4 nodes, grid-stride)
 int prepare_blocks(int64_t n_pad);
@@ -498,7 +500,8 @@ struct RowRefArgs {
   long long* jstar;       // j*, the first valid source of maximal weight (-1: none)
   double* fstar;          // [r] f(x_j*)
   double kapd[YY_MAX_SCALES], taud[YY_MAX_SCALES];
-  float* rref;            // [S][n]
+  float* rref;            // [S][n] the rows' lower bounds
+  float* rhv;             // [S][n] the exact term of the pair (i, j*) where the row counts it apart, else -inf
 };
 
 struct combine_args {

@@ -91,7 +91,28 @@ struct MArgs {
   int* any_flag;               // deferred planes: k_src_bias clears it, the screen sets it on a flagged tile
   int32_t pull;                // pull-form kernel (biases and the sign of c2 follow it)
   const float* rref;           // [S][n] lower bounds of the row maxima (>= the self-pair exponent), or null
+  const float* rhv;            // [S][n] with rref: the exact term of the pair (i, j*) where the row counts it
+                               // at initialisation and leaves it out of the tiles, else -inf
+  const long long* jstar;      // with rref: j*, the heaviest source (-1: none)
 };
+
+// j* of the call (-1: none, or no rows floor), read once per block and kept in scalar registers
+// (the argument set may come from global memory).
+__device__ inline int64_t heavy_source(const MArgs& a) {
+  const long long v = a.jstar ? *a.jstar : -1;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(unsigned long long)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((unsigned long long)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Slab index jb * 16 + v, in the lane half g, of source offset d from the lane
+// group's first source (the 32 x 32 accumulator layout: source 8 (v >> 2) +
+// 4 g + (v & 3) of block jb); -1 if this lane half does not hold it.
+template <int NJB>
+__device__ inline int slab_index(int64_t d, int g) {
+  return (d >= 0 && d < 32 * NJB && (int)((d >> 2) & 1) == g) ? (int)((d >> 5) * 16 + ((d >> 3) & 3) * 4 + (d & 3))
+                                                               : -1;
+}
 
 // Physical 16-byte chunk of logical chunk c in LDS row `row` (bank-conflict swizzle).
 // A 32-lane group reads 16 bytes from each of 32 consecutive rows; the XOR
@@ -222,14 +243,13 @@ __device__ __noinline__ float2 refine_slab(const Rare* rr, int64_t i, int64_t jb
 template <int S, bool PULL>
 __device__ inline void epilogue_target(const MArgs& a, const Rare* rare, const f32x16_t (&G)[kJB],
                                        const f32x16_t (&H)[kJB], const float* sb, int64_t i, int64_t j0,
-                                       int jl0, int g, bool diag, const float (&at)[S],
+                                       int jl0, int g, bool diag, int bheavy, const float (&at)[S],
                                        const float (&margin)[S], float (&M)[S], float (&Ssum)[S]) {
   // The self pair (source j = i) is accounted for at initialisation; this
   // lane holds it iff d = i - j0 - jl0 is in [0, 32 kJB) with bit 2 equal to g.
-  const int64_t d = i - j0 - jl0;
-  const bool self = diag && d >= 0 && d < 32 * kJB && (int)((d >> 2) & 1) == g;
-  // slab index jb * 16 + v of the self pair in this lane (-1: none)
-  const int bself = self ? (int)((d >> 5) * 16 + ((d >> 3) & 3) * 4 + (d & 3)) : -1;
+  // bself: its slab index in this lane (-1: none); bheavy: the same for the
+  // pair (i, j*) where the row counts that one at initialisation too.
+  const int bself = diag ? slab_index<kJB>(i - j0 - jl0, g) : -1;
 #pragma unroll
   for (int s = 0; s < S; ++s) {
     const float c1 = a.c1[s], c2 = a.c2[s];
@@ -240,7 +260,7 @@ __device__ inline void epilogue_target(const MArgs& a, const Rare* rare, const f
       for (int v = 0; v < 16; ++v) {
         const int jl = jb * 32 + 8 * (v >> 2) + 4 * g + (v & 3);
         float e = fmaf(c2, H[jb][v], fmaf(c1, G[jb][v], at[s] + sb[s * kMJ + jl0 + jl]));
-        if (jb * 16 + v == bself) e = -INFINITY;
+        if (jb * 16 + v == bself || jb * 16 + v == bheavy) e = -INFINITY;
         m = fmaxf(m, e);
       }
     // Every exact exponent of the slab is at most m + (margin - kSkip - 16): below
@@ -253,7 +273,7 @@ __device__ inline void epilogue_target(const MArgs& a, const Rare* rare, const f
       for (int v = 0; v < 16; ++v) {
         const int jl = jb * 32 + 8 * (v >> 2) + 4 * g + (v & 3);
         float x = fmaf(c2, H[jb][v], fmaf(c1, G[jb][v], at[s] + sb[s * kMJ + jl0 + jl]));
-        if (jb * 16 + v == bself) x = -INFINITY;
+        if (jb * 16 + v == bself || jb * 16 + v == bheavy) x = -INFINITY;
         e[jb * 16 + v] = x;
       }
     const float2 r = refine_slab<PULL>(rare, i, j0 + jl0, g, s, margin[s], e, M[s], Ssum[s]);
@@ -310,7 +330,8 @@ __device__ inline void merge_and_store(const MArgs& a, float (&M)[kIB][S], float
 // margin adds the skip depth and 16 bits of safety.
 template <int S>
 __device__ inline void init_targets(const MArgs& a, int64_t i0, int split, float (&at)[kIB][S],
-                                    float (&M)[kIB][S], float (&Ssum)[kIB][S], float (&margin)[S]) {
+                                    float (&M)[kIB][S], float (&Ssum)[kIB][S], float (&margin)[S],
+                                    bool (&hv)[kIB]) {
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wi = wave / kWJ, wj = wave % kWJ, col = lane & 31, g = lane >> 5;
   const double X = a.scal[1], F = a.scal[2];
@@ -332,9 +353,12 @@ __device__ inline void init_targets(const MArgs& a, int64_t i0, int split, float
     // The self pair is one of the terms, so its exact exponent bounds the row
     // maximum from below: every partial state starts at it (tiles far below
     // are then skipped untouched) and exactly one state -- the one whose
-    // source range holds j = i -- starts with it counted.
+    // source range holds j = i -- starts with it counted.  Where the row's
+    // bound is the pair with the heaviest source j*, that state also counts
+    // that pair's exact term, and the tiles leave it out (hv).
     const bool owner = valid && (int64_t)split == i / a.j_per_split && wj == (int)((i % kMJ) / (32 * kJB)) &&
                        g == (int)((i >> 2) & 1);
+    hv[ib] = valid && a.rhv && a.rhv[i] != -INFINITY;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       // target term: -kap |x_i|^2 (push), -kap |x_i - tau f_i|^2 (pull)
@@ -346,6 +370,10 @@ __device__ inline void init_targets(const MArgs& a, int64_t i0, int split, float
       const float ref = (valid && a.rref) ? a.rref[(size_t)s * a.n + i] : self;
       M[ib][s] = ref;
       Ssum[ib][s] = (owner && self != -INFINITY) ? (self == ref ? 1.f : fast_exp2(self - ref)) : 0.f;
+      if (owner && hv[ib]) {
+        const float h = a.rhv[(size_t)s * a.n + i];
+        Ssum[ib][s] += h == ref ? 1.f : fast_exp2(h - ref);
+      }
     }
   }
 }
@@ -700,8 +728,10 @@ __device__ __forceinline__ void pair_block(const MArgs& a, int tb, int split, un
           for (int s = 0; s < S; ++s) {
             const float self = li != -INFINITY ? li - (float)(a.kapd[s] * a.taud[s] * a.taud[s] * nf) : -INFINITY;
             const float M0 = a.rref ? a.rref[(size_t)s * a.n + i] : self;
-            a.part[((size_t)split * S + s) * a.n + i] =
-                make_float2(M0, (own && self != -INFINITY) ? (self == M0 ? 1.f : fast_exp2(self - M0)) : 0.f);
+            const float h = a.rhv ? a.rhv[(size_t)s * a.n + i] : -INFINITY;
+            float sum = (own && self != -INFINITY) ? (self == M0 ? 1.f : fast_exp2(self - M0)) : 0.f;
+            if (own && h != -INFINITY) sum += h == M0 ? 1.f : fast_exp2(h - M0);
+            a.part[((size_t)split * S + s) * a.n + i] = make_float2(M0, sum);
           }
         }
       }
@@ -717,7 +747,9 @@ __device__ __forceinline__ void pair_block(const MArgs& a, int tb, int split, un
   const uint32_t sb_lds = __builtin_amdgcn_readfirstlane(lds_addr(&sbuf[0][0]));
 
   float at[kIB][S], M[kIB][S], Ssum[kIB][S], margin[S];
-  init_targets<S>(a, i0, split, at, M, Ssum, margin);
+  bool hv[kIB];
+  init_targets<S>(a, i0, split, at, M, Ssum, margin, hv);
+  const int64_t jstar = heavy_source(a);
 
   for (int w0 = 0; w0 < ntiles_all; w0 += FLAGGED ? kTileWindow : ntiles_all) {
     int ntiles = ntiles_all;
@@ -795,13 +827,15 @@ __device__ __forceinline__ void pair_block(const MArgs& a, int tb, int split, un
       }
       const float* sb = &sbuf[t & 1][0];
       const bool diag = j0 < i0 + kMI && i0 < j0 + kMJ;
+      const bool htile = jstar >= j0 && jstar < j0 + kMJ;
 #pragma unroll
       for (int ib = 0; ib < kIB; ++ib) {
         const int64_t i = i0 + wi * (32 * kIB) + ib * 32 + col;
+        const int bheavy = (htile && hv[ib]) ? slab_index<kJB>(jstar - j0 - wj * (32 * kJB), g) : -1;
         // keep one target's accumulators in flight at a time (register pressure)
         __builtin_amdgcn_sched_barrier(0);
-        epilogue_target<S, PULL>(a, &rare, G[ib], H[ib], sb, i, j0, wj * (32 * kJB), g, diag, at[ib], margin,
-                                 M[ib], Ssum[ib]);
+        epilogue_target<S, PULL>(a, &rare, G[ib], H[ib], sb, i, j0, wj * (32 * kJB), g, diag, bheavy, at[ib],
+                                 margin, M[ib], Ssum[ib]);
       }
       __builtin_amdgcn_sched_barrier(0);
     }
@@ -932,6 +966,8 @@ __device__ __forceinline__ void screen_block(const MArgs& a, int tb, int split, 
   const double X = a.scal[1], F = a.scal[2];
   const double gam = a.rp * 0x1p-24;
   float at[kIB][S], M[kIB][S], margin[S], slack[kIB][S];
+  bool hv[kIB];   // the row counts the pair (i, j*) apart: it is no pair of the verdict
+  const int64_t jstar = heavy_source(a);
 #pragma unroll
   for (int s = 0; s < S; ++s) {
     const double XT = X + a.taud[s] * F;
@@ -942,6 +978,7 @@ __device__ __forceinline__ void screen_block(const MArgs& a, int tb, int split, 
   for (int ib = 0; ib < kIB; ++ib) {
     const int64_t i = i0 + wi * (32 * kIB) + ib * 32 + col;
     const bool valid = i < a.n;
+    hv[ib] = valid && a.rhv && a.rhv[i] != -INFINITY;
     const double nx = valid ? a.node[i] : 0.0;
     const double nf = valid ? a.node[a.n + i] : 0.0;
     const double nxf = valid ? a.node[2 * a.n + i] : 0.0;
@@ -1002,17 +1039,20 @@ __device__ __forceinline__ void screen_block(const MArgs& a, int tb, int split, 
     const float* sb = &sbuf[t & 1][0];
     const bool diag = j0 < i0 + kMI && i0 < j0 + kSJ;
     const int jl0 = wj * (32 * kSJB);
+    const bool htile = jstar >= j0 + jl0 && jstar < j0 + jl0 + 32 * kSJB;
     bool need = false;
-    int bself[kIB];   // slab index jb * 16 + v of the self pair in this lane (-1: none)
+    // slab indices jb * 16 + v in this lane of the self pair and of the pair (i, j*) where the row
+    // counts that one apart (-1: none)
+    int bself[kIB], bheavy[kIB];
 #pragma unroll
     for (int ib = 0; ib < kIB; ++ib) {
-      const int64_t d = i0 + wi * (32 * kIB) + ib * 32 + col - j0 - jl0;
-      const bool self = diag && d >= 0 && d < 32 * kSJB && (int)((d >> 2) & 1) == g;
-      bself[ib] = self ? (int)((d >> 5) * 16 + ((d >> 3) & 3) * 4 + (d & 3)) : -1;
+      const int64_t i = i0 + wi * (32 * kIB) + ib * 32 + col;
+      bself[ib] = diag ? slab_index<kSJB>(i - j0 - jl0, g) : -1;
+      bheavy[ib] = (htile && hv[ib]) ? slab_index<kSJB>(jstar - j0 - jl0, g) : -1;
     }
     // scales outermost: each source bias is read once for both target blocks;
     // the per-target term a_i + hx_i F is added after the maximum, and only a
-    // tile that holds self pairs compares slab indices
+    // tile that holds self pairs or j* compares slab indices
     auto scan = [&](auto with_self) {
 #pragma unroll
       for (int s = 0; s < S; ++s) {
@@ -1029,7 +1069,8 @@ __device__ __forceinline__ void screen_block(const MArgs& a, int tb, int split, 
 #pragma unroll
             for (int ib = 0; ib < kIB; ++ib) {
               float e = fmaf(c1, G[ib][jb][v], bj);
-              if (decltype(with_self)::value && jb * 16 + v == bself[ib]) e = -INFINITY;
+              if (decltype(with_self)::value && (jb * 16 + v == bself[ib] || jb * 16 + v == bheavy[ib]))
+                e = -INFINITY;
               m[ib] = fmaxf(m[ib], e);
             }
           }
@@ -1068,7 +1109,7 @@ __device__ __forceinline__ void screen_block(const MArgs& a, int tb, int split, 
       for (int ib = 0; ib < kIB; ++ib) doubt |= fmaf(a.c1[s], gmax[ib], bm) + at[ib][s] > M[ib][s] - margin[s];
     }
     if (__any(doubt)) {
-      if (diag) scan(std::true_type{});
+      if (diag || htile) scan(std::true_type{});
       else scan(std::false_type{});
     }
     __builtin_amdgcn_sched_barrier(0);
@@ -1155,10 +1196,13 @@ __device__ __forceinline__ void prescreen_block(const MArgs& a, int tb, int spli
   }
   // the targets' fragments, all PC stages (rows i0 .. i0 + 255 < n_pad)
   bf16x8_t bt[PC][kIB];
+  bool hv[kIB];   // the row counts the pair (i, j*) apart: it is no pair of the verdict
+  const int64_t jstar = heavy_source(a);
 #pragma unroll
   for (int ib = 0; ib < kIB; ++ib) {
     const int64_t i = i0 + wi * (32 * kIB) + ib * 32 + col;
     const bool valid = i < a.n && !a.bnd[i];
+    hv[ib] = valid && a.rhv && a.rhv[i] != -INFINITY;
     const double nx = valid ? a.node[3 * a.n + i] : 0.0;
     const double nf = valid ? a.node[a.n + i] : 0.0;
     const float li = valid ? a.lw2[i] : -INFINITY;
@@ -1260,12 +1304,15 @@ __device__ __forceinline__ void prescreen_block(const MArgs& a, int tb, int spli
     }
     bool need = false;
     if (__any(doubt)) {
-      int bself[kIB];   // slab index jb * 16 + v of the self pair in this lane (-1: none)
+      // slab indices jb * 16 + v in this lane of the self pair and of the pair (i, j*) where the row
+      // counts that one apart (-1: none)
+      const bool htile = jstar >= j0 && jstar < j0 + kPJ;
+      int bself[kIB], bheavy[kIB];
 #pragma unroll
       for (int ib = 0; ib < kIB; ++ib) {
-        const int64_t d = i0 + wi * (32 * kIB) + ib * 32 + col - j0;
-        const bool self = diag && d >= 0 && d < 32 * kSJB && (int)((d >> 2) & 1) == g;
-        bself[ib] = self ? (int)((d >> 5) * 16 + ((d >> 3) & 3) * 4 + (d & 3)) : -1;
+        const int64_t i = i0 + wi * (32 * kIB) + ib * 32 + col;
+        bself[ib] = diag ? slab_index<kSJB>(i - j0, g) : -1;
+        bheavy[ib] = (htile && hv[ib]) ? slab_index<kSJB>(jstar - j0, g) : -1;
       }
       // (the biases through the scalar cache: the addresses are wave-uniform
       // up to the lane half g, and a vector load would wait for the copies)
@@ -1288,7 +1335,7 @@ __device__ __forceinline__ void prescreen_block(const MArgs& a, int tb, int spli
 #pragma unroll
             for (int ib = 0; ib < kIB; ++ib) {
               float e = fmaf(c1, G[ib][jb][v], bj);
-              if (jb * 16 + v == bself[ib]) e = -INFINITY;
+              if (jb * 16 + v == bself[ib] || jb * 16 + v == bheavy[ib]) e = -INFINITY;
               m[ib] = fmaxf(m[ib], e);
             }
           }
@@ -1450,6 +1497,8 @@ static MArgs make_args(const PairArgs& pa, int prec, const MfmaExtra& ex) {
   m.pre_chunks = std::min(kPreK, (int)pa.rp) / kKC;
   m.any_flag = ex.deferred ? ex.deferred->defer : nullptr;
   m.rref = pa.pull ? nullptr : ex.rref;
+  m.rhv = pa.pull ? nullptr : ex.rhv;
+  m.jstar = pa.pull ? nullptr : ex.jstar;
   return m;
 }
 

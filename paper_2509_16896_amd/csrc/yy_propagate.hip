@@ -415,7 +415,11 @@ __global__ void __launch_bounds__(kBlock) k_lw_convert(int64_t n, int nparts,
 // direct differences: lw2_j* = 0, d = x_i - x_j* - tau_s f(x_j*)).  The second
 // is formed only for rows whose self term lies more than kRowRefGap bits below
 // the heaviest weight; elsewhere the self term is within kRowRefGap bits of
-// any term the heaviest source could give.  Rows: x (the nodes, or with
+// any term the heaviest source could give.  Where it is formed, that exact
+// term is also kept (rhv): the pairwise kernels count the pair (i, j*) at
+// initialisation from it, as they count the self pair, and leave it out of
+// their tiles and screens, so a posterior collapsed onto one node flags no
+// tile for its sake.  Rows: x (the nodes, or with
 // general noise their whitened images; the box centre cancels in the
 // differences).  k_heavy (one block) reduces the conversion blocks' candidates
 // to j* (the first valid source of maximal weight) and evaluates f(x_j*) once;
@@ -480,8 +484,11 @@ __device__ __forceinline__ void k_row_ref_body(const RowRefArgs& a, int bx_) {
   for (int u = wave; u < kRowRefTargets; u += kBlock / 64) {
     const int64_t i = i0 + u;
     if (i >= a.n) break;
-    float ref[YY_MAX_SCALES];
-    for (int s = 0; s < a.S; ++s) ref[s] = sself[s][u];
+    float ref[YY_MAX_SCALES], hv[YY_MAX_SCALES];
+    for (int s = 0; s < a.S; ++s) {
+      ref[s] = sself[s][u];
+      hv[s] = -INFINITY;
+    }
     if (sneed[u]) {
       const double* xi = a.x + (size_t)i * a.r;
       const double* xj = a.x + (size_t)js * a.r;
@@ -496,11 +503,15 @@ __device__ __forceinline__ void k_row_ref_body(const RowRefArgs& a, int bx_) {
       for (int s = 0; s < a.S; ++s) {
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) D[s] += __shfl_xor(D[s], off, 64);
-        ref[s] = fmaxf(ref[s], (float)(-a.kapd[s] * D[s]));
+        hv[s] = (float)(-a.kapd[s] * D[s]);
+        ref[s] = fmaxf(ref[s], hv[s]);
       }
     }
     if (lane == 0)
-      for (int s = 0; s < a.S; ++s) a.rref[(size_t)s * a.n + i] = ref[s];
+      for (int s = 0; s < a.S; ++s) {
+        a.rref[(size_t)s * a.n + i] = ref[s];
+        a.rhv[(size_t)s * a.n + i] = hv[s];
+      }
   }
 }
 
@@ -1158,7 +1169,7 @@ yy_status propagate_begin(yy_ctx ctx, const yy_model* model, const yy_scales* sc
   if (mfma && (st = launch_src_bias(ctx->stream, a, ex)) != YY_OK) return st;
   if (mfma && !pull) {
     // a lower bound of every row maximum: the self pair, or the pair with the heaviest source
-    if ((st = ctx->rref.ensure((size_t)S * n * sizeof(float))) != YY_OK) return st;
+    if ((st = ctx->rref.ensure(2 * (size_t)S * n * sizeof(float))) != YY_OK) return st;
     RowRefArgs ra{};
     ra.n = n;
     ra.r = a.r;
@@ -1180,11 +1191,14 @@ yy_status propagate_begin(yy_ctx ctx, const yy_model* model, const yy_scales* sc
       ra.taud[s] = taud[s];
     }
     ra.rref = ctx->rref.as<float>();
+    ra.rhv = ra.rref + (size_t)S * n;
     k_heavy<<<1, kBlock, 0, ctx->stream>>>(ra);
     YY_LAUNCH_CHECK("k_heavy");
     k_row_ref<<<(unsigned)((n + kRowRefTargets - 1) / kRowRefTargets), kBlock, 0, ctx->stream>>>(ra);
     YY_LAUNCH_CHECK("k_row_ref");
     ex.rref = ra.rref;
+    ex.rhv = ra.rhv;
+    ex.jstar = ra.jstar;
   }
 
   // (4) combination parameters

@@ -181,3 +181,45 @@ def test_deferred_planes_across_calls_on_one_node_set():
     finally:
         yy.yy_destroy(a)
         yy.yy_destroy(b)
+
+
+# A posterior collapsed onto one node j*: every other weight lies far below, so each row's maximum is
+# its pair with j* (the self pair lies far below it). The row floor counts that pair exactly at
+# initialisation and leaves it out of the tiles, so the screens flag no tile; j* in an inner tile, in
+# the ragged last tile, and where it shares a tile with the self pairs of a target block.
+COLLAPSED = {
+    "r100_n3000_jstar_inner": dict(r=100, n=3000, q=0.5, dt=0.02, half=0.3, seed=51, jstar=1300),
+    "r64_n9000_jstar_tail": dict(r=64, n=9000, q=1.0, dt=0.02, half=0.3, seed=52, jstar=8997),
+    "r200_n2000_jstar_first": dict(r=200, n=2000, q=1.0, dt=0.01, half=0.3, seed=53, jstar=0),
+}
+
+
+@pytest.mark.parametrize("name", sorted(COLLAPSED))
+def test_collapsed_posterior_flags_no_tile(ctx, name):
+    kw = dict(COLLAPSED[name])
+    jstar = kw.pop("jstar")
+    c = _case(**kw)
+    n = c["n"]
+    rng = np.random.default_rng(kw["seed"])
+    lw = -1e6 - 1e3 * rng.random(n)
+    lw[jstar] = 0.0
+    c["lw"] = lw
+    s = np.asarray(c["scales"])
+    ref = oracle.propagate(c["om"], s, oracle.kernel_coefficients(s), c["x"], c["lo"], c["hi"], c["dt"], lw)[0]
+    from gpu_util import compare_logw
+    g3 = _run(ctx, c, "bf16x3g")
+    for form in ("bf16x3p", "bf16x3s"):
+        got = _run(ctx, c, form)
+        flagged, tiles = yy.yy_screen_count(ctx)
+        print(f"{name}: {form} flagged {flagged} of {tiles} tiles")
+        assert flagged == 0
+        f = np.isfinite(g3)
+        assert np.array_equal(np.isfinite(got), f)
+        assert np.max(np.abs(got[f] - g3[f]) / np.maximum(1.0, np.abs(g3[f]))) < 2e-6
+        worst, cnt = compare_logw(got, ref, 1e-5)
+        print(f"{name}: {form} worst err/allowed = {worst:.3g} over {cnt} nodes")
+        assert worst <= 1.0
+        # every row's value is dominated by its pair with j*: against the oracle on all rows
+        fr = np.isfinite(ref)
+        assert np.array_equal(np.isfinite(got), fr)
+        assert np.max(np.abs(got[fr] - ref[fr]) / np.maximum(1.0, np.abs(ref[fr]))) < 1e-5
