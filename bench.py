@@ -21,6 +21,7 @@ and the FP64 oracle on a bounded sample of the same step on the host cores.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import hashlib
 import json
 import math
@@ -226,6 +227,106 @@ def sampled_parity(w, f, prec, sample):
     return float(np.max(rel)) if rel.size else float("nan")
 
 
+# the paper's table of its large-scale test: (r, n) -> time for 1000 steps (s), RMSE, ME, each mean and
+# standard deviation over 20 runs, on the paper's own hardware (context, not a target)
+PAPER_E1_TABLE = {10: ((0.271, 0.023), (0.165, 0.002), (0.160, 0.002)),
+                  50: ((1.006, 0.026), (0.368, 0.001), (0.365, 0.001)),
+                  100: ((4.824, 0.095), (0.523, 0.005), (0.520, 0.005)),
+                  300: ((16.833, 0.374), (0.964, 0.034), (0.955, 0.033)),
+                  600: ((37.160, 0.065), (1.376, 0.049), (1.356, 0.046)),
+                  1000: ((150.540, 6.431), (1.609, 0.013), (1.582, 0.012))}
+
+
+def main_e1_table(args):
+    """The paper's large-scale test at its six (r, n) sizes: 1000 filter steps per run, `seeds` runs
+    per size (truth path, observations and node scramble keyed by the seed), the wall time of the
+    1000 steps on the GPU (state initialised and observations resident before the clock starts), RMSE
+    and ME to the true path; printed beside the paper's own table."""
+    import numpy as np
+    import torch
+
+    from paper_2509_16896_amd import workloads as W
+    from paper_2509_16896_amd.filter import GpuFilter
+
+    out = []
+    for r, n in PAPER_E1:
+        times, rmses, mes = [], [], []
+        for sd in range(args.seeds):
+            w = W.paper_e1(r, seed=sd)
+            xs, dys = W.simulate(w)
+            f = GpuFilter(w, prec=args.prec)
+            try:
+                f.set_observations(dys)
+                f.init()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for k in range(1, w.K + 1):
+                    f.step(k)
+                torch.cuda.synchronize()
+                times.append(time.perf_counter() - t0)
+                est = f.hist.cpu().numpy()
+            finally:
+                f.close()
+            rmses.append(W.rmse(est, xs[1:]))
+            mes.append(W.mean_error(est, xs[1:]))
+        pt, pr, pm = PAPER_E1_TABLE[r]
+        row = {"r": r, "n": n, "steps": 1000, "runs": args.seeds,
+               "time_s": [round(float(np.mean(times)), 4), round(float(np.std(times)), 4)],
+               "rmse": [round(float(np.mean(rmses)), 4), round(float(np.std(rmses)), 4)],
+               "me": [round(float(np.mean(mes)), 4), round(float(np.std(mes)), 4)],
+               "paper_time_s": list(pt), "paper_rmse": list(pr), "paper_me": list(pm)}
+        out.append(row)
+        log(f"[bench] paper E1 r={r} n={n}: {row['time_s'][0]:.3f} s per 1000 steps, RMSE {row['rmse'][0]:.3f}, "
+            f"ME {row['me'][0]:.3f} (paper: {pt[0]} s, {pr[0]}, {pm[0]})")
+    print(json.dumps({"workload": "paper_e1_table", "precision": args.prec, "data": "synthetic",
+                      "sizes": out}), flush=True)
+
+
+def main_form_compare(args):
+    """Push form against the pull form of eq. kernel (divergence in closed form) on the cubic
+    sensor r=2 (n=1024, fixed box), the linear-Gaussian r=10 (n=4096) and the cubic sensor r=100
+    (n=16384): `seeds` full runs each, RMSE and ME to the true path and steps/s of the whole step.
+    The plain FP32 form where r < 32 (the matrix cores need r >= 32), the split form BF16X3G
+    otherwise (the screened forms are push-form only)."""
+    import numpy as np
+    import torch
+
+    from paper_2509_16896_amd import workloads as W
+    from paper_2509_16896_amd.filter import GpuFilter
+
+    out = []
+    for w0 in (W.cubic_r2(), W.linear_r10(), W.cubic_r100()):
+        prec = "fp32" if w0.r < 32 else "bf16x3g"
+        row = {"workload": w0.name, "r": w0.r, "n": w0.n, "K": w0.K, "precision": prec}
+        for form in ("push", "pull"):
+            rm, me, sps = [], [], []
+            for sd in range(args.seeds):
+                w = dataclasses.replace(w0, seed=sd)
+                xs, dys = W.simulate(w)
+                f = GpuFilter(w, prec=prec, form=form)
+                try:
+                    f.set_observations(dys)
+                    f.init()
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    for k in range(1, w.K + 1):
+                        f.step(k)
+                    torch.cuda.synchronize()
+                    sps.append(w.K / (time.perf_counter() - t0))
+                    est = f.hist.cpu().numpy()
+                finally:
+                    f.close()
+                rm.append(W.rmse(est, xs[1:]))
+                me.append(W.mean_error(est, xs[1:]))
+            row[form] = {"rmse": [round(float(np.mean(rm)), 4), round(float(np.std(rm)), 4)],
+                         "me": [round(float(np.mean(me)), 4), round(float(np.std(me)), 4)],
+                         "steps_per_s": round(float(np.mean(sps)), 1)}
+            log(f"[bench] {w0.name} {form}: RMSE {row[form]['rmse'][0]:.4f}, ME {row[form]['me'][0]:.4f}, "
+                f"{row[form]['steps_per_s']} steps/s")
+        out.append(row)
+    print(json.dumps({"workload": "push_vs_pull", "runs": args.seeds, "data": "synthetic", "rows": out}), flush=True)
+
+
 def main_batch(args):
     """The batch of 64 uneven cubic-sensor runs: aggregate filter steps/s of the graph-replayed
     step loop, beside the same batch stepped eagerly and the runs filtered one after another."""
@@ -355,6 +456,12 @@ def main():
     ap.add_argument("--operator", action="store_true",
                     help="predict with the stored operator (Sec. 10 offline/online split): built once per node "
                          "set inside the timed loop, applied every step; the roofline is the apply's HBM stream")
+    ap.add_argument("--e1-table", action="store_true",
+                    help="the paper's large-scale test at its six sizes: time, RMSE and ME over --seeds runs of "
+                         "1000 steps, beside the paper's table")
+    ap.add_argument("--seeds", type=int, default=20)
+    ap.add_argument("--form-compare", action="store_true",
+                    help="push form against the pull form on the r=2, r=10 and r=100 workloads over --seeds runs")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="one 1 GiB copy + one yy_propagate, for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE")
     args = ap.parse_args()
@@ -367,6 +474,10 @@ def main():
         args.prec = "bf16x3g" if args.form == "pull" else ("fp32" if args.operator else "bf16x3p")
     if args.workload == "batch64":
         return main_batch(args)
+    if args.e1_table:
+        return main_e1_table(args)
+    if args.form_compare:
+        return main_form_compare(args)
 
     import numpy as np
     import torch

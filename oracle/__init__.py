@@ -40,6 +40,25 @@ Parity status of the oracle's functions and the tests that pin each one:
 * restart -- pinned: the reference set translated by the estimate and its
   mean (test_oracle_bruteforce.py::test_restart_translates_the_reference_set),
   containment and the prior's closed form (test_oracle_update.py).
+* pull-form kernel (eq. kernel) -- pinned: single sources against scipy's
+  Gaussian log-density centred at x_i - tau f(x_i) times exp(-tau div f(x_i))
+  (test_oracle_pull_noise.py::test_pull_single_source_matches_gaussian_density);
+  50-digit double sums for n <= 64 with signed scales
+  (::test_pull_prediction_equals_50_digit_double_sum); first and second order
+  consistency and agreement with the push form
+  (::test_pull_form_consistency_orders_and_agreement_with_push).
+* divergence (closed forms; the complex-step sum of Sec. 8) -- pinned:
+  mpmath's 30-digit numerical derivative
+  (::test_divergence_closed_form_and_complex_step_against_numerical_derivative).
+* general noise a = U U^T, b = V V^T (Sec. 7) -- pinned: the Moore-Penrose
+  conditions, numpy's pinv and the log pseudo-determinant of a rank-deficient a
+  (::test_noise_pinv_moore_penrose_and_log_pseudo_determinant); a = q I against the
+  isotropic path; single sources against scipy's full-covariance Gaussian,
+  and in the range coordinates of a singular a; null-space invariance; the
+  observation update against scipy's likelihood ratio with covariance b dt,
+  invertible and singular (::test_general_noise_single_source_against_scipy,
+  ::test_general_noise_linearity_and_pseudo_inverse_invariance,
+  ::test_general_observation_noise_update).
 * learned restart proposal (``proposal.py``, NumPy) -- pinned: GELU against
   scipy's normal CDF, loss against the brute-force Gaussian log-density of
   samples, backward against finite differences, Adam's closed-form first

@@ -202,7 +202,7 @@ def _random_U(r, rank, seed):
     return Q @ np.diag(np.sqrt(lam)), Q, lam
 
 
-def test_noise_pinv_of_the_paper(oracle_lib):
+def test_noise_pinv_moore_penrose_and_log_pseudo_determinant(oracle_lib):
     U, Q, lam = _random_U(6, 4, 1)
     ap, logdet, rank = oracle.noise_pinv(U)
     assert rank == 4
