@@ -254,7 +254,7 @@ def main_e1_table(args):
         for sd in range(args.seeds):
             w = W.paper_e1(r, seed=sd)
             xs, dys = W.simulate(w)
-            f = GpuFilter(w, prec=args.prec)
+            f = GpuFilter(w, prec=args.prec_given or w.precision)
             try:
                 f.set_observations(dys)
                 f.init()
@@ -270,7 +270,7 @@ def main_e1_table(args):
             rmses.append(W.rmse(est, xs[1:]))
             mes.append(W.mean_error(est, xs[1:]))
         pt, pr, pm = PAPER_E1_TABLE[r]
-        row = {"r": r, "n": n, "steps": 1000, "runs": args.seeds,
+        row = {"r": r, "n": n, "steps": 1000, "runs": args.seeds, "precision": args.prec_given or w.precision,
                "time_s": [round(float(np.mean(times)), 4), round(float(np.std(times)), 4)],
                "rmse": [round(float(np.mean(rmses)), 4), round(float(np.std(rmses)), 4)],
                "me": [round(float(np.mean(mes)), 4), round(float(np.std(mes)), 4)],
@@ -278,7 +278,7 @@ def main_e1_table(args):
         out.append(row)
         log(f"[bench] paper E1 r={r} n={n}: {row['time_s'][0]:.3f} s per 1000 steps, RMSE {row['rmse'][0]:.3f}, "
             f"ME {row['me'][0]:.3f} (paper: {pt[0]} s, {pr[0]}, {pm[0]})")
-    print(json.dumps({"workload": "paper_e1_table", "precision": args.prec, "data": "synthetic",
+    print(json.dumps({"workload": "paper_e1_table", "data": "synthetic",
                       "sizes": out}), flush=True)
 
 
@@ -346,10 +346,18 @@ def main_batch(args):
         f"n in [{min(w.n for w in ws)}, {max(w.n for w in ws)}], K={K}, prec={args.prec}")
     bt = Batch(ws, dys, prec=args.prec)
     t0 = time.perf_counter()
-    bt.step()
-    best = bt.tune(reps=2)
+    if args.batch_forms == "rule":
+        for q, w in enumerate(ws):
+            if w.r < 32:
+                bt.set_run_form(q, "fp32")
+    for _ in range(4):     # a state past the first restarts: the screens' cost depends on the weights
+        bt.step()
+    best = bt.tune(reps=2, forms=args.batch_forms == "tuned")
     tune_s = time.perf_counter() - t0
-    log(f"[bench] tuned max source splits per run: {best} ({tune_s:.2f} s)")
+    forms = [bt.run_form(q) for q in range(len(ws))]
+    mfma_runs = [q for q, fm in enumerate(forms) if fm != "fp32"]
+    log(f"[bench] tuned: {len(ws) - len(mfma_runs)} runs on the vector ALUs (plain FP32), {len(mfma_runs)} in "
+        f"{args.prec}; max source splits per run {best} ({tune_s:.2f} s)")
 
     def run_eager():
         bt.reset()
@@ -386,18 +394,24 @@ def main_batch(args):
     kms = ms / max(cnt, 1)
     kernel = "k_pair_mfma_batch"
     dense = alg
+    # the matrix-core roofline counts the matrix-core runs' work; the vector-ALU runs' launch is inside
+    # the same timed region, so the rate is a lower bound
+    alg = sum(2.0 * ws[q].n * ws[q].n * ws[q].r * 2 for q in mfma_runs)
     if args.prec in ("bf16x3s", "bf16x3p"):
         # each run's screen products plus the method's products on its flagged tiles
-        counts = [bt.screen_count(q) for q in range(len(ws))]
-        alg = sum(screened_work(w, args.prec, fl, tl)[0] for w, (fl, tl) in zip(ws, counts))
+        counts = {q: bt.screen_count(q) for q in mfma_runs}
+        alg = sum(screened_work(ws[q], args.prec, fl, tl)[0] for q, (fl, tl) in counts.items())
         kernel = ("k_pair_prescreen_batch" if args.prec == "bf16x3p" else "k_pair_screen_batch") + \
             ", then k_pair_mfma_batch (split form) on flagged tiles"
-        log(f"[bench] screens flagged {sum(c[0] for c in counts)} of {sum(c[1] for c in counts)} tiles")
+        log(f"[bench] screens flagged {sum(c[0] for c in counts.values())} of "
+            f"{sum(c[1] for c in counts.values())} tiles")
+    if len(mfma_runs) < len(ws):
+        kernel += "; k_pair_valu_batch for the runs on the vector ALUs"
     bt.close()
     # the same runs one after another through the single-run calls
     t_seq = 0.0
-    for w, d in zip(ws, dys):
-        f = GpuFilter(w, prec=args.prec)
+    for w, d, fm in zip(ws, dys, forms):
+        f = GpuFilter(w, prec=fm)
         f.set_observations(d)
         f.init()
         torch.cuda.synchronize()
@@ -414,12 +428,14 @@ def main_batch(args):
         "unit": "steps/s", "n_gpus": 1, "steps": K, "warmup": 2, "ms_per_step": round(1e3 * t_graph / K, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
         "config": {"workload": "batch64_cubic_r10-200_n2048-32768", "runs": len(ws), "K": K,
-                   "precision": args.prec, "max_split": best},
+                   "precision": args.prec, "max_split": best, "forms": args.batch_forms,
+                   "runs_on_vector_alus": len(ws) - len(mfma_runs)},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_TFLOPS[args.prec],
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS[args.prec], 4), "traffic": None,
                      "kernel": kernel, "kernel_ms": round(kms, 3),
-                     "work_basis": "each run's screen products plus 2 n^2 r P on its flagged tiles"
-                     if args.prec in ("bf16x3s", "bf16x3p") else "2 n^2 r P of every run",
+                     "work_basis": ("each matrix-core run's screen products plus 2 n^2 r P on its flagged tiles"
+                                    if args.prec in ("bf16x3s", "bf16x3p") else "2 n^2 r P of every matrix-core run")
+                     + "; the timed launches include the vector-ALU runs",
                      "method_dense_at_peak_ms": round(dense / (PEAK_TFLOPS[args.prec] * 1e12) * 1e3, 4)},
         "eager_steps_per_s": round(steps / t_eager, 2),
         "sequential_single_run_steps_per_s": round(steps / t_seq, 2),
@@ -456,6 +472,10 @@ def main():
     ap.add_argument("--operator", action="store_true",
                     help="predict with the stored operator (Sec. 10 offline/online split): built once per node "
                          "set inside the timed loop, applied every step; the roofline is the apply's HBM stream")
+    ap.add_argument("--batch-forms", default="matrix", choices=["matrix", "tuned", "rule"],
+                    help="batch64: each run's pairwise form -- the matrix-core form for every run (matrix, the "
+                         "default), chosen per run by timing (tuned), or plain FP32 on the vector ALUs below "
+                         "r = 32 (rule)")
     ap.add_argument("--e1-table", action="store_true",
                     help="the paper's large-scale test at its six sizes: time, RMSE and ME over --seeds runs of "
                          "1000 steps, beside the paper's table")
@@ -470,6 +490,7 @@ def main():
         print(json.dumps({"error": "this build benchmarks one GPU only; run with --gpus 1"}))
         sys.exit(2)
 
+    args.prec_given = args.prec
     if args.prec is None:
         args.prec = "bf16x3g" if args.form == "pull" else ("fp32" if args.operator else "bf16x3p")
     if args.workload == "batch64":
@@ -486,6 +507,8 @@ def main():
 
     if args.workload.startswith("paper_e1_r"):
         w = W.paper_e1(int(args.workload[len("paper_e1_r"):]))
+        if args.prec_given is None and not args.operator and args.form == "push":
+            args.prec = w.precision   # the plain FP32 form below r = 32
     else:
         w = {"cubic_r1000": W.cubic_r1000, "cubic_r100": W.cubic_r100}[args.workload]()
     if args.traffic_probe:

@@ -407,8 +407,12 @@ typedef struct yy_batch_s* yy_batch;
 
 /* Creates the batch and its initial state (step 0: nodes, N(0, I) prior,
  * normalised).  prec: a matrix-core form (YY_PREC_FP32_MFMA, BF16X3, BF16X3G,
- * BF16X3S, BF16X3P or BF16X1; every run uses it).  max_split: upper bound of the source splits per
- * run (0: 16); yy_batch_tune can choose it. */
+ * BF16X3S, BF16X3P or BF16X1).  Each run takes its pairwise sum in that form
+ * (the default) or in the plain FP32 form on the vector ALUs (YY_PREC_FP32), as
+ * yy_batch_tune (with forms) or yy_batch_set_run_form choose; either way a run
+ * computes exactly what the single-run calls compute in its form.
+ * max_split: upper bound of the source splits per matrix-core run (0: 16);
+ * yy_batch_tune can choose it. */
 yy_status yy_batch_create(yy_ctx ctx, int32_t nruns, const yy_batch_run* runs, const yy_scales* scales,
                           int32_t prec, int32_t max_split, yy_batch* out);
 yy_status yy_batch_destroy(yy_batch b);
@@ -421,10 +425,22 @@ yy_status yy_batch_step(yy_batch b);
  * launched (k_end - k)/2 times; an odd remainder runs eagerly.  ctx's stream
  * must be a created stream (not the null stream) and timing must be off. */
 yy_status yy_batch_run_graph(yy_batch b, int32_t k_end);
-/* Tries max_split = 1, 2, 4, ..., 64 on the batched pairwise launch of the
- * current state (reps launches each after a warm-up; results discarded) and
- * keeps the fastest; best_out: host scalar or NULL.  Drops a captured graph. */
-yy_status yy_batch_tune(yy_batch b, int32_t reps, int32_t* best_out);
+/* Tunes the pairwise launches on the current state (reps launches per
+ * candidate after a warm-up; results discarded): with forms != 0 first each
+ * run's form, by timing its single-run pairwise call in the batch's
+ * matrix-core form and in YY_PREC_FP32 (runs of equal r and n share one
+ * decision; the screened forms' cost depends on the weights, so tune on a
+ * state a few steps in); then max_split = 1, 2, 4, ..., 64 on the batched
+ * launch.  Keeps the fastest; best_out (host scalar or NULL) receives
+ * max_split.  Drops a captured graph. */
+yy_status yy_batch_tune(yy_batch b, int32_t reps, int32_t forms, int32_t* best_out);
+/* The pairwise form of run `run`: the batch's matrix-core form or
+ * YY_PREC_FP32 (host scalar). */
+yy_status yy_batch_run_form(yy_batch b, int32_t run, int32_t* prec);
+/* Sets run `run`'s pairwise form (the batch's form or YY_PREC_FP32) and
+ * rebuilds the launches; the run continues from its current state.  Drops a
+ * captured graph; YY_ERR_UNSUPPORTED while the stream is capturing. */
+yy_status yy_batch_set_run_form(yy_batch b, int32_t run, int32_t prec);
 /* Results of run `run` so far: per-step posterior mean (device [K*r]), log
  * normaliser logZ_k (device [K]) and ESS (device [K]); each nullable.  Copies
  * on ctx's stream. */

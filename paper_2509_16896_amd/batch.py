@@ -56,12 +56,20 @@ class Batch:
     def run_graph(self, k_end: int):
         yy.yy_batch_run_graph(self.b, k_end)
 
-    def tune(self, reps: int = 3) -> int:
-        return yy.yy_batch_tune(self.b, reps)
+    def tune(self, reps: int = 3, forms: bool = False) -> int:
+        """Each run's pairwise form (forms=True), then the source splits; returns the split bound."""
+        return yy.yy_batch_tune(self.b, reps, forms)
 
     @property
     def k(self) -> int:
         return yy.yy_batch_step_count(self.b)
+
+    def run_form(self, run: int) -> str:
+        """Run `run`'s pairwise form: the batch's matrix-core form, or "fp32" on the vector ALUs."""
+        return yy.yy_batch_run_form(self.b, run)
+
+    def set_run_form(self, run: int, prec: str):
+        yy.yy_batch_set_run_form(self.b, run, prec)
 
     def screen_count(self, run: int):
         """(flagged tiles, tiles) of run `run`'s last screen (screened forms only)."""

@@ -117,10 +117,15 @@ struct yy_batch_s {
   unsigned char* pinned = nullptr; // staging for uploads
   size_t pinned_bytes = 0;
   bool built = false;
-  // the pairwise launch
+  // each run's form of the pairwise sum: the batch's matrix-core form (the default), or the plain FP32
+  // form on the vector ALUs (yy_batch_tune with forms, or yy_batch_set_run_form)
+  std::vector<int32_t> form;
+  // the pairwise launches: matrix-core runs, then vector-ALU runs by staging width (2, 4, 8, 16)
   yy::DevBuf d_sets, d_items;
   int nitems = 0;
-  bool k64 = true;                 // every run's K padding is a multiple of 64
+  bool k64 = true;                 // every matrix-core run's K padding is a multiple of 64
+  yy::DevBuf v_sets, v_items[4];
+  int v_nitems[4] = {0, 0, 0, 0};
   yy::BLaunch<int> src_bias;       // argument sets = d_sets
   // parity-dependent launches (index k % 2 of the step)
   yy::BLaunch<yy::lw_max_args> lw_max[2];
@@ -237,7 +242,8 @@ static yy_status build(yy_batch b) {
     // preparation after every restart, never by this call
     const int64_t jtl = (R.d.n + 127) / 128;
     const int split = (int)std::max<int64_t>(1, std::min<int64_t>(b->max_split, jtl));
-    if ((st = propagate_begin(R.rc, &R.d.model, &sc, b->prec, R.d.n, R.x.as<double>(), 1, R.lo.as<double>(),
+    const int32_t form = b->form[&R - b->runs.data()];
+    if ((st = propagate_begin(R.rc, &R.d.model, &sc, form, R.d.n, R.x.as<double>(), 1, R.lo.as<double>(),
                               R.hi.as<double>(), R.d.dt, R.lw[0].as<double>(), R.lw[1].as<double>(), split,
                               R.plan)) != YY_OK)
       return st;
@@ -254,9 +260,27 @@ static yy_status build(yy_batch b) {
     int64_t cost;
   };
   std::vector<Item> items;
-  std::vector<int> bias_blocks(nr);
+  std::vector<int> bias_blocks(nr, 0);
+  std::vector<ValuSet> vsets;
+  std::vector<int4> vitems[4];
   for (int q = 0; q < nr; ++q) {
     const PropPlan& P = b->runs[q].plan;
+    if (!P.mfma) {
+      // the vector-ALU form: the single-run launch's blocks (64 targets, its source splits)
+      ValuSet v{};
+      v.a = P.a;
+      v.per = valu_per(P.a);
+      for (int s = 0; s < b->S; ++s) {
+        v.taud[s] = P.taud[s];
+        v.kapd[s] = P.kapd[s];
+      }
+      const int kc = valu_kc(P.a.r), cls = kc == 2 ? 0 : kc == 4 ? 1 : kc == 8 ? 2 : 3;
+      const int64_t tiles = (P.n + 63) / 64;
+      for (int sp = 0; sp < P.a.nsplit; ++sp)
+        for (int64_t t = 0; t < tiles; ++t) vitems[cls].push_back(make_int4((int)vsets.size(), (int)t, sp, 0));
+      vsets.push_back(v);
+      continue;
+    }
     pair_mfma_fill_args(P.a, b->prec, P.ex, sets.data() + q * asz);
     bias_blocks[q] = nblk(P.ex.n_pad);
     const int64_t n = P.n, tbs = P.ex.n_pad / 256, jps = P.ex.j_per_split;
@@ -275,7 +299,13 @@ static yy_status build(yy_batch b) {
   if ((st = upload(b, b->d_items, it4.data(), it4.size() * sizeof(int4))) != YY_OK) return st;
   b->nitems = (int)items.size();
   b->k64 = true;
-  for (const BRun& R : b->runs) b->k64 = b->k64 && R.plan.a.rp % 64 == 0;
+  for (const BRun& R : b->runs) b->k64 = b->k64 && (!R.plan.mfma || R.plan.a.rp % 64 == 0);
+  if (!vsets.empty() && (st = upload(b, b->v_sets, vsets.data(), vsets.size() * sizeof(ValuSet))) != YY_OK) return st;
+  for (int c = 0; c < 4; ++c) {
+    b->v_nitems[c] = (int)vitems[c].size();
+    if (!vitems[c].empty() && (st = upload(b, b->v_items[c], vitems[c].data(), vitems[c].size() * sizeof(int4))) != YY_OK)
+      return st;
+  }
   if ((st = build_launch(b, b->src_bias, std::vector<int>{}, bias_blocks)) != YY_OK) return st;
 
   const BCtl* ctl = b->ctl.as<BCtl>();
@@ -335,8 +365,11 @@ static yy_status build(yy_batch b) {
         N1[post].push_back({n, lwo, pmax, pr});
         N2[post].push_back({n, nb, pmax, lwo, psum, pr});
         N3[post].push_back({nb, pmax, psum, scv, R.logZ_step.as<double>(), acc, R.rc->d_flags, pr});
-        N4[post].push_back({n, r, rows, scv, R.x.as<double>(), lwo, R.w.as<double>(), pw2, pmean, pr});
-        N5[post].push_back({nb, r, scv, pw2, pmean, R.mean.as<double>(), R.ess.as<double>(), pr});
+        // the restart prior's normalisation (post = 1) forms no moments and keeps no weights, as the
+        // single-run filter's: x is not read
+        N4[post].push_back({n, r, rows, scv, post ? nullptr : R.x.as<double>(), lwo, post ? nullptr : R.w.as<double>(),
+                            pw2, pmean, pr});
+        N5[post].push_back({nb, r, scv, pw2, pmean, post ? nullptr : R.mean.as<double>(), R.ess.as<double>(), pr});
       }
       b_nb.push_back(nb);
       b_one.push_back(1);
@@ -427,10 +460,11 @@ static yy_status build(yy_batch b) {
       ra.kapd[s2] = R.plan.kapd[s2];
       ra.taud[s2] = R.plan.taud[s2];
     }
-    ra.rref = R.rc->rref.as<float>();
-    ra.rhv = ra.rref + (size_t)b->S * n;
+    // (the vector-ALU form has no row floor: no heavy source, no blocks)
+    ra.rref = R.plan.mfma ? R.rc->rref.as<float>() : nullptr;
+    ra.rhv = R.plan.mfma ? ra.rref + (size_t)b->S * n : nullptr;
     Rr.push_back(ra);
-    b_rr.push_back((int)((n + 15) / 16));
+    b_rr.push_back(R.plan.mfma ? (int)((n + row_ref_targets(r, n) - 1) / row_ref_targets(r, n)) : 0);
   }
   if ((st = build_launch(b, b->record, Rc, b_r)) != YY_OK) return st;
   if ((st = build_launch(b, b->rs_local, S1, b_rs)) != YY_OK) return st;
@@ -452,6 +486,24 @@ yy_status launch_batched(hipStream_t st, const record_args* A, const int* pre, i
   return YY_OK;
 }
 
+// The pairwise launches of a step: the matrix-core runs' work items, then the vector-ALU runs' per
+// staging width.
+static yy_status launch_pairwise(yy_batch b) {
+  hipStream_t strm = b->ctx->stream;
+  yy_status st;
+  if (b->nitems > 0 &&
+      (st = launch_pair_mfma_batch(strm, b->S, b->prec, b->d_sets.ptr, b->d_items.as<int4>(), b->nitems, b->k64)) !=
+          YY_OK)
+    return st;
+  static const int kcs[4] = {2, 4, 8, 16};
+  for (int c = 0; c < 4; ++c)
+    if (b->v_nitems[c] > 0 &&
+        (st = launch_pair_valu_batch(strm, b->S, kcs[c], b->v_sets.as<ValuSet>(), b->v_items[c].as<int4>(),
+                                     b->v_nitems[c])) != YY_OK)
+      return st;
+  return YY_OK;
+}
+
 // One step of every run: 2 + 5 + 1 + 6 + 5 launches, plus 9 restart launches
 // that return at once in runs not restarting this step.
 static yy_status batch_step_impl(yy_batch b) {
@@ -468,8 +520,7 @@ static yy_status batch_step_impl(yy_batch b) {
     return st;
   if ((st = run_launch(b, b->rowref)) != YY_OK) return st;
   if ((st = timing_begin(b->ctx)) != YY_OK) return st;
-  if ((st = launch_pair_mfma_batch(strm, b->S, b->prec, b->d_sets.ptr, b->d_items.as<int4>(), b->nitems, b->k64)) != YY_OK)
-    return st;
+  if ((st = launch_pairwise(b)) != YY_OK) return st;
   if ((st = timing_end(b->ctx)) != YY_OK) return st;
   if ((st = run_launch(b, b->combine[par])) != YY_OK) return st;
   if ((st = run_launch(b, b->loglik[par])) != YY_OK) return st;
@@ -651,6 +702,8 @@ extern "C" yy_status yy_batch_create(yy_ctx ctx, int32_t nruns, const yy_batch_r
     for (int s = 0; s <= b->S; ++s) b->c[s] = scales->c[s];
   }
   b->runs.resize(nruns);
+  b->form.resize(nruns);
+  for (int32_t q = 0; q < nruns; ++q) b->form[q] = prec;
   yy_status st = YY_OK;
   for (int32_t q = 0; q < nruns && st == YY_OK; ++q) {
     BRun& R = b->runs[q];
@@ -696,6 +749,8 @@ extern "C" yy_status yy_batch_destroy(yy_batch b) {
   b->ctl.release();
   b->d_sets.release();
   b->d_items.release();
+  b->v_sets.release();
+  for (int c = 0; c < 4; ++c) b->v_items[c].release();
   if (b->pinned) (void)hipHostFree(b->pinned);
   delete b;
   return YY_OK;
@@ -764,7 +819,7 @@ extern "C" yy_status yy_batch_run_graph(yy_batch b, int32_t k_end) {
   return YY_OK;
 }
 
-extern "C" yy_status yy_batch_tune(yy_batch b, int32_t reps, int32_t* best_out) {
+extern "C" yy_status yy_batch_tune(yy_batch b, int32_t reps, int32_t forms, int32_t* best_out) {
   if (!b) return fail(YY_ERR_ARG, "yy_batch_tune: NULL batch");
   if (reps < 1 || reps > 1000) return fail(YY_ERR_ARG, "yy_batch_tune: reps out of range");
   YY_HIP(hipSetDevice(b->ctx->device));
@@ -774,18 +829,52 @@ extern "C" yy_status yy_batch_tune(yy_batch b, int32_t reps, int32_t* best_out) 
   hipEvent_t e0, e1;
   YY_HIP(hipEventCreate(&e0));
   YY_HIP(hipEventCreate(&e1));
+  yy_status s = YY_OK;
+  // (1) each run's form: its pairwise call (on its own context, as the batch plans it) timed in the
+  // batch's matrix-core form and in the plain FP32 form on the vector ALUs; the faster is kept.
+  // Runs of the same (r, n) share the first one's choice.
+  if (forms) {
+    const yy_scales sc = batch_scales(b);
+    std::vector<std::pair<std::pair<int32_t, int64_t>, int32_t>> chosen;
+    for (size_t q = 0; q < b->runs.size() && s == YY_OK; ++q) {
+      BRun& R = b->runs[q];
+      const std::pair<int32_t, int64_t> key(R.d.model.r, R.d.n);
+      int32_t pick = -1;
+      for (const auto& c : chosen)
+        if (c.first == key) pick = c.second;
+      if (pick < 0) {
+        float ms_f[2] = {0.f, 0.f};
+        const int32_t forms[2] = {b->prec, YY_PREC_FP32};
+        for (int f = 0; f < 2 && s == YY_OK; ++f) {
+          const int64_t jtl = (R.d.n + 127) / 128;
+          const int split = (int)std::max<int64_t>(1, std::min<int64_t>(b->max_split, jtl));
+          PropPlan plan;
+          s = propagate_begin(R.rc, &R.d.model, &sc, forms[f], R.d.n, R.x.as<double>(), 1, R.lo.as<double>(),
+                              R.hi.as<double>(), R.d.dt, R.lw[0].as<double>(), R.lw[1].as<double>(), split, plan);
+          if (s == YY_OK) s = propagate_pair(R.rc, plan);   // warm-up
+          if (s == YY_OK && hipEventRecord(e0, st) != hipSuccess) s = fail(YY_ERR_HIP, "yy_batch_tune: event");
+          for (int t = 0; t < reps && s == YY_OK; ++t) s = propagate_pair(R.rc, plan);
+          if (s == YY_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+            s = fail(YY_ERR_HIP, "yy_batch_tune: event");
+          if (s == YY_OK) (void)hipEventElapsedTime(&ms_f[f], e0, e1);
+        }
+        if (s != YY_OK) break;
+        pick = ms_f[1] < ms_f[0] ? YY_PREC_FP32 : b->prec;
+        chosen.push_back({key, pick});
+      }
+      b->form[q] = pick;
+    }
+  }
   const int keep = b->max_split;
   int best = keep;
   float best_ms = -1.f;
-  yy_status s = YY_OK;
+  // (2) the matrix-core runs' source splits
   for (int cand = 1; cand <= 64 && s == YY_OK; cand *= 2) {
     b->max_split = cand;
     if ((s = build(b)) != YY_OK) break;
-    if ((s = launch_pair_mfma_batch(st, b->S, b->prec, b->d_sets.ptr, b->d_items.as<int4>(), b->nitems, b->k64)) != YY_OK)
-      break;
+    if ((s = launch_pairwise(b)) != YY_OK) break;
     if (hipEventRecord(e0, st) != hipSuccess) { s = fail(YY_ERR_HIP, "yy_batch_tune: event"); break; }
-    for (int q = 0; q < reps && s == YY_OK; ++q)
-      s = launch_pair_mfma_batch(st, b->S, b->prec, b->d_sets.ptr, b->d_items.as<int4>(), b->nitems, b->k64);
+    for (int q = 0; q < reps && s == YY_OK; ++q) s = launch_pairwise(b);
     if (s != YY_OK) break;
     if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
       s = fail(YY_ERR_HIP, "yy_batch_tune: event");
@@ -819,6 +908,24 @@ extern "C" yy_status yy_batch_results(yy_batch b, int32_t run, double* mean_hist
   if (logZ_hist) YY_HIP(hipMemcpyAsync(logZ_hist, R.logZ_hist.ptr, K * 8, hipMemcpyDeviceToDevice, st));
   if (ess_hist) YY_HIP(hipMemcpyAsync(ess_hist, R.ess_hist.ptr, K * 8, hipMemcpyDeviceToDevice, st));
   return YY_OK;
+}
+
+extern "C" yy_status yy_batch_run_form(yy_batch b, int32_t run, int32_t* prec) {
+  if (!b || run < 0 || run >= (int32_t)b->runs.size() || !prec) return fail(YY_ERR_ARG, "yy_batch_run_form: bad run");
+  *prec = b->form[run];
+  return YY_OK;
+}
+
+extern "C" yy_status yy_batch_set_run_form(yy_batch b, int32_t run, int32_t prec) {
+  if (!b || run < 0 || run >= (int32_t)b->runs.size()) return fail(YY_ERR_ARG, "yy_batch_set_run_form: bad run");
+  if (prec != b->prec && prec != YY_PREC_FP32)
+    return fail(YY_ERR_ARG, "yy_batch_set_run_form: the batch's matrix-core form or YY_PREC_FP32");
+  YY_HIP(hipSetDevice(b->ctx->device));
+  if (capturing(b->ctx->stream)) return fail(YY_ERR_UNSUPPORTED, "yy_batch_set_run_form: stream is capturing");
+  if (b->form[run] == prec) return YY_OK;
+  drop_graph(b);
+  b->form[run] = prec;
+  return build(b);
 }
 
 extern "C" yy_status yy_batch_screen_count(yy_batch b, int32_t run, int64_t* flagged, int64_t* tiles) {

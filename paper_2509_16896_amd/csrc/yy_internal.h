@@ -259,6 +259,18 @@ struct CombineArgs {
 // source weights, biases and the launch parameters; pair = the pairwise
 // kernel; end = the combination.  nsplit_override > 0 fixes the number of
 // source splits of the matrix-core kernel.
+// One node set of the batched vector-ALU pairwise launch: its arguments, source range per split and
+// FP64 scale constants, as the single-run launch passes them.
+struct ValuSet {
+  PairArgs a;
+  int64_t per;
+  double taud[YY_MAX_SCALES], kapd[YY_MAX_SCALES];
+};
+int valu_kc(int32_t r);                  // coordinates staged per step: 2, 4, 8 or 16
+int64_t valu_per(const PairArgs& a);     // sources per split
+yy_status launch_pair_valu_batch(hipStream_t st, int32_t S, int kc, const ValuSet* sets, const int4* items,
+                                 int nitems);
+
 struct PropPlan {
   int64_t n = 0;
   int32_t prec = 0;
@@ -280,9 +292,19 @@ yy_status source_weights(yy_ctx ctx, int64_t n, const double* logw_in, const int
                          double** lref_out, long long** heavy_out = nullptr);
 yy_status launch_combine(hipStream_t st, const CombineArgs& cb);
 
-// Blocks of the normalisation kernels for n nodes (64 rows per block, at most
-// 1024 blocks): enough blocks to stream the n x r coordinates at full bandwidth.
-inline int norm_blocks(int64_t n) { return (int)((n + 63) / 64 < 1024 ? (n + 63) / 64 : 1024); }
+// Blocks of the normalisation kernels for n nodes: 64 rows per block (at most 1024
+// blocks), enough blocks to stream the n x r coordinates at full bandwidth; up to
+// n = 4096, 16 rows per block, so that a wave's chain of rows is short where the
+// kernel is bound by latency rather than bandwidth.
+inline int norm_blocks(int64_t n) {
+  if (n <= 4096) return (int)((n + 15) / 16);
+  return (int)((n + 63) / 64 < 1024 ? (n + 63) / 64 : 1024);
+}
+
+// Targets per block of the row-floor kernel: 16 rows of 16 lanes each where r <= 256;
+// for longer rows the whole wave across a row's coordinates, one row per wave up to
+// n = 8192 (latency-bound sizes), four rows per wave beyond.
+__host__ __device__ inline int row_ref_targets(int32_t r, int64_t n) { return r > 256 && n <= 8192 ? 4 : 16; }
 
 // Tuned source-split counts of the matrix-core kernel (yy_tune), 0 if none.
 int tune_lookup(yy_ctx ctx, int32_t rp, int64_t n_pad, int32_t S, int32_t prec);

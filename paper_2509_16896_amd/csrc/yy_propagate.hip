@@ -423,8 +423,9 @@ __global__ void __launch_bounds__(kBlock) k_lw_convert(int64_t n, int nparts,
 // general noise their whitened images; the box centre cancels in the
 // differences).  k_heavy (one block) reduces the conversion blocks' candidates
 // to j* (the first valid source of maximal weight) and evaluates f(x_j*) once;
-// k_row_ref takes 16 targets per block, a wave per target at a time with the
-// lanes across the coordinates.
+// k_row_ref takes a wave per target with the lanes across the coordinates (4 or
+// 16 targets per block, row_ref_targets), or where r <= 256 16 targets of 16
+// lanes each.
 constexpr float kRowRefGap = 160.f;
 constexpr int kRowRefTargets = 16;
 
@@ -461,9 +462,10 @@ __device__ __forceinline__ void k_heavy_body(const RowRefArgs& a) {
 __device__ __forceinline__ void k_row_ref_body(const RowRefArgs& a, int bx_) {
   __shared__ float sself[YY_MAX_SCALES][kRowRefTargets];
   __shared__ int sneed[kRowRefTargets];
-  const int64_t i0 = (int64_t)bx_ * kRowRefTargets;
+  const int T = row_ref_targets(a.r, a.n);   // <= kRowRefTargets
+  const int64_t i0 = (int64_t)bx_ * T;
   const long long js = *a.jstar;
-  if (threadIdx.x < kRowRefTargets) {
+  if (threadIdx.x < T) {
     const int64_t i = i0 + threadIdx.x;
     bool need = false;
     if (i < a.n) {
@@ -480,37 +482,40 @@ __device__ __forceinline__ void k_row_ref_body(const RowRefArgs& a, int bx_) {
     sneed[threadIdx.x] = need;
   }
   __syncthreads();
+  // lanes per target: the whole wave across the coordinates of a long row; for r <= 256, groups of 16
+  // lanes, four targets per wave at a time (the shuffles stay inside a group and run in converged flow)
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int u = wave; u < kRowRefTargets; u += kBlock / 64) {
+  const int L = a.r > 256 ? 64 : 16;
+  const int per = 64 / L, sg = lane / L, sl = lane % L;
+  for (int u0 = wave * per; u0 < T; u0 += (kBlock / 64) * per) {
+    const int u = u0 + sg;   // < T: u0 is a multiple of per, which divides T
     const int64_t i = i0 + u;
-    if (i >= a.n) break;
-    float ref[YY_MAX_SCALES], hv[YY_MAX_SCALES];
-    for (int s = 0; s < a.S; ++s) {
-      ref[s] = sself[s][u];
-      hv[s] = -INFINITY;
-    }
-    if (sneed[u]) {
+    const bool valid = i < a.n;
+    const bool need = valid && sneed[u];
+    double D[YY_MAX_SCALES] = {0, 0, 0, 0, 0, 0};
+    if (need) {
       const double* xi = a.x + (size_t)i * a.r;
       const double* xj = a.x + (size_t)js * a.r;
-      double D[YY_MAX_SCALES] = {0, 0, 0, 0, 0, 0};
-      for (int32_t k = lane; k < a.r; k += 64) {
+#pragma unroll 4
+      for (int32_t k = sl; k < a.r; k += L) {
         const double d = xi[k] - xj[k], fk = a.fstar[k];
         for (int s = 0; s < a.S; ++s) {
           const double e = d - a.taud[s] * fk;
           D[s] = fma(e, e, D[s]);
         }
       }
-      for (int s = 0; s < a.S; ++s) {
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) D[s] += __shfl_xor(D[s], off, 64);
-        hv[s] = (float)(-a.kapd[s] * D[s]);
-        ref[s] = fmaxf(ref[s], hv[s]);
-      }
     }
-    if (lane == 0)
+    for (int s = 0; s < a.S; ++s)
+      for (int off = L / 2; off > 0; off >>= 1) D[s] += __shfl_xor(D[s], off, 64);
+    if (valid && sl == 0)
       for (int s = 0; s < a.S; ++s) {
-        a.rref[(size_t)s * a.n + i] = ref[s];
-        a.rhv[(size_t)s * a.n + i] = hv[s];
+        float ref = sself[s][u], hv = -INFINITY;
+        if (need) {
+          hv = (float)(-a.kapd[s] * D[s]);
+          ref = fmaxf(ref, hv);
+        }
+        a.rref[(size_t)s * a.n + i] = ref;
+        a.rhv[(size_t)s * a.n + i] = hv;
       }
   }
 }
@@ -521,6 +526,7 @@ __global__ void __launch_bounds__(kBlock) k_row_ref(RowRefArgs a) { k_row_ref_bo
 // batched: the first block of each run's range evaluates its heavy source, the rows follow in a second launch
 __global__ void __launch_bounds__(kBlock) k_heavy_batch(const RowRefArgs* __restrict__ A, const int* __restrict__ pre,
                                                         int nr) {
+  if (!A[blockIdx.x].rref) return;   // a run in the vector-ALU form has no row floor
   k_heavy_body(A[blockIdx.x]);
 }
 
@@ -550,11 +556,10 @@ constexpr int kVI = 64, kVJ = 64;
 
 // Push form: |x_i - x_j - tau f_j|^2; pull form: |x_i - tau f_i - x_j|^2 (the
 // f rows of the targets instead of the sources).
+// bx: the block of 64 targets, by: the source split (the batched launch takes both from its work item).
 template <int S, int KC, bool PULL>
-__global__ void __launch_bounds__(256) k_pair_valu(PairArgs a, int64_t j_per_split,
-                                                   double tau0, double tau1, double tau2, double tau3,
-                                                   double tau4, double tau5, double kd0, double kd1,
-                                                   double kd2, double kd3, double kd4, double kd5) {
+__device__ __forceinline__ void pair_valu_body(const PairArgs& a, int64_t j_per_split, const double* taud,
+                                               const double* kapd, int bx, int by) {
   __shared__ float sxi[KC][kVI + 4];
   __shared__ float sxj[KC][kVJ + 4];
   __shared__ float sfj[KC][kVJ + 4];
@@ -562,11 +567,9 @@ __global__ void __launch_bounds__(256) k_pair_valu(PairArgs a, int64_t j_per_spl
   const int tid = threadIdx.x;
   const int ti = tid >> 4, tj = tid & 15;
   const int64_t n = a.n;
-  const int64_t i0 = (int64_t)blockIdx.x * kVI;
-  const int64_t jb = (int64_t)blockIdx.y * j_per_split;
+  const int64_t i0 = (int64_t)bx * kVI;
+  const int64_t jb = (int64_t)by * j_per_split;
   const int64_t je = jb + j_per_split < n ? jb + j_per_split : n;
-  const double taud[6] = {tau0, tau1, tau2, tau3, tau4, tau5};
-  const double kapd[6] = {kd0, kd1, kd2, kd3, kd4, kd5};
 
   float M[4][S], Ssum[4][S];
 #pragma unroll
@@ -682,17 +685,67 @@ __global__ void __launch_bounds__(256) k_pair_valu(PairArgs a, int64_t j_per_spl
       if (gi >= n) continue;
 #pragma unroll
       for (int s = 0; s < S; ++s)
-        a.part[((size_t)blockIdx.y * S + s) * n + gi] = make_float2(M[p][s], Ssum[p][s]);
+        a.part[((size_t)by * S + s) * n + gi] = make_float2(M[p][s], Ssum[p][s]);
     }
   }
+}
+
+template <int S, int KC, bool PULL>
+__global__ void __launch_bounds__(256) k_pair_valu(PairArgs a, int64_t j_per_split,
+                                                   double tau0, double tau1, double tau2, double tau3,
+                                                   double tau4, double tau5, double kd0, double kd1,
+                                                   double kd2, double kd3, double kd4, double kd5) {
+  const double taud[6] = {tau0, tau1, tau2, tau3, tau4, tau5};
+  const double kapd[6] = {kd0, kd1, kd2, kd3, kd4, kd5};
+  pair_valu_body<S, KC, PULL>(a, j_per_split, taud, kapd, blockIdx.x, blockIdx.y);
+}
+
+// Many node sets (push form): block b takes work item items[b] = (set, block of 64 targets, source
+// split), the same blocks as the single-run launch of that set.
+template <int S, int KC>
+__global__ void __launch_bounds__(256) k_pair_valu_batch(const ValuSet* __restrict__ sets,
+                                                         const int4* __restrict__ items) {
+  const int4 it = items[blockIdx.x];
+  const ValuSet& v = sets[it.x];
+  pair_valu_body<S, KC, false>(v.a, v.per, v.taud, v.kapd, it.y, it.z);
+}
+
+int valu_kc(int32_t r) { return r <= 2 ? 2 : r <= 4 ? 4 : r <= 8 ? 8 : 16; }
+
+int64_t valu_per(const PairArgs& a) {
+  const int64_t jtiles = (a.n + kVJ - 1) / kVJ;
+  return ((jtiles + a.nsplit - 1) / a.nsplit) * kVJ;
+}
+
+template <int S>
+static void launch_valu_batch_s(hipStream_t st, int kc, const ValuSet* sets, const int4* items, int nitems) {
+  if (kc == 2) k_pair_valu_batch<S, 2><<<nitems, 256, 0, st>>>(sets, items);
+  else if (kc == 4) k_pair_valu_batch<S, 4><<<nitems, 256, 0, st>>>(sets, items);
+  else if (kc == 8) k_pair_valu_batch<S, 8><<<nitems, 256, 0, st>>>(sets, items);
+  else k_pair_valu_batch<S, 16><<<nitems, 256, 0, st>>>(sets, items);
+}
+
+yy_status launch_pair_valu_batch(hipStream_t st, int32_t S, int kc, const ValuSet* sets, const int4* items,
+                                 int nitems) {
+  if (nitems <= 0) return YY_OK;
+  switch (S) {
+    case 1: launch_valu_batch_s<1>(st, kc, sets, items, nitems); break;
+    case 2: launch_valu_batch_s<2>(st, kc, sets, items, nitems); break;
+    case 3: launch_valu_batch_s<3>(st, kc, sets, items, nitems); break;
+    case 4: launch_valu_batch_s<4>(st, kc, sets, items, nitems); break;
+    case 5: launch_valu_batch_s<5>(st, kc, sets, items, nitems); break;
+    case 6: launch_valu_batch_s<6>(st, kc, sets, items, nitems); break;
+    default: return fail(YY_ERR_ARG, "bad scale count");
+  }
+  YY_LAUNCH_CHECK("k_pair_valu_batch");
+  return YY_OK;
 }
 
 template <int S>
 static yy_status launch_valu_s(hipStream_t st, const PairArgs& a, const double* taud,
                                const double* kapd) {
   const int64_t tiles = (a.n + kVI - 1) / kVI;
-  const int64_t jtiles = (a.n + kVJ - 1) / kVJ;
-  const int64_t per = ((jtiles + a.nsplit - 1) / a.nsplit) * kVJ;
+  const int64_t per = valu_per(a);
   dim3 grid((unsigned)tiles, (unsigned)a.nsplit);
 #define YY_VALU_LAUNCH(KC)                                                                              \
   do {                                                                                                  \
@@ -705,9 +758,10 @@ static yy_status launch_valu_s(hipStream_t st, const PairArgs& a, const double* 
                                                       taud[5], kapd[0], kapd[1], kapd[2], kapd[3], kapd[4], \
                                                       kapd[5]);                                         \
   } while (0)
-  if (a.r <= 2) YY_VALU_LAUNCH(2);
-  else if (a.r <= 4) YY_VALU_LAUNCH(4);
-  else if (a.r <= 8) YY_VALU_LAUNCH(8);
+  const int kc = valu_kc(a.r);
+  if (kc == 2) YY_VALU_LAUNCH(2);
+  else if (kc == 4) YY_VALU_LAUNCH(4);
+  else if (kc == 8) YY_VALU_LAUNCH(8);
   else YY_VALU_LAUNCH(16);
 #undef YY_VALU_LAUNCH
   YY_LAUNCH_CHECK("k_pair_valu");
@@ -1194,7 +1248,7 @@ yy_status propagate_begin(yy_ctx ctx, const yy_model* model, const yy_scales* sc
     ra.rhv = ra.rref + (size_t)S * n;
     k_heavy<<<1, kBlock, 0, ctx->stream>>>(ra);
     YY_LAUNCH_CHECK("k_heavy");
-    k_row_ref<<<(unsigned)((n + kRowRefTargets - 1) / kRowRefTargets), kBlock, 0, ctx->stream>>>(ra);
+    k_row_ref<<<(unsigned)((n + row_ref_targets(a.r, n) - 1) / row_ref_targets(a.r, n)), kBlock, 0, ctx->stream>>>(ra);
     YY_LAUNCH_CHECK("k_row_ref");
     ex.rref = ra.rref;
     ex.rhv = ra.rhv;

@@ -90,11 +90,13 @@ PAPER_E1_SIZES = ((10, 100), (50, 300), (100, 500), (300, 800), (600, 1000), (10
 def paper_e1(r: int, seed: int = 0) -> Workload:
     """The paper's large-scale cubic sensor test: f = sin(x)(Ax) + sin(2x)(A1 x) with its bidiagonal A and
     A1, h = (x - 100)^3, unit noise, dt = 0.01, 1000 steps, restarts of half-width 0.3 every 2 steps, n as
-    the paper pairs it with r; scales {1,2,4} and an initial box of half-width 3 around the prior N(0, I)."""
+    the paper pairs it with r; scales {1,2,4} and an initial box of half-width 3 around the prior N(0, I).
+    The chosen form BF16X3P where r >= 32; below that the matrix cores would pad every K stage to 32
+    coordinates, and the plain FP32 form on the vector ALUs is both exact and faster."""
     n = dict(PAPER_E1_SIZES)[r]
     return Workload(f"paper_e1_r{r}_n{n}", r=r, n=n, dt=0.01, K=1000, drift=F_PAPER_SINMIX, obs=H_CUBE, q=1.0,
                     rho2=1.0, scales=(1.0, 2.0, 4.0), box_half=3.0, restart_every=2, R=0.3, seed=seed,
-                    h_shift=100.0, precision="bf16x3p")
+                    h_shift=100.0, precision="bf16x3p" if r >= 32 else "fp32")
 
 
 def batch_runs(count: int = 64, seed: int = 0):

@@ -38,7 +38,7 @@ EXPORTED = ["yy_last_error", "yy_create", "yy_destroy", "yy_set_stream", "yy_get
             "yy_proposal_set_params", "yy_proposal_forward", "yy_proposal_train_step", "yy_sample_moments",
             "yy_tune", "yy_batch_create", "yy_batch_destroy", "yy_batch_reset", "yy_batch_step",
             "yy_batch_run_graph", "yy_batch_tune", "yy_batch_results", "yy_batch_step_count",
-            "yy_batch_screen_count"]
+            "yy_batch_screen_count", "yy_batch_run_form", "yy_batch_set_run_form"]
 
 
 class YYError(RuntimeError):
@@ -113,10 +113,12 @@ for _name, _args in {
     "yy_batch_reset": [_P],
     "yy_batch_step": [_P],
     "yy_batch_run_graph": [_P, _i32],
-    "yy_batch_tune": [_P, _i32, ctypes.POINTER(_i32)],
+    "yy_batch_tune": [_P, _i32, _i32, ctypes.POINTER(_i32)],
     "yy_batch_results": [_P, _i32, _P, _P, _P],
     "yy_batch_step_count": [_P, ctypes.POINTER(_i32)],
     "yy_batch_screen_count": [_P, _i32, ctypes.POINTER(_i64), ctypes.POINTER(_i64)],
+    "yy_batch_run_form": [_P, _i32, ctypes.POINTER(_i32)],
+    "yy_batch_set_run_form": [_P, _i32, _i32],
     "yy_timing_enable": [_P, _i32],
     "yy_timing_read": [_P, ctypes.POINTER(_f64), ctypes.POINTER(_i64)],
     "yy_screen_count": [_P, ctypes.POINTER(_i64), ctypes.POINTER(_i64)],
@@ -453,9 +455,9 @@ def yy_batch_run_graph(b, k_end):
     _check(_lib.yy_batch_run_graph(b, int(k_end)), "yy_batch_run_graph")
 
 
-def yy_batch_tune(b, reps=3) -> int:
+def yy_batch_tune(b, reps=3, forms=False) -> int:
     best = _i32(0)
-    _check(_lib.yy_batch_tune(b, int(reps), ctypes.byref(best)), "yy_batch_tune")
+    _check(_lib.yy_batch_tune(b, int(reps), 1 if forms else 0, ctypes.byref(best)), "yy_batch_tune")
     return int(best.value)
 
 
@@ -470,6 +472,17 @@ def yy_batch_screen_count(b, run):
     f, t = _i64(0), _i64(0)
     _check(_lib.yy_batch_screen_count(b, int(run), ctypes.byref(f), ctypes.byref(t)), "yy_batch_screen_count")
     return int(f.value), int(t.value)
+
+
+def yy_batch_run_form(b, run) -> str:
+    """Run `run`'s pairwise form: the batch's matrix-core form or "fp32" (vector ALUs)."""
+    p = _i32(0)
+    _check(_lib.yy_batch_run_form(b, int(run), ctypes.byref(p)), "yy_batch_run_form")
+    return {v: k for k, v in PREC_BY_NAME.items() if k != "auto"}[int(p.value)]
+
+
+def yy_batch_set_run_form(b, run, prec: str):
+    _check(_lib.yy_batch_set_run_form(b, int(run), PREC_BY_NAME[prec]), "yy_batch_set_run_form")
 
 
 def yy_batch_step_count(b) -> int:

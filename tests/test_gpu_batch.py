@@ -42,23 +42,31 @@ def _single(w, dys, prec):
         f.close()
 
 
+@pytest.mark.parametrize("small_r", ["matrix", "fp32"])
 @pytest.mark.parametrize("prec", ["bf16x3g", "bf16x3s", "bf16x3p", "fp32_mfma"])
-def test_batch_matches_single_runs_exactly(prec):
+def test_batch_matches_single_runs_exactly(prec, small_r):
+    """Every run against the single-run filter in the run's form: all runs in the batch's matrix-core
+    form (the default, "matrix"), or the runs below r = 32 set to the plain FP32 form ("fp32")."""
     ws = _workloads()
     dys = [W.simulate(w)[1] for w in ws]
     bt = Batch(ws, dys, prec=prec, max_split=16)
     try:
+        for q, w in enumerate(ws):
+            assert bt.run_form(q) == prec
+            if small_r == "fp32" and w.r < 32:
+                bt.set_run_form(q, "fp32")
+                assert bt.run_form(q) == "fp32"
         for _ in range(ws[0].K):
             bt.step()
         assert bt.k == ws[0].K
         for q, w in enumerate(ws):
             mean, lz, ess = (host(t) for t in bt.results(q))
-            ref = _single(w, dys[q], prec)
+            ref = _single(w, dys[q], bt.run_form(q))
             assert np.array_equal(mean, ref[0]), w.name
             assert np.array_equal(lz, ref[1]), w.name
             assert np.array_equal(ess, ref[2]), w.name
             assert np.all(np.isfinite(mean))
-            if prec in ("bf16x3s", "bf16x3p"):
+            if prec in ("bf16x3s", "bf16x3p") and bt.run_form(q) == prec:
                 flagged, tiles = bt.screen_count(q)
                 assert tiles == ((w.n + 255) // 256) * ((w.n + 127) // 128) and 0 <= flagged <= tiles
     finally:
@@ -120,20 +128,43 @@ def test_graph_from_step_zero_with_odd_end():
 
 
 def test_batch_tuner_keeps_results():
+    """The tuner picks each run's form (matrix cores or vector ALUs) and the source splits; every run then
+    matches the single-run filter in its chosen form (another split count changes only the summation
+    order of the partial sums)."""
     ws = _workloads(K=6)
     dys = [W.simulate(w)[1] for w in ws]
     b = Batch(ws, dys, prec="bf16x3g")
     try:
-        b.step()
-        best = b.tune(reps=2)
+        best = b.tune(reps=2, forms=True)
         assert best in (1, 2, 4, 8, 16, 32, 64)
-        for _ in range(5):
+        forms = [b.run_form(q) for q in range(len(ws))]
+        print("tuned forms:", list(zip([w.r for w in ws], [w.n for w in ws], forms)))
+        assert all(f in ("bf16x3g", "fp32") for f in forms)
+        for _ in range(6):
             b.step()
         for q, w in enumerate(ws):
             mean = host(b.results(q)[0])
-            ref = _single(w, dys[q], "bf16x3g")[0]
-            # another split count changes only the summation order of the partial sums
+            ref = _single(w, dys[q], forms[q])[0]
             assert np.allclose(mean, ref, rtol=1e-9, atol=1e-9), w.name
+    finally:
+        b.close()
+
+
+def test_batch_run_form_arguments():
+    ws = _workloads(K=2)
+    dys = [W.simulate(w)[1] for w in ws]
+    b = Batch(ws, dys, prec="bf16x3p")
+    try:
+        with pytest.raises(yy.YYError):
+            b.set_run_form(1, "bf16x3g")        # neither the batch's form nor fp32
+        with pytest.raises(yy.YYError):
+            b.run_form(len(ws))
+        b.set_run_form(2, "fp32")               # r = 64 on the vector ALUs
+        assert b.run_form(2) == "fp32"
+        b.step()
+        b.step()
+        ref = _single(ws[2], dys[2], "fp32")
+        assert np.array_equal(host(b.results(2)[0]), ref[0])
     finally:
         b.close()
 
