@@ -289,6 +289,8 @@ yy_status yy_destroy(yy_ctx ctx) {
   ctx->prep.wbnd.release();
   ctx->obsw.release();
   ctx->rref.release();
+  ctx->sym_items.release();
+  ctx->tT.release();
   ctx->fstar.release();
   ctx->lw2.release();
   ctx->part.release();

@@ -94,6 +94,14 @@ struct MArgs {
   const float* rhv;            // [S][n] with rref: the exact term of the pair (i, j*) where the row counts it
                                // at initialisation and leaves it out of the tiles, else -inf
   const long long* jstar;      // with rref: j*, the heaviest source (-1: none)
+  // the symmetric partial-distance screen (BF16X3P on one run, many target blocks): its work items
+  // (A, B0, B1): target block A against target blocks [B0, B1) as sources, B0 >= A; and per 64-row
+  // group g and scale s the largest a_j^p + hx_j^p F^p - M_j over the group's valid rows with the
+  // heavy pair counted apart (tT[s][g]) and without (tT[(S + s)][g])
+  const int4* sym_items;
+  const float* tT;
+  const float* tTn;            // the same per row: [2][S][n_pad], -inf where the row is in the other class
+  int32_t sym_nitems, ngroups;
 };
 
 // j* of the call (-1: none, or no rows floor), read once per block and kept in scalar registers
@@ -1354,6 +1362,423 @@ __device__ __forceinline__ void prescreen_block(const MArgs& a, int tb, int spli
   }
 }
 
+// The symmetric partial-distance screen.  G^p = X^p X^p^T is symmetric, so one
+// block of products between target blocks A and B (A < B) serves both
+// orientations: A's rows against B's sources, with the per-row verdict of
+// prescreen_block, and B's rows against A's sources, with a coarse bound per
+// (wave, 64 rows of B): for row j of B and source i of the wave's 64 nodes of A,
+//   e_ji <= a_j + c1 G_ij + b_i <= c1 max_(wave x group) G + max_i b_i + max_j (a_j - M_j) + M_j,
+// so no row j of the group is within the margin of its lower bound M_j unless
+// c1 max G + max b + max (a - M) > -margin.  The rows that count the pair with
+// the heaviest source j* apart take max b over the wave's sources without j*.
+// Work items (A, B0, B1) cover every unordered pair of target blocks once (the
+// diagonal A = B with the per-row verdict only), and each flag byte is written
+// by exactly one wave per call: (A, tiles of B >= A) in the normal orientation,
+// (B, tiles of A < B) in the transposed one.
+//
+// Where that coarse bound leaves a doubt, the rows are checked one by one: per
+// source column j of the wave's products, max_i (c1 G_ij + b_i) over the wave's
+// 64 nodes of A (a maximum across the 32 lanes that hold the column), plus
+// a_j - M_j against -margin.
+//
+// k_tgt_bound: per row and scale a_j^p + hx_j^p F^p - M_j, in one of two arrays by
+// whether the row counts the heavy pair apart (-inf in the other; a_j is the
+// screen's target term, M_j the row's lower bound as the screens take it), and
+// per 64-row group the maxima of both.
+__global__ void __launch_bounds__(kBlock) k_tgt_bound(MArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int g = (int)(((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6);
+  if (g >= a.ngroups) return;   // whole waves: ngroups groups of 64 rows
+  const int64_t j = (int64_t)g * 64 + lane;
+  const double F = a.scal[5];
+  const bool valid = j < a.n && !a.bnd[j];
+  const double nx = valid ? a.node[3 * a.n + j] : 0.0;
+  const double nf = valid ? a.node[a.n + j] : 0.0;
+  const float li = valid ? a.lw2[j] : -INFINITY;
+  const bool hv = valid && a.rhv && a.rhv[j] != -INFINITY;
+  const double hF = 2.0 * a.kapd[0] * a.taud[0] * sqrt(nx) * F * (1.0 + 0x1p-20);
+  float* out = const_cast<float*>(a.tT);
+  float* outn = const_cast<float*>(a.tTn);
+  for (int s = 0; s < a.S; ++s) {
+    float v = -INFINITY;
+    if (valid) {
+      const float at = (float)(-a.kapd[s] * nx + hF);
+      const float self = li != -INFINITY ? li - (float)(a.kapd[s] * a.taud[s] * a.taud[s] * nf) : -INFINITY;
+      const float M = a.rref ? a.rref[(size_t)s * a.n + j] : self;
+      v = at - M;   // +inf where M = -inf: any pair may then be near
+    }
+    float vh = hv ? v : -INFINITY, vn = hv ? -INFINITY : v;
+    outn[(size_t)s * a.n_pad + j] = vh;
+    outn[(size_t)(a.S + s) * a.n_pad + j] = vn;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      vh = fmaxf(vh, __shfl_xor(vh, off, 64));
+      vn = fmaxf(vn, __shfl_xor(vn, off, 64));
+    }
+    if (lane == 0) {
+      out[(size_t)s * a.ngroups + g] = vh;
+      out[(size_t)(a.S + s) * a.ngroups + g] = vn;
+    }
+  }
+}
+
+// The transposed rows of one 64-source half of a tile, one by one: tl[0][s][c] and tl[1][s][c] are
+// this lane's maxima of c1 G_ij + b_i over its nodes i of A for column c (c = 16 jb' + v of the
+// half), with and without j*; the maxima across the 32 lanes that hold the column, plus the row's
+// a_j - M_j (tTn), against -margin.  Returns whether any row of the half may hold a near pair.
+template <int S>
+__device__ __noinline__ bool sym_rows_check(const MArgs& a, const float* tl, bool jsw, int64_t jh, int g,
+                                            const float* margin) {
+  bool f = false;
+  for (int s = 0; s < S; ++s) {
+    const double lim = -((double)margin[s] + 1.0);
+    for (int c = 0; c < 32; ++c) {
+      float t = tl[s * 32 + c], tx = tl[(S + s) * 32 + c];
+      for (int off = 1; off < 32; off <<= 1) {   // the 32 lanes of this lane half hold the column
+        t = fmaxf(t, __shfl_xor(t, off, 64));
+        tx = fmaxf(tx, __shfl_xor(tx, off, 64));
+      }
+      if (!jsw) tx = t;
+      const int jb = c >> 4, v = c & 15;
+      const int64_t j = jh + jb * 32 + 8 * (v >> 2) + 4 * g + (v & 3);
+      const double th = a.tTn[(size_t)s * a.n_pad + j], tn = a.tTn[(size_t)(S + s) * a.n_pad + j];
+      f |= (double)tx + th > lim;
+      f |= (double)t + tn > lim;
+    }
+  }
+  return __any(f);
+}
+
+template <int S, int PC, int NS>
+__device__ __forceinline__ void prescreen_sym_block(const MArgs& a, int A, int B0, int B1, unsigned char* smem,
+                                                    uint8_t (*sbits)[4][4], float* stT,
+                                                    double (*slim)[2][S]) {
+  static_assert(NS % PC == 0 && NS / PC >= 2, "the ring holds at least two tiles");
+  static_assert(PC * kKC <= kPreK, "the screen covers the first kPreK coordinates");
+  static_assert(kPW == 4 && kPW * 32 == kPJ && kSJB * 32 == kPJ, "4 waves of 64 targets; a wave spans the tile");
+  constexpr int LA = NS / PC - 1;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wi = wave, col = lane & 31, g = lane >> 5;
+  const int64_t i0 = (int64_t)A * kMI;
+  const int jt0 = 2 * B0;
+  const int jt1 = (int)(2 * (int64_t)B1 < a.jtl ? 2 * (int64_t)B1 : a.jtl);
+  const int ntiles = __builtin_amdgcn_readfirstlane(jt1 - jt0);
+  if (ntiles <= 0) return;
+  const unsigned char* gb = reinterpret_cast<const unsigned char*>(a.bf);
+  const int64_t n_pad = a.n_pad;
+  const uint32_t smem_lds = __builtin_amdgcn_readfirstlane(lds_addr(smem));
+
+  const double X = a.scal[4], F = a.scal[5];
+  const double gam = PC * kKC * 0x1p-24;
+  float at[kIB][S], M[kIB][S], margin[S];
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const double XT = X + a.taud[s] * F;
+    const double dD = 2.0 * X * (a.eps_g1 + gam) * X + 16.0 * 0x1p-24 * XT * XT;
+    margin[s] = (float)(2.0 * a.kapd[s] * dD + (double)kSkip + 16.0);
+  }
+  bf16x8_t bt[PC][kIB];
+  bool hv[kIB];
+  const int64_t jstar = heavy_source(a);
+#pragma unroll
+  for (int ib = 0; ib < kIB; ++ib) {
+    const int64_t i = i0 + wi * (32 * kIB) + ib * 32 + col;
+    const bool valid = i < a.n && !a.bnd[i];
+    hv[ib] = valid && a.rhv && a.rhv[i] != -INFINITY;
+    const double nx = valid ? a.node[3 * a.n + i] : 0.0;
+    const double nf = valid ? a.node[a.n + i] : 0.0;
+    const float li = valid ? a.lw2[i] : -INFINITY;
+    const double hF = 2.0 * a.kapd[0] * a.taud[0] * sqrt(nx) * F * (1.0 + 0x1p-20);
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      at[ib][s] = valid ? (float)(-a.kapd[s] * nx + hF) : -INFINITY;
+      const float self = (valid && li != -INFINITY) ? li - (float)(a.kapd[s] * a.taud[s] * a.taud[s] * nf) : -INFINITY;
+      M[ib][s] = (valid && a.rref) ? a.rref[(size_t)s * a.n + i] : self;
+    }
+#pragma unroll
+    for (int c = 0; c < PC; ++c)
+      bt[c][ib] = *reinterpret_cast<const bf16x8_t*>(gb + ((size_t)c * n_pad + i) * 32 + g * 16);
+  }
+  // the transposed orientation: the wave's 64 nodes of A as sources, their largest prefix bias with
+  // and without j*
+  float bA[S], bAx[S], bown[kIB][S];
+#pragma unroll
+  for (int ib = 0; ib < kIB; ++ib)
+#pragma unroll
+    for (int s = 0; s < S; ++s) bown[ib][s] = a.bpre[(size_t)s * n_pad + i0 + wi * 64 + ib * 32 + col];
+  // where the wave's nodes hold j*, the lane that holds it as node ib (-1: none)
+  int jsl = -1;
+  if (jstar >= i0 + wi * 64 && jstar < i0 + wi * 64 + 64) {
+    const int d = (int)(jstar - i0 - wi * 64);
+    if ((d & 31) == col) jsl = d >> 5;
+  }
+  const bool jsw = __builtin_amdgcn_readfirstlane(jstar >= i0 + wi * 64 && jstar < i0 + wi * 64 + 64) != 0;
+  {
+    const int64_t i = i0 + wi * 64 + lane;   // < n_pad
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      float v = a.bpre[(size_t)s * n_pad + i], vx = i == jstar ? -INFINITY : v;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        v = fmaxf(v, __shfl_xor(v, off, 64));
+        vx = fmaxf(vx, __shfl_xor(vx, off, 64));
+      }
+      bA[s] = v;
+      bAx[s] = vx;
+    }
+  }
+  // the transposed check's limits per wave in LDS, read after each tile's barrier (kept in registers they
+  // would be spilled, and the reload would wait for every copy in flight): -(margin + 1) less the
+  // wave's largest source bias, with j* left out and with it
+  if (lane == 0)
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const double lim = -((double)margin[s] + 1.0);
+      slim[wi][0][s] = lim - (double)bAx[s];
+      slim[wi][1][s] = lim - (double)bA[s];
+    }
+  typedef const __attribute__((address_space(4))) float* const_f32_ptr;
+  const float* tmax = a.bpre + (size_t)S * n_pad;   // [S][n_pad / 128] the tiles' maxima
+  float bblk[S];
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    float m = -INFINITY;
+    for (int t = lane; t < ntiles; t += 64) m = fmaxf(m, tmax[(size_t)s * (n_pad / kMJ) + (size_t)jt0 + t]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+    bblk[s] = m;
+  }
+  // the group bounds of the block's sources (B0 .. B1, 4 groups each) into LDS: stT[(c S + s) 4 kSymChunk + k]
+  {
+    const int ng = 4 * (B1 - B0);   // <= 4 kSymChunk
+    for (int e = threadIdx.x; e < 2 * S * ng; e += kPW * 64) {
+      const int cs = e / ng, k = e % ng;
+      stT[cs * 4 * kSymChunk + k] = a.tT[(size_t)cs * a.ngroups + 4 * B0 + k];
+    }
+  }
+  wait_vmcnt<0>();   // before the first copy: the waits below count copies only (the first tile's barrier
+                     // publishes stT)
+
+#pragma unroll
+  for (int p = 0; p < LA; ++p)
+    if (p < ntiles)
+#pragma unroll
+      for (int u = 0; u < PC; ++u)
+        prescreen_issue(gb, n_pad, smem_lds + ((p * PC + u) % NS) * kPStage, u, (int64_t)(jt0 + p) * kPJ, wave);
+
+  bool anyT = false;
+  // writes the flag entries (B, 2A) and (B, 2A + 1) from the waves' bits of B (wave 0, after a barrier)
+  // (the lane index is formed afresh here: a value kept from the kernel's start would be spilled, and
+  // its reload would wait for every copy in flight)
+  auto store_transposed = [&](int B) {
+    if (wave == 0) {
+      const int h = fresh_lane();   // A's source tile 2A + h: waves 2h and 2h + 1
+      if (h < 2) {
+        const uint8_t(*sb)[4] = sbits[B & 1];
+        uint64_t v = 0;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) v |= (uint64_t)(sb[2 * h][w] | sb[2 * h + 1][w]) << (8 * w);
+        *reinterpret_cast<uint64_t*>(a.flags + ((size_t)B * a.jtl + 2 * A + h) * 8) = v;
+      }
+    }
+  };
+  for (int t = 0; t < ntiles; ++t) {
+    const int jt = jt0 + t;
+    const int64_t j0 = (int64_t)jt * kPJ;
+    const int B = jt >> 1, hB = jt & 1;
+    if (t + LA - 1 < ntiles) wait_vmcnt<(LA - 1) * PC>();
+    else wait_vmcnt<0>();
+    __syncthreads();   // the copies of tile t have landed for every wave; the bits of the B before last are read
+    if (hB == 0 && B - 1 > A && B - 1 >= B0) store_transposed(B - 1);
+    if (t + LA < ntiles)
+#pragma unroll
+      for (int u = 0; u < PC; ++u)
+        prescreen_issue(gb, n_pad, smem_lds + (((t + LA) * PC + u) % NS) * kPStage, u, j0 + (int64_t)LA * kPJ, wave);
+    f32x16_t G[kIB][kSJB];
+#pragma unroll
+    for (int x = 0; x < kIB; ++x)
+#pragma unroll
+      for (int y = 0; y < kSJB; ++y)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) G[x][y][v] = 0.f;
+#pragma unroll
+    for (int u = 0; u < PC; ++u) {
+      const unsigned char* base = smem + ((t * PC + u) % NS) * kPStage;
+      const int ln = fresh_lane(), cl = ln & 31, gl = ln >> 5;
+      bf16x8_t xh[kSJB];
+#pragma unroll
+      for (int jb = 0; jb < kSJB; ++jb) {
+        const int row = jb * 32 + cl;
+        xh[jb] = *reinterpret_cast<const bf16x8_t*>(base + row * 32 + swz<2>(row, gl) * 16);
+      }
+#pragma unroll
+      for (int ib = 0; ib < kIB; ++ib)
+#pragma unroll
+        for (int jb = 0; jb < kSJB; ++jb)
+          G[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[jb], bt[u][ib], G[ib][jb], 0, 0, 0);
+    }
+    // the lane's maxima of G per (node block ib, source half q): both orientations' coarse bounds
+    // take them, so that the tile's values are scanned once
+    float pm[kIB][2];
+#pragma unroll
+    for (int ib = 0; ib < kIB; ++ib)
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        float m = -INFINITY;
+#pragma unroll
+        for (int jb = 2 * q; jb < 2 * q + 2; ++jb)
+#pragma unroll
+          for (int v = 0; v < 16; ++v) m = fmaxf(m, G[ib][jb][v]);
+        pm[ib][q] = m;
+      }
+    // (1) A's rows against this tile's sources: as prescreen_block
+    const bool diag = j0 < i0 + kMI && i0 < j0 + kPJ;
+    float gmax[kIB];
+#pragma unroll
+    for (int ib = 0; ib < kIB; ++ib) gmax[ib] = fmaxf(pm[ib][0], pm[ib][1]);
+    bool doubt = false;
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+#pragma unroll
+      for (int ib = 0; ib < kIB; ++ib) doubt |= fmaf(a.c1[s], gmax[ib], bblk[s]) + at[ib][s] > M[ib][s] - margin[s];
+    if (__any(doubt)) {
+      const const_f32_ptr bmax = (const_f32_ptr)(tmax + (size_t)jt);
+      doubt = false;
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const float bm = bmax[(size_t)s * (n_pad / kMJ)];
+#pragma unroll
+        for (int ib = 0; ib < kIB; ++ib) doubt |= fmaf(a.c1[s], gmax[ib], bm) + at[ib][s] > M[ib][s] - margin[s];
+      }
+    }
+    bool need = false;
+    if (__any(doubt)) {
+      const bool htile = jstar >= j0 && jstar < j0 + kPJ;
+      int bself[kIB], bheavy[kIB];
+#pragma unroll
+      for (int ib = 0; ib < kIB; ++ib) {
+        const int64_t i = i0 + wi * (32 * kIB) + ib * 32 + col;
+        bself[ib] = diag ? slab_index<kSJB>(i - j0, g) : -1;
+        bheavy[ib] = (htile && hv[ib]) ? slab_index<kSJB>(jstar - j0, g) : -1;
+      }
+      typedef float f32x8_t __attribute__((ext_vector_type(8)));
+      typedef const __attribute__((address_space(4))) f32x8_t* const_f32x8_ptr;
+      const const_f32x8_ptr bs = (const_f32x8_ptr)(a.bpre + j0);
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const float c1 = a.c1[s];
+        float m[kIB];
+#pragma unroll
+        for (int ib = 0; ib < kIB; ++ib) m[ib] = -INFINITY;
+#pragma unroll
+        for (int jb = 0; jb < kSJB; ++jb) {
+#pragma unroll
+          for (int v = 0; v < 16; ++v) {
+            const f32x8_t q = bs[((size_t)s * n_pad) / 8 + jb * 4 + (v >> 2)];
+            const float bj = g ? q[4 + (v & 3)] : q[v & 3];
+#pragma unroll
+            for (int ib = 0; ib < kIB; ++ib) {
+              float e = fmaf(c1, G[ib][jb][v], bj);
+              if (jb * 16 + v == bself[ib] || jb * 16 + v == bheavy[ib]) e = -INFINITY;
+              m[ib] = fmaxf(m[ib], e);
+            }
+          }
+        }
+#pragma unroll
+        for (int ib = 0; ib < kIB; ++ib) need |= m[ib] + at[ib][s] > M[ib][s] - margin[s];
+      }
+    }
+    const bool flag = __any(need);
+    if (lane == 0 && jt < a.jtl) {
+      a.flags[((size_t)A * a.jtl + jt) * 8 + wi] = flag ? 1 : 0;
+      a.flags[((size_t)A * a.jtl + jt) * 8 + 4 + wi] = 0;
+      if (flag && a.any_flag) *a.any_flag = 1;
+    }
+    // (2) B's rows (sub-blocks 2 hB and 2 hB + 1) against the wave's 64 sources of A: the coarse bound
+    if (B != A) {
+      float gm[2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        float m = -INFINITY;
+#pragma unroll
+        for (int ib = 0; ib < kIB; ++ib) m = fmaxf(m, pm[ib][q]);
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+        gm[q] = m;
+      }
+      // (the groups' bounds from LDS: a load from memory here would wait for the copies in flight)
+      bool fq[2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int k = (B - B0) * 4 + 2 * hB + q;   // B's 64-row group, within the block's sources
+        bool f = false;
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+          // in FP64, with one bit of slack for the terms' own FP32 rounding
+          const double th = stT[s * 4 * kSymChunk + k], tn = stT[(S + s) * 4 * kSymChunk + k];
+          const double cg = (double)a.c1[s] * (double)gm[q];
+          f |= cg + th > slim[wi][0][s];
+          f |= cg + tn > slim[wi][1][s];
+        }
+        fq[q] = f;
+      }
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        if (!fq[q]) continue;   // wave-uniform
+        // the rows one by one (rare): the lane's maxima over its nodes of A per source column, then the
+        // maxima across the lanes and the check, out of line
+        float tl[2][S][32];
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+#pragma unroll
+          for (int jb = 2 * q; jb < 2 * q + 2; ++jb)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+              float t = -INFINITY, tx = -INFINITY;
+#pragma unroll
+              for (int ib = 0; ib < kIB; ++ib) {
+                const float e = fmaf(a.c1[s], G[ib][jb][v], bown[ib][s]);
+                t = fmaxf(t, e);
+                if (ib != jsl) tx = fmaxf(tx, e);
+              }
+              tl[0][s][(jb - 2 * q) * 16 + v] = t;
+              tl[1][s][(jb - 2 * q) * 16 + v] = tx;
+            }
+        fq[q] = sym_rows_check<S>(a, &tl[0][0][0], jsw, j0 + 64 * q, g, margin);
+      }
+      if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          sbits[B & 1][wi][2 * hB + q] = fq[q] ? 1 : 0;
+          anyT |= fq[q];
+        }
+        if (hB == 0 && jt + 1 >= a.jtl) {   // B's second tile lies past the last node: its rows are empty
+          sbits[B & 1][wi][2] = 0;
+          sbits[B & 1][wi][3] = 0;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  {
+    const int Bl = (jt1 - 1) >> 1;
+    if (Bl > A) store_transposed(Bl);
+  }
+  if (anyT && a.any_flag) *a.any_flag = 1;
+}
+
+template <int S, int PC, int NS>
+__global__ void __launch_bounds__(kPW * 64, 2) k_pair_prescreen_sym(MArgs a) {
+  __shared__ __attribute__((aligned(1024))) unsigned char smem[NS * kPStage];
+  __shared__ uint8_t sbits[2][4][4];
+  __shared__ float stT[2 * S * 4 * kSymChunk];
+  __shared__ double slim[kPW][2][S];
+  const int4 it = a.sym_items[blockIdx.x];
+  prescreen_sym_block<S, PC, NS>(a, __builtin_amdgcn_readfirstlane(it.x), __builtin_amdgcn_readfirstlane(it.y),
+                                 __builtin_amdgcn_readfirstlane(it.z), smem, sbits, stT, slim);
+}
+
 template <int S, int PC, int NS>
 __global__ void __launch_bounds__(kPW * 64, 2) k_pair_prescreen(MArgs a) {
   __shared__ __attribute__((aligned(1024))) unsigned char smem[NS * kPStage];
@@ -1499,6 +1924,11 @@ static MArgs make_args(const PairArgs& pa, int prec, const MfmaExtra& ex) {
   m.rref = pa.pull ? nullptr : ex.rref;
   m.rhv = pa.pull ? nullptr : ex.rhv;
   m.jstar = pa.pull ? nullptr : ex.jstar;
+  m.sym_items = ex.sym_items;
+  m.tT = ex.tT;
+  m.tTn = ex.tT ? ex.tT + 2 * (size_t)pa.S * (ex.n_pad / 64) : nullptr;
+  m.sym_nitems = ex.sym_nitems;
+  m.ngroups = (int32_t)(ex.n_pad / 64);
   return m;
 }
 
@@ -1581,8 +2011,18 @@ static yy_status launch_s(hipStream_t st, const MArgs& m, int prec, int nblocks,
     mp.s_nsplit = ps;
     mp.s_jps = ((stiles + ps - 1) / ps) * kPJ;
     static_assert(kPreK == 64, "4 K stages, or 2 where r_p = 32");
-    if (m.pre_chunks == 4) k_pair_prescreen<S, 4, 16><<<m.tb_count * ps, kPW * 64, 0, st>>>(mp);
-    else k_pair_prescreen<S, 2, 8><<<m.tb_count * ps, kPW * 64, 0, st>>>(mp);
+    if (m.sym_items && m.sym_nitems > 0 && m.rref) {
+      // many target blocks: the symmetric screen (each pair of target blocks once), after the
+      // rows' bounds for its transposed orientation
+      k_tgt_bound<<<(unsigned)((m.ngroups + kBlock / 64 - 1) / (kBlock / 64)), kBlock, 0, st>>>(m);
+      YY_LAUNCH_CHECK("k_tgt_bound");
+      if (m.pre_chunks == 4) k_pair_prescreen_sym<S, 4, 16><<<m.sym_nitems, kPW * 64, 0, st>>>(m);
+      else k_pair_prescreen_sym<S, 2, 8><<<m.sym_nitems, kPW * 64, 0, st>>>(m);
+    } else if (m.pre_chunks == 4) {
+      k_pair_prescreen<S, 4, 16><<<m.tb_count * ps, kPW * 64, 0, st>>>(mp);
+    } else {
+      k_pair_prescreen<S, 2, 8><<<m.tb_count * ps, kPW * 64, 0, st>>>(mp);
+    }
     YY_LAUNCH_CHECK("k_pair_mfma (partial-distance screen)");
     if (dp) {
       // the planes beyond the screen's prefix, if it flagged a tile and they are not yet written

@@ -496,7 +496,6 @@ __device__ __forceinline__ void k_row_ref_body(const RowRefArgs& a, int bx_) {
     if (need) {
       const double* xi = a.x + (size_t)i * a.r;
       const double* xj = a.x + (size_t)js * a.r;
-#pragma unroll 4
       for (int32_t k = sl; k < a.r; k += L) {
         const double d = xi[k] - xj[k], fk = a.fstar[k];
         for (int s = 0; s < a.S; ++s) {
@@ -1253,6 +1252,32 @@ yy_status propagate_begin(yy_ctx ctx, const yy_model* model, const yy_scales* sc
     ex.rref = ra.rref;
     ex.rhv = ra.rhv;
     ex.jstar = ra.jstar;
+    const int64_t tbs = ex.n_pad / 256;
+    if (prec == YY_PREC_BF16X3P && tbs > kSymMinBlocks) {
+      // the symmetric screen's work items: target block A against the target blocks [B0, B1) >= A as
+      // sources, kSymChunk at a time, the longest first (then by source range, so that items started
+      // together share sources); built once per block count
+      if (ctx->sym_tbs != tbs) {
+        std::vector<int4> items;
+        for (int64_t A = 0; A < tbs; ++A)
+          for (int64_t B0 = A; B0 < tbs; B0 += kSymChunk)
+            items.push_back(make_int4((int)A, (int)B0, (int)std::min<int64_t>(B0 + kSymChunk, tbs), 0));
+        std::stable_sort(items.begin(), items.end(), [](const int4& u, const int4& v) {
+          const int lu = u.z - u.y, lv = v.z - v.y;
+          return lu != lv ? lu > lv : u.y < v.y;
+        });
+        if ((st = ctx->sym_items.ensure(items.size() * sizeof(int4))) != YY_OK) return st;
+        YY_HIP(hipMemcpyAsync(ctx->sym_items.ptr, items.data(), items.size() * sizeof(int4), hipMemcpyHostToDevice,
+                              ctx->stream));
+        YY_HIP(hipStreamSynchronize(ctx->stream));   // `items` is a host temporary
+        ctx->sym_tbs = tbs;
+        ctx->sym_nitems = (int)items.size();
+      }
+      if ((st = ctx->tT.ensure(2 * (size_t)S * (ex.n_pad / 64 + ex.n_pad) * sizeof(float))) != YY_OK) return st;
+      ex.sym_items = ctx->sym_items.as<int4>();
+      ex.tT = ctx->tT.as<float>();
+      ex.sym_nitems = ctx->sym_nitems;
+    }
   }
 
   // (4) combination parameters
