@@ -291,6 +291,7 @@ yy_status yy_destroy(yy_ctx ctx) {
   ctx->rref.release();
   ctx->sym_items.release();
   ctx->tT.release();
+  ctx->sym_list.release();
   ctx->fstar.release();
   ctx->lw2.release();
   ctx->part.release();

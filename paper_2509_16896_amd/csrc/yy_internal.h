@@ -129,9 +129,11 @@ struct yy_ctx_s {
   yy::DevBuf sflags;                  // screen verdicts of the screened split form
   yy::DevBuf obsw;                    // general observation noise: h(x) rows, W_b h(x) rows, W_b dy
   yy::DevBuf rref;                    // float [2][S][n]: lower bounds of the pairwise rows' maxima, heavy-pair terms
-  yy::DevBuf sym_items, tT;           // the symmetric screen: int4 work items; float [2][S][n_pad / 64] then [2][S][n_pad]
+  yy::DevBuf sym_items, tT, sym_list;  // the symmetric screen: int4 work items; float [2][S][n_pad / 64];
+                                       // the doubted units' counter (16 bytes) and int4 list
   int64_t sym_tbs = 0;                // target blocks the items were built for
   int sym_nitems = 0;
+  int sym_cap = 0;                    // list entries: 8 per tile of the items (2 row groups x 4 waves), at most kSymListMax
   yy::DevBuf fstar;                   // double [r]: f at the heaviest source
   int64_t sflags_tbs = 0, sflags_jtl = 0;   // their shape at the last screened propagation
   // tuned source-split counts: (rp, n_pad, S, prec) -> nsplit
@@ -223,12 +225,17 @@ struct MfmaExtra {
   const float* rhv = nullptr;      // [S][n] the pair (i, j*) counted apart (exact term), or -inf; with rref
   const long long* jstar = nullptr;   // j*, the heaviest source (-1: none); with rref
   // BF16X3P on one run with more than kSymMinBlocks target blocks: the symmetric screen's work items
-  // (A, B0, B1) and its row bounds ([2][S][n_pad / 64] per 64-row group, then [2][S][n_pad] per row)
+  // (A, B0, B1), its row bounds ([2][S][n_pad / 64] per 64-row group), and the counter and list of the
+  // units whose coarse bound doubted (room for sym_cap)
   const int4* sym_items = nullptr;
   float* tT = nullptr;
   int sym_nitems = 0;
+  int* sym_n = nullptr;
+  int4* sym_list = nullptr;
+  int sym_cap = 0;
 };
 constexpr int kSymMinBlocks = 32;   // target blocks of 256 above which the symmetric screen runs
+constexpr int64_t kSymListMax = 1 << 20;   // doubted units held at most (a full list flags the rest)
 constexpr int kSymChunk = 32;       // target blocks of sources per work item
 // blocks of the node preparation kernel (one wave per 4 nodes, grid-stride)
 int prepare_blocks(int64_t n_pad);

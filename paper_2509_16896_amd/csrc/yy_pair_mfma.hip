@@ -100,8 +100,12 @@ struct MArgs {
   // heavy pair counted apart (tT[s][g]) and without (tT[(S + s)][g])
   const int4* sym_items;
   const float* tT;
-  const float* tTn;            // the same per row: [2][S][n_pad], -inf where the row is in the other class
   int32_t sym_nitems, ngroups;
+  // the units (B, group of 64 rows of B, A, wave of A) whose coarse bound doubted, for k_sym_recheck: a
+  // counter (cleared by k_tgt_bound) and room for sym_cap entries
+  int* sym_n;
+  int4* sym_list;
+  int32_t sym_cap;
 };
 
 // j* of the call (-1: none, or no rows floor), read once per block and kept in scalar registers
@@ -1376,18 +1380,18 @@ __device__ __forceinline__ void prescreen_block(const MArgs& a, int tb, int spli
 // by exactly one wave per call: (A, tiles of B >= A) in the normal orientation,
 // (B, tiles of A < B) in the transposed one.
 //
-// Where that coarse bound leaves a doubt, the rows are checked one by one: per
-// source column j of the wave's products, max_i (c1 G_ij + b_i) over the wave's
-// 64 nodes of A (a maximum across the 32 lanes that hold the column), plus
-// a_j - M_j against -margin.
+// Where that coarse bound leaves a doubt, the unit (B, group, A, wave) goes to a
+// list, and k_sym_recheck takes the group's rows against the wave's sources one
+// by one with the per-row verdict, after the screen.
 //
-// k_tgt_bound: per row and scale a_j^p + hx_j^p F^p - M_j, in one of two arrays by
-// whether the row counts the heavy pair apart (-inf in the other; a_j is the
-// screen's target term, M_j the row's lower bound as the screens take it), and
-// per 64-row group the maxima of both.
+// k_tgt_bound: per 64-row group and scale the largest a_j^p + hx_j^p F^p - M_j over
+// the group's rows, split by whether the row counts the heavy pair apart (a_j is
+// the screen's target term, M_j the row's lower bound as the screens take it);
+// and it clears the list's counter.
 __global__ void __launch_bounds__(kBlock) k_tgt_bound(MArgs a) {
   const int lane = threadIdx.x & 63;
   const int g = (int)(((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6);
+  if (blockIdx.x == 0 && threadIdx.x == 0) *a.sym_n = 0;
   if (g >= a.ngroups) return;   // whole waves: ngroups groups of 64 rows
   const int64_t j = (int64_t)g * 64 + lane;
   const double F = a.scal[5];
@@ -1398,7 +1402,6 @@ __global__ void __launch_bounds__(kBlock) k_tgt_bound(MArgs a) {
   const bool hv = valid && a.rhv && a.rhv[j] != -INFINITY;
   const double hF = 2.0 * a.kapd[0] * a.taud[0] * sqrt(nx) * F * (1.0 + 0x1p-20);
   float* out = const_cast<float*>(a.tT);
-  float* outn = const_cast<float*>(a.tTn);
   for (int s = 0; s < a.S; ++s) {
     float v = -INFINITY;
     if (valid) {
@@ -1408,8 +1411,6 @@ __global__ void __launch_bounds__(kBlock) k_tgt_bound(MArgs a) {
       v = at - M;   // +inf where M = -inf: any pair may then be near
     }
     float vh = hv ? v : -INFINITY, vn = hv ? -INFINITY : v;
-    outn[(size_t)s * a.n_pad + j] = vh;
-    outn[(size_t)(a.S + s) * a.n_pad + j] = vn;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
       vh = fmaxf(vh, __shfl_xor(vh, off, 64));
@@ -1422,31 +1423,51 @@ __global__ void __launch_bounds__(kBlock) k_tgt_bound(MArgs a) {
   }
 }
 
-// The transposed rows of one 64-source half of a tile, one by one: tl[0][s][c] and tl[1][s][c] are
-// this lane's maxima of c1 G_ij + b_i over its nodes i of A for column c (c = 16 jb' + v of the
-// half), with and without j*; the maxima across the 32 lanes that hold the column, plus the row's
-// a_j - M_j (tTn), against -margin.  Returns whether any row of the half may hold a near pair.
-template <int S>
-__device__ __noinline__ bool sym_rows_check(const MArgs& a, const float* tl, bool jsw, int64_t jh, int g,
-                                            const float* margin) {
-  bool f = false;
+// DPP moves within rows of 16 lanes (quad_perm and row_ror controls): every lane gets the largest value of
+// its row; with the four rows' lanes 0 read as scalars a wave is reduced without the LDS permute path.
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float row16_max(float v) {
+  v = fmaxf(v, dpp_mov<0xB1>(v));    // quad_perm [1, 0, 3, 2]
+  v = fmaxf(v, dpp_mov<0x4E>(v));    // quad_perm [2, 3, 0, 1]
+  v = fmaxf(v, dpp_mov<0x124>(v));   // row_ror 4
+  return fmaxf(v, dpp_mov<0x128>(v));   // row_ror 8
+}
+__device__ __forceinline__ float lane_of(float v, int l) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+
+// The partial-distance screen's per-scale margin over its first PC stages, and per target row i its term
+// a_i^p + hx_i^p F^p, the lower bound M_i of its maximum (the row floor, else the self-pair exponent)
+// and whether it counts the pair with the heaviest source apart.
+template <int S, int PC>
+__device__ __forceinline__ void screen_margins(const MArgs& a, float (&margin)[S]) {
+  const double X = a.scal[4], F = a.scal[5];
+  const double gam = PC * kKC * 0x1p-24;
+#pragma unroll
   for (int s = 0; s < S; ++s) {
-    const double lim = -((double)margin[s] + 1.0);
-    for (int c = 0; c < 32; ++c) {
-      float t = tl[s * 32 + c], tx = tl[(S + s) * 32 + c];
-      for (int off = 1; off < 32; off <<= 1) {   // the 32 lanes of this lane half hold the column
-        t = fmaxf(t, __shfl_xor(t, off, 64));
-        tx = fmaxf(tx, __shfl_xor(tx, off, 64));
-      }
-      if (!jsw) tx = t;
-      const int jb = c >> 4, v = c & 15;
-      const int64_t j = jh + jb * 32 + 8 * (v >> 2) + 4 * g + (v & 3);
-      const double th = a.tTn[(size_t)s * a.n_pad + j], tn = a.tTn[(size_t)(S + s) * a.n_pad + j];
-      f |= (double)tx + th > lim;
-      f |= (double)t + tn > lim;
-    }
+    const double XT = X + a.taud[s] * F;
+    const double dD = 2.0 * X * (a.eps_g1 + gam) * X + 16.0 * 0x1p-24 * XT * XT;
+    margin[s] = (float)(2.0 * a.kapd[s] * dD + (double)kSkip + 16.0);
   }
-  return __any(f);
+}
+template <int S>
+__device__ __forceinline__ bool screen_target(const MArgs& a, int64_t i, float (&at)[S], float (&M)[S]) {
+  const double F = a.scal[5];
+  const bool valid = i < a.n && !a.bnd[i];
+  const double nx = valid ? a.node[3 * a.n + i] : 0.0;
+  const double nf = valid ? a.node[a.n + i] : 0.0;
+  const float li = valid ? a.lw2[i] : -INFINITY;
+  const double hF = 2.0 * a.kapd[0] * a.taud[0] * sqrt(nx) * F * (1.0 + 0x1p-20);
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    at[s] = valid ? (float)(-a.kapd[s] * nx + hF) : -INFINITY;
+    const float self = (valid && li != -INFINITY) ? li - (float)(a.kapd[s] * a.taud[s] * a.taud[s] * nf) : -INFINITY;
+    M[s] = (valid && a.rref) ? a.rref[(size_t)s * a.n + i] : self;
+  }
+  return valid && a.rhv && a.rhv[i] != -INFINITY;
 }
 
 template <int S, int PC, int NS>
@@ -1469,51 +1490,22 @@ __device__ __forceinline__ void prescreen_sym_block(const MArgs& a, int A, int B
   const int64_t n_pad = a.n_pad;
   const uint32_t smem_lds = __builtin_amdgcn_readfirstlane(lds_addr(smem));
 
-  const double X = a.scal[4], F = a.scal[5];
-  const double gam = PC * kKC * 0x1p-24;
   float at[kIB][S], M[kIB][S], margin[S];
-#pragma unroll
-  for (int s = 0; s < S; ++s) {
-    const double XT = X + a.taud[s] * F;
-    const double dD = 2.0 * X * (a.eps_g1 + gam) * X + 16.0 * 0x1p-24 * XT * XT;
-    margin[s] = (float)(2.0 * a.kapd[s] * dD + (double)kSkip + 16.0);
-  }
+  screen_margins<S, PC>(a, margin);
   bf16x8_t bt[PC][kIB];
   bool hv[kIB];
   const int64_t jstar = heavy_source(a);
 #pragma unroll
   for (int ib = 0; ib < kIB; ++ib) {
     const int64_t i = i0 + wi * (32 * kIB) + ib * 32 + col;
-    const bool valid = i < a.n && !a.bnd[i];
-    hv[ib] = valid && a.rhv && a.rhv[i] != -INFINITY;
-    const double nx = valid ? a.node[3 * a.n + i] : 0.0;
-    const double nf = valid ? a.node[a.n + i] : 0.0;
-    const float li = valid ? a.lw2[i] : -INFINITY;
-    const double hF = 2.0 * a.kapd[0] * a.taud[0] * sqrt(nx) * F * (1.0 + 0x1p-20);
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-      at[ib][s] = valid ? (float)(-a.kapd[s] * nx + hF) : -INFINITY;
-      const float self = (valid && li != -INFINITY) ? li - (float)(a.kapd[s] * a.taud[s] * a.taud[s] * nf) : -INFINITY;
-      M[ib][s] = (valid && a.rref) ? a.rref[(size_t)s * a.n + i] : self;
-    }
+    hv[ib] = screen_target<S>(a, i, at[ib], M[ib]);
 #pragma unroll
     for (int c = 0; c < PC; ++c)
       bt[c][ib] = *reinterpret_cast<const bf16x8_t*>(gb + ((size_t)c * n_pad + i) * 32 + g * 16);
   }
   // the transposed orientation: the wave's 64 nodes of A as sources, their largest prefix bias with
   // and without j*
-  float bA[S], bAx[S], bown[kIB][S];
-#pragma unroll
-  for (int ib = 0; ib < kIB; ++ib)
-#pragma unroll
-    for (int s = 0; s < S; ++s) bown[ib][s] = a.bpre[(size_t)s * n_pad + i0 + wi * 64 + ib * 32 + col];
-  // where the wave's nodes hold j*, the lane that holds it as node ib (-1: none)
-  int jsl = -1;
-  if (jstar >= i0 + wi * 64 && jstar < i0 + wi * 64 + 64) {
-    const int d = (int)(jstar - i0 - wi * 64);
-    if ((d & 31) == col) jsl = d >> 5;
-  }
-  const bool jsw = __builtin_amdgcn_readfirstlane(jstar >= i0 + wi * 64 && jstar < i0 + wi * 64 + 64) != 0;
+  float bA[S], bAx[S];
   {
     const int64_t i = i0 + wi * 64 + lane;   // < n_pad
 #pragma unroll
@@ -1703,9 +1695,8 @@ __device__ __forceinline__ void prescreen_sym_block(const MArgs& a, int A, int B
         float m = -INFINITY;
 #pragma unroll
         for (int ib = 0; ib < kIB; ++ib) m = fmaxf(m, pm[ib][q]);
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
-        gm[q] = m;
+        m = row16_max(m);
+        gm[q] = fmaxf(fmaxf(lane_of(m, 0), lane_of(m, 16)), fmaxf(lane_of(m, 32), lane_of(m, 48)));
       }
       // (the groups' bounds from LDS: a load from memory here would wait for the copies in flight)
       bool fq[2];
@@ -1723,35 +1714,20 @@ __device__ __forceinline__ void prescreen_sym_block(const MArgs& a, int A, int B
         }
         fq[q] = f;
       }
-#pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        if (!fq[q]) continue;   // wave-uniform
-        // the rows one by one (rare): the lane's maxima over its nodes of A per source column, then the
-        // maxima across the lanes and the check, out of line
-        float tl[2][S][32];
-#pragma unroll
-        for (int s = 0; s < S; ++s)
-#pragma unroll
-          for (int jb = 2 * q; jb < 2 * q + 2; ++jb)
-#pragma unroll
-            for (int v = 0; v < 16; ++v) {
-              float t = -INFINITY, tx = -INFINITY;
-#pragma unroll
-              for (int ib = 0; ib < kIB; ++ib) {
-                const float e = fmaf(a.c1[s], G[ib][jb][v], bown[ib][s]);
-                t = fmaxf(t, e);
-                if (ib != jsl) tx = fmaxf(tx, e);
-              }
-              tl[0][s][(jb - 2 * q) * 16 + v] = t;
-              tl[1][s][(jb - 2 * q) * 16 + v] = tx;
-            }
-        fq[q] = sym_rows_check<S>(a, &tl[0][0][0], jsw, j0 + 64 * q, g, margin);
-      }
+
+      // where the bound doubts, the group's rows go to k_sym_recheck (its flag byte stays 0 here; with
+      // the list full, the group is flagged)
       if (lane == 0) {
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
-          sbits[B & 1][wi][2 * hB + q] = fq[q] ? 1 : 0;
-          anyT |= fq[q];
+          bool bit = false;
+          if (fq[q]) {
+            const int u = atomicAdd(a.sym_n, 1);
+            if (u < a.sym_cap) a.sym_list[u] = make_int4(B, 2 * hB + q, A, wi);
+            else bit = true;
+          }
+          sbits[B & 1][wi][2 * hB + q] = bit ? 1 : 0;
+          anyT |= bit;
         }
         if (hB == 0 && jt + 1 >= a.jtl) {   // B's second tile lies past the last node: its rows are empty
           sbits[B & 1][wi][2] = 0;
@@ -1777,6 +1753,81 @@ __global__ void __launch_bounds__(kPW * 64, 2) k_pair_prescreen_sym(MArgs a) {
   const int4 it = a.sym_items[blockIdx.x];
   prescreen_sym_block<S, PC, NS>(a, __builtin_amdgcn_readfirstlane(it.x), __builtin_amdgcn_readfirstlane(it.y),
                                  __builtin_amdgcn_readfirstlane(it.z), smem, sbits, stT, slim);
+}
+
+// The units where the symmetric screen's coarse bound doubted, row by row in the normal orientation: the 64
+// rows of group grp of target block B against the 64 sources that wave wi of target block A holds, from
+// the same BF16 products over the first PC stages of coordinates (recomputed here), with
+// prescreen_block's per-row verdict (B > A, so no self pair; a row that counts j* apart leaves it out).
+// A flagged unit sets its byte of the flag entry (B, source tile 2A + wi / 2).  A wave per unit, the grid
+// striding over the list.
+template <int S, int PC>
+__global__ void __launch_bounds__(kPW * 64) k_sym_recheck(MArgs a) {
+  const int nu = __builtin_amdgcn_readfirstlane(min(*a.sym_n, a.sym_cap));
+  const int lane = threadIdx.x & 63, col = lane & 31, g = lane >> 5;
+  const int nw = (int)gridDim.x * kPW;
+  int u = __builtin_amdgcn_readfirstlane((int)blockIdx.x * kPW + (int)(threadIdx.x >> 6));
+  if (u >= nu) return;
+  const unsigned char* gb = reinterpret_cast<const unsigned char*>(a.bf);
+  const int64_t n_pad = a.n_pad;
+  float margin[S];
+  screen_margins<S, PC>(a, margin);
+  const int64_t jstar = heavy_source(a);
+  for (; u < nu; u += nw) {
+    const int4 e = a.sym_list[u];
+    const int B = __builtin_amdgcn_readfirstlane(e.x), grp = __builtin_amdgcn_readfirstlane(e.y);
+    const int A = __builtin_amdgcn_readfirstlane(e.z), wi = __builtin_amdgcn_readfirstlane(e.w);
+    const int64_t t0 = (int64_t)B * kMI + grp * 64, s0 = (int64_t)A * kMI + wi * 64;
+    float at[kIB][S], M[kIB][S];
+    bool hv[kIB];
+    bf16x8_t bt[PC][kIB], xs[PC][2];
+#pragma unroll
+    for (int ib = 0; ib < kIB; ++ib) {
+      const int64_t i = t0 + ib * 32 + col;
+      hv[ib] = screen_target<S>(a, i, at[ib], M[ib]);
+#pragma unroll
+      for (int c = 0; c < PC; ++c)
+        bt[c][ib] = *reinterpret_cast<const bf16x8_t*>(gb + ((size_t)c * n_pad + i) * 32 + g * 16);
+    }
+#pragma unroll
+    for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+      for (int c = 0; c < PC; ++c)
+        xs[c][jb] = *reinterpret_cast<const bf16x8_t*>(gb + ((size_t)c * n_pad + s0 + jb * 32 + col) * 32 + g * 16);
+    f32x16_t G[kIB][2];
+#pragma unroll
+    for (int ib = 0; ib < kIB; ++ib)
+#pragma unroll
+      for (int jb = 0; jb < 2; ++jb) {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) G[ib][jb][v] = 0.f;
+#pragma unroll
+        for (int c = 0; c < PC; ++c) G[ib][jb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xs[c][jb], bt[c][ib], G[ib][jb], 0, 0, 0);
+      }
+    bool need = false;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const float c1 = a.c1[s];
+#pragma unroll
+      for (int ib = 0; ib < kIB; ++ib) {
+        float m = -INFINITY;
+#pragma unroll
+        for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+          for (int v = 0; v < 16; ++v) {
+            const int64_t j = s0 + jb * 32 + 8 * (v >> 2) + 4 * g + (v & 3);
+            float ev = fmaf(c1, G[ib][jb][v], a.bpre[(size_t)s * n_pad + j]);
+            if (hv[ib] && j == jstar) ev = -INFINITY;
+            m = fmaxf(m, ev);
+          }
+        need |= m + at[ib][s] > M[ib][s] - margin[s];
+      }
+    }
+    if (__any(need) && lane == 0) {
+      a.flags[((size_t)B * a.jtl + 2 * A + (wi >> 1)) * 8 + grp] = 1;
+      if (a.any_flag) *a.any_flag = 1;
+    }
+  }
 }
 
 template <int S, int PC, int NS>
@@ -1926,7 +1977,9 @@ static MArgs make_args(const PairArgs& pa, int prec, const MfmaExtra& ex) {
   m.jstar = pa.pull ? nullptr : ex.jstar;
   m.sym_items = ex.sym_items;
   m.tT = ex.tT;
-  m.tTn = ex.tT ? ex.tT + 2 * (size_t)pa.S * (ex.n_pad / 64) : nullptr;
+  m.sym_n = ex.sym_n;
+  m.sym_list = ex.sym_list;
+  m.sym_cap = ex.sym_cap;
   m.sym_nitems = ex.sym_nitems;
   m.ngroups = (int32_t)(ex.n_pad / 64);
   return m;
@@ -2018,6 +2071,10 @@ static yy_status launch_s(hipStream_t st, const MArgs& m, int prec, int nblocks,
       YY_LAUNCH_CHECK("k_tgt_bound");
       if (m.pre_chunks == 4) k_pair_prescreen_sym<S, 4, 16><<<m.sym_nitems, kPW * 64, 0, st>>>(m);
       else k_pair_prescreen_sym<S, 2, 8><<<m.sym_nitems, kPW * 64, 0, st>>>(m);
+      YY_LAUNCH_CHECK("k_pair_prescreen_sym");
+      // the doubted units (a wave each; a grid of two blocks per CU strides over the list)
+      if (m.pre_chunks == 4) k_sym_recheck<S, 4><<<512, kPW * 64, 0, st>>>(m);
+      else k_sym_recheck<S, 2><<<512, kPW * 64, 0, st>>>(m);
     } else if (m.pre_chunks == 4) {
       k_pair_prescreen<S, 4, 16><<<m.tb_count * ps, kPW * 64, 0, st>>>(mp);
     } else {

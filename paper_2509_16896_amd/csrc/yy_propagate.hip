@@ -1270,13 +1270,20 @@ yy_status propagate_begin(yy_ctx ctx, const yy_model* model, const yy_scales* sc
         YY_HIP(hipMemcpyAsync(ctx->sym_items.ptr, items.data(), items.size() * sizeof(int4), hipMemcpyHostToDevice,
                               ctx->stream));
         YY_HIP(hipStreamSynchronize(ctx->stream));   // `items` is a host temporary
+        int64_t tiles = 0;
+        for (const int4& u : items) tiles += 2 * (int64_t)(u.z - u.y);
         ctx->sym_tbs = tbs;
         ctx->sym_nitems = (int)items.size();
+        ctx->sym_cap = (int)std::min<int64_t>(8 * tiles, kSymListMax);
       }
-      if ((st = ctx->tT.ensure(2 * (size_t)S * (ex.n_pad / 64 + ex.n_pad) * sizeof(float))) != YY_OK) return st;
+      if ((st = ctx->tT.ensure(2 * (size_t)S * (ex.n_pad / 64) * sizeof(float))) != YY_OK) return st;
+      if ((st = ctx->sym_list.ensure(16 + (size_t)ctx->sym_cap * sizeof(int4))) != YY_OK) return st;
       ex.sym_items = ctx->sym_items.as<int4>();
       ex.tT = ctx->tT.as<float>();
       ex.sym_nitems = ctx->sym_nitems;
+      ex.sym_n = ctx->sym_list.as<int>();
+      ex.sym_list = reinterpret_cast<int4*>(ctx->sym_list.as<unsigned char>() + 16);
+      ex.sym_cap = ctx->sym_cap;
     }
   }
 
