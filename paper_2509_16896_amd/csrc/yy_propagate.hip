@@ -492,22 +492,30 @@ __device__ __forceinline__ void k_row_ref_body(const RowRefArgs& a, int bx_) {
     const int64_t i = i0 + u;
     const bool valid = i < a.n;
     const bool need = valid && sneed[u];
+    // (scale loops unrolled to YY_MAX_SCALES so that D stays in registers)
     double D[YY_MAX_SCALES] = {0, 0, 0, 0, 0, 0};
     if (need) {
       const double* xi = a.x + (size_t)i * a.r;
       const double* xj = a.x + (size_t)js * a.r;
       for (int32_t k = sl; k < a.r; k += L) {
         const double d = xi[k] - xj[k], fk = a.fstar[k];
-        for (int s = 0; s < a.S; ++s) {
-          const double e = d - a.taud[s] * fk;
-          D[s] = fma(e, e, D[s]);
-        }
+#pragma unroll
+        for (int s = 0; s < YY_MAX_SCALES; ++s)
+          if (s < a.S) {
+            const double e = d - a.taud[s] * fk;
+            D[s] = fma(e, e, D[s]);
+          }
       }
     }
-    for (int s = 0; s < a.S; ++s)
-      for (int off = L / 2; off > 0; off >>= 1) D[s] += __shfl_xor(D[s], off, 64);
+    if (__any(need))   // wave-uniform, so the shuffles run in converged flow; skipped where no row needs them
+#pragma unroll
+      for (int s = 0; s < YY_MAX_SCALES; ++s)
+        if (s < a.S)
+          for (int off = L / 2; off > 0; off >>= 1) D[s] += __shfl_xor(D[s], off, 64);
     if (valid && sl == 0)
-      for (int s = 0; s < a.S; ++s) {
+#pragma unroll
+      for (int s = 0; s < YY_MAX_SCALES; ++s) {
+        if (s >= a.S) break;
         float ref = sself[s][u], hv = -INFINITY;
         if (need) {
           hv = (float)(-a.kapd[s] * D[s]);

@@ -26,15 +26,25 @@ def test_algorithmic_flops_of_the_method():
 def test_screened_work():
     w = W.cubic_r1000()
     n2 = 65536.0 * 65536.0
-    # nothing flagged: only the screen's product, over the coordinates it uses
+    # nothing flagged: only the screen's product, over the coordinates it uses; one run of 256 target
+    # blocks takes the symmetric screen: block A against source tiles 2A .. 511, 65792 tiles of 256 x 128
+    sym_pairs = 256.0 * 128.0 * sum(512 - 2 * a for a in range(256))
+    assert sym_pairs == 256.0 * 128.0 * 65792
     alg, ex = bench.screened_work(w, "bf16x3p", 0, 131072)
+    assert alg == ex == 2.0 * sym_pairs * 64
+    alg, ex = bench.screened_work(w, "bf16x3p", 0, 131072, batch=True)
     assert alg == ex == 2.0 * n2 * 64
     alg, ex = bench.screened_work(w, "bf16x3s", 0, 131072)
     assert alg == ex == 2.0 * n2 * 1000
     # every tile flagged: the method's products on top, executed twice over by the split form
     alg, ex = bench.screened_work(w, "bf16x3p", 131072, 131072)
-    assert alg == 2.0 * n2 * 64 + bench.alg_flops(w)
-    assert ex == 2.0 * n2 * 64 + 2.0 * bench.alg_flops(w)
+    assert alg == 2.0 * sym_pairs * 64 + bench.alg_flops(w)
+    assert ex == 2.0 * sym_pairs * 64 + 2.0 * bench.alg_flops(w)
+    # 32 target blocks or fewer: every ordered pair
+    mid = W.shrink(w, n=8192)
+    assert bench.screen_pairs(8192, "bf16x3p") == 8192.0 * 8192.0
+    assert bench.screen_pairs(8193, "bf16x3p") == 256.0 * 128.0 * sum(65 - 2 * a for a in range(33))
+    assert bench.screened_work(mid, "bf16x3p", 0, 1)[0] == 2.0 * 8192 * 8192 * 64
     # a run narrower than the prefix screens all its coordinates
     small = W.shrink(w, r=20, n=1024)
     assert bench.screened_work(small, "bf16x3p", 0, 32)[0] == 2.0 * 1024 * 1024 * 20
