@@ -72,26 +72,26 @@ def alg_flops(w) -> float:
     return 2.0 * w.n * w.n * w.r * P
 
 
-def screen_pairs(n, prec, batch=False):
+def screen_pairs(n, prec, r=1000):
     """Pairs whose screen product is formed: every ordered pair, or, where the symmetric screen
-    runs (BF16X3P on one run with more than SYM_MIN_BLOCKS target blocks of 256), the 256 x 128
-    tiles of each target block A against the source tiles from 2A on (G = X X^T serves both
-    orientations of a block pair; diagonal blocks are formed whole)."""
+    runs (BF16X3P with more than SYM_MIN_BLOCKS target blocks of 256 and r > 32, whose screen spans
+    64 coordinates), the 256 x 128 tiles of each target block A against the source tiles from 2A on
+    (G = X X^T serves both orientations of a block pair; diagonal blocks are formed whole)."""
     tbs = -(-n // 256)
-    if prec != "bf16x3p" or batch or tbs <= SYM_MIN_BLOCKS:
+    if prec != "bf16x3p" or tbs <= SYM_MIN_BLOCKS or r <= 32:
         return float(n) * n
     jtl = -(-n // 128)
     return 256.0 * 128.0 * sum(jtl - 2 * a for a in range(tbs))
 
 
-def screened_work(w, prec, flagged, tiles, batch=False):
+def screened_work(w, prec, flagged, tiles):
     """(algorithmic, executed) matrix-core flop of one propagation in a screened form: the
     screen's product x.x for every pair it forms (screen_pairs) over the coordinates it uses
     (all r for BF16X3S, the first 64 for BF16X3P; the x.f term is bounded, not formed), plus
     the method's products on the flagged tiles, which the split form executes twice over
     (three BF16 products for x.x, one for x.f)."""
     k = w.r if prec == "bf16x3s" else min(PRE_K, w.r)
-    screen = 2.0 * screen_pairs(w.n, prec, batch) * k
+    screen = 2.0 * screen_pairs(w.n, prec, w.r) * k
     split = alg_flops(w) * flagged / max(tiles, 1)
     return screen + split, screen + 2.0 * split
 
@@ -413,7 +413,7 @@ def main_batch(args):
     if args.prec in ("bf16x3s", "bf16x3p"):
         # each run's screen products plus the method's products on its flagged tiles
         counts = {q: bt.screen_count(q) for q in mfma_runs}
-        alg = sum(screened_work(ws[q], args.prec, fl, tl, batch=True)[0] for q, (fl, tl) in counts.items())
+        alg = sum(screened_work(ws[q], args.prec, fl, tl)[0] for q, (fl, tl) in counts.items())
         kernel = ("k_pair_prescreen_batch" if args.prec == "bf16x3p" else "k_pair_screen_batch") + \
             ", then k_pair_mfma_batch (split form) on flagged tiles"
         log(f"[bench] screens flagged {sum(c[0] for c in counts.values())} of "
@@ -563,12 +563,12 @@ def main():
         flagged, tiles = yy.yy_screen_count(f.ctx)
         screen = {"flagged_tiles": flagged, "tiles": tiles}
         alg, executed = screened_work(w, args.prec, flagged, tiles)
-        sym = screen_pairs(w.n, args.prec) < float(w.n) * w.n
+        sym = screen_pairs(w.n, args.prec, w.r) < float(w.n) * w.n
         kernel = ("k_tgt_bound, k_pair_prescreen_sym and k_sym_recheck" if sym else
                   "k_pair_prescreen" if args.prec == "bf16x3p" else "k_pair_screen") + \
             ", then k_pair_mfma (split form) on flagged tiles"
         basis = (f"the screen's x.x over the first {min(PRE_K, w.r)} coordinates for every pair it forms "
-                 f"({'each pair of target blocks once: ' if sym else ''}{screen_pairs(w.n, args.prec):.6g} pairs), "
+                 f"({'each pair of target blocks once: ' if sym else ''}{screen_pairs(w.n, args.prec, w.r):.6g} pairs), "
                  f"plus 2 r P per pair of the flagged tiles ({flagged} of {tiles})" if args.prec == "bf16x3p" else
                  f"the screen's x.x over all r coordinates for every pair, plus 2 r P per pair of the "
                  f"flagged tiles ({flagged} of {tiles})")

@@ -123,6 +123,10 @@ struct yy_batch_s {
   // the pairwise launches: matrix-core runs, then vector-ALU runs by staging width (2, 4, 8, 16)
   yy::DevBuf d_sets, d_items;
   int nitems = 0;
+  // BF16X3P: the screen's work lists (symmetric items for runs of more than kSymMinBlocks target
+  // blocks, one-sided items for the others; group bounds and rechecks of the symmetric runs)
+  yy::DevBuf d_scr_items, d_bound_items, d_recheck_items;
+  yy::BatchScreen scr;
   bool k64 = true;                 // every matrix-core run's K padding is a multiple of 64
   yy::DevBuf v_sets, v_items[4];
   int v_nitems[4] = {0, 0, 0, 0};
@@ -260,6 +264,12 @@ static yy_status build(yy_batch b) {
     int64_t cost;
   };
   std::vector<Item> items;
+  struct ScrItem {
+    int4 it;
+    int64_t cost;
+  };
+  std::vector<ScrItem> sitems;
+  std::vector<int4> bitems, ritems;
   std::vector<int> bias_blocks(nr, 0);
   std::vector<ValuSet> vsets;
   std::vector<int4> vitems[4];
@@ -289,6 +299,28 @@ static yy_status build(yy_batch b) {
       const int64_t cost = ((j1 - j0 + 127) / 128) * (int64_t)P.a.rp;
       for (int64_t tb = 0; tb < tbs; ++tb) items.push_back({q, (int)tb, sp, cost});
     }
+    if (b->prec == YY_PREC_BF16X3P) {
+      // the screen's items, costed in 128-source tiles (a symmetric tile carries both orientations'
+      // verdicts: about 1.4 one-sided tiles)
+      const int64_t jtl = (n + 127) / 128;
+      if (P.ex.sym_items && P.ex.sym_nitems > 0 && P.ex.rref) {
+        for (const int4& u : sym_work_items(tbs)) {
+          const int64_t tiles = std::min<int64_t>(2 * (int64_t)u.z, jtl) - 2 * (int64_t)u.y;
+          sitems.push_back({make_int4(q, u.x, u.y, u.z), tiles * 14 / 10});
+        }
+        const int64_t gblocks = (P.ex.n_pad / 64 + kBlock / 64 - 1) / (kBlock / 64);
+        for (int64_t g = 0; g < gblocks; ++g) bitems.push_back(make_int4(q, (int)g, 0, 0));
+        const int nb = 256;   // blocks striding over the run's list of doubted units (4 waves each;
+                              // blocks past the list's end return at once)
+        for (int g = 0; g < nb; ++g) ritems.push_back(make_int4(q, g, nb, 0));
+      } else {
+        for (int sp = 0; sp < P.a.nsplit; ++sp) {
+          const int64_t j0 = (int64_t)sp * jps, j1 = std::min<int64_t>(j0 + jps, n);
+          for (int64_t tb = 0; tb < tbs; ++tb)
+            sitems.push_back({make_int4(q, (int)tb, sp, -1), (j1 - j0 + 127) / 128});
+        }
+      }
+    }
   }
   std::stable_sort(items.begin(), items.end(), [](const Item& x, const Item& y) { return x.cost > y.cost; });
   if (items.size() > (size_t)INT32_MAX) return fail(YY_ERR_UNSUPPORTED, "yy_batch: too many work items");
@@ -298,6 +330,24 @@ static yy_status build(yy_batch b) {
   if ((st = upload(b, b->d_sets, sets.data(), sets.size())) != YY_OK) return st;
   if ((st = upload(b, b->d_items, it4.data(), it4.size() * sizeof(int4))) != YY_OK) return st;
   b->nitems = (int)items.size();
+  b->scr = yy::BatchScreen{};
+  if (!sitems.empty()) {
+    std::stable_sort(sitems.begin(), sitems.end(), [](const ScrItem& x, const ScrItem& y) { return x.cost > y.cost; });
+    if (sitems.size() > (size_t)INT32_MAX) return fail(YY_ERR_UNSUPPORTED, "yy_batch: too many work items");
+    std::vector<int4> s4(sitems.size());
+    for (size_t t = 0; t < sitems.size(); ++t) s4[t] = sitems[t].it;
+    if ((st = upload(b, b->d_scr_items, s4.data(), s4.size() * sizeof(int4))) != YY_OK) return st;
+    b->scr.screen_items = b->d_scr_items.as<int4>();
+    b->scr.nscreen = (int)s4.size();
+  }
+  if (!bitems.empty()) {
+    if ((st = upload(b, b->d_bound_items, bitems.data(), bitems.size() * sizeof(int4))) != YY_OK) return st;
+    b->scr.bound_items = b->d_bound_items.as<int4>();
+    b->scr.nbound = (int)bitems.size();
+    if ((st = upload(b, b->d_recheck_items, ritems.data(), ritems.size() * sizeof(int4))) != YY_OK) return st;
+    b->scr.recheck_items = b->d_recheck_items.as<int4>();
+    b->scr.nrecheck = (int)ritems.size();
+  }
   b->k64 = true;
   for (const BRun& R : b->runs) b->k64 = b->k64 && (!R.plan.mfma || R.plan.a.rp % 64 == 0);
   if (!vsets.empty() && (st = upload(b, b->v_sets, vsets.data(), vsets.size() * sizeof(ValuSet))) != YY_OK) return st;
@@ -492,7 +542,8 @@ static yy_status launch_pairwise(yy_batch b) {
   hipStream_t strm = b->ctx->stream;
   yy_status st;
   if (b->nitems > 0 &&
-      (st = launch_pair_mfma_batch(strm, b->S, b->prec, b->d_sets.ptr, b->d_items.as<int4>(), b->nitems, b->k64)) !=
+      (st = launch_pair_mfma_batch(strm, b->S, b->prec, b->d_sets.ptr, b->d_items.as<int4>(), b->nitems, b->k64,
+                                   &b->scr)) !=
           YY_OK)
     return st;
   static const int kcs[4] = {2, 4, 8, 16};
@@ -749,6 +800,9 @@ extern "C" yy_status yy_batch_destroy(yy_batch b) {
   b->ctl.release();
   b->d_sets.release();
   b->d_items.release();
+  b->d_scr_items.release();
+  b->d_bound_items.release();
+  b->d_recheck_items.release();
   b->v_sets.release();
   for (int c = 0; c < 4; ++c) b->v_items[c].release();
   if (b->pinned) (void)hipHostFree(b->pinned);

@@ -234,9 +234,13 @@ struct MfmaExtra {
   int4* sym_list = nullptr;
   int sym_cap = 0;
 };
-constexpr int kSymMinBlocks = 32;   // target blocks of 256 above which the symmetric screen runs
+constexpr int kSymMinBlocks = 32;   // target blocks of 256 above which the symmetric screen runs (r_p > 32)
 constexpr int64_t kSymListMax = 1 << 20;   // doubted units held at most (a full list flags the rest)
 constexpr int kSymChunk = 32;       // target blocks of sources per work item
+// The symmetric screen's work items for tbs target blocks: (A, B0, B1, 0), target block A against the
+// target blocks [B0, B1) >= A as sources, kSymChunk at a time, the longest first (then by source range,
+// so that items started together share sources).
+std::vector<int4> sym_work_items(int64_t tbs);
 // blocks of the node preparation kernel (one wave per 4 nodes, grid-stride)
 int prepare_blocks(int64_t n_pad);
 yy_status launch_src_bias(hipStream_t st, const PairArgs& a, const MfmaExtra& ex);
@@ -246,9 +250,21 @@ yy_status launch_pair_mfma(hipStream_t st, const PairArgs& a, int prec, const Mf
 // items[b] = (set, target block, source split, cost).
 size_t pair_mfma_args_bytes();
 void pair_mfma_fill_args(const PairArgs& pa, int prec, const MfmaExtra& ex, void* out);
-// k64: every set's K padding is a multiple of 64 (the screen's four-stage groups)
+// k64: every set's K padding is a multiple of 64 (the screen's four-stage groups).
+// BF16X3P takes its screen's work lists (device int4 arrays) in `scr`: the screen items, (set, A, B0,
+// B1) of the symmetric screen for sets of more than kSymMinBlocks target blocks, (set, target block,
+// source split, -1) for the others; the group-bound items (set, block, 0, 0) and the recheck items
+// (set, block, blocks of the set, 0) of the symmetric sets.
+struct BatchScreen {
+  const int4* screen_items = nullptr;
+  int nscreen = 0;
+  const int4* bound_items = nullptr;
+  int nbound = 0;
+  const int4* recheck_items = nullptr;
+  int nrecheck = 0;
+};
 yy_status launch_pair_mfma_batch(hipStream_t st, int S, int prec, const void* sets, const int4* items, int nitems,
-                                 bool k64);
+                                 bool k64, const BatchScreen* scr = nullptr);
 
 // (4) combination in FP64: merge the source splits, add the constants, signed
 // log-sum-exp over the scales and the identity term.

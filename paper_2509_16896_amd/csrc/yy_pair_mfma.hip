@@ -1388,10 +1388,10 @@ __device__ __forceinline__ void prescreen_block(const MArgs& a, int tb, int spli
 // the group's rows, split by whether the row counts the heavy pair apart (a_j is
 // the screen's target term, M_j the row's lower bound as the screens take it);
 // and it clears the list's counter.
-__global__ void __launch_bounds__(kBlock) k_tgt_bound(MArgs a) {
+__device__ __forceinline__ void tgt_bound_body(const MArgs& a, int bx) {
   const int lane = threadIdx.x & 63;
-  const int g = (int)(((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6);
-  if (blockIdx.x == 0 && threadIdx.x == 0) *a.sym_n = 0;
+  const int g = (int)(((int64_t)bx * kBlock + threadIdx.x) >> 6);
+  if (bx == 0 && threadIdx.x == 0) *a.sym_n = 0;
   if (g >= a.ngroups) return;   // whole waves: ngroups groups of 64 rows
   const int64_t j = (int64_t)g * 64 + lane;
   const double F = a.scal[5];
@@ -1421,6 +1421,13 @@ __global__ void __launch_bounds__(kBlock) k_tgt_bound(MArgs a) {
       out[(size_t)(a.S + s) * a.ngroups + g] = vn;
     }
   }
+}
+__global__ void __launch_bounds__(kBlock) k_tgt_bound(MArgs a) { tgt_bound_body(a, blockIdx.x); }
+// batched: items (run, block of the run's launch)
+__global__ void __launch_bounds__(kBlock) k_tgt_bound_batch(const MArgs* __restrict__ sets,
+                                                            const int4* __restrict__ items) {
+  const int4 it = items[blockIdx.x];
+  tgt_bound_body(sets[__builtin_amdgcn_readfirstlane(it.x)], __builtin_amdgcn_readfirstlane(it.y));
 }
 
 // DPP moves within rows of 16 lanes (quad_perm and row_ror controls): every lane gets the largest value of
@@ -1762,11 +1769,11 @@ __global__ void __launch_bounds__(kPW * 64, 2) k_pair_prescreen_sym(MArgs a) {
 // A flagged unit sets its byte of the flag entry (B, source tile 2A + wi / 2).  A wave per unit, the grid
 // striding over the list.
 template <int S, int PC>
-__global__ void __launch_bounds__(kPW * 64) k_sym_recheck(MArgs a) {
+__device__ __forceinline__ void sym_recheck_body(const MArgs& a, int bx, int nblocks) {
   const int nu = __builtin_amdgcn_readfirstlane(min(*a.sym_n, a.sym_cap));
   const int lane = threadIdx.x & 63, col = lane & 31, g = lane >> 5;
-  const int nw = (int)gridDim.x * kPW;
-  int u = __builtin_amdgcn_readfirstlane((int)blockIdx.x * kPW + (int)(threadIdx.x >> 6));
+  const int nw = nblocks * kPW;
+  int u = __builtin_amdgcn_readfirstlane(bx * kPW + (int)(threadIdx.x >> 6));
   if (u >= nu) return;
   const unsigned char* gb = reinterpret_cast<const unsigned char*>(a.bf);
   const int64_t n_pad = a.n_pad;
@@ -1829,6 +1836,19 @@ __global__ void __launch_bounds__(kPW * 64) k_sym_recheck(MArgs a) {
     }
   }
 }
+template <int S, int PC>
+__global__ void __launch_bounds__(kPW * 64) k_sym_recheck(MArgs a) {
+  sym_recheck_body<S, PC>(a, blockIdx.x, gridDim.x);
+}
+// batched: items (run, block b of the run's nb blocks, nb)
+template <int S>
+__global__ void __launch_bounds__(kPW * 64) k_sym_recheck_batch(const MArgs* __restrict__ sets,
+                                                                const int4* __restrict__ items) {
+  const int4 it = items[blockIdx.x];
+  const MArgs& a = sets[__builtin_amdgcn_readfirstlane(it.x)];
+  const int b = __builtin_amdgcn_readfirstlane(it.y), nb = __builtin_amdgcn_readfirstlane(it.z);
+  sym_recheck_body<S, 4>(a, b, nb);   // four K stages (host rule)
+}
 
 template <int S, int PC, int NS>
 __global__ void __launch_bounds__(kPW * 64, 2) k_pair_prescreen(MArgs a) {
@@ -1841,15 +1861,26 @@ __global__ void __launch_bounds__(kPW * 64, 2) k_pair_prescreen(MArgs a) {
 // Many node sets: block b takes work item items[b] = (set, target block,
 // source split) of the split pass; 4 or 2 K stages as the set's K padding
 // allows, 3 tiles in flight either way.
+// Items of two kinds: (run, A, B0, B1) with B1 > 0, a symmetric-screen item of a run with more than
+// kSymMinBlocks target blocks and r_p > 32; (run, target block, source split, -1), a one-sided one.
 template <int S>
 __global__ void __launch_bounds__(kPW * 64, 2) k_pair_prescreen_batch(const MArgs* __restrict__ sets,
                                                                       const int4* __restrict__ items) {
   __shared__ __attribute__((aligned(1024))) unsigned char smem[16 * kPStage];
+  __shared__ uint8_t sbits[2][4][4];
+  __shared__ float stT[2 * S * 4 * kSymChunk];
+  __shared__ double slim[kPW][2][S];
   const int4 it = items[blockIdx.x];
   const MArgs& a = sets[__builtin_amdgcn_readfirstlane(it.x)];
-  const int tb = __builtin_amdgcn_readfirstlane(it.y), split = __builtin_amdgcn_readfirstlane(it.z);
-  if (__builtin_amdgcn_readfirstlane(a.pre_chunks) == 4) prescreen_block<S, 4, 16>(a, tb, split, smem);
-  else prescreen_block<S, 2, 8>(a, tb, split, smem);
+  const int y = __builtin_amdgcn_readfirstlane(it.y), z = __builtin_amdgcn_readfirstlane(it.z);
+  const int w = __builtin_amdgcn_readfirstlane(it.w);
+  const bool k4 = __builtin_amdgcn_readfirstlane(a.pre_chunks) == 4;
+  if (w > 0) {
+    prescreen_sym_block<S, 4, 16>(a, y, z, w, smem, sbits, stT, slim);   // four K stages (host rule)
+  } else {
+    if (k4) prescreen_block<S, 4, 16>(a, y, z, smem);
+    else prescreen_block<S, 2, 8>(a, y, z, smem);
+  }
 }
 
 
@@ -1994,7 +2025,7 @@ yy_status launch_src_bias(hipStream_t st, const PairArgs& pa, const MfmaExtra& e
 
 template <int S>
 static yy_status launch_batch_s(hipStream_t st, const MArgs* sets, const int4* items, int nitems, int prec,
-                                bool k64) {
+                                bool k64, const BatchScreen* scr) {
   if (prec == YY_PREC_BF16X3) {
     k_pair_mfma_batch<S, 3, 4, 2, false><<<nitems, kNT, 0, st>>>(sets, items);
   } else if (prec == YY_PREC_BF16X3G) {
@@ -2006,9 +2037,21 @@ static yy_status launch_batch_s(hipStream_t st, const MArgs* sets, const int4* i
     YY_LAUNCH_CHECK("k_pair_mfma_batch (screen)");
     k_pair_mfma_batch<S, 2, 4, 2, true><<<nitems, kNT, 0, st>>>(sets, items);
   } else if (prec == YY_PREC_BF16X3P) {
-    // the partial-distance screen over the split pass's work items, then the split pass
-    k_pair_prescreen_batch<S><<<nitems, kPW * 64, 0, st>>>(sets, items);
-    YY_LAUNCH_CHECK("k_pair_mfma_batch (partial-distance screen)");
+    // the group bounds of the symmetric sets, the partial-distance screens (symmetric and one-sided
+    // items in one launch), the recheck of the doubted units, then the split pass
+    if (!scr) return fail(YY_ERR_ARG, "the batched partial-distance screen needs its work lists");
+    if (scr->nbound > 0) {
+      k_tgt_bound_batch<<<scr->nbound, kBlock, 0, st>>>(sets, scr->bound_items);
+      YY_LAUNCH_CHECK("k_tgt_bound_batch");
+    }
+    if (scr->nscreen > 0) {
+      k_pair_prescreen_batch<S><<<scr->nscreen, kPW * 64, 0, st>>>(sets, scr->screen_items);
+      YY_LAUNCH_CHECK("k_pair_mfma_batch (partial-distance screen)");
+    }
+    if (scr->nrecheck > 0) {
+      k_sym_recheck_batch<S><<<scr->nrecheck, kPW * 64, 0, st>>>(sets, scr->recheck_items);
+      YY_LAUNCH_CHECK("k_sym_recheck_batch");
+    }
     k_pair_mfma_batch<S, 2, 4, 2, true><<<nitems, kNT, 0, st>>>(sets, items);
   } else if (prec == YY_PREC_BF16X1) {
     k_pair_mfma_batch<S, 1, 8, 4, false><<<nitems, kNT, 0, st>>>(sets, items);
@@ -2069,12 +2112,11 @@ static yy_status launch_s(hipStream_t st, const MArgs& m, int prec, int nblocks,
       // rows' bounds for its transposed orientation
       k_tgt_bound<<<(unsigned)((m.ngroups + kBlock / 64 - 1) / (kBlock / 64)), kBlock, 0, st>>>(m);
       YY_LAUNCH_CHECK("k_tgt_bound");
-      if (m.pre_chunks == 4) k_pair_prescreen_sym<S, 4, 16><<<m.sym_nitems, kPW * 64, 0, st>>>(m);
-      else k_pair_prescreen_sym<S, 2, 8><<<m.sym_nitems, kPW * 64, 0, st>>>(m);
+      // (the symmetric screen runs only where the screen spans 64 coordinates: four K stages)
+      k_pair_prescreen_sym<S, 4, 16><<<m.sym_nitems, kPW * 64, 0, st>>>(m);
       YY_LAUNCH_CHECK("k_pair_prescreen_sym");
       // the doubted units (a wave each; a grid of two blocks per CU strides over the list)
-      if (m.pre_chunks == 4) k_sym_recheck<S, 4><<<512, kPW * 64, 0, st>>>(m);
-      else k_sym_recheck<S, 2><<<512, kPW * 64, 0, st>>>(m);
+      k_sym_recheck<S, 4><<<512, kPW * 64, 0, st>>>(m);
     } else if (m.pre_chunks == 4) {
       k_pair_prescreen<S, 4, 16><<<m.tb_count * ps, kPW * 64, 0, st>>>(mp);
     } else {
@@ -2123,14 +2165,14 @@ void pair_mfma_fill_args(const PairArgs& pa, int prec, const MfmaExtra& ex, void
 }
 
 yy_status launch_pair_mfma_batch(hipStream_t st, int S, int prec, const void* sets, const int4* items, int nitems,
-                                 bool k64) {
+                                 bool k64, const BatchScreen* scr) {
   if (nitems <= 0) return YY_OK;
   const MArgs* m = static_cast<const MArgs*>(sets);
   switch (S) {
-    case 1: return launch_batch_s<1>(st, m, items, nitems, prec, k64);
-    case 2: return launch_batch_s<2>(st, m, items, nitems, prec, k64);
-    case 3: return launch_batch_s<3>(st, m, items, nitems, prec, k64);
-    case 4: return launch_batch_s<4>(st, m, items, nitems, prec, k64);
+    case 1: return launch_batch_s<1>(st, m, items, nitems, prec, k64, scr);
+    case 2: return launch_batch_s<2>(st, m, items, nitems, prec, k64, scr);
+    case 3: return launch_batch_s<3>(st, m, items, nitems, prec, k64, scr);
+    case 4: return launch_batch_s<4>(st, m, items, nitems, prec, k64, scr);
   }
   return fail(YY_ERR_UNSUPPORTED, "the matrix-core path supports up to 4 scales");
 }

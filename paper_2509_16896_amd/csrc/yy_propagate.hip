@@ -1092,6 +1092,18 @@ yy_status launch_combine(hipStream_t st, const CombineArgs& cb) {
 
 // Steps (1), (2) and the launch parameters of (3) and (4) for one call; the
 // batched step (yy_batch.hip) runs (3) for many plans in one launch.
+std::vector<int4> sym_work_items(int64_t tbs) {
+  std::vector<int4> items;
+  for (int64_t A = 0; A < tbs; ++A)
+    for (int64_t B0 = A; B0 < tbs; B0 += kSymChunk)
+      items.push_back(make_int4((int)A, (int)B0, (int)std::min<int64_t>(B0 + kSymChunk, tbs), 0));
+  std::stable_sort(items.begin(), items.end(), [](const int4& u, const int4& v) {
+    const int lu = u.z - u.y, lv = v.z - v.y;
+    return lu != lv ? lu > lv : u.y < v.y;
+  });
+  return items;
+}
+
 yy_status propagate_begin(yy_ctx ctx, const yy_model* model, const yy_scales* scales, int32_t prec, int64_t n,
                           const double* x, uint64_t node_version, const double* box_lo, const double* box_hi,
                           double dt, const double* logw_in, double* logw_out, int nsplit_override,
@@ -1261,19 +1273,14 @@ yy_status propagate_begin(yy_ctx ctx, const yy_model* model, const yy_scales* sc
     ex.rhv = ra.rhv;
     ex.jstar = ra.jstar;
     const int64_t tbs = ex.n_pad / 256;
-    if (prec == YY_PREC_BF16X3P && tbs > kSymMinBlocks) {
+    // (only where the screen spans 64 coordinates: over 32 the transposed coarse bound leaves most groups
+    // in doubt, and their rechecks cost more than the halved products save)
+    if (prec == YY_PREC_BF16X3P && tbs > kSymMinBlocks && a.rp > 32) {
       // the symmetric screen's work items: target block A against the target blocks [B0, B1) >= A as
       // sources, kSymChunk at a time, the longest first (then by source range, so that items started
       // together share sources); built once per block count
       if (ctx->sym_tbs != tbs) {
-        std::vector<int4> items;
-        for (int64_t A = 0; A < tbs; ++A)
-          for (int64_t B0 = A; B0 < tbs; B0 += kSymChunk)
-            items.push_back(make_int4((int)A, (int)B0, (int)std::min<int64_t>(B0 + kSymChunk, tbs), 0));
-        std::stable_sort(items.begin(), items.end(), [](const int4& u, const int4& v) {
-          const int lu = u.z - u.y, lv = v.z - v.y;
-          return lu != lv ? lu > lv : u.y < v.y;
-        });
+        const std::vector<int4> items = sym_work_items(tbs);
         if ((st = ctx->sym_items.ensure(items.size() * sizeof(int4))) != YY_OK) return st;
         YY_HIP(hipMemcpyAsync(ctx->sym_items.ptr, items.data(), items.size() * sizeof(int4), hipMemcpyHostToDevice,
                               ctx->stream));

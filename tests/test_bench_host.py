@@ -32,8 +32,10 @@ def test_screened_work():
     assert sym_pairs == 256.0 * 128.0 * 65792
     alg, ex = bench.screened_work(w, "bf16x3p", 0, 131072)
     assert alg == ex == 2.0 * sym_pairs * 64
-    alg, ex = bench.screened_work(w, "bf16x3p", 0, 131072, batch=True)
-    assert alg == ex == 2.0 * n2 * 64
+    # r <= 32 (a screen over 32 coordinates): every ordered pair
+    narrow = W.shrink(w, r=32)
+    alg, ex = bench.screened_work(narrow, "bf16x3p", 0, 131072)
+    assert alg == ex == 2.0 * n2 * 32
     alg, ex = bench.screened_work(w, "bf16x3s", 0, 131072)
     assert alg == ex == 2.0 * n2 * 1000
     # every tile flagged: the method's products on top, executed twice over by the split form
@@ -44,6 +46,7 @@ def test_screened_work():
     mid = W.shrink(w, n=8192)
     assert bench.screen_pairs(8192, "bf16x3p") == 8192.0 * 8192.0
     assert bench.screen_pairs(8193, "bf16x3p") == 256.0 * 128.0 * sum(65 - 2 * a for a in range(33))
+    assert bench.screen_pairs(8193, "bf16x3p", r=32) == 8193.0 * 8193.0
     assert bench.screened_work(mid, "bf16x3p", 0, 1)[0] == 2.0 * 8192 * 8192 * 64
     # a run narrower than the prefix screens all its coordinates
     small = W.shrink(w, r=20, n=1024)

@@ -73,6 +73,31 @@ def test_batch_matches_single_runs_exactly(prec, small_r):
         bt.close()
 
 
+def test_batch_symmetric_screen_matches_single_runs():
+    """Runs of more than 32 target blocks (n > 8192, ragged last blocks) take the symmetric screen in
+    the batched step too, beside runs with the one-sided screen: bit for bit the single-run filter's
+    results, with the flags of every screen within range."""
+    shapes = [(64, 12000), (33, 9000), (100, 2048), (20, 8500)]
+    ws = _workloads(K=6, shapes=shapes)
+    dys = [W.simulate(w)[1] for w in ws]
+    bt = Batch(ws, dys, prec="bf16x3p", max_split=16)
+    try:
+        for _ in range(ws[0].K):
+            bt.step()
+        for q, w in enumerate(ws):
+            mean, lz, ess = (host(t) for t in bt.results(q))
+            ref = _single(w, dys[q], "bf16x3p")
+            assert np.array_equal(mean, ref[0]), w.name
+            assert np.array_equal(lz, ref[1]), w.name
+            assert np.array_equal(ess, ref[2]), w.name
+            assert np.all(np.isfinite(mean))
+            flagged, tiles = bt.screen_count(q)
+            assert tiles == ((w.n + 255) // 256) * ((w.n + 127) // 128) and 0 <= flagged <= tiles
+            print(f"{w.name}: flagged {flagged} of {tiles} tiles in the last step")
+    finally:
+        bt.close()
+
+
 @pytest.mark.parametrize("prec", ["bf16x3g", "bf16x3s", "bf16x3p"])
 def test_graph_replay_equals_eager_steps(prec):
     ws = _workloads(K=10)

@@ -61,12 +61,14 @@ CASES = {
     # a partial screen over source ranges longer than a 64-tile window (16 splits of 69 tiles)
     "r32_n140000_stripes": dict(r=32, n=140000, q=1.0, dt=0.05, half=0.25, seed=45, stripes=2560),
     "r100_n3000_zero_weights": dict(r=100, n=3000, q=0.3, dt=0.02, half=0.3, seed=46, zero_every=7),
-    # more than 32 target blocks: BF16X3P's symmetric screen (each pair of target blocks once, the
-    # transposed orientation by a coarse bound per 64 rows), with a ragged last block and tile
+    # more than 32 target blocks and r > 32: BF16X3P's symmetric screen (each pair of target blocks once,
+    # the transposed orientation by a coarse bound per 64 rows), with a ragged last block and tile
     "r100_n12000_mid_sym": dict(r=100, n=12000, q=0.3, dt=0.02, half=0.3, seed=48),
     "r64_n20000_wide_sym": dict(r=64, n=20000, q=2.0, dt=0.05, half=0.25, seed=49),
     "r200_n8500_narrow_sym": dict(r=200, n=8500, q=0.09, dt=0.005, half=0.3, seed=50, zero_every=11),
-    "r32_n9000_stripes_sym": dict(r=32, n=9000, q=1.0, dt=0.05, half=0.25, seed=51, stripes=640),
+    "r48_n9000_stripes_sym": dict(r=48, n=9000, q=1.0, dt=0.05, half=0.25, seed=51, stripes=640),
+    # r <= 32 (a screen over 32 coordinates) keeps the one-sided screen at any size
+    "r32_n9000_stripes": dict(r=32, n=9000, q=1.0, dt=0.05, half=0.25, seed=52, stripes=640),
 }
 
 
