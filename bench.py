@@ -414,7 +414,9 @@ def main_batch(args):
         # each run's screen products plus the method's products on its flagged tiles
         counts = {q: bt.screen_count(q) for q in mfma_runs}
         alg = sum(screened_work(ws[q], args.prec, fl, tl)[0] for q, (fl, tl) in counts.items())
-        kernel = ("k_pair_prescreen_batch" if args.prec == "bf16x3p" else "k_pair_screen_batch") + \
+        kernel = ("k_tgt_bound_batch, k_pair_prescreen_batch (symmetric items for runs of more than 32 target "
+                  "blocks with r > 32, one-sided items for the others) and k_sym_recheck_batch"
+                  if args.prec == "bf16x3p" else "k_pair_screen_batch") + \
             ", then k_pair_mfma_batch (split form) on flagged tiles"
         log(f"[bench] screens flagged {sum(c[0] for c in counts.values())} of "
             f"{sum(c[1] for c in counts.values())} tiles")
