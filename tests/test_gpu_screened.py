@@ -67,6 +67,9 @@ CASES = {
     "r64_n20000_wide_sym": dict(r=64, n=20000, q=2.0, dt=0.05, half=0.25, seed=49),
     "r200_n8500_narrow_sym": dict(r=200, n=8500, q=0.09, dt=0.005, half=0.3, seed=50, zero_every=11),
     "r48_n9000_stripes_sym": dict(r=48, n=9000, q=1.0, dt=0.05, half=0.25, seed=51, stripes=640),
+    # wide kernels over 547 target blocks: every group of the transposed orientation is doubted, about
+    # 2.4 million units against a list of 2^20, so the groups past the list's end are flagged directly
+    "r64_n140000_wide_sym": dict(r=64, n=140000, q=2.0, dt=0.05, half=0.25, seed=53),
     # r <= 32 (a screen over 32 coordinates) keeps the one-sided screen at any size
     "r32_n9000_stripes": dict(r=32, n=9000, q=1.0, dt=0.05, half=0.25, seed=52, stripes=640),
 }
