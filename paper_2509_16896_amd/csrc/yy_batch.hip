@@ -294,9 +294,13 @@ static yy_status build(yy_batch b) {
     pair_mfma_fill_args(P.a, b->prec, P.ex, sets.data() + q * asz);
     bias_blocks[q] = nblk(P.ex.n_pad);
     const int64_t n = P.n, tbs = P.ex.n_pad / 256, jps = P.ex.j_per_split;
+    // (in the partial-distance screened form a run whose screen spans 32 coordinates (r_p = 32) has a
+    // weak screen that flags many of its tiles, so its split-pass items are costed as flagged and start
+    // first instead of forming the launch's tail)
+    const int64_t weak = b->prec == YY_PREC_BF16X3P && P.a.rp <= 32 ? 64 : 1;
     for (int sp = 0; sp < P.a.nsplit; ++sp) {
       const int64_t j0 = (int64_t)sp * jps, j1 = std::min<int64_t>(j0 + jps, n);
-      const int64_t cost = ((j1 - j0 + 127) / 128) * (int64_t)P.a.rp;
+      const int64_t cost = ((j1 - j0 + 127) / 128) * (int64_t)P.a.rp * weak;
       for (int64_t tb = 0; tb < tbs; ++tb) items.push_back({q, (int)tb, sp, cost});
     }
     if (b->prec == YY_PREC_BF16X3P) {

@@ -1910,8 +1910,10 @@ __global__ void __launch_bounds__(kNT, 1) k_pair_screen_batch(const MArgs* __res
 // out[S n_pad + s (n_pad / 128) + block] (the screen's coarse bound).  With
 // a.bpre the same over the first kPreK coordinates, to a.bpre in the same
 // layout.  n_pad is a multiple of the 256 threads of a block.
+// (the argument set by reference: in the batched kernel it lives in global memory, and a copy would be
+// private memory on every lane)
 __device__ __forceinline__ void k_src_bias_body(int64_t n, int64_t n_pad, int32_t S,
-                                                     MArgs a, float* __restrict__ out, int bx_, int gx_) {
+                                                     const MArgs& a, float* __restrict__ out, int bx_, int gx_) {
   __shared__ double sh[kBlock / 64];
   const int64_t j = (int64_t)bx_ * kBlock + threadIdx.x;
   if (a.any_flag && bx_ == 0 && threadIdx.x == 0) *a.any_flag = 0;

@@ -842,7 +842,9 @@ __global__ void __launch_bounds__(kBlock) k_divergence(int64_t n, int32_t r, int
 // (4) combination in FP64: merge the source splits, add the constants, signed
 // log-sum-exp over the scales and the identity term.
 
-__device__ __forceinline__ void k_combine_body(CombineArgs a, int bx_, int gx_) {
+// (the argument set by reference: in the batched kernel it lives in global memory, and a copy would be
+// private memory on every lane)
+__device__ __forceinline__ void k_combine_body(const CombineArgs& a, int bx_, int gx_) {
   const int64_t i = (int64_t)bx_ * kBlock + threadIdx.x;
   if (i >= a.n) return;
   // deferred planes: written in this call when the screen flagged a tile
