@@ -127,6 +127,8 @@ struct yy_batch_s {
   // blocks, one-sided items for the others; group bounds and rechecks of the symmetric runs)
   yy::DevBuf d_scr_items, d_bound_items, d_recheck_items;
   yy::BatchScreen scr;
+  // BF16X3P: per run a device int[2], [0] raised by the run's screen when it flags a tile in the step
+  yy::DevBuf d_words;
   bool k64 = true;                 // every matrix-core run's K padding is a multiple of 64
   yy::DevBuf v_sets, v_items[4];
   int v_nitems[4] = {0, 0, 0, 0};
@@ -258,6 +260,9 @@ static yy_status build(yy_batch b) {
   }
   // pairwise kernel argument sets and cost-ordered work items
   const size_t asz = pair_mfma_args_bytes();
+  if ((st = b->d_words.ensure((size_t)2 * nr * sizeof(int))) != YY_OK) return st;
+  YY_HIP(hipMemsetAsync(b->d_words.ptr, 0, (size_t)2 * nr * sizeof(int), b->ctx->stream));
+  int* words = b->d_words.as<int>();
   std::vector<unsigned char> sets(nr * asz);
   struct Item {
     int run, tb, split;
@@ -291,7 +296,9 @@ static yy_status build(yy_batch b) {
       vsets.push_back(v);
       continue;
     }
-    pair_mfma_fill_args(P.a, b->prec, P.ex, sets.data() + q * asz);
+    MfmaExtra ex = P.ex;
+    if (b->prec == YY_PREC_BF16X3P) ex.flag_word = words + 2 * q;
+    pair_mfma_fill_args(P.a, b->prec, ex, sets.data() + q * asz);
     bias_blocks[q] = nblk(P.ex.n_pad);
     const int64_t n = P.n, tbs = P.ex.n_pad / 256, jps = P.ex.j_per_split;
     // (in the partial-distance screened form a run whose screen spans 32 coordinates (r_p = 32) has a
@@ -395,6 +402,9 @@ static yy_status build(yy_batch b) {
       CombineArgs cb = R.plan.cb;
       cb.logw_in = lwi;
       cb.logw_out = lwo;
+      // the run's flag word: with no tile flagged in the step only the splits holding self pairs were
+      // written (a run in the vector-ALU form has none and combines every split)
+      if (b->prec == YY_PREC_BF16X3P && R.plan.mfma) cb.defer = b->d_words.as<int>() + 2 * q;
       A3.push_back({cb, nullptr});
       A4.push_back({n, r, d.model.m, d.model.obs, d.model.H, d.model.h_shift, R.x.as<double>(), d.dys, d.dt,
                     d.model.rho2, lwo, nullptr, &ctl[q].k});
@@ -805,6 +815,7 @@ extern "C" yy_status yy_batch_destroy(yy_batch b) {
   b->d_sets.release();
   b->d_items.release();
   b->d_scr_items.release();
+  b->d_words.release();
   b->d_bound_items.release();
   b->d_recheck_items.release();
   b->v_sets.release();

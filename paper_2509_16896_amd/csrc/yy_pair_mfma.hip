@@ -2004,7 +2004,7 @@ static MArgs make_args(const PairArgs& pa, int prec, const MfmaExtra& ex) {
   m.s_nsplit = pa.nsplit;
   m.s_jps = ((ex.j_per_split + kSJ - 1) / kSJ) * kSJ;
   m.pre_chunks = std::min(kPreK, (int)pa.rp) / kKC;
-  m.any_flag = ex.deferred ? ex.deferred->defer : nullptr;
+  m.any_flag = ex.deferred ? ex.deferred->defer : prec == YY_PREC_BF16X3P ? ex.flag_word : nullptr;
   m.rref = pa.pull ? nullptr : ex.rref;
   m.rhv = pa.pull ? nullptr : ex.rhv;
   m.jstar = pa.pull ? nullptr : ex.jstar;
