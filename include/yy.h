@@ -185,7 +185,13 @@ typedef enum {
  * self-pair exponent of its row is negligible.  Its screen moves and
  * multiplies 64 of the r coordinates; where the partial distance does not
  * separate the nodes it flags more tiles than the BF16X3S screen, and the
- * result is the same. */
+ * result is the same.  Where r > 32 and n > 8192 (more than 32 blocks of 256
+ * targets), single runs and runs of a batch alike, the BF16X3P screen forms
+ * the products of each pair of target blocks once and judges both
+ * orientations from them (the transposed one by a bound per 64 rows, with the
+ * doubtful groups rechecked row by row); the flags it raises are those a
+ * one-sided screen would raise or more, never fewer, so the result is the
+ * same. */
 
 /* ------------------------------------------------------------------------ */
 /* Sobol nodes (Appendix A; Sec. 2.2.1 state sampling; Sec. 6 reference set).
