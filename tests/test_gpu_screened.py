@@ -70,6 +70,8 @@ CASES = {
     # wide kernels over 547 target blocks: every group of the transposed orientation is doubted, about
     # 2.4 million units against a list of 2^20, so the groups past the list's end are flagged directly
     "r64_n140000_wide_sym": dict(r=64, n=140000, q=2.0, dt=0.05, half=0.25, seed=53),
+    # the smallest n with 33 target blocks: the last block holds one node and one source tile
+    "r40_n8193_edge_sym": dict(r=40, n=8193, q=0.5, dt=0.02, half=0.4, seed=54),
     # r <= 32 (a screen over 32 coordinates) keeps the one-sided screen at any size
     "r32_n9000_stripes": dict(r=32, n=9000, q=1.0, dt=0.05, half=0.25, seed=52, stripes=640),
 }
