@@ -246,6 +246,10 @@ constexpr int kSymChunk = 32;       // target blocks of sources per work item
 // so that items started together share sources).
 std::vector<int4> sym_work_items(int64_t tbs);
 // blocks of the node preparation kernel (one wave per 4 nodes, grid-stride)
+// Node preparation takes a wavefront per node up to kPrepWideMax padded nodes (a short
+// chain of steps per row where the node set is small), 16 lanes per node beyond.
+constexpr int64_t kPrepWideMax = 8192;
+__host__ __device__ inline bool prep_wide(int64_t n_pad) { return n_pad <= kPrepWideMax; }
 int prepare_blocks(int64_t n_pad);
 yy_status launch_src_bias(hipStream_t st, const PairArgs& a, const MfmaExtra& ex);
 yy_status launch_pair_mfma(hipStream_t st, const PairArgs& a, int prec, const MfmaExtra& ex);

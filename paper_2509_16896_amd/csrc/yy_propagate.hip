@@ -23,23 +23,27 @@
 namespace yy {
 
 // ---------------------------------------------------------------------------
-// (1) node preparation: one wavefront per 4 consecutive nodes, 16 lanes per
-// node.  Rows of even length take two 32-wide K ranges per step, a coordinate
-// pair per lane in each (whole 128-byte lines of the row-major planes, and of
-// the tiled planes: 4 nodes x 16 K values per chunk); other rows one 16-wide K
-// chunk per step, a coordinate per lane.
+// (1) node preparation: W lanes per node -- W = 16, one wavefront per 4
+// consecutive nodes, or where n_pad <= kPrepWideMax W = 64, a wavefront per
+// node, so that a small node set's rows are walked in fewer dependent steps.
+// Rows of even length take two 2W-wide K ranges per step, a coordinate pair per
+// lane in each (with W = 16 whole 128-byte lines of the row-major planes, and
+// of the tiled planes: 4 nodes x 16 K values per chunk); other rows one W-wide
+// K range per step, a coordinate per lane.  Single runs and the batched step
+// choose W by the same rule, so their node norms agree bit for bit.
 // Matrix-core planes are tiled [plane][rp/16][n_pad][16] so that 16 K values
 // of consecutive nodes are contiguous; rows n..n_pad-1 are zero.
-__device__ inline double sum16(double v) {
+template <int W>
+__device__ inline double sum_node(double v) {   // over the W lanes of a node
 #pragma unroll
-  for (int off = 8; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  for (int off = W / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
 }
 
 // MODE 0 writes everything; MODE 1 (BF16X3P, deferred planes) the node norms, the
 // boundary flags, the maxima and hi(xc) over the first kPreK coordinates; MODE 2
 // the planes and rows only (the rest of a MODE 1 preparation).
-template <int MODE>
+template <int MODE, int W>
 __device__ __forceinline__ void k_prepare_body(int64_t n, int64_t n_pad, int32_t r, int32_t rp,
                                                     int32_t drift, const double* __restrict__ A,
                                                     const double* __restrict__ x,
@@ -52,15 +56,18 @@ __device__ __forceinline__ void k_prepare_body(int64_t n, int64_t n_pad, int32_t
                                                     const int* __restrict__ bnd_given = nullptr) {
   // fgiven: drift values [n][r] when drift == kDriftGiven (a whitened node set); bnd_given: the
   // boundary flags, when the box test does not apply to these coordinates
-  const int lane = threadIdx.x & 63, sub = lane >> 4, kl = lane & 15;
+  static_assert(W == 16 || W == 64, "16 or 64 lanes per node");
+  constexpr int NPW = 64 / W;   // nodes per wave
+  const int lane = threadIdx.x & 63, sub = lane / W, kl = lane % W;
   const int64_t wave = ((int64_t)bx_ * blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gx_ * blockDim.x) >> 6;
   const size_t plane = (size_t)n_pad * rp;
-  static_assert(kPreK % 64 == 0, "the prefix is whole 64-coordinate steps of the paired path");
+  static_assert(kPreK % 32 == 0, "the prefix is whole coordinate pairs");
   double mx[4] = {0.0, 0.0, 0.0, 0.0};   // running maxima of the norms (all >= 0)
   // Rows of even length with 16-byte aligned x, lo and hi take the paired path: each lane handles
-  // the coordinate pairs k0 + 2 kl and k0 + 32 + 2 kl (16-byte loads, 8-byte stores), 64
-  // coordinates per step; the linear drift keeps one coordinate per lane.
+  // the coordinate pairs k0 + 2 kl and k0 + 2 W + 2 kl (16-byte loads, 8-byte stores), 4 W
+  // coordinates per step; the linear drift keeps one coordinate per lane.  A lane's prefix sums
+  // (the first kPreK coordinates) are its running sums after its last coordinate below kPreK.
   const bool pairs = (r & 1) == 0 && drift != YY_F_LINEAR &&
                      ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(lo) |
                        reinterpret_cast<uintptr_t>(hi) | reinterpret_cast<uintptr_t>(fgiven)) & 15) == 0;
@@ -76,7 +83,7 @@ __device__ __forceinline__ void k_prepare_body(int64_t n, int64_t n_pad, int32_t
     h = hv;
     l = f32_to_bf16((float)(d - (double)bf16_to_f32(hv)));
   };
-  for (int64_t i4 = wave * 4; i4 < n_pad; i4 += nwaves * 4) {
+  for (int64_t i4 = wave * NPW; i4 < n_pad; i4 += nwaves * NPW) {
     const int64_t i = i4 + sub;   // n_pad is a multiple of 4
     const bool real = i < n;
     const double* xi = x + (size_t)(real ? i : 0) * r;
@@ -84,10 +91,10 @@ __device__ __forceinline__ void k_prepare_body(int64_t n, int64_t n_pad, int32_t
     double pxx = 0.0, pff = 0.0, pxf = 0.0;   // over the first kPreK coordinates
     int b = 0;
     if (pairs) {
-      for (int32_t k0 = 0; k0 < rp; k0 += 64) {
+      for (int32_t k0 = 0; k0 < rp; k0 += 4 * W) {
 #pragma unroll 1
         for (int half = 0; half < 2; ++half) {
-          const int32_t k = k0 + 32 * half + 2 * kl;
+          const int32_t k = k0 + 2 * W * half + 2 * kl;
           double xc0 = 0.0, xc1 = 0.0, f0 = 0.0, f1 = 0.0;
           if (real && k < r) {   // r is even: both coordinates of the pair are inside
             const double2 xv = *reinterpret_cast<const double2*>(xi + k);
@@ -113,6 +120,11 @@ __device__ __forceinline__ void k_prepare_body(int64_t n, int64_t n_pad, int32_t
             sxx = fma(xc1, xc1, sxx);
             sff = fma(f1, f1, sff);
             sxf = fma(xc1, f1, sxf);
+          }
+          if (k < kPreK) {
+            pxx = sxx;
+            pff = sff;
+            pxf = sxf;
           }
           // rp is a multiple of 32: the pair is inside or outside as a whole
           if (k < (MODE == 1 ? min(rp, kPreK) : rp)) {
@@ -147,14 +159,9 @@ __device__ __forceinline__ void k_prepare_body(int64_t n, int64_t n_pad, int32_t
             }
           }
         }
-        if (k0 < kPreK) {
-          pxx = sxx;
-          pff = sff;
-          pxf = sxf;
-        }
       }
     } else {
-      for (int32_t k0 = 0; k0 < rp; k0 += 16) {
+      for (int32_t k0 = 0; k0 < rp; k0 += W) {
         const int32_t k = k0 + kl;
         float xcv = 0.f, fv = 0.f;
         double xcd = 0.0, fd = 0.0;
@@ -181,14 +188,15 @@ __device__ __forceinline__ void k_prepare_body(int64_t n, int64_t n_pad, int32_t
           xcv = (float)xcd;
           fv = (float)fd;
         }
-        if (k0 < kPreK) {
+        if (k < kPreK) {
           pxx = sxx;
           pff = sff;
           pxf = sxf;
         }
-        const size_t t = ((size_t)(k0 >> 4) * n_pad + i) * 16 + kl;
+        if (k >= rp) continue;   // (W = 64 runs past r_p where r_p = 32: no plane or row holds those)
+        const size_t t = ((size_t)(k >> 4) * n_pad + i) * 16 + (k & 15);
         if (MODE == 1) {
-          if (k0 < kPreK) bf[t] = f32_to_bf16(xcv);
+          if (k < kPreK) bf[t] = f32_to_bf16(xcv);
           continue;
         }
         if (real) {
@@ -213,14 +221,14 @@ __device__ __forceinline__ void k_prepare_body(int64_t n, int64_t n_pad, int32_t
       }
     }
     if (MODE == 2) continue;
-    sxx = sum16(sxx);
-    sff = sum16(sff);
-    sxf = sum16(sxf);
-    pxx = sum16(pxx);
-    pff = sum16(pff);
-    pxf = sum16(pxf);
+    sxx = sum_node<W>(sxx);
+    sff = sum_node<W>(sff);
+    sxf = sum_node<W>(sxf);
+    pxx = sum_node<W>(pxx);
+    pff = sum_node<W>(pff);
+    pxf = sum_node<W>(pxf);
 #pragma unroll
-    for (int off = 8; off > 0; off >>= 1) b |= __shfl_xor(b, off, 64);
+    for (int off = W / 2; off > 0; off >>= 1) b |= __shfl_xor(b, off, 64);
     if (bnd_given && real) b = bnd_given[i];
     if (kl == 0 && real) {
       node[i] = sxx;
@@ -249,7 +257,9 @@ __device__ __forceinline__ void k_prepare_body(int64_t n, int64_t n_pad, int32_t
   }
 }
 
-int prepare_blocks(int64_t n_pad) { return (int)std::min<int64_t>((n_pad + 15) / 16, 16384); }
+int prepare_blocks(int64_t n_pad) {
+  return prep_wide(n_pad) ? (int)(n_pad / 4) : (int)std::min<int64_t>((n_pad + 15) / 16, 16384);
+}
 
 // MODE 1 marks the deferred planes as not yet written (defer[1] = 0).
 template <int MODE>
@@ -264,8 +274,12 @@ __global__ void __launch_bounds__(kBlock, 4) k_prepare(int64_t n, int64_t n_pad,
                                                        int* __restrict__ defer, const double* __restrict__ fgiven,
                                                        const int* __restrict__ bnd_given) {
   if (MODE == 1 && blockIdx.x == 0 && threadIdx.x == 0) defer[1] = 0;
-  k_prepare_body<MODE>(n, n_pad, r, rp, drift, A, x, lo, hi, xc32, f32, bf, f32t, node, bnd, blockIdx.x,
-                       gridDim.x, fgiven, bnd_given);
+  if (prep_wide(n_pad))
+    k_prepare_body<MODE, 64>(n, n_pad, r, rp, drift, A, x, lo, hi, xc32, f32, bf, f32t, node, bnd, blockIdx.x,
+                             gridDim.x, fgiven, bnd_given);
+  else
+    k_prepare_body<MODE, 16>(n, n_pad, r, rp, drift, A, x, lo, hi, xc32, f32, bf, f32t, node, bnd, blockIdx.x,
+                             gridDim.x, fgiven, bnd_given);
 }
 
 // The rest of a MODE 1 preparation, after the screen: every block returns at
@@ -273,8 +287,12 @@ __global__ void __launch_bounds__(kBlock, 4) k_prepare(int64_t n, int64_t n_pad,
 // yet complete (k_combine then marks them complete).
 __global__ void __launch_bounds__(kBlock, 4) k_prepare_rest(DeferredPrep d) {
   if (d.defer[0] == 0 || d.defer[1] != 0) return;
-  k_prepare_body<2>(d.n, d.n_pad, d.r, d.rp, d.drift, d.A, d.x, d.lo, d.hi, d.xc32, d.f32, d.bf, nullptr,
-                    nullptr, nullptr, blockIdx.x, gridDim.x);
+  if (prep_wide(d.n_pad))
+    k_prepare_body<2, 64>(d.n, d.n_pad, d.r, d.rp, d.drift, d.A, d.x, d.lo, d.hi, d.xc32, d.f32, d.bf, nullptr,
+                          nullptr, nullptr, blockIdx.x, gridDim.x);
+  else
+    k_prepare_body<2, 16>(d.n, d.n_pad, d.r, d.rp, d.drift, d.A, d.x, d.lo, d.hi, d.xc32, d.f32, d.bf, nullptr,
+                          nullptr, nullptr, blockIdx.x, gridDim.x);
 }
 
 yy_status launch_prepare_rest(hipStream_t st, const DeferredPrep& d) {
@@ -288,8 +306,12 @@ __global__ void __launch_bounds__(kBlock, 4) k_prepare_batch(const prepare_args*
   const int q = batch_find(pre, nr, blockIdx.x);
   const prepare_args& a = A[q];
   if (a.pred && *a.pred == 0) return;
-  k_prepare_body<0>(a.n, a.n_pad, a.r, a.rp, a.drift, a.A, a.x, a.lo, a.hi, a.xc32, a.f32, a.bf, a.f32t, a.node, a.bnd,
-                 blockIdx.x - pre[q], pre[q + 1] - pre[q]);
+  if (prep_wide(a.n_pad))
+    k_prepare_body<0, 64>(a.n, a.n_pad, a.r, a.rp, a.drift, a.A, a.x, a.lo, a.hi, a.xc32, a.f32, a.bf, a.f32t, a.node,
+                          a.bnd, blockIdx.x - pre[q], pre[q + 1] - pre[q]);
+  else
+    k_prepare_body<0, 16>(a.n, a.n_pad, a.r, a.rp, a.drift, a.A, a.x, a.lo, a.hi, a.xc32, a.f32, a.bf, a.f32t, a.node,
+                          a.bnd, blockIdx.x - pre[q], pre[q + 1] - pre[q]);
 }
 
 
