@@ -365,12 +365,16 @@ def main_batch(args):
                 bt.set_run_form(q, "fp32")
     for _ in range(4):     # a state past the first restarts: the screens' cost depends on the weights
         bt.step()
-    best = bt.tune(reps=2, forms=args.batch_forms == "tuned")
+    # (in BF16X3P each run's screen is also timed against the split form on every tile)
+    best = bt.tune(reps=2, forms=args.batch_forms == "tuned",
+                   dense=args.prec == "bf16x3p" and args.batch_forms != "rule")
     tune_s = time.perf_counter() - t0
     forms = [bt.run_form(q) for q in range(len(ws))]
     mfma_runs = [q for q, fm in enumerate(forms) if fm != "fp32"]
+    dense_runs = [q for q in mfma_runs if forms[q] != args.prec]
     log(f"[bench] tuned: {len(ws) - len(mfma_runs)} runs on the vector ALUs (plain FP32), {len(mfma_runs)} in "
-        f"{args.prec}; max source splits per run {best} ({tune_s:.2f} s)")
+        f"{args.prec} ({len(dense_runs)} of them with the split form on every tile, no screen: "
+        f"{sorted((ws[q].r, ws[q].n) for q in dense_runs)}); max source splits per run {best} ({tune_s:.2f} s)")
 
     def run_eager():
         bt.reset()
@@ -412,8 +416,10 @@ def main_batch(args):
     alg = sum(2.0 * ws[q].n * ws[q].n * ws[q].r * 2 for q in mfma_runs)
     if args.prec in ("bf16x3s", "bf16x3p"):
         # each run's screen products plus the method's products on its flagged tiles
+        # (a run with the split form on every tile forms no screen products)
         counts = {q: bt.screen_count(q) for q in mfma_runs}
-        alg = sum(screened_work(ws[q], args.prec, fl, tl)[0] for q, (fl, tl) in counts.items())
+        alg = sum(alg_flops(ws[q]) if q in dense_runs else screened_work(ws[q], args.prec, fl, tl)[0]
+                  for q, (fl, tl) in counts.items())
         kernel = ("k_tgt_bound_batch, k_pair_prescreen_batch (symmetric items for runs of more than 32 target "
                   "blocks with r > 32, one-sided items for the others) and k_sym_recheck_batch"
                   if args.prec == "bf16x3p" else "k_pair_screen_batch") + \
@@ -444,11 +450,13 @@ def main_batch(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
         "config": {"workload": "batch64_cubic_r10-200_n2048-32768", "runs": len(ws), "K": K,
                    "precision": args.prec, "max_split": best, "forms": args.batch_forms,
-                   "runs_on_vector_alus": len(ws) - len(mfma_runs)},
+                   "runs_on_vector_alus": len(ws) - len(mfma_runs),
+                   "runs_split_on_every_tile": len(dense_runs)},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_TFLOPS[args.prec],
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS[args.prec], 4), "traffic": None,
                      "kernel": kernel, "kernel_ms": round(kms, 3),
-                     "work_basis": ("each matrix-core run's screen products plus 2 n^2 r P on its flagged tiles"
+                     "work_basis": ("each matrix-core run's screen products plus 2 n^2 r P on its flagged tiles "
+                                    "(on every tile for a run with no screen)"
                                     if args.prec in ("bf16x3s", "bf16x3p") else "2 n^2 r P of every matrix-core run")
                      + "; the timed launches include the vector-ALU runs",
                      "method_dense_at_peak_ms": round(dense / (PEAK_TFLOPS[args.prec] * 1e12) * 1e3, 4)},

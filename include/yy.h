@@ -416,7 +416,14 @@ typedef struct yy_batch_s* yy_batch;
  * BF16X3S, BF16X3P or BF16X1).  Each run takes its pairwise sum in that form
  * (the default) or in the plain FP32 form on the vector ALUs (YY_PREC_FP32), as
  * yy_batch_tune (with forms) or yy_batch_set_run_form choose; either way a run
- * computes exactly what the single-run calls compute in its form.
+ * computes exactly what the single-run calls compute in its form.  In a
+ * BF16X3P batch a run may also take YY_PREC_BF16X3G: BF16X3P's plan with no
+ * screen and every tile flagged, i.e. the split form on every tile summed in
+ * BF16X3P's order (row floor and the pair with the heaviest source first).  It
+ * differs from the single-run BF16X3P call only by the tiles that call's screen
+ * drops, whose pairs lie more than 2^-80 below their row's floor, so the
+ * results agree to rounding (where the screen spans only 32 coordinates it
+ * flags most tiles, and skipping it is faster).
  * max_split: upper bound of the source splits per matrix-core run (0: 16);
  * yy_batch_tune can choose it. */
 yy_status yy_batch_create(yy_ctx ctx, int32_t nruns, const yy_batch_run* runs, const yy_scales* scales,
@@ -434,16 +441,19 @@ yy_status yy_batch_run_graph(yy_batch b, int32_t k_end);
 /* Tunes the pairwise launches on the current state (reps launches per
  * candidate after a warm-up; results discarded): with forms != 0 first each
  * run's form, by timing its single-run pairwise call in the batch's
- * matrix-core form and in YY_PREC_FP32 (runs of equal r and n share one
- * decision; the screened forms' cost depends on the weights, so tune on a
- * state a few steps in); then max_split = 1, 2, 4, ..., 64 on the batched
- * launch.  Keeps the fastest; best_out (host scalar or NULL) receives
- * max_split.  Drops a captured graph. */
+ * matrix-core form and in the candidates that the bits of forms name: bit 0
+ * YY_PREC_FP32, bit 1 (BF16X3P batches) YY_PREC_BF16X3G, timed as the
+ * single-run BF16X3G call (runs of equal r and n share one decision; the
+ * screened forms' cost depends on the weights, so tune on a state a few steps
+ * in); then max_split = 1, 2, 4, ..., 64 on the batched launch.  Keeps the
+ * fastest; best_out (host scalar or NULL) receives max_split.  Drops a
+ * captured graph. */
 yy_status yy_batch_tune(yy_batch b, int32_t reps, int32_t forms, int32_t* best_out);
-/* The pairwise form of run `run`: the batch's matrix-core form or
- * YY_PREC_FP32 (host scalar). */
+/* The pairwise form of run `run`: the batch's matrix-core form, YY_PREC_FP32
+ * or (BF16X3P batches) YY_PREC_BF16X3G (host scalar). */
 yy_status yy_batch_run_form(yy_batch b, int32_t run, int32_t* prec);
-/* Sets run `run`'s pairwise form (the batch's form or YY_PREC_FP32) and
+/* Sets run `run`'s pairwise form (the batch's form, YY_PREC_FP32, or in a
+ * BF16X3P batch YY_PREC_BF16X3G) and
  * rebuilds the launches; the run continues from its current state.  Drops a
  * captured graph; YY_ERR_UNSUPPORTED while the stream is capturing. */
 yy_status yy_batch_set_run_form(yy_batch b, int32_t run, int32_t prec);

@@ -56,16 +56,19 @@ class Batch:
     def run_graph(self, k_end: int):
         yy.yy_batch_run_graph(self.b, k_end)
 
-    def tune(self, reps: int = 3, forms: bool = False) -> int:
-        """Each run's pairwise form (forms=True), then the source splits; returns the split bound."""
-        return yy.yy_batch_tune(self.b, reps, forms)
+    def tune(self, reps: int = 3, forms: bool = False, dense: bool = False) -> int:
+        """Each run's pairwise form -- against the vector-ALU form (forms=True) and, in a BF16X3P
+        batch, against the split form on every tile (dense=True) -- then the source splits; returns
+        the split bound."""
+        return yy.yy_batch_tune(self.b, reps, (1 if forms else 0) | (2 if dense else 0))
 
     @property
     def k(self) -> int:
         return yy.yy_batch_step_count(self.b)
 
     def run_form(self, run: int) -> str:
-        """Run `run`'s pairwise form: the batch's matrix-core form, or "fp32" on the vector ALUs."""
+        """Run `run`'s pairwise form: the batch's matrix-core form, "fp32" on the vector ALUs, or in a
+        BF16X3P batch "bf16x3g" (no screen, every tile)."""
         return yy.yy_batch_run_form(self.b, run)
 
     def set_run_form(self, run: int, prec: str):

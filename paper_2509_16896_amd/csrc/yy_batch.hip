@@ -117,8 +117,9 @@ struct yy_batch_s {
   unsigned char* pinned = nullptr; // staging for uploads
   size_t pinned_bytes = 0;
   bool built = false;
-  // each run's form of the pairwise sum: the batch's matrix-core form (the default), or the plain FP32
-  // form on the vector ALUs (yy_batch_tune with forms, or yy_batch_set_run_form)
+  // each run's form of the pairwise sum: the batch's matrix-core form (the default), the plain FP32
+  // form on the vector ALUs, or in a BF16X3P batch BF16X3G (BF16X3P with no screen and every tile
+  // flagged) -- by yy_batch_tune with forms, or yy_batch_set_run_form
   std::vector<int32_t> form;
   // the pairwise launches: matrix-core runs, then vector-ALU runs by staging width (2, 4, 8, 16)
   yy::DevBuf d_sets, d_items;
@@ -237,6 +238,14 @@ static yy_status reset_ctl(yy_batch b) {
   return upload(b, b->ctl, c.data(), c.size() * sizeof(BCtl));
 }
 
+// A run of a BF16X3P batch set to BF16X3G takes BF16X3P's plan (row floor,
+// pair with the heaviest source, flagged split pass) with no screen and every
+// tile flagged: the split form on every tile, summed in BF16X3P's order.
+static bool run_dense(yy_batch b, int q) {
+  return b->prec == YY_PREC_BF16X3P && b->form[q] == YY_PREC_BF16X3G;
+}
+static int32_t run_plan_form(yy_batch b, int q) { return run_dense(b, q) ? b->prec : b->form[q]; }
+
 // All launch descriptions: per-run plans (same split rule and scratch as the
 // single-run calls), kernel argument sets for both step parities, work items.
 static yy_status build(yy_batch b) {
@@ -248,7 +257,7 @@ static yy_status build(yy_batch b) {
     // preparation after every restart, never by this call
     const int64_t jtl = (R.d.n + 127) / 128;
     const int split = (int)std::max<int64_t>(1, std::min<int64_t>(b->max_split, jtl));
-    const int32_t form = b->form[&R - b->runs.data()];
+    const int32_t form = run_plan_form(b, (int)(&R - b->runs.data()));
     if ((st = propagate_begin(R.rc, &R.d.model, &sc, form, R.d.n, R.x.as<double>(), 1, R.lo.as<double>(),
                               R.hi.as<double>(), R.d.dt, R.lw[0].as<double>(), R.lw[1].as<double>(), split,
                               R.plan)) != YY_OK)
@@ -297,20 +306,24 @@ static yy_status build(yy_batch b) {
       continue;
     }
     MfmaExtra ex = P.ex;
-    if (b->prec == YY_PREC_BF16X3P) ex.flag_word = words + 2 * q;
+    const bool dense = run_dense(b, q);
+    if (b->prec == YY_PREC_BF16X3P && !dense) ex.flag_word = words + 2 * q;
     pair_mfma_fill_args(P.a, b->prec, ex, sets.data() + q * asz);
     bias_blocks[q] = nblk(P.ex.n_pad);
     const int64_t n = P.n, tbs = P.ex.n_pad / 256, jps = P.ex.j_per_split;
     // (in the partial-distance screened form a run whose screen spans 32 coordinates (r_p = 32) has a
     // weak screen that flags many of its tiles, so its split-pass items are costed as flagged and start
     // first instead of forming the launch's tail)
-    const int64_t weak = b->prec == YY_PREC_BF16X3P && P.a.rp <= 32 ? 64 : 1;
+    const int64_t weak = b->prec == YY_PREC_BF16X3P && (P.a.rp <= 32 || dense) ? 64 : 1;
     for (int sp = 0; sp < P.a.nsplit; ++sp) {
       const int64_t j0 = (int64_t)sp * jps, j1 = std::min<int64_t>(j0 + jps, n);
       const int64_t cost = ((j1 - j0 + 127) / 128) * (int64_t)P.a.rp * weak;
       for (int64_t tb = 0; tb < tbs; ++tb) items.push_back({q, (int)tb, sp, cost});
     }
-    if (b->prec == YY_PREC_BF16X3P) {
+    if (dense) {
+      // the split form on every tile: no screen; every flag set once here (no kernel writes them)
+      YY_HIP(hipMemsetAsync(P.ex.flags, 1, (size_t)tbs * ((n + 127) / 128) * 8, b->ctx->stream));
+    } else if (b->prec == YY_PREC_BF16X3P) {
       // the screen's items, costed in 128-source tiles (a symmetric tile carries both orientations'
       // verdicts: about 1.4 one-sided tiles)
       const int64_t jtl = (n + 127) / 128;
@@ -404,7 +417,7 @@ static yy_status build(yy_batch b) {
       cb.logw_out = lwo;
       // the run's flag word: with no tile flagged in the step only the splits holding self pairs were
       // written (a run in the vector-ALU form has none and combines every split)
-      if (b->prec == YY_PREC_BF16X3P && R.plan.mfma) cb.defer = b->d_words.as<int>() + 2 * q;
+      if (b->prec == YY_PREC_BF16X3P && R.plan.mfma && !run_dense(b, q)) cb.defer = b->d_words.as<int>() + 2 * q;
       A3.push_back({cb, nullptr});
       A4.push_back({n, r, d.model.m, d.model.obs, d.model.H, d.model.h_shift, R.x.as<double>(), d.dys, d.dt,
                     d.model.rho2, lwo, nullptr, &ctl[q].k});
@@ -900,25 +913,30 @@ extern "C" yy_status yy_batch_tune(yy_batch b, int32_t reps, int32_t forms, int3
   YY_HIP(hipEventCreate(&e1));
   yy_status s = YY_OK;
   // (1) each run's form: its pairwise call (on its own context, as the batch plans it) timed in the
-  // batch's matrix-core form and in the plain FP32 form on the vector ALUs; the faster is kept.
-  // Runs of the same (r, n) share the first one's choice.
-  if (forms) {
+  // batch's matrix-core form and in the candidates `forms` names -- the plain FP32 form on the vector
+  // ALUs (bit 0), the split form on every tile in a BF16X3P batch (bit 1, BF16X3G's single-run call
+  // standing for it) -- the fastest is kept.  Runs of the same (r, n) share the first one's choice.
+  if (forms & 3) {
     const yy_scales sc = batch_scales(b);
     std::vector<std::pair<std::pair<int32_t, int64_t>, int32_t>> chosen;
     for (size_t q = 0; q < b->runs.size() && s == YY_OK; ++q) {
       BRun& R = b->runs[q];
+      if (!(forms & 1) && b->form[q] == YY_PREC_FP32) continue;   // keeps the vector-ALU form
       const std::pair<int32_t, int64_t> key(R.d.model.r, R.d.n);
       int32_t pick = -1;
       for (const auto& c : chosen)
         if (c.first == key) pick = c.second;
       if (pick < 0) {
-        float ms_f[2] = {0.f, 0.f};
-        const int32_t forms[2] = {b->prec, YY_PREC_FP32};
-        for (int f = 0; f < 2 && s == YY_OK; ++f) {
+        float ms_f[3] = {0.f, 0.f, 0.f};
+        int32_t cand[3] = {b->prec, 0, 0};
+        int nc = 1;
+        if (forms & 1) cand[nc++] = YY_PREC_FP32;
+        if ((forms & 2) && b->prec == YY_PREC_BF16X3P) cand[nc++] = YY_PREC_BF16X3G;
+        for (int f = 0; f < nc && s == YY_OK; ++f) {
           const int64_t jtl = (R.d.n + 127) / 128;
           const int split = (int)std::max<int64_t>(1, std::min<int64_t>(b->max_split, jtl));
           PropPlan plan;
-          s = propagate_begin(R.rc, &R.d.model, &sc, forms[f], R.d.n, R.x.as<double>(), 1, R.lo.as<double>(),
+          s = propagate_begin(R.rc, &R.d.model, &sc, cand[f], R.d.n, R.x.as<double>(), 1, R.lo.as<double>(),
                               R.hi.as<double>(), R.d.dt, R.lw[0].as<double>(), R.lw[1].as<double>(), split, plan);
           if (s == YY_OK) s = propagate_pair(R.rc, plan);   // warm-up
           if (s == YY_OK && hipEventRecord(e0, st) != hipSuccess) s = fail(YY_ERR_HIP, "yy_batch_tune: event");
@@ -928,7 +946,10 @@ extern "C" yy_status yy_batch_tune(yy_batch b, int32_t reps, int32_t forms, int3
           if (s == YY_OK) (void)hipEventElapsedTime(&ms_f[f], e0, e1);
         }
         if (s != YY_OK) break;
-        pick = ms_f[1] < ms_f[0] ? YY_PREC_FP32 : b->prec;
+        int best_f = 0;
+        for (int f = 1; f < nc; ++f)
+          if (ms_f[f] < ms_f[best_f]) best_f = f;
+        pick = cand[best_f];
         chosen.push_back({key, pick});
       }
       b->form[q] = pick;
@@ -987,8 +1008,10 @@ extern "C" yy_status yy_batch_run_form(yy_batch b, int32_t run, int32_t* prec) {
 
 extern "C" yy_status yy_batch_set_run_form(yy_batch b, int32_t run, int32_t prec) {
   if (!b || run < 0 || run >= (int32_t)b->runs.size()) return fail(YY_ERR_ARG, "yy_batch_set_run_form: bad run");
-  if (prec != b->prec && prec != YY_PREC_FP32)
-    return fail(YY_ERR_ARG, "yy_batch_set_run_form: the batch's matrix-core form or YY_PREC_FP32");
+  if (prec != b->prec && prec != YY_PREC_FP32 && !(b->prec == YY_PREC_BF16X3P && prec == YY_PREC_BF16X3G))
+    return fail(YY_ERR_ARG,
+                "yy_batch_set_run_form: the batch's matrix-core form, YY_PREC_FP32, or in a BF16X3P batch "
+                "YY_PREC_BF16X3G");
   YY_HIP(hipSetDevice(b->ctx->device));
   if (capturing(b->ctx->stream)) return fail(YY_ERR_UNSUPPORTED, "yy_batch_set_run_form: stream is capturing");
   if (b->form[run] == prec) return YY_OK;

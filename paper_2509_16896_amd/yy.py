@@ -455,9 +455,10 @@ def yy_batch_run_graph(b, k_end):
     _check(_lib.yy_batch_run_graph(b, int(k_end)), "yy_batch_run_graph")
 
 
-def yy_batch_tune(b, reps=3, forms=False) -> int:
+def yy_batch_tune(b, reps=3, forms=0) -> int:
+    """forms: bit 0 the vector-ALU form, bit 1 (BF16X3P batches) the split form on every tile."""
     best = _i32(0)
-    _check(_lib.yy_batch_tune(b, int(reps), 1 if forms else 0, ctypes.byref(best)), "yy_batch_tune")
+    _check(_lib.yy_batch_tune(b, int(reps), int(forms), ctypes.byref(best)), "yy_batch_tune")
     return int(best.value)
 
 
@@ -475,7 +476,8 @@ def yy_batch_screen_count(b, run):
 
 
 def yy_batch_run_form(b, run) -> str:
-    """Run `run`'s pairwise form: the batch's matrix-core form or "fp32" (vector ALUs)."""
+    """Run `run`'s pairwise form: the batch's matrix-core form, "fp32" (vector ALUs) or, in a
+    BF16X3P batch, "bf16x3g" (the split form on every tile, no screen)."""
     p = _i32(0)
     _check(_lib.yy_batch_run_form(b, int(run), ctypes.byref(p)), "yy_batch_run_form")
     return {v: k for k, v in PREC_BY_NAME.items() if k != "auto"}[int(p.value)]

@@ -179,9 +179,16 @@ def test_batch_run_form_arguments():
     ws = _workloads(K=2)
     dys = [W.simulate(w)[1] for w in ws]
     b = Batch(ws, dys, prec="bf16x3p")
+    s = Batch(ws[:2], dys[:2], prec="bf16x3s")
     try:
         with pytest.raises(yy.YYError):
-            b.set_run_form(1, "bf16x3g")        # neither the batch's form nor fp32
+            b.set_run_form(1, "bf16x1")         # neither the batch's form, fp32 nor (BF16X3P) bf16x3g
+        with pytest.raises(yy.YYError):
+            s.set_run_form(1, "bf16x3g")        # the split form on every tile only in a BF16X3P batch
+        b.set_run_form(1, "bf16x3g")
+        assert b.run_form(1) == "bf16x3g"
+        b.set_run_form(1, "bf16x3p")
+        assert b.run_form(1) == "bf16x3p"
         with pytest.raises(yy.YYError):
             b.run_form(len(ws))
         b.set_run_form(2, "fp32")               # r = 64 on the vector ALUs
@@ -190,6 +197,83 @@ def test_batch_run_form_arguments():
         b.step()
         ref = _single(ws[2], dys[2], "fp32")
         assert np.array_equal(host(b.results(2)[0]), ref[0])
+    finally:
+        b.close()
+        s.close()
+
+
+# runs whose screen spans 32 coordinates (r <= 32) beside screened runs, one of them with the
+# symmetric screen (n > 8192, r > 32) and ragged last target blocks
+DENSE_SHAPES = [(10, 2048), (20, 8500), (24, 4096), (64, 4096), (33, 9000), (32, 1000)]
+
+
+def test_batch_split_on_every_tile_runs():
+    """Runs of a BF16X3P batch set to BF16X3G skip the screen and take the split form on every tile in
+    BF16X3P's order: each flags every tile, and its results equal the single-run BF16X3P filter's up to
+    the pairs that filter's screen drops (more than 2^-80 below their row's floor, so nothing at FP64
+    rounding of the means here); the screened runs beside them stay bit for bit the single-run
+    filter's.  The graph-replayed batch repeats the eager one exactly (the flags are set once, at the
+    batch's build)."""
+    ws = _workloads(K=6, shapes=DENSE_SHAPES)
+    dys = [W.simulate(w)[1] for w in ws]
+    dense = [q for q, w in enumerate(ws) if w.r <= 32]
+    a = Batch(ws, dys, prec="bf16x3p", max_split=16)
+    g = Batch(ws, dys, prec="bf16x3p", max_split=16)
+    try:
+        for bt in (a, g):
+            for q in dense:
+                bt.set_run_form(q, "bf16x3g")
+        for _ in range(ws[0].K):
+            a.step()
+        g.step()
+        g.step()
+        g.run_graph(ws[0].K)
+        for q, w in enumerate(ws):
+            mean, lz, ess = (host(t) for t in a.results(q))
+            for x, y in zip((mean, lz, ess), (host(t) for t in g.results(q))):
+                assert np.array_equal(x, y), w.name
+            ref = _single(w, dys[q], "bf16x3p")
+            flagged, tiles = a.screen_count(q)
+            assert tiles == ((w.n + 255) // 256) * ((w.n + 127) // 128)
+            assert np.all(np.isfinite(mean))
+            if q in dense:
+                assert a.run_form(q) == "bf16x3g" and flagged == tiles, w.name
+                dm = float(np.max(np.abs(mean - ref[0])))
+                print(f"{w.name}: every tile; |mean - single-run BF16X3P| <= {dm:.3g}")
+                assert np.allclose(mean, ref[0], rtol=0, atol=1e-12), w.name
+                assert np.allclose(lz, ref[1], rtol=1e-12, atol=1e-12), w.name
+                assert np.allclose(ess, ref[2], rtol=1e-12, atol=0), w.name
+            else:
+                assert np.array_equal(mean, ref[0]), w.name
+                assert np.array_equal(lz, ref[1]), w.name
+                assert np.array_equal(ess, ref[2]), w.name
+    finally:
+        a.close()
+        g.close()
+
+
+def test_batch_tuner_screen_or_every_tile():
+    """The tuner's second search (BF16X3P batches): each run keeps its screen or takes the split form
+    on every tile, whichever its single-run call runs faster; every run then matches the single-run
+    BF16X3P filter (another split count changes only the summation order of the partial sums)."""
+    ws = _workloads(K=6, shapes=DENSE_SHAPES)
+    dys = [W.simulate(w)[1] for w in ws]
+    b = Batch(ws, dys, prec="bf16x3p")
+    try:
+        for _ in range(2):
+            b.step()
+        best = b.tune(reps=2, dense=True)
+        assert best in (1, 2, 4, 8, 16, 32, 64)
+        forms = [b.run_form(q) for q in range(len(ws))]
+        print("tuned forms:", list(zip([w.r for w in ws], [w.n for w in ws], forms)))
+        assert all(f in ("bf16x3p", "bf16x3g") for f in forms)
+        b.reset()
+        for _ in range(6):
+            b.step()
+        for q, w in enumerate(ws):
+            mean = host(b.results(q)[0])
+            ref = _single(w, dys[q], "bf16x3p")[0]
+            assert np.allclose(mean, ref, rtol=1e-9, atol=1e-9), w.name
     finally:
         b.close()
 
