@@ -276,6 +276,24 @@ yy_status launch_pair_mfma_batch(hipStream_t st, int S, int prec, const void* se
 
 // (4) combination in FP64: merge the source splits, add the constants, signed
 // log-sum-exp over the scales and the identity term.
+// The state (maximum, sum; base 2) with which target i's partial sum at scale s
+// starts in the source split that holds its self pair: the row floor rref as the
+// maximum (the self-pair exponent where there is none), and in the sum the self
+// pair's term and, where the row counts it apart, the heavy pair's exact term rhv.
+// li: the target's source weight (lw2); fnorm: |f(x_i)|^2.  The other splits
+// start at (maximum, 0).  A split whose source range holds no flagged tile keeps
+// this state; where a call flags no tile at all, the combination forms it here
+// rather than reading it from the split form's output.
+__device__ __forceinline__ float2 owner_start(float li, double fnorm, double kapd, double taud, const float* rref,
+                                              const float* rhv, int64_t n, int64_t i, int s) {
+  const float self = li != -INFINITY ? li - (float)(kapd * taud * taud * fnorm) : -INFINITY;
+  const float M0 = rref ? rref[(size_t)s * n + i] : self;
+  const float h = rhv ? rhv[(size_t)s * n + i] : -INFINITY;
+  float sum = self != -INFINITY ? (self == M0 ? 1.f : __builtin_amdgcn_exp2f(self - M0)) : 0.f;
+  if (h != -INFINITY) sum += h == M0 ? 1.f : __builtin_amdgcn_exp2f(h - M0);
+  return make_float2(M0, sum);
+}
+
 struct CombineArgs {
   int64_t n;
   int32_t S, nsplit;
@@ -294,6 +312,12 @@ struct CombineArgs {
   int64_t j_per_split;             // sources per split of the matrix-core kernel
   const double* div;               // pull form: div f(x_i) [n]; its factor exp(-tau_s div) per scale, else null
   double taud[YY_MAX_SCALES];      // tau_s
+  // the self-pair split's starting state (owner_start) where no tile of the call is flagged (defer[0] = 0)
+  double kapd[YY_MAX_SCALES];      // the pairwise kernel's kappa_s
+  const float* lw2;                // source weights [n]
+  const double* node;              // node norms ([n, 2n) holds |f|^2)
+  const float* rref;               // row floors [S][n], or null
+  const float* rhv;                // heavy-pair terms [S][n], or null
 };
 
 // One yy_propagate call split into its phases: begin = node preparation,

@@ -706,12 +706,9 @@ __device__ __forceinline__ void pair_block(const MArgs& a, int tb, int split, un
   const int ntiles_all = __builtin_amdgcn_readfirstlane((int)((jb1 - jb0 + kMJ - 1) / kMJ));
   const int nchunks = __builtin_amdgcn_readfirstlane(a.rp / kKC);
   const int64_t jt0 = jb0 / kMJ;   // global index of the split's first source tile
-  if (FLAGGED && a.any_flag && *a.any_flag == 0) {
-    // no tile flagged in this call: only the split that holds a target's self pair writes its
-    // state (below), so a block whose source range holds none of its targets has nothing to do
-    const int64_t ilast = (i0 + kMI < a.n ? i0 + kMI : a.n) - 1;
-    if (i0 >= a.n || split < i0 / a.j_per_split || split > ilast / a.j_per_split) return;
-  }
+  // no tile flagged in this call: every split keeps its starting state, and the combination forms
+  // the one of the split that holds each target's self pair itself (owner_start), reading no other
+  if (FLAGGED && a.any_flag && *a.any_flag == 0) return;
   if (FLAGGED) {
     // A source range without a flagged tile leaves every partial state as it
     // starts (the self-pair exponent; sum 1 in the split that holds the self
@@ -727,23 +724,17 @@ __device__ __forceinline__ void pair_block(const MArgs& a, int tb, int split, un
     }
     __syncthreads();
     if (tl[kTileWindow] == 0) {
-      // (when the screen flagged no tile at all in this call and says so, k_combine reads only
-      // the split that holds the self pair: the others are not written)
-      const bool owner_only = a.any_flag && *a.any_flag == 0;
       if (tid < kMI) {
         const int64_t i = i0 + tid;
         const bool own = (int64_t)split == i / a.j_per_split;
-        if (i < a.n && (own || !owner_only)) {
+        if (i < a.n) {
           const float li = a.lw2[i];
           const double nf = a.node[a.n + i];
 #pragma unroll
           for (int s = 0; s < S; ++s) {
-            const float self = li != -INFINITY ? li - (float)(a.kapd[s] * a.taud[s] * a.taud[s] * nf) : -INFINITY;
-            const float M0 = a.rref ? a.rref[(size_t)s * a.n + i] : self;
-            const float h = a.rhv ? a.rhv[(size_t)s * a.n + i] : -INFINITY;
-            float sum = (own && self != -INFINITY) ? (self == M0 ? 1.f : fast_exp2(self - M0)) : 0.f;
-            if (own && h != -INFINITY) sum += h == M0 ? 1.f : fast_exp2(h - M0);
-            a.part[((size_t)split * S + s) * a.n + i] = make_float2(M0, sum);
+            float2 v = owner_start(li, nf, a.kapd[s], a.taud[s], a.rref, a.rhv, a.n, i, s);
+            if (!own) v.y = 0.f;
+            a.part[((size_t)split * S + s) * a.n + i] = v;
           }
         }
       }

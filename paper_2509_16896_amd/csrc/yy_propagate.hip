@@ -877,23 +877,30 @@ __device__ __forceinline__ void k_combine_body(const CombineArgs& a, int bx_, in
   }
   const double logvol = a.scal[0];
   const double lref = *a.lref;
-  // deferred planes and no tile flagged in this call: every split's state is the self pair's
-  // exponent with sum 1 in the split that holds the self pair and 0 elsewhere, so that split alone
-  // gives the same (max, sum); the split pass writes only it
+  // no tile flagged in this call: every split keeps its starting state, (row floor, 0) except in
+  // the split that holds the self pair, so that split's state alone gives the same (max, sum); it is
+  // formed here (owner_start) and the split pass writes nothing
   const bool owner_only = a.defer && a.defer[0] == 0;
-  const int p0 = owner_only ? (int)(i / a.j_per_split) : 0;
-  const int p1 = owner_only ? p0 + 1 : a.nsplit;
+  const float li2 = owner_only ? a.lw2[i] : 0.f;
+  const double fn = owner_only ? a.node[a.n + i] : 0.0;
   double T[YY_MAX_SCALES + 1], sg[YY_MAX_SCALES + 1];
   int nt = 0;
   for (int s = 0; s < a.S; ++s) {
     if (a.sign[s] == 0.0 || lref == -INFINITY) continue;
     float M = -INFINITY;
-    for (int p = p0; p < p1; ++p) M = fmaxf(M, a.part[((size_t)p * a.S + s) * a.n + i].x);
-    if (M == -INFINITY) continue;
     double sum = 0.0;
-    for (int p = p0; p < p1; ++p) {
-      const float2 v = a.part[((size_t)p * a.S + s) * a.n + i];
-      if (v.x != -INFINITY) sum += (double)v.y * exp2((double)v.x - (double)M);
+    if (owner_only) {
+      const float2 v = owner_start(li2, fn, a.kapd[s], a.taud[s], a.rref, a.rhv, a.n, i, s);
+      M = v.x;
+      if (M == -INFINITY) continue;
+      sum = (double)v.y * exp2((double)v.x - (double)M);
+    } else {
+      for (int p = 0; p < a.nsplit; ++p) M = fmaxf(M, a.part[((size_t)p * a.S + s) * a.n + i].x);
+      if (M == -INFINITY) continue;
+      for (int p = 0; p < a.nsplit; ++p) {
+        const float2 v = a.part[((size_t)p * a.S + s) * a.n + i];
+        if (v.x != -INFINITY) sum += (double)v.y * exp2((double)v.x - (double)M);
+      }
     }
     const double L = ((double)M + log2(sum)) * kLn2 + lref;
     T[nt] = a.kap[s] + logvol + L;
@@ -1352,7 +1359,14 @@ yy_status propagate_begin(yy_ctx ctx, const yy_model* model, const yy_scales* sc
   cb.defer = P.deferred && mfma ? ctx->d_defer : nullptr;
   cb.j_per_split = ex.j_per_split;
   cb.div = pull ? P.div.as<double>() : nullptr;
-  for (int s = 0; s < S; ++s) cb.taud[s] = taud[s];
+  for (int s = 0; s < S; ++s) {
+    cb.taud[s] = taud[s];
+    cb.kapd[s] = kapd[s];
+  }
+  cb.lw2 = a.lw2;
+  cb.node = a.node;
+  cb.rref = mfma && !pull ? ex.rref : nullptr;
+  cb.rhv = mfma && !pull ? ex.rhv : nullptr;
   return YY_OK;
 }
 
