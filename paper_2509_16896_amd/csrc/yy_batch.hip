@@ -415,8 +415,9 @@ static yy_status build(yy_batch b) {
       CombineArgs cb = R.plan.cb;
       cb.logw_in = lwi;
       cb.logw_out = lwo;
-      // the run's flag word: with no tile flagged in the step only the splits holding self pairs were
-      // written (a run in the vector-ALU form has none and combines every split)
+      // the run's flag word: with no tile flagged in the step the split pass wrote nothing and the
+      // combination forms each target's self-pair split state itself (a run in the vector-ALU form, or
+      // one with the split form on every tile, has none and combines every split)
       if (b->prec == YY_PREC_BF16X3P && R.plan.mfma && !run_dense(b, q)) cb.defer = b->d_words.as<int>() + 2 * q;
       A3.push_back({cb, nullptr});
       A4.push_back({n, r, d.model.m, d.model.obs, d.model.H, d.model.h_shift, R.x.as<double>(), d.dys, d.dt,

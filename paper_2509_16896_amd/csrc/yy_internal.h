@@ -222,8 +222,8 @@ struct MfmaExtra {
   float* bpre;                 // BF16X3P: source biases over the first kPreK coordinates, laid out as bsrc
   const DeferredPrep* deferred;   // BF16X3P on one run with deferred planes, else null
   // BF16X3P without deferred planes (the batched step): a device word that the source biases clear and
-  // the screens raise when they flag a tile, so that with none flagged only the splits holding self
-  // pairs are written and combined (null: every split)
+  // the screens raise when they flag a tile, so that with none flagged the split pass writes nothing
+  // and the combination forms the self-pair splits' states (null: every split written and combined)
   int* flag_word = nullptr;
   const float* rref = nullptr;     // [S][n] lower bounds of the row maxima (push form), or null: self pairs
   const float* rhv = nullptr;      // [S][n] the pair (i, j*) counted apart (exact term), or -inf; with rref
