@@ -55,12 +55,6 @@ __device__ __forceinline__ void k_rs_local_body(int64_t n, const double* __restr
   if (threadIdx.x == kBlock - 1) tot[bx_] = s[kBlock - 1];
 }
 
-__global__ void __launch_bounds__(kBlock) k_rs_local(int64_t n, const double* __restrict__ w,
-                                                     unsigned long long* __restrict__ C,
-                                                     unsigned long long* __restrict__ tot) {
-  k_rs_local_body(n, w, C, tot, blockIdx.x, gridDim.x);
-}
-
 __global__ void __launch_bounds__(kBlock) k_rs_local_batch(const rs_local_args* __restrict__ A,
                                                            const int* __restrict__ pre, int nr) {
   const int q = batch_find(pre, nr, blockIdx.x);
@@ -318,6 +312,27 @@ __global__ void __launch_bounds__(kBlock) k_ess_check(const double* __restrict__
   k_ess_check_body(ess, ess_min, flags, blockIdx.x, gridDim.x);
 }
 
+// The first resampling kernel of a single run with the restart's independent small
+// steps folded in, to save their launches: the ESS check (block 0, where ess is
+// given) and the plain restart box (where box_lo is given; the coordinates grid-
+// strided over the blocks, the same arithmetic as k_box_plain).
+__global__ void __launch_bounds__(kBlock) k_rs_local_front(int64_t n, const double* __restrict__ w,
+                                                           unsigned long long* __restrict__ C,
+                                                           unsigned long long* __restrict__ tot,
+                                                           const double* __restrict__ ess, double ess_min,
+                                                           uint32_t* __restrict__ flags, int32_t r, double R,
+                                                           const double* __restrict__ mean,
+                                                           double* __restrict__ box_lo, double* __restrict__ box_hi) {
+  if (ess) k_ess_check_body(ess, ess_min, flags, blockIdx.x, gridDim.x);
+  if (box_lo) {
+    for (int64_t d = (int64_t)blockIdx.x * kBlock + threadIdx.x; d < r; d += (int64_t)gridDim.x * kBlock) {
+      box_lo[d] = __dsub_rn(mean[d], R);
+      box_hi[d] = __dadd_rn(mean[d], R);
+    }
+  }
+  k_rs_local_body(n, w, C, tot, blockIdx.x, gridDim.x);
+}
+
 __global__ void __launch_bounds__(kBlock) k_ess_check_batch(const ess_check_args* __restrict__ A,
                                                             const int* __restrict__ pre, int nr) {
   const int q = batch_find(pre, nr, blockIdx.x);
@@ -407,7 +422,9 @@ extern "C" yy_status yy_restart(yy_ctx ctx, int64_t n, int32_t r, const uint32_t
       return fail(YY_ERR_ARG, "yy_restart: cover_min must be in [0, 1]");
   }
   YY_HIP(hipSetDevice(ctx->device));
-  if (ess) {
+  // with resampling, the ESS check and the plain box run inside its first kernel
+  const bool front = idx != nullptr;
+  if (ess && !front) {
     k_ess_check<<<1, 64, 0, ctx->stream>>>(ess, params->ess_min, ctx->d_flags);
     YY_LAUNCH_CHECK("k_ess_check");
   }
@@ -417,8 +434,10 @@ extern "C" yy_status yy_restart(yy_ctx ctx, int64_t n, int32_t r, const uint32_t
     if (st != YY_OK) return st;
     unsigned long long* C = ctx->scan.as<unsigned long long>();
     unsigned long long* tot = C + n;
-    k_rs_local<<<nb, kBlock, 0, ctx->stream>>>(n, w, C, tot);
-    YY_LAUNCH_CHECK("k_rs_local");
+    k_rs_local_front<<<nb, kBlock, 0, ctx->stream>>>(n, w, C, tot, ess, params->ess_min, ctx->d_flags, r,
+                                                     params->R, mean, prop ? nullptr : box_lo,
+                                                     prop ? nullptr : box_hi);
+    YY_LAUNCH_CHECK("k_rs_local_front");
     k_rs_offsets<<<1, kBlock, 0, ctx->stream>>>(nb, tot);
     YY_LAUNCH_CHECK("k_rs_offsets");
     k_rs_add<<<nb, kBlock, 0, ctx->stream>>>(n, tot, C);
@@ -435,7 +454,7 @@ extern "C" yy_status yy_restart(yy_ctx ctx, int64_t n, int32_t r, const uint32_t
     yy_status st = proposal_restart_prepare(ctx, prop, n, r, x_cur, idx, mean, params->R, params->cover_min,
                                             box_lo, box_hi, &dec);
     if (st != YY_OK) return st;
-  } else {
+  } else if (!front) {
     k_box_plain<<<(unsigned)((r + kBlock - 1) / kBlock), kBlock, 0, ctx->stream>>>(r, params->R, mean, box_lo,
                                                                                  box_hi);
     YY_LAUNCH_CHECK("k_box_plain");
