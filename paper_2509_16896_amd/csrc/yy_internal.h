@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <climits>
 
 #include <string>
 #include <vector>
@@ -590,6 +591,42 @@ struct RowRefArgs {
   float* rref;            // [S][n] the rows' lower bounds
   float* rhv;             // [S][n] the exact term of the pair (i, j*) where the row counts it apart, else -inf
 };
+
+// j*, the first valid source of maximal weight, from the conversion blocks'
+// candidates (one block), and f(x_j*) over the r coordinates.
+__device__ __forceinline__ void k_heavy_body(const RowRefArgs& a) {
+  __shared__ long long sj;
+  if (threadIdx.x == 0) sj = LLONG_MAX;
+  __syncthreads();
+  long long m = LLONG_MAX;
+  for (int p = threadIdx.x; p < a.nheavy; p += kBlock) m = a.heavy[p] < m ? a.heavy[p] : m;
+  if (m != LLONG_MAX) atomicMin(&sj, m);
+  __syncthreads();
+  const long long js = sj == LLONG_MAX ? -1 : sj;
+  if (threadIdx.x == 0) *a.jstar = js;
+  if (js < 0) return;
+  const double* xj = a.x + (size_t)js * a.r;
+  for (int32_t k = threadIdx.x; k < a.r; k += kBlock) {
+    double fk = 0.0;
+    if (a.fw) {
+      fk = a.fw[(size_t)js * a.r + k];
+    } else if (a.drift == YY_F_COS) {
+      fk = cos(xj[k]);
+    } else if (a.drift == YY_F_PAPER_SINMIX) {
+      const double xv = xj[k], xn = k + 1 < a.r ? xj[k + 1] : 0.0;
+      fk = sin(xv) * (-0.5 * xv + 0.1 * xn) + sin(2.0 * xv) * (-0.3 * xv + 0.3 * xn);
+    } else if (a.drift == YY_F_LINEAR) {
+      double acc = 0.0;
+      for (int32_t l = 0; l < a.r; ++l) acc = fma(a.A[(size_t)k * a.r + l], xj[l], acc);
+      fk = acc;
+    }
+    a.fstar[k] = fk;
+  }
+}
+
+// The source biases (k_src_bias) and, in one more block, j* with f(x_j*)
+// (k_heavy_body): one launch, as neither reads what the other writes.
+yy_status launch_src_bias_heavy(hipStream_t st, const PairArgs& a, const MfmaExtra& ex, const RowRefArgs& ra);
 
 struct combine_args {
   CombineArgs a;

@@ -1938,6 +1938,13 @@ __global__ void __launch_bounds__(kBlock) k_src_bias(int64_t n, int64_t n_pad, i
   k_src_bias_body(n, n_pad, S, a, out, blockIdx.x, gridDim.x);
 }
 
+// Blocks [0, nbias): the source biases; block nbias: j* and f(x_j*).
+__global__ void __launch_bounds__(kBlock) k_src_bias_heavy(int64_t n, int64_t n_pad, int32_t S, MArgs a,
+                                                           float* __restrict__ out, RowRefArgs ra, int nbias) {
+  if ((int)blockIdx.x < nbias) k_src_bias_body(n, n_pad, S, a, out, blockIdx.x, nbias);
+  else k_heavy_body(ra);
+}
+
 __global__ void __launch_bounds__(kBlock) k_src_bias_batch(const MArgs* __restrict__ sets, const int* __restrict__ pre,
                                                            int nr) {
   const int q = batch_find(pre, nr, blockIdx.x);
@@ -2013,6 +2020,14 @@ yy_status launch_src_bias(hipStream_t st, const PairArgs& pa, const MfmaExtra& e
   MArgs m = make_args(pa, YY_PREC_BF16X3, ex);
   k_src_bias<<<(unsigned)((ex.n_pad + kBlock - 1) / kBlock), kBlock, 0, st>>>(pa.n, ex.n_pad, pa.S, m, ex.bsrc);
   YY_LAUNCH_CHECK("k_src_bias");
+  return YY_OK;
+}
+
+yy_status launch_src_bias_heavy(hipStream_t st, const PairArgs& pa, const MfmaExtra& ex, const RowRefArgs& ra) {
+  MArgs m = make_args(pa, YY_PREC_BF16X3, ex);
+  const int nbias = (int)((ex.n_pad + kBlock - 1) / kBlock);
+  k_src_bias_heavy<<<(unsigned)nbias + 1, kBlock, 0, st>>>(pa.n, ex.n_pad, pa.S, m, ex.bsrc, ra, nbias);
+  YY_LAUNCH_CHECK("k_src_bias_heavy");
   return YY_OK;
 }
 

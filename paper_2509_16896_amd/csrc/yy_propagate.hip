@@ -451,36 +451,6 @@ __global__ void __launch_bounds__(kBlock) k_lw_convert(int64_t n, int nparts,
 constexpr float kRowRefGap = 160.f;
 constexpr int kRowRefTargets = 16;
 
-__device__ __forceinline__ void k_heavy_body(const RowRefArgs& a) {
-  __shared__ long long sj;
-  if (threadIdx.x == 0) sj = LLONG_MAX;
-  __syncthreads();
-  long long m = LLONG_MAX;
-  for (int p = threadIdx.x; p < a.nheavy; p += kBlock) m = a.heavy[p] < m ? a.heavy[p] : m;
-  if (m != LLONG_MAX) atomicMin(&sj, m);
-  __syncthreads();
-  const long long js = sj == LLONG_MAX ? -1 : sj;
-  if (threadIdx.x == 0) *a.jstar = js;
-  if (js < 0) return;
-  const double* xj = a.x + (size_t)js * a.r;
-  for (int32_t k = threadIdx.x; k < a.r; k += kBlock) {
-    double fk = 0.0;
-    if (a.fw) {
-      fk = a.fw[(size_t)js * a.r + k];
-    } else if (a.drift == YY_F_COS) {
-      fk = cos(xj[k]);
-    } else if (a.drift == YY_F_PAPER_SINMIX) {
-      const double xv = xj[k], xn = k + 1 < a.r ? xj[k + 1] : 0.0;
-      fk = sin(xv) * (-0.5 * xv + 0.1 * xn) + sin(2.0 * xv) * (-0.3 * xv + 0.3 * xn);
-    } else if (a.drift == YY_F_LINEAR) {
-      double acc = 0.0;
-      for (int32_t l = 0; l < a.r; ++l) acc = fma(a.A[(size_t)k * a.r + l], xj[l], acc);
-      fk = acc;
-    }
-    a.fstar[k] = fk;
-  }
-}
-
 __device__ __forceinline__ void k_row_ref_body(const RowRefArgs& a, int bx_) {
   __shared__ float sself[YY_MAX_SCALES][kRowRefTargets];
   __shared__ int sneed[kRowRefTargets];
@@ -549,7 +519,6 @@ __device__ __forceinline__ void k_row_ref_body(const RowRefArgs& a, int bx_) {
   }
 }
 
-__global__ void __launch_bounds__(kBlock) k_heavy(RowRefArgs a) { k_heavy_body(a); }
 __global__ void __launch_bounds__(kBlock) k_row_ref(RowRefArgs a) { k_row_ref_body(a, blockIdx.x); }
 
 // batched: the first block of each run's range evaluates its heavy source, the rows follow in a second launch
@@ -1270,7 +1239,7 @@ yy_status propagate_begin(yy_ctx ctx, const yy_model* model, const yy_scales* sc
   a.nsplit = nsplit;
   if ((st = ctx->part.ensure((size_t)nsplit * S * n * sizeof(float2))) != YY_OK) return st;
   a.part = ctx->part.as<float2>();
-  if (mfma && (st = launch_src_bias(ctx->stream, a, ex)) != YY_OK) return st;
+  if (mfma && pull && (st = launch_src_bias(ctx->stream, a, ex)) != YY_OK) return st;
   if (mfma && !pull) {
     // a lower bound of every row maximum: the self pair, or the pair with the heaviest source
     if ((st = ctx->rref.ensure(2 * (size_t)S * n * sizeof(float))) != YY_OK) return st;
@@ -1296,8 +1265,8 @@ yy_status propagate_begin(yy_ctx ctx, const yy_model* model, const yy_scales* sc
     }
     ra.rref = ctx->rref.as<float>();
     ra.rhv = ra.rref + (size_t)S * n;
-    k_heavy<<<1, kBlock, 0, ctx->stream>>>(ra);
-    YY_LAUNCH_CHECK("k_heavy");
+    // the source biases and j* (with f(x_j*)) in one launch: both read only the converted weights
+    if ((st = launch_src_bias_heavy(ctx->stream, a, ex, ra)) != YY_OK) return st;
     k_row_ref<<<(unsigned)((n + row_ref_targets(a.r, n) - 1) / row_ref_targets(a.r, n)), kBlock, 0, ctx->stream>>>(ra);
     YY_LAUNCH_CHECK("k_row_ref");
     ex.rref = ra.rref;
