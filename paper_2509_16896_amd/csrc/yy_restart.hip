@@ -292,6 +292,20 @@ __global__ void __launch_bounds__(kBlock) k_restart_nodes(int64_t n, int32_t r, 
   k_restart_nodes_body(n, r, codes, mean, box_lo, box_hi, only_if, x_new, logw_new, blockIdx.x, gridDim.x);
 }
 
+// The resampling offsets (block 0, one block as k_rs_offsets) beside the new nodes in the
+// plain box (the other blocks, as k_restart_nodes): the nodes read neither the weights nor
+// the resampling buffers, so the two share a launch.
+__global__ void __launch_bounds__(kBlock) k_rs_offsets_nodes(int nb, unsigned long long* __restrict__ tot, int64_t n,
+                                                             int32_t r, const uint32_t* __restrict__ codes,
+                                                             const double* __restrict__ mean,
+                                                             const double* __restrict__ box_lo,
+                                                             const double* __restrict__ box_hi,
+                                                             double* __restrict__ x_new, double* __restrict__ logw_new,
+                                                             int node_blocks) {
+  if (blockIdx.x == 0) k_rs_offsets_body(nb, tot, 0, 1);
+  else k_restart_nodes_body(n, r, codes, mean, box_lo, box_hi, nullptr, x_new, logw_new, blockIdx.x - 1, node_blocks);
+}
+
 __global__ void __launch_bounds__(kBlock) k_restart_nodes_batch(const restart_nodes_args* __restrict__ A,
                                                                 const int* __restrict__ pre, int nr) {
   const int q = batch_find(pre, nr, blockIdx.x);
@@ -428,6 +442,24 @@ extern "C" yy_status yy_restart(yy_ctx ctx, int64_t n, int32_t r, const uint32_t
     k_ess_check<<<1, 64, 0, ctx->stream>>>(ess, params->ess_min, ctx->d_flags);
     YY_LAUNCH_CHECK("k_ess_check");
   }
+  int64_t blocks = (n + 3) / 4;
+  if (blocks > 16384) blocks = 16384;
+  if (blocks * kBlock < r) blocks = (r + kBlock - 1) / kBlock;
+  // plain box with resampling: the new nodes go out beside the resampling offsets, unless the caller's
+  // arrays overlap so that the order between them matters
+  auto overlaps = [](const void* a, size_t na, const void* b, size_t nb_) {
+    const char *pa = static_cast<const char*>(a), *pb = static_cast<const char*>(b);
+    return pa && pb && pa < pb + nb_ && pb < pa + na;
+  };
+  const size_t xb = (size_t)n * r * sizeof(double), nbytes = (size_t)n * sizeof(double);
+  const bool early_nodes =
+      front && !prop && !overlaps(w, nbytes, x_new, xb) && !overlaps(w, nbytes, logw_new, nbytes) &&
+      !overlaps(idx, (size_t)n * sizeof(int64_t), x_new, xb) &&
+      !overlaps(idx, (size_t)n * sizeof(int64_t), logw_new, nbytes) &&
+      !overlaps(idx, (size_t)n * sizeof(int64_t), mean, (size_t)r * sizeof(double)) &&
+      !overlaps(idx, (size_t)n * sizeof(int64_t), box_lo, (size_t)r * sizeof(double)) &&
+      !overlaps(idx, (size_t)n * sizeof(int64_t), box_hi, (size_t)r * sizeof(double)) &&
+      !overlaps(idx, (size_t)n * sizeof(int64_t), codes, (size_t)n * r * sizeof(uint32_t));
   if (idx) {
     const int nb = (int)((n + kBlock - 1) / kBlock);
     yy_status st = ctx->scan.ensure(((size_t)n + nb + 1) * sizeof(unsigned long long));
@@ -438,17 +470,20 @@ extern "C" yy_status yy_restart(yy_ctx ctx, int64_t n, int32_t r, const uint32_t
                                                      params->R, mean, prop ? nullptr : box_lo,
                                                      prop ? nullptr : box_hi);
     YY_LAUNCH_CHECK("k_rs_local_front");
-    k_rs_offsets<<<1, kBlock, 0, ctx->stream>>>(nb, tot);
-    YY_LAUNCH_CHECK("k_rs_offsets");
+    if (early_nodes) {
+      k_rs_offsets_nodes<<<(unsigned)blocks + 1, kBlock, 0, ctx->stream>>>(nb, tot, n, r, codes, mean, box_lo, box_hi,
+                                                                           x_new, logw_new, (int)blocks);
+      YY_LAUNCH_CHECK("k_rs_offsets_nodes");
+    } else {
+      k_rs_offsets<<<1, kBlock, 0, ctx->stream>>>(nb, tot);
+      YY_LAUNCH_CHECK("k_rs_offsets");
+    }
     k_rs_add<<<nb, kBlock, 0, ctx->stream>>>(n, tot, C);
     YY_LAUNCH_CHECK("k_rs_add");
     const uint64_t U = h_sm64(h_sm64(params->seed, kDomainResample), (uint64_t)step) >> 32;
     k_rs_search<<<nb, kBlock, 0, ctx->stream>>>(n, nb, tot, C, U, idx, ctx->d_flags);
     YY_LAUNCH_CHECK("k_rs_search");
   }
-  int64_t blocks = (n + 3) / 4;
-  if (blocks > 16384) blocks = 16384;
-  if (blocks * kBlock < r) blocks = (r + kBlock - 1) / kBlock;
   int* dec = nullptr;
   if (prop) {
     yy_status st = proposal_restart_prepare(ctx, prop, n, r, x_cur, idx, mean, params->R, params->cover_min,
@@ -459,9 +494,11 @@ extern "C" yy_status yy_restart(yy_ctx ctx, int64_t n, int32_t r, const uint32_t
                                                                                  box_hi);
     YY_LAUNCH_CHECK("k_box_plain");
   }
-  k_restart_nodes<<<(unsigned)blocks, kBlock, 0, ctx->stream>>>(n, r, codes, mean, box_lo, box_hi, nullptr,
-                                                                x_new, logw_new);
-  YY_LAUNCH_CHECK("k_restart_nodes");
+  if (!early_nodes) {
+    k_restart_nodes<<<(unsigned)blocks, kBlock, 0, ctx->stream>>>(n, r, codes, mean, box_lo, box_hi, nullptr,
+                                                                  x_new, logw_new);
+    YY_LAUNCH_CHECK("k_restart_nodes");
+  }
   if (prop) {
     yy_status st = proposal_restart_finish(ctx, prop, n, r, logw_new, mean, params->R, params->ess_min, box_lo,
                                            box_hi, dec, used);
