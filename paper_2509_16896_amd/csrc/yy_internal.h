@@ -362,6 +362,7 @@ yy_status launch_combine(hipStream_t st, const CombineArgs& cb);
 // blocks), enough blocks to stream the n x r coordinates at full bandwidth; up to
 // n = 4096, 16 rows per block, so that a wave's chain of rows is short where the
 // kernel is bound by latency rather than bandwidth.
+constexpr int kMaxNormBlocks = 1024;   // the largest norm_blocks(n)
 inline int norm_blocks(int64_t n) {
   if (n <= 4096) return (int)((n + 15) / 16);
   return (int)((n + 63) / 64 < 1024 ? (n + 63) / 64 : 1024);

@@ -582,20 +582,29 @@ __global__ void __launch_bounds__(kBlock) k_ln_partials(int64_t n, int32_t r, in
   }
 }
 
-// logZ = M + log Z with M = max_b m_b and Z = sum_b e^(m_b - M) S_b; the ESS is
-// Z^2 / sum_b e^(2(m_b - M)) S2_b.  sc = {logZ, valid, M, Z, then the factors
-// e^(m_b - M) of the nb blocks}.
-__global__ void __launch_bounds__(kBlock) k_ln_logz(int nb, int32_t r, const double* __restrict__ part,
-                                                    double* __restrict__ sc, double* __restrict__ logZ_step,
-                                                    double* __restrict__ logZ_acc, double* __restrict__ ess,
-                                                    uint32_t* __restrict__ flags) {
+// Every block first forms, from the nb block sums, M = max_b m_b, Z = sum_b e^(m_b - M) S_b
+// and the factors e^(m_b - M) (fixed-order reductions, so every block gets the same values):
+// logZ = M + log Z and the ESS Z^2 / sum_b e^(2(m_b - M)) S2_b, written by block 0 with
+// sc = {logZ, valid, M, Z, then the factors}.  Then blocks [0, nfb): mean[k] =
+// sum_b e^(m_b - M) part[b][3 + k] / Z in a fixed order (as k_norm_final); the others:
+// logw -= logZ in place, w = e^logw.  (The scalars are formed in every block rather than in a
+// one-block kernel before: that launch cost more than the repeated reduction over nb <= 1024.)
+__global__ void __launch_bounds__(kBlock) k_ln_final(int64_t n, int nb, int32_t r, int nfb,
+                                                     const double* __restrict__ part, double* __restrict__ sc,
+                                                     double* __restrict__ logZ_step, double* __restrict__ logZ_acc,
+                                                     double* __restrict__ ess, uint32_t* __restrict__ flags,
+                                                     double* __restrict__ mean, double* __restrict__ logw,
+                                                     double* __restrict__ w) {
+  __shared__ double smn[kNormFinalParts][kNormFinalK];
   __shared__ double sh[kBlock / 64];
+  __shared__ double sg[kMaxNormBlocks];
+  const bool head = blockIdx.x == 0 && threadIdx.x == 0;
   const size_t stride = 3 + (size_t)r;
   double M = -INFINITY;
   for (int b = threadIdx.x; b < nb; b += kBlock) M = fmax(M, part[b * stride]);
   M = block_max<kBlock>(M, sh);
   if (M == -INFINITY) {
-    if (threadIdx.x == 0) {
+    if (head) {
       sc[0] = -INFINITY;
       sc[1] = 0.0;
       *logZ_step = -INFINITY;
@@ -606,14 +615,15 @@ __global__ void __launch_bounds__(kBlock) k_ln_logz(int nb, int32_t r, const dou
   double z = 0.0, z2 = 0.0;
   for (int b = threadIdx.x; b < nb; b += kBlock) {
     const double g = exp(part[b * stride] - M);
-    sc[4 + b] = g;
+    sg[b] = g;
+    if (blockIdx.x == 0) sc[4 + b] = g;
     z = fma(g, part[b * stride + 1], z);
     z2 = fma(g * g, part[b * stride + 2], z2);
   }
   z = block_sum<kBlock>(z, sh);
-  z2 = block_sum<kBlock>(z2, sh);
-  if (threadIdx.x == 0) {
-    const double lz = M + log(z);
+  z2 = block_sum<kBlock>(z2, sh);   // (its barriers also publish sg)
+  const double lz = M + log(z);
+  if (head) {
     sc[0] = lz;
     sc[1] = 1.0;
     sc[2] = M;
@@ -622,18 +632,7 @@ __global__ void __launch_bounds__(kBlock) k_ln_logz(int nb, int32_t r, const dou
     *logZ_acc += lz;
     *ess = z * z / z2;
   }
-}
-
-// Blocks [0, nfb): mean[k] = sum_b e^(m_b - M) part[b][3 + k] / Z in a fixed
-// order (as k_norm_final); the others: logw -= logZ in place, w = e^logw.
-__global__ void __launch_bounds__(kBlock) k_ln_final(int64_t n, int nb, int32_t r, int nfb,
-                                                     const double* __restrict__ part,
-                                                     const double* __restrict__ sc, double* __restrict__ mean,
-                                                     double* __restrict__ logw, double* __restrict__ w) {
-  __shared__ double smn[kNormFinalParts][kNormFinalK];
-  if (sc[1] == 0.0) return;
   if ((int)blockIdx.x >= nfb) {
-    const double lz = sc[0];
     const int64_t nwb = (int64_t)gridDim.x - nfb;
     for (int64_t i = ((int64_t)blockIdx.x - nfb) * kBlock + threadIdx.x; i < n; i += nwb * kBlock) {
       const double l = logw[i] - lz;
@@ -642,15 +641,13 @@ __global__ void __launch_bounds__(kBlock) k_ln_final(int64_t n, int nb, int32_t 
     }
     return;
   }
-  const size_t stride = 3 + (size_t)r;
-  const double z = sc[3];
   const int kk = threadIdx.x % kNormFinalK, pp = threadIdx.x / kNormFinalK;
   const int k = blockIdx.x * kNormFinalK + kk;
   double t = 0.0;
   if (k < r) {
     // (unrolled so that the loads of 8 partial rows are in flight at once; the additions keep their order)
 #pragma unroll 8
-    for (int b = pp; b < nb; b += kNormFinalParts) t = fma(sc[4 + b], part[b * stride + 3 + k], t);
+    for (int b = pp; b < nb; b += kNormFinalParts) t = fma(sg[b], part[b * stride + 3 + k], t);
   }
   smn[pp][kk] = t;
   __syncthreads();
@@ -825,11 +822,10 @@ extern "C" yy_status yy_loglik_normalise(yy_ctx ctx, const yy_model* model, int6
                                                      logw, part);
   }
   YY_LAUNCH_CHECK("k_ln_partials");
-  k_ln_logz<<<1, kBlock, 0, ctx->stream>>>(nb, r, part, sc, logZ_step, logZ_acc, ess, ctx->d_flags);
-  YY_LAUNCH_CHECK("k_ln_logz");
   const int nfb = norm_final_blocks(r);
   const int nwb = (int)std::min<int64_t>((n + kBlock - 1) / kBlock, 1024);
-  k_ln_final<<<nfb + nwb, kBlock, 0, ctx->stream>>>(n, nb, r, nfb, part, sc, mean, logw, w);
+  k_ln_final<<<nfb + nwb, kBlock, 0, ctx->stream>>>(n, nb, r, nfb, part, sc, logZ_step, logZ_acc, ess,
+                                                     ctx->d_flags, mean, logw, w);
   YY_LAUNCH_CHECK("k_ln_final");
   return YY_OK;
 }
