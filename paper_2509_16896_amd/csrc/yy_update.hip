@@ -178,15 +178,6 @@ __device__ __forceinline__ void k_norm_logz_body(int nb, const double* __restric
   }
 }
 
-__global__ void __launch_bounds__(kBlock) k_norm_logz(int nb, const double* __restrict__ pmax,
-                                                      const double* __restrict__ psum,
-                                                      double* __restrict__ sc,
-                                                      double* __restrict__ logZ_step,
-                                                      double* __restrict__ logZ_acc,
-                                                      uint32_t* __restrict__ flags) {
-  k_norm_logz_body(nb, pmax, psum, sc, logZ_step, logZ_acc, flags, blockIdx.x, gridDim.x);
-}
-
 __global__ void __launch_bounds__(kBlock) k_norm_logz_batch(const norm_logz_args* __restrict__ A,
                                                             const int* __restrict__ pre, int nr) {
   const int q = batch_find(pre, nr, blockIdx.x);
@@ -198,18 +189,13 @@ __global__ void __launch_bounds__(kBlock) k_norm_logz_batch(const norm_logz_args
 
 
 // Block b handles rows [b*rows, (b+1)*rows): normalised log-weights, weights,
-// partial sum of w^2 and partial weighted coordinate sums.
-__device__ __forceinline__ void k_norm_weights_body(int64_t n, int32_t r, int64_t rows,
-                                                         const double* __restrict__ sc,
-                                                         const double* __restrict__ x,
-                                                         double* __restrict__ lw,
-                                                         double* __restrict__ w,
-                                                         double* __restrict__ pw2,
-                                                         double* __restrict__ pmean, int bx_, int gx_) {
+// partial sum of w^2 and partial weighted coordinate sums, given logZ = lz.
+__device__ __forceinline__ void k_norm_weights_core(int64_t n, int32_t r, int64_t rows, double lz,
+                                                    const double* __restrict__ x, double* __restrict__ lw,
+                                                    double* __restrict__ w, double* __restrict__ pw2,
+                                                    double* __restrict__ pmean, int bx_, int gx_) {
   __shared__ double sw[kBlock];
   __shared__ double sh[kBlock / 64];
-  if (sc[1] == 0.0) return;
-  const double lz = sc[0];
   const int64_t b0 = (int64_t)bx_ * rows;
   const int64_t b1 = std::min<int64_t>(b0 + rows, n);
   double w2 = 0.0;
@@ -285,14 +271,51 @@ __device__ __forceinline__ void k_norm_weights_body(int64_t n, int32_t r, int64_
   }
 }
 
-__global__ void __launch_bounds__(kBlock) k_norm_weights(int64_t n, int32_t r, int64_t rows,
-                                                         const double* __restrict__ sc,
-                                                         const double* __restrict__ x,
-                                                         double* __restrict__ lw,
-                                                         double* __restrict__ w,
-                                                         double* __restrict__ pw2,
-                                                         double* __restrict__ pmean) {
-  k_norm_weights_body(n, r, rows, sc, x, lw, w, pw2, pmean, blockIdx.x, gridDim.x);
+// The same with logZ read from sc (written by k_norm_logz; sc[1] = 0: nothing to do).
+__device__ __forceinline__ void k_norm_weights_body(int64_t n, int32_t r, int64_t rows,
+                                                    const double* __restrict__ sc, const double* __restrict__ x,
+                                                    double* __restrict__ lw, double* __restrict__ w,
+                                                    double* __restrict__ pw2, double* __restrict__ pmean, int bx_,
+                                                    int gx_) {
+  if (sc[1] == 0.0) return;
+  k_norm_weights_core(n, r, rows, sc[0], x, lw, w, pw2, pmean, bx_, gx_);
+}
+
+// A single run's logZ and weights in one launch: every block forms logZ from the nb block
+// maxima and sums with k_norm_logz_body's fixed-order reductions (the same value in every
+// block; block 0 writes sc and the outputs, as k_norm_logz does), then its rows' weights.
+__global__ void __launch_bounds__(kBlock) k_norm_logz_weights(int64_t n, int32_t r, int64_t rows, int nb,
+                                                              const double* __restrict__ pmax,
+                                                              const double* __restrict__ psum,
+                                                              double* __restrict__ sc, double* __restrict__ logZ_step,
+                                                              double* __restrict__ logZ_acc,
+                                                              uint32_t* __restrict__ flags,
+                                                              const double* __restrict__ x, double* __restrict__ lw,
+                                                              double* __restrict__ w, double* __restrict__ pw2,
+                                                              double* __restrict__ pmean) {
+  __shared__ double sh[kBlock / 64];
+  double M = -INFINITY;
+  for (int p = threadIdx.x; p < nb; p += kBlock) M = fmax(M, pmax[p]);
+  M = block_max<kBlock>(M, sh);
+  double s = 0.0;
+  for (int p = threadIdx.x; p < nb; p += kBlock) s += psum[p];
+  s = block_sum<kBlock>(s, sh);
+  const double lz = M == -INFINITY ? -INFINITY : M + log(s);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (M == -INFINITY) {
+      sc[0] = -INFINITY;
+      sc[1] = 0.0;
+      *logZ_step = -INFINITY;
+      atomicOr(flags, YY_FLAG_ALL_ZERO);
+    } else {
+      sc[0] = lz;
+      sc[1] = 1.0;
+      *logZ_step = lz;
+      *logZ_acc += lz;
+    }
+  }
+  if (M == -INFINITY) return;
+  k_norm_weights_core(n, r, rows, lz, x, lw, w, pw2, pmean, blockIdx.x, gridDim.x);
 }
 
 __global__ void __launch_bounds__(kBlock) k_norm_weights_batch(const norm_weights_args* __restrict__ A,
@@ -704,10 +727,9 @@ static yy_status normalise_launch(yy_ctx ctx, int64_t n, int32_t r, const double
   YY_LAUNCH_CHECK("k_norm_max");
   k_norm_sumexp<<<nb, kBlock, 0, ctx->stream>>>(n, nb, pmax, logw, psum);
   YY_LAUNCH_CHECK("k_norm_sumexp");
-  k_norm_logz<<<1, kBlock, 0, ctx->stream>>>(nb, pmax, psum, sc, logZ_step, logZ_acc, ctx->d_flags);
-  YY_LAUNCH_CHECK("k_norm_logz");
-  k_norm_weights<<<nb, kBlock, 0, ctx->stream>>>(n, r, rows, sc, mean ? x : nullptr, logw, wbuf, pw2, pmean);
-  YY_LAUNCH_CHECK("k_norm_weights");
+  k_norm_logz_weights<<<nb, kBlock, 0, ctx->stream>>>(n, r, rows, nb, pmax, psum, sc, logZ_step, logZ_acc,
+                                                       ctx->d_flags, mean ? x : nullptr, logw, wbuf, pw2, pmean);
+  YY_LAUNCH_CHECK("k_norm_logz_weights");
   k_norm_final<<<mean ? norm_final_blocks(r) : 1, kBlock, 0, ctx->stream>>>(nb, r, sc, pw2, pmean, mean, ess);
   YY_LAUNCH_CHECK("k_norm_final");
   if (cov) {
